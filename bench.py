@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the FMM gravity forward model on one MI355X.
+
+Workload (the metric's configuration): 64^3 cells on the unit cube, 2-point
+Gauss rule per axis (2,097,152 source points), density = 32 seeded Gaussian
+blobs + U[-0.01, 0.01] noise, g (3 components) at all 262,144 cell centres,
+p = 10, mixed precision (FP32 P2P and FP32-MFMA M2L, FP64 expansions and
+combine).  A step is one full grav_eval (P2M, M2M, M2L, L2L, P2P, L2P +
+combine) with rho already resident in HBM.  The FP64 path is timed on the
+same workload at the smallest p that reaches rel err <= 1e-6 (p = 12), and its
+p = 10 error is reported beside it.
+
+Prints ONE JSON line (rank 0).  Extra fields: pair-equivalent throughput,
+p50/p99 step latency, relative L2 error against the FP64 oracle on a seeded
+sample of targets, the dominant kernel's roofline, the oracle's CPU
+throughput on that sample, and the FP64 result.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "gz evals/s (src·tgt pairs/s equiv) at rel err ≤1e-6/1e-4; p50/p99 latency"
+PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vector": 157.3, "fp64_vector": 78.6}
+P2P_FLOP_PER_PAIR = 20.0  # Sec. 1.1 cost model: 5 add + 7 mul + 1 sqrt ~ 20 multiplications
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--p64", type=int, default=12)
+    ap.add_argument("--leaf", type=int, default=512)
+    ap.add_argument("--sample", type=int, default=2048, help="oracle targets for cpu_baseline/rel_err")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def timed_steps(plan, rho, out, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.eval(rho, out)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    evs[0].record()
+    for i in range(steps):
+        plan.eval(rho, out)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    total_ms = evs[0].elapsed_time(evs[steps])
+    return total_ms, lat, wall
+
+
+def stage_profile(plan, rho, out, steps):
+    """Average per-stage duration (HIP events on the eval stream)."""
+    import torch
+    plan.set_profiling(True)
+    acc = {}
+    for _ in range(steps):
+        plan.eval(rho, out)
+        for name, ms in plan.stage_times():
+            acc[name] = acc.get(name, 0.0) + ms
+    plan.set_profiling(False)
+    torch.cuda.synchronize()
+    return {k: v / steps for k, v in acc.items()}
+
+
+def pct(xs, q):
+    s = sorted(xs)
+    return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solve would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1107_5951_amd as G
+    import workloads as W
+
+    n = args.n
+    grid = W.Grid.unit(n)
+    rho_h = W.gaussian_blobs(grid, 32, 1002, noise=0.01)
+    rho = torch.as_tensor(rho_h, device="cuda")
+    M = grid.ncell
+
+    def make(prec, p):
+        t0 = time.perf_counter()
+        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, quad_order=2, voxel_centres=True,
+                                 components=3, p=p, leaf_size=args.leaf, precision=prec))
+        return plan, time.perf_counter() - t0
+
+    plan, plan_s = make(G.GRAV_MIXED, args.p)
+    out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
+    total_ms, lat, wall = timed_steps(plan, rho, out, args.steps, args.warmup)
+    ms = total_ms / args.steps
+    stages = stage_profile(plan, rho, out, max(5, min(args.steps, 20)))
+    m2l_pairs, p2p_pairs, n_src = plan.work()
+    g_mixed = out[0].cpu().numpy()
+
+    value = M / (ms * 1e-3)
+    P2 = args.p * args.p
+    # dominant kernel and its roofline
+    flops_m2l = 2.0 * P2 * P2 * m2l_pairs
+    flops_p2p = P2P_FLOP_PER_PAIR * p2p_pairs
+    dom = max(("m2l", "p2p"), key=lambda k: stages.get(k, 0.0))
+    if dom == "m2l":
+        ach = flops_m2l / (stages["m2l"] * 1e-3) / 1e12
+        roof = {"kernel": "k_m2l<7,float> (M2L, FP32 MFMA 16x16x4)", "bound": "mfma",
+                "achieved": ach, "peak": PEAK["fp32_mfma"], "unit": "TFLOP/s"}
+    else:
+        ach = flops_p2p / (stages["p2p"] * 1e-3) / 1e12
+        roof = {"kernel": "k_p2p<float> (near field, FP32 VALU)", "bound": "alu",
+                "achieved": ach, "peak": PEAK["fp32_vector"], "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel_ms"] = stages.get(dom)
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "gz evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (mixed: P2P VALU + M2L MFMA in f32; expansions, M2M/L2L/L2P and combine in f64)",
+        "data": "synthetic",
+        "config": {"workload": "%d^3 cells, 2-point Gauss (%d sources), g at %d cell centres, p=%d, "
+                               "mixed precision, leaf %d cells" % (n, n_src, M, args.p, plan.leaf_cells ** 3),
+                   "levels": plan.levels, "leaf_cells": plan.leaf_cells, "batch": 1},
+        "pair_equiv_per_s": value * n_src,
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "plan_s": plan_s,
+        "stages_ms": stages,
+        "work": {"m2l_box_pairs": m2l_pairs, "p2p_point_pairs": p2p_pairs, "m2l_gflop": flops_m2l / 1e9,
+                 "p2p_gflop_20": flops_p2p / 1e9},
+        "roofline": roof,
+    }
+
+    fp64 = None
+    if not args.no_fp64:
+        del plan
+        plan64, plan64_s = make(G.GRAV_FP64, args.p64)
+        tms, lat64, _ = timed_steps(plan64, rho, out, args.steps, args.warmup)
+        st64 = stage_profile(plan64, rho, out, 5)
+        g64 = out[0].cpu().numpy()
+        ms64 = tms / args.steps
+        m2l64, _, _ = plan64.work()
+        del plan64
+        fp64 = {"p": args.p64, "value": M / (ms64 * 1e-3), "ms_per_step": ms64,
+                "p50_ms": pct(lat64, 50), "p99_ms": pct(lat64, 99), "stages_ms": st64,
+                "m2l_tflops": 2.0 * args.p64 ** 4 * m2l64 / (st64.get("m2l", 1e9) * 1e-3) / 1e12}
+        plan10, _ = make(G.GRAV_FP64, args.p)
+        plan10.eval(rho, out)
+        torch.cuda.synchronize()
+        g64_p = out[0].cpu().numpy()
+        del plan10
+        res["fp64"] = fp64
+
+    if not args.no_cpu:
+        import oracle
+        idx = W.sample_indices(M, args.sample, seed=7)
+        tg = grid.centres()[idx]
+        threads = oracle.num_threads()
+        t0 = time.perf_counter()
+        ref = oracle.forward(rho_h, grid.origin, grid.h, 2, tg, comps=3)
+        cpu_s = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(idx) / cpu_s, "unit": "gz evals/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "%d seeded cell-centre targets (of %d) x all %d source points, "
+                                         "FP64 direct sum, %.1f s" % (len(idx), M, n_src, cpu_s),
+                               "pair_equiv_per_s": len(idx) * n_src / cpu_s}
+        res["rel_err"] = oracle.rel_l2(g_mixed[idx], ref)
+        res["rel_err_bar"] = 1e-4
+        if fp64 is not None:
+            fp64["rel_err"] = oracle.rel_l2(g64[idx], ref)
+            fp64["rel_err_p%d" % args.p] = oracle.rel_l2(g64_p[idx], ref)
+            fp64["rel_err_bar"] = 1e-6
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

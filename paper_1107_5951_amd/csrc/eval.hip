@@ -1,0 +1,617 @@
+// Forward evaluation: upward sweep (P2M, M2M), downward sweep (M2L, L2L),
+// evaluation (L2P and the near-field direct sum), following the stages of
+// the FMM in Sec. 2.3.  All geometry is in the lattice frame (cell units,
+// mesh origin at 0); see plan.hip.
+#include <algorithm>
+#include <cmath>
+
+#include "eval_common.hpp"
+
+namespace grav {
+
+// --------------------------------------------------------------------------
+// P2M on the lattice: the scaled ME of a leaf is a fixed linear map of its
+// b^3 cell densities (all leaves share the point layout), ME = Pm * rho_leaf.
+// One workgroup per source leaf; thread t produces coefficient t.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const double *pm,
+                                             double *me)
+{
+    extern __shared__ double sh[];
+    const DevLev &lv = g.lev[g.L];
+    const int64_t leaf = blockIdx.x;
+    const int lx = (int)(leaf % lv.ns[0]);
+    const int ly = (int)((leaf / lv.ns[0]) % lv.ns[1]);
+    const int lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    // first cell of the leaf (cell coordinates)
+    const int vx0 = (lv.s0[0] + lx - g.shift[0]) * g.b;
+    const int vy0 = (lv.s0[1] + ly - g.shift[1]) * g.b;
+    const int vz0 = (lv.s0[2] + lz - g.shift[2]) * g.b;
+    const int b3 = g.b * g.b * g.b;
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    for (int bm = 0; bm < g.B; ++bm) {
+        for (int v = threadIdx.x; v < b3; v += blockDim.x) {
+            const int ix = vx0 + v % g.b, iy = vy0 + (v / g.b) % g.b, iz = vz0 + v / (g.b * g.b);
+            double r = 0.0;
+            if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
+                r = rho[bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+            sh[v] = r;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < g.PS; t += blockDim.x) {
+            double acc = 0.0;
+            for (int v = 0; v < b3; ++v)
+                acc += pm[(int64_t)v * g.PS + t] * sh[v];
+            me[((lv.me_off + leaf) * g.B + bm) * g.PS + t] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// M2M: parent ME = sum over its (up to 8) children of T_c * child ME.
+// One workgroup per parent box of level l.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_m2m(DevGeom g, int l, const double *m2m, double *me)
+{
+    extern __shared__ double sh[];  // [8][PS]
+    const DevLev &lp = g.lev[l];
+    const DevLev &lc = g.lev[l + 1];
+    const int64_t box = blockIdx.x;
+    const int px = lp.s0[0] + (int)(box % lp.ns[0]);
+    const int py = lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1]);
+    const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
+    for (int bm = 0; bm < g.B; ++bm) {
+        for (int i = threadIdx.x; i < 8 * g.PS; i += blockDim.x) {
+            const int c = i / g.PS, t = i % g.PS;
+            const int cx = 2 * px + (c & 1) - lc.s0[0];
+            const int cy = 2 * py + ((c >> 1) & 1) - lc.s0[1];
+            const int cz = 2 * pz + ((c >> 2) & 1) - lc.s0[2];
+            double v = 0.0;
+            if (cx >= 0 && cy >= 0 && cz >= 0 && cx < lc.ns[0] && cy < lc.ns[1] && cz < lc.ns[2]) {
+                const int64_t ci = lc.me_off + ((int64_t)cz * lc.ns[1] + cy) * lc.ns[0] + cx;
+                v = me[(ci * g.B + bm) * g.PS + t];
+            }
+            sh[i] = v;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < g.PS; t += blockDim.x) {
+            double acc = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const double *mc = m2m + (int64_t)c * g.PS * g.PS;
+                const double *x = sh + c * g.PS;
+                for (int s = 0; s < g.P2; ++s)
+                    acc += mc[(int64_t)s * g.PS + t] * x[s];
+            }
+            me[((lp.me_off + box) * g.B + bm) * g.PS + t] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
+// child-parity class, model); wave w owns columns 16w..16w+15.  For each of
+// the class's 189 interaction-list offsets d the wave accumulates
+// LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA tiles; K_d comes
+// pre-swizzled so that each A fragment is one coalesced 512-byte load.
+// Accumulation stays in registers across all offsets; no atomics.
+// --------------------------------------------------------------------------
+template <int RB, typename T>
+__device__ inline void m2l_body(const DevGeom &g, const M2LTile &tile, const uint32_t *tkey,
+                                const int32_t *torder, const int32_t *class_off, const T *K,
+                                const double *me, double *le)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const DevLev &lv = g.lev[tile.level];
+    const int cl = wave * 16 + (lane & 15);
+    const bool cvalid = cl < tile.ncol;
+    const int64_t col = tile.col0 + cl;
+    const int64_t boxpos = col / g.B;
+    const int bm = (int)(col % g.B);
+    int64_t box = 0;
+    int bx = 0, by = 0, bz = 0;
+    if (cvalid) {
+        box = torder[lv.tbox_off + lv.class_start[tile.cls] + boxpos];
+        const uint32_t key = tkey[lv.tbox_off + box];
+        bx = (int)compact3(key);
+        by = (int)compact3(key >> 1);
+        bz = (int)compact3(key >> 2);
+    }
+    vec4 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+        acc[rb] = vec4{0, 0, 0, 0};
+    const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
+    const int krow = lane >> 4;
+    for (int o = 0; o < kClassOffsets; ++o) {
+        const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
+        const int id = offs[4 * o + 3];
+        const int sx = bx + dx - lv.s0[0], sy = by + dy - lv.s0[1], sz = bz + dz - lv.s0[2];
+        const bool have = cvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] &&
+                          sy < lv.ns[1] && sz < lv.ns[2];
+        if (__ballot(have) == 0ull)
+            continue;  // no column of this wave sees a source box at this offset
+        const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
+        const double *mp = me + (have ? (si * g.B + bm) * g.PS : 0);
+        const T *kp = K + (int64_t)id * g.KS * RB * 64 + lane;
+        for (int ks = 0; ks < g.KS; ++ks) {
+            const T bv = have ? (T)mp[4 * ks + krow] : (T)0;
+            const T *ka = kp + (int64_t)ks * RB * 64;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                if constexpr (sizeof(T) == 8)
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ka[rb * 64], bv, acc[rb], 0, 0, 0);
+                else
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ka[rb * 64], bv, acc[rb], 0, 0, 0);
+            }
+        }
+    }
+    if (!cvalid)
+        return;
+    // Output fragment: lane holds column lane % 16 and four rows; the FP32
+    // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
+    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * g.PS;
+    constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
+    const int rbase = sizeof(T) == 8 ? krow : 4 * krow;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            dst[16 * rb + rbase + rstride * r] = (double)acc[rb][r];
+}
+
+template <int RB, typename T>
+__global__ void __launch_bounds__(256)
+k_m2l(DevGeom g, const M2LTile *tiles, const uint32_t *tkey, const int32_t *torder,
+      const int32_t *class_off, const T *K, const double *me, double *le)
+{
+    m2l_body<RB, T>(g, tiles[blockIdx.x], tkey, torder, class_off, K, me, le);
+}
+
+// --------------------------------------------------------------------------
+// L2L: LE of a level-l box += S_c * LE of its parent (c = child octant).
+// One workgroup per target box of level l >= 3.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_l2l(DevGeom g, int l, const uint32_t *tkey,
+                                             const int32_t *tparent, const double *l2l, double *le)
+{
+    extern __shared__ double sh[];
+    const DevLev &lv = g.lev[l];
+    const DevLev &lp = g.lev[l - 1];
+    const int64_t box = blockIdx.x;
+    const uint32_t key = tkey[lv.tbox_off + box];
+    const int c = (int)(key & 7u);
+    const int64_t par = tparent[lv.tbox_off + box];
+    const double *mc = l2l + (int64_t)c * g.PS * g.PS;
+    for (int bm = 0; bm < g.B; ++bm) {
+        for (int s = threadIdx.x; s < g.PS; s += blockDim.x)
+            sh[s] = le[((lp.tgt_off + par) * g.B + bm) * g.PS + s];
+        __syncthreads();
+        for (int t = threadIdx.x; t < g.PS; t += blockDim.x) {
+            double acc = 0.0;
+            for (int s = 0; s < g.P2; ++s)
+                acc += mc[(int64_t)s * g.PS + t] * sh[s];
+            le[((lv.tgt_off + box) * g.B + bm) * g.PS + t] += acc;
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// Near field (P2P): direct sum over the quadrature points of the cells of the
+// 27 leaves around a target leaf (the near term of Eq. (13)); coincident
+// pairs are skipped.  One workgroup per target leaf; each neighbour leaf's
+// densities are staged in LDS; targets are spread over lanes and, when a leaf
+// holds fewer than 256 targets, the sources over several lane groups whose
+// partial sums are reduced through LDS.  Output in the lattice frame:
+// near[i][model] = (sum m/r, sum m d/r^3).
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_start,
+      const uint32_t *tkey, double *near)
+{
+    __shared__ double srho[512];
+    __shared__ double red[256][4];
+    const DevLev &lv = g.lev[g.L];
+    const int64_t leaf = blockIdx.x;
+    const int64_t ts = leaf_start[leaf], te = leaf_start[leaf + 1];
+    const int64_t nt = te - ts;
+    const uint32_t key = tkey[lv.tbox_off + leaf];
+    const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
+    int corner[3];
+    for (int a = 0; a < 3; ++a)
+        corner[a] = (lc[a] - g.shift[a]) * g.b;  // cell coords of the leaf corner
+    const int b = g.b, b3 = b * b * b;
+    int TC = 1;
+    while (TC < nt && TC < 256)
+        TC <<= 1;
+    const int S = 256 / TC;
+    const int t = threadIdx.x;
+    const int ti = t % TC, si = t / TC;
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const T go = (T)(0.5 / 1.7320508075688772);  // Gauss point offset, cell units
+    for (int bm = 0; bm < g.B; ++bm) {
+        for (int64_t c0 = 0; c0 < nt; c0 += TC) {
+            const int64_t j = ts + c0 + ti;
+            const bool valid = (c0 + ti) < nt;
+            T tl[3] = {0, 0, 0};
+            if (valid)
+                for (int a = 0; a < 3; ++a)
+                    tl[a] = (T)(tpos[3 * j + a] - (double)corner[a]);
+            T acc[4] = {0, 0, 0, 0};
+            for (int nb = 0; nb < 27; ++nb) {
+                const int d[3] = {nb % 3 - 1, (nb / 3) % 3 - 1, nb / 9 - 1};
+                bool inb = true;
+                for (int a = 0; a < 3; ++a) {
+                    const int s = lc[a] + d[a] - lv.s0[a];
+                    if (s < 0 || s >= lv.ns[a])
+                        inb = false;
+                }
+                if (!inb)
+                    continue;  // uniform over the workgroup
+                __syncthreads();
+                for (int v = t; v < b3; v += 256) {
+                    const int ix = corner[0] + d[0] * b + v % b;
+                    const int iy = corner[1] + d[1] * b + (v / b) % b;
+                    const int iz = corner[2] + d[2] * b + v / (b * b);
+                    double r = 0.0;
+                    if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
+                        r = rho[bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+                    srho[v] = r;
+                }
+                __syncthreads();
+                if (!valid)
+                    continue;
+                for (int v = si; v < b3; v += S) {
+                    const T rv = (T)srho[v];
+                    if (rv == (T)0)
+                        continue;
+                    const T cx = tl[0] - (T)(d[0] * b + v % b) - (T)0.5;
+                    const T cy = tl[1] - (T)(d[1] * b + (v / b) % b) - (T)0.5;
+                    const T cz = tl[2] - (T)(d[2] * b + v / (b * b)) - (T)0.5;
+                    if (g.q == 1) {
+                        const T r2 = cx * cx + cy * cy + cz * cz;
+                        if (r2 > coincident2<T>()) {
+                            const T ri = rsqrt_t(r2);
+                            const T m = rv * ri;
+                            const T m3 = m * ri * ri;
+                            acc[0] += m;
+                            acc[1] += m3 * cx;
+                            acc[2] += m3 * cy;
+                            acc[3] += m3 * cz;
+                        }
+                    } else {
+                        const T mw = rv * (T)0.125;
+#pragma unroll
+                        for (int gp = 0; gp < 8; ++gp) {
+                            const T ux = cx - ((gp & 1) ? go : -go);
+                            const T uy = cy - ((gp & 2) ? go : -go);
+                            const T uz = cz - ((gp & 4) ? go : -go);
+                            const T r2 = ux * ux + uy * uy + uz * uz;
+                            if (r2 > coincident2<T>()) {
+                                const T ri = rsqrt_t(r2);
+                                const T m = mw * ri;
+                                const T m3 = m * ri * ri;
+                                acc[0] += m;
+                                acc[1] += m3 * ux;
+                                acc[2] += m3 * uy;
+                                acc[3] += m3 * uz;
+                            }
+                        }
+                    }
+                }
+            }
+            // reduce the S source groups
+            __syncthreads();
+            for (int c = 0; c < 4; ++c)
+                red[t][c] = (double)acc[c];
+            __syncthreads();
+            if (si == 0 && valid) {
+                double s4[4] = {0, 0, 0, 0};
+                for (int k = 0; k < S; ++k)
+                    for (int c = 0; c < 4; ++c)
+                        s4[c] += red[k * TC + ti][c];
+                double *o = near + (j * g.B + bm) * 4;
+                for (int c = 0; c < 4; ++c)
+                    o[c] = s4[c];
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// L2P + combine: far field at each target from its leaf LE (phi and
+// g = -grad phi), plus the near field, times G and the lattice-to-physical
+// scale, scattered back to descriptor order.  One thread per target.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_l2p_combine(DevGeom g, const double *tpos, const int32_t *tleaf, const uint32_t *tkey,
+              const uint32_t *perm, const double *le, const double *near, double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.M)
+        return;
+    const DevLev &lv = g.lev[g.L];
+    const int64_t leaf = tleaf[i];
+    double u[3] = {0, 0, 0};
+    if (g.L >= 2) {
+        const uint32_t key = tkey[lv.tbox_off + leaf];
+        const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
+        const double inv_w = 1.0 / (double)g.b;
+        for (int a = 0; a < 3; ++a) {
+            const double centre = ((double)(lc[a] - g.shift[a]) + 0.5) * g.b;
+            u[a] = (tpos[3 * i + a] - centre) * inv_w;
+        }
+    }
+    const int64_t dst_t = perm[i];
+    for (int bm = 0; bm < g.B; ++bm) {
+        double far[4] = {0, 0, 0, 0};
+        if (g.L >= 2) {
+            const double *L = le + ((lv.tgt_off + leaf) * g.B + bm) * g.PS;
+            l2p_eval(g.P, L, u[0], u[1], u[2], far);
+            const double inv_w = 1.0 / (double)g.b;
+            far[0] *= inv_w;
+            const double s = inv_w * inv_w;
+            far[1] = -far[1] * s;  // g = -grad phi
+            far[2] = -far[2] * s;
+            far[3] = -far[3] * s;
+        }
+        const double *nr = near + (i * g.B + bm) * 4;
+        double v[4];
+        for (int c = 0; c < 4; ++c)
+            v[c] = nr[c] + far[c];
+        double *o = out + ((int64_t)bm * g.M + dst_t) * g.C;
+        const double sg = g.G * g.h, sp = g.G * g.h * g.h;
+        if (g.C == 1) {
+            o[0] = sg * v[3];
+        } else if (g.C == 3) {
+            o[0] = sg * v[1];
+            o[1] = sg * v[2];
+            o[2] = sg * v[3];
+        } else {
+            o[0] = sp * v[0];
+            o[1] = sg * v[1];
+            o[2] = sg * v[2];
+            o[3] = sg * v[3];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// host side
+// --------------------------------------------------------------------------
+DevGeom make_geom(const Plan *p)
+{
+    DevGeom g{};
+    for (int l = 0; l <= p->L && l <= kMaxLevels; ++l) {
+        const LevelInfo &s = p->lev[l];
+        DevLev &d = g.lev[l];
+        for (int a = 0; a < 3; ++a) {
+            d.s0[a] = s.s0[a];
+            d.ns[a] = s.ns[a];
+        }
+        d.me_off = s.me_off;
+        d.tgt_off = s.tgt_off;
+        d.tbox_off = p->tbox_off[l];
+        for (int c = 0; c < 9; ++c)
+            d.class_start[c] = s.class_start[c];
+    }
+    g.L = p->L;
+    g.b = p->b;
+    g.q = p->q;
+    g.P = p->P;
+    g.P2 = p->P2;
+    g.PS = p->PS;
+    g.KS = p->KS;
+    g.B = p->B;
+    g.C = p->C;
+    g.n[0] = p->d.nx;
+    g.n[1] = p->d.ny;
+    g.n[2] = p->d.nz;
+    for (int a = 0; a < 3; ++a)
+        g.shift[a] = p->shift[a];
+    g.M = p->M;
+    g.G = p->d.G;
+    g.h = p->d.h;
+    return g;
+}
+
+void stage_begin(Plan *p, const char *name, hipStream_t s)
+{
+    if (!p->profiling)
+        return;
+    if ((int)p->stages.size() <= p->n_stage_used) {
+        Stage st;
+        (void)hipEventCreate(&st.a);
+        (void)hipEventCreate(&st.b);
+        p->stages.push_back(st);
+    }
+    Stage &st = p->stages[p->n_stage_used];
+    st.name = name;
+    (void)hipEventRecord(st.a, s);
+}
+
+void stage_end(Plan *p, hipStream_t s)
+{
+    if (!p->profiling)
+        return;
+    (void)hipEventRecord(p->stages[p->n_stage_used].b, s);
+    ++p->n_stage_used;
+}
+
+template <typename T>
+static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
+{
+    const int RB = p->PS / 16;
+    dim3 grid(p->n_tiles), blk(256);
+#define M2L_CASE(R)                                                                             \
+    case R:                                                                                     \
+        hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const M2LTile *)p->d_tiles,     \
+                           (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
+                           (const int32_t *)p->d_class_off, K, (const double *)p->d_me,         \
+                           p->d_le);                                                            \
+        break;
+    switch (RB) {
+        M2L_CASE(1)
+        M2L_CASE(2)
+        M2L_CASE(3)
+        M2L_CASE(4)
+        M2L_CASE(6)
+        M2L_CASE(7)
+        M2L_CASE(8)
+        M2L_CASE(9)
+        M2L_CASE(11)
+        M2L_CASE(13)
+        M2L_CASE(15)
+        M2L_CASE(16)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef M2L_CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t s)
+{
+    const DevGeom g = make_geom(p);
+    const int L = p->L;
+    if (p->M == 0)
+        return GRAV_OK;
+    if (L >= 2) {
+        stage_begin(p, "p2m", s);
+        const int b3 = p->b * p->b * p->b;
+        hipLaunchKernelGGL(k_p2m, dim3((unsigned)p->lev[L].n_src), dim3(256),
+                           sizeof(double) * b3, s, g, rho, (const double *)p->d_pm, p->d_me);
+        GRAV_HIP(hipGetLastError());
+        stage_end(p, s);
+        stage_begin(p, "m2m", s);
+        for (int l = L - 1; l >= 2; --l) {
+            hipLaunchKernelGGL(k_m2m, dim3((unsigned)p->lev[l].n_src), dim3(256),
+                               sizeof(double) * 8 * p->PS, s, g, l, (const double *)p->d_m2m,
+                               p->d_me);
+            GRAV_HIP(hipGetLastError());
+        }
+        stage_end(p, s);
+        stage_begin(p, "m2l", s);
+        if (p->n_tiles > 0) {
+            if (p->d.precision == GRAV_FP64)
+                GRAV_CHECK(launch_m2l<double>(p, g, s, p->d_k64));
+            else
+                GRAV_CHECK(launch_m2l<float>(p, g, s, p->d_k32));
+        }
+        stage_end(p, s);
+        stage_begin(p, "l2l", s);
+        for (int l = 3; l <= L; ++l) {
+            if (p->lev[l].n_tgt == 0)
+                continue;
+            hipLaunchKernelGGL(k_l2l, dim3((unsigned)p->lev[l].n_tgt), dim3(256),
+                               sizeof(double) * p->PS, s, g, l, (const uint32_t *)p->d_tkey,
+                               (const int32_t *)p->d_tparent, (const double *)p->d_l2l, p->d_le);
+            GRAV_HIP(hipGetLastError());
+        }
+        stage_end(p, s);
+    }
+    stage_begin(p, "p2p", s);
+    if (p->d.precision == GRAV_FP64)
+        hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+                           (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
+                           (const uint32_t *)p->d_tkey, p->d_near);
+    else
+        hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+                           (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
+                           (const uint32_t *)p->d_tkey, p->d_near);
+    GRAV_HIP(hipGetLastError());
+    stage_end(p, s);
+    stage_begin(p, "l2p", s);
+    hipLaunchKernelGGL(k_l2p_combine, dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s, g,
+                       (const double *)p->d_tpos, (const int32_t *)p->d_tleaf,
+                       (const uint32_t *)p->d_tkey, (const uint32_t *)p->d_perm,
+                       (const double *)p->d_le, (const double *)p->d_near, out);
+    GRAV_HIP(hipGetLastError());
+    stage_end(p, s);
+    return GRAV_OK;
+}
+
+grav_status begin_call(Plan *p, hipStream_t s)
+{
+    if (p->has_pending && p->last_stream != s) {
+        const hipError_t q = hipEventQuery(p->done);
+        if (q == hipErrorNotReady)
+            return GRAV_EBUSY;
+        if (q != hipSuccess)
+            return GRAV_EDEVICE;
+    }
+    p->n_stage_used = 0;
+    return GRAV_OK;
+}
+
+grav_status end_call(Plan *p, hipStream_t s)
+{
+    GRAV_HIP(hipEventRecord(p->done, s));
+    p->has_pending = true;
+    p->last_stream = s;
+    return GRAV_OK;
+}
+
+}  // namespace grav
+
+using namespace grav;
+
+extern "C" grav_status grav_eval(grav_plan_t plan, const double *rho, double *g_out, void *stream)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (p->M == 0)
+        return GRAV_OK;
+    if (!rho || !g_out)
+        return GRAV_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    GRAV_HIP(hipGetDevice(&cur));
+    if (cur != p->device)
+        GRAV_HIP(hipSetDevice(p->device));
+    grav_status st = begin_call(p, s);
+    if (st == GRAV_OK)
+        st = enqueue_forward(p, rho, g_out, s);
+    if (st == GRAV_OK)
+        st = end_call(p, s);
+    if (cur != p->device)
+        (void)hipSetDevice(cur);
+    return st;
+}
+
+extern "C" grav_status grav_set_profiling(grav_plan_t plan, int32_t enable)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    (reinterpret_cast<Plan *>(plan))->profiling = enable != 0;
+    return GRAV_OK;
+}
+
+extern "C" grav_status grav_stage_times(grav_plan_t plan, const char **names, double *ms,
+                                        int32_t n, int32_t *count)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    int k = 0;
+    for (int i = 0; i < p->n_stage_used && k < n; ++i, ++k) {
+        Stage &st = p->stages[i];
+        GRAV_HIP(hipEventSynchronize(st.b));
+        float t = 0.f;
+        GRAV_HIP(hipEventElapsedTime(&t, st.a, st.b));
+        if (names)
+            names[k] = st.name.c_str();
+        if (ms)
+            ms[k] = t;
+    }
+    if (count)
+        *count = k;
+    return GRAV_OK;
+}

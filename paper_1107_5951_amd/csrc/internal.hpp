@@ -1,0 +1,151 @@
+// Internal plan layout and shared device helpers of libgrav.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/grav.h"
+
+namespace grav {
+
+constexpr int kMaxP = 16;
+constexpr int kMaxLevels = 10;
+constexpr int kNumOffsets = 316;   // M2L offsets d with 2 <= |d|_inf <= 3
+constexpr int kClassOffsets = 189; // offsets valid for one child-parity class
+constexpr int kTileCols = 64;      // columns (box, model) per M2L tile
+constexpr int kMaxLeafCells = 8;   // leaf edge cap: a leaf's densities fit one 512-entry LDS stage
+
+struct LevelInfo {
+    int l = 0;
+    double w = 0.0;                   // box edge
+    int s0[3] = {0, 0, 0};            // source block start (root-relative box coords, x,y,z)
+    int ns[3] = {0, 0, 0};            // source block size
+    int64_t n_src = 0;                // ns[0]*ns[1]*ns[2]
+    int64_t me_off = 0;               // offset (in expansions) of this level in the ME array
+    int64_t n_tgt = 0;                // boxes holding evaluation points
+    int64_t tgt_off = 0;              // offset of this level in the per-target-box arrays
+    int64_t class_start[9] = {0};     // class-grouped order boundaries
+};
+
+struct M2LTile {
+    int32_t level;
+    int32_t cls;
+    int64_t col0;    // first column (class-ordered box position * B + model)
+    int32_t ncol;    // columns in this tile (<= kTileCols)
+    int32_t pad;
+};
+
+struct Stage {
+    std::string name;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+struct Plan {
+    grav_plan_desc d{};
+    int device = 0;
+    int P = 0, P2 = 0, PS = 0;     // order, p^2, padded stride (multiple of 16)
+    int KS = 0;                    // k-steps of 4 covering P2
+    int q = 1, nq3 = 1, b = 1;     // quadrature points per axis, per cell, leaf edge in cells
+    int L = 0;                     // leaf level
+    int B = 1, C = 3;
+    double wl = 0.0;               // leaf edge
+    double root0[3] = {0, 0, 0};   // root lower corner
+    int shift[3] = {0, 0, 0};      // leaves between root corner and the mesh origin
+    int64_t M = 0;                 // evaluation points
+    int64_t n_leaf = 0;            // leaves holding evaluation points
+    LevelInfo lev[kMaxLevels + 1];
+    int64_t n_me = 0, n_le = 0;    // expansions (per model) in the ME / LE arrays
+    int64_t n_tbox = 0;            // target boxes over all levels >= 2
+    std::vector<M2LTile> tiles_host;
+
+    // device buffers
+    double *d_points = nullptr;    // [n_points][3] user points (unsorted)
+    uint32_t *d_perm = nullptr;    // [M] sorted position -> user index
+    double *d_tpos = nullptr;      // [M][3] sorted target positions
+    int32_t *d_tleaf = nullptr;    // [M] sorted target -> leaf (index in level-L list)
+    int64_t *d_leaf_start = nullptr; // [n_leaf + 1]
+    uint32_t *d_tkey = nullptr;    // [n_tbox_all] Morton key of every target box, per level
+    int32_t *d_tparent = nullptr;  // [n_tbox_all] index (within its level) of the parent box
+    int32_t *d_torder = nullptr;   // [n_tbox_all] class-grouped order -> box index (per level)
+    int64_t tbox_off[kMaxLevels + 1] = {0}; // start of each level in the three arrays above
+    M2LTile *d_tiles = nullptr;
+    int32_t n_tiles = 0;
+    int32_t *d_class_off = nullptr; // [8][kClassOffsets][4] (dx, dy, dz, offset id)
+
+    double *d_pm = nullptr;        // [b^3][PS] lattice P2M
+    double *d_m2m = nullptr;       // [8][PS][PS]
+    double *d_l2l = nullptr;       // [8][PS][PS]
+    double *d_k64 = nullptr;       // [316][RB][KS][64] swizzled M2L (FP64)
+    float *d_k32 = nullptr;        // same, FP32
+
+    double *d_me = nullptr;        // [n_me][B][PS]
+    double *d_le = nullptr;        // [n_tbox][B][PS]
+    double *d_near = nullptr;      // [M][B][4] near field (phi, gx, gy, gz), sorted order
+
+    int64_t m2l_pairs = 0;         // box pairs translated by M2L (per model)
+    int64_t p2p_pairs = 0;         // point pairs of the near-field sum (per model)
+    size_t bytes_resident = 0, bytes_call = 0;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool has_pending = false;
+
+    bool profiling = false;
+    std::vector<Stage> stages;
+    int n_stage_used = 0;
+};
+
+#define GRAV_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return GRAV_EDEVICE;                                                       \
+    } while (0)
+
+#define GRAV_CHECK(call)                                                               \
+    do {                                                                               \
+        grav_status s_ = (call);                                                       \
+        if (s_ != GRAV_OK)                                                             \
+            return s_;                                                                 \
+    } while (0)
+
+// Morton interleave of 10-bit coordinates (x in bit 0).
+__host__ __device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x000003ffu;
+    return v;
+}
+__host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// Device scans / sorts (sort.hip).
+grav_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                               hipStream_t s);
+size_t scan_tmp_words(int64_t n);
+grav_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp,
+                             uint32_t *vals_tmp, int64_t n, int bits, uint32_t *scratch,
+                             hipStream_t s);
+size_t radix_scratch_words(int64_t n);
+
+// Stage helpers (eval.hip)
+void stage_begin(Plan *p, const char *name, hipStream_t s);
+void stage_end(Plan *p, hipStream_t s);
+
+}  // namespace grav

@@ -1,0 +1,964 @@
+// grav_plan: geometry, device octree build and operator set-up.
+//
+// Internally every length is in cell units with the mesh origin at 0 (the
+// "lattice frame"): cell (i, j, k) spans [i, i+1) x [j, j+1) x [k, k+1), a
+// quadrature point has mass rho * w_a with w_a the rule's weight fraction,
+// and the physical field follows as g = G h g_lat, phi = G h^2 phi_lat.
+// Cell-centre evaluation points are placed at exact half-integers, so a
+// point that coincides with a 1-point source has an exactly zero offset.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+#include "operators.hpp"
+
+namespace grav {
+
+namespace {
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Position (lattice frame) of evaluation point i in descriptor order.
+__device__ inline void target_lattice(int64_t i, const double *pts, int64_t npts, int nx, int ny,
+                                      const double org[3], double inv_h, double out[3])
+{
+    if (i < npts) {
+        out[0] = (pts[3 * i + 0] - org[0]) * inv_h;
+        out[1] = (pts[3 * i + 1] - org[1]) * inv_h;
+        out[2] = (pts[3 * i + 2] - org[2]) * inv_h;
+    } else {
+        const int64_t c = i - npts;
+        const int64_t ix = c % nx;
+        const int64_t iy = (c / nx) % ny;
+        const int64_t iz = c / ((int64_t)nx * ny);
+        out[0] = (double)ix + 0.5;
+        out[1] = (double)iy + 0.5;
+        out[2] = (double)iz + 0.5;
+    }
+}
+
+struct KeyArgs {
+    const double *pts;
+    int64_t npts, M;
+    int nx, ny;
+    double org[3];
+    double inv_h;
+    double shift_lat[3];  // shift * b: lattice distance from root corner to origin
+    double inv_b;
+    int kmax;             // leaves per axis - 1
+    int L;
+};
+
+__global__ void k_target_keys(KeyArgs a, uint32_t *keys, uint32_t *vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.M)
+        return;
+    double u[3];
+    target_lattice(i, a.pts, a.npts, a.nx, a.ny, a.org, a.inv_h, u);
+    uint32_t c[3];
+    for (int d = 0; d < 3; ++d) {
+        double f = floor((u[d] + a.shift_lat[d]) * a.inv_b);
+        f = fmin(fmax(f, 0.0), (double)a.kmax);
+        c[d] = (uint32_t)f;
+    }
+    keys[i] = morton3(c[0], c[1], c[2]);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_gather_targets(KeyArgs a, const uint32_t *perm, double *tpos)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.M)
+        return;
+    double u[3];
+    target_lattice((int64_t)perm[i], a.pts, a.npts, a.nx, a.ny, a.org, a.inv_h, u);
+    tpos[3 * i + 0] = u[0];
+    tpos[3 * i + 1] = u[1];
+    tpos[3 * i + 2] = u[2];
+}
+
+// flags[i] = 1 where (key[i] >> sh) differs from its predecessor.
+__global__ void k_head_flags(const uint32_t *keys, int64_t n, int sh, uint32_t *flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    flags[i] = (i == 0 || (keys[i] >> sh) != (keys[i - 1] >> sh)) ? 1u : 0u;
+}
+
+// Leaf level: sorted target -> leaf id, leaf start offsets, leaf keys.
+__global__ void k_leaf_build(const uint32_t *keys, const uint32_t *flags, const uint32_t *scan,
+                             int64_t n, int32_t *tleaf, int64_t *leaf_start, uint32_t *leaf_key)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t id = scan[i] + flags[i] - 1u;
+    tleaf[i] = (int32_t)id;
+    if (flags[i]) {
+        leaf_start[id] = i;
+        leaf_key[id] = keys[i];
+    }
+}
+
+// Parent level from the sorted child box keys.
+__global__ void k_parent_build(const uint32_t *ckeys, const uint32_t *flags, const uint32_t *scan,
+                               int64_t n, int32_t *cparent, uint32_t *pkeys)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t id = scan[i] + flags[i] - 1u;
+    cparent[i] = (int32_t)id;
+    if (flags[i])
+        pkeys[id] = ckeys[i] >> 3;
+}
+
+__global__ void k_class_keys(const uint32_t *bkeys, int64_t n, uint32_t *ck, uint32_t *cv,
+                             uint32_t *counts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t k = bkeys[i];
+    const uint32_t cls = k & 7u;  // Morton bits 0,1,2 = x, y, z parity
+    ck[i] = cls;
+    cv[i] = (uint32_t)i;
+    atomicAdd(&counts[cls], 1u);
+}
+
+struct CountArgs {
+    int s0[3], ns[3];   // source block of the level
+    int n[3], shift[3];
+    int b, nq3;
+};
+
+// M2L box pairs of one level: in-block offsets of each target box's class list.
+__global__ void k_count_m2l(const uint32_t *bkeys, int64_t n, CountArgs a, const int32_t *cls_off,
+                            unsigned long long *acc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t k = bkeys[i];
+    const int x = (int)compact3(k), y = (int)compact3(k >> 1), z = (int)compact3(k >> 2);
+    const int32_t *o = cls_off + (k & 7u) * kClassOffsets * 4;
+    unsigned long long c = 0;
+    for (int j = 0; j < kClassOffsets; ++j) {
+        const int sx = x + o[4 * j] - a.s0[0], sy = y + o[4 * j + 1] - a.s0[1],
+                  sz = z + o[4 * j + 2] - a.s0[2];
+        if (sx >= 0 && sy >= 0 && sz >= 0 && sx < a.ns[0] && sy < a.ns[1] && sz < a.ns[2])
+            ++c;
+    }
+    atomicAdd(acc, c);
+}
+
+// P2P point pairs: targets of a leaf times source points in its 27 neighbours.
+__global__ void k_count_p2p(const uint32_t *lkeys, const int64_t *leaf_start, int64_t n,
+                            CountArgs a, unsigned long long *acc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t k = lkeys[i];
+    const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+    unsigned long long cells = 0;
+    for (int nb = 0; nb < 27; ++nb) {
+        const int d[3] = {nb % 3 - 1, (nb / 3) % 3 - 1, nb / 9 - 1};
+        unsigned long long leaf_cells = 1;
+        for (int ax = 0; ax < 3; ++ax) {
+            const int lc = c[ax] + d[ax];
+            if (lc - a.s0[ax] < 0 || lc - a.s0[ax] >= a.ns[ax]) {
+                leaf_cells = 0;
+                break;
+            }
+            const int lo = (lc - a.shift[ax]) * a.b;
+            const int hi = min(lo + a.b, a.n[ax]);
+            leaf_cells *= (unsigned long long)max(0, hi - max(lo, 0));
+        }
+        cells += leaf_cells;
+    }
+    atomicAdd(acc, cells * (unsigned long long)a.nq3 * (unsigned long long)(leaf_start[i + 1] - leaf_start[i]));
+}
+
+__global__ void k_fill_last(int64_t *leaf_start, int64_t n_leaf, int64_t M)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        leaf_start[n_leaf] = M;
+}
+
+template <class T>
+grav_status dalloc(Plan *p, T **ptr, size_t count, bool resident)
+{
+    *ptr = nullptr;
+    if (count == 0)
+        return GRAV_OK;
+    if (hipMalloc((void **)ptr, sizeof(T) * count) != hipSuccess) {
+        *ptr = nullptr;
+        return GRAV_ENOMEM;
+    }
+    if (resident)
+        p->bytes_resident += sizeof(T) * count;
+    else
+        p->bytes_call += sizeof(T) * count;
+    return GRAV_OK;
+}
+
+void free_plan(Plan *p)
+{
+    if (!p)
+        return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    void *bufs[] = {p->d_points, p->d_perm, p->d_tpos, p->d_tleaf, p->d_leaf_start, p->d_tkey,
+                    p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_pm, p->d_m2m,
+                    p->d_l2l, p->d_k64, p->d_k32, p->d_me, p->d_le, p->d_near};
+    for (void *b : bufs)
+        if (b)
+            (void)hipFree(b);
+    if (p->done)
+        (void)hipEventDestroy(p->done);
+    for (auto &st : p->stages) {
+        if (st.a)
+            (void)hipEventDestroy(st.a);
+        if (st.b)
+            (void)hipEventDestroy(st.b);
+    }
+    (void)hipSetDevice(cur);
+    delete p;
+}
+
+grav_status validate(const grav_plan_desc *d)
+{
+    if (!d)
+        return GRAV_EINVAL;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return GRAV_EINVAL;
+    if (!(d->h > 0.0) || !std::isfinite(d->h))
+        return GRAV_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->origin[a]))
+            return GRAV_EINVAL;
+    if (d->quad_order != 1 && d->quad_order != 2)
+        return GRAV_EINVAL;
+    if (d->n_points < 0 || (d->n_points > 0 && !d->points))
+        return GRAV_EINVAL;
+    if (d->components != 1 && d->components != 3 && d->components != 4)
+        return GRAV_EINVAL;
+    if (d->p < 1)
+        return GRAV_EINVAL;
+    if (d->p > kMaxP)
+        return GRAV_EUNSUPPORTED;
+    if (d->leaf_size < 1)
+        return GRAV_EINVAL;
+    if (d->precision != GRAV_FP64 && d->precision != GRAV_MIXED)
+        return GRAV_EINVAL;
+    if (d->batch < 1)
+        return GRAV_EINVAL;
+    if (!std::isfinite(d->G))
+        return GRAV_EINVAL;
+    const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
+    const int64_t M = d->n_points + (d->voxel_centres ? ncell : 0);
+    if (M > 0xffffffffll || (int64_t)d->nx > 0x3fffffff)
+        return GRAV_EUNSUPPORTED;
+    return GRAV_OK;
+}
+
+// Enumerate the 316 M2L offsets and, per child-parity class, the 189 valid ones.
+void offsets_tables(std::vector<int> &all, std::vector<int32_t> &cls)
+{
+    all.clear();
+    for (int dz = -3; dz <= 3; ++dz)
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dx = -3; dx <= 3; ++dx)
+                if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) >= 2) {
+                    all.push_back(dx);
+                    all.push_back(dy);
+                    all.push_back(dz);
+                }
+    cls.assign(8 * kClassOffsets * 4, 0);
+    for (int c = 0; c < 8; ++c) {
+        const int par[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+        int cnt = 0;
+        for (int id = 0; id < (int)all.size() / 3; ++id) {
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                const int v = all[3 * id + a];
+                if (v < -2 - par[a] || v > 3 - par[a])
+                    ok = false;
+            }
+            if (!ok)
+                continue;
+            int32_t *e = &cls[(c * kClassOffsets + cnt) * 4];
+            e[0] = all[3 * id];
+            e[1] = all[3 * id + 1];
+            e[2] = all[3 * id + 2];
+            e[3] = id;
+            ++cnt;
+        }
+    }
+}
+
+grav_status build_operators(Plan *p)
+{
+    const int P = p->P, PS = p->PS, KS = p->KS, RB = PS / 16;
+    const int b3 = p->b * p->b * p->b;
+    std::vector<double> pm((size_t)b3 * PS);
+    p2m_lattice(P, p->b, p->q, 1.0, PS, pm.data());
+    GRAV_CHECK(dalloc(p, &p->d_pm, pm.size(), true));
+    GRAV_HIP(hipMemcpy(p->d_pm, pm.data(), sizeof(double) * pm.size(), hipMemcpyHostToDevice));
+
+    // M2M / L2L: stored transposed ([child][in s][out t]) for coalesced reads
+    std::vector<double> m((size_t)PS * PS), m2m(8 * (size_t)PS * PS), l2l(8 * (size_t)PS * PS);
+    for (int c = 0; c < 8; ++c) {
+        const double delta[3] = {((c & 1) - 0.5) * 0.5, (((c >> 1) & 1) - 0.5) * 0.5,
+                                 (((c >> 2) & 1) - 0.5) * 0.5};
+        m2m_matrix(P, delta, PS, m.data());
+        for (int t = 0; t < PS; ++t)
+            for (int s = 0; s < PS; ++s)
+                m2m[((size_t)c * PS + s) * PS + t] = m[(size_t)t * PS + s];
+        l2l_matrix(P, delta, PS, m.data());
+        for (int t = 0; t < PS; ++t)
+            for (int s = 0; s < PS; ++s)
+                l2l[((size_t)c * PS + s) * PS + t] = m[(size_t)t * PS + s];
+    }
+    GRAV_CHECK(dalloc(p, &p->d_m2m, m2m.size(), true));
+    GRAV_CHECK(dalloc(p, &p->d_l2l, l2l.size(), true));
+    GRAV_HIP(hipMemcpy(p->d_m2m, m2m.data(), sizeof(double) * m2m.size(), hipMemcpyHostToDevice));
+    GRAV_HIP(hipMemcpy(p->d_l2l, l2l.data(), sizeof(double) * l2l.size(), hipMemcpyHostToDevice));
+
+    if (p->L < 2)
+        return GRAV_OK;
+    // M2L, swizzled for the 16x16x4 MFMA A operand: [id][ks][rb][lane] holds
+    // K[16 rb + lane % 16][4 ks + lane / 16].
+    std::vector<int> all;
+    std::vector<int32_t> cls;
+    offsets_tables(all, cls);
+    const size_t per = (size_t)KS * RB * 64;
+    std::vector<double> k64(per * kNumOffsets);
+    for (int id = 0; id < kNumOffsets; ++id) {
+        // source = target + d  =>  target centre - source centre = -d
+        const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1],
+                              -(double)all[3 * id + 2]};
+        m2l_matrix(P, dd, PS, m.data());
+        double *dst = k64.data() + per * id;
+        for (int ks = 0; ks < KS; ++ks)
+            for (int rb = 0; rb < RB; ++rb)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int row = 16 * rb + (lane & 15);
+                    const int col = 4 * ks + (lane >> 4);
+                    dst[((size_t)ks * RB + rb) * 64 + lane] = col < PS ? m[(size_t)row * PS + col] : 0.0;
+                }
+    }
+    if (p->d.precision == GRAV_FP64) {
+        GRAV_CHECK(dalloc(p, &p->d_k64, k64.size(), true));
+        GRAV_HIP(hipMemcpy(p->d_k64, k64.data(), sizeof(double) * k64.size(), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> k32(k64.size());
+        for (size_t i = 0; i < k64.size(); ++i)
+            k32[i] = (float)k64[i];
+        GRAV_CHECK(dalloc(p, &p->d_k32, k32.size(), true));
+        GRAV_HIP(hipMemcpy(p->d_k32, k32.data(), sizeof(float) * k32.size(), hipMemcpyHostToDevice));
+    }
+    GRAV_CHECK(dalloc(p, &p->d_class_off, cls.size(), true));
+    GRAV_HIP(hipMemcpy(p->d_class_off, cls.data(), sizeof(int32_t) * cls.size(),
+                       hipMemcpyHostToDevice));
+    return GRAV_OK;
+}
+
+grav_status count_work(Plan *p)
+{
+    unsigned long long *acc = nullptr;
+    GRAV_HIP(hipMalloc(&acc, 2 * sizeof(unsigned long long)));
+    grav_status st = GRAV_OK;
+    do {
+        if (hipMemset(acc, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+            st = GRAV_EDEVICE;
+            break;
+        }
+        CountArgs a{};
+        for (int ax = 0; ax < 3; ++ax) {
+            a.shift[ax] = p->shift[ax];
+        }
+        a.n[0] = p->d.nx;
+        a.n[1] = p->d.ny;
+        a.n[2] = p->d.nz;
+        a.b = p->b;
+        a.nq3 = p->nq3;
+        if (p->L >= 2 && p->d_class_off)
+            for (int l = 2; l <= p->L; ++l) {
+                const int64_t n = p->lev[l].n_tgt;
+                if (n == 0)
+                    continue;
+                for (int ax = 0; ax < 3; ++ax) {
+                    a.s0[ax] = p->lev[l].s0[ax];
+                    a.ns[ax] = p->lev[l].ns[ax];
+                }
+                hipLaunchKernelGGL(k_count_m2l, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, 0,
+                                   (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n, a,
+                                   (const int32_t *)p->d_class_off, acc);
+            }
+        if (p->n_leaf > 0) {
+            for (int ax = 0; ax < 3; ++ax) {
+                a.s0[ax] = p->lev[p->L].s0[ax];
+                a.ns[ax] = p->lev[p->L].ns[ax];
+            }
+            hipLaunchKernelGGL(k_count_p2p, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, 0,
+                               (const uint32_t *)(p->d_tkey + p->tbox_off[p->L]),
+                               (const int64_t *)p->d_leaf_start, p->n_leaf, a, acc + 1);
+        }
+        unsigned long long h[2] = {0, 0};
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpy(h, acc, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+            st = GRAV_EDEVICE;
+            break;
+        }
+        p->m2l_pairs = (int64_t)h[0];
+        p->p2p_pairs = (int64_t)h[1];
+    } while (0);
+    (void)hipFree(acc);
+    return st;
+}
+
+grav_status build_tree(Plan *p, hipStream_t s)
+{
+    const grav_plan_desc &d = p->d;
+    const int64_t M = p->M;
+    const int T = 256;
+    // temporaries (freed at the end)
+    uint32_t *keys = nullptr, *vals = nullptr, *ktmp = nullptr, *vtmp = nullptr;
+    uint32_t *flags = nullptr, *scan = nullptr, *scr = nullptr, *ccount = nullptr;
+    const int64_t nmax = std::max<int64_t>(M, 1);
+    const size_t scr_words = std::max(radix_scratch_words(nmax), scan_tmp_words(nmax));
+    grav_status st = GRAV_OK;
+    auto fail = [&](grav_status e) {
+        st = e;
+        return e;
+    };
+    auto cleanup = [&]() {
+        uint32_t *bufs[] = {keys, vals, ktmp, vtmp, flags, scan, scr, ccount};
+        for (auto *b : bufs)
+            if (b)
+                (void)hipFree(b);
+    };
+    if (hipMalloc(&keys, 4 * nmax) != hipSuccess || hipMalloc(&vals, 4 * nmax) != hipSuccess ||
+        hipMalloc(&ktmp, 4 * nmax) != hipSuccess || hipMalloc(&vtmp, 4 * nmax) != hipSuccess ||
+        hipMalloc(&flags, 4 * nmax) != hipSuccess || hipMalloc(&scan, 4 * nmax) != hipSuccess ||
+        hipMalloc(&scr, 4 * scr_words) != hipSuccess || hipMalloc(&ccount, 4 * 8) != hipSuccess) {
+        cleanup();
+        return GRAV_ENOMEM;
+    }
+
+    KeyArgs ka{};
+    ka.pts = p->d_points;
+    ka.npts = d.n_points;
+    ka.M = M;
+    ka.nx = d.nx;
+    ka.ny = d.ny;
+    for (int a = 0; a < 3; ++a) {
+        ka.org[a] = d.origin[a];
+        ka.shift_lat[a] = (double)p->shift[a] * p->b;
+    }
+    ka.inv_h = 1.0 / d.h;
+    ka.inv_b = 1.0 / p->b;
+    ka.kmax = (1 << p->L) - 1;
+    ka.L = p->L;
+
+    do {
+        if (dalloc(p, &p->d_perm, M, true) || dalloc(p, &p->d_tpos, 3 * M, true) ||
+            dalloc(p, &p->d_tleaf, M, true)) {
+            fail(GRAV_ENOMEM);
+            break;
+        }
+        const unsigned gM = (unsigned)ceil_div(M, T);
+        hipLaunchKernelGGL(k_target_keys, dim3(gM), dim3(T), 0, s, ka, keys, vals);
+        if (hipGetLastError() != hipSuccess) {
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        if (radix_sort_pairs(keys, vals, ktmp, vtmp, M, 3 * p->L, scr, s) != GRAV_OK) {
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        if (hipMemcpyAsync(p->d_perm, vals, 4 * M, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        hipLaunchKernelGGL(k_gather_targets, dim3(gM), dim3(T), 0, s, ka,
+                           (const uint32_t *)p->d_perm, p->d_tpos);
+        // leaf level
+        hipLaunchKernelGGL(k_head_flags, dim3(gM), dim3(T), 0, s, (const uint32_t *)keys, M, 0,
+                           flags);
+        if (scan_exclusive_u32(flags, scan, M, scr, s) != GRAV_OK) {
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        uint32_t last[2] = {0, 0};
+        if (hipMemcpyAsync(&last[0], scan + (M - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&last[1], flags + (M - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        p->n_leaf = (int64_t)last[0] + last[1];
+
+        // Per-level target box counts: leaf level from the scan, parents by
+        // repeated compaction.  Box keys of all levels go into one array.
+        const int L = p->L;
+        const int lo = L >= 2 ? 2 : L;
+        // first pass: compute counts (needs the compaction of each level)
+        std::vector<int64_t> cnt(L + 1, 0);
+        cnt[L] = p->n_leaf;
+        // allocate the per-level arrays with an upper bound n_leaf per level
+        int64_t total = 0;
+        for (int l = lo; l <= L; ++l)
+            total += p->n_leaf;
+        uint32_t *bk = nullptr;
+        int32_t *bp = nullptr;
+        if (hipMalloc(&bk, 4 * std::max<int64_t>(total, 1)) != hipSuccess ||
+            hipMalloc(&bp, 4 * std::max<int64_t>(total, 1)) != hipSuccess) {
+            if (bk)
+                (void)hipFree(bk);
+            fail(GRAV_ENOMEM);
+            break;
+        }
+        // level L at slot 0 of the bound layout
+        std::vector<int64_t> off_bound(L + 1, 0);
+        {
+            int64_t o = 0;
+            for (int l = L; l >= lo; --l) {
+                off_bound[l] = o;
+                o += p->n_leaf;
+            }
+        }
+        if (dalloc(p, &p->d_leaf_start, p->n_leaf + 1, true)) {
+            (void)hipFree(bk);
+            (void)hipFree(bp);
+            fail(GRAV_ENOMEM);
+            break;
+        }
+        hipLaunchKernelGGL(k_leaf_build, dim3(gM), dim3(T), 0, s, (const uint32_t *)keys,
+                           (const uint32_t *)flags, (const uint32_t *)scan, M, p->d_tleaf,
+                           p->d_leaf_start, bk + off_bound[L]);
+        hipLaunchKernelGGL(k_fill_last, dim3(1), dim3(1), 0, s, p->d_leaf_start, p->n_leaf, M);
+        bool ok = true;
+        for (int l = L - 1; l >= lo; --l) {
+            const int64_t nc = cnt[l + 1];
+            const unsigned g = (unsigned)ceil_div(nc, T);
+            hipLaunchKernelGGL(k_head_flags, dim3(g), dim3(T), 0, s,
+                               (const uint32_t *)(bk + off_bound[l + 1]), nc, 3, flags);
+            if (scan_exclusive_u32(flags, scan, nc, scr, s) != GRAV_OK) {
+                ok = false;
+                break;
+            }
+            hipLaunchKernelGGL(k_parent_build, dim3(g), dim3(T), 0, s,
+                               (const uint32_t *)(bk + off_bound[l + 1]), (const uint32_t *)flags,
+                               (const uint32_t *)scan, nc, bp + off_bound[l + 1],
+                               bk + off_bound[l]);
+            if (hipMemcpyAsync(&last[0], scan + (nc - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(&last[1], flags + (nc - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                ok = false;
+                break;
+            }
+            cnt[l] = (int64_t)last[0] + last[1];
+        }
+        if (!ok) {
+            (void)hipFree(bk);
+            (void)hipFree(bp);
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        // compact layout: levels lo..L in increasing order
+        int64_t o = 0;
+        for (int l = 0; l <= kMaxLevels; ++l)
+            p->tbox_off[l] = 0;
+        for (int l = lo; l <= L; ++l) {
+            p->tbox_off[l] = o;
+            p->lev[l].n_tgt = cnt[l];
+            o += cnt[l];
+        }
+        const int64_t nall = std::max<int64_t>(o, 1);
+        if (dalloc(p, &p->d_tkey, nall, true) || dalloc(p, &p->d_tparent, nall, true) ||
+            dalloc(p, &p->d_torder, nall, true)) {
+            (void)hipFree(bk);
+            (void)hipFree(bp);
+            fail(GRAV_ENOMEM);
+            break;
+        }
+        for (int l = lo; l <= L; ++l) {
+            if (hipMemcpyAsync(p->d_tkey + p->tbox_off[l], bk + off_bound[l], 4 * cnt[l],
+                               hipMemcpyDeviceToDevice, s) != hipSuccess)
+                ok = false;
+            if (l > lo) {
+                if (hipMemcpyAsync(p->d_tparent + p->tbox_off[l], bp + off_bound[l], 4 * cnt[l],
+                                   hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    ok = false;
+            } else {
+                if (hipMemsetAsync(p->d_tparent + p->tbox_off[l], 0xff, 4 * cnt[l], s) != hipSuccess)
+                    ok = false;
+            }
+        }
+        if (hipStreamSynchronize(s) != hipSuccess)
+            ok = false;
+        (void)hipFree(bk);
+        (void)hipFree(bp);
+        if (!ok) {
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        p->n_tbox = 0;
+        if (L >= 2)
+            for (int l = 2; l <= L; ++l) {
+                p->lev[l].tgt_off = p->n_tbox;
+                p->n_tbox += cnt[l];
+            }
+
+        // class grouping per level (levels >= 2): a 3-bit radix pass
+        p->tiles_host.clear();
+        for (int l = 2; l <= L && ok; ++l) {
+            const int64_t n = cnt[l];
+            const unsigned g = (unsigned)ceil_div(n, T);
+            if (hipMemsetAsync(ccount, 0, 32, s) != hipSuccess) {
+                ok = false;
+                break;
+            }
+            hipLaunchKernelGGL(k_class_keys, dim3(g), dim3(T), 0, s,
+                               (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n, keys, vals, ccount);
+            if (radix_sort_pairs(keys, vals, ktmp, vtmp, n, 3, scr, s) != GRAV_OK) {
+                ok = false;
+                break;
+            }
+            if (hipMemcpyAsync(p->d_torder + p->tbox_off[l], vals, 4 * n, hipMemcpyDeviceToDevice,
+                               s) != hipSuccess) {
+                ok = false;
+                break;
+            }
+            uint32_t cc[8];
+            if (hipMemcpyAsync(cc, ccount, 32, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                ok = false;
+                break;
+            }
+            int64_t acc = 0;
+            for (int c = 0; c < 8; ++c) {
+                p->lev[l].class_start[c] = acc;
+                const int64_t cols = (int64_t)cc[c] * p->B;
+                for (int64_t c0 = 0; c0 < cols; c0 += kTileCols) {
+                    M2LTile t{};
+                    t.level = l;
+                    t.cls = c;
+                    t.col0 = c0;
+                    t.ncol = (int32_t)std::min<int64_t>(kTileCols, cols - c0);
+                    p->tiles_host.push_back(t);
+                }
+                acc += cc[c];
+            }
+            p->lev[l].class_start[8] = acc;
+        }
+        if (!ok) {
+            fail(GRAV_EDEVICE);
+            break;
+        }
+        p->n_tiles = (int32_t)p->tiles_host.size();
+        if (p->n_tiles > 0) {
+            if (dalloc(p, &p->d_tiles, p->tiles_host.size(), true)) {
+                fail(GRAV_ENOMEM);
+                break;
+            }
+            if (hipMemcpy(p->d_tiles, p->tiles_host.data(), sizeof(M2LTile) * p->tiles_host.size(),
+                          hipMemcpyHostToDevice) != hipSuccess) {
+                fail(GRAV_EDEVICE);
+                break;
+            }
+        }
+    } while (0);
+    cleanup();
+    return st;
+}
+
+}  // namespace
+
+}  // namespace grav
+
+using namespace grav;
+
+extern "C" void grav_desc_init(grav_plan_desc *d)
+{
+    if (!d)
+        return;
+    std::memset(d, 0, sizeof(*d));
+    d->nx = d->ny = d->nz = 1;
+    d->h = 1.0;
+    d->quad_order = 1;
+    d->components = 3;
+    d->p = 8;
+    d->leaf_size = 64;
+    d->precision = GRAV_FP64;
+    d->batch = 1;
+    d->G = 1.0;
+    d->device = 0;
+}
+
+extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
+{
+    if (!out)
+        return GRAV_EINVAL;
+    *out = nullptr;
+    GRAV_CHECK(validate(desc));
+    Plan *p = new (std::nothrow) Plan();
+    if (!p)
+        return GRAV_ENOMEM;
+    p->d = *desc;
+    p->d.points = nullptr;
+    p->device = desc->device;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(desc->device) != hipSuccess) {
+        delete p;
+        return GRAV_EDEVICE;
+    }
+    grav_status st = GRAV_OK;
+    hipStream_t s = nullptr;
+    do {
+        p->P = desc->p;
+        p->P2 = p->P * p->P;
+        p->PS = (int)ceil_div(p->P2, 16) * 16;
+        p->KS = (int)ceil_div(p->P2, 4);
+        p->q = desc->quad_order;
+        p->nq3 = p->q * p->q * p->q;
+        p->B = desc->batch;
+        p->C = desc->components;
+        int b = (int)std::floor(std::cbrt((double)desc->leaf_size / p->nq3) + 1e-9);
+        p->b = std::min(kMaxLeafCells, std::max(1, b));
+        const int n3[3] = {desc->nx, desc->ny, desc->nz};
+        const int64_t ncell = (int64_t)desc->nx * desc->ny * desc->nz;
+        p->M = desc->n_points + (desc->voxel_centres ? ncell : 0);
+        // bounding box of evaluation points in the lattice frame (cell
+        // centres span [1/2, n - 1/2]; the mesh itself is covered separately)
+        double tmin[3] = {0.5, 0.5, 0.5};
+        double tmax[3] = {n3[0] - 0.5, n3[1] - 0.5, n3[2] - 0.5};
+        if (!desc->voxel_centres && desc->n_points > 0)
+            for (int a = 0; a < 3; ++a) {
+                tmin[a] = (desc->points[a] - desc->origin[a]) / desc->h;
+                tmax[a] = tmin[a];
+            }
+        for (int64_t i = 0; i < desc->n_points; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double u = (desc->points[3 * i + a] - desc->origin[a]) / desc->h;
+                if (!std::isfinite(u)) {
+                    st = GRAV_EINVAL;
+                    break;
+                }
+                tmin[a] = std::min(tmin[a], u);
+                tmax[a] = std::max(tmax[a], u);
+            }
+        if (st != GRAV_OK)
+            break;
+        int64_t need = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double sh = std::ceil(-tmin[a] / p->b - 1e-12);
+            p->shift[a] = (int)std::max(0.0, sh);
+            const int64_t src_hi = ceil_div(n3[a], p->b) + p->shift[a];
+            const int64_t tgt_hi = (int64_t)std::floor((tmax[a] + (double)p->shift[a] * p->b) / p->b) + 1;
+            need = std::max(need, std::max(src_hi, tgt_hi));
+        }
+        int L = 0;
+        while ((int64_t(1) << L) < need)
+            ++L;
+        if (L > kMaxLevels) {
+            st = GRAV_EUNSUPPORTED;
+            break;
+        }
+        p->L = L;
+        p->wl = (double)p->b;
+        for (int a = 0; a < 3; ++a)
+            p->root0[a] = -(double)p->shift[a] * p->b;
+        // source blocks per level
+        for (int l = 0; l <= L; ++l) {
+            LevelInfo &lv = p->lev[l];
+            lv.l = l;
+            lv.w = (double)p->b * (double)(int64_t(1) << (L - l));
+            lv.n_src = 1;
+            for (int a = 0; a < 3; ++a) {
+                const int s0 = p->shift[a];
+                const int s1 = p->shift[a] + (int)ceil_div(n3[a], p->b) - 1;
+                lv.s0[a] = s0 >> (L - l);
+                lv.ns[a] = (s1 >> (L - l)) - lv.s0[a] + 1;
+                lv.n_src *= lv.ns[a];
+            }
+        }
+        p->n_me = 0;
+        if (L >= 2)
+            for (int l = 2; l <= L; ++l) {
+                p->lev[l].me_off = p->n_me;
+                p->n_me += p->lev[l].n_src;
+            }
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            st = GRAV_EDEVICE;
+            break;
+        }
+        if (desc->n_points > 0) {
+            if ((st = dalloc(p, &p->d_points, 3 * desc->n_points, true)) != GRAV_OK)
+                break;
+            if (hipMemcpy(p->d_points, desc->points, sizeof(double) * 3 * desc->n_points,
+                          hipMemcpyHostToDevice) != hipSuccess) {
+                st = GRAV_EDEVICE;
+                break;
+            }
+        }
+        if (p->M > 0 && (st = build_tree(p, s)) != GRAV_OK)
+            break;
+        if ((st = build_operators(p)) != GRAV_OK)
+            break;
+        if (p->M > 0 && (st = count_work(p)) != GRAV_OK)
+            break;
+        // workspace
+        if ((st = dalloc(p, &p->d_me, (size_t)p->n_me * p->B * p->PS, false)) != GRAV_OK)
+            break;
+        if ((st = dalloc(p, &p->d_le, (size_t)p->n_tbox * p->B * p->PS, false)) != GRAV_OK)
+            break;
+        if ((st = dalloc(p, &p->d_near, (size_t)p->M * p->B * 4, false)) != GRAV_OK)
+            break;
+        if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
+            st = GRAV_EDEVICE;
+            break;
+        }
+    } while (0);
+    if (s)
+        (void)hipStreamDestroy(s);
+    (void)hipSetDevice(cur);
+    if (st != GRAV_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = reinterpret_cast<grav_plan_t>(p);
+    return GRAV_OK;
+}
+
+extern "C" void grav_plan_destroy(grav_plan_t plan)
+{
+    if (!plan)
+        return;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (p->has_pending && p->done)
+        (void)hipEventSynchronize(p->done);
+    free_plan(p);
+}
+
+extern "C" grav_status grav_plan_bytes(grav_plan_t plan, size_t *resident, size_t *per_call)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (resident)
+        *resident = p->bytes_resident;
+    if (per_call)
+        *per_call = p->bytes_call;
+    return GRAV_OK;
+}
+
+extern "C" grav_status grav_plan_info(grav_plan_t plan, int64_t *n_targets, int32_t *levels,
+                                      int32_t *leaf_cells, int64_t *n_target_leaves)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (n_targets)
+        *n_targets = p->M;
+    if (levels)
+        *levels = p->L;
+    if (leaf_cells)
+        *leaf_cells = p->b;
+    if (n_target_leaves)
+        *n_target_leaves = p->n_leaf;
+    return GRAV_OK;
+}
+
+extern "C" grav_status grav_plan_work(grav_plan_t plan, int64_t *m2l_pairs, int64_t *p2p_pairs,
+                                      int64_t *n_sources)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (m2l_pairs)
+        *m2l_pairs = p->m2l_pairs;
+    if (p2p_pairs)
+        *p2p_pairs = p->p2p_pairs;
+    if (n_sources)
+        *n_sources = (int64_t)p->d.nx * p->d.ny * p->d.nz * p->nq3;
+    return GRAV_OK;
+}
+
+extern "C" grav_status grav_operator(int32_t p, int32_t kind, int32_t which, int32_t dx,
+                                     int32_t dy, int32_t dz, double *out)
+{
+    if (!out || p < 1)
+        return GRAV_EINVAL;
+    if (p > kMaxP)
+        return GRAV_EUNSUPPORTED;
+    const int P2 = p * p;
+    if (kind == 0 || kind == 1) {
+        if (which < 0 || which > 7)
+            return GRAV_EINVAL;
+        const double delta[3] = {((which & 1) - 0.5) * 0.5, (((which >> 1) & 1) - 0.5) * 0.5,
+                                 (((which >> 2) & 1) - 0.5) * 0.5};
+        if (kind == 0)
+            m2m_matrix(p, delta, P2, out);
+        else
+            l2l_matrix(p, delta, P2, out);
+        return GRAV_OK;
+    }
+    if (kind == 2) {
+        const int mx = std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz)));
+        if (mx < 2 || mx > 3)
+            return GRAV_EINVAL;
+        const double d[3] = {-(double)dx, -(double)dy, -(double)dz};
+        m2l_matrix(p, d, P2, out);
+        return GRAV_OK;
+    }
+    return GRAV_EINVAL;
+}
+
+extern "C" grav_status grav_harmonics(int32_t p, int32_t kind, double x, double y, double z,
+                                      double *out)
+{
+    if (!out || p < 1 || (kind != 0 && kind != 1))
+        return GRAV_EINVAL;
+    if (p > kMaxP)
+        return GRAV_EUNSUPPORTED;
+    std::vector<cd> A;
+    if (kind == 0)
+        solid_regular(x, y, z, p, A);
+    else {
+        if (x == 0.0 && y == 0.0 && z == 0.0)
+            return GRAV_EINVAL;
+        solid_irregular(x, y, z, p, A);
+    }
+    for (int n = 0; n < p; ++n) {
+        out[ridx(n, 0, 0)] = A[n * p].real();
+        for (int m = 1; m <= n; ++m) {
+            out[ridx(n, m, 0)] = A[n * p + m].real();
+            out[ridx(n, m, 1)] = A[n * p + m].imag();
+        }
+    }
+    return GRAV_OK;
+}
+
+extern "C" const char *grav_status_string(grav_status s)
+{
+    switch (s) {
+    case GRAV_OK: return "ok";
+    case GRAV_EINVAL: return "invalid argument";
+    case GRAV_ENOMEM: return "out of memory";
+    case GRAV_EDEVICE: return "device error";
+    case GRAV_EUNSUPPORTED: return "unsupported request";
+    case GRAV_EBUSY: return "plan busy on another stream";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *grav_version(void) { return "grav-mi355x 0.1"; }

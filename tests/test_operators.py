@@ -1,0 +1,134 @@
+"""Host FP64 expansion operators of libgrav, checked against direct sums.
+
+These run on the CPU through the C ABI entry points grav_operator and
+grav_harmonics (no device needed).  They pin the real solid-harmonic basis
+and the translation formulas (M2M and L2L exact, M2L convergent in p, the
+far-field expansion of 1/r) independently of the oracle.
+"""
+import numpy as np
+import pytest
+
+import paper_1107_5951_amd as G
+
+
+def _ridx(n, m, part):
+    return n * n if m == 0 else n * n + 2 * m - 1 + part
+
+
+def _p2m(p, src, q, c, w):
+    """Scaled ME: sum q conj(R((x - c)/w)) in the real layout."""
+    me = np.zeros(p * p)
+    for x, qq in zip(src, q):
+        R = G.grav_harmonics(p, 0, *((x - c) / w))
+        v = R.copy()
+        for n in range(p):
+            for m in range(1, n + 1):
+                v[_ridx(n, m, 1)] = -R[_ridx(n, m, 1)]  # conjugate
+        me += qq * v
+    return me
+
+
+def _eval_me(p, me, c, w, x):
+    """phi(x) = sum M_n^m I_n^m(x - c) with M scaled by w^n."""
+    I = G.grav_harmonics(p, 1, *((x - c) / w))
+    s = 0.0
+    for n in range(p):
+        s += me[_ridx(n, 0, 0)] * I[_ridx(n, 0, 0)]
+        for m in range(1, n + 1):
+            mr, mi = me[_ridx(n, m, 0)], me[_ridx(n, m, 1)]
+            ir, ii = I[_ridx(n, m, 0)], I[_ridx(n, m, 1)]
+            s += 2.0 * (mr * ir - mi * ii)
+    return s / w
+
+
+def _eval_le(p, le, c, w, x):
+    """phi(x) = sum L_j^k R_j^k(x - c) with L scaled by w^(j+1)."""
+    R = G.grav_harmonics(p, 0, *((x - c) / w))
+    s = 0.0
+    for n in range(p):
+        s += le[_ridx(n, 0, 0)] * R[_ridx(n, 0, 0)]
+        for m in range(1, n + 1):
+            s += 2.0 * (le[_ridx(n, m, 0)] * R[_ridx(n, m, 0)] - le[_ridx(n, m, 1)] * R[_ridx(n, m, 1)])
+    return s / w
+
+
+def test_low_degree_harmonics_closed_form():
+    x, y, z = 0.3, -0.2, 0.5
+    R = G.grav_harmonics(3, 0, x, y, z)
+    assert R[0] == 1.0
+    np.testing.assert_allclose(R[1:4], [z, x / 2, y / 2], rtol=1e-15)
+    r = np.sqrt(x * x + y * y + z * z)
+    I = G.grav_harmonics(3, 1, x, y, z)
+    np.testing.assert_allclose(I[0:4], [1 / r, z / r ** 3, x / r ** 3, y / r ** 3], rtol=1e-14)
+    # R_2^0 = (2 z^2 - x^2 - y^2) / 4
+    assert R[4] == pytest.approx((2 * z * z - x * x - y * y) / 4, rel=1e-14)
+
+
+def test_multipole_expansion_converges_to_direct():
+    rng = np.random.default_rng(1)
+    src = rng.uniform(-0.5, 0.5, size=(30, 3))
+    q = rng.normal(size=30)
+    x = np.array([1.7, -0.4, 1.1])
+    direct = (q / np.linalg.norm(x - src, axis=1)).sum()
+    errs = []
+    for p in (4, 8, 12, 16):
+        me = _p2m(p, src, q, np.zeros(3), 1.0)
+        errs.append(abs(_eval_me(p, me, np.zeros(3), 1.0, x) - direct) / abs(direct))
+    assert errs[-1] < 1e-6
+    assert all(errs[i + 1] < errs[i] / 5 for i in range(3))
+
+
+@pytest.mark.parametrize("which", range(8))
+def test_m2m_is_exact(which):
+    p = 10
+    rng = np.random.default_rng(which)
+    delta = (np.array([which & 1, (which >> 1) & 1, (which >> 2) & 1]) - 0.5) * 0.5
+    src = delta + rng.uniform(-0.25, 0.25, size=(12, 3))
+    q = rng.normal(size=12)
+    child = _p2m(p, src, q, delta, 0.5)
+    parent = _p2m(p, src, q, np.zeros(3), 1.0)
+    T = G.grav_operator(p, 0, which)
+    np.testing.assert_allclose(T @ child, parent, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("which", [0, 3, 5, 7])
+def test_l2l_is_exact(which):
+    """Re-centring a local expansion onto a child box reproduces it exactly."""
+    p = 10
+    rng = np.random.default_rng(10 + which)
+    le = rng.normal(size=p * p)
+    for n in range(p):
+        le[n * n:(n + 1) * (n + 1)] *= 0.5 ** n
+    delta = (np.array([which & 1, (which >> 1) & 1, (which >> 2) & 1]) - 0.5) * 0.5
+    child = G.grav_operator(p, 1, which) @ le
+    for _ in range(5):
+        y = delta + rng.uniform(-0.25, 0.25, size=3)
+        a = _eval_le(p, le, np.zeros(3), 1.0, y)
+        b = _eval_le(p, child, delta, 0.5, y)
+        assert b == pytest.approx(a, rel=1e-12, abs=1e-14)
+
+
+@pytest.mark.parametrize("d", [(2, 0, 0), (0, -3, 2), (3, 3, 3), (-2, 1, -1)])
+def test_m2l_converges_in_p(d):
+    rng = np.random.default_rng(7)
+    src = rng.uniform(-0.5, 0.5, size=(25, 3)) + np.array(d, float)  # source box at offset d
+    q = rng.normal(size=25)
+    ys = rng.uniform(-0.5, 0.5, size=(6, 3))  # points in the target box (centre 0)
+    direct = np.array([(q / np.linalg.norm(y - src, axis=1)).sum() for y in ys])
+    errs = []
+    for p in (4, 8, 12, 16):
+        me = _p2m(p, src, q, np.array(d, float), 1.0)
+        le = G.grav_operator(p, 2, 0, d) @ me
+        approx = np.array([_eval_le(p, le, np.zeros(3), 1.0, y) for y in ys])
+        errs.append(np.abs(approx - direct).max() / np.abs(direct).max())
+    assert errs[-1] < 5e-5
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+
+
+def test_operator_rejects_bad_arguments():
+    with pytest.raises(G.GravError):
+        G.grav_operator(8, 2, 0, (1, 0, 0))  # a neighbour, not in any interaction list
+    with pytest.raises(G.GravError):
+        G.grav_operator(17, 0, 0)
+    with pytest.raises(G.GravError):
+        G.grav_operator(8, 0, 9)
