@@ -140,6 +140,14 @@ grav_status grav_set_profiling(grav_plan_t plan, int32_t enable);
 grav_status grav_stage_times(grav_plan_t plan, const char **names, double *ms, int32_t n,
                              int32_t *count);
 
+/* Validate a plan's index tables on the host: copies the tables back and
+ * checks, with the same column/term resolvers the kernels use, that every
+ * expansion, matrix, target-range and cell index of every stage lies inside
+ * the buffer it addresses and that no two columns of a stage write the same
+ * expansion.  Launches no compute kernel.  Returns GRAV_OK, or GRAV_EINVAL
+ * with the first violation described in msg (msglen bytes, may be NULL). */
+grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msglen);
+
 /* Operator matrices used by the plan (FP64, row-major, p^2 x p^2, real
  * solid-harmonic basis), for inspection and the operator tests:
  * kind 0 = M2M from child octant `which` (bit 0: +x, bit 1: +y, bit 2: +z)

@@ -57,11 +57,13 @@ def _load():
                                            ctypes.c_int, ctypes.c_int, dp, ctypes.c_int64, dp,
                                            ctypes.c_int, ctypes.c_double, dp]
             lib.oracle_adjoint.argtypes = lib.oracle_forward.argtypes
+            lib.oracle_adjoint_cells.argtypes = lib.oracle_forward.argtypes[:-1] + [
+                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp]
             lib.oracle_points.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int64, dp,
                                           ctypes.c_int, ctypes.c_double, dp]
             lib.oracle_num_threads.argtypes = []
-            for f in (lib.oracle_forward, lib.oracle_adjoint, lib.oracle_points,
-                      lib.oracle_num_threads):
+            for f in (lib.oracle_forward, lib.oracle_adjoint, lib.oracle_adjoint_cells,
+                      lib.oracle_points, lib.oracle_num_threads):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -129,6 +131,34 @@ def adjoint(resid, origin, h, q, shape, targets, comps=3, G=1.0) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_adjoint failed with code %d" % rc)
     return drho[0] if squeeze else drho
+
+
+def adjoint_cells(resid, origin, h, q, shape, targets, cells, comps=3, G=1.0) -> np.ndarray:
+    """:func:`adjoint` evaluated only at the flat cell indices ``cells``.
+
+    Returns ``[len(cells)]`` (or ``[batch, len(cells)]`` for batched resid).
+    """
+    resid = _f64(resid)
+    squeeze = resid.ndim == 2
+    if squeeze:
+        resid = resid[None]
+    batch, m, c = resid.shape
+    if c != comps:
+        raise ValueError("resid has %d components, expected %d" % (c, comps))
+    nz, ny, nx = shape
+    tg = _f64(targets).reshape(-1, 3)
+    if tg.shape[0] != m:
+        raise ValueError("resid and targets disagree on the number of targets")
+    cl = np.ascontiguousarray(cells, dtype=np.int64).reshape(-1)
+    org = _f64(origin).reshape(3)
+    hh = _f64(np.broadcast_to(np.asarray(h, dtype=np.float64), (3,)))
+    out = np.zeros((batch, cl.size), dtype=np.float64)
+    rc = _load().oracle_adjoint_cells(nx, ny, nz, _ptr(org), _ptr(hh), int(q), batch, _ptr(resid),
+                                      m, _ptr(tg), int(comps), float(G), cl.size,
+                                      cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_adjoint_cells failed with code %d" % rc)
+    return out[0] if squeeze else out
 
 
 def points(src, mass, targets, comps=4, G=1.0) -> np.ndarray:

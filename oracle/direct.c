@@ -256,6 +256,79 @@ int oracle_adjoint(int nx, int ny, int nz, const double *origin, const double *h
     return err;
 }
 
+/* Transpose restricted to a list of cells: drho[b][k] for cell index
+ * cells[k] (flat index into [nz][ny][nx]); same pair set and arithmetic as
+ * oracle_adjoint, for sampled checks on large meshes. */
+int oracle_adjoint_cells(int nx, int ny, int nz, const double *origin, const double *h, int q,
+                         int batch, const double *resid, int64_t m, const double *targets,
+                         int comps, double G, int64_t ncells, const int64_t *cells, double *drho)
+{
+    double gx[2], gw[2];
+    int nq = gauss_rule(q, gx, gw);
+    if (nq == 0 || nx < 0 || ny < 0 || nz < 0 || batch < 1 || m < 0 || ncells < 0 ||
+        !valid_comps(comps))
+        return -1;
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    const double vol = h[0] * h[1] * h[2];
+    int err = 0;
+#pragma omp parallel
+    {
+        nsum_t *acc = (nsum_t *)malloc(sizeof(nsum_t) * (size_t)batch);
+        if (!acc) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t kk = 0; kk < ncells; ++kk) {
+            const int64_t cell = cells[kk];
+            if (!acc || cell < 0 || cell >= ncell)
+                continue;
+            const int i = (int)(cell % nx);
+            const int jj = (int)((cell / nx) % ny);
+            const int k = (int)(cell / ((int64_t)nx * ny));
+            const double cx = origin[0] + (i + 0.5) * h[0];
+            const double cy = origin[1] + (jj + 0.5) * h[1];
+            const double cz = origin[2] + (k + 0.5) * h[2];
+            memset(acc, 0, sizeof(nsum_t) * (size_t)batch);
+            for (int a = 0; a < nq; ++a)
+                for (int bq = 0; bq < nq; ++bq)
+                    for (int c = 0; c < nq; ++c) {
+                        const double px = cx + gx[c] * h[0];
+                        const double py = cy + gx[bq] * h[1];
+                        const double pz = cz + gx[a] * h[2];
+                        const double w = vol * gw[a] * gw[bq] * gw[c];
+                        for (int64_t j = 0; j < m; ++j) {
+                            const double dx = targets[3 * j + 0] - px;
+                            const double dy = targets[3 * j + 1] - py;
+                            const double dz = targets[3 * j + 2] - pz;
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            if (r2 == 0.0)
+                                continue;
+                            const double r = sqrt(r2);
+                            const double inv_r = 1.0 / r;
+                            const double inv_r3 = 1.0 / (r2 * r);
+                            for (int b = 0; b < batch; ++b) {
+                                const double *rr = resid + ((int64_t)b * m + j) * comps;
+                                double sv;
+                                if (comps == 1)
+                                    sv = rr[0] * dz * inv_r3;
+                                else if (comps == 3)
+                                    sv = (rr[0] * dx + rr[1] * dy + rr[2] * dz) * inv_r3;
+                                else
+                                    sv = rr[0] * inv_r +
+                                         (rr[1] * dx + rr[2] * dy + rr[3] * dz) * inv_r3;
+                                nsum_add(&acc[b], w * sv);
+                            }
+                        }
+                    }
+            for (int b = 0; b < batch; ++b)
+                drho[b * ncells + kk] = G * nsum_value(&acc[b]);
+        }
+        free(acc);
+    }
+    return err;
+}
+
 /* Direct sum over an explicit list of point masses (no lattice): used by the
  * tests that pin the voxel path to plain point-mass physics. */
 int oracle_points(int64_t n, const double *src, const double *mass, int64_t m,

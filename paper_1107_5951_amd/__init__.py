@@ -130,6 +130,12 @@ class Plan:
               "grav_plan_work")
         return a.value, b.value, c.value
 
+    def check(self) -> str:
+        """Host validation of the plan's index tables ('ok' or the first violation)."""
+        buf = ctypes.create_string_buffer(512)
+        load().grav_plan_check(self.handle, buf, 512)
+        return buf.value.decode()
+
     def eval(self, rho, out=None, stream=None):
         """g = A rho for a float64 device tensor rho [B, nz, ny, nx] (or [nz, ny, nx])."""
         import torch

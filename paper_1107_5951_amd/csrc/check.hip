@@ -1,0 +1,226 @@
+// grav_plan_check: host-side validation of a plan's index tables.
+//
+// Copies the plan's device tables back and runs, on the host, the same
+// column/term resolvers the M2L kernels use (they are compiled for both
+// sides), plus the tree tables the other kernels index,
+// checking every expansion, matrix, target-range and cell index against the
+// size of the buffer it addresses, and that no two columns of one stage
+// write the same expansion.  No compute kernel is launched.
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "resolve.hpp"
+
+namespace grav {
+
+namespace {
+
+template <class T>
+std::vector<T> fetch(const T *d, size_t n)
+{
+    std::vector<T> h(n);
+    if (n && d && hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+        h.clear();
+    return h;
+}
+
+struct Checker {
+    bool ok = true;
+    std::string msg;
+    void fail(const char *stage, const char *what, long long a, long long b)
+    {
+        if (ok) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf, "%s: %s (%lld vs %lld)", stage, what, a, b);
+            msg = buf;
+        }
+        ok = false;
+    }
+};
+
+// Tiles of a stage whose offsets are split S ways: tile.pad in [0, S) names
+// the offset range [pad * 189 / S, (pad + 1) * 189 / S) and, for S > 1, the
+// slab of the partial-sum workspace it writes ([S][ysize] expansions).
+template <class Res>
+void check_stage(Checker &ck, const char *name, const Res &res, const TileRange &r, int S,
+                 int64_t n_ids, int64_t xsize, int64_t ysize, std::vector<char> &written)
+{
+    written.assign((size_t)(S > 1 ? S : 1) * ysize, 0);
+    for (int64_t b = 0; b < r.n && ck.ok; ++b) {
+        const GemmTile &tile = res.tiles[b];
+        if (tile.ncol < 1 || tile.ncol > kTileCols)
+            ck.fail(name, "tile width out of range", tile.ncol, kTileCols);
+        if (tile.pad < 0 || tile.pad >= S)
+            ck.fail(name, "split index out of range", tile.pad, S);
+        if (!ck.ok)
+            break;
+        const int t0 = tile.pad * res.nterms(tile) / S, t1 = (tile.pad + 1) * res.nterms(tile) / S;
+        for (int cl = 0; cl < kTileCols && ck.ok; ++cl) {
+            const GemmCol col = res.column(tile, cl);
+            if (!col.valid)
+                continue;
+            for (int it = t0; it < t1; ++it) {
+                const GemmTerm tm = res.term(tile, it);
+                if (tm.kid < 0 || tm.kid >= n_ids)
+                    ck.fail(name, "matrix id out of range", tm.kid, n_ids);
+                const int64_t s = res.src(tile, col, tm);
+                if (s < -1 || s >= xsize)
+                    ck.fail(name, "source expansion out of range", s, xsize);
+            }
+            const int64_t o = res.out(tile, col);
+            if (o < 0 || o >= ysize) {
+                ck.fail(name, "destination expansion out of range", o, ysize);
+            } else {
+                const int64_t w = (S > 1 ? tile.pad : 0) * ysize + o;
+                if (written[w])
+                    ck.fail(name, "two columns write one expansion", o, ysize);
+                written[w] = 1;
+            }
+        }
+    }
+    for (size_t i = 0; i < written.size() && ck.ok; ++i)
+        if (!written[i])
+            ck.fail(name, "expansion never written", (long long)i, ysize);
+}
+
+}  // namespace
+
+}  // namespace grav
+
+using namespace grav;
+
+extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msglen)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    Checker ck;
+    auto report = [&]() {
+        if (msg && msglen > 0) {
+            std::snprintf(msg, (size_t)msglen, "%s", ck.ok ? "ok" : ck.msg.c_str());
+        }
+        return ck.ok ? GRAV_OK : GRAV_EINVAL;
+    };
+    if (p->M == 0)
+        return report();
+    int cur = 0;
+    GRAV_HIP(hipGetDevice(&cur));
+    GRAV_HIP(hipSetDevice(p->device));
+    GRAV_HIP(hipDeviceSynchronize());
+    const DevGeom g = make_geom(p);
+    const int L = p->L;
+    int64_t ntile = 0;
+    for (int k = 0; k < TK_COUNT; ++k)
+        for (int l = 0; l <= kMaxLevels; ++l)
+            ntile = std::max<int64_t>(ntile, p->tiles[k][l].off + p->tiles[k][l].n);
+    int64_t ntb = 0;
+    const int lo = L >= 2 ? 2 : L;
+    for (int l = lo; l <= L; ++l)
+        ntb = std::max<int64_t>(ntb, p->tbox_off[l] + p->lev[l].n_tgt);
+    const auto tiles = fetch(p->d_tiles, (size_t)ntile);
+    const auto tkey = fetch(p->d_tkey, (size_t)ntb);
+    const auto torder = fetch(p->d_torder, (size_t)ntb);
+    const auto tparent = fetch(p->d_tparent, (size_t)ntb);
+    const auto tmap = fetch(p->d_tmap, (size_t)p->n_tmap);
+    const auto tchild = fetch(p->d_tchild, (size_t)p->n_tchild);
+    const auto leaf_start = fetch(p->d_leaf_start, (size_t)p->n_leaf + 1);
+    const auto tleaf = fetch(p->d_tleaf, (size_t)p->M);
+    const auto perm = fetch(p->d_perm, (size_t)p->M);
+    std::vector<int32_t> coff, roff;
+    if (L >= 2) {
+        coff = fetch(p->d_class_off, 8 * kClassOffsets * 4);
+        roff = fetch(p->d_rclass_off, 8 * kClassOffsets * 4);
+    }
+    (void)hipSetDevice(cur);
+
+    // target tables
+    for (int64_t i = 0; i < p->n_leaf && ck.ok; ++i)
+        if (leaf_start[i] >= leaf_start[i + 1])
+            ck.fail("tree", "empty or unordered leaf range", leaf_start[i], leaf_start[i + 1]);
+    if (ck.ok && leaf_start[p->n_leaf] != p->M)
+        ck.fail("tree", "leaf ranges do not cover the targets", leaf_start[p->n_leaf], p->M);
+    std::vector<char> seen(p->M, 0);
+    for (int64_t i = 0; i < p->M && ck.ok; ++i) {
+        if (tleaf[i] < 0 || tleaf[i] >= p->n_leaf)
+            ck.fail("tree", "target leaf out of range", tleaf[i], p->n_leaf);
+        else if (i < leaf_start[tleaf[i]] || i >= leaf_start[tleaf[i] + 1])
+            ck.fail("tree", "target outside its leaf range", i, tleaf[i]);
+        if (perm[i] >= (uint64_t)p->M || seen[perm[i]])
+            ck.fail("tree", "permutation not a bijection", perm[i], p->M);
+        else
+            seen[perm[i]] = 1;
+    }
+    for (int l = lo; l <= L && ck.ok; ++l) {
+        const DevLev &lv = g.lev[l];
+        for (int64_t i = 0; i < p->lev[l].n_tgt && ck.ok; ++i) {
+            const uint32_t k = tkey[lv.tbox_off + i];
+            if (i > 0 && k <= tkey[lv.tbox_off + i - 1])
+                ck.fail("tree", "box keys not strictly increasing", l, i);
+            if (l > lo) {
+                const int32_t par = tparent[lv.tbox_off + i];
+                if (par < 0 || par >= p->lev[l - 1].n_tgt)
+                    ck.fail("tree", "parent out of range", par, p->lev[l - 1].n_tgt);
+                else if (tkey[g.lev[l - 1].tbox_off + par] != (k >> 3))
+                    ck.fail("tree", "parent key mismatch", l, i);
+            }
+            if (l >= 2) {
+                const int32_t o = torder[lv.tbox_off + i];
+                if (o < 0 || o >= p->lev[l].n_tgt)
+                    ck.fail("tree", "class order out of range", o, p->lev[l].n_tgt);
+            }
+        }
+        // target map entries
+        const int64_t msz = (int64_t)(lv.ns[0] + 6) * (lv.ns[1] + 6) * (lv.ns[2] + 6);
+        for (int64_t i = 0; i < msz && ck.ok; ++i) {
+            const int32_t v = tmap[lv.tmap_off + i];
+            if (v < -1 || v >= p->lev[l].n_tgt)
+                ck.fail("tmap", "entry out of range", v, p->lev[l].n_tgt);
+        }
+    }
+    for (int l = 2; l < L && ck.ok; ++l) {
+        const DevLev &lv = g.lev[l];
+        for (int64_t i = 0; i < p->lev[l].n_tgt && ck.ok; ++i) {
+            const int32_t a = tchild[lv.tchild_off + i], b = tchild[lv.tchild_off + i + 1];
+            if (!(0 <= a && a < b && b <= p->lev[l + 1].n_tgt && b - a <= 8))
+                ck.fail("tchild", "bad child range", a, b);
+        }
+    }
+    // near field / leaf kernels: neighbour leaves within the source block or skipped
+    if (ck.ok && L >= 0) {
+        const DevLev &lv = g.lev[L];
+        for (int64_t i = 0; i < p->n_leaf && ck.ok; ++i) {
+            const uint32_t k = tkey[lv.tbox_off + i];
+            const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+            for (int a = 0; a < 3; ++a)
+                if (c[a] >= (1 << L))
+                    ck.fail("leaf", "leaf coordinate outside the root", c[a], 1 << L);
+        }
+    }
+
+    if (L >= 2 && ck.ok) {
+        const int64_t xme = p->n_me * p->B, xle = p->n_tbox * p->B;
+        std::vector<char> w;
+        {
+            const TileRange &r = p->tiles[TK_M2L][0];
+            ResM2L res{&g, tiles.data() + r.off, tkey.data(), torder.data(), coff.data()};
+            check_stage(ck, "m2l", res, r, p->split[TK_M2L], kNumOffsets, xme, xle, w);
+        }
+        {
+            const TileRange &r = p->tiles[TK_M2LT][0];
+            ResM2LT res{&g, tiles.data() + r.off, tmap.data(), roff.data()};
+            check_stage(ck, "m2lT", res, r, p->split[TK_M2LT], kNumOffsets, xle, xme, w);
+        }
+        // M2M / M2M^T: every parent of a level >= 3 box lies in the block above
+        for (int l = 3; l <= L && ck.ok; ++l) {
+            const DevLev &lv = g.lev[l];
+            for (int z = 0; z < lv.ns[2] && ck.ok; ++z)
+                for (int y = 0; y < lv.ns[1] && ck.ok; ++y)
+                    for (int x = 0; x < lv.ns[0] && ck.ok; ++x)
+                        if (dense_index(g.lev[l - 1], (lv.s0[0] + x) >> 1, (lv.s0[1] + y) >> 1,
+                                        (lv.s0[2] + z) >> 1) < 0)
+                            ck.fail("m2mT", "parent outside the source block", l, x);
+        }
+    }
+    return report();
+}

@@ -5,7 +5,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "eval_common.hpp"
+#include "resolve.hpp"
 
 namespace grav {
 
@@ -98,9 +98,9 @@ __global__ void __launch_bounds__(256) k_m2m(DevGeom g, int l, const double *m2m
 // Accumulation stays in registers across all offsets; no atomics.
 // --------------------------------------------------------------------------
 template <int RB, typename T>
-__device__ inline void m2l_body(const DevGeom &g, const M2LTile &tile, const uint32_t *tkey,
+__device__ inline void m2l_body(const DevGeom &g, const GemmTile &tile, const uint32_t *tkey,
                                 const int32_t *torder, const int32_t *class_off, const T *K,
-                                const double *me, double *le)
+                                const double *me, double *le, int S, int64_t part_stride)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     const int lane = threadIdx.x & 63;
@@ -126,7 +126,9 @@ __device__ inline void m2l_body(const DevGeom &g, const M2LTile &tile, const uin
         acc[rb] = vec4{0, 0, 0, 0};
     const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
     const int krow = lane >> 4;
-    for (int o = 0; o < kClassOffsets; ++o) {
+    // offsets [o0, o1) of this split (tile.pad of S)
+    const int o0 = tile.pad * kClassOffsets / S, o1 = (tile.pad + 1) * kClassOffsets / S;
+    for (int o = o0; o < o1; ++o) {
         const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
         const int id = offs[4 * o + 3];
         const int sx = bx + dx - lv.s0[0], sy = by + dy - lv.s0[1], sz = bz + dz - lv.s0[2];
@@ -153,7 +155,8 @@ __device__ inline void m2l_body(const DevGeom &g, const M2LTile &tile, const uin
         return;
     // Output fragment: lane holds column lane % 16 and four rows; the FP32
     // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
-    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * g.PS;
+    // (split partials go to their own slab of the workspace)
+    double *dst = le + (tile.pad * part_stride + (lv.tgt_off + box) * g.B + bm) * g.PS;
     constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
     const int rbase = sizeof(T) == 8 ? krow : 4 * krow;
 #pragma unroll
@@ -165,10 +168,22 @@ __device__ inline void m2l_body(const DevGeom &g, const M2LTile &tile, const uin
 
 template <int RB, typename T>
 __global__ void __launch_bounds__(256)
-k_m2l(DevGeom g, const M2LTile *tiles, const uint32_t *tkey, const int32_t *torder,
-      const int32_t *class_off, const T *K, const double *me, double *le)
+k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
+      const int32_t *class_off, const T *K, const double *me, double *le, int S, int64_t part_stride)
 {
-    m2l_body<RB, T>(g, tiles[blockIdx.x], tkey, torder, class_off, K, me, le);
+    m2l_body<RB, T>(g, tiles[blockIdx.x], tkey, torder, class_off, K, me, le, S, part_stride);
+}
+
+// out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ...
+__global__ void __launch_bounds__(256) k_sum_parts(const double *part, int S, int64_t n, double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double acc = part[i];
+    for (int s = 1; s < S; ++s)
+        acc += part[(int64_t)s * n + i];
+    out[i] = acc;
 }
 
 // --------------------------------------------------------------------------
@@ -399,6 +414,8 @@ DevGeom make_geom(const Plan *p)
         d.tbox_off = p->tbox_off[l];
         for (int c = 0; c < 9; ++c)
             d.class_start[c] = s.class_start[c];
+        d.tmap_off = s.tmap_off;
+        d.tchild_off = s.tchild_off;
     }
     g.L = p->L;
     g.b = p->b;
@@ -447,13 +464,19 @@ template <typename T>
 static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
 {
     const int RB = p->PS / 16;
-    dim3 grid(p->n_tiles), blk(256);
+    const TileRange &r = p->tiles[TK_M2L][0];
+    if (r.n == 0)
+        return GRAV_OK;
+    dim3 grid(r.n), blk(256);
+    const int S = p->split[TK_M2L];
+    const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
+    double *dst = S > 1 ? p->d_part : p->d_le;
 #define M2L_CASE(R)                                                                             \
     case R:                                                                                     \
-        hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const M2LTile *)p->d_tiles,     \
+        hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off),     \
                            (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
-                           (const int32_t *)p->d_class_off, K, (const double *)p->d_me,         \
-                           p->d_le);                                                            \
+                           (const int32_t *)p->d_class_off, K, (const double *)p->d_me, dst,    \
+                           S, pstride);                                                         \
         break;
     switch (RB) {
         M2L_CASE(1)
@@ -473,6 +496,12 @@ static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T 
     }
 #undef M2L_CASE
     GRAV_HIP(hipGetLastError());
+    if (S > 1) {
+        const int64_t n = pstride * p->PS;
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const double *)p->d_part, S, n, p->d_le);
+        GRAV_HIP(hipGetLastError());
+    }
     return GRAV_OK;
 }
 
@@ -498,12 +527,10 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         }
         stage_end(p, s);
         stage_begin(p, "m2l", s);
-        if (p->n_tiles > 0) {
-            if (p->d.precision == GRAV_FP64)
-                GRAV_CHECK(launch_m2l<double>(p, g, s, p->d_k64));
-            else
-                GRAV_CHECK(launch_m2l<float>(p, g, s, p->d_k32));
-        }
+        if (p->d.precision == GRAV_FP64)
+            GRAV_CHECK(launch_m2l<double>(p, g, s, p->d_k64));
+        else
+            GRAV_CHECK(launch_m2l<float>(p, g, s, p->d_k32));
         stage_end(p, s);
         stage_begin(p, "l2l", s);
         for (int l = 3; l <= L; ++l) {

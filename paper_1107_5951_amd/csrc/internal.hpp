@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/grav.h"
+#include "grav.h"
 
 namespace grav {
 
@@ -28,14 +28,17 @@ struct LevelInfo {
     int64_t n_tgt = 0;                // boxes holding evaluation points
     int64_t tgt_off = 0;              // offset of this level in the per-target-box arrays
     int64_t class_start[9] = {0};     // class-grouped order boundaries
+    int64_t tmap_off = 0;             // offset of this level's target map (source block + halo 3)
+    int64_t tchild_off = 0;           // offset of this level's first-child table
+    int64_t src_class[8] = {0};       // source boxes of each parity class
 };
 
-struct M2LTile {
-    int32_t level;
-    int32_t cls;
-    int64_t col0;    // first column (class-ordered box position * B + model)
-    int32_t ncol;    // columns in this tile (<= kTileCols)
-    int32_t pad;
+// Tiled stages: forward and transposed M2L.
+enum TileKind { TK_M2L = 0, TK_M2LT, TK_COUNT };
+
+struct TileRange {
+    int64_t off = 0;
+    int32_t n = 0;
 };
 
 struct Stage {
@@ -59,7 +62,7 @@ struct Plan {
     LevelInfo lev[kMaxLevels + 1];
     int64_t n_me = 0, n_le = 0;    // expansions (per model) in the ME / LE arrays
     int64_t n_tbox = 0;            // target boxes over all levels >= 2
-    std::vector<M2LTile> tiles_host;
+    int64_t n_tmap = 0, n_tchild = 0;
 
     // device buffers
     double *d_points = nullptr;    // [n_points][3] user points (unsorted)
@@ -71,15 +74,23 @@ struct Plan {
     int32_t *d_tparent = nullptr;  // [n_tbox_all] index (within its level) of the parent box
     int32_t *d_torder = nullptr;   // [n_tbox_all] class-grouped order -> box index (per level)
     int64_t tbox_off[kMaxLevels + 1] = {0}; // start of each level in the three arrays above
-    M2LTile *d_tiles = nullptr;
-    int32_t n_tiles = 0;
-    int32_t *d_class_off = nullptr; // [8][kClassOffsets][4] (dx, dy, dz, offset id)
+    struct GemmTile *d_tiles = nullptr;            // all M2L tiles
+    TileRange tiles[TK_COUNT][kMaxLevels + 1];     // per stage (slot 0: all levels)
+    int split[TK_COUNT] = {1, 1};                  // workgroups sharing the offsets of one tile
+    double *d_part = nullptr;                      // [split][expansions][PS] partial sums
+    int32_t *d_class_off = nullptr;  // [8][189][4] (dx, dy, dz, offset id)
+    int32_t *d_rclass_off = nullptr; // same for the transposed M2L, keyed by source class
+    int32_t *d_tmap = nullptr;       // per level: target-box index over source block + halo 3
+    int32_t *d_tchild = nullptr;     // per level: first child (in level l+1) of each box, + sentinel
+    struct DevGeom *d_geom = nullptr;
 
     double *d_pm = nullptr;        // [b^3][PS] lattice P2M
-    double *d_m2m = nullptr;       // [8][PS][PS]
-    double *d_l2l = nullptr;       // [8][PS][PS]
-    double *d_k64 = nullptr;       // [316][RB][KS][64] swizzled M2L (FP64)
-    float *d_k32 = nullptr;        // same, FP32
+    double *d_m2m = nullptr;       // [8][PS][PS] M2M, stored [child][in][out]
+    double *d_l2l = nullptr;       // [8][PS][PS] L2L, stored [child][in][out]
+    double *d_k64 = nullptr;       // [316][KS][RB][64] swizzled M2L (FP64)
+    double *d_k64T = nullptr;      // transposes
+    float *d_k32 = nullptr;        // same, FP32 (mixed precision)
+    float *d_k32T = nullptr;
 
     double *d_me = nullptr;        // [n_me][B][PS]
     double *d_le = nullptr;        // [n_tbox][B][PS]

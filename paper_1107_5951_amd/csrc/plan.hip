@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 
+#include "resolve.hpp"
 #include "internal.hpp"
 #include "operators.hpp"
 
@@ -215,8 +216,10 @@ void free_plan(Plan *p)
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(p->device);
     void *bufs[] = {p->d_points, p->d_perm, p->d_tpos, p->d_tleaf, p->d_leaf_start, p->d_tkey,
-                    p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_pm, p->d_m2m,
-                    p->d_l2l, p->d_k64, p->d_k32, p->d_me, p->d_le, p->d_near};
+                    p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
+                    p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
+                    p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
+                    p->d_le, p->d_near, p->d_part};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -268,8 +271,11 @@ grav_status validate(const grav_plan_desc *d)
     return GRAV_OK;
 }
 
-// Enumerate the 316 M2L offsets and, per child-parity class, the 189 valid ones.
-void offsets_tables(std::vector<int> &all, std::vector<int32_t> &cls)
+// The 316 M2L offsets (2 <= |d|_inf <= 3), and per child-parity class the
+// 189 valid ones, entries (dx, dy, dz, offset id).  Forward: a target box of
+// class c sees sources at T + d for d_a in [-2 - c_a, 3 - c_a].  Transposed:
+// a source box S of class c feeds targets T = S - d whose class admits d.
+void offsets_tables(std::vector<int> &all, std::vector<int32_t> &fwd, std::vector<int32_t> &rev)
 {
     all.clear();
     for (int dz = -3; dz <= 3; ++dz)
@@ -280,27 +286,55 @@ void offsets_tables(std::vector<int> &all, std::vector<int32_t> &cls)
                     all.push_back(dy);
                     all.push_back(dz);
                 }
-    cls.assign(8 * kClassOffsets * 4, 0);
+    fwd.assign(8 * kClassOffsets * 4, 0);
+    rev.assign(8 * kClassOffsets * 4, 0);
     for (int c = 0; c < 8; ++c) {
-        const int par[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-        int cnt = 0;
+        int nf = 0, nr = 0;
         for (int id = 0; id < (int)all.size() / 3; ++id) {
-            bool ok = true;
+            const int *d = &all[3 * id];
+            bool okf = true, okr = true;
             for (int a = 0; a < 3; ++a) {
-                const int v = all[3 * id + a];
-                if (v < -2 - par[a] || v > 3 - par[a])
-                    ok = false;
+                const int pc = (c >> a) & 1;           // target class bit (forward)
+                if (d[a] < -2 - pc || d[a] > 3 - pc)
+                    okf = false;
+                const int pt = ((c >> a) - d[a]) & 1;  // class bit of T = S - d
+                if (d[a] < -2 - pt || d[a] > 3 - pt)
+                    okr = false;
             }
-            if (!ok)
-                continue;
-            int32_t *e = &cls[(c * kClassOffsets + cnt) * 4];
-            e[0] = all[3 * id];
-            e[1] = all[3 * id + 1];
-            e[2] = all[3 * id + 2];
-            e[3] = id;
-            ++cnt;
+            if (okf) {
+                int32_t *e = &fwd[(c * kClassOffsets + nf++) * 4];
+                e[0] = d[0], e[1] = d[1], e[2] = d[2], e[3] = id;
+            }
+            if (okr) {
+                int32_t *e = &rev[(c * kClassOffsets + nr++) * 4];
+                e[0] = d[0], e[1] = d[1], e[2] = d[2], e[3] = id;
+            }
         }
     }
+}
+
+// Swizzle a dense [PS][PS] matrix (or its transpose) into the MFMA A-operand
+// order [ks][rb][lane] = K[16 rb + lane % 16][4 ks + lane / 16].
+void swizzle(const double *m, int PS, int KS, bool transpose, double *dst)
+{
+    const int RB = PS / 16;
+    for (int ks = 0; ks < KS; ++ks)
+        for (int rb = 0; rb < RB; ++rb)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = 16 * rb + (lane & 15);
+                const int col = 4 * ks + (lane >> 4);
+                dst[((size_t)ks * RB + rb) * 64 + lane] =
+                    transpose ? m[(size_t)col * PS + row] : m[(size_t)row * PS + col];
+            }
+}
+
+template <class T>
+grav_status upload(Plan *p, T **dst, const std::vector<T> &src)
+{
+    GRAV_CHECK(dalloc(p, dst, src.size(), true));
+    if (!src.empty())
+        GRAV_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return GRAV_OK;
 }
 
 grav_status build_operators(Plan *p)
@@ -309,64 +343,190 @@ grav_status build_operators(Plan *p)
     const int b3 = p->b * p->b * p->b;
     std::vector<double> pm((size_t)b3 * PS);
     p2m_lattice(P, p->b, p->q, 1.0, PS, pm.data());
-    GRAV_CHECK(dalloc(p, &p->d_pm, pm.size(), true));
-    GRAV_HIP(hipMemcpy(p->d_pm, pm.data(), sizeof(double) * pm.size(), hipMemcpyHostToDevice));
+    GRAV_CHECK(upload(p, &p->d_pm, pm));
+    if (p->L < 2)
+        return GRAV_OK;
 
-    // M2M / L2L: stored transposed ([child][in s][out t]) for coalesced reads
+    // M2M / L2L: [child][in s][out t] (the transpose of the matrix), so that
+    // thread t of the forward kernels reads consecutive entries
     std::vector<double> m((size_t)PS * PS), m2m(8 * (size_t)PS * PS), l2l(8 * (size_t)PS * PS);
     for (int c = 0; c < 8; ++c) {
         const double delta[3] = {((c & 1) - 0.5) * 0.5, (((c >> 1) & 1) - 0.5) * 0.5,
                                  (((c >> 2) & 1) - 0.5) * 0.5};
         m2m_matrix(P, delta, PS, m.data());
         for (int t = 0; t < PS; ++t)
-            for (int s = 0; s < PS; ++s)
-                m2m[((size_t)c * PS + s) * PS + t] = m[(size_t)t * PS + s];
+            for (int s2 = 0; s2 < PS; ++s2)
+                m2m[((size_t)c * PS + s2) * PS + t] = m[(size_t)t * PS + s2];
         l2l_matrix(P, delta, PS, m.data());
         for (int t = 0; t < PS; ++t)
-            for (int s = 0; s < PS; ++s)
-                l2l[((size_t)c * PS + s) * PS + t] = m[(size_t)t * PS + s];
+            for (int s2 = 0; s2 < PS; ++s2)
+                l2l[((size_t)c * PS + s2) * PS + t] = m[(size_t)t * PS + s2];
     }
-    GRAV_CHECK(dalloc(p, &p->d_m2m, m2m.size(), true));
-    GRAV_CHECK(dalloc(p, &p->d_l2l, l2l.size(), true));
-    GRAV_HIP(hipMemcpy(p->d_m2m, m2m.data(), sizeof(double) * m2m.size(), hipMemcpyHostToDevice));
-    GRAV_HIP(hipMemcpy(p->d_l2l, l2l.data(), sizeof(double) * l2l.size(), hipMemcpyHostToDevice));
+    GRAV_CHECK(upload(p, &p->d_m2m, m2m));
+    GRAV_CHECK(upload(p, &p->d_l2l, l2l));
 
-    if (p->L < 2)
-        return GRAV_OK;
-    // M2L, swizzled for the 16x16x4 MFMA A operand: [id][ks][rb][lane] holds
-    // K[16 rb + lane % 16][4 ks + lane / 16].
+    // M2L for all 316 offsets, swizzled for the MFMA A operand, and transposes
     std::vector<int> all;
-    std::vector<int32_t> cls;
-    offsets_tables(all, cls);
+    std::vector<int32_t> fwd, rev;
+    offsets_tables(all, fwd, rev);
     const size_t per = (size_t)KS * RB * 64;
-    std::vector<double> k64(per * kNumOffsets);
+    std::vector<double> k(per * kNumOffsets), kT(per * kNumOffsets);
     for (int id = 0; id < kNumOffsets; ++id) {
         // source = target + d  =>  target centre - source centre = -d
-        const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1],
-                              -(double)all[3 * id + 2]};
+        const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
         m2l_matrix(P, dd, PS, m.data());
-        double *dst = k64.data() + per * id;
-        for (int ks = 0; ks < KS; ++ks)
-            for (int rb = 0; rb < RB; ++rb)
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int row = 16 * rb + (lane & 15);
-                    const int col = 4 * ks + (lane >> 4);
-                    dst[((size_t)ks * RB + rb) * 64 + lane] = col < PS ? m[(size_t)row * PS + col] : 0.0;
-                }
+        swizzle(m.data(), PS, KS, false, k.data() + per * id);
+        swizzle(m.data(), PS, KS, true, kT.data() + per * id);
     }
     if (p->d.precision == GRAV_FP64) {
-        GRAV_CHECK(dalloc(p, &p->d_k64, k64.size(), true));
-        GRAV_HIP(hipMemcpy(p->d_k64, k64.data(), sizeof(double) * k64.size(), hipMemcpyHostToDevice));
+        GRAV_CHECK(upload(p, &p->d_k64, k));
+        GRAV_CHECK(upload(p, &p->d_k64T, kT));
     } else {
-        std::vector<float> k32(k64.size());
-        for (size_t i = 0; i < k64.size(); ++i)
-            k32[i] = (float)k64[i];
-        GRAV_CHECK(dalloc(p, &p->d_k32, k32.size(), true));
-        GRAV_HIP(hipMemcpy(p->d_k32, k32.data(), sizeof(float) * k32.size(), hipMemcpyHostToDevice));
+        std::vector<float> k32(k.begin(), k.end()), k32T(kT.begin(), kT.end());
+        GRAV_CHECK(upload(p, &p->d_k32, k32));
+        GRAV_CHECK(upload(p, &p->d_k32T, k32T));
     }
-    GRAV_CHECK(dalloc(p, &p->d_class_off, cls.size(), true));
-    GRAV_HIP(hipMemcpy(p->d_class_off, cls.data(), sizeof(int32_t) * cls.size(),
-                       hipMemcpyHostToDevice));
+    GRAV_CHECK(upload(p, &p->d_class_off, fwd));
+    GRAV_CHECK(upload(p, &p->d_rclass_off, rev));
+    return GRAV_OK;
+}
+
+// Source boxes of parity class c in a dense block.
+int64_t class_count(const LevelInfo &lv, int c)
+{
+    int64_t n = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int par = (c >> a) & 1;
+        const int first = lv.s0[a] + ((par - lv.s0[a]) & 1);
+        n *= std::max(0, (lv.ns[a] - (first - lv.s0[a]) + 1) / 2);
+    }
+    return n;
+}
+
+// Tile lists of the M2L stages: 64 columns (4 waves x 16) per tile, per
+// level and child-parity class; forward columns are target boxes, transposed
+// columns source boxes.
+grav_status build_tiles(Plan *p)
+{
+    std::vector<GemmTile> all;
+    const int L = p->L;
+    const int64_t B = p->B;
+    auto add = [&](int kind, int level, int cls, int64_t ncols) {
+        TileRange &r = p->tiles[kind][0];
+        if (r.n == 0)
+            r.off = (int64_t)all.size();
+        for (int64_t c0 = 0; c0 < ncols; c0 += kTileCols) {
+            GemmTile t{};
+            t.level = level;
+            t.cls = cls;
+            t.col0 = c0;
+            t.ncol = (int32_t)std::min<int64_t>(kTileCols, ncols - c0);
+            all.push_back(t);
+            ++r.n;
+        }
+    };
+    for (int k = 0; k < TK_COUNT; ++k)
+        for (int l = 0; l <= kMaxLevels; ++l)
+            p->tiles[k][l] = TileRange{};
+    if (L >= 2) {
+        for (int l = 2; l <= L; ++l)
+            for (int c = 0; c < 8; ++c)
+                add(TK_M2L, l, c, (p->lev[l].class_start[c + 1] - p->lev[l].class_start[c]) * B);
+        for (int l = 2; l <= L; ++l)
+            for (int c = 0; c < 8; ++c)
+                add(TK_M2LT, l, c, class_count(p->lev[l], c) * B);
+    }
+    // Split the 189 offsets of each tile over S workgroups when there are too
+    // few tiles to fill the device (about 2048 workgroups wanted); the S
+    // partial expansions are summed in a fixed order afterwards.
+    std::vector<GemmTile> split;
+    for (int k = 0; k < TK_COUNT; ++k) {
+        TileRange &r = p->tiles[k][0];
+        const int S = r.n == 0 ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, ceil_div(2048, r.n)));
+        p->split[k] = S;
+        const int64_t off = (int64_t)split.size();
+        for (int64_t i = 0; i < r.n; ++i)
+            for (int q = 0; q < S; ++q) {
+                GemmTile t = all[r.off + i];
+                t.pad = q;
+                split.push_back(t);
+            }
+        r.off = off;
+        r.n *= S;
+    }
+    if (!split.empty())
+        GRAV_CHECK(upload(p, &p->d_tiles, split));
+    return GRAV_OK;
+}
+
+__global__ void k_fill_tmap(const uint32_t *bkeys, int64_t n, int s0x, int s0y, int s0z, int mx,
+                            int my, int mz, int32_t *tmap)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t k = bkeys[i];
+    const int x = (int)compact3(k) - s0x + 3, y = (int)compact3(k >> 1) - s0y + 3,
+              z = (int)compact3(k >> 2) - s0z + 3;
+    if (x >= 0 && y >= 0 && z >= 0 && x < mx && y < my && z < mz)
+        tmap[((int64_t)z * my + y) * mx + x] = (int32_t)i;
+}
+
+__global__ void k_fill_tchild(const int32_t *cparent, int64_t nc, int64_t np, int32_t *tchild)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nc)
+        return;
+    if (i == nc) {
+        tchild[np] = (int32_t)nc;
+        return;
+    }
+    if (i == 0 || cparent[i] != cparent[i - 1])
+        tchild[cparent[i]] = (int32_t)i;
+}
+
+// Lookup tables of the adjoint: target-box maps over each level's source
+// block plus a halo of 3 boxes (M2L transpose, near field transpose) and the
+// first-child table of each level (L2L transpose).
+grav_status build_adjoint_maps(Plan *p)
+{
+    const int L = p->L;
+    const int lo = L >= 2 ? 2 : L;
+    p->n_tmap = 0;
+    for (int l = lo; l <= L; ++l) {
+        const LevelInfo &lv = p->lev[l];
+        p->lev[l].tmap_off = p->n_tmap;
+        p->n_tmap += (int64_t)(lv.ns[0] + 6) * (lv.ns[1] + 6) * (lv.ns[2] + 6);
+    }
+    GRAV_CHECK(dalloc(p, &p->d_tmap, (size_t)p->n_tmap, true));
+    GRAV_HIP(hipMemset(p->d_tmap, 0xff, sizeof(int32_t) * p->n_tmap));
+    for (int l = lo; l <= L; ++l) {
+        const LevelInfo &lv = p->lev[l];
+        const int64_t n = lv.n_tgt;
+        if (n == 0)
+            continue;
+        hipLaunchKernelGGL(k_fill_tmap, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, 0,
+                           (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n, lv.s0[0], lv.s0[1],
+                           lv.s0[2], lv.ns[0] + 6, lv.ns[1] + 6, lv.ns[2] + 6,
+                           p->d_tmap + lv.tmap_off);
+        GRAV_HIP(hipGetLastError());
+    }
+    p->n_tchild = 0;
+    for (int l = 2; l < L; ++l) {
+        p->lev[l].tchild_off = p->n_tchild;
+        p->n_tchild += p->lev[l].n_tgt + 1;
+    }
+    if (p->n_tchild > 0) {
+        GRAV_CHECK(dalloc(p, &p->d_tchild, (size_t)p->n_tchild, true));
+        for (int l = 2; l < L; ++l) {
+            const int64_t nc = p->lev[l + 1].n_tgt;
+            hipLaunchKernelGGL(k_fill_tchild, dim3((unsigned)ceil_div(nc + 1, 256)), dim3(256), 0, 0,
+                               (const int32_t *)(p->d_tparent + p->tbox_off[l + 1]), nc,
+                               p->lev[l].n_tgt, p->d_tchild + p->lev[l].tchild_off);
+            GRAV_HIP(hipGetLastError());
+        }
+    }
+    GRAV_HIP(hipDeviceSynchronize());
     return GRAV_OK;
 }
 
@@ -619,7 +779,6 @@ grav_status build_tree(Plan *p, hipStream_t s)
             }
 
         // class grouping per level (levels >= 2): a 3-bit radix pass
-        p->tiles_host.clear();
         for (int l = 2; l <= L && ok; ++l) {
             const int64_t n = cnt[l];
             const unsigned g = (unsigned)ceil_div(n, T);
@@ -647,15 +806,6 @@ grav_status build_tree(Plan *p, hipStream_t s)
             int64_t acc = 0;
             for (int c = 0; c < 8; ++c) {
                 p->lev[l].class_start[c] = acc;
-                const int64_t cols = (int64_t)cc[c] * p->B;
-                for (int64_t c0 = 0; c0 < cols; c0 += kTileCols) {
-                    M2LTile t{};
-                    t.level = l;
-                    t.cls = c;
-                    t.col0 = c0;
-                    t.ncol = (int32_t)std::min<int64_t>(kTileCols, cols - c0);
-                    p->tiles_host.push_back(t);
-                }
                 acc += cc[c];
             }
             p->lev[l].class_start[8] = acc;
@@ -663,18 +813,6 @@ grav_status build_tree(Plan *p, hipStream_t s)
         if (!ok) {
             fail(GRAV_EDEVICE);
             break;
-        }
-        p->n_tiles = (int32_t)p->tiles_host.size();
-        if (p->n_tiles > 0) {
-            if (dalloc(p, &p->d_tiles, p->tiles_host.size(), true)) {
-                fail(GRAV_ENOMEM);
-                break;
-            }
-            if (hipMemcpy(p->d_tiles, p->tiles_host.data(), sizeof(M2LTile) * p->tiles_host.size(),
-                          hipMemcpyHostToDevice) != hipSuccess) {
-                fail(GRAV_EDEVICE);
-                break;
-            }
         }
     } while (0);
     cleanup();
@@ -814,6 +952,10 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             break;
         if ((st = build_operators(p)) != GRAV_OK)
             break;
+        if (p->M > 0 && (st = build_tiles(p)) != GRAV_OK)
+            break;
+        if (p->M > 0 && (st = build_adjoint_maps(p)) != GRAV_OK)
+            break;
         if (p->M > 0 && (st = count_work(p)) != GRAV_OK)
             break;
         // workspace
@@ -823,6 +965,25 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             break;
         if ((st = dalloc(p, &p->d_near, (size_t)p->M * p->B * 4, false)) != GRAV_OK)
             break;
+        {
+            // partial expansions of split M2L stages
+            size_t part = 0;
+            if (p->split[TK_M2L] > 1)
+                part = std::max(part, (size_t)p->split[TK_M2L] * p->n_tbox * p->B * p->PS);
+            if (p->split[TK_M2LT] > 1)
+                part = std::max(part, (size_t)p->split[TK_M2LT] * p->n_me * p->B * p->PS);
+            if ((st = dalloc(p, &p->d_part, part, false)) != GRAV_OK)
+                break;
+        }
+        {
+            const DevGeom g = make_geom(p);
+            if ((st = dalloc(p, &p->d_geom, 1, true)) != GRAV_OK)
+                break;
+            if (hipMemcpy(p->d_geom, &g, sizeof(DevGeom), hipMemcpyHostToDevice) != hipSuccess) {
+                st = GRAV_EDEVICE;
+                break;
+            }
+        }
         if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
             st = GRAV_EDEVICE;
             break;

@@ -1,0 +1,156 @@
+// Index helpers of the M2L stages: tile/column/term resolution for the
+// forward M2L (columns are target boxes of one child-parity class, terms the
+// class's 189 interaction-list offsets) and the transposed M2L (columns are
+// source boxes of one class, terms the offsets d with S - d a target box whose
+// class admits d).  The functions compile for host and device: the M2L
+// kernels use them, and grav_plan_check runs them on the host to validate a
+// plan's tables.
+#pragma once
+
+#include "eval_common.hpp"
+
+namespace grav {
+
+// A tile of columns: one level, one class (or none), columns [col0, col0 + ncol).
+struct GemmTile {
+    int32_t level;
+    int32_t cls;
+    int64_t col0;
+    int32_t ncol;
+    int32_t pad;
+};
+
+struct GemmCol {
+    bool valid;
+    int bm;             // density model
+    int x, y, z;        // root-relative box coordinates
+    int64_t box;        // index of the box in its list (meaning depends on the resolver)
+};
+
+struct GemmTerm {
+    int kid;            // offset id: index of the translation matrix
+    int dx, dy, dz;
+};
+
+// Enumerate the k-th box with parity class c in a dense block [s0, s0 + ns).
+__host__ __device__ inline void class_box(int k, int c, const int s0[3], const int ns[3], int out[3])
+{
+    int first[3], cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        const int par = (c >> a) & 1;
+        first[a] = s0[a] + ((par - s0[a]) & 1);
+        cnt[a] = (ns[a] - (first[a] - s0[a]) + 1) / 2;
+    }
+    const int kx = k % cnt[0];
+    const int ky = (k / cnt[0]) % cnt[1];
+    const int kz = k / (cnt[0] * cnt[1]);
+    out[0] = first[0] + 2 * kx;
+    out[1] = first[1] + 2 * ky;
+    out[2] = first[2] + 2 * kz;
+}
+
+__host__ __device__ inline int64_t dense_index(const DevLev &lv, int x, int y, int z)
+{
+    const int sx = x - lv.s0[0], sy = y - lv.s0[1], sz = z - lv.s0[2];
+    if (sx < 0 || sy < 0 || sz < 0 || sx >= lv.ns[0] || sy >= lv.ns[1] || sz >= lv.ns[2])
+        return -1;
+    return ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
+}
+
+// Target-box map around a level's source block (halo H): index or -1.
+__host__ __device__ inline int64_t tmap_lookup(const DevLev &lv, const int32_t *tmap, int H, int x, int y, int z)
+{
+    const int mx = lv.ns[0] + 2 * H, my = lv.ns[1] + 2 * H, mz = lv.ns[2] + 2 * H;
+    const int sx = x - lv.s0[0] + H, sy = y - lv.s0[1] + H, sz = z - lv.s0[2] + H;
+    if (sx < 0 || sy < 0 || sz < 0 || sx >= mx || sy >= my || sz >= mz)
+        return -1;
+    return tmap[lv.tmap_off + ((int64_t)sz * my + sy) * mx + sx];
+}
+
+// ---------------------------------------------------------------- resolvers
+// Forward M2L: columns = target boxes of one class (class-grouped order);
+// terms = the class's 189 interaction-list offsets; X = ME, Y = LE (store).
+struct ResM2L {
+    const DevGeom *g;
+    const GemmTile *tiles;
+    const uint32_t *tkey;
+    const int32_t *torder;
+    const int32_t *offs;  // [8][189][4]: dx, dy, dz, offset id (0..315)
+    __host__ __device__ int nterms(const GemmTile &) const { return kClassOffsets; }
+    __host__ __device__ GemmCol column(const GemmTile &t, int cl) const
+    {
+        GemmCol c{};
+        c.valid = cl < t.ncol;
+        if (!c.valid)
+            return c;
+        const DevLev &lv = g->lev[t.level];
+        const int64_t col = t.col0 + cl;
+        c.bm = (int)(col % g->B);
+        c.box = torder[lv.tbox_off + lv.class_start[t.cls] + col / g->B];
+        const uint32_t key = tkey[lv.tbox_off + c.box];
+        c.x = (int)compact3(key);
+        c.y = (int)compact3(key >> 1);
+        c.z = (int)compact3(key >> 2);
+        return c;
+    }
+    __host__ __device__ GemmTerm term(const GemmTile &t, int i) const
+    {
+        const int32_t *e = offs + (t.cls * kClassOffsets + i) * 4;
+        return GemmTerm{e[3], e[0], e[1], e[2]};
+    }
+    __host__ __device__ int64_t src(const GemmTile &t, const GemmCol &c, const GemmTerm &m) const
+    {
+        const DevLev &lv = g->lev[t.level];
+        const int64_t s = dense_index(lv, c.x + m.dx, c.y + m.dy, c.z + m.dz);
+        return s < 0 ? -1 : (lv.me_off + s) * g->B + c.bm;
+    }
+    __host__ __device__ int64_t out(const GemmTile &t, const GemmCol &c) const
+    {
+        return (g->lev[t.level].tgt_off + c.box) * g->B + c.bm;
+    }
+};
+
+// Transposed M2L: columns = source boxes of one class; terms = offsets d
+// with S - d a target box whose class admits d; X = LE adjoint, Y = ME
+// adjoint (store).
+struct ResM2LT {
+    const DevGeom *g;
+    const GemmTile *tiles;
+    const int32_t *tmap;
+    const int32_t *offs;  // reverse class tables, same layout as ResM2L's
+    __host__ __device__ int nterms(const GemmTile &) const { return kClassOffsets; }
+    __host__ __device__ GemmCol column(const GemmTile &t, int cl) const
+    {
+        GemmCol c{};
+        c.valid = cl < t.ncol;
+        if (!c.valid)
+            return c;
+        const DevLev &lv = g->lev[t.level];
+        const int64_t col = t.col0 + cl;
+        c.bm = (int)(col % g->B);
+        int xyz[3];
+        class_box((int)(col / g->B), t.cls, lv.s0, lv.ns, xyz);
+        c.x = xyz[0];
+        c.y = xyz[1];
+        c.z = xyz[2];
+        c.box = dense_index(lv, c.x, c.y, c.z);
+        return c;
+    }
+    __host__ __device__ GemmTerm term(const GemmTile &t, int i) const
+    {
+        const int32_t *e = offs + (t.cls * kClassOffsets + i) * 4;
+        return GemmTerm{e[3], e[0], e[1], e[2]};
+    }
+    __host__ __device__ int64_t src(const GemmTile &t, const GemmCol &c, const GemmTerm &m) const
+    {
+        const DevLev &lv = g->lev[t.level];
+        const int64_t ti = tmap_lookup(lv, tmap, 3, c.x - m.dx, c.y - m.dy, c.z - m.dz);
+        return ti < 0 ? -1 : (lv.tgt_off + ti) * g->B + c.bm;
+    }
+    __host__ __device__ int64_t out(const GemmTile &t, const GemmCol &c) const
+    {
+        return (g->lev[t.level].me_off + c.box) * g->B + c.bm;
+    }
+};
+
+}  // namespace grav
