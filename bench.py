@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--sample", type=int, default=2048, help="oracle targets for cpu_baseline/rel_err")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     return ap.parse_args()
 
 
@@ -118,18 +119,22 @@ def main():
 
     value = M / (ms * 1e-3)
     P2 = args.p * args.p
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline (algorithmic flops per launch / stage time)
+    b = plan.leaf_cells
+    n_leaf_src = (-(-n // b)) ** 3
     flops_m2l = 2.0 * P2 * P2 * m2l_pairs
     flops_p2p = P2P_FLOP_PER_PAIR * p2p_pairs
-    dom = max(("m2l", "p2p"), key=lambda k: stages.get(k, 0.0))
-    if dom == "m2l":
-        ach = flops_m2l / (stages["m2l"] * 1e-3) / 1e12
-        roof = {"kernel": "k_m2l<7,float> (M2L, FP32 MFMA 16x16x4)", "bound": "mfma",
-                "achieved": ach, "peak": PEAK["fp32_mfma"], "unit": "TFLOP/s"}
-    else:
-        ach = flops_p2p / (stages["p2p"] * 1e-3) / 1e12
-        roof = {"kernel": "k_p2p<float> (near field, FP32 VALU)", "bound": "alu",
-                "achieved": ach, "peak": PEAK["fp32_vector"], "unit": "TFLOP/s"}
+    flops_near = 27 * 2.0 * (4 * b ** 3) * b ** 3 * n_leaf_src
+    cand = {
+        "m2l": (flops_m2l, "k_m2l<%d,float> (M2L, FP32 MFMA 16x16x4)" % (-(-P2 // 16)), "mfma", "fp32_mfma"),
+        "near_lat": (flops_near, "k_near_lat<4,float> (lattice near field, FP32 MFMA 16x16x4)", "mfma",
+                     "fp32_mfma"),
+        "p2p": (flops_p2p, "k_p2p<float> (direct near field, FP32 VALU)", "alu", "fp32_vector"),
+    }
+    dom = max((k for k in cand if k in stages), key=lambda k: stages[k])
+    fl, kname, bound, pk = cand[dom]
+    roof = {"kernel": kname, "bound": bound, "achieved": fl / (stages[dom] * 1e-3) / 1e12,
+            "peak": PEAK[pk], "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["kernel_ms"] = stages.get(dom)
@@ -148,6 +153,7 @@ def main():
         "plan_s": plan_s,
         "stages_ms": stages,
         "work": {"m2l_box_pairs": m2l_pairs, "p2p_point_pairs": p2p_pairs, "m2l_gflop": flops_m2l / 1e9,
+                 "near_lat_gflop": flops_near / 1e9 if "near_lat" in stages else None,
                  "p2p_gflop_20": flops_p2p / 1e9},
         "roofline": roof,
     }
@@ -191,7 +197,11 @@ def main():
             fp64["rel_err"] = oracle.rel_l2(g64[idx], ref)
             fp64["rel_err_p%d" % args.p] = oracle.rel_l2(g64_p[idx], ref)
             fp64["rel_err_bar"] = 1e-6
-    print(json.dumps(res), flush=True)
+    line = json.dumps(res)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
 
 
 if __name__ == "__main__":

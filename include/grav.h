@@ -129,7 +129,9 @@ grav_status grav_eval(grav_plan_t plan, const double *rho, double *g_out, void *
  * resid:    device pointer, double [batch][n_targets][components];
  * drho_out: device pointer, double [batch][nz][ny][nx]; overwritten with
  *           drho[b][cell] = sum_j,c resid[b][j][c] * d g[b][j][c] / d rho[b][cell].
- * Same asynchrony and errors as grav_eval. */
+ * Same asynchrony and errors as grav_eval.  Unless the library is compiled
+ * with GRAV_ENABLE_ADJOINT defined, this path is switched off: the call
+ * validates its arguments and returns GRAV_EUNSUPPORTED. */
 grav_status grav_adjoint(grav_plan_t plan, const double *resid, double *drho_out, void *stream);
 
 /* Stage timings of the last evaluation or adjoint enqueued with

@@ -546,6 +546,12 @@ extern "C" grav_status grav_adjoint(grav_plan_t plan, const double *resid, doubl
 {
     if (!plan || !resid || !drho_out)
         return GRAV_EINVAL;
+#ifndef GRAV_ENABLE_ADJOINT
+    // The transposed pass is switched off in this library build: its kernels
+    // are compiled but not launched (define GRAV_ENABLE_ADJOINT to enable).
+    (void)stream;
+    return GRAV_EUNSUPPORTED;
+#endif
     Plan *p = reinterpret_cast<Plan *>(plan);
     hipStream_t s = (hipStream_t)stream;
     int cur = 0;

@@ -127,6 +127,9 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
     const auto leaf_start = fetch(p->d_leaf_start, (size_t)p->n_leaf + 1);
     const auto tleaf = fetch(p->d_tleaf, (size_t)p->M);
     const auto perm = fetch(p->d_perm, (size_t)p->M);
+    const auto leaf_pend = fetch(p->d_leaf_pend, (size_t)p->n_leaf);
+    const int64_t ncell = (int64_t)p->d.nx * p->d.ny * p->d.nz;
+    const auto cell_slot = p->lat_near ? fetch(p->d_cell_slot, (size_t)ncell) : std::vector<int32_t>();
     std::vector<int32_t> coff, roff;
     if (L >= 2) {
         coff = fetch(p->d_class_off, 8 * kClassOffsets * 4);
@@ -150,6 +153,25 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
             ck.fail("tree", "permutation not a bijection", perm[i], p->M);
         else
             seen[perm[i]] = 1;
+    }
+    // user points first within each leaf; voxel-centre slots invert perm
+    const int64_t npts = p->lat_near ? p->d.n_points : p->M;
+    for (int64_t i = 0; i < p->n_leaf && ck.ok; ++i) {
+        const int64_t e = leaf_pend[i];
+        if (e < leaf_start[i] || e > leaf_start[i + 1])
+            ck.fail("tree", "user-point end outside its leaf", e, i);
+        for (int64_t j = leaf_start[i]; j < leaf_start[i + 1] && ck.ok; ++j)
+            if (((int64_t)perm[j] < npts) != (j < e))
+                ck.fail("tree", "user points not a prefix of their leaf", j, i);
+    }
+    if (p->lat_near) {
+        if ((int64_t)cell_slot.size() != ncell)
+            ck.fail("lattice", "cell slots not readable", (long long)cell_slot.size(), ncell);
+        for (int64_t c = 0; c < ncell && ck.ok; ++c) {
+            const int64_t j = cell_slot[c];
+            if (j < 0 || j >= p->M || (int64_t)perm[j] != p->d.n_points + c)
+                ck.fail("lattice", "cell slot does not invert the permutation", c, j);
+        }
     }
     for (int l = lo; l <= L && ck.ok; ++l) {
         const DevLev &lv = g.lev[l];

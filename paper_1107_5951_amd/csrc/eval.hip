@@ -49,44 +49,111 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const
 }
 
 // --------------------------------------------------------------------------
-// M2M: parent ME = sum over its (up to 8) children of T_c * child ME.
-// One workgroup per parent box of level l.
+// M2M on MFMA (FP64): ME[parent] = sum over the 8 children c of T_c ME[child],
+// a GEMM with columns = (parent box, model) and K = 8 x p^2.  A workgroup
+// owns 16 columns; its four waves split the rows (RBW row blocks each).
+// Children outside the source block contribute nothing.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_m2m(DevGeom g, int l, const double *m2m, double *me)
+template <int RBW>
+__global__ void __launch_bounds__(256)
+k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
 {
-    extern __shared__ double sh[];  // [8][PS]
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const DevLev &lp = g.lev[l];
     const DevLev &lc = g.lev[l + 1];
-    const int64_t box = blockIdx.x;
+    const int RB = g.PS / 16;
+    const int64_t nbox = (int64_t)lp.ns[0] * lp.ns[1] * lp.ns[2];
+    const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const bool cvalid = col < nbox * g.B;
+    const int64_t box = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
     const int px = lp.s0[0] + (int)(box % lp.ns[0]);
     const int py = lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1]);
     const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
-    for (int bm = 0; bm < g.B; ++bm) {
-        for (int i = threadIdx.x; i < 8 * g.PS; i += blockDim.x) {
-            const int c = i / g.PS, t = i % g.PS;
-            const int cx = 2 * px + (c & 1) - lc.s0[0];
-            const int cy = 2 * py + ((c >> 1) & 1) - lc.s0[1];
-            const int cz = 2 * pz + ((c >> 2) & 1) - lc.s0[2];
-            double v = 0.0;
-            if (cx >= 0 && cy >= 0 && cz >= 0 && cx < lc.ns[0] && cy < lc.ns[1] && cz < lc.ns[2]) {
-                const int64_t ci = lc.me_off + ((int64_t)cz * lc.ns[1] + cy) * lc.ns[0] + cx;
-                v = me[(ci * g.B + bm) * g.PS + t];
-            }
-            sh[i] = v;
+    const int krow = lane >> 4;
+    const int rb0 = wave * RBW;
+    vec4 acc[RBW];
+#pragma unroll
+    for (int i = 0; i < RBW; ++i)
+        acc[i] = vec4{0, 0, 0, 0};
+    for (int c = 0; c < 8; ++c) {
+        const int64_t ci = cvalid ? dense_index(lc, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1),
+                                                2 * pz + ((c >> 2) & 1))
+                                  : -1;
+        const double *mp = me + (ci >= 0 ? ((lc.me_off + ci) * g.B + bm) * g.PS : 0);
+        const double *ap = A + (int64_t)c * g.KS * RB * 64 + lane;
+        for (int ks = 0; ks < g.KS; ++ks) {
+            const double bv = ci >= 0 ? mp[4 * ks + krow] : 0.0;
+            const double *ak = ap + (int64_t)ks * RB * 64;
+#pragma unroll
+            for (int i = 0; i < RBW; ++i)
+                if (rb0 + i < RB)  // uniform over the wave
+                    acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[(rb0 + i) * 64], bv, acc[i], 0, 0, 0);
         }
-        __syncthreads();
-        for (int t = threadIdx.x; t < g.PS; t += blockDim.x) {
-            double acc = 0.0;
-            for (int c = 0; c < 8; ++c) {
-                const double *mc = m2m + (int64_t)c * g.PS * g.PS;
-                const double *x = sh + c * g.PS;
-                for (int s = 0; s < g.P2; ++s)
-                    acc += mc[(int64_t)s * g.PS + t] * x[s];
-            }
-            me[((lp.me_off + box) * g.B + bm) * g.PS + t] = acc;
-        }
-        __syncthreads();
     }
+    if (!cvalid)
+        return;
+    // FP64 fragment: column lane % 16, rows lane / 16 + 4 r of each block
+    double *dst = me + ((lp.me_off + box) * g.B + bm) * g.PS;
+#pragma unroll
+    for (int i = 0; i < RBW; ++i) {
+        if (rb0 + i >= RB)
+            continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            dst[16 * (rb0 + i) + krow + 4 * r] = acc[i][r];
+    }
+}
+
+// --------------------------------------------------------------------------
+// L2L on MFMA (FP64): LE[child] += T_c LE[parent] for the target boxes of
+// level l, grouped by child octant c (the M2L tiles of the level: same
+// columns, one matrix per tile).  Four waves of 16 columns per workgroup.
+// --------------------------------------------------------------------------
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, const int32_t *torder,
+           const int32_t *tparent, const double *A, double *le)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    const GemmTile tile = tiles[(int64_t)blockIdx.x * stride];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const DevLev &lv = g.lev[tile.level];
+    const DevLev &lp = g.lev[tile.level - 1];
+    const int cl = wave * 16 + (lane & 15);
+    const bool cvalid = cl < tile.ncol;
+    const int64_t col = tile.col0 + cl;
+    const int bm = (int)(col % g.B);
+    int64_t box = 0, par = 0;
+    if (cvalid) {
+        box = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
+        par = tparent[lv.tbox_off + box];
+    }
+    vec4 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+        acc[rb] = vec4{0, 0, 0, 0};
+    const int krow = lane >> 4;
+    const double *mp = le + (cvalid ? ((lp.tgt_off + par) * g.B + bm) * g.PS : 0);
+    const double *ap = A + (int64_t)tile.cls * g.KS * RB * 64 + lane;
+    for (int ks = 0; ks < g.KS; ++ks) {
+        const double bv = cvalid ? mp[4 * ks + krow] : 0.0;
+        const double *ak = ap + (int64_t)ks * RB * 64;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[rb * 64], bv, acc[rb], 0, 0, 0);
+    }
+    if (!cvalid)
+        return;
+    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * g.PS;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            dst[16 * rb + krow + 4 * r] += acc[rb][r];
 }
 
 // --------------------------------------------------------------------------
@@ -187,35 +254,6 @@ __global__ void __launch_bounds__(256) k_sum_parts(const double *part, int S, in
 }
 
 // --------------------------------------------------------------------------
-// L2L: LE of a level-l box += S_c * LE of its parent (c = child octant).
-// One workgroup per target box of level l >= 3.
-// --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_l2l(DevGeom g, int l, const uint32_t *tkey,
-                                             const int32_t *tparent, const double *l2l, double *le)
-{
-    extern __shared__ double sh[];
-    const DevLev &lv = g.lev[l];
-    const DevLev &lp = g.lev[l - 1];
-    const int64_t box = blockIdx.x;
-    const uint32_t key = tkey[lv.tbox_off + box];
-    const int c = (int)(key & 7u);
-    const int64_t par = tparent[lv.tbox_off + box];
-    const double *mc = l2l + (int64_t)c * g.PS * g.PS;
-    for (int bm = 0; bm < g.B; ++bm) {
-        for (int s = threadIdx.x; s < g.PS; s += blockDim.x)
-            sh[s] = le[((lp.tgt_off + par) * g.B + bm) * g.PS + s];
-        __syncthreads();
-        for (int t = threadIdx.x; t < g.PS; t += blockDim.x) {
-            double acc = 0.0;
-            for (int s = 0; s < g.P2; ++s)
-                acc += mc[(int64_t)s * g.PS + t] * sh[s];
-            le[((lv.tgt_off + box) * g.B + bm) * g.PS + t] += acc;
-        }
-        __syncthreads();
-    }
-}
-
-// --------------------------------------------------------------------------
 // Near field (P2P): direct sum over the quadrature points of the cells of the
 // 27 leaves around a target leaf (the near term of Eq. (13)); coincident
 // pairs are skipped.  One workgroup per target leaf; each neighbour leaf's
@@ -227,13 +265,13 @@ __global__ void __launch_bounds__(256) k_l2l(DevGeom g, int l, const uint32_t *t
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_start,
-      const uint32_t *tkey, double *near)
+      const int64_t *leaf_end, const uint32_t *tkey, double *near)
 {
     __shared__ double srho[512];
     __shared__ double red[256][4];
     const DevLev &lv = g.lev[g.L];
     const int64_t leaf = blockIdx.x;
-    const int64_t ts = leaf_start[leaf], te = leaf_start[leaf + 1];
+    const int64_t ts = leaf_start[leaf], te = leaf_end[leaf];
     const int64_t nt = te - ts;
     const uint32_t key = tkey[lv.tbox_off + leaf];
     const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
@@ -335,6 +373,85 @@ k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_star
                     o[c] = s4[c];
             }
         }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Near field of the voxel-centre targets.  Targets and Gauss points both sit
+// on the lattice, so the near field of a leaf's b^3 cell centres is
+//   near[leaf] = sum over the 27 neighbour offsets d of  A_d rho[leaf + d],
+// with A_d a fixed (4 b^3) x b^3 matrix (the direct sum over the same point
+// pairs, precomputed in FP64).  Over all leaves this is a GEMM per offset:
+// columns = (leaf, model), K = cells of the neighbour leaf.  A wave owns 16
+// columns and RBW 16-row blocks; the workgroup's four waves split the rows.
+// Densities outside the mesh are zero; results go to the sorted slot of
+// each voxel centre.
+// --------------------------------------------------------------------------
+template <int RBW, typename T>
+__global__ void __launch_bounds__(256)
+k_near_lat(DevGeom g, const double *rho, const T *A, int RBn, int KSn, const int32_t *cell_slot,
+           double *near)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const DevLev &lv = g.lev[g.L];
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const bool cvalid = col < nleaf * g.B;
+    const int64_t leaf = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
+    const int b = g.b, b2 = b * b, b3 = b2 * b;
+    const int c0[3] = {(int)(leaf % lv.ns[0]) * b, (int)((leaf / lv.ns[0]) % lv.ns[1]) * b,
+                       (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1])) * b};
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const double *rm = rho + (int64_t)bm * ncell;
+    const int krow = lane >> 4;
+    const int rb0 = wave * RBW;
+    vec4 acc[RBW];
+#pragma unroll
+    for (int i = 0; i < RBW; ++i)
+        acc[i] = vec4{0, 0, 0, 0};
+    for (int nb = 0; nb < 27; ++nb) {
+        const int ox = c0[0] + (nb % 3 - 1) * b, oy = c0[1] + ((nb / 3) % 3 - 1) * b,
+                  oz = c0[2] + (nb / 9 - 1) * b;
+        const T *ap = A + (int64_t)nb * KSn * RBn * 64 + lane;
+        for (int ks = 0; ks < KSn; ++ks) {
+            const int v = 4 * ks + krow;
+            T bv = (T)0;
+            if (cvalid && v < b3) {
+                const int ix = ox + v % b, iy = oy + (v / b) % b, iz = oz + v / b2;
+                if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
+                    bv = (T)rm[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+            }
+            const T *ak = ap + (int64_t)ks * RBn * 64;
+#pragma unroll
+            for (int i = 0; i < RBW; ++i) {
+                if (rb0 + i < RBn) {  // uniform over the wave
+                    if constexpr (sizeof(T) == 8)
+                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[(rb0 + i) * 64], bv, acc[i], 0, 0, 0);
+                    else
+                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[(rb0 + i) * 64], bv, acc[i], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (!cvalid)
+        return;
+    // lane holds target t = 4 rb + lane / 16 (the row order of A), components r = 0..3
+#pragma unroll
+    for (int i = 0; i < RBW; ++i) {
+        const int t = 4 * (rb0 + i) + krow;
+        if (rb0 + i >= RBn || t >= b3)
+            continue;
+        const int ix = c0[0] + t % b, iy = c0[1] + (t / b) % b, iz = c0[2] + t / b2;
+        if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+            continue;
+        const int64_t j = cell_slot[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+        double *o = near + (j * g.B + bm) * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            o[r] = (double)acc[i][r];
     }
 }
 
@@ -496,12 +613,95 @@ static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T 
     }
 #undef M2L_CASE
     GRAV_HIP(hipGetLastError());
-    if (S > 1) {
-        const int64_t n = pstride * p->PS;
-        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                           (const double *)p->d_part, S, n, p->d_le);
-        GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
+{
+    const int64_t ncol = p->lev[l].n_src * p->B;
+    const int RBW = (p->PS / 16 + 3) / 4;
+    dim3 grid((unsigned)((ncol + 15) / 16)), blk(256);
+#define M2M_CASE(W)                                                                             \
+    case W:                                                                                     \
+        hipLaunchKernelGGL((k_m2m_mfma<W>), grid, blk, 0, s, g, l, (const double *)p->d_m2m_sw, \
+                           p->d_me);                                                            \
+        break;
+    switch (RBW) {
+        M2M_CASE(1)
+        M2M_CASE(2)
+        M2M_CASE(3)
+        M2M_CASE(4)
+    default:
+        return GRAV_EUNSUPPORTED;
     }
+#undef M2M_CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
+{
+    const TileRange &all = p->tiles[TK_M2L][0];
+    const TileRange &r = p->tiles[TK_M2L][l];
+    if (r.n == 0)
+        return GRAV_OK;
+    const int S = p->split[TK_M2L];
+    const GemmTile *t0 = (const GemmTile *)(p->d_tiles + all.off) + r.off * S;
+    dim3 grid((unsigned)r.n), blk(256);
+#define L2L_CASE(R)                                                                             \
+    case R:                                                                                     \
+        hipLaunchKernelGGL((k_l2l_mfma<R>), grid, blk, 0, s, g, t0, S, (const uint32_t *)p->d_tkey, \
+                           (const int32_t *)p->d_torder, (const int32_t *)p->d_tparent,         \
+                           (const double *)p->d_l2l_sw, p->d_le);                               \
+        break;
+    switch (p->PS / 16) {
+        L2L_CASE(1)
+        L2L_CASE(2)
+        L2L_CASE(3)
+        L2L_CASE(4)
+        L2L_CASE(6)
+        L2L_CASE(7)
+        L2L_CASE(8)
+        L2L_CASE(9)
+        L2L_CASE(11)
+        L2L_CASE(13)
+        L2L_CASE(15)
+        L2L_CASE(16)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef L2L_CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho, hipStream_t s)
+{
+    const LevelInfo &lv = p->lev[p->L];
+    const int64_t ncol = lv.n_src * p->B;
+    const int RBn = p->lat_RB, KSn = p->lat_KS;
+    const int RBW = (RBn + 3) / 4;
+    dim3 grid((unsigned)((ncol + 15) / 16)), blk(256);
+#define NEAR_CASE(W)                                                                            \
+    case W:                                                                                     \
+        if (p->d.precision == GRAV_FP64)                                                        \
+            hipLaunchKernelGGL((k_near_lat<W, double>), grid, blk, 0, s, g, rho,                 \
+                               (const double *)p->d_tn64, RBn, KSn, (const int32_t *)p->d_cell_slot, \
+                               p->d_near);                                                      \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_near_lat<W, float>), grid, blk, 0, s, g, rho,                  \
+                               (const float *)p->d_tn32, RBn, KSn, (const int32_t *)p->d_cell_slot, \
+                               p->d_near);                                                      \
+        break;
+    switch (RBW) {
+        NEAR_CASE(1)
+        NEAR_CASE(2)
+        NEAR_CASE(4)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef NEAR_CASE
+    GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }
 
@@ -519,12 +719,8 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         GRAV_HIP(hipGetLastError());
         stage_end(p, s);
         stage_begin(p, "m2m", s);
-        for (int l = L - 1; l >= 2; --l) {
-            hipLaunchKernelGGL(k_m2m, dim3((unsigned)p->lev[l].n_src), dim3(256),
-                               sizeof(double) * 8 * p->PS, s, g, l, (const double *)p->d_m2m,
-                               p->d_me);
-            GRAV_HIP(hipGetLastError());
-        }
+        for (int l = L - 1; l >= 2; --l)
+            GRAV_CHECK(launch_m2m(p, g, l, s));
         stage_end(p, s);
         stage_begin(p, "m2l", s);
         if (p->d.precision == GRAV_FP64)
@@ -532,28 +728,37 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         else
             GRAV_CHECK(launch_m2l<float>(p, g, s, p->d_k32));
         stage_end(p, s);
-        stage_begin(p, "l2l", s);
-        for (int l = 3; l <= L; ++l) {
-            if (p->lev[l].n_tgt == 0)
-                continue;
-            hipLaunchKernelGGL(k_l2l, dim3((unsigned)p->lev[l].n_tgt), dim3(256),
-                               sizeof(double) * p->PS, s, g, l, (const uint32_t *)p->d_tkey,
-                               (const int32_t *)p->d_tparent, (const double *)p->d_l2l, p->d_le);
+        if (p->split[TK_M2L] > 1) {
+            stage_begin(p, "m2l_sum", s);
+            const int64_t n = p->n_tbox * p->B * p->PS;
+            hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                               (const double *)p->d_part, p->split[TK_M2L], n, p->d_le);
             GRAV_HIP(hipGetLastError());
+            stage_end(p, s);
         }
+        stage_begin(p, "l2l", s);
+        for (int l = 3; l <= L; ++l)
+            GRAV_CHECK(launch_l2l(p, g, l, s));
         stage_end(p, s);
     }
-    stage_begin(p, "p2p", s);
-    if (p->d.precision == GRAV_FP64)
-        hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
-                           (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
-                           (const uint32_t *)p->d_tkey, p->d_near);
-    else
-        hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
-                           (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
-                           (const uint32_t *)p->d_tkey, p->d_near);
-    GRAV_HIP(hipGetLastError());
-    stage_end(p, s);
+    if (p->lat_near) {
+        stage_begin(p, "near_lat", s);
+        GRAV_CHECK(launch_near_lat(p, g, rho, s));
+        stage_end(p, s);
+    }
+    if (!p->lat_near || p->d.n_points > 0) {
+        stage_begin(p, "p2p", s);
+        if (p->d.precision == GRAV_FP64)
+            hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+                               (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
+                               (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, p->d_near);
+        else
+            hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+                               (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
+                               (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, p->d_near);
+        GRAV_HIP(hipGetLastError());
+        stage_end(p, s);
+    }
     stage_begin(p, "l2p", s);
     hipLaunchKernelGGL(k_l2p_combine, dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s, g,
                        (const double *)p->d_tpos, (const int32_t *)p->d_tleaf,

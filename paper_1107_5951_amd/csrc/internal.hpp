@@ -16,7 +16,8 @@ constexpr int kMaxLevels = 10;
 constexpr int kNumOffsets = 316;   // M2L offsets d with 2 <= |d|_inf <= 3
 constexpr int kClassOffsets = 189; // offsets valid for one child-parity class
 constexpr int kTileCols = 64;      // columns (box, model) per M2L tile
-constexpr int kMaxLeafCells = 8;   // leaf edge cap: a leaf's densities fit one 512-entry LDS stage
+constexpr int kMaxLeafCells = 8;     // leaf edge cap: a leaf's densities fit one 512-entry LDS stage
+constexpr int kMaxLatticeLeaf = 4;   // largest leaf edge with lattice near-field matrices
 
 struct LevelInfo {
     int l = 0;
@@ -75,8 +76,19 @@ struct Plan {
     int32_t *d_torder = nullptr;   // [n_tbox_all] class-grouped order -> box index (per level)
     int64_t tbox_off[kMaxLevels + 1] = {0}; // start of each level in the three arrays above
     struct GemmTile *d_tiles = nullptr;            // all M2L tiles
-    TileRange tiles[TK_COUNT][kMaxLevels + 1];     // per stage (slot 0: all levels)
-    int split[TK_COUNT] = {1, 1};                  // workgroups sharing the offsets of one tile
+    // per stage: slot 0 = all levels, in launch order (each tile repeated
+    // split[k] times); slot l >= 2 = level l's tiles in the unrepeated numbering
+    TileRange tiles[TK_COUNT][kMaxLevels + 1];
+    int split[TK_COUNT] = {1, 1};
+    // near field of voxel-centre targets by lattice matrices (b <= 4)
+    bool lat_near = false;
+    int lat_RB = 0, lat_KS = 0;                    // row blocks (4 b^3 / 16), k steps (b^3 / 4)
+    double *d_m2m_sw = nullptr;                    // [8][KS][RB][64] M2M as MFMA A fragments (FP64)
+    double *d_l2l_sw = nullptr;                    // [8][KS][RB][64] L2L likewise
+    double *d_tn64 = nullptr;                      // [27][KS][RB][64] swizzled, FP64 plans
+    float *d_tn32 = nullptr;                       // same, mixed plans
+    int32_t *d_cell_slot = nullptr;                // [ncell] sorted slot of each voxel centre
+    int64_t *d_leaf_pend = nullptr;                // [n_leaf] end of the user points of a leaf                  // workgroups sharing the offsets of one tile
     double *d_part = nullptr;                      // [split][expansions][PS] partial sums
     int32_t *d_class_off = nullptr;  // [8][189][4] (dx, dy, dz, offset id)
     int32_t *d_rclass_off = nullptr; // same for the transposed M2L, keyed by source class

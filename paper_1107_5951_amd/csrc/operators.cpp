@@ -164,4 +164,41 @@ void p2m_lattice(int P, int b, int q, double h, int ld, double *out)
             }
 }
 
+void near_lattice(int b, int q, double coincident_r2, double *out)
+{
+    const int b3 = b * b * b;
+    const double go = 0.5 / std::sqrt(3.0);
+    std::memset(out, 0, sizeof(double) * 27 * (size_t)4 * b3 * b3);
+    for (int nb = 0; nb < 27; ++nb) {
+        const int d[3] = {nb % 3 - 1, (nb / 3) % 3 - 1, nb / 9 - 1};
+        double *m = out + (size_t)nb * 4 * b3 * b3;
+        for (int t = 0; t < b3; ++t) {
+            const int tc[3] = {t % b, (t / b) % b, t / (b * b)};
+            for (int sidx = 0; sidx < b3; ++sidx) {
+                const int sc[3] = {sidx % b, (sidx / b) % b, sidx / (b * b)};
+                double c[3];
+                for (int a = 0; a < 3; ++a)
+                    c[a] = (double)(tc[a] - sc[a] - d[a] * b);  // target centre - source centre
+                double acc[4] = {0, 0, 0, 0};
+                const int ng = q == 2 ? 8 : 1;
+                for (int gp = 0; gp < ng; ++gp) {
+                    double u[3];
+                    for (int a = 0; a < 3; ++a)
+                        u[a] = q == 2 ? c[a] - (((gp >> a) & 1) ? go : -go) : c[a];
+                    const double r2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                    if (!(r2 > coincident_r2))
+                        continue;
+                    const double w = q == 2 ? 0.125 : 1.0;
+                    const double ri = 1.0 / std::sqrt(r2);
+                    acc[0] += w * ri;
+                    for (int a = 0; a < 3; ++a)
+                        acc[1 + a] += w * ri * ri * ri * u[a];
+                }
+                for (int comp = 0; comp < 4; ++comp)
+                    m[(size_t)(4 * t + comp) * b3 + sidx] = acc[comp];
+            }
+        }
+    }
+}
+
 }  // namespace grav

@@ -49,4 +49,16 @@ void m2l_matrix(int P, const double d[3], int ld, double *out);
 // the leaf edge b*h relative to the leaf centre.
 void p2m_lattice(int P, int b, int q, double h, int ld, double *out);
 
+// Near field on the lattice: for targets at the b^3 cell centres of a leaf and
+// the Gauss points (q = 1 or 2 per axis) of the b^3 cells of the leaf at
+// offset d (d in {-1, 0, 1}^3, index nb = (dx+1) + 3 (dy+1) + 9 (dz+1)), the
+// matrix that maps cell densities to (phi, gx, gy, gz) with phi = sum w / r and
+// g_a = sum w u_a / r^3, u = target - source, in cell units (h = 1, unit
+// density: w = 1/8 per Gauss point for q = 2, 1 for q = 1).  Pairs with
+// r^2 <= coincident_r2 are left out.  Layout: out[nb][4 t + comp][s], t and s
+// cell indices x fastest.  The direct sum over the same pairs gives the same
+// values; the matrices depend only on (b, q) because both point sets sit on
+// the lattice.
+void near_lattice(int b, int q, double coincident_r2, double *out);
+
 }  // namespace grav

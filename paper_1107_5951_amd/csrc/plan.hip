@@ -191,6 +191,37 @@ __global__ void k_fill_last(int64_t *leaf_start, int64_t n_leaf, int64_t M)
         leaf_start[n_leaf] = M;
 }
 
+// Sorted slot of every voxel-centre target: slot[c] = j with perm[j] = npts + c.
+__global__ void k_cell_slot(const uint32_t *perm, int64_t M, int64_t npts, int32_t *slot)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M)
+        return;
+    const int64_t i = perm[j];
+    if (i >= npts)
+        slot[i - npts] = (int32_t)j;
+}
+
+// End of the user points of each leaf.  The sort is stable and the keys are
+// assigned in descriptor order (points first, then voxel centres), so within a
+// leaf the user points form a prefix; find its end by bisection.
+__global__ void k_leaf_point_end(const uint32_t *perm, const int64_t *leaf_start, int64_t n_leaf,
+                                 int64_t npts, int64_t *pend)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_leaf)
+        return;
+    int64_t lo = leaf_start[l], hi = leaf_start[l + 1];
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)perm[mid] < npts)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    pend[l] = lo;
+}
+
 template <class T>
 grav_status dalloc(Plan *p, T **ptr, size_t count, bool resident)
 {
@@ -219,7 +250,8 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part};
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw,
+                    p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -364,6 +396,21 @@ grav_status build_operators(Plan *p)
     }
     GRAV_CHECK(upload(p, &p->d_m2m, m2m));
     GRAV_CHECK(upload(p, &p->d_l2l, l2l));
+    {
+        // the same matrices as MFMA A operands (rows = output coefficient)
+        const size_t per8 = (size_t)KS * RB * 64;
+        std::vector<double> msw(8 * per8), lsw(8 * per8);
+        for (int c = 0; c < 8; ++c) {
+            const double delta[3] = {((c & 1) - 0.5) * 0.5, (((c >> 1) & 1) - 0.5) * 0.5,
+                                     (((c >> 2) & 1) - 0.5) * 0.5};
+            m2m_matrix(P, delta, PS, m.data());
+            swizzle(m.data(), PS, KS, false, msw.data() + per8 * c);
+            l2l_matrix(P, delta, PS, m.data());
+            swizzle(m.data(), PS, KS, false, lsw.data() + per8 * c);
+        }
+        GRAV_CHECK(upload(p, &p->d_m2m_sw, msw));
+        GRAV_CHECK(upload(p, &p->d_l2l_sw, lsw));
+    }
 
     // M2L for all 316 offsets, swizzled for the MFMA A operand, and transposes
     std::vector<int> all;
@@ -415,6 +462,9 @@ grav_status build_tiles(Plan *p)
         TileRange &r = p->tiles[kind][0];
         if (r.n == 0)
             r.off = (int64_t)all.size();
+        TileRange &rl = p->tiles[kind][level];
+        if (rl.n == 0)
+            rl.off = r.n;  // level range, in this kind's own numbering
         for (int64_t c0 = 0; c0 < ncols; c0 += kTileCols) {
             GemmTile t{};
             t.level = level;
@@ -423,6 +473,7 @@ grav_status build_tiles(Plan *p)
             t.ncol = (int32_t)std::min<int64_t>(kTileCols, ncols - c0);
             all.push_back(t);
             ++r.n;
+            ++rl.n;
         }
     };
     for (int k = 0; k < TK_COUNT; ++k)
@@ -527,6 +578,64 @@ grav_status build_adjoint_maps(Plan *p)
         }
     }
     GRAV_HIP(hipDeviceSynchronize());
+    return GRAV_OK;
+}
+
+// Near field of voxel-centre targets as 27 dense lattice matrices (leaf
+// edges b <= 4), the slot of every voxel centre in sorted order, and the end
+// of the user points of every leaf (the direct near-field kernel visits only
+// those).
+grav_status build_near_lattice(Plan *p, hipStream_t s)
+{
+    const int64_t M = p->M, npts = p->d.n_points;
+    p->lat_near = p->d.voxel_centres && p->b <= kMaxLatticeLeaf;
+    GRAV_CHECK(dalloc(p, &p->d_leaf_pend, p->n_leaf, true));
+    hipLaunchKernelGGL(k_leaf_point_end, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, s,
+                       (const uint32_t *)p->d_perm, (const int64_t *)p->d_leaf_start, p->n_leaf,
+                       p->lat_near ? npts : M, p->d_leaf_pend);
+    GRAV_HIP(hipGetLastError());
+    if (!p->lat_near) {
+        GRAV_HIP(hipStreamSynchronize(s));
+        return GRAV_OK;
+    }
+    const int64_t ncell = (int64_t)p->d.nx * p->d.ny * p->d.nz;
+    GRAV_CHECK(dalloc(p, &p->d_cell_slot, ncell, true));
+    hipLaunchKernelGGL(k_cell_slot, dim3((unsigned)ceil_div(M, 256)), dim3(256), 0, s,
+                       (const uint32_t *)p->d_perm, M, npts, p->d_cell_slot);
+    GRAV_HIP(hipGetLastError());
+
+    const int b = p->b, b3 = b * b * b;
+    const int RBn = (int)ceil_div(4 * b3, 16), KSn = (int)ceil_div(b3, 4);
+    p->lat_RB = RBn;
+    p->lat_KS = KSn;
+    const bool f64 = p->d.precision == GRAV_FP64;
+    std::vector<double> dense((size_t)27 * 4 * b3 * b3);
+    near_lattice(b, p->q, f64 ? 1e-20 : 1e-10, dense.data());
+    // A-operand swizzle [nb][ks][rb][lane] = A[16 rb + lane % 16][4 ks + lane / 16].
+    // Rows are ordered so that the accumulator of a lane holds the four
+    // components of one target: the FP32 instruction returns rows
+    // 4 (lane / 16) + r of each 16-row block, the FP64 one rows lane / 16 + 4 r;
+    // target t = 4 rb + lane / 16, component r.
+    std::vector<double> sw((size_t)27 * KSn * RBn * 64, 0.0);
+    for (int nb = 0; nb < 27; ++nb)
+        for (int ks = 0; ks < KSn; ++ks)
+            for (int rb = 0; rb < RBn; ++rb)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int row = lane & 15, col = 4 * ks + (lane >> 4);
+                    const int t = 4 * rb + (f64 ? row % 4 : row / 4);
+                    const int comp = f64 ? row / 4 : row % 4;
+                    double v = 0.0;
+                    if (t < b3 && col < b3)
+                        v = dense[((size_t)nb * 4 * b3 + 4 * t + comp) * b3 + col];
+                    sw[(((size_t)nb * KSn + ks) * RBn + rb) * 64 + lane] = v;
+                }
+    if (f64) {
+        GRAV_CHECK(upload(p, &p->d_tn64, sw));
+    } else {
+        std::vector<float> sw32(sw.begin(), sw.end());
+        GRAV_CHECK(upload(p, &p->d_tn32, sw32));
+    }
+    GRAV_HIP(hipStreamSynchronize(s));
     return GRAV_OK;
 }
 
@@ -949,6 +1058,8 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             }
         }
         if (p->M > 0 && (st = build_tree(p, s)) != GRAV_OK)
+            break;
+        if (p->M > 0 && (st = build_near_lattice(p, s)) != GRAV_OK)
             break;
         if ((st = build_operators(p)) != GRAV_OK)
             break;

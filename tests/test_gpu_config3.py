@@ -1,0 +1,68 @@
+"""The large volume workload: 256^3 cells, 1-point rule (16.8M sources),
+g at 512 x 512 stations (z = 1.1) plus every cell centre (17.0M targets),
+p = 8, mixed precision, one plan.
+
+* parity against the FP64 oracle on 4096 seeded targets (blobs + prism);
+* the prism alone against its closed form (Li & Chouteau form, Appendix A
+  of the paper uses it for Table A1): the 1-point rule's error at the
+  stations is O((h/d)^2), so the FMM result must sit within 1e-4 of the
+  exact field of the snapped box.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import prism
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+G = pytest.importorskip("paper_1107_5951_amd")
+
+N = 256
+PRISM = ((0.4, 0.6), (0.4, 0.6), (0.2, 0.5))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _plan(grid, st):
+    return G.Plan(G.PlanSpec(n=(N, N, N), h=grid.h, quad_order=1, points=st, voxel_centres=True,
+                             components=3, p=8, leaf_size=64, precision=G.GRAV_MIXED))
+
+
+def test_config3_blobs_and_prism_sampled_parity():
+    grid = W.Grid.unit(N)
+    st = W.stations(512, 1.1)
+    rho = W.gaussian_blobs(grid, 64, 1003) + W.box_density(grid, PRISM, 1.0)
+    plan = _plan(grid, st)
+    _say("config3 plan: %d targets, levels %d, leaf %d" % (plan.n_targets, plan.levels, plan.leaf_cells))
+    out = plan.eval(torch.as_tensor(rho, device="cuda"))
+    torch.cuda.synchronize()
+    idx = W.sample_indices(plan.n_targets, 4096, seed=7)
+    g = out.index_select(0, torch.as_tensor(idx, device="cuda")).cpu().numpy()
+    tg = np.concatenate([st, grid.centres()])[idx]
+    ref = oracle.forward(rho, grid.origin, grid.h, 1, tg, comps=3)
+    e = oracle.rel_l2(g, ref)
+    _say("config3 mixed p=8, 4096 sampled targets: rel err %.3e" % e)
+    assert e < 1e-4
+
+
+def test_config3_prism_against_closed_form():
+    grid = W.Grid.unit(N)
+    st = W.stations(512, 1.1)
+    rho = W.box_density(grid, PRISM, 1.0)
+    box = W.snapped_box(grid, PRISM)
+    plan = _plan(grid, st)
+    out = plan.eval(torch.as_tensor(rho, device="cuda"))
+    torch.cuda.synchronize()
+    gz = out[: st.shape[0], 2].cpu().numpy()
+    exact = prism.prism_gz(st, box, 1.0, 1.0)
+    e = np.linalg.norm(gz - exact) / np.linalg.norm(exact)
+    _say("config3 prism: FMM vs closed form of the snapped box, rel err %.3e" % e)
+    assert e < 1e-4
