@@ -64,6 +64,10 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     const DevLev &lp = g.lev[l];
     const DevLev &lc = g.lev[l + 1];
     const int RB = g.PS / 16;
+    const int rb0 = wave * RBW;
+    const int nr = min(RBW, RB - rb0);
+    if (nr <= 0)
+        return;  // whole wave: no row block left
     const int64_t nbox = (int64_t)lp.ns[0] * lp.ns[1] * lp.ns[2];
     const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
     const bool cvalid = col < nbox * g.B;
@@ -73,7 +77,6 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     const int py = lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1]);
     const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
     const int krow = lane >> 4;
-    const int rb0 = wave * RBW;
     vec4 acc[RBW];
 #pragma unroll
     for (int i = 0; i < RBW; ++i)
@@ -83,15 +86,8 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
                                                 2 * pz + ((c >> 2) & 1))
                                   : -1;
         const double *mp = me + (ci >= 0 ? ((lc.me_off + ci) * g.B + bm) * g.PS : 0);
-        const double *ap = A + (int64_t)c * g.KS * RB * 64 + lane;
-        for (int ks = 0; ks < g.KS; ++ks) {
-            const double bv = ci >= 0 ? mp[4 * ks + krow] : 0.0;
-            const double *ak = ap + (int64_t)ks * RB * 64;
-#pragma unroll
-            for (int i = 0; i < RBW; ++i)
-                if (rb0 + i < RB)  // uniform over the wave
-                    acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[(rb0 + i) * 64], bv, acc[i], 0, 0, 0);
-        }
+        mfma_panel<RBW, panel_unroll<RBW, double>(), double>(acc, A + (int64_t)c * g.KS * RB * 64 + lane, RB,
+                                                             rb0, nr, mp, ci >= 0, g.KS, krow);
     }
     if (!cvalid)
         return;
@@ -99,7 +95,7 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     double *dst = me + ((lp.me_off + box) * g.B + bm) * g.PS;
 #pragma unroll
     for (int i = 0; i < RBW; ++i) {
-        if (rb0 + i >= RB)
+        if (i >= nr)
             continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -138,14 +134,8 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
         acc[rb] = vec4{0, 0, 0, 0};
     const int krow = lane >> 4;
     const double *mp = le + (cvalid ? ((lp.tgt_off + par) * g.B + bm) * g.PS : 0);
-    const double *ap = A + (int64_t)tile.cls * g.KS * RB * 64 + lane;
-    for (int ks = 0; ks < g.KS; ++ks) {
-        const double bv = cvalid ? mp[4 * ks + krow] : 0.0;
-        const double *ak = ap + (int64_t)ks * RB * 64;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-            acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[rb * 64], bv, acc[rb], 0, 0, 0);
-    }
+    mfma_panel<RB, panel_unroll<RB, double>(), double>(acc, A + (int64_t)tile.cls * g.KS * RB * 64 + lane, RB,
+                                                       0, RB, mp, cvalid, g.KS, krow);
     if (!cvalid)
         return;
     double *dst = le + ((lv.tgt_off + box) * g.B + bm) * g.PS;
@@ -206,17 +196,7 @@ __device__ inline void m2l_body(const DevGeom &g, const GemmTile &tile, const ui
         const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
         const double *mp = me + (have ? (si * g.B + bm) * g.PS : 0);
         const T *kp = K + (int64_t)id * g.KS * RB * 64 + lane;
-        for (int ks = 0; ks < g.KS; ++ks) {
-            const T bv = have ? (T)mp[4 * ks + krow] : (T)0;
-            const T *ka = kp + (int64_t)ks * RB * 64;
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                if constexpr (sizeof(T) == 8)
-                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ka[rb * 64], bv, acc[rb], 0, 0, 0);
-                else
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ka[rb * 64], bv, acc[rb], 0, 0, 0);
-            }
-        }
+        mfma_panel<RB, panel_unroll<RB, T>(), T>(acc, kp, RB, 0, RB, mp, have, g.KS, krow);
     }
     if (!cvalid)
         return;
@@ -377,24 +357,56 @@ k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_star
 }
 
 // --------------------------------------------------------------------------
+// Densities in leaf blocks for the lattice near field: blk[pl][model][v],
+// pl = leaf index in the source block padded by one leaf on every side
+// (the padding and cells outside the mesh stay zero), v = cell in the leaf
+// (x fastest), rows padded to a multiple of 4.  One thread per entry.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_rho_blocks(DevGeom g, const double *rho, int KP, double *blk)
+{
+    const DevLev &lv = g.lev[g.L];
+    const int b = g.b, b2 = b * b, b3 = b2 * b;
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaf * g.B * b3)
+        return;
+    const int v = (int)(i % b3);
+    const int bm = (int)((i / b3) % g.B);
+    const int64_t leaf = i / ((int64_t)b3 * g.B);
+    const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    const int ix = lx * b + v % b, iy = ly * b + (v / b) % b, iz = lz * b + v / b2;
+    double r = 0.0;
+    if (ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
+        r = rho[(int64_t)bm * g.n[0] * g.n[1] * g.n[2] + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+    const int64_t pl = ((int64_t)(lz + 1) * (lv.ns[1] + 2) + (ly + 1)) * (lv.ns[0] + 2) + (lx + 1);
+    blk[(pl * g.B + bm) * KP + v] = r;
+}
+
+// --------------------------------------------------------------------------
 // Near field of the voxel-centre targets.  Targets and Gauss points both sit
 // on the lattice, so the near field of a leaf's b^3 cell centres is
 //   near[leaf] = sum over the 27 neighbour offsets d of  A_d rho[leaf + d],
 // with A_d a fixed (4 b^3) x b^3 matrix (the direct sum over the same point
 // pairs, precomputed in FP64).  Over all leaves this is a GEMM per offset:
-// columns = (leaf, model), K = cells of the neighbour leaf.  A wave owns 16
-// columns and RBW 16-row blocks; the workgroup's four waves split the rows.
-// Densities outside the mesh are zero; results go to the sorted slot of
+// columns = (leaf, model), K = cells of the neighbour leaf, read from the
+// padded leaf blocks.  A wave owns 16 columns and RBW 16-row blocks; the
+// workgroup's four waves split the rows.  Results go to the sorted slot of
 // each voxel centre.
 // --------------------------------------------------------------------------
 template <int RBW, typename T>
 __global__ void __launch_bounds__(256)
-k_near_lat(DevGeom g, const double *rho, const T *A, int RBn, int KSn, const int32_t *cell_slot,
+k_near_lat(DevGeom g, const double *blk, int KP, const T *A, int RBn, int KSn, const int32_t *cell_slot,
            double *near)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int rb0 = wave * RBW;
+    const int nr = min(RBW, RBn - rb0);
+    if (nr <= 0)
+        return;  // whole wave: no row block left
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
     const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
@@ -402,39 +414,19 @@ k_near_lat(DevGeom g, const double *rho, const T *A, int RBn, int KSn, const int
     const int64_t leaf = cvalid ? col / g.B : 0;
     const int bm = cvalid ? (int)(col % g.B) : 0;
     const int b = g.b, b2 = b * b, b3 = b2 * b;
-    const int c0[3] = {(int)(leaf % lv.ns[0]) * b, (int)((leaf / lv.ns[0]) % lv.ns[1]) * b,
-                       (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1])) * b};
-    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    const double *rm = rho + (int64_t)bm * ncell;
+    const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    const int px = lv.ns[0] + 2, py = lv.ns[1] + 2;
     const int krow = lane >> 4;
-    const int rb0 = wave * RBW;
     vec4 acc[RBW];
 #pragma unroll
     for (int i = 0; i < RBW; ++i)
         acc[i] = vec4{0, 0, 0, 0};
     for (int nb = 0; nb < 27; ++nb) {
-        const int ox = c0[0] + (nb % 3 - 1) * b, oy = c0[1] + ((nb / 3) % 3 - 1) * b,
-                  oz = c0[2] + (nb / 9 - 1) * b;
-        const T *ap = A + (int64_t)nb * KSn * RBn * 64 + lane;
-        for (int ks = 0; ks < KSn; ++ks) {
-            const int v = 4 * ks + krow;
-            T bv = (T)0;
-            if (cvalid && v < b3) {
-                const int ix = ox + v % b, iy = oy + (v / b) % b, iz = oz + v / b2;
-                if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
-                    bv = (T)rm[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
-            }
-            const T *ak = ap + (int64_t)ks * RBn * 64;
-#pragma unroll
-            for (int i = 0; i < RBW; ++i) {
-                if (rb0 + i < RBn) {  // uniform over the wave
-                    if constexpr (sizeof(T) == 8)
-                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[(rb0 + i) * 64], bv, acc[i], 0, 0, 0);
-                    else
-                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[(rb0 + i) * 64], bv, acc[i], 0, 0, 0);
-                }
-            }
-        }
+        const int64_t pl = ((int64_t)(lz + nb / 9) * py + (ly + (nb / 3) % 3)) * px + (lx + nb % 3);
+        const double *bp = blk + (pl * g.B + bm) * KP;
+        mfma_panel<RBW, panel_unroll<RBW, T>(), T>(acc, A + (int64_t)nb * KSn * RBn * 64 + lane, RBn, rb0,
+                                                   nr, bp, cvalid, KSn, krow);
     }
     if (!cvalid)
         return;
@@ -442,9 +434,9 @@ k_near_lat(DevGeom g, const double *rho, const T *A, int RBn, int KSn, const int
 #pragma unroll
     for (int i = 0; i < RBW; ++i) {
         const int t = 4 * (rb0 + i) + krow;
-        if (rb0 + i >= RBn || t >= b3)
+        if (i >= nr || t >= b3)
             continue;
-        const int ix = c0[0] + t % b, iy = c0[1] + (t / b) % b, iz = c0[2] + t / b2;
+        const int ix = lx * b + t % b, iy = ly * b + (t / b) % b, iz = lz * b + t / b2;
         if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
             continue;
         const int64_t j = cell_slot[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
@@ -678,6 +670,11 @@ static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
 static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho, hipStream_t s)
 {
     const LevelInfo &lv = p->lev[p->L];
+    const int b3 = p->b * p->b * p->b;
+    const int64_t nfill = lv.n_src * p->B * b3;
+    hipLaunchKernelGGL(k_rho_blocks, dim3((unsigned)((nfill + 255) / 256)), dim3(256), 0, s, g, rho,
+                       4 * p->lat_KS, p->d_rho_blk);
+    GRAV_HIP(hipGetLastError());
     const int64_t ncol = lv.n_src * p->B;
     const int RBn = p->lat_RB, KSn = p->lat_KS;
     const int RBW = (RBn + 3) / 4;
@@ -685,13 +682,13 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
 #define NEAR_CASE(W)                                                                            \
     case W:                                                                                     \
         if (p->d.precision == GRAV_FP64)                                                        \
-            hipLaunchKernelGGL((k_near_lat<W, double>), grid, blk, 0, s, g, rho,                 \
-                               (const double *)p->d_tn64, RBn, KSn, (const int32_t *)p->d_cell_slot, \
-                               p->d_near);                                                      \
+            hipLaunchKernelGGL((k_near_lat<W, double>), grid, blk, 0, s, g,                      \
+                               (const double *)p->d_rho_blk, 4 * KSn, (const double *)p->d_tn64, \
+                               RBn, KSn, (const int32_t *)p->d_cell_slot, p->d_near);           \
         else                                                                                    \
-            hipLaunchKernelGGL((k_near_lat<W, float>), grid, blk, 0, s, g, rho,                  \
-                               (const float *)p->d_tn32, RBn, KSn, (const int32_t *)p->d_cell_slot, \
-                               p->d_near);                                                      \
+            hipLaunchKernelGGL((k_near_lat<W, float>), grid, blk, 0, s, g,                       \
+                               (const double *)p->d_rho_blk, 4 * KSn, (const float *)p->d_tn32,  \
+                               RBn, KSn, (const int32_t *)p->d_cell_slot, p->d_near);           \
         break;
     switch (RBW) {
         NEAR_CASE(1)

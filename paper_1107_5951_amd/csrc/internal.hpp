@@ -88,6 +88,7 @@ struct Plan {
     double *d_tn64 = nullptr;                      // [27][KS][RB][64] swizzled, FP64 plans
     float *d_tn32 = nullptr;                       // same, mixed plans
     int32_t *d_cell_slot = nullptr;                // [ncell] sorted slot of each voxel centre
+    double *d_rho_blk = nullptr;                   // [padded leaves][B][4 KS] densities per leaf
     int64_t *d_leaf_pend = nullptr;                // [n_leaf] end of the user points of a leaf                  // workgroups sharing the offsets of one tile
     double *d_part = nullptr;                      // [split][expansions][PS] partial sums
     int32_t *d_class_off = nullptr;  // [8][189][4] (dx, dy, dz, offset id)

@@ -250,7 +250,7 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw,
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk,
                     p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
@@ -629,6 +629,14 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
                         v = dense[((size_t)nb * 4 * b3 + 4 * t + comp) * b3 + col];
                     sw[(((size_t)nb * KSn + ks) * RBn + rb) * 64 + lane] = v;
                 }
+    {
+        // leaf blocks of the densities, padded by one leaf per side; the
+        // padding and the rows past b^3 stay zero
+        const LevelInfo &lv = p->lev[p->L];
+        const size_t n = (size_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B * 4 * KSn;
+        GRAV_CHECK(dalloc(p, &p->d_rho_blk, n, false));
+        GRAV_HIP(hipMemset(p->d_rho_blk, 0, sizeof(double) * n));
+    }
     if (f64) {
         GRAV_CHECK(upload(p, &p->d_tn64, sw));
     } else {
