@@ -148,39 +148,56 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
 
 // --------------------------------------------------------------------------
 // M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
-// child-parity class, model); wave w owns columns 16w..16w+15.  For each of
-// the class's 189 interaction-list offsets d the wave accumulates
-// LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA tiles; K_d comes
-// pre-swizzled so that each A fragment is one coalesced 512-byte load.
-// Accumulation stays in registers across all offsets; no atomics.
+// child-parity class, model) of one split of the class's 189 interaction-
+// list offsets d.  For each d the workgroup accumulates
+// LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA tiles.  The four
+// waves split the rows: wave w owns row blocks [w RBW, w RBW + RBW) of all
+// four 16-column panels, so each K fragment is fetched once per workgroup
+// and feeds four instructions.  K_d comes pre-swizzled so that each A
+// fragment is one coalesced load.  Accumulation stays in registers across
+// the offsets; no atomics.
 // --------------------------------------------------------------------------
-template <int RB, typename T>
-__device__ inline void m2l_body(const DevGeom &g, const GemmTile &tile, const uint32_t *tkey,
-                                const int32_t *torder, const int32_t *class_off, const T *K,
-                                const double *me, double *le, int S, int64_t part_stride)
+template <int RBW, typename T>
+__global__ void __launch_bounds__(256)
+k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
+      const int32_t *class_off, const T *K, const double *me, double *le, int S, int64_t part_stride)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
+    constexpr int NB = 4;
+    const GemmTile tile = tiles[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int RB = g.PS / 16;
+    const int rb0 = wave * RBW;
+    const int nr = min(RBW, RB - rb0);
+    if (nr <= 0)
+        return;  // whole wave: no row block left
     const DevLev &lv = g.lev[tile.level];
-    const int cl = wave * 16 + (lane & 15);
-    const bool cvalid = cl < tile.ncol;
-    const int64_t col = tile.col0 + cl;
-    const int64_t boxpos = col / g.B;
-    const int bm = (int)(col % g.B);
-    int64_t box = 0;
-    int bx = 0, by = 0, bz = 0;
-    if (cvalid) {
-        box = torder[lv.tbox_off + lv.class_start[tile.cls] + boxpos];
-        const uint32_t key = tkey[lv.tbox_off + box];
-        bx = (int)compact3(key);
-        by = (int)compact3(key >> 1);
-        bz = (int)compact3(key >> 2);
-    }
-    vec4 acc[RB];
+    int bx[NB], by[NB], bz[NB], bmj[NB];
+    int64_t box[NB];
+    bool cv[NB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-        acc[rb] = vec4{0, 0, 0, 0};
+    for (int j = 0; j < NB; ++j) {
+        const int cl = 16 * j + (lane & 15);
+        cv[j] = cl < tile.ncol;
+        const int64_t col = tile.col0 + cl;
+        bmj[j] = (int)(col % g.B);
+        box[j] = 0;
+        bx[j] = by[j] = bz[j] = 0;
+        if (cv[j]) {
+            box[j] = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
+            const uint32_t key = tkey[lv.tbox_off + box[j]];
+            bx[j] = (int)compact3(key);
+            by[j] = (int)compact3(key >> 1);
+            bz[j] = (int)compact3(key >> 2);
+        }
+    }
+    vec4 acc[NB][RBW];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int i = 0; i < RBW; ++i)
+            acc[j][i] = vec4{0, 0, 0, 0};
     const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
     const int krow = lane >> 4;
     // offsets [o0, o1) of this split (tile.pad of S)
@@ -188,37 +205,42 @@ __device__ inline void m2l_body(const DevGeom &g, const GemmTile &tile, const ui
     for (int o = o0; o < o1; ++o) {
         const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
         const int id = offs[4 * o + 3];
-        const int sx = bx + dx - lv.s0[0], sy = by + dy - lv.s0[1], sz = bz + dz - lv.s0[2];
-        const bool have = cvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] &&
-                          sy < lv.ns[1] && sz < lv.ns[2];
-        if (__ballot(have) == 0ull)
-            continue;  // no column of this wave sees a source box at this offset
-        const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
-        const double *mp = me + (have ? (si * g.B + bm) * g.PS : 0);
-        const T *kp = K + (int64_t)id * g.KS * RB * 64 + lane;
-        mfma_panel<RB, panel_unroll<RB, T>(), T>(acc, kp, RB, 0, RB, mp, have, g.KS, krow);
+        const double *mp[NB];
+        bool have[NB];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int sx = bx[j] + dx - lv.s0[0], sy = by[j] + dy - lv.s0[1], sz = bz[j] + dz - lv.s0[2];
+            have[j] = cv[j] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
+                      sz < lv.ns[2];
+            const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
+            mp[j] = me + (have[j] ? (si * g.B + bmj[j]) * g.PS : 0);
+            any = any || have[j];
+        }
+        if (__ballot(any) == 0ull)
+            continue;  // no column of the tile sees a source box at this offset
+        mfma_panels<RBW, NB, panel_unroll<RBW, T, NB>(), T>(acc, K + (int64_t)id * g.KS * RB * 64 + lane, RB,
+                                                            rb0, nr, mp, have, g.KS, krow);
     }
-    if (!cvalid)
-        return;
-    // Output fragment: lane holds column lane % 16 and four rows; the FP32
-    // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
-    // (split partials go to their own slab of the workspace)
-    double *dst = le + (tile.pad * part_stride + (lv.tgt_off + box) * g.B + bm) * g.PS;
+    // Output fragment: lane holds column lane % 16 of each panel and four
+    // rows; the FP32 instruction gives rows 4*(lane/16) + r, the FP64 one
+    // rows lane/16 + 4r.  Split partials go to their own slab.
     constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
     const int rbase = sizeof(T) == 8 ? krow : 4 * krow;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int j = 0; j < NB; ++j) {
+        if (!cv[j])
+            continue;
+        double *dst = le + (tile.pad * part_stride + (lv.tgt_off + box[j]) * g.B + bmj[j]) * g.PS;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            dst[16 * rb + rbase + rstride * r] = (double)acc[rb][r];
-}
-
-template <int RB, typename T>
-__global__ void __launch_bounds__(256)
-k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
-      const int32_t *class_off, const T *K, const double *me, double *le, int S, int64_t part_stride)
-{
-    m2l_body<RB, T>(g, tiles[blockIdx.x], tkey, torder, class_off, K, me, le, S, part_stride);
+        for (int i = 0; i < RBW; ++i) {
+            if (i >= nr)
+                continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                dst[16 * (rb0 + i) + rbase + rstride * r] = (double)acc[j][i][r];
+        }
+    }
 }
 
 // out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ...
@@ -572,34 +594,26 @@ void stage_end(Plan *p, hipStream_t s)
 template <typename T>
 static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
 {
-    const int RB = p->PS / 16;
     const TileRange &r = p->tiles[TK_M2L][0];
     if (r.n == 0)
         return GRAV_OK;
+    const int RBW = (p->PS / 16 + 3) / 4;
     dim3 grid(r.n), blk(256);
     const int S = p->split[TK_M2L];
     const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
     double *dst = S > 1 ? p->d_part : p->d_le;
-#define M2L_CASE(R)                                                                             \
-    case R:                                                                                     \
-        hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off),     \
+#define M2L_CASE(W)                                                                             \
+    case W:                                                                                     \
+        hipLaunchKernelGGL((k_m2l<W, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
                            (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
                            (const int32_t *)p->d_class_off, K, (const double *)p->d_me, dst,    \
                            S, pstride);                                                         \
         break;
-    switch (RB) {
+    switch (RBW) {
         M2L_CASE(1)
         M2L_CASE(2)
         M2L_CASE(3)
         M2L_CASE(4)
-        M2L_CASE(6)
-        M2L_CASE(7)
-        M2L_CASE(8)
-        M2L_CASE(9)
-        M2L_CASE(11)
-        M2L_CASE(13)
-        M2L_CASE(15)
-        M2L_CASE(16)
     default:
         return GRAV_EUNSUPPORTED;
     }

@@ -79,11 +79,51 @@ __device__ inline void mfma_panel(__attribute__((__vector_size__(4 * sizeof(T)))
     }
 }
 
+// NB column panels sharing the A fragments: acc[j][i] += A[rb0 + i] * B_j.
+// Lane reads column j's value from bp[j][4 ks + lane / 16].  Each A fragment
+// is loaded once and used NB times.
+template <int NR, int NB, int U, typename T>
+__device__ inline void mfma_panels(__attribute__((__vector_size__(4 * sizeof(T)))) T (&acc)[NB][NR],
+                                   const T *ap, int RBS, int rb0, int nr, const double *const (&bp)[NB],
+                                   const bool (&use_b)[NB], int KS, int krow)
+{
+    for (int ks0 = 0; ks0 < KS; ks0 += U) {
+        T bv[U][NB];
+        T av[U][NR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ks = min(ks0 + u, KS - 1);
+            const bool in = ks0 + u < KS;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const double v = bp[j][4 * ks + krow];
+                bv[u][j] = (use_b[j] && in) ? (T)v : (T)0;
+            }
+            const T *ak = ap + ((int64_t)ks * RBS + rb0) * 64;
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+                av[u][i] = i < nr ? ak[i * 64] : (T)0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    if constexpr (sizeof(T) == 8)
+                        acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[j][i], 0, 0, 0);
+                    else
+                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][i], bv[u][j], acc[j][i], 0, 0, 0);
+                }
+    }
+}
+
 // Loads in flight per k step chunk: keep U * NR operand registers near 64.
-template <int NR, typename T>
+template <int NR, typename T, int NB = 1>
 constexpr int panel_unroll()
 {
-    constexpr int w = NR * (int)(sizeof(T) / 4);
+    constexpr int w = (NR + NB) * (int)(sizeof(T) / 4);
     return w >= 64 ? 1 : (64 / w > 8 ? 8 : 64 / w);
 }
 
