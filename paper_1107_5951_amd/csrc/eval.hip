@@ -51,25 +51,24 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const
 // --------------------------------------------------------------------------
 // M2M on MFMA (FP64): ME[parent] = sum over the 8 children c of T_c ME[child],
 // a GEMM with columns = (parent box, model) and K = 8 x p^2.  A workgroup
-// owns 16 columns; its four waves split the rows (RBW row blocks each).
-// Children outside the source block contribute nothing.
+// owns 16 columns and one 16-row block; its four waves take two children
+// each and their partial fragments are added through LDS.  Children outside
+// the source block contribute nothing.
 // --------------------------------------------------------------------------
-template <int RBW>
 __global__ void __launch_bounds__(256)
 k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    __shared__ double red[4][256];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const DevLev &lp = g.lev[l];
     const DevLev &lc = g.lev[l + 1];
     const int RB = g.PS / 16;
-    const int rb0 = wave * RBW;
-    const int nr = min(RBW, RB - rb0);
-    if (nr <= 0)
-        return;  // whole wave: no row block left
+    const int64_t cg = blockIdx.x / RB;
+    const int rb = (int)(blockIdx.x % RB);
     const int64_t nbox = (int64_t)lp.ns[0] * lp.ns[1] * lp.ns[2];
-    const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const int64_t col = cg * 16 + (lane & 15);
     const bool cvalid = col < nbox * g.B;
     const int64_t box = cvalid ? col / g.B : 0;
     const int bm = cvalid ? (int)(col % g.B) : 0;
@@ -77,29 +76,27 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     const int py = lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1]);
     const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
     const int krow = lane >> 4;
-    vec4 acc[RBW];
-#pragma unroll
-    for (int i = 0; i < RBW; ++i)
-        acc[i] = vec4{0, 0, 0, 0};
-    for (int c = 0; c < 8; ++c) {
+    vec4 acc[1] = {vec4{0, 0, 0, 0}};
+    // wave w takes children 2w and 2w + 1
+    for (int c = 2 * wave; c < 2 * wave + 2; ++c) {
         const int64_t ci = cvalid ? dense_index(lc, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1),
                                                 2 * pz + ((c >> 2) & 1))
                                   : -1;
         const double *mp = me + (ci >= 0 ? ((lc.me_off + ci) * g.B + bm) * g.PS : 0);
-        mfma_panel<RBW, panel_unroll<RBW, double>(), double>(acc, A + (int64_t)c * g.KS * RB * 64 + lane, RB,
-                                                             rb0, nr, mp, ci >= 0, g.KS, krow);
+        mfma_panel<1, panel_unroll<1, double>(), double>(acc, A + (int64_t)c * g.KS * RB * 64 + lane, RB, rb, 1,
+                                                         mp, ci >= 0, g.KS, krow);
     }
-    if (!cvalid)
-        return;
-    // FP64 fragment: column lane % 16, rows lane / 16 + 4 r of each block
-    double *dst = me + ((lp.me_off + box) * g.B + bm) * g.PS;
+    // the four waves' fragments share one lane layout: add them in wave order
 #pragma unroll
-    for (int i = 0; i < RBW; ++i) {
-        if (i >= nr)
-            continue;
+    for (int r = 0; r < 4; ++r)
+        red[wave][lane * 4 + r] = acc[0][r];
+    __syncthreads();
+    if (wave == 0 && cvalid) {
+        double *dst = me + ((lp.me_off + box) * g.B + bm) * g.PS;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            dst[16 * (rb0 + i) + krow + 4 * r] = acc[i][r];
+            dst[16 * rb + krow + 4 * r] =
+                ((red[0][lane * 4 + r] + red[1][lane * 4 + r]) + red[2][lane * 4 + r]) + red[3][lane * 4 + r];
     }
 }
 
@@ -149,98 +146,96 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
 // --------------------------------------------------------------------------
 // M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
 // child-parity class, model) of one split of the class's 189 interaction-
-// list offsets d.  For each d the workgroup accumulates
-// LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA tiles.  The four
-// waves split the rows: wave w owns row blocks [w RBW, w RBW + RBW) of all
-// four 16-column panels, so each K fragment is fetched once per workgroup
-// and feeds four instructions.  K_d comes pre-swizzled so that each A
-// fragment is one coalesced load.  Accumulation stays in registers across
-// the offsets; no atomics.
+// list offsets d; wave w owns columns 16w..16w+15 and all row blocks.  For
+// each d the wave accumulates LE[:, col] += K_d * ME[box(col) + d] with
+// 16x16x4 MFMA tiles, accumulating in registers across the offsets (no
+// atomics).
+//
+// Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
+// instruction take coefficient c = kr * PS/4 + ks (ks = 0 .. PS/4 - 1), so
+// a lane's B values for four consecutive k steps are four consecutive
+// coefficients of one expansion (one aligned 32-byte load), and the A
+// fragments of four k steps are stored contiguously per lane
+// ([d][q][lane][u][rb], ks = 4q + u): RB aligned vector loads.  Padding
+// coefficients (c >= p^2) are zero in the expansions.
 // --------------------------------------------------------------------------
-template <int RBW, typename T>
+template <int RB, typename T>
 __global__ void __launch_bounds__(256)
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
       const int32_t *class_off, const T *K, const double *me, double *le, int S, int64_t part_stride)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
-    constexpr int NB = 4;
     const GemmTile tile = tiles[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int RB = g.PS / 16;
-    const int rb0 = wave * RBW;
-    const int nr = min(RBW, RB - rb0);
-    if (nr <= 0)
-        return;  // whole wave: no row block left
     const DevLev &lv = g.lev[tile.level];
-    int bx[NB], by[NB], bz[NB], bmj[NB];
-    int64_t box[NB];
-    bool cv[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int cl = 16 * j + (lane & 15);
-        cv[j] = cl < tile.ncol;
-        const int64_t col = tile.col0 + cl;
-        bmj[j] = (int)(col % g.B);
-        box[j] = 0;
-        bx[j] = by[j] = bz[j] = 0;
-        if (cv[j]) {
-            box[j] = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
-            const uint32_t key = tkey[lv.tbox_off + box[j]];
-            bx[j] = (int)compact3(key);
-            by[j] = (int)compact3(key >> 1);
-            bz[j] = (int)compact3(key >> 2);
-        }
+    const int cl = wave * 16 + (lane & 15);
+    const bool cvalid = cl < tile.ncol;
+    const int64_t col = tile.col0 + cl;
+    const int bm = (int)(col % g.B);
+    int64_t box = 0;
+    int bx = 0, by = 0, bz = 0;
+    if (cvalid) {
+        box = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
+        const uint32_t key = tkey[lv.tbox_off + box];
+        bx = (int)compact3(key);
+        by = (int)compact3(key >> 1);
+        bz = (int)compact3(key >> 2);
     }
-    vec4 acc[NB][RBW];
+    vec4 acc[RB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int i = 0; i < RBW; ++i)
-            acc[j][i] = vec4{0, 0, 0, 0};
+    for (int rb = 0; rb < RB; ++rb)
+        acc[rb] = vec4{0, 0, 0, 0};
     const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
-    const int krow = lane >> 4;
+    const int kr = lane >> 4;
+    constexpr int PS = 16 * RB;
+    constexpr int64_t kstride = (int64_t)RB * 64 * 4 * RB;  // elements per offset matrix
     // offsets [o0, o1) of this split (tile.pad of S)
     const int o0 = tile.pad * kClassOffsets / S, o1 = (tile.pad + 1) * kClassOffsets / S;
     for (int o = o0; o < o1; ++o) {
         const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
         const int id = offs[4 * o + 3];
-        const double *mp[NB];
-        bool have[NB];
-        bool any = false;
+        const int sx = bx + dx - lv.s0[0], sy = by + dy - lv.s0[1], sz = bz + dz - lv.s0[2];
+        const bool have = cvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] &&
+                          sy < lv.ns[1] && sz < lv.ns[2];
+        if (__ballot(have) == 0ull)
+            continue;  // no column of this wave sees a source box at this offset
+        const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
+        const double2 *mp = (const double2 *)(me + (have ? (si * g.B + bm) * PS : 0) + kr * (PS / 4));
+        const T *kp = K + (int64_t)id * kstride + lane * 4 * RB;
+        for (int q = 0; q < RB; ++q) {
+            const double2 b01 = mp[2 * q], b23 = mp[2 * q + 1];
+            T av[4 * RB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int sx = bx[j] + dx - lv.s0[0], sy = by[j] + dy - lv.s0[1], sz = bz[j] + dz - lv.s0[2];
-            have[j] = cv[j] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
-                      sz < lv.ns[2];
-            const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
-            mp[j] = me + (have[j] ? (si * g.B + bmj[j]) * g.PS : 0);
-            any = any || have[j];
+            for (int e = 0; e < 4 * RB; ++e)
+                av[e] = kp[(int64_t)q * 64 * 4 * RB + e];
+            __builtin_amdgcn_sched_barrier(0);
+            const T bv[4] = {have ? (T)b01.x : (T)0, have ? (T)b01.y : (T)0, have ? (T)b23.x : (T)0,
+                             have ? (T)b23.y : (T)0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    if constexpr (sizeof(T) == 8)
+                        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u * RB + rb], bv[u], acc[rb], 0, 0, 0);
+                    else
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u * RB + rb], bv[u], acc[rb], 0, 0, 0);
+                }
         }
-        if (__ballot(any) == 0ull)
-            continue;  // no column of the tile sees a source box at this offset
-        mfma_panels<RBW, NB, panel_unroll<RBW, T, NB>(), T>(acc, K + (int64_t)id * g.KS * RB * 64 + lane, RB,
-                                                            rb0, nr, mp, have, g.KS, krow);
     }
-    // Output fragment: lane holds column lane % 16 of each panel and four
-    // rows; the FP32 instruction gives rows 4*(lane/16) + r, the FP64 one
-    // rows lane/16 + 4r.  Split partials go to their own slab.
+    if (!cvalid)
+        return;
+    // Output fragment: lane holds column lane % 16 and four rows; the FP32
+    // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
+    // Split partials go to their own slab of the workspace.
+    double *dst = le + (tile.pad * part_stride + (lv.tgt_off + box) * g.B + bm) * PS;
     constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
-    const int rbase = sizeof(T) == 8 ? krow : 4 * krow;
+    const int rbase = sizeof(T) == 8 ? kr : 4 * kr;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        if (!cv[j])
-            continue;
-        double *dst = le + (tile.pad * part_stride + (lv.tgt_off + box[j]) * g.B + bmj[j]) * g.PS;
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < RBW; ++i) {
-            if (i >= nr)
-                continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                dst[16 * (rb0 + i) + rbase + rstride * r] = (double)acc[j][i][r];
-        }
-    }
+        for (int r = 0; r < 4; ++r)
+            dst[16 * rb + rbase + rstride * r] = (double)acc[rb][r];
 }
 
 // out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ...
@@ -597,23 +592,30 @@ static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T 
     const TileRange &r = p->tiles[TK_M2L][0];
     if (r.n == 0)
         return GRAV_OK;
-    const int RBW = (p->PS / 16 + 3) / 4;
     dim3 grid(r.n), blk(256);
     const int S = p->split[TK_M2L];
     const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
     double *dst = S > 1 ? p->d_part : p->d_le;
-#define M2L_CASE(W)                                                                             \
-    case W:                                                                                     \
-        hipLaunchKernelGGL((k_m2l<W, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
+#define M2L_CASE(R)                                                                             \
+    case R:                                                                                     \
+        hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
                            (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
                            (const int32_t *)p->d_class_off, K, (const double *)p->d_me, dst,    \
                            S, pstride);                                                         \
         break;
-    switch (RBW) {
+    switch (p->PS / 16) {
         M2L_CASE(1)
         M2L_CASE(2)
         M2L_CASE(3)
         M2L_CASE(4)
+        M2L_CASE(6)
+        M2L_CASE(7)
+        M2L_CASE(8)
+        M2L_CASE(9)
+        M2L_CASE(11)
+        M2L_CASE(13)
+        M2L_CASE(15)
+        M2L_CASE(16)
     default:
         return GRAV_EUNSUPPORTED;
     }
@@ -624,23 +626,9 @@ static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T 
 
 static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
 {
-    const int64_t ncol = p->lev[l].n_src * p->B;
-    const int RBW = (p->PS / 16 + 3) / 4;
-    dim3 grid((unsigned)((ncol + 15) / 16)), blk(256);
-#define M2M_CASE(W)                                                                             \
-    case W:                                                                                     \
-        hipLaunchKernelGGL((k_m2m_mfma<W>), grid, blk, 0, s, g, l, (const double *)p->d_m2m_sw, \
-                           p->d_me);                                                            \
-        break;
-    switch (RBW) {
-        M2M_CASE(1)
-        M2M_CASE(2)
-        M2M_CASE(3)
-        M2M_CASE(4)
-    default:
-        return GRAV_EUNSUPPORTED;
-    }
-#undef M2M_CASE
+    const int64_t ncg = (p->lev[l].n_src * p->B + 15) / 16;
+    hipLaunchKernelGGL(k_m2m_mfma, dim3((unsigned)(ncg * (p->PS / 16))), dim3(256), 0, s, g, l,
+                       (const double *)p->d_m2m_sw, p->d_me);
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }

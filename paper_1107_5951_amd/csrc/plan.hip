@@ -360,6 +360,23 @@ void swizzle(const double *m, int PS, int KS, bool transpose, double *dst)
             }
 }
 
+// Forward M2L operand layout: k step ks (0 .. PS/4 - 1) and instruction
+// sub-row kr = lane / 16 contract coefficient kr * PS/4 + ks; the fragments
+// of four consecutive k steps are contiguous per lane:
+// dst[q][lane][u][rb] = m[16 rb + lane % 16][(lane / 16) * PS/4 + 4 q + u].
+void swizzle_panel(const double *m, int PS, double *dst)
+{
+    const int RB = PS / 16, KP = PS / 4;
+    for (int q = 0; q < RB; ++q)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int u = 0; u < 4; ++u)
+                for (int rb = 0; rb < RB; ++rb) {
+                    const int row = 16 * rb + (lane & 15);
+                    const int col = (lane >> 4) * KP + 4 * q + u;
+                    dst[(((size_t)q * 64 + lane) * 4 + u) * RB + rb] = m[(size_t)row * PS + col];
+                }
+}
+
 template <class T>
 grav_status upload(Plan *p, T **dst, const std::vector<T> &src)
 {
@@ -417,12 +434,13 @@ grav_status build_operators(Plan *p)
     std::vector<int32_t> fwd, rev;
     offsets_tables(all, fwd, rev);
     const size_t per = (size_t)KS * RB * 64;
-    std::vector<double> k(per * kNumOffsets), kT(per * kNumOffsets);
+    const size_t perp = (size_t)RB * 64 * 4 * RB;  // forward M2L: PS/4 k steps, grouped by four
+    std::vector<double> k(perp * kNumOffsets), kT(per * kNumOffsets);
     for (int id = 0; id < kNumOffsets; ++id) {
         // source = target + d  =>  target centre - source centre = -d
         const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
         m2l_matrix(P, dd, PS, m.data());
-        swizzle(m.data(), PS, KS, false, k.data() + per * id);
+        swizzle_panel(m.data(), PS, k.data() + perp * id);
         swizzle(m.data(), PS, KS, true, kT.data() + per * id);
     }
     if (p->d.precision == GRAV_FP64) {
