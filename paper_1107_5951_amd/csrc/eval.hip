@@ -203,24 +203,47 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
         const double2 *mp = (const double2 *)(me + (have ? (si * g.B + bm) * PS : 0) + kr * (PS / 4));
         const T *kp = K + (int64_t)id * kstride + lane * 4 * RB;
-        for (int q = 0; q < RB; ++q) {
-            const double2 b01 = mp[2 * q], b23 = mp[2 * q + 1];
-            T av[4 * RB];
+        // two register sets (when they fit): the loads of chunk q + 1 are in
+        // flight while the instructions of chunk q run
+        constexpr int NSET = 4 * RB * (int)sizeof(T) <= 128 ? 2 : 1;
+        T av[NSET][4 * RB];
+        double2 bb[NSET][2];
+        auto load = [&](int q, int set) {
+            bb[set][0] = mp[2 * q];
+            bb[set][1] = mp[2 * q + 1];
 #pragma unroll
             for (int e = 0; e < 4 * RB; ++e)
-                av[e] = kp[(int64_t)q * 64 * 4 * RB + e];
-            __builtin_amdgcn_sched_barrier(0);
-            const T bv[4] = {have ? (T)b01.x : (T)0, have ? (T)b01.y : (T)0, have ? (T)b23.x : (T)0,
-                             have ? (T)b23.y : (T)0};
+                av[set][e] = kp[(int64_t)q * 64 * 4 * RB + e];
+        };
+        auto compute = [&](int set) {
+            const T bv[4] = {have ? (T)bb[set][0].x : (T)0, have ? (T)bb[set][0].y : (T)0,
+                             have ? (T)bb[set][1].x : (T)0, have ? (T)bb[set][1].y : (T)0};
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
                     if constexpr (sizeof(T) == 8)
-                        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u * RB + rb], bv[u], acc[rb], 0, 0, 0);
+                        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[u], acc[rb], 0, 0, 0);
                     else
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u * RB + rb], bv[u], acc[rb], 0, 0, 0);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[u], acc[rb], 0, 0, 0);
                 }
+        };
+        if constexpr (NSET == 2) {
+            load(0, 0);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                if (q + 1 < RB)
+                    load(q + 1, (q + 1) & 1);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(q & 1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            for (int q = 0; q < RB; ++q) {
+                load(q, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(0);
+            }
         }
     }
     if (!cvalid)
@@ -402,22 +425,26 @@ k_rho_blocks(DevGeom g, const double *rho, int KP, double *blk)
 }
 
 // --------------------------------------------------------------------------
-// Near field of the voxel-centre targets.  Targets and Gauss points both sit
-// on the lattice, so the near field of a leaf's b^3 cell centres is
+// The voxel-centre targets, fused: near field + far field + combine.
+// Targets and Gauss points both sit on the lattice, so the near field of a
+// leaf's b^3 cell centres is
 //   near[leaf] = sum over the 27 neighbour offsets d of  A_d rho[leaf + d],
 // with A_d a fixed (4 b^3) x b^3 matrix (the direct sum over the same point
-// pairs, precomputed in FP64).  Over all leaves this is a GEMM per offset:
-// columns = (leaf, model), K = cells of the neighbour leaf, read from the
-// padded leaf blocks.  A wave owns 16 columns and RBW 16-row blocks; the
-// workgroup's four waves split the rows.  Results go to the sorted slot of
-// each voxel centre.
+// pairs, precomputed in FP64), and the far field is a fixed (4 b^3) x PS
+// matrix applied to the leaf's local expansion (L2P at fixed points, FP64).
+// Over all leaves these are GEMMs with columns = (leaf, model).  A workgroup
+// owns 16 columns; its waves split the 4 b^3 rows; operand fragments are
+// laid out per lane ([q][rb][lane][u], four k steps per vector load).  The
+// result goes straight to the output in descriptor order, G applied.
 // --------------------------------------------------------------------------
 template <int RBW, typename T>
 __global__ void __launch_bounds__(256)
-k_near_lat(DevGeom g, const double *blk, int KP, const T *A, int RBn, int KSn, const int32_t *cell_slot,
-           double *near)
+k_near_lat(DevGeom g, const double *blk, const T *A, int RBn, int Qn, const double *Lm,
+           const int32_t *tmap, const double *le, int64_t npts, double *out)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
+    using dvec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    using tvec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rb0 = wave * RBW;
@@ -434,33 +461,94 @@ k_near_lat(DevGeom g, const double *blk, int KP, const T *A, int RBn, int KSn, c
     const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
               lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
     const int px = lv.ns[0] + 2, py = lv.ns[1] + 2;
-    const int krow = lane >> 4;
+    const int kr = lane >> 4;
+    const int KP = 16 * Qn;
     vec4 acc[RBW];
 #pragma unroll
     for (int i = 0; i < RBW; ++i)
         acc[i] = vec4{0, 0, 0, 0};
     for (int nb = 0; nb < 27; ++nb) {
         const int64_t pl = ((int64_t)(lz + nb / 9) * py + (ly + (nb / 3) % 3)) * px + (lx + nb % 3);
-        const double *bp = blk + (pl * g.B + bm) * KP;
-        mfma_panel<RBW, panel_unroll<RBW, T>(), T>(acc, A + (int64_t)nb * KSn * RBn * 64 + lane, RBn, rb0,
-                                                   nr, bp, cvalid, KSn, krow);
+        const double2 *bp = (const double2 *)(blk + (pl * g.B + bm) * KP + kr * (KP / 4));
+        const tvec4 *ap = (const tvec4 *)A + ((int64_t)nb * Qn * RBn + rb0) * 64 + lane;
+        for (int q = 0; q < Qn; ++q) {
+            const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
+            tvec4 av[RBW];
+#pragma unroll
+            for (int i = 0; i < RBW; ++i)
+                av[i] = i < nr ? ap[((int64_t)q * RBn + i) * 64] : tvec4{0, 0, 0, 0};
+            __builtin_amdgcn_sched_barrier(0);
+            const T bv[4] = {cvalid ? (T)b01.x : (T)0, cvalid ? (T)b01.y : (T)0, cvalid ? (T)b23.x : (T)0,
+                             cvalid ? (T)b23.y : (T)0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int i = 0; i < RBW; ++i) {
+                    if constexpr (sizeof(T) == 8)
+                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[u], acc[i], 0, 0, 0);
+                    else
+                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][u], bv[u], acc[i], 0, 0, 0);
+                }
+        }
+    }
+    // far field from the leaf's local expansion (FP64 in both precisions)
+    dvec4 far[RBW];
+#pragma unroll
+    for (int i = 0; i < RBW; ++i)
+        far[i] = dvec4{0, 0, 0, 0};
+    if (g.L >= 2) {
+        const int64_t tl = cvalid ? tmap_lookup(lv, tmap, 3, lv.s0[0] + lx, lv.s0[1] + ly, lv.s0[2] + lz) : -1;
+        const bool hl = tl >= 0;
+        const double2 *bp = (const double2 *)(le + (hl ? ((lv.tgt_off + tl) * g.B + bm) * g.PS : 0) +
+                                              kr * (g.PS / 4));
+        const dvec4 *ap = (const dvec4 *)Lm + (int64_t)rb0 * 64 + lane;
+        const int QL = g.PS / 16;
+        for (int q = 0; q < QL; ++q) {
+            const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
+            dvec4 av[RBW];
+#pragma unroll
+            for (int i = 0; i < RBW; ++i)
+                av[i] = i < nr ? ap[((int64_t)q * RBn + i) * 64] : dvec4{0, 0, 0, 0};
+            __builtin_amdgcn_sched_barrier(0);
+            const double bv[4] = {hl ? b01.x : 0.0, hl ? b01.y : 0.0, hl ? b23.x : 0.0, hl ? b23.y : 0.0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int i = 0; i < RBW; ++i)
+                    far[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[u], far[i], 0, 0, 0);
+        }
     }
     if (!cvalid)
         return;
-    // lane holds target t = 4 rb + lane / 16 (the row order of A), components r = 0..3
+    // lane holds target t = 4 rb + lane / 16 (the row order of both
+    // operators), components r = 0..3 = (phi, gx, gy, gz) in lattice units
+    const double sg = g.G * g.h, sp = g.G * g.h * g.h;
 #pragma unroll
     for (int i = 0; i < RBW; ++i) {
-        const int t = 4 * (rb0 + i) + krow;
+        const int t = 4 * (rb0 + i) + kr;
         if (i >= nr || t >= b3)
             continue;
         const int ix = lx * b + t % b, iy = ly * b + (t / b) % b, iz = lz * b + t / b2;
         if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
             continue;
-        const int64_t j = cell_slot[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
-        double *o = near + (j * g.B + bm) * 4;
+        double v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            o[r] = (double)acc[i][r];
+            v[r] = (double)acc[i][r] + far[i][r];
+        const int64_t cell = ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
+        double *o = out + ((int64_t)bm * g.M + npts + cell) * g.C;
+        if (g.C == 1) {
+            o[0] = sg * v[3];
+        } else if (g.C == 3) {
+            o[0] = sg * v[1];
+            o[1] = sg * v[2];
+            o[2] = sg * v[3];
+        } else {
+            o[0] = sp * v[0];
+            o[1] = sg * v[1];
+            o[2] = sg * v[2];
+            o[3] = sg * v[3];
+        }
     }
 }
 
@@ -471,11 +559,14 @@ k_near_lat(DevGeom g, const double *blk, int KP, const T *A, int RBn, int KSn, c
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_l2p_combine(DevGeom g, const double *tpos, const int32_t *tleaf, const uint32_t *tkey,
-              const uint32_t *perm, const double *le, const double *near, double *out)
+              const uint32_t *perm, const double *le, const double *near, int64_t first_lattice,
+              double *out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.M)
         return;
+    if ((int64_t)perm[i] >= first_lattice)
+        return;  // a voxel centre written by the fused lattice kernel
     const DevLev &lv = g.lev[g.L];
     const int64_t leaf = tleaf[i];
     double u[3] = {0, 0, 0};
@@ -669,28 +760,31 @@ static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
     return GRAV_OK;
 }
 
-static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho, hipStream_t s)
+static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho, double *out, hipStream_t s)
 {
     const LevelInfo &lv = p->lev[p->L];
     const int b3 = p->b * p->b * p->b;
     const int64_t nfill = lv.n_src * p->B * b3;
     hipLaunchKernelGGL(k_rho_blocks, dim3((unsigned)((nfill + 255) / 256)), dim3(256), 0, s, g, rho,
-                       4 * p->lat_KS, p->d_rho_blk);
+                       16 * p->lat_Q, p->d_rho_blk);
     GRAV_HIP(hipGetLastError());
     const int64_t ncol = lv.n_src * p->B;
-    const int RBn = p->lat_RB, KSn = p->lat_KS;
+    const int RBn = p->lat_RB, Qn = p->lat_Q;
     const int RBW = (RBn + 3) / 4;
     dim3 grid((unsigned)((ncol + 15) / 16)), blk(256);
+    const int64_t npts = p->d.n_points;
 #define NEAR_CASE(W)                                                                            \
     case W:                                                                                     \
         if (p->d.precision == GRAV_FP64)                                                        \
             hipLaunchKernelGGL((k_near_lat<W, double>), grid, blk, 0, s, g,                      \
-                               (const double *)p->d_rho_blk, 4 * KSn, (const double *)p->d_tn64, \
-                               RBn, KSn, (const int32_t *)p->d_cell_slot, p->d_near);           \
+                               (const double *)p->d_rho_blk, (const double *)p->d_tn64, RBn, Qn, \
+                               (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,           \
+                               (const double *)p->d_le, npts, out);                             \
         else                                                                                    \
             hipLaunchKernelGGL((k_near_lat<W, float>), grid, blk, 0, s, g,                       \
-                               (const double *)p->d_rho_blk, 4 * KSn, (const float *)p->d_tn32,  \
-                               RBn, KSn, (const int32_t *)p->d_cell_slot, p->d_near);           \
+                               (const double *)p->d_rho_blk, (const float *)p->d_tn32, RBn, Qn,  \
+                               (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,           \
+                               (const double *)p->d_le, npts, out);                             \
         break;
     switch (RBW) {
         NEAR_CASE(1)
@@ -742,7 +836,7 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
     }
     if (p->lat_near) {
         stage_begin(p, "near_lat", s);
-        GRAV_CHECK(launch_near_lat(p, g, rho, s));
+        GRAV_CHECK(launch_near_lat(p, g, rho, out, s));
         stage_end(p, s);
     }
     if (!p->lat_near || p->d.n_points > 0) {
@@ -757,14 +851,15 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
                                (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, p->d_near);
         GRAV_HIP(hipGetLastError());
         stage_end(p, s);
+        stage_begin(p, "l2p", s);
+        hipLaunchKernelGGL(k_l2p_combine, dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s, g,
+                           (const double *)p->d_tpos, (const int32_t *)p->d_tleaf,
+                           (const uint32_t *)p->d_tkey, (const uint32_t *)p->d_perm,
+                           (const double *)p->d_le, (const double *)p->d_near,
+                           p->lat_near ? p->d.n_points : p->M, out);
+        GRAV_HIP(hipGetLastError());
+        stage_end(p, s);
     }
-    stage_begin(p, "l2p", s);
-    hipLaunchKernelGGL(k_l2p_combine, dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s, g,
-                       (const double *)p->d_tpos, (const int32_t *)p->d_tleaf,
-                       (const uint32_t *)p->d_tkey, (const uint32_t *)p->d_perm,
-                       (const double *)p->d_le, (const double *)p->d_near, out);
-    GRAV_HIP(hipGetLastError());
-    stage_end(p, s);
     return GRAV_OK;
 }
 

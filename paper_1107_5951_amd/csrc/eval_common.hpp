@@ -130,8 +130,8 @@ constexpr int panel_unroll()
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
 
-__device__ inline double lre(const double *L, int n, int m) { return m == 0 ? L[n * n] : L[n * n + 2 * m - 1]; }
-__device__ inline double lim(const double *L, int n, int m) { return m == 0 ? 0.0 : L[n * n + 2 * m]; }
+__host__ __device__ inline double lre(const double *L, int n, int m) { return m == 0 ? L[n * n] : L[n * n + 2 * m - 1]; }
+__host__ __device__ inline double lim(const double *L, int n, int m) { return m == 0 ? 0.0 : L[n * n + 2 * m]; }
 
 // Local expansion evaluation at u (box-width units from the box centre):
 // out[0] = sum L_j^k R_j^k(u), out[1..3] = its gradient with respect to u.
@@ -140,7 +140,7 @@ __device__ inline double lim(const double *L, int n, int m) { return m == 0 ? 0.
 // d/dz R_n^m = R_{n-1}^m, d/dx R_n^m = (R_{n-1}^{m-1} - R_{n-1}^{m+1})/2 and
 // d/dy R_n^m = i (R_{n-1}^{m-1} + R_{n-1}^{m+1})/2, each R_n^m pairs with
 // degree-(n+1) coefficients for the gradient.
-__device__ inline void l2p_eval(int P, const double *L, double x, double y, double z, double out[4])
+__host__ __device__ inline void l2p_eval(int P, const double *L, double x, double y, double z, double out[4])
 {
     double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
     const double r2 = x * x + y * y + z * z;

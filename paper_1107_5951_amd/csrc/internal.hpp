@@ -82,13 +82,14 @@ struct Plan {
     int split[TK_COUNT] = {1, 1};
     // near field of voxel-centre targets by lattice matrices (b <= 4)
     bool lat_near = false;
-    int lat_RB = 0, lat_KS = 0;                    // row blocks (4 b^3 / 16), k steps (b^3 / 4)
+    int lat_RB = 0, lat_Q = 0;                     // row blocks (4 b^3 / 16); chunks of four k steps
+    double *d_tl2p = nullptr;                      // [PS/16][RB][64][4] far field (L2P) at the cell centres, FP64
     double *d_m2m_sw = nullptr;                    // [8][KS][RB][64] M2M as MFMA A fragments (FP64)
     double *d_l2l_sw = nullptr;                    // [8][KS][RB][64] L2L likewise
     double *d_tn64 = nullptr;                      // [27][KS][RB][64] swizzled, FP64 plans
     float *d_tn32 = nullptr;                       // same, mixed plans
     int32_t *d_cell_slot = nullptr;                // [ncell] sorted slot of each voxel centre
-    double *d_rho_blk = nullptr;                   // [padded leaves][B][4 KS] densities per leaf
+    double *d_rho_blk = nullptr;                   // [padded leaves][B][16 Q] densities per leaf
     int64_t *d_leaf_pend = nullptr;                // [n_leaf] end of the user points of a leaf                  // workgroups sharing the offsets of one tile
     double *d_part = nullptr;                      // [split][expansions][PS] partial sums
     int32_t *d_class_off = nullptr;  // [8][189][4] (dx, dy, dz, offset id)

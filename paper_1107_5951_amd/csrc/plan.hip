@@ -250,7 +250,7 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk,
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p,
                     p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
@@ -505,13 +505,14 @@ grav_status build_tiles(Plan *p)
             for (int c = 0; c < 8; ++c)
                 add(TK_M2LT, l, c, class_count(p->lev[l], c) * B);
     }
-    // Split the 189 offsets of each tile over S workgroups when there are too
-    // few tiles to fill the device (about 2048 workgroups wanted); the S
-    // partial expansions are summed in a fixed order afterwards.
+    // Split the 189 offsets of each tile over S <= 16 workgroups when there
+    // are too few tiles to fill the device (about 4096 workgroups wanted, so
+    // that work also balances over the 1024 SIMDs); the S partial expansions
+    // are summed in a fixed order afterwards.
     std::vector<GemmTile> split;
     for (int k = 0; k < TK_COUNT; ++k) {
         TileRange &r = p->tiles[k][0];
-        const int S = r.n == 0 ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, ceil_div(2048, r.n)));
+        const int S = r.n == 0 ? 1 : (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(4096, r.n)));
         p->split[k] = S;
         const int64_t off = (int64_t)split.size();
         for (int64_t i = 0; i < r.n; ++i)
@@ -623,35 +624,44 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
     GRAV_HIP(hipGetLastError());
 
     const int b = p->b, b3 = b * b * b;
-    const int RBn = (int)ceil_div(4 * b3, 16), KSn = (int)ceil_div(b3, 4);
+    // rows: (target, component) pairs, 4 b^3, in RBn blocks of 16; the
+    // contraction runs over Qn chunks of four k steps, k step ks and
+    // instruction sub-row kr taking cell kr * 4 Qn + ks (cells past b^3 are
+    // zero in both operands)
+    const int RBn = (int)ceil_div(4 * b3, 16), Qn = (int)ceil_div(ceil_div(b3, 4), 4);
+    const int KP = 16 * Qn;
     p->lat_RB = RBn;
-    p->lat_KS = KSn;
+    p->lat_Q = Qn;
     const bool f64 = p->d.precision == GRAV_FP64;
     std::vector<double> dense((size_t)27 * 4 * b3 * b3);
     near_lattice(b, p->q, f64 ? 1e-20 : 1e-10, dense.data());
-    // A-operand swizzle [nb][ks][rb][lane] = A[16 rb + lane % 16][4 ks + lane / 16].
-    // Rows are ordered so that the accumulator of a lane holds the four
-    // components of one target: the FP32 instruction returns rows
-    // 4 (lane / 16) + r of each 16-row block, the FP64 one rows lane / 16 + 4 r;
-    // target t = 4 rb + lane / 16, component r.
-    std::vector<double> sw((size_t)27 * KSn * RBn * 64, 0.0);
+    // Row order: the accumulator of a lane holds the four components of one
+    // target: the FP32 instruction returns rows 4 (lane / 16) + r of each
+    // 16-row block, the FP64 one rows lane / 16 + 4 r; target t = 4 rb +
+    // lane / 16, component r.  Layout [nb][q][rb][lane][u], ks = 4 q + u.
+    auto row_target = [](int row, bool dbl, int rb, int &t, int &comp) {
+        t = 4 * rb + (dbl ? row % 4 : row / 4);
+        comp = dbl ? row / 4 : row % 4;
+    };
+    std::vector<double> sw((size_t)27 * Qn * RBn * 64 * 4, 0.0);
     for (int nb = 0; nb < 27; ++nb)
-        for (int ks = 0; ks < KSn; ++ks)
+        for (int q = 0; q < Qn; ++q)
             for (int rb = 0; rb < RBn; ++rb)
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int row = lane & 15, col = 4 * ks + (lane >> 4);
-                    const int t = 4 * rb + (f64 ? row % 4 : row / 4);
-                    const int comp = f64 ? row / 4 : row % 4;
-                    double v = 0.0;
-                    if (t < b3 && col < b3)
-                        v = dense[((size_t)nb * 4 * b3 + 4 * t + comp) * b3 + col];
-                    sw[(((size_t)nb * KSn + ks) * RBn + rb) * 64 + lane] = v;
-                }
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int u = 0; u < 4; ++u) {
+                        int t, comp;
+                        row_target(lane & 15, f64, rb, t, comp);
+                        const int cell = (lane >> 4) * 4 * Qn + 4 * q + u;
+                        double v = 0.0;
+                        if (t < b3 && cell < b3)
+                            v = dense[((size_t)nb * 4 * b3 + 4 * t + comp) * b3 + cell];
+                        sw[((((size_t)nb * Qn + q) * RBn + rb) * 64 + lane) * 4 + u] = v;
+                    }
     {
         // leaf blocks of the densities, padded by one leaf per side; the
         // padding and the rows past b^3 stay zero
         const LevelInfo &lv = p->lev[p->L];
-        const size_t n = (size_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B * 4 * KSn;
+        const size_t n = (size_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B * KP;
         GRAV_CHECK(dalloc(p, &p->d_rho_blk, n, false));
         GRAV_HIP(hipMemset(p->d_rho_blk, 0, sizeof(double) * n));
     }
@@ -660,6 +670,40 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
     } else {
         std::vector<float> sw32(sw.begin(), sw.end());
         GRAV_CHECK(upload(p, &p->d_tn32, sw32));
+    }
+    if (p->L >= 2) {
+        // Far field at the cell centres from the leaf's local expansion, with
+        // the scaling of the combine folded in (phi / w, -grad phi / w^2), as
+        // FP64 MFMA A fragments over the expansion's PS/4 k steps (same
+        // contraction order as the M2L: coefficient kr * PS/4 + ks).
+        const int PS = p->PS, QL = PS / 16;
+        std::vector<double> e(PS, 0.0), full((size_t)4 * b3 * PS, 0.0);
+        const double inv_w = 1.0 / b;
+        for (int t = 0; t < b3; ++t) {
+            const double u[3] = {((t % b) + 0.5 - 0.5 * b) * inv_w, (((t / b) % b) + 0.5 - 0.5 * b) * inv_w,
+                                 ((t / (b * b)) + 0.5 - 0.5 * b) * inv_w};
+            for (int c = 0; c < p->P2; ++c) {
+                e[c] = 1.0;
+                double o[4];
+                l2p_eval(p->P, e.data(), u[0], u[1], u[2], o);
+                e[c] = 0.0;
+                full[(size_t)(4 * t + 0) * PS + c] = o[0] * inv_w;
+                for (int a = 0; a < 3; ++a)
+                    full[(size_t)(4 * t + 1 + a) * PS + c] = -o[1 + a] * inv_w * inv_w;
+            }
+        }
+        std::vector<double> lsw((size_t)QL * RBn * 64 * 4, 0.0);
+        for (int q = 0; q < QL; ++q)
+            for (int rb = 0; rb < RBn; ++rb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int u = 0; u < 4; ++u) {
+                        int t, comp;
+                        row_target(lane & 15, true, rb, t, comp);
+                        const int c = (lane >> 4) * (PS / 4) + 4 * q + u;
+                        lsw[(((size_t)q * RBn + rb) * 64 + lane) * 4 + u] =
+                            t < b3 ? full[(size_t)(4 * t + comp) * PS + c] : 0.0;
+                    }
+        GRAV_CHECK(upload(p, &p->d_tl2p, lsw));
     }
     GRAV_HIP(hipStreamSynchronize(s));
     return GRAV_OK;
