@@ -7,6 +7,12 @@
 
 #include "resolve.hpp"
 
+// Largest per-lane A chunk (bytes) for which the M2L keeps two register
+// sets (loads of the next chunk in flight during this chunk's MFMAs).
+#ifndef GRAV_M2L_DB_BYTES
+#define GRAV_M2L_DB_BYTES 128
+#endif
+
 namespace grav {
 
 // --------------------------------------------------------------------------
@@ -205,7 +211,7 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         const T *kp = K + (int64_t)id * kstride + lane * 4 * RB;
         // two register sets (when they fit): the loads of chunk q + 1 are in
         // flight while the instructions of chunk q run
-        constexpr int NSET = 4 * RB * (int)sizeof(T) <= 128 ? 2 : 1;
+        constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
         T av[NSET][4 * RB];
         double2 bb[NSET][2];
         auto load = [&](int q, int set) {

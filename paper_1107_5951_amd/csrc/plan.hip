@@ -15,6 +15,14 @@
 #include "internal.hpp"
 #include "operators.hpp"
 
+// Splitting of the M2L offsets over workgroups (see build_tiles).
+#ifndef GRAV_M2L_SPLIT_MAX
+#define GRAV_M2L_SPLIT_MAX 16
+#endif
+#ifndef GRAV_M2L_TARGET_WG
+#define GRAV_M2L_TARGET_WG 4096
+#endif
+
 namespace grav {
 
 namespace {
@@ -512,7 +520,9 @@ grav_status build_tiles(Plan *p)
     std::vector<GemmTile> split;
     for (int k = 0; k < TK_COUNT; ++k) {
         TileRange &r = p->tiles[k][0];
-        const int S = r.n == 0 ? 1 : (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(4096, r.n)));
+        const int S = r.n == 0 ? 1
+                              : (int)std::min<int64_t>(GRAV_M2L_SPLIT_MAX,
+                                                       std::max<int64_t>(1, ceil_div(GRAV_M2L_TARGET_WG, r.n)));
         p->split[k] = S;
         const int64_t off = (int64_t)split.size();
         for (int64_t i = 0; i < r.n; ++i)
