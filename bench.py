@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum comparison")
+    ap.add_argument("--crossover", action="store_true",
+                    help="only time FMM vs GPU direct sum over station counts (summation/FMM crossover)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -87,6 +90,41 @@ def pct(xs, q):
     return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
 
 
+def crossover(args):
+    """Summation vs FMM as the number of stations grows (cf. the paper's
+    crossover discussion, Sec. 4): a fixed 64^3 mesh, 1-point rule, gz at
+    ns x ns stations at z = 1.1, mixed precision p = 8."""
+    import torch
+
+    import paper_1107_5951_amd as G
+    import workloads as W
+    n = 64
+    grid = W.Grid.unit(n)
+    rho = torch.as_tensor(W.gaussian_blobs(grid, 32, 1002), device="cuda")
+    rows = []
+    for ns in (2, 4, 8, 16, 32, 64, 128, 256):
+        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=W.stations(ns, 1.1), components=1, p=8,
+                                 leaf_size=64, precision=G.GRAV_MIXED))
+        out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
+        t = {}
+        for name, fn in (("fmm", plan.eval), ("direct", plan.direct)):
+            fn(rho, out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10 if name == "fmm" else 3
+            e0.record()
+            for _ in range(reps):
+                fn(rho, out)
+            e1.record()
+            torch.cuda.synchronize()
+            t[name] = e0.elapsed_time(e1) / reps
+        rows.append({"stations": ns * ns, "fmm_ms": t["fmm"], "direct_ms": t["direct"]})
+        print(json.dumps(rows[-1]), flush=True)
+    faster = [r["stations"] for r in rows if r["fmm_ms"] < r["direct_ms"]]
+    print(json.dumps({"crossover_stations": min(faster) if faster else None, "mesh": "64^3, q=1",
+                      "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -108,6 +146,10 @@ def main():
 
     import paper_1107_5951_amd as G
     import workloads as W
+
+    if args.crossover:
+        crossover(args)
+        return
 
     n = args.n
     grid = W.Grid.unit(n)
@@ -190,6 +232,25 @@ def main():
         del plan10
         res["fp64"] = fp64
 
+    if not args.no_direct:
+        # the summation method on the same GPU, same targets and arithmetic
+        # class (FP32 pairs for the mixed plan): one evaluation
+        plan_d, _ = make(G.GRAV_MIXED, args.p)
+        plan_d.direct(rho, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        plan_d.direct(rho, out)
+        ev1.record()
+        torch.cuda.synchronize()
+        dms = ev0.elapsed_time(ev1)
+        g_direct = out[0].cpu().numpy()
+        del plan_d
+        res["direct_sum"] = {"ms": dms, "value": M / (dms * 1e-3), "pairs_per_s": M * n_src / (dms * 1e-3),
+                             "fmm_speedup": dms / ms, "kernel": "k_direct<float> (Sec. 2.1 summation, FP32)"}
+
     if not args.no_cpu:
         import oracle
         idx = W.sample_indices(M, args.sample, seed=7)
@@ -204,6 +265,8 @@ def main():
                                          "FP64 direct sum, %.1f s" % (len(idx), M, n_src, cpu_s),
                                "pair_equiv_per_s": len(idx) * n_src / cpu_s}
         res["rel_err"] = oracle.rel_l2(g_mixed[idx], ref)
+        if "direct_sum" in res:
+            res["direct_sum"]["rel_err"] = oracle.rel_l2(g_direct[idx], ref)
         res["rel_err_bar"] = 1e-4
         if fp64 is not None:
             fp64["rel_err"] = oracle.rel_l2(g64[idx], ref)

@@ -134,6 +134,15 @@ grav_status grav_eval(grav_plan_t plan, const double *rho, double *g_out, void *
  * validates its arguments and returns GRAV_EUNSUPPORTED. */
 grav_status grav_adjoint(grav_plan_t plan, const double *resid, double *drho_out, void *stream);
 
+/* Direct summation (the summation method of Sec. 2.1, SUM-G1 / SUM-G2): the
+ * same output as grav_eval for the plan's evaluation points and quadrature
+ * rule, computed as the plain sum over every (target, quadrature point) pair
+ * with the same coincidence rule, O(M N) work, no expansions.  Arguments,
+ * layouts, asynchrony and errors as grav_eval; arithmetic in the plan's
+ * precision (FP64, or FP32 for GRAV_MIXED with the target-source offset
+ * formed in FP64).  Shares the plan's workspace lock (GRAV_EBUSY). */
+grav_status grav_direct(grav_plan_t plan, const double *rho, double *g_out, void *stream);
+
 /* Stage timings of the last evaluation or adjoint enqueued with
  * grav_set_profiling(plan, 1), in milliseconds from HIP events on the
  * evaluation stream: up to n entries of (name, ms).  Synchronizes with the
