@@ -89,6 +89,8 @@ struct Plan {
     double *d_tn64 = nullptr;                      // [27][KS][RB][64] swizzled, FP64 plans
     float *d_tn32 = nullptr;                       // same, mixed plans
     int32_t *d_cell_slot = nullptr;                // [ncell] sorted slot of each voxel centre
+    int direct_chunks = 1;                         // source chunks of grav_direct
+    double *d_dpart = nullptr;                     // [chunks][M][B][4] its partial sums
     double *d_rho_blk = nullptr;                   // [padded leaves][B][16 Q] densities per leaf
     int64_t *d_leaf_pend = nullptr;                // [n_leaf] end of the user points of a leaf                  // workgroups sharing the offsets of one tile
     double *d_part = nullptr;                      // [split][expansions][PS] partial sums

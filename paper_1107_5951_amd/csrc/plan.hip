@@ -258,7 +258,7 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p,
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart,
                     p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
@@ -1156,6 +1156,19 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             break;
         if ((st = dalloc(p, &p->d_near, (size_t)p->M * p->B * 4, false)) != GRAV_OK)
             break;
+        {
+            // grav_direct: enough source chunks for ~2048 workgroups, partial
+            // sums capped at 64 MB
+            const int64_t ncell = (int64_t)desc->nx * desc->ny * desc->nz;
+            const int64_t tiles = std::max<int64_t>(1, ceil_div(p->M, 256));
+            int64_t nch = std::min<int64_t>(std::max<int64_t>(1, ceil_div(2048, tiles)), ceil_div(ncell, 256));
+            const int64_t per = std::max<int64_t>(1, p->M * p->B * 4 * 8);
+            nch = std::max<int64_t>(1, std::min<int64_t>(nch, (64 << 20) / per));
+            p->direct_chunks = (int)std::min<int64_t>(nch, 65535);
+            if (p->direct_chunks > 1 &&
+                (st = dalloc(p, &p->d_dpart, (size_t)p->direct_chunks * p->M * p->B * 4, false)) != GRAV_OK)
+                break;
+        }
         {
             // partial expansions of split M2L stages
             size_t part = 0;
