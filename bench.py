@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum comparison")
+    ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
+                    help="only run the serving workload: COUNT Poisson requests (rate 50/s, n in [32, 192])")
     ap.add_argument("--crossover", action="store_true",
                     help="only time FMM vs GPU direct sum over station counts (summation/FMM crossover)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -88,6 +90,31 @@ def stage_profile(plan, rho, out, steps):
 def pct(xs, q):
     s = sorted(xs)
     return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
+
+
+def serving(args):
+    """Many small forward solves: a seeded Poisson trace (rate 50/s) of
+    meshes n = round(exp U[ln 32, ln 192]), q in {1, 2}, gz at n x n
+    stations, p = 8 mixed.  Plans are built first (timed separately); then
+    the trace is served back to back (capacity) and at its arrival times
+    (latency under load)."""
+    import torch
+
+    from paper_1107_5951_amd import serve
+    reqs = serve.poisson_trace(args.serve, rate=50.0, seed=1005, host_blobs=False)
+    srv = serve.GravServer(n_streams=4)
+    t0 = time.perf_counter()
+    for r in reqs:
+        srv.cache.get(r.n, r.q)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    _, cap = srv.run(reqs)
+    _, live = srv.run(reqs, realtime=True)
+    srv.close()
+    print(json.dumps({"workload": "serving: %d Poisson requests at 50/s, n in [32, 192], q in {1, 2}, "
+                                  "gz at n^2 stations, p=8 mixed, forward only" % args.serve,
+                      "plans": len(set((r.n, r.q) for r in reqs)), "plan_build_s": build_s,
+                      "capacity": cap, "realtime": live}), flush=True)
 
 
 def crossover(args):
@@ -149,6 +176,9 @@ def main():
 
     if args.crossover:
         crossover(args)
+        return
+    if args.serve:
+        serving(args)
         return
 
     n = args.n

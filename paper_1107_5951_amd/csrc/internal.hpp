@@ -89,6 +89,7 @@ struct Plan {
     double *d_tn64 = nullptr;                      // [27][KS][RB][64] swizzled, FP64 plans
     float *d_tn32 = nullptr;                       // same, mixed plans
     int32_t *d_cell_slot = nullptr;                // [ncell] sorted slot of each voxel centre
+    hipStream_t bs = nullptr;                      // plan-build stream (non-blocking), only inside grav_plan
     int direct_chunks = 1;                         // source chunks of grav_direct
     double *d_dpart = nullptr;                     // [chunks][M][B][4] its partial sums
     double *d_rho_blk = nullptr;                   // [padded leaves][B][16 Q] densities per leaf

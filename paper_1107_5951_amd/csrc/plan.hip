@@ -390,7 +390,8 @@ grav_status upload(Plan *p, T **dst, const std::vector<T> &src)
 {
     GRAV_CHECK(dalloc(p, dst, src.size(), true));
     if (!src.empty())
-        GRAV_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+        GRAV_HIP(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, p->bs));
+    GRAV_HIP(hipStreamSynchronize(p->bs));
     return GRAV_OK;
 }
 
@@ -579,13 +580,13 @@ grav_status build_adjoint_maps(Plan *p)
         p->n_tmap += (int64_t)(lv.ns[0] + 6) * (lv.ns[1] + 6) * (lv.ns[2] + 6);
     }
     GRAV_CHECK(dalloc(p, &p->d_tmap, (size_t)p->n_tmap, true));
-    GRAV_HIP(hipMemset(p->d_tmap, 0xff, sizeof(int32_t) * p->n_tmap));
+    GRAV_HIP(hipMemsetAsync(p->d_tmap, 0xff, sizeof(int32_t) * p->n_tmap, p->bs));
     for (int l = lo; l <= L; ++l) {
         const LevelInfo &lv = p->lev[l];
         const int64_t n = lv.n_tgt;
         if (n == 0)
             continue;
-        hipLaunchKernelGGL(k_fill_tmap, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, 0,
+        hipLaunchKernelGGL(k_fill_tmap, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, p->bs,
                            (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n, lv.s0[0], lv.s0[1],
                            lv.s0[2], lv.ns[0] + 6, lv.ns[1] + 6, lv.ns[2] + 6,
                            p->d_tmap + lv.tmap_off);
@@ -600,13 +601,13 @@ grav_status build_adjoint_maps(Plan *p)
         GRAV_CHECK(dalloc(p, &p->d_tchild, (size_t)p->n_tchild, true));
         for (int l = 2; l < L; ++l) {
             const int64_t nc = p->lev[l + 1].n_tgt;
-            hipLaunchKernelGGL(k_fill_tchild, dim3((unsigned)ceil_div(nc + 1, 256)), dim3(256), 0, 0,
+            hipLaunchKernelGGL(k_fill_tchild, dim3((unsigned)ceil_div(nc + 1, 256)), dim3(256), 0, p->bs,
                                (const int32_t *)(p->d_tparent + p->tbox_off[l + 1]), nc,
                                p->lev[l].n_tgt, p->d_tchild + p->lev[l].tchild_off);
             GRAV_HIP(hipGetLastError());
         }
     }
-    GRAV_HIP(hipDeviceSynchronize());
+    GRAV_HIP(hipStreamSynchronize(p->bs));
     return GRAV_OK;
 }
 
@@ -673,7 +674,8 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
         const LevelInfo &lv = p->lev[p->L];
         const size_t n = (size_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B * KP;
         GRAV_CHECK(dalloc(p, &p->d_rho_blk, n, false));
-        GRAV_HIP(hipMemset(p->d_rho_blk, 0, sizeof(double) * n));
+        GRAV_HIP(hipMemsetAsync(p->d_rho_blk, 0, sizeof(double) * n, p->bs));
+        GRAV_HIP(hipStreamSynchronize(p->bs));
     }
     if (f64) {
         GRAV_CHECK(upload(p, &p->d_tn64, sw));
@@ -725,7 +727,7 @@ grav_status count_work(Plan *p)
     GRAV_HIP(hipMalloc(&acc, 2 * sizeof(unsigned long long)));
     grav_status st = GRAV_OK;
     do {
-        if (hipMemset(acc, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        if (hipMemsetAsync(acc, 0, 2 * sizeof(unsigned long long), p->bs) != hipSuccess) {
             st = GRAV_EDEVICE;
             break;
         }
@@ -747,7 +749,7 @@ grav_status count_work(Plan *p)
                     a.s0[ax] = p->lev[l].s0[ax];
                     a.ns[ax] = p->lev[l].ns[ax];
                 }
-                hipLaunchKernelGGL(k_count_m2l, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, 0,
+                hipLaunchKernelGGL(k_count_m2l, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, p->bs,
                                    (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n, a,
                                    (const int32_t *)p->d_class_off, acc);
             }
@@ -756,13 +758,14 @@ grav_status count_work(Plan *p)
                 a.s0[ax] = p->lev[p->L].s0[ax];
                 a.ns[ax] = p->lev[p->L].ns[ax];
             }
-            hipLaunchKernelGGL(k_count_p2p, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, 0,
+            hipLaunchKernelGGL(k_count_p2p, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, p->bs,
                                (const uint32_t *)(p->d_tkey + p->tbox_off[p->L]),
                                (const int64_t *)p->d_leaf_start, p->n_leaf, a, acc + 1);
         }
         unsigned long long h[2] = {0, 0};
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpy(h, acc, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+            hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, p->bs) != hipSuccess ||
+            hipStreamSynchronize(p->bs) != hipSuccess) {
             st = GRAV_EDEVICE;
             break;
         }
@@ -1128,11 +1131,13 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             st = GRAV_EDEVICE;
             break;
         }
+        p->bs = s;
         if (desc->n_points > 0) {
             if ((st = dalloc(p, &p->d_points, 3 * desc->n_points, true)) != GRAV_OK)
                 break;
-            if (hipMemcpy(p->d_points, desc->points, sizeof(double) * 3 * desc->n_points,
-                          hipMemcpyHostToDevice) != hipSuccess) {
+            if (hipMemcpyAsync(p->d_points, desc->points, sizeof(double) * 3 * desc->n_points,
+                               hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
                 st = GRAV_EDEVICE;
                 break;
             }
@@ -1183,7 +1188,8 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             const DevGeom g = make_geom(p);
             if ((st = dalloc(p, &p->d_geom, 1, true)) != GRAV_OK)
                 break;
-            if (hipMemcpy(p->d_geom, &g, sizeof(DevGeom), hipMemcpyHostToDevice) != hipSuccess) {
+            if (hipMemcpyAsync(p->d_geom, &g, sizeof(DevGeom), hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
                 st = GRAV_EDEVICE;
                 break;
             }
@@ -1193,6 +1199,7 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             break;
         }
     } while (0);
+    p->bs = nullptr;
     if (s)
         (void)hipStreamDestroy(s);
     (void)hipSetDevice(cur);
