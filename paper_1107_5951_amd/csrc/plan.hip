@@ -1163,12 +1163,12 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             break;
         {
             // grav_direct: enough source chunks for ~2048 workgroups, partial
-            // sums capped at 64 MB
+            // sums capped at 8 MB (the plan keeps them for its lifetime)
             const int64_t ncell = (int64_t)desc->nx * desc->ny * desc->nz;
             const int64_t tiles = std::max<int64_t>(1, ceil_div(p->M, 256));
             int64_t nch = std::min<int64_t>(std::max<int64_t>(1, ceil_div(2048, tiles)), ceil_div(ncell, 256));
             const int64_t per = std::max<int64_t>(1, p->M * p->B * 4 * 8);
-            nch = std::max<int64_t>(1, std::min<int64_t>(nch, (64 << 20) / per));
+            nch = std::max<int64_t>(1, std::min<int64_t>(nch, (8 << 20) / per));
             p->direct_chunks = (int)std::min<int64_t>(nch, 65535);
             if (p->direct_chunks > 1 &&
                 (st = dalloc(p, &p->d_dpart, (size_t)p->direct_chunks * p->M * p->B * 4, false)) != GRAV_OK)
