@@ -87,6 +87,30 @@ def stage_profile(plan, rho, out, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None if it is for another kernel or the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "m2l_volume64_q2_hbm_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, "paper_1107_5951_amd", "csrc", f), "rb").read()
+                   for f in ("eval.hip", "eval_common.hpp"))
+    if fields.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    if not kernel_name.startswith(fields.get("kernel", "?")):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def pct(xs, q):
     s = sorted(xs)
     return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
@@ -220,7 +244,7 @@ def main():
     roof = {"kernel": kname, "bound": bound, "achieved": fl / (stages[dom] * 1e-3) / 1e12,
             "peak": PEAK[pk], "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(kname)
     roof["kernel_ms"] = stages.get(dom)
 
     res = {
