@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum comparison")
     ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
                     help="only run the serving workload: COUNT Poisson requests (rate 50/s, n in [32, 192])")
+    ap.add_argument("--paper-sequence", action="store_true",
+                    help="only time the FMM on the paper's model over its mesh sequence (Mbar = 12 .. 384)")
     ap.add_argument("--crossover", action="store_true",
                     help="only time FMM vs GPU direct sum over station counts (summation/FMM crossover)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -114,6 +116,44 @@ def measured_traffic(kernel_name):
 def pct(xs, q):
     s = sorted(xs)
     return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
+
+
+def paper_sequence(args):
+    """The paper's model (Sec. 3) on Mbar^3 meshes, 1-point rule, gz at every
+    cell centroid, p = 8, 27 cells per leaf (the setting of its FMM timing
+    table), FP64 and mixed precision: plan time and evaluation time."""
+    import torch
+
+    import paper_1107_5951_amd as G
+    import workloads as W
+    rows = []
+    for nbar in (12, 24, 48, 96, 192, 384):
+        grid, rho_h = W.paper_model(nbar)
+        rho = torch.as_tensor(rho_h, device="cuda")
+        del rho_h
+        row = {"Mbar": nbar, "cells": nbar ** 3}
+        for prec, tag in ((G.GRAV_FP64, "fp64"), (G.GRAV_MIXED, "mixed")):
+            t0 = time.perf_counter()
+            plan = G.Plan(G.PlanSpec(n=(nbar, nbar, nbar), h=grid.h, origin=grid.origin, quad_order=1,
+                                     voxel_centres=True, components=1, p=8, leaf_size=27, precision=prec,
+                                     G=W.G_SI))
+            plan_s = time.perf_counter() - t0
+            out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
+            plan.eval(rho, out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                plan.eval(rho, out)
+            e1.record()
+            torch.cuda.synchronize()
+            row[tag] = {"plan_s": plan_s, "eval_ms": e0.elapsed_time(e1) / 5, "levels": plan.levels}
+            del plan, out
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        del rho
+        torch.cuda.empty_cache()
+    print(json.dumps({"paper_sequence": rows}), flush=True)
 
 
 def serving(args):
@@ -203,6 +243,9 @@ def main():
         return
     if args.serve:
         serving(args)
+        return
+    if args.paper_sequence:
+        paper_sequence(args)
         return
 
     n = args.n
