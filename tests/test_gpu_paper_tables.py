@@ -7,12 +7,12 @@ Eqs. (15)-(17) against the closed-form prism with a one-point rule per cell.
 
 * Table 1: with the 1- and 2-point rules and an FMM accurate to rounding
   (FP64, p = 16) the rates are the summation rates of Table 1.
-* Table 3: the FMM's rates rise towards those rates as p grows; the
-  highest order printed (p = 20) equals the 1-point summation rates, and so
-  do ours at p = 16.  The lower orders depend on the expansion basis and
-  on the meaning of p (Sec. 2.3 leaves both open: our p is the number of
-  degrees), so only the trend is compared there (parity unpinned for the
-  individual low-p values).
+* Table 3: the FMM's rates rise towards those rates as p grows.  Ours at
+  p = 8 equal the printed p = 8 column (1.45, 1.51, 0.99) and ours at p = 16
+  the printed p = 20 column (the 1-point summation rates).  The lowest
+  orders (p = 1, 4) depend on the expansion basis and on the meaning of p
+  (Sec. 2.3 leaves both open: our p is the number of degrees), so there only
+  the trend is compared (parity unpinned for those two columns).
 """
 import json
 import os
@@ -66,8 +66,10 @@ def test_fmm_rates_rise_with_p_towards_table3():
     for p in (1, 4, 8, 16):
         _say("p=%2d rates %s" % (p, {k: round(v, 2) for k, v in got[p].items()}))
     _say("Table 3 (p = 1, 4, 8, 20): E1 %s  E2 %s  Einf %s" % (t3["E1"], t3["E2"], t3["Einf"]))
-    # the highest order reaches the printed p = 20 column
+    # p = 8 reproduces the printed p = 8 column; the highest order reaches
+    # the printed p = 20 column
     for k in ("E1", "E2", "Einf"):
+        assert round(got[8][k], 2) == pytest.approx(t3[k][2], abs=1e-9), k
         assert round(got[16][k], 2) == pytest.approx(t3[k][-1], abs=1e-9), k
     # and the E1 rate does not fall as p grows
     e1 = [got[p]["E1"] for p in (1, 4, 8, 16)]
