@@ -61,16 +61,18 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const
 // each and their partial fragments are added through LDS.  Children outside
 // the source block contribute nothing.
 // --------------------------------------------------------------------------
+template <int RB>
 __global__ void __launch_bounds__(256)
 k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     __shared__ double red[4][256];
+    constexpr int PS = 16 * RB;
+    constexpr int U = RB < 8 ? RB : 8;  // chunks of four k steps loaded together
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const DevLev &lp = g.lev[l];
     const DevLev &lc = g.lev[l + 1];
-    const int RB = g.PS / 16;
     const int64_t cg = blockIdx.x / RB;
     const int rb = (int)(blockIdx.x % RB);
     const int64_t nbox = (int64_t)lp.ns[0] * lp.ns[1] * lp.ns[2];
@@ -81,27 +83,48 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     const int px = lp.s0[0] + (int)(box % lp.ns[0]);
     const int py = lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1]);
     const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
-    const int krow = lane >> 4;
-    vec4 acc[1] = {vec4{0, 0, 0, 0}};
+    const int kr = lane >> 4;
+    vec4 acc = vec4{0, 0, 0, 0};
     // wave w takes children 2w and 2w + 1
     for (int c = 2 * wave; c < 2 * wave + 2; ++c) {
         const int64_t ci = cvalid ? dense_index(lc, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1),
                                                 2 * pz + ((c >> 2) & 1))
                                   : -1;
-        const double *mp = me + (ci >= 0 ? ((lc.me_off + ci) * g.B + bm) * g.PS : 0);
-        mfma_panel<1, panel_unroll<1, double>(), double>(acc, A + (int64_t)c * g.KS * RB * 64 + lane, RB, rb, 1,
-                                                         mp, ci >= 0, g.KS, krow);
+        const bool have = ci >= 0;
+        const double2 *bp = (const double2 *)(me + (have ? ((lc.me_off + ci) * g.B + bm) * PS : 0) + kr * (PS / 4));
+        const vec4 *ap = (const vec4 *)A + ((int64_t)c * RB * RB + rb) * 64 + lane;  // [c][q][rb][lane]
+        for (int q0 = 0; q0 < RB; q0 += U) {
+            vec4 av[U];
+            double2 bb[U][2];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = min(q0 + u, RB - 1);
+                av[u] = ap[(int64_t)q * RB * 64];
+                bb[u][0] = bp[2 * q];
+                bb[u][1] = bp[2 * q + 1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = have && q0 + u < RB;
+                const double bv[4] = {in ? bb[u][0].x : 0.0, in ? bb[u][0].y : 0.0, in ? bb[u][1].x : 0.0,
+                                      in ? bb[u][1].y : 0.0};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][k], bv[k], acc, 0, 0, 0);
+            }
+        }
     }
     // the four waves' fragments share one lane layout: add them in wave order
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        red[wave][lane * 4 + r] = acc[0][r];
+        red[wave][lane * 4 + r] = acc[r];
     __syncthreads();
     if (wave == 0 && cvalid) {
-        double *dst = me + ((lp.me_off + box) * g.B + bm) * g.PS;
+        double *dst = me + ((lp.me_off + box) * g.B + bm) * PS;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            dst[16 * rb + krow + 4 * r] =
+            dst[16 * rb + kr + 4 * r] =
                 ((red[0][lane * 4 + r] + red[1][lane * 4 + r]) + red[2][lane * 4 + r]) + red[3][lane * 4 + r];
     }
 }
@@ -117,6 +140,7 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
            const int32_t *tparent, const double *A, double *le)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
     const GemmTile tile = tiles[(int64_t)blockIdx.x * stride];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -135,18 +159,32 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
         acc[rb] = vec4{0, 0, 0, 0};
-    const int krow = lane >> 4;
-    const double *mp = le + (cvalid ? ((lp.tgt_off + par) * g.B + bm) * g.PS : 0);
-    mfma_panel<RB, panel_unroll<RB, double>(), double>(acc, A + (int64_t)tile.cls * g.KS * RB * 64 + lane, RB,
-                                                       0, RB, mp, cvalid, g.KS, krow);
+    const int kr = lane >> 4;
+    const double2 *bp = (const double2 *)(le + (cvalid ? ((lp.tgt_off + par) * g.B + bm) * PS : 0) + kr * (PS / 4));
+    const double *ap = A + (int64_t)tile.cls * PS * PS + lane * 4 * RB;  // [c][q][lane][u][rb]
+    for (int q = 0; q < RB; ++q) {
+        const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
+        double av[4 * RB];
+#pragma unroll
+        for (int e = 0; e < 4 * RB; ++e)
+            av[e] = ap[(int64_t)q * 64 * 4 * RB + e];
+        __builtin_amdgcn_sched_barrier(0);
+        const double bv[4] = {cvalid ? b01.x : 0.0, cvalid ? b01.y : 0.0, cvalid ? b23.x : 0.0,
+                              cvalid ? b23.y : 0.0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u * RB + rb], bv[u], acc[rb], 0, 0, 0);
+    }
     if (!cvalid)
         return;
-    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * g.PS;
+    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            dst[16 * rb + krow + 4 * r] += acc[rb][r];
+            dst[16 * rb + kr + 4 * r] += acc[rb][r];
 }
 
 // --------------------------------------------------------------------------
@@ -723,9 +761,29 @@ static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T 
 
 static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
 {
-    const int64_t ncg = (p->lev[l].n_src * p->B + 15) / 16;
-    hipLaunchKernelGGL(k_m2m_mfma, dim3((unsigned)(ncg * (p->PS / 16))), dim3(256), 0, s, g, l,
-                       (const double *)p->d_m2m_sw, p->d_me);
+    const int RB = p->PS / 16;
+    const dim3 grid((unsigned)((p->lev[l].n_src * p->B + 15) / 16 * RB)), blk(256);
+#define M2M_CASE(R)                                                                             \
+    case R:                                                                                     \
+        hipLaunchKernelGGL((k_m2m_mfma<R>), grid, blk, 0, s, g, l, (const double *)p->d_m2m_sw, p->d_me); \
+        break;
+    switch (RB) {
+        M2M_CASE(1)
+        M2M_CASE(2)
+        M2M_CASE(3)
+        M2M_CASE(4)
+        M2M_CASE(6)
+        M2M_CASE(7)
+        M2M_CASE(8)
+        M2M_CASE(9)
+        M2M_CASE(11)
+        M2M_CASE(13)
+        M2M_CASE(15)
+        M2M_CASE(16)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef M2M_CASE
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }

@@ -385,6 +385,20 @@ void swizzle_panel(const double *m, int PS, double *dst)
                 }
 }
 
+// Row-blocked variant: dst[q][rb][lane][u] = m[16 rb + lane % 16][(lane / 16) * PS/4 + 4 q + u].
+void swizzle_rows(const double *m, int PS, double *dst)
+{
+    const int RB = PS / 16, KP = PS / 4;
+    for (int q = 0; q < RB; ++q)
+        for (int rb = 0; rb < RB; ++rb)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int u = 0; u < 4; ++u) {
+                    const int row = 16 * rb + (lane & 15);
+                    const int col = (lane >> 4) * KP + 4 * q + u;
+                    dst[(((size_t)q * RB + rb) * 64 + lane) * 4 + u] = m[(size_t)row * PS + col];
+                }
+}
+
 template <class T>
 grav_status upload(Plan *p, T **dst, const std::vector<T> &src)
 {
@@ -423,16 +437,19 @@ grav_status build_operators(Plan *p)
     GRAV_CHECK(upload(p, &p->d_m2m, m2m));
     GRAV_CHECK(upload(p, &p->d_l2l, l2l));
     {
-        // the same matrices as MFMA A operands (rows = output coefficient)
-        const size_t per8 = (size_t)KS * RB * 64;
+        // the same matrices as MFMA A operands (rows = output coefficient),
+        // contraction order kr * PS/4 + ks as in the M2L: M2M with row blocks
+        // outermost per four k steps (a workgroup takes one row block), L2L
+        // with all row blocks contiguous per lane (a wave takes all rows)
+        const size_t per8 = (size_t)PS * PS;
         std::vector<double> msw(8 * per8), lsw(8 * per8);
         for (int c = 0; c < 8; ++c) {
             const double delta[3] = {((c & 1) - 0.5) * 0.5, (((c >> 1) & 1) - 0.5) * 0.5,
                                      (((c >> 2) & 1) - 0.5) * 0.5};
             m2m_matrix(P, delta, PS, m.data());
-            swizzle(m.data(), PS, KS, false, msw.data() + per8 * c);
+            swizzle_rows(m.data(), PS, msw.data() + per8 * c);
             l2l_matrix(P, delta, PS, m.data());
-            swizzle(m.data(), PS, KS, false, lsw.data() + per8 * c);
+            swizzle_panel(m.data(), PS, lsw.data() + per8 * c);
         }
         GRAV_CHECK(upload(p, &p->d_m2m_sw, msw));
         GRAV_CHECK(upload(p, &p->d_l2l_sw, lsw));
