@@ -40,7 +40,9 @@ def test_config4_batched_forward(prec):
     assert e < 5e-4  # p = 8 with the stations three leaves above the mesh
     single = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=st, components=1, p=8, leaf_size=64,
                                precision=prec))
+    # same sums, grouped differently (the M2L offset split depends on the
+    # number of columns): rounding-level agreement, FP32 level when mixed
     for b in (0, 17, 31):
         g1 = single.eval(r[b])[:, 0].cpu().numpy()
-        np.testing.assert_allclose(gz[b], g1, rtol=1e-12 if prec == 0 else 1e-6,
-                                   atol=1e-12 * np.abs(g1).max())
+        d = oracle.rel_l2(gz[b], g1)
+        assert d < (1e-12 if prec == 0 else 1e-5), (b, d)
