@@ -105,7 +105,7 @@ def measured_traffic(kernel_name):
             k, v = line.strip().split(":", 1)
             fields[k.strip()] = v.strip()
     src = b"".join(open(os.path.join(ROOT, "paper_1107_5951_amd", "csrc", f), "rb").read()
-                   for f in ("eval.hip", "eval_common.hpp"))
+                   for f in ("m2l.hip", "eval_common.hpp"))
     if fields.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
         return None
     if not kernel_name.startswith(fields.get("kernel", "?")):

@@ -7,12 +7,6 @@
 
 #include "resolve.hpp"
 
-// Largest per-lane A chunk (bytes) for which the M2L keeps two register
-// sets (loads of the next chunk in flight during this chunk's MFMAs).
-#ifndef GRAV_M2L_DB_BYTES
-#define GRAV_M2L_DB_BYTES 128
-#endif
-
 namespace grav {
 
 // --------------------------------------------------------------------------
@@ -187,122 +181,13 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
             dst[16 * rb + kr + 4 * r] += acc[rb][r];
 }
 
-// --------------------------------------------------------------------------
-// M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
-// child-parity class, model) of one split of the class's 189 interaction-
-// list offsets d; wave w owns columns 16w..16w+15 and all row blocks.  For
-// each d the wave accumulates LE[:, col] += K_d * ME[box(col) + d] with
-// 16x16x4 MFMA tiles, accumulating in registers across the offsets (no
-// atomics).
-//
-// Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
-// instruction take coefficient c = kr * PS/4 + ks (ks = 0 .. PS/4 - 1), so
-// a lane's B values for four consecutive k steps are four consecutive
-// coefficients of one expansion (one aligned 32-byte load), and the A
-// fragments of four k steps are stored contiguously per lane
-// ([d][q][lane][u][rb], ks = 4q + u): RB aligned vector loads.  Padding
-// coefficients (c >= p^2) are zero in the expansions.
-// --------------------------------------------------------------------------
-template <int RB, typename T>
-__global__ void __launch_bounds__(256)
-k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
-      const int32_t *class_off, const T *K, const double *me, double *le, int S, int64_t part_stride)
+// FP32 copy of the multipole expansions for the mixed-precision M2L (its
+// MFMA operands are FP32 anyway; the copy halves the bytes it gathers).
+__global__ void __launch_bounds__(256) k_to_float(const double *src, int64_t n, float *dst)
 {
-    using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
-    const GemmTile tile = tiles[blockIdx.x];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const DevLev &lv = g.lev[tile.level];
-    const int cl = wave * 16 + (lane & 15);
-    const bool cvalid = cl < tile.ncol;
-    const int64_t col = tile.col0 + cl;
-    const int bm = (int)(col % g.B);
-    int64_t box = 0;
-    int bx = 0, by = 0, bz = 0;
-    if (cvalid) {
-        box = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
-        const uint32_t key = tkey[lv.tbox_off + box];
-        bx = (int)compact3(key);
-        by = (int)compact3(key >> 1);
-        bz = (int)compact3(key >> 2);
-    }
-    vec4 acc[RB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-        acc[rb] = vec4{0, 0, 0, 0};
-    const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
-    const int kr = lane >> 4;
-    constexpr int PS = 16 * RB;
-    constexpr int64_t kstride = (int64_t)RB * 64 * 4 * RB;  // elements per offset matrix
-    // offsets [o0, o1) of this split (tile.pad of S)
-    const int o0 = tile.pad * kClassOffsets / S, o1 = (tile.pad + 1) * kClassOffsets / S;
-    for (int o = o0; o < o1; ++o) {
-        const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
-        const int id = offs[4 * o + 3];
-        const int sx = bx + dx - lv.s0[0], sy = by + dy - lv.s0[1], sz = bz + dz - lv.s0[2];
-        const bool have = cvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] &&
-                          sy < lv.ns[1] && sz < lv.ns[2];
-        if (__ballot(have) == 0ull)
-            continue;  // no column of this wave sees a source box at this offset
-        const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
-        const double2 *mp = (const double2 *)(me + (have ? (si * g.B + bm) * PS : 0) + kr * (PS / 4));
-        const T *kp = K + (int64_t)id * kstride + lane * 4 * RB;
-        // two register sets (when they fit): the loads of chunk q + 1 are in
-        // flight while the instructions of chunk q run
-        constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
-        T av[NSET][4 * RB];
-        double2 bb[NSET][2];
-        auto load = [&](int q, int set) {
-            bb[set][0] = mp[2 * q];
-            bb[set][1] = mp[2 * q + 1];
-#pragma unroll
-            for (int e = 0; e < 4 * RB; ++e)
-                av[set][e] = kp[(int64_t)q * 64 * 4 * RB + e];
-        };
-        auto compute = [&](int set) {
-            const T bv[4] = {have ? (T)bb[set][0].x : (T)0, have ? (T)bb[set][0].y : (T)0,
-                             have ? (T)bb[set][1].x : (T)0, have ? (T)bb[set][1].y : (T)0};
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    if constexpr (sizeof(T) == 8)
-                        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[u], acc[rb], 0, 0, 0);
-                    else
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[u], acc[rb], 0, 0, 0);
-                }
-        };
-        if constexpr (NSET == 2) {
-            load(0, 0);
-#pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                if (q + 1 < RB)
-                    load(q + 1, (q + 1) & 1);
-                __builtin_amdgcn_sched_barrier(0);
-                compute(q & 1);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        } else {
-            for (int q = 0; q < RB; ++q) {
-                load(q, 0);
-                __builtin_amdgcn_sched_barrier(0);
-                compute(0);
-            }
-        }
-    }
-    if (!cvalid)
-        return;
-    // Output fragment: lane holds column lane % 16 and four rows; the FP32
-    // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
-    // Split partials go to their own slab of the workspace.
-    double *dst = le + (tile.pad * part_stride + (lv.tgt_off + box) * g.B + bm) * PS;
-    constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
-    const int rbase = sizeof(T) == 8 ? kr : 4 * kr;
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            dst[16 * rb + rbase + rstride * r] = (double)acc[rb][r];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = (float)src[i];
 }
 
 // out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ...
@@ -721,44 +606,6 @@ void stage_end(Plan *p, hipStream_t s)
     ++p->n_stage_used;
 }
 
-template <typename T>
-static grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
-{
-    const TileRange &r = p->tiles[TK_M2L][0];
-    if (r.n == 0)
-        return GRAV_OK;
-    dim3 grid(r.n), blk(256);
-    const int S = p->split[TK_M2L];
-    const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
-    double *dst = S > 1 ? p->d_part : p->d_le;
-#define M2L_CASE(R)                                                                             \
-    case R:                                                                                     \
-        hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
-                           (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
-                           (const int32_t *)p->d_class_off, K, (const double *)p->d_me, dst,    \
-                           S, pstride);                                                         \
-        break;
-    switch (p->PS / 16) {
-        M2L_CASE(1)
-        M2L_CASE(2)
-        M2L_CASE(3)
-        M2L_CASE(4)
-        M2L_CASE(6)
-        M2L_CASE(7)
-        M2L_CASE(8)
-        M2L_CASE(9)
-        M2L_CASE(11)
-        M2L_CASE(13)
-        M2L_CASE(15)
-        M2L_CASE(16)
-    default:
-        return GRAV_EUNSUPPORTED;
-    }
-#undef M2L_CASE
-    GRAV_HIP(hipGetLastError());
-    return GRAV_OK;
-}
-
 static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
 {
     const int RB = p->PS / 16;
@@ -879,6 +726,12 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         for (int l = L - 1; l >= 2; --l)
             GRAV_CHECK(launch_m2m(p, g, l, s));
         stage_end(p, s);
+        if (p->d.precision != GRAV_FP64) {
+            const int64_t n = p->n_me * p->B * p->PS;
+            hipLaunchKernelGGL(k_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                               (const double *)p->d_me, n, p->d_me32);
+            GRAV_HIP(hipGetLastError());
+        }
         stage_begin(p, "m2l", s);
         if (p->d.precision == GRAV_FP64)
             GRAV_CHECK(launch_m2l<double>(p, g, s, p->d_k64));

@@ -27,6 +27,8 @@ struct DevGeom {
 
 DevGeom make_geom(const Plan *p);
 __global__ void k_sum_parts(const double *part, int S, int64_t n, double *out);
+template <typename T>
+grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K);
 grav_status begin_call(Plan *p, hipStream_t s);
 grav_status end_call(Plan *p, hipStream_t s);
 
@@ -36,6 +38,25 @@ grav_status end_call(Plan *p, hipStream_t s);
 template <typename T> __device__ constexpr T coincident2();
 template <> __device__ constexpr double coincident2<double>() { return 1e-20; }
 template <> __device__ constexpr float coincident2<float>() { return 1e-10f; }
+
+// Four consecutive values from a 16-byte (float) or 32-byte (double)
+// aligned address, as vector loads.
+__device__ inline void load4(const float *p, float v[4])
+{
+    const float4 x = *(const float4 *)p;
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+}
+__device__ inline void load4(const double *p, double v[4])
+{
+    const double2 a = ((const double2 *)p)[0], b = ((const double2 *)p)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
 
 // ---------------------------------------------------------------------------
 // One 16-column MFMA panel: acc[i] += A[rb0 + i] * B over k = 0 .. 4 KS - 1,

@@ -92,6 +92,7 @@ struct Plan {
     hipStream_t bs = nullptr;                      // plan-build stream (non-blocking), only inside grav_plan
     int direct_chunks = 1;                         // source chunks of grav_direct
     double *d_dpart = nullptr;                     // [chunks][M][B][4] its partial sums
+    float *d_me32 = nullptr;                       // FP32 copy of the ME for the mixed M2L
     double *d_rho_blk = nullptr;                   // [padded leaves][B][16 Q] densities per leaf
     int64_t *d_leaf_pend = nullptr;                // [n_leaf] end of the user points of a leaf                  // workgroups sharing the offsets of one tile
     double *d_part = nullptr;                      // [split][expansions][PS] partial sums

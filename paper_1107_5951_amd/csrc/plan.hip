@@ -258,7 +258,7 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart,
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_me32,
                     p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
@@ -1175,6 +1175,9 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
         if ((st = dalloc(p, &p->d_me, (size_t)p->n_me * p->B * p->PS, false)) != GRAV_OK)
             break;
         if ((st = dalloc(p, &p->d_le, (size_t)p->n_tbox * p->B * p->PS, false)) != GRAV_OK)
+            break;
+        if (p->d.precision != GRAV_FP64 &&
+            (st = dalloc(p, &p->d_me32, (size_t)p->n_me * p->B * p->PS, false)) != GRAV_OK)
             break;
         if ((st = dalloc(p, &p->d_near, (size_t)p->M * p->B * 4, false)) != GRAV_OK)
             break;
