@@ -468,7 +468,7 @@ static grav_status launch_m2lT(Plan *p, const DevGeom &g, hipStream_t s, const T
     GRAV_HIP(hipGetLastError());
     if (S > 1) {
         const int64_t n = pstride * p->PS;
-        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_sum_parts<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                            (const double *)p->d_part, S, n, p->d_me);
         GRAV_HIP(hipGetLastError());
     }

@@ -190,17 +190,20 @@ __global__ void __launch_bounds__(256) k_to_float(const double *src, int64_t n, 
         dst[i] = (float)src[i];
 }
 
-// out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ...
-__global__ void __launch_bounds__(256) k_sum_parts(const double *part, int S, int64_t n, double *out)
+// out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ..., in FP64
+template <typename T>
+__global__ void __launch_bounds__(256) k_sum_parts(const T *part, int S, int64_t n, double *out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    double acc = part[i];
+    double acc = (double)part[i];
     for (int s = 1; s < S; ++s)
-        acc += part[(int64_t)s * n + i];
+        acc += (double)part[(int64_t)s * n + i];
     out[i] = acc;
 }
+template __global__ void k_sum_parts<double>(const double *, int, int64_t, double *);
+template __global__ void k_sum_parts<float>(const float *, int, int64_t, double *);
 
 // --------------------------------------------------------------------------
 // Near field (P2P): direct sum over the quadrature points of the cells of the
@@ -369,20 +372,21 @@ k_rho_blocks(DevGeom g, const double *rho, int KP, double *blk)
 template <int RBW, typename T>
 __global__ void __launch_bounds__(256)
 k_near_lat(DevGeom g, const double *blk, const T *A, int RBn, int Qn, const double *Lm,
-           const int32_t *tmap, const double *le, int64_t npts, double *out)
+           const int32_t *tmap, const double *le, int64_t npts, int wgrows, double *out)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     using dvec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     using tvec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int rb0 = wave * RBW;
+    const int64_t cg = blockIdx.x / wgrows;
+    const int rb0 = ((int)(blockIdx.x % wgrows) * 4 + wave) * RBW;
     const int nr = min(RBW, RBn - rb0);
     if (nr <= 0)
         return;  // whole wave: no row block left
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
-    const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const int64_t col = cg * 16 + (lane & 15);
     const bool cvalid = col < nleaf * g.B;
     const int64_t leaf = cvalid ? col / g.B : 0;
     const int bm = cvalid ? (int)(col % g.B) : 0;
@@ -396,29 +400,48 @@ k_near_lat(DevGeom g, const double *blk, const T *A, int RBn, int Qn, const doub
 #pragma unroll
     for (int i = 0; i < RBW; ++i)
         acc[i] = vec4{0, 0, 0, 0};
-    for (int nb = 0; nb < 27; ++nb) {
+    // chunk i = (neighbour nb, four k steps q); operands of chunk i + 1 are
+    // loaded while chunk i's instructions run
+    const int NI = 27 * Qn;
+    auto loadc = [&](int i, double2 (&bb)[2], tvec4 (&aa)[RBW]) {
+        const int nb = i / Qn, q = i % Qn;
         const int64_t pl = ((int64_t)(lz + nb / 9) * py + (ly + (nb / 3) % 3)) * px + (lx + nb % 3);
         const double2 *bp = (const double2 *)(blk + (pl * g.B + bm) * KP + kr * (KP / 4));
-        const tvec4 *ap = (const tvec4 *)A + ((int64_t)nb * Qn * RBn + rb0) * 64 + lane;
-        for (int q = 0; q < Qn; ++q) {
-            const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
-            tvec4 av[RBW];
+        bb[0] = bp[2 * q];
+        bb[1] = bp[2 * q + 1];
+        const tvec4 *ap = (const tvec4 *)A + (((int64_t)nb * Qn + q) * RBn + rb0) * 64 + lane;
 #pragma unroll
-            for (int i = 0; i < RBW; ++i)
-                av[i] = i < nr ? ap[((int64_t)q * RBn + i) * 64] : tvec4{0, 0, 0, 0};
-            __builtin_amdgcn_sched_barrier(0);
-            const T bv[4] = {cvalid ? (T)b01.x : (T)0, cvalid ? (T)b01.y : (T)0, cvalid ? (T)b23.x : (T)0,
-                             cvalid ? (T)b23.y : (T)0};
+        for (int k = 0; k < RBW; ++k)
+            aa[k] = k < nr ? ap[(int64_t)k * 64] : tvec4{0, 0, 0, 0};
+    };
+    auto compute = [&](const double2 (&bb)[2], const tvec4 (&aa)[RBW]) {
+        const T bv[4] = {cvalid ? (T)bb[0].x : (T)0, cvalid ? (T)bb[0].y : (T)0, cvalid ? (T)bb[1].x : (T)0,
+                         cvalid ? (T)bb[1].y : (T)0};
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int i = 0; i < RBW; ++i) {
-                    if constexpr (sizeof(T) == 8)
-                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[u], acc[i], 0, 0, 0);
-                    else
-                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][u], bv[u], acc[i], 0, 0, 0);
-                }
-        }
+            for (int k = 0; k < RBW; ++k) {
+                if constexpr (sizeof(T) == 8)
+                    acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[k][u], bv[u], acc[k], 0, 0, 0);
+                else
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[k][u], bv[u], acc[k], 0, 0, 0);
+            }
+    };
+    double2 bA[2], bB[2];
+    tvec4 aA[RBW], aB[RBW];
+    loadc(0, bA, aA);
+    for (int i = 0; i < NI; i += 2) {
+        if (i + 1 < NI)
+            loadc(i + 1, bB, aB);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(bA, aA);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 2 < NI)
+            loadc(i + 2, bA, aA);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 1 < NI)
+            compute(bB, aB);
+        __builtin_amdgcn_sched_barrier(0);
     }
     // far field from the leaf's local expansion (FP64 in both precisions)
     dvec4 far[RBW];
@@ -681,8 +704,10 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
     GRAV_HIP(hipGetLastError());
     const int64_t ncol = lv.n_src * p->B;
     const int RBn = p->lat_RB, Qn = p->lat_Q;
-    const int RBW = (RBn + 3) / 4;
-    dim3 grid((unsigned)((ncol + 15) / 16)), blk(256);
+    // one row block per wave, four per workgroup: 16 columns x 4 row blocks
+    constexpr int RBW = 1;
+    const int wgrows = (RBn + 3) / 4;
+    dim3 grid((unsigned)((ncol + 15) / 16 * wgrows)), blk(256);
     const int64_t npts = p->d.n_points;
 #define NEAR_CASE(W)                                                                            \
     case W:                                                                                     \
@@ -690,17 +715,15 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
             hipLaunchKernelGGL((k_near_lat<W, double>), grid, blk, 0, s, g,                      \
                                (const double *)p->d_rho_blk, (const double *)p->d_tn64, RBn, Qn, \
                                (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,           \
-                               (const double *)p->d_le, npts, out);                             \
+                               (const double *)p->d_le, npts, wgrows, out);                     \
         else                                                                                    \
             hipLaunchKernelGGL((k_near_lat<W, float>), grid, blk, 0, s, g,                       \
                                (const double *)p->d_rho_blk, (const float *)p->d_tn32, RBn, Qn,  \
                                (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,           \
-                               (const double *)p->d_le, npts, out);                             \
+                               (const double *)p->d_le, npts, wgrows, out);                     \
         break;
     switch (RBW) {
         NEAR_CASE(1)
-        NEAR_CASE(2)
-        NEAR_CASE(4)
     default:
         return GRAV_EUNSUPPORTED;
     }
@@ -741,8 +764,12 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         if (p->split[TK_M2L] > 1) {
             stage_begin(p, "m2l_sum", s);
             const int64_t n = p->n_tbox * p->B * p->PS;
-            hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                               (const double *)p->d_part, p->split[TK_M2L], n, p->d_le);
+            if (p->d.precision == GRAV_FP64)
+                hipLaunchKernelGGL(k_sum_parts<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                                   (const double *)p->d_part, p->split[TK_M2L], n, p->d_le);
+            else
+                hipLaunchKernelGGL(k_sum_parts<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                                   (const float *)p->d_part, p->split[TK_M2L], n, p->d_le);
             GRAV_HIP(hipGetLastError());
             stage_end(p, s);
         }

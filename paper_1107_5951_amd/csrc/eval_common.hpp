@@ -26,7 +26,8 @@ struct DevGeom {
 };
 
 DevGeom make_geom(const Plan *p);
-__global__ void k_sum_parts(const double *part, int S, int64_t n, double *out);
+template <typename T>
+__global__ void k_sum_parts(const T *part, int S, int64_t n, double *out);
 template <typename T>
 grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K);
 grav_status begin_call(Plan *p, hipStream_t s);

@@ -29,7 +29,7 @@ namespace grav {
 template <int RB, typename T>
 __global__ void __launch_bounds__(256)
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
-      const int32_t *class_off, const T *K, const T *me, double *le, int S, int64_t part_stride)
+      const int32_t *class_off, const T *K, const T *me, double *le, T *part, int S, int64_t part_stride)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     const GemmTile tile = tiles[blockIdx.x];
@@ -117,9 +117,19 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
     // Output fragment: lane holds column lane % 16 and four rows; the FP32
     // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
     // Split partials go to their own slab of the workspace.
-    double *dst = le + (tile.pad * part_stride + (lv.tgt_off + box) * g.B + bm) * PS;
     constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
     const int rbase = sizeof(T) == 8 ? kr : 4 * kr;
+    if (S > 1) {
+        // partial sums in the accumulation type, one slab per split
+        T *dst = part + (tile.pad * part_stride + (lv.tgt_off + box) * g.B + bm) * PS;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                dst[16 * rb + rbase + rstride * r] = acc[rb][r];
+        return;
+    }
+    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -136,7 +146,7 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     dim3 grid(r.n), blk(256);
     const int S = p->split[TK_M2L];
     const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
-    double *dst = S > 1 ? p->d_part : p->d_le;
+    T *part = reinterpret_cast<T *>(p->d_part);  // sized for FP64 partials
     const T *me_in;
     if constexpr (sizeof(T) == 8)
         me_in = p->d_me;
@@ -146,7 +156,7 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     case R:                                                                                     \
         hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
                            (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
-                           (const int32_t *)p->d_class_off, K, me_in, dst, S, pstride);         \
+                           (const int32_t *)p->d_class_off, K, me_in, p->d_le, part, S, pstride); \
         break;
     switch (p->PS / 16) {
         M2L_CASE(1)
