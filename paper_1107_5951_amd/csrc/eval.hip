@@ -86,14 +86,14 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
                                   : -1;
         const bool have = ci >= 0;
         const double2 *bp = (const double2 *)(me + (have ? ((lc.me_off + ci) * g.B + bm) * PS : 0) + kr * (PS / 4));
-        const vec4 *ap = (const vec4 *)A + ((int64_t)c * RB * RB + rb) * 64 + lane;  // [c][q][rb][lane]
+        const double *ap = A + ((int64_t)c * RB * RB + rb) * 256;  // [c][q][rb] sets of 4 per lane
         for (int q0 = 0; q0 < RB; q0 += U) {
-            vec4 av[U];
+            double av[U][4];
             double2 bb[U][2];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = min(q0 + u, RB - 1);
-                av[u] = ap[(int64_t)q * RB * 64];
+                load_frags<double, 4>(ap + (int64_t)q * RB * 256, lane, av[u]);
                 bb[u][0] = bp[2 * q];
                 bb[u][1] = bp[2 * q + 1];
             }
@@ -155,13 +155,11 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
         acc[rb] = vec4{0, 0, 0, 0};
     const int kr = lane >> 4;
     const double2 *bp = (const double2 *)(le + (cvalid ? ((lp.tgt_off + par) * g.B + bm) * PS : 0) + kr * (PS / 4));
-    const double *ap = A + (int64_t)tile.cls * PS * PS + lane * 4 * RB;  // [c][q][lane][u][rb]
+    const double *ap = A + (int64_t)tile.cls * PS * PS;  // [c][q] sets of 4 RB values per lane
     for (int q = 0; q < RB; ++q) {
         const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
         double av[4 * RB];
-#pragma unroll
-        for (int e = 0; e < 4 * RB; ++e)
-            av[e] = ap[(int64_t)q * 64 * 4 * RB + e];
+        load_frags<double, 4 * RB>(ap + (int64_t)q * 64 * 4 * RB, lane, av);
         __builtin_amdgcn_sched_barrier(0);
         const double bv[4] = {cvalid ? b01.x : 0.0, cvalid ? b01.y : 0.0, cvalid ? b23.x : 0.0,
                               cvalid ? b23.y : 0.0};
@@ -329,13 +327,19 @@ k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_star
 }
 
 // --------------------------------------------------------------------------
-// Densities in leaf blocks for the lattice near field: blk[pl][model][v],
-// pl = leaf index in the source block padded by one leaf on every side
-// (the padding and cells outside the mesh stay zero), v = cell in the leaf
-// (x fastest), rows padded to a multiple of 4.  One thread per entry.
+// Densities in leaf blocks for the lattice near field, in the element type
+// of the near-field contraction.  Cell v of a leaf (x fastest, v < b^3) is
+// contraction index v = kr * 4Q + 4 q + u (Q chunks of four k steps per
+// instruction sub-row kr); the blocks are stored chunk-major,
+//   blk[q][kr][pl * B + model][u],
+// pl = leaf index in the source block padded by one leaf on every side, so
+// that the 16 columns of a wave (consecutive leaves) read four contiguous
+// runs per chunk.  The padding and cells outside the mesh stay zero.  One
+// thread per cell.
 // --------------------------------------------------------------------------
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_rho_blocks(DevGeom g, const double *rho, int KP, double *blk)
+k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
 {
     const DevLev &lv = g.lev[g.L];
     const int b = g.b, b2 = b * b, b3 = b2 * b;
@@ -353,7 +357,8 @@ k_rho_blocks(DevGeom g, const double *rho, int KP, double *blk)
     if (ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
         r = rho[(int64_t)bm * g.n[0] * g.n[1] * g.n[2] + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
     const int64_t pl = ((int64_t)(lz + 1) * (lv.ns[1] + 2) + (ly + 1)) * (lv.ns[0] + 2) + (lx + 1);
-    blk[(pl * g.B + bm) * KP + v] = r;
+    const int kr = v / (4 * Qn), q = (v % (4 * Qn)) / 4, u = v % 4;
+    blk[((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm) * 4 + u] = (T)r;
 }
 
 // --------------------------------------------------------------------------
@@ -365,25 +370,25 @@ k_rho_blocks(DevGeom g, const double *rho, int KP, double *blk)
 // pairs, precomputed in FP64), and the far field is a fixed (4 b^3) x PS
 // matrix applied to the leaf's local expansion (L2P at fixed points, FP64).
 // Over all leaves these are GEMMs with columns = (leaf, model).  A workgroup
-// owns 16 columns; its waves split the 4 b^3 rows; operand fragments are
-// laid out per lane ([q][rb][lane][u], four k steps per vector load).  The
-// result goes straight to the output in descriptor order, G applied.
+// owns 16 columns and 4 RBW row blocks, RBW per wave; operand fragments are
+// group-major sets per (d, q, rb), the densities chunk-major (both read with
+// contiguous-kilobyte vector loads).  The result goes straight to the output
+// in descriptor order, G applied.
 // --------------------------------------------------------------------------
 template <int RBW, typename T>
 __global__ void __launch_bounds__(256)
-k_near_lat(DevGeom g, const double *blk, const T *A, int RBn, int Qn, const double *Lm,
+k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, const double *Lm,
            const int32_t *tmap, const double *le, int64_t npts, int wgrows, double *out)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     using dvec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
-    using tvec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t cg = blockIdx.x / wgrows;
     const int rb0 = ((int)(blockIdx.x % wgrows) * 4 + wave) * RBW;
     const int nr = min(RBW, RBn - rb0);
     if (nr <= 0)
-        return;  // whole wave: no row block left
+        return;  // whole wave: no row block left (no barrier follows)
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
     const int64_t col = cg * 16 + (lane & 15);
@@ -395,40 +400,44 @@ k_near_lat(DevGeom g, const double *blk, const T *A, int RBn, int Qn, const doub
               lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
     const int px = lv.ns[0] + 2, py = lv.ns[1] + 2;
     const int kr = lane >> 4;
-    const int KP = 16 * Qn;
     vec4 acc[RBW];
 #pragma unroll
     for (int i = 0; i < RBW; ++i)
         acc[i] = vec4{0, 0, 0, 0};
-    // chunk i = (neighbour nb, four k steps q); operands of chunk i + 1 are
-    // loaded while chunk i's instructions run
+    // chunk i = (neighbour nb, four k steps q); the operands of chunk i + 1
+    // are in flight while chunk i's instructions run
     const int NI = 27 * Qn;
-    auto loadc = [&](int i, double2 (&bb)[2], tvec4 (&aa)[RBW]) {
+    auto loadc = [&](int i, T (&bb)[4], T (&aa)[RBW][4]) {
         const int nb = i / Qn, q = i % Qn;
         const int64_t pl = ((int64_t)(lz + nb / 9) * py + (ly + (nb / 3) % 3)) * px + (lx + nb % 3);
-        const double2 *bp = (const double2 *)(blk + (pl * g.B + bm) * KP + kr * (KP / 4));
-        bb[0] = bp[2 * q];
-        bb[1] = bp[2 * q + 1];
-        const tvec4 *ap = (const tvec4 *)A + (((int64_t)nb * Qn + q) * RBn + rb0) * 64 + lane;
+        load4(blk + ((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm) * 4, bb);
+        const T *ap = A + (((int64_t)nb * Qn + q) * RBn + rb0) * 256;
 #pragma unroll
-        for (int k = 0; k < RBW; ++k)
-            aa[k] = k < nr ? ap[(int64_t)k * 64] : tvec4{0, 0, 0, 0};
+        for (int k = 0; k < RBW; ++k) {
+            if (k < nr) {
+                load_frags<T, 4>(ap + (int64_t)k * 256, lane, aa[k]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    aa[k][u] = (T)0;
+            }
+        }
     };
-    auto compute = [&](const double2 (&bb)[2], const tvec4 (&aa)[RBW]) {
-        const T bv[4] = {cvalid ? (T)bb[0].x : (T)0, cvalid ? (T)bb[0].y : (T)0, cvalid ? (T)bb[1].x : (T)0,
-                         cvalid ? (T)bb[1].y : (T)0};
+    auto compute = [&](const T (&bb)[4], const T (&aa)[RBW][4]) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) {
+            const T bv = cvalid ? bb[u] : (T)0;
 #pragma unroll
             for (int k = 0; k < RBW; ++k) {
                 if constexpr (sizeof(T) == 8)
-                    acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[k][u], bv[u], acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[k][u], bv, acc[k], 0, 0, 0);
                 else
-                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[k][u], bv[u], acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[k][u], bv, acc[k], 0, 0, 0);
             }
+        }
     };
-    double2 bA[2], bB[2];
-    tvec4 aA[RBW], aB[RBW];
+    T bA[4], bB[4];
+    T aA[RBW][4], aB[RBW][4];
     loadc(0, bA, aA);
     for (int i = 0; i < NI; i += 2) {
         if (i + 1 < NI)
@@ -453,14 +462,20 @@ k_near_lat(DevGeom g, const double *blk, const T *A, int RBn, int Qn, const doub
         const bool hl = tl >= 0;
         const double2 *bp = (const double2 *)(le + (hl ? ((lv.tgt_off + tl) * g.B + bm) * g.PS : 0) +
                                               kr * (g.PS / 4));
-        const dvec4 *ap = (const dvec4 *)Lm + (int64_t)rb0 * 64 + lane;
         const int QL = g.PS / 16;
         for (int q = 0; q < QL; ++q) {
             const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
-            dvec4 av[RBW];
+            double av[RBW][4];
 #pragma unroll
-            for (int i = 0; i < RBW; ++i)
-                av[i] = i < nr ? ap[((int64_t)q * RBn + i) * 64] : dvec4{0, 0, 0, 0};
+            for (int i = 0; i < RBW; ++i) {
+                if (i < nr) {
+                    load_frags<double, 4>(Lm + ((int64_t)q * RBn + rb0 + i) * 256, lane, av[i]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        av[i][u] = 0.0;
+                }
+            }
             __builtin_amdgcn_sched_barrier(0);
             const double bv[4] = {hl ? b01.x : 0.0, hl ? b01.y : 0.0, hl ? b23.x : 0.0, hl ? b23.y : 0.0};
 #pragma unroll
@@ -694,36 +709,49 @@ static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
     return GRAV_OK;
 }
 
+#ifndef GRAV_NEAR_RBW
+#define GRAV_NEAR_RBW 2
+#endif
+
 static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho, double *out, hipStream_t s)
 {
     const LevelInfo &lv = p->lev[p->L];
     const int b3 = p->b * p->b * p->b;
     const int64_t nfill = lv.n_src * p->B * b3;
-    hipLaunchKernelGGL(k_rho_blocks, dim3((unsigned)((nfill + 255) / 256)), dim3(256), 0, s, g, rho,
-                       16 * p->lat_Q, p->d_rho_blk);
+    const int64_t nplB = (int64_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B;
+    const bool f64 = p->d.precision == GRAV_FP64;
+    const dim3 fgrid((unsigned)((nfill + 255) / 256));
+    if (f64)
+        hipLaunchKernelGGL((k_rho_blocks<double>), fgrid, dim3(256), 0, s, g, rho, p->lat_Q, nplB,
+                           p->d_rho_blk);
+    else
+        hipLaunchKernelGGL((k_rho_blocks<float>), fgrid, dim3(256), 0, s, g, rho, p->lat_Q, nplB,
+                           reinterpret_cast<float *>(p->d_rho_blk));
     GRAV_HIP(hipGetLastError());
     const int64_t ncol = lv.n_src * p->B;
     const int RBn = p->lat_RB, Qn = p->lat_Q;
-    // one row block per wave, four per workgroup: 16 columns x 4 row blocks
-    constexpr int RBW = 1;
-    const int wgrows = (RBn + 3) / 4;
+    // a workgroup: 16 columns x 4 RBW row blocks, RBW per wave
+    const int RBW = RBn <= 4 ? 1 : GRAV_NEAR_RBW;
+    const int wgrows = (RBn + 4 * RBW - 1) / (4 * RBW);
     dim3 grid((unsigned)((ncol + 15) / 16 * wgrows)), blk(256);
     const int64_t npts = p->d.n_points;
 #define NEAR_CASE(W)                                                                            \
     case W:                                                                                     \
-        if (p->d.precision == GRAV_FP64)                                                        \
+        if (f64)                                                                                \
             hipLaunchKernelGGL((k_near_lat<W, double>), grid, blk, 0, s, g,                      \
-                               (const double *)p->d_rho_blk, (const double *)p->d_tn64, RBn, Qn, \
-                               (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,           \
+                               (const double *)p->d_rho_blk, nplB, (const double *)p->d_tn64,   \
+                               RBn, Qn, (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,  \
                                (const double *)p->d_le, npts, wgrows, out);                     \
         else                                                                                    \
             hipLaunchKernelGGL((k_near_lat<W, float>), grid, blk, 0, s, g,                       \
-                               (const double *)p->d_rho_blk, (const float *)p->d_tn32, RBn, Qn,  \
-                               (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,           \
+                               (const float *)p->d_rho_blk, nplB, (const float *)p->d_tn32,     \
+                               RBn, Qn, (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,  \
                                (const double *)p->d_le, npts, wgrows, out);                     \
         break;
     switch (RBW) {
         NEAR_CASE(1)
+        NEAR_CASE(2)
+        NEAR_CASE(4)
     default:
         return GRAV_EUNSUPPORTED;
     }

@@ -59,6 +59,26 @@ __device__ inline void load4(const double *p, double v[4])
     v[3] = b.y;
 }
 
+// Per-lane MFMA operand fragments in HBM, group-major: a set of E values per
+// lane is stored as [E / G][64 lanes][G] with G = 16 bytes / sizeof(T), so
+// every 16-byte vector load of a wave reads one contiguous kilobyte (eight
+// cache lines).  The set must start on a 16-byte boundary.
+template <typename T, int E>
+__device__ __forceinline__ void load_frags(const T *set, int lane, T (&v)[E])
+{
+    constexpr int G = 16 / (int)sizeof(T);
+    static_assert(E % G == 0, "fragment set not a whole number of 16-byte groups");
+    using g16 = __attribute__((__vector_size__(16))) T;
+    const g16 *p = reinterpret_cast<const g16 *>(set) + lane;
+#pragma unroll
+    for (int j = 0; j < E / G; ++j) {
+        const g16 x = p[j * 64];
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+            v[j * G + t] = x[t];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // One 16-column MFMA panel: acc[i] += A[rb0 + i] * B over k = 0 .. 4 KS - 1,
 // with 16x16x4 instructions.  A is pre-swizzled ([ks][rb][lane], RBS row

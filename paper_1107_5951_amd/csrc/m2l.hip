@@ -21,10 +21,11 @@ namespace grav {
 // Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
 // instruction take coefficient c = kr * PS/4 + ks (ks = 0 .. PS/4 - 1), so
 // a lane's B values for four consecutive k steps are four consecutive
-// coefficients of one expansion (one aligned 32-byte load), and the A
-// fragments of four k steps are stored contiguously per lane
-// ([d][q][lane][u][rb], ks = 4q + u): RB aligned vector loads.  Padding
-// coefficients (c >= p^2) are zero in the expansions.
+// coefficients of one expansion (one aligned vector load), and the A
+// fragments of four k steps and all row blocks form one group-major set
+// per (d, q) (value u * RB + rb, ks = 4q + u), read with 4 RB / G 16-byte
+// loads that each cover a contiguous kilobyte.  Padding coefficients
+// (c >= p^2) are zero in the expansions.
 // --------------------------------------------------------------------------
 template <int RB, typename T>
 __global__ void __launch_bounds__(256)
@@ -69,7 +70,7 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
             continue;  // no column of this wave sees a source box at this offset
         const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
         const T *mp = me + (have ? (si * g.B + bm) * PS : 0) + kr * (PS / 4);
-        const T *kp = K + (int64_t)id * kstride + lane * 4 * RB;
+        const T *kp = K + (int64_t)id * kstride;
         // two register sets (when they fit): the loads of chunk q + 1 are in
         // flight while the instructions of chunk q run
         constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
@@ -77,9 +78,7 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         T bb[NSET][4];
         auto load = [&](int q, int set) {
             load4(mp + 4 * q, bb[set]);
-#pragma unroll
-            for (int e = 0; e < 4 * RB; ++e)
-                av[set][e] = kp[(int64_t)q * 64 * 4 * RB + e];
+            load_frags<T, 4 * RB>(kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
         };
         auto compute = [&](int set) {
             const T bv[4] = {have ? bb[set][0] : (T)0, have ? bb[set][1] : (T)0, have ? bb[set][2] : (T)0,

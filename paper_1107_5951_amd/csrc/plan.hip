@@ -368,11 +368,21 @@ void swizzle(const double *m, int PS, int KS, bool transpose, double *dst)
             }
 }
 
+// Position of value e (of E per lane) of a lane in a set of MFMA operand
+// fragments stored group-major, [E / G][64 lanes][G] with G = 16 bytes /
+// element size: the layout the kernels read with one 16-byte vector load per
+// group (a contiguous kilobyte per wave).
+static inline size_t frag_pos(int lane, int e, int G)
+{
+    return ((size_t)(e / G) * 64 + lane) * G + e % G;
+}
+
 // Forward M2L operand layout: k step ks (0 .. PS/4 - 1) and instruction
-// sub-row kr = lane / 16 contract coefficient kr * PS/4 + ks; the fragments
-// of four consecutive k steps are contiguous per lane:
-// dst[q][lane][u][rb] = m[16 rb + lane % 16][(lane / 16) * PS/4 + 4 q + u].
-void swizzle_panel(const double *m, int PS, double *dst)
+// sub-row kr = lane / 16 contract coefficient kr * PS/4 + ks.  The fragments
+// of four consecutive k steps (ks = 4 q + u) and all row blocks form one set
+// of E = 4 RB values per lane, value e = u * RB + rb:
+// set q, value (lane, e)  =  m[16 rb + lane % 16][(lane / 16) * PS/4 + 4 q + u].
+void swizzle_panel(const double *m, int PS, int G, double *dst)
 {
     const int RB = PS / 16, KP = PS / 4;
     for (int q = 0; q < RB; ++q)
@@ -381,12 +391,13 @@ void swizzle_panel(const double *m, int PS, double *dst)
                 for (int rb = 0; rb < RB; ++rb) {
                     const int row = 16 * rb + (lane & 15);
                     const int col = (lane >> 4) * KP + 4 * q + u;
-                    dst[(((size_t)q * 64 + lane) * 4 + u) * RB + rb] = m[(size_t)row * PS + col];
+                    dst[(size_t)q * 64 * 4 * RB + frag_pos(lane, u * RB + rb, G)] = m[(size_t)row * PS + col];
                 }
 }
 
-// Row-blocked variant: dst[q][rb][lane][u] = m[16 rb + lane % 16][(lane / 16) * PS/4 + 4 q + u].
-void swizzle_rows(const double *m, int PS, double *dst)
+// Row-blocked variant, one set of four values per (q, rb):
+// set (q, rb), value (lane, u)  =  m[16 rb + lane % 16][(lane / 16) * PS/4 + 4 q + u].
+void swizzle_rows(const double *m, int PS, int G, double *dst)
 {
     const int RB = PS / 16, KP = PS / 4;
     for (int q = 0; q < RB; ++q)
@@ -395,7 +406,7 @@ void swizzle_rows(const double *m, int PS, double *dst)
                 for (int u = 0; u < 4; ++u) {
                     const int row = 16 * rb + (lane & 15);
                     const int col = (lane >> 4) * KP + 4 * q + u;
-                    dst[(((size_t)q * RB + rb) * 64 + lane) * 4 + u] = m[(size_t)row * PS + col];
+                    dst[((size_t)q * RB + rb) * 256 + frag_pos(lane, u, G)] = m[(size_t)row * PS + col];
                 }
 }
 
@@ -447,9 +458,9 @@ grav_status build_operators(Plan *p)
             const double delta[3] = {((c & 1) - 0.5) * 0.5, (((c >> 1) & 1) - 0.5) * 0.5,
                                      (((c >> 2) & 1) - 0.5) * 0.5};
             m2m_matrix(P, delta, PS, m.data());
-            swizzle_rows(m.data(), PS, msw.data() + per8 * c);
+            swizzle_rows(m.data(), PS, 2, msw.data() + per8 * c);
             l2l_matrix(P, delta, PS, m.data());
-            swizzle_panel(m.data(), PS, lsw.data() + per8 * c);
+            swizzle_panel(m.data(), PS, 2, lsw.data() + per8 * c);
         }
         GRAV_CHECK(upload(p, &p->d_m2m_sw, msw));
         GRAV_CHECK(upload(p, &p->d_l2l_sw, lsw));
@@ -466,7 +477,7 @@ grav_status build_operators(Plan *p)
         // source = target + d  =>  target centre - source centre = -d
         const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
         m2l_matrix(P, dd, PS, m.data());
-        swizzle_panel(m.data(), PS, k.data() + perp * id);
+        swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, k.data() + perp * id);
         swizzle(m.data(), PS, KS, true, kT.data() + per * id);
     }
     if (p->d.precision == GRAV_FP64) {
@@ -683,7 +694,7 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
                         double v = 0.0;
                         if (t < b3 && cell < b3)
                             v = dense[((size_t)nb * 4 * b3 + 4 * t + comp) * b3 + cell];
-                        sw[((((size_t)nb * Qn + q) * RBn + rb) * 64 + lane) * 4 + u] = v;
+                        sw[(((size_t)nb * Qn + q) * RBn + rb) * 256 + frag_pos(lane, u, f64 ? 2 : 4)] = v;
                     }
     {
         // leaf blocks of the densities, padded by one leaf per side; the
@@ -729,7 +740,7 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
                         int t, comp;
                         row_target(lane & 15, true, rb, t, comp);
                         const int c = (lane >> 4) * (PS / 4) + 4 * q + u;
-                        lsw[(((size_t)q * RBn + rb) * 64 + lane) * 4 + u] =
+                        lsw[((size_t)q * RBn + rb) * 256 + frag_pos(lane, u, 2)] =
                             t < b3 ? full[(size_t)(4 * t + comp) * PS + c] : 0.0;
                     }
         GRAV_CHECK(upload(p, &p->d_tl2p, lsw));
