@@ -126,7 +126,14 @@ __global__ void k_parent_build(const uint32_t *ckeys, const uint32_t *flags, con
         pkeys[id] = ckeys[i] >> 3;
 }
 
-__global__ void k_class_keys(const uint32_t *bkeys, int64_t n, uint32_t *ck, uint32_t *cv,
+// Sort key of a target box for the class-grouped order: parity class
+// (Morton bits 0..2) first, then the box's boundary signature, the range of
+// interaction-list offsets d (|d_a| <= 3) that stay inside the source block
+// on each axis.  Boxes with one signature see the same set of source boxes,
+// so a wave of columns that shares a signature skips the same offsets and
+// wastes no MFMA work on missing sources.  The sort is stable: within a
+// signature the boxes stay in Morton order.
+__global__ void k_class_keys(const uint32_t *bkeys, int64_t n, int3 s0, int3 ns, uint32_t *ck, uint32_t *cv,
                              uint32_t *counts)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,7 +141,15 @@ __global__ void k_class_keys(const uint32_t *bkeys, int64_t n, uint32_t *ck, uin
         return;
     const uint32_t k = bkeys[i];
     const uint32_t cls = k & 7u;  // Morton bits 0,1,2 = x, y, z parity
-    ck[i] = cls;
+    const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+    const int lo[3] = {s0.x, s0.y, s0.z}, len[3] = {ns.x, ns.y, ns.z};
+    uint32_t sig = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int dlo = min(4, max(-3, lo[a] - c[a]));               // lowest valid offset
+        const int dhi = max(-4, min(3, lo[a] + len[a] - 1 - c[a]));  // highest valid offset
+        sig = sig * 64u + (uint32_t)((dlo + 3) * 8 + (dhi + 4));
+    }
+    ck[i] = (cls << 18) | sig;
     cv[i] = (uint32_t)i;
     atomicAdd(&counts[cls], 1u);
 }
@@ -998,7 +1013,7 @@ grav_status build_tree(Plan *p, hipStream_t s)
                 p->n_tbox += cnt[l];
             }
 
-        // class grouping per level (levels >= 2): a 3-bit radix pass
+        // class grouping per level (levels >= 2): radix sort on (class, signature)
         for (int l = 2; l <= L && ok; ++l) {
             const int64_t n = cnt[l];
             const unsigned g = (unsigned)ceil_div(n, T);
@@ -1006,9 +1021,12 @@ grav_status build_tree(Plan *p, hipStream_t s)
                 ok = false;
                 break;
             }
+            const LevelInfo &lv = p->lev[l];
             hipLaunchKernelGGL(k_class_keys, dim3(g), dim3(T), 0, s,
-                               (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n, keys, vals, ccount);
-            if (radix_sort_pairs(keys, vals, ktmp, vtmp, n, 3, scr, s) != GRAV_OK) {
+                               (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n,
+                               make_int3(lv.s0[0], lv.s0[1], lv.s0[2]), make_int3(lv.ns[0], lv.ns[1], lv.ns[2]),
+                               keys, vals, ccount);
+            if (radix_sort_pairs(keys, vals, ktmp, vtmp, n, 21, scr, s) != GRAV_OK) {
                 ok = false;
                 break;
             }
