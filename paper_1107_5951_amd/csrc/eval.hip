@@ -369,141 +369,194 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
 // with A_d a fixed (4 b^3) x b^3 matrix (the direct sum over the same point
 // pairs, precomputed in FP64), and the far field is a fixed (4 b^3) x PS
 // matrix applied to the leaf's local expansion (L2P at fixed points, FP64).
-// Over all leaves these are GEMMs with columns = (leaf, model).  A workgroup
-// owns 16 columns and 4 RBW row blocks, RBW per wave; operand fragments are
-// group-major sets per (d, q, rb), the densities chunk-major (both read with
-// contiguous-kilobyte vector loads).  The result goes straight to the output
-// in descriptor order, G applied.
+// Over all leaves these are GEMMs with columns = (leaf, model).
+//
+// A workgroup owns a tile of 16 CW columns x 16 RW rows.  Its four waves
+// all hold the whole tile (CW x RW MFMA blocks, so every fragment loaded
+// feeds CW or RW instructions) and split the contraction: wave w takes a
+// quarter of the 27 Q near chunks (chunk = neighbour d, four k steps) and
+// every fourth chunk of the far field.  The four partial tiles meet in LDS
+// and are added in wave order (fixed, so the result is deterministic); wave
+// w then finishes blocks w, w + 4, ... of the tile and writes them straight
+// to the output in descriptor order, G applied.  Operand fragments are
+// group-major sets per (d, q, rb), the densities chunk-major (both read
+// with contiguous-kilobyte vector loads).
 // --------------------------------------------------------------------------
-template <int RBW, typename T>
+template <int RW, int CW, typename T>
 __global__ void __launch_bounds__(256)
 k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, const double *Lm,
-           const int32_t *tmap, const double *le, int64_t npts, int wgrows, double *out)
+           const int32_t *tmap, const double *le, int64_t npts, int nrg, double *out)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     using dvec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    __shared__ double red[4][CW * RW * 4][64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t cg = blockIdx.x / wgrows;
-    const int rb0 = ((int)(blockIdx.x % wgrows) * 4 + wave) * RBW;
-    const int nr = min(RBW, RBn - rb0);
-    if (nr <= 0)
-        return;  // whole wave: no row block left (no barrier follows)
+    const int64_t cg = blockIdx.x / nrg;
+    const int rb0 = (int)(blockIdx.x % nrg) * RW;
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
-    const int64_t col = cg * 16 + (lane & 15);
-    const bool cvalid = col < nleaf * g.B;
-    const int64_t leaf = cvalid ? col / g.B : 0;
-    const int bm = cvalid ? (int)(col % g.B) : 0;
     const int b = g.b, b2 = b * b, b3 = b2 * b;
-    const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
-              lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
     const int px = lv.ns[0] + 2, py = lv.ns[1] + 2;
     const int kr = lane >> 4;
-    vec4 acc[RBW];
+    // this lane's column in each column block
+    bool cvalid[CW];
+    int bm[CW], lx[CW], ly[CW], lz[CW];
 #pragma unroll
-    for (int i = 0; i < RBW; ++i)
-        acc[i] = vec4{0, 0, 0, 0};
-    // chunk i = (neighbour nb, four k steps q); the operands of chunk i + 1
-    // are in flight while chunk i's instructions run
+    for (int c = 0; c < CW; ++c) {
+        const int64_t col = (cg * CW + c) * 16 + (lane & 15);
+        cvalid[c] = col < nleaf * g.B;
+        const int64_t leaf = cvalid[c] ? col / g.B : 0;
+        bm[c] = cvalid[c] ? (int)(col % g.B) : 0;
+        lx[c] = (int)(leaf % lv.ns[0]);
+        ly[c] = (int)((leaf / lv.ns[0]) % lv.ns[1]);
+        lz[c] = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    }
+    bool rvalid[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+        rvalid[r] = rb0 + r < RBn;
+    vec4 acc[CW][RW];
+    dvec4 far[CW][RW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c)
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            acc[c][r] = vec4{0, 0, 0, 0};
+            far[c][r] = dvec4{0, 0, 0, 0};
+        }
+    // near chunks [i0, i1) of this wave; the operands of the next chunk are
+    // in flight while this chunk's instructions run
     const int NI = 27 * Qn;
-    auto loadc = [&](int i, T (&bb)[4], T (&aa)[RBW][4]) {
+    const int i0 = wave * NI / 4, i1 = (wave + 1) * NI / 4;
+    auto loadc = [&](int i, T (&bb)[CW][4], T (&aa)[RW][4]) {
         const int nb = i / Qn, q = i % Qn;
-        const int64_t pl = ((int64_t)(lz + nb / 9) * py + (ly + (nb / 3) % 3)) * px + (lx + nb % 3);
-        load4(blk + ((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm) * 4, bb);
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int64_t pl = ((int64_t)(lz[c] + nb / 9) * py + (ly[c] + (nb / 3) % 3)) * px + (lx[c] + nb % 3);
+            load4(blk + ((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm[c]) * 4, bb[c]);
+        }
         const T *ap = A + (((int64_t)nb * Qn + q) * RBn + rb0) * 256;
 #pragma unroll
-        for (int k = 0; k < RBW; ++k) {
-            if (k < nr) {
-                load_frags<T, 4>(ap + (int64_t)k * 256, lane, aa[k]);
+        for (int r = 0; r < RW; ++r) {
+            if (rvalid[r]) {
+                load_frags<T, 4>(ap + (int64_t)r * 256, lane, aa[r]);
             } else {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    aa[k][u] = (T)0;
+                    aa[r][u] = (T)0;
             }
         }
     };
-    auto compute = [&](const T (&bb)[4], const T (&aa)[RBW][4]) {
+    auto compute = [&](const T (&bb)[CW][4], const T (&aa)[RW][4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const T bv = cvalid ? bb[u] : (T)0;
+            T bv[CW];
 #pragma unroll
-            for (int k = 0; k < RBW; ++k) {
-                if constexpr (sizeof(T) == 8)
-                    acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[k][u], bv, acc[k], 0, 0, 0);
-                else
-                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[k][u], bv, acc[k], 0, 0, 0);
-            }
+            for (int c = 0; c < CW; ++c)
+                bv[c] = cvalid[c] ? bb[c][u] : (T)0;
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    if constexpr (sizeof(T) == 8)
+                        acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[r][u], bv[c], acc[c][r], 0, 0, 0);
+                    else
+                        acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[r][u], bv[c], acc[c][r], 0, 0, 0);
+                }
         }
     };
-    T bA[4], bB[4];
-    T aA[RBW][4], aB[RBW][4];
-    loadc(0, bA, aA);
-    for (int i = 0; i < NI; i += 2) {
-        if (i + 1 < NI)
-            loadc(i + 1, bB, aB);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(bA, aA);
-        __builtin_amdgcn_sched_barrier(0);
-        if (i + 2 < NI)
-            loadc(i + 2, bA, aA);
-        __builtin_amdgcn_sched_barrier(0);
-        if (i + 1 < NI)
-            compute(bB, aB);
-        __builtin_amdgcn_sched_barrier(0);
+    if (i0 < i1) {
+        T bA[CW][4], bB[CW][4];
+        T aA[RW][4], aB[RW][4];
+        loadc(i0, bA, aA);
+        for (int i = i0; i < i1; i += 2) {
+            if (i + 1 < i1)
+                loadc(i + 1, bB, aB);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(bA, aA);
+            __builtin_amdgcn_sched_barrier(0);
+            if (i + 2 < i1)
+                loadc(i + 2, bA, aA);
+            __builtin_amdgcn_sched_barrier(0);
+            if (i + 1 < i1)
+                compute(bB, aB);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
-    // far field from the leaf's local expansion (FP64 in both precisions)
-    dvec4 far[RBW];
-#pragma unroll
-    for (int i = 0; i < RBW; ++i)
-        far[i] = dvec4{0, 0, 0, 0};
+    // far field from the leaf's local expansion (FP64 in both precisions):
+    // chunks q = wave, wave + 4, ...
     if (g.L >= 2) {
-        const int64_t tl = cvalid ? tmap_lookup(lv, tmap, 3, lv.s0[0] + lx, lv.s0[1] + ly, lv.s0[2] + lz) : -1;
-        const bool hl = tl >= 0;
-        const double2 *bp = (const double2 *)(le + (hl ? ((lv.tgt_off + tl) * g.B + bm) * g.PS : 0) +
-                                              kr * (g.PS / 4));
-        const int QL = g.PS / 16;
-        for (int q = 0; q < QL; ++q) {
-            const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
-            double av[RBW][4];
+        bool hl[CW];
+        const double2 *bp[CW];
 #pragma unroll
-            for (int i = 0; i < RBW; ++i) {
-                if (i < nr) {
-                    load_frags<double, 4>(Lm + ((int64_t)q * RBn + rb0 + i) * 256, lane, av[i]);
+        for (int c = 0; c < CW; ++c) {
+            const int64_t tl = cvalid[c] ? tmap_lookup(lv, tmap, 3, lv.s0[0] + lx[c], lv.s0[1] + ly[c],
+                                                       lv.s0[2] + lz[c])
+                                         : -1;
+            hl[c] = tl >= 0;
+            bp[c] = (const double2 *)(le + (hl[c] ? ((lv.tgt_off + tl) * g.B + bm[c]) * g.PS : 0) + kr * (g.PS / 4));
+        }
+        const int QL = g.PS / 16;
+        for (int q = wave; q < QL; q += 4) {
+            double bv[CW][4];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const double2 b01 = bp[c][2 * q], b23 = bp[c][2 * q + 1];
+                bv[c][0] = hl[c] ? b01.x : 0.0;
+                bv[c][1] = hl[c] ? b01.y : 0.0;
+                bv[c][2] = hl[c] ? b23.x : 0.0;
+                bv[c][3] = hl[c] ? b23.y : 0.0;
+            }
+            double av[RW][4];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                if (rvalid[r]) {
+                    load_frags<double, 4>(Lm + ((int64_t)q * RBn + rb0 + r) * 256, lane, av[r]);
                 } else {
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        av[i][u] = 0.0;
+                        av[r][u] = 0.0;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
-            const double bv[4] = {hl ? b01.x : 0.0, hl ? b01.y : 0.0, hl ? b23.x : 0.0, hl ? b23.y : 0.0};
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int i = 0; i < RBW; ++i)
-                    far[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[u], far[i], 0, 0, 0);
+                for (int r = 0; r < RW; ++r)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c)
+                        far[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][u], bv[c][u], far[c][r], 0, 0, 0);
         }
     }
-    if (!cvalid)
-        return;
-    // lane holds target t = 4 rb + lane / 16 (the row order of both
-    // operators), components r = 0..3 = (phi, gx, gy, gz) in lattice units
-    const double sg = g.G * g.h, sp = g.G * g.h * g.h;
+    // partial tiles to LDS (FP64), then each wave adds the four partials of
+    // its blocks in wave order
 #pragma unroll
-    for (int i = 0; i < RBW; ++i) {
-        const int t = 4 * (rb0 + i) + kr;
-        if (i >= nr || t >= b3)
+    for (int c = 0; c < CW; ++c)
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                red[wave][(c * RW + r) * 4 + k][lane] = (double)acc[c][r][k] + far[c][r][k];
+    __syncthreads();
+    // lane holds target t = 4 rb + lane / 16 (the row order of both
+    // operators), components k = 0..3 = (phi, gx, gy, gz) in lattice units
+    const double sg = g.G * g.h, sp = g.G * g.h * g.h;
+    for (int j = wave; j < CW * RW; j += 4) {
+        const int c = j / RW, r = j % RW;
+        const int t = 4 * (rb0 + r) + kr;
+        if (!cvalid[c] || !rvalid[r] || t >= b3)
             continue;
-        const int ix = lx * b + t % b, iy = ly * b + (t / b) % b, iz = lz * b + t / b2;
+        const int ix = lx[c] * b + t % b, iy = ly[c] * b + (t / b) % b, iz = lz[c] * b + t / b2;
         if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
             continue;
         double v[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            v[r] = (double)acc[i][r] + far[i][r];
+        for (int k = 0; k < 4; ++k)
+            v[k] = ((red[0][j * 4 + k][lane] + red[1][j * 4 + k][lane]) + red[2][j * 4 + k][lane]) +
+                   red[3][j * 4 + k][lane];
         const int64_t cell = ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
-        double *o = out + ((int64_t)bm * g.M + npts + cell) * g.C;
+        double *o = out + ((int64_t)bm[c] * g.M + npts + cell) * g.C;
         if (g.C == 1) {
             o[0] = sg * v[3];
         } else if (g.C == 3) {
@@ -709,8 +762,13 @@ static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
     return GRAV_OK;
 }
 
-#ifndef GRAV_NEAR_RBW
-#define GRAV_NEAR_RBW 2
+// Lattice near-field tile per workgroup: GRAV_NEAR_RW row blocks x
+// GRAV_NEAR_CW column blocks of 16.
+#ifndef GRAV_NEAR_RW
+#define GRAV_NEAR_RW 2
+#endif
+#ifndef GRAV_NEAR_CW
+#define GRAV_NEAR_CW 2
 #endif
 
 static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho, double *out, hipStream_t s)
@@ -730,32 +788,21 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
     GRAV_HIP(hipGetLastError());
     const int64_t ncol = lv.n_src * p->B;
     const int RBn = p->lat_RB, Qn = p->lat_Q;
-    // a workgroup: 16 columns x 4 RBW row blocks, RBW per wave
-    const int RBW = RBn <= 4 ? 1 : GRAV_NEAR_RBW;
-    const int wgrows = (RBn + 4 * RBW - 1) / (4 * RBW);
-    dim3 grid((unsigned)((ncol + 15) / 16 * wgrows)), blk(256);
-    const int64_t npts = p->d.n_points;
-#define NEAR_CASE(W)                                                                            \
-    case W:                                                                                     \
-        if (f64)                                                                                \
-            hipLaunchKernelGGL((k_near_lat<W, double>), grid, blk, 0, s, g,                      \
-                               (const double *)p->d_rho_blk, nplB, (const double *)p->d_tn64,   \
-                               RBn, Qn, (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,  \
-                               (const double *)p->d_le, npts, wgrows, out);                     \
-        else                                                                                    \
-            hipLaunchKernelGGL((k_near_lat<W, float>), grid, blk, 0, s, g,                       \
-                               (const float *)p->d_rho_blk, nplB, (const float *)p->d_tn32,     \
-                               RBn, Qn, (const double *)p->d_tl2p, (const int32_t *)p->d_tmap,  \
-                               (const double *)p->d_le, npts, wgrows, out);                     \
-        break;
-    switch (RBW) {
-        NEAR_CASE(1)
-        NEAR_CASE(2)
-        NEAR_CASE(4)
-    default:
+    constexpr int RW = GRAV_NEAR_RW, CW = GRAV_NEAR_CW;
+    const int nrg = (RBn + RW - 1) / RW;
+    const int64_t ncg = (ncol + 16 * CW - 1) / (16 * CW);
+    if (ncg * nrg > 0x7fffffffll)
         return GRAV_EUNSUPPORTED;
-    }
-#undef NEAR_CASE
+    dim3 grid((unsigned)(ncg * nrg)), blk(256);
+    const int64_t npts = p->d.n_points;
+    if (f64)
+        hipLaunchKernelGGL((k_near_lat<RW, CW, double>), grid, blk, 0, s, g, (const double *)p->d_rho_blk, nplB,
+                           (const double *)p->d_tn64, RBn, Qn, (const double *)p->d_tl2p,
+                           (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
+    else
+        hipLaunchKernelGGL((k_near_lat<RW, CW, float>), grid, blk, 0, s, g, (const float *)p->d_rho_blk, nplB,
+                           (const float *)p->d_tn32, RBn, Qn, (const double *)p->d_tl2p,
+                           (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }

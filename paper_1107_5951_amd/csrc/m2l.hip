@@ -7,16 +7,27 @@
 #ifndef GRAV_M2L_DB_BYTES
 #define GRAV_M2L_DB_BYTES 128
 #endif
+// 16-column blocks per wave (1, 2 or 4) for the FP32 and FP64 kernels: each
+// A fragment feeds this many instructions; a workgroup holds 4 / NC waves
+// (64 columns).  FP64 keeps one block: its accumulators for two would leave
+// one wave per SIMD.
+#ifndef GRAV_M2L_NC32
+#define GRAV_M2L_NC32 2
+#endif
+#ifndef GRAV_M2L_NC64
+#define GRAV_M2L_NC64 1
+#endif
 
 namespace grav {
 
 // --------------------------------------------------------------------------
 // M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
 // child-parity class, model) of one split of the class's 189 interaction-
-// list offsets d; wave w owns columns 16w..16w+15 and all row blocks.  For
-// each d the wave accumulates LE[:, col] += K_d * ME[box(col) + d] with
-// 16x16x4 MFMA tiles, accumulating in registers across the offsets (no
-// atomics).
+// list offsets d.  A workgroup has 4 / NC waves; wave w owns the NC blocks
+// of 16 columns 16 (NC w + c), c < NC, and all row blocks.  For each d the
+// wave accumulates LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA
+// tiles, accumulating in registers across the offsets (no atomics); every
+// A fragment loaded feeds NC instructions.
 //
 // Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
 // instruction take coefficient c = kr * PS/4 + ks (ks = 0 .. PS/4 - 1), so
@@ -27,8 +38,8 @@ namespace grav {
 // loads that each cover a contiguous kilobyte.  Padding coefficients
 // (c >= p^2) are zero in the expansions.
 // --------------------------------------------------------------------------
-template <int RB, typename T>
-__global__ void __launch_bounds__(256)
+template <int RB, int NC, typename T>
+__global__ void __launch_bounds__(256 / NC)
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
       const int32_t *class_off, const T *K, const T *me, double *le, T *part, int S, int64_t part_stride)
 {
@@ -37,23 +48,31 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const DevLev &lv = g.lev[tile.level];
-    const int cl = wave * 16 + (lane & 15);
-    const bool cvalid = cl < tile.ncol;
-    const int64_t col = tile.col0 + cl;
-    const int bm = (int)(col % g.B);
-    int64_t box = 0;
-    int bx = 0, by = 0, bz = 0;
-    if (cvalid) {
-        box = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
-        const uint32_t key = tkey[lv.tbox_off + box];
-        bx = (int)compact3(key);
-        by = (int)compact3(key >> 1);
-        bz = (int)compact3(key >> 2);
-    }
-    vec4 acc[RB];
+    bool cvalid[NC];
+    int bm[NC], bx[NC], by[NC], bz[NC];
+    int64_t box[NC];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-        acc[rb] = vec4{0, 0, 0, 0};
+    for (int c = 0; c < NC; ++c) {
+        const int cl = (wave * NC + c) * 16 + (lane & 15);
+        cvalid[c] = cl < tile.ncol;
+        const int64_t col = tile.col0 + cl;
+        bm[c] = (int)(col % g.B);
+        box[c] = 0;
+        bx[c] = by[c] = bz[c] = 0;
+        if (cvalid[c]) {
+            box[c] = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
+            const uint32_t key = tkey[lv.tbox_off + box[c]];
+            bx[c] = (int)compact3(key);
+            by[c] = (int)compact3(key >> 1);
+            bz[c] = (int)compact3(key >> 2);
+        }
+    }
+    vec4 acc[NC][RB];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+            acc[c][rb] = vec4{0, 0, 0, 0};
     const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
     const int kr = lane >> 4;
     constexpr int PS = 16 * RB;
@@ -63,35 +82,51 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
     for (int o = o0; o < o1; ++o) {
         const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
         const int id = offs[4 * o + 3];
-        const int sx = bx + dx - lv.s0[0], sy = by + dy - lv.s0[1], sz = bz + dz - lv.s0[2];
-        const bool have = cvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] &&
-                          sy < lv.ns[1] && sz < lv.ns[2];
-        if (__ballot(have) == 0ull)
+        bool have[NC];
+        const T *mp[NC];
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int sx = bx[c] + dx - lv.s0[0], sy = by[c] + dy - lv.s0[1], sz = bz[c] + dz - lv.s0[2];
+            have[c] = cvalid[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
+                      sz < lv.ns[2];
+            const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
+            mp[c] = me + (have[c] ? (si * g.B + bm[c]) * PS : 0) + kr * (PS / 4);
+            any = any || have[c];
+        }
+        if (__ballot(any) == 0ull)
             continue;  // no column of this wave sees a source box at this offset
-        const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
-        const T *mp = me + (have ? (si * g.B + bm) * PS : 0) + kr * (PS / 4);
         const T *kp = K + (int64_t)id * kstride;
         // two register sets (when they fit): the loads of chunk q + 1 are in
         // flight while the instructions of chunk q run
         constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
         T av[NSET][4 * RB];
-        T bb[NSET][4];
+        T bb[NSET][NC][4];
         auto load = [&](int q, int set) {
-            load4(mp + 4 * q, bb[set]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                load4(mp[c] + 4 * q, bb[set][c]);
             load_frags<T, 4 * RB>(kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
         };
         auto compute = [&](int set) {
-            const T bv[4] = {have ? bb[set][0] : (T)0, have ? bb[set][1] : (T)0, have ? bb[set][2] : (T)0,
-                             have ? bb[set][3] : (T)0};
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
+                T bv[NC];
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    if constexpr (sizeof(T) == 8)
-                        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[u], acc[rb], 0, 0, 0);
-                    else
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[u], acc[rb], 0, 0, 0);
-                }
+                for (int c = 0; c < NC; ++c)
+                    bv[c] = have[c] ? bb[set][c][u] : (T)0;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        if constexpr (sizeof(T) == 8)
+                            acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[c],
+                                                                              acc[c][rb], 0, 0, 0);
+                        else
+                            acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[c],
+                                                                              acc[c][rb], 0, 0, 0);
+                    }
+            }
         };
         if constexpr (NSET == 2) {
             load(0, 0);
@@ -111,29 +146,32 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
             }
         }
     }
-    if (!cvalid)
-        return;
     // Output fragment: lane holds column lane % 16 and four rows; the FP32
     // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
     // Split partials go to their own slab of the workspace.
     constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
     const int rbase = sizeof(T) == 8 ? kr : 4 * kr;
-    if (S > 1) {
-        // partial sums in the accumulation type, one slab per split
-        T *dst = part + (tile.pad * part_stride + (lv.tgt_off + box) * g.B + bm) * PS;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+    for (int c = 0; c < NC; ++c) {
+        if (!cvalid[c])
+            continue;
+        if (S > 1) {
+            // partial sums in the accumulation type, one slab per split
+            T *dst = part + (tile.pad * part_stride + (lv.tgt_off + box[c]) * g.B + bm[c]) * PS;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                dst[16 * rb + rbase + rstride * r] = acc[rb][r];
-        return;
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    dst[16 * rb + rbase + rstride * r] = acc[c][rb][r];
+        } else {
+            double *dst = le + ((lv.tgt_off + box[c]) * g.B + bm[c]) * PS;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    dst[16 * rb + rbase + rstride * r] = (double)acc[c][rb][r];
+        }
     }
-    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            dst[16 * rb + rbase + rstride * r] = (double)acc[rb][r];
 }
 
 template <typename T>
@@ -142,7 +180,8 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     const TileRange &r = p->tiles[TK_M2L][0];
     if (r.n == 0)
         return GRAV_OK;
-    dim3 grid(r.n), blk(256);
+    constexpr int NC = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;  // column blocks per wave
+    dim3 grid(r.n), blk(256 / NC);
     const int S = p->split[TK_M2L];
     const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
     T *part = reinterpret_cast<T *>(p->d_part);  // sized for FP64 partials
@@ -153,7 +192,7 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
         me_in = p->d_me32;
 #define M2L_CASE(R)                                                                             \
     case R:                                                                                     \
-        hipLaunchKernelGGL((k_m2l<R, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
+        hipLaunchKernelGGL((k_m2l<R, NC, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
                            (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
                            (const int32_t *)p->d_class_off, K, me_in, p->d_le, part, S, pstride); \
         break;

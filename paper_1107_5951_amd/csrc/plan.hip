@@ -17,10 +17,10 @@
 
 // Splitting of the M2L offsets over workgroups (see build_tiles).
 #ifndef GRAV_M2L_SPLIT_MAX
-#define GRAV_M2L_SPLIT_MAX 16
+#define GRAV_M2L_SPLIT_MAX 32
 #endif
 #ifndef GRAV_M2L_TARGET_WG
-#define GRAV_M2L_TARGET_WG 4096
+#define GRAV_M2L_TARGET_WG 8192
 #endif
 
 namespace grav {
