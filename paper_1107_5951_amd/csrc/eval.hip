@@ -179,14 +179,46 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
             dst[16 * rb + kr + 4 * r] += acc[rb][r];
 }
 
-// FP32 copy of the multipole expansions for the mixed-precision M2L (its
-// MFMA operands are FP32 anyway; the copy halves the bytes it gathers).
-__global__ void __launch_bounds__(256) k_to_float(const double *src, int64_t n, float *dst)
+// The multipole expansions regathered for the M2L's B operand, in the
+// M2L's element type.  Per level, boxes are ordered by parity class (x
+// fastest within a class, see class_split) and the coefficients chunk-major:
+//   out[level][q][kr][pos * B + model][u],  coefficient kr * PS/4 + 4 q + u.
+// The source boxes that one wave's 16 columns read at one interaction offset
+// are boxes of a single class with consecutive x, so each B fragment load
+// of the M2L covers a few contiguous runs instead of 64 scattered lines.
+// One thread per (box, model, chunk q, sub-row kr).
+template <typename T>
+__global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, int64_t n_me, T *out)
 {
+    const int NP = g.PS / 4;  // (q, kr) planes
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        dst[i] = (float)src[i];
+    if (i >= n_me * g.B * NP)
+        return;
+    const int plane = (int)(i % NP);
+    const int64_t col = i / NP;  // box * B + model
+    const int bm = (int)(col % g.B);
+    const int64_t box = col / g.B;
+    int l = 2;
+    while (l < g.L && box >= g.lev[l + 1].me_off)
+        ++l;
+    const DevLev &lv = g.lev[l];
+    const int64_t j = box - lv.me_off;
+    const int ax = lv.s0[0] + (int)(j % lv.ns[0]), ay = lv.s0[1] + (int)((j / lv.ns[0]) % lv.ns[1]),
+              az = lv.s0[2] + (int)(j / ((int64_t)lv.ns[0] * lv.ns[1]));
+    int first[3], cnt[3];
+    const int64_t pos = class_split(lv, (ax & 1) | ((ay & 1) << 1) | ((az & 1) << 2), first, cnt) +
+                        ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
+                        ((ax - first[0]) >> 1);
+    const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
+    const int q = plane / 4, kr = plane % 4;
+    const double *src = me + col * g.PS + kr * NP + 4 * q;
+    T *dst = out + lv.me_off * g.B * g.PS + ((int64_t)plane * nB + pos * g.B + bm) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        dst[u] = (T)src[u];
 }
+template __global__ void k_me_gather<double>(DevGeom, const double *, int64_t, double *);
+template __global__ void k_me_gather<float>(DevGeom, const double *, int64_t, float *);
 
 // out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ..., in FP64
 template <typename T>
@@ -824,12 +856,19 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         for (int l = L - 1; l >= 2; --l)
             GRAV_CHECK(launch_m2m(p, g, l, s));
         stage_end(p, s);
-        if (p->d.precision != GRAV_FP64) {
-            const int64_t n = p->n_me * p->B * p->PS;
-            hipLaunchKernelGGL(k_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                               (const double *)p->d_me, n, p->d_me32);
+        stage_begin(p, "me_gather", s);
+        {
+            const int64_t n = p->n_me * p->B * (p->PS / 4);
+            const dim3 gg((unsigned)((n + 255) / 256));
+            if (p->d.precision == GRAV_FP64)
+                hipLaunchKernelGGL((k_me_gather<double>), gg, dim3(256), 0, s, g, (const double *)p->d_me, p->n_me,
+                                   p->d_meg);
+            else
+                hipLaunchKernelGGL((k_me_gather<float>), gg, dim3(256), 0, s, g, (const double *)p->d_me, p->n_me,
+                                   reinterpret_cast<float *>(p->d_meg));
             GRAV_HIP(hipGetLastError());
         }
+        stage_end(p, s);
         stage_begin(p, "m2l", s);
         if (p->d.precision == GRAV_FP64)
             GRAV_CHECK(launch_m2l<double>(p, g, s, p->d_k64));

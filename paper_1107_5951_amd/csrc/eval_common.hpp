@@ -25,6 +25,31 @@ struct DevGeom {
     double G, h;
 };
 
+// Boxes of one parity class (bit a of cls = parity of coordinate a) of a
+// level's source block, in x-fastest order; classes follow each other in
+// order 0..7.  Returns the class's first box position and, per axis, its
+// first absolute coordinate and box count.
+__host__ __device__ inline int64_t class_split(const DevLev &lv, int cls, int first[3], int cnt[3])
+{
+    int64_t start = 0;
+    for (int c = 0; c <= cls; ++c) {
+        int64_t n = 1;
+        for (int a = 0; a < 3; ++a) {
+            const int f = lv.s0[a] + ((((c >> a) & 1) - lv.s0[a]) & 1);
+            const int k = (lv.ns[a] - (f - lv.s0[a]) + 1) / 2;
+            const int kk = k > 0 ? k : 0;
+            if (c == cls) {
+                first[a] = f;
+                cnt[a] = kk;
+            }
+            n *= kk;
+        }
+        if (c < cls)
+            start += n;
+    }
+    return start;
+}
+
 DevGeom make_geom(const Plan *p);
 template <typename T>
 __global__ void k_sum_parts(const T *part, int S, int64_t n, double *out);

@@ -92,7 +92,8 @@ struct Plan {
     hipStream_t bs = nullptr;                      // plan-build stream (non-blocking), only inside grav_plan
     int direct_chunks = 1;                         // source chunks of grav_direct
     double *d_dpart = nullptr;                     // [chunks][M][B][4] its partial sums
-    float *d_me32 = nullptr;                       // FP32 copy of the ME for the mixed M2L
+    double *d_meg = nullptr;                       // ME regathered for the M2L's B operand (class-split,
+                                                   // chunk-major; FP32 in mixed plans)
     double *d_rho_blk = nullptr;                   // [Q][4][padded leaves x B][4] densities per leaf (FP32 in mixed plans)
     int64_t *d_leaf_pend = nullptr;                // [n_leaf] end of the user points of a leaf                  // workgroups sharing the offsets of one tile
     double *d_part = nullptr;                      // [split][expansions][PS] partial sums

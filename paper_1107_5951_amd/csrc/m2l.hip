@@ -32,7 +32,10 @@ namespace grav {
 // Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
 // instruction take coefficient c = kr * PS/4 + ks (ks = 0 .. PS/4 - 1), so
 // a lane's B values for four consecutive k steps are four consecutive
-// coefficients of one expansion (one aligned vector load), and the A
+// coefficients of one expansion (one aligned vector load from the
+// regathered, class-split expansions: the 16 source boxes of a wave at one
+// offset are one class, consecutive in x, so the load covers a few
+// contiguous runs), and the A
 // fragments of four k steps and all row blocks form one group-major set
 // per (d, q) (value u * RB + rb, ks = 4q + u), read with 4 RB / G 16-byte
 // loads that each cover a contiguous kilobyte.  Padding coefficients
@@ -76,22 +79,33 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
     const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
     const int kr = lane >> 4;
     constexpr int PS = 16 * RB;
+    // regathered expansions of this level: plane (q, kr) holds four
+    // coefficients of every (class-split box, model), plane stride pstr
+    const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
+    const int64_t pstr = nB * 4;
+    const T *mlev = me + lv.me_off * g.B * PS + kr * pstr;
     constexpr int64_t kstride = (int64_t)RB * 64 * 4 * RB;  // elements per offset matrix
     // offsets [o0, o1) of this split (tile.pad of S)
     const int o0 = tile.pad * kClassOffsets / S, o1 = (tile.pad + 1) * kClassOffsets / S;
     for (int o = o0; o < o1; ++o) {
         const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
         const int id = offs[4 * o + 3];
+        // the source boxes at this offset all belong to one parity class
+        int first[3], cnt[3];
+        const int64_t cstart =
+            class_split(lv, tile.cls ^ ((dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2)), first, cnt);
         bool have[NC];
         const T *mp[NC];
         bool any = false;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const int sx = bx[c] + dx - lv.s0[0], sy = by[c] + dy - lv.s0[1], sz = bz[c] + dz - lv.s0[2];
+            const int ax = bx[c] + dx, ay = by[c] + dy, az = bz[c] + dz;
+            const int sx = ax - lv.s0[0], sy = ay - lv.s0[1], sz = az - lv.s0[2];
             have[c] = cvalid[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
                       sz < lv.ns[2];
-            const int64_t si = lv.me_off + ((int64_t)sz * lv.ns[1] + sy) * lv.ns[0] + sx;
-            mp[c] = me + (have[c] ? (si * g.B + bm[c]) * PS : 0) + kr * (PS / 4);
+            const int64_t pos = cstart + ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
+                                ((ax - first[0]) >> 1);
+            mp[c] = mlev + (have[c] ? (pos * g.B + bm[c]) * 4 : 0);
             any = any || have[c];
         }
         if (__ballot(any) == 0ull)
@@ -105,7 +119,7 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         auto load = [&](int q, int set) {
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                load4(mp[c] + 4 * q, bb[set][c]);
+                load4(mp[c] + (int64_t)q * 4 * pstr, bb[set][c]);
             load_frags<T, 4 * RB>(kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
         };
         auto compute = [&](int set) {
@@ -185,11 +199,7 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     const int S = p->split[TK_M2L];
     const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
     T *part = reinterpret_cast<T *>(p->d_part);  // sized for FP64 partials
-    const T *me_in;
-    if constexpr (sizeof(T) == 8)
-        me_in = p->d_me;
-    else
-        me_in = p->d_me32;
+    const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see k_me_gather)
 #define M2L_CASE(R)                                                                             \
     case R:                                                                                     \
         hipLaunchKernelGGL((k_m2l<R, NC, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \

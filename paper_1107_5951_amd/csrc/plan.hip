@@ -126,31 +126,43 @@ __global__ void k_parent_build(const uint32_t *ckeys, const uint32_t *flags, con
         pkeys[id] = ckeys[i] >> 3;
 }
 
-// Sort key of a target box for the class-grouped order: parity class
-// (Morton bits 0..2) first, then the box's boundary signature, the range of
-// interaction-list offsets d (|d_a| <= 3) that stay inside the source block
-// on each axis.  Boxes with one signature see the same set of source boxes,
-// so a wave of columns that shares a signature skips the same offsets and
-// wastes no MFMA work on missing sources.  The sort is stable: within a
-// signature the boxes stay in Morton order.
-__global__ void k_class_keys(const uint32_t *bkeys, int64_t n, int3 s0, int3 ns, uint32_t *ck, uint32_t *cv,
-                             uint32_t *counts)
+// Sort keys of the target boxes of a level for the class-grouped order
+// (the column order of the M2L and L2L tiles).  First pass: x-fastest
+// lexicographic order of the boxes.  Second, stable pass: parity class
+// (Morton bits 0..2), then the box's boundary signature in y and z (the
+// range of interaction-list offsets, |d| <= 3, that stay inside the source
+// block on those axes).  A wave's 16 columns are then boxes of one class
+// along x rows that mostly see the same source offsets, so (i) the waves
+// skip the same missing offsets and waste little MFMA work, and (ii) the
+// source boxes a wave reads at one offset are consecutive in x, which the
+// regathered expansions store contiguously.
+__global__ void k_lex_keys(const uint32_t *bkeys, int64_t n, int bits, uint32_t *ck, uint32_t *cv)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     const uint32_t k = bkeys[i];
+    ck[i] = (compact3(k >> 2) << (2 * bits)) | (compact3(k >> 1) << bits) | compact3(k);
+    cv[i] = (uint32_t)i;
+}
+
+__global__ void k_class_keys(const uint32_t *bkeys, const uint32_t *order, int64_t n, int3 s0, int3 ns,
+                             uint32_t *ck, uint32_t *counts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t k = bkeys[order[i]];
     const uint32_t cls = k & 7u;  // Morton bits 0,1,2 = x, y, z parity
-    const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
-    const int lo[3] = {s0.x, s0.y, s0.z}, len[3] = {ns.x, ns.y, ns.z};
+    const int c[2] = {(int)compact3(k >> 1), (int)compact3(k >> 2)};
+    const int lo[2] = {s0.y, s0.z}, len[2] = {ns.y, ns.z};
     uint32_t sig = 0;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 2; ++a) {
         const int dlo = min(4, max(-3, lo[a] - c[a]));               // lowest valid offset
         const int dhi = max(-4, min(3, lo[a] + len[a] - 1 - c[a]));  // highest valid offset
         sig = sig * 64u + (uint32_t)((dlo + 3) * 8 + (dhi + 4));
     }
-    ck[i] = (cls << 18) | sig;
-    cv[i] = (uint32_t)i;
+    ck[i] = (cls << 12) | sig;
     atomicAdd(&counts[cls], 1u);
 }
 
@@ -273,7 +285,7 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_me32,
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg,
                     p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
@@ -1013,7 +1025,7 @@ grav_status build_tree(Plan *p, hipStream_t s)
                 p->n_tbox += cnt[l];
             }
 
-        // class grouping per level (levels >= 2): radix sort on (class, signature)
+        // class grouping per level (levels >= 2): lexicographic, then stable on (class, signature)
         for (int l = 2; l <= L && ok; ++l) {
             const int64_t n = cnt[l];
             const unsigned g = (unsigned)ceil_div(n, T);
@@ -1022,11 +1034,16 @@ grav_status build_tree(Plan *p, hipStream_t s)
                 break;
             }
             const LevelInfo &lv = p->lev[l];
-            hipLaunchKernelGGL(k_class_keys, dim3(g), dim3(T), 0, s,
-                               (const uint32_t *)(p->d_tkey + p->tbox_off[l]), n,
+            const uint32_t *bk_l = (const uint32_t *)(p->d_tkey + p->tbox_off[l]);
+            hipLaunchKernelGGL(k_lex_keys, dim3(g), dim3(T), 0, s, bk_l, n, l, keys, vals);
+            if (radix_sort_pairs(keys, vals, ktmp, vtmp, n, 3 * l, scr, s) != GRAV_OK) {
+                ok = false;
+                break;
+            }
+            hipLaunchKernelGGL(k_class_keys, dim3(g), dim3(T), 0, s, bk_l, (const uint32_t *)vals, n,
                                make_int3(lv.s0[0], lv.s0[1], lv.s0[2]), make_int3(lv.ns[0], lv.ns[1], lv.ns[2]),
-                               keys, vals, ccount);
-            if (radix_sort_pairs(keys, vals, ktmp, vtmp, n, 21, scr, s) != GRAV_OK) {
+                               keys, ccount);
+            if (radix_sort_pairs(keys, vals, ktmp, vtmp, n, 15, scr, s) != GRAV_OK) {
                 ok = false;
                 break;
             }
@@ -1205,8 +1222,7 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             break;
         if ((st = dalloc(p, &p->d_le, (size_t)p->n_tbox * p->B * p->PS, false)) != GRAV_OK)
             break;
-        if (p->d.precision != GRAV_FP64 &&
-            (st = dalloc(p, &p->d_me32, (size_t)p->n_me * p->B * p->PS, false)) != GRAV_OK)
+        if (p->L >= 2 && (st = dalloc(p, &p->d_meg, (size_t)p->n_me * p->B * p->PS, false)) != GRAV_OK)
             break;
         if ((st = dalloc(p, &p->d_near, (size_t)p->M * p->B * 4, false)) != GRAV_OK)
             break;

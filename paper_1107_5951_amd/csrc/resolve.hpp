@@ -98,11 +98,25 @@ struct ResM2L {
         const int32_t *e = offs + (t.cls * kClassOffsets + i) * 4;
         return GemmTerm{e[3], e[0], e[1], e[2]};
     }
+    // position of the source expansion in the regathered (class-split) array
+    // the M2L reads, computed as the kernel does; a position that does not
+    // enumerate back to the same box is returned out of range
     __host__ __device__ int64_t src(const GemmTile &t, const GemmCol &c, const GemmTerm &m) const
     {
         const DevLev &lv = g->lev[t.level];
-        const int64_t s = dense_index(lv, c.x + m.dx, c.y + m.dy, c.z + m.dz);
-        return s < 0 ? -1 : (lv.me_off + s) * g->B + c.bm;
+        const int ax = c.x + m.dx, ay = c.y + m.dy, az = c.z + m.dz;
+        if (dense_index(lv, ax, ay, az) < 0)
+            return -1;
+        const int sc = t.cls ^ ((m.dx & 1) | ((m.dy & 1) << 1) | ((m.dz & 1) << 2));
+        int first[3], cnt[3];
+        const int64_t start = class_split(lv, sc, first, cnt);
+        const int64_t k = ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
+                          ((ax - first[0]) >> 1);
+        int xyz[3];
+        class_box((int)k, sc, lv.s0, lv.ns, xyz);
+        if (k < 0 || xyz[0] != ax || xyz[1] != ay || xyz[2] != az)
+            return INT64_MAX / 2;
+        return (lv.me_off + start + k) * g->B + c.bm;
     }
     __host__ __device__ int64_t out(const GemmTile &t, const GemmCol &c) const
     {
