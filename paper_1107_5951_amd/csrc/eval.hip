@@ -468,17 +468,12 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
             const int64_t pl = ((int64_t)(lz[c] + nb / 9) * py + (ly[c] + (nb / 3) % 3)) * px + (lx[c] + nb % 3);
             load4(blk + ((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm[c]) * 4, bb[c]);
         }
-        const T *ap = A + (((int64_t)nb * Qn + q) * RBn + rb0) * 256;
+        // rows past the last row block read the last one (in bounds) and
+        // are zeroed in compute: the load sequence has no branch
+        const T *ap = A + ((int64_t)nb * Qn + q) * RBn * 256;
 #pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            if (rvalid[r]) {
-                load_frags<T, 4>(ap + (int64_t)r * 256, lane, aa[r]);
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    aa[r][u] = (T)0;
-            }
-        }
+        for (int r = 0; r < RW; ++r)
+            load_frags<T, 4>(ap + (int64_t)min(rb0 + r, RBn - 1) * 256, lane, aa[r]);
     };
     auto compute = [&](const T (&bb)[CW][4], const T (&aa)[RW][4]) {
 #pragma unroll
@@ -488,32 +483,38 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
             for (int c = 0; c < CW; ++c)
                 bv[c] = cvalid[c] ? bb[c][u] : (T)0;
 #pragma unroll
-            for (int r = 0; r < RW; ++r)
+            for (int r = 0; r < RW; ++r) {
+                const T av = rvalid[r] ? aa[r][u] : (T)0;
 #pragma unroll
                 for (int c = 0; c < CW; ++c) {
                     if constexpr (sizeof(T) == 8)
-                        acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[r][u], bv[c], acc[c][r], 0, 0, 0);
+                        acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c][r], 0, 0, 0);
                     else
-                        acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[r][u], bv[c], acc[c][r], 0, 0, 0);
+                        acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c], acc[c][r], 0, 0, 0);
                 }
+            }
         }
     };
+    // each step issues the next chunk's loads between this chunk's matrix
+    // instructions (the index is clamped, so the last step reloads the last
+    // chunk instead of branching)
+    constexpr int NLD = CW + RW * 4 * (int)sizeof(T) / 16, NMF = 4 * RW * CW;
     if (i0 < i1) {
         T bA[CW][4], bB[CW][4];
         T aA[RW][4], aB[RW][4];
         loadc(i0, bA, aA);
+        __builtin_amdgcn_sched_barrier(0);
         for (int i = i0; i < i1; i += 2) {
-            if (i + 1 < i1)
-                loadc(i + 1, bB, aB);
-            __builtin_amdgcn_sched_barrier(0);
+            loadc(min(i + 1, i1 - 1), bB, aB);
             compute(bA, aA);
+            interleave_loads<NLD, NMF>();
             __builtin_amdgcn_sched_barrier(0);
-            if (i + 2 < i1)
-                loadc(i + 2, bA, aA);
-            __builtin_amdgcn_sched_barrier(0);
-            if (i + 1 < i1)
+            if (i + 1 < i1) {
+                loadc(min(i + 2, i1 - 1), bA, aA);
                 compute(bB, aB);
-            __builtin_amdgcn_sched_barrier(0);
+                interleave_loads<NLD, NMF>();
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
     // far field from the leaf's local expansion (FP64 in both precisions):

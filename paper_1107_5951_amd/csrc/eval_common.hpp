@@ -84,6 +84,26 @@ __device__ inline void load4(const double *p, double v[4])
     v[3] = b.y;
 }
 
+// Scheduling pattern for one software-pipelined step that issues NLD vector
+// loads (of the next step's operands) and NMF matrix instructions (of this
+// step): load, NMF / NLD instructions, load, ..., then the rest.  Without it
+// the compiler either issues every load in one block ahead of the matrix
+// instructions (the matrix pipe idles while the loads issue) or moves each
+// load next to its single use (no overlap at all).  Place it at the end of
+// the scheduling region that holds those loads and instructions.
+template <int NLD, int NMF>
+__device__ __forceinline__ void interleave_loads()
+{
+    constexpr int K = NMF / NLD > 0 ? NMF / NLD : 1;
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one VMEM read
+        __builtin_amdgcn_sched_group_barrier(0x008, K, 0);  // K MFMA
+    }
+    if constexpr (NMF > K * NLD)
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF - K * NLD, 0);
+}
+
 // Per-lane MFMA operand fragments in HBM, group-major: a set of E values per
 // lane is stored as [E / G][64 lanes][G] with G = 16 bytes / sizeof(T), so
 // every 16-byte vector load of a wave reads one contiguous kilobyte (eight

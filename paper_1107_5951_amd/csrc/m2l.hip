@@ -144,12 +144,19 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         };
         if constexpr (NSET == 2) {
             load(0, 0);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
-                if (q + 1 < RB)
+                if (q + 1 < RB) {
+                    // the loads of chunk q + 1 issue one by one between this
+                    // chunk's instructions, so the matrix pipe keeps running
+                    // while the wave feeds the memory pipeline
                     load(q + 1, (q + 1) & 1);
-                __builtin_amdgcn_sched_barrier(0);
-                compute(q & 1);
+                    compute(q & 1);
+                    interleave_loads<NC + 4 * RB * (int)sizeof(T) / 16, 4 * RB * NC>();
+                } else {
+                    compute(q & 1);
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
