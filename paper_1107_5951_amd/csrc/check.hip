@@ -6,8 +6,10 @@
 // checking every expansion, matrix, target-range and cell index against the
 // size of the buffer it addresses, and that no two columns of one stage
 // write the same expansion.  No compute kernel is launched.
+#include <algorithm>
 #include <cstdio>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "resolve.hpp"
@@ -114,6 +116,7 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
     for (int k = 0; k < TK_COUNT; ++k)
         for (int l = 0; l <= kMaxLevels; ++l)
             ntile = std::max<int64_t>(ntile, p->tiles[k][l].off + p->tiles[k][l].n);
+    ntile = std::max<int64_t>(ntile, p->m2l_order.off + p->m2l_order.n);
     int64_t ntb = 0;
     const int lo = L >= 2 ? 2 : L;
     for (int l = lo; l <= L; ++l)
@@ -220,6 +223,26 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
         }
     }
 
+    if (L >= 2 && ck.ok) {
+        // the M2L launch order is a permutation of its (tile, split) units
+        const TileRange &r = p->tiles[TK_M2L][0], &o = p->m2l_order;
+        if (o.n != r.n) {
+            ck.fail("m2l", "launch order has the wrong unit count", o.n, r.n);
+        } else {
+            auto key = [](const GemmTile &t) {
+                return std::make_tuple(t.level, t.cls, t.col0, t.ncol, t.pad);
+            };
+            std::vector<std::tuple<int, int, int64_t, int, int>> a, b;
+            for (int64_t i = 0; i < r.n; ++i) {
+                a.push_back(key(tiles[r.off + i]));
+                b.push_back(key(tiles[o.off + i]));
+            }
+            std::sort(a.begin(), a.end());
+            std::sort(b.begin(), b.end());
+            if (a != b)
+                ck.fail("m2l", "launch order is not a permutation of the units", o.n, r.n);
+        }
+    }
     if (L >= 2 && ck.ok) {
         const int64_t xme = p->n_me * p->B, xle = p->n_tbox * p->B;
         std::vector<char> w;

@@ -13,6 +13,17 @@ namespace grav {
 
 constexpr int kMaxP = 16;
 constexpr int kMaxLevels = 10;
+
+// Forward M2L: 16-column blocks per wave (1, 2 or 4) for the FP32 and FP64
+// kernels: each A fragment feeds this many instructions; a workgroup holds
+// 4 / NC waves (64 columns).  FP64 keeps one block: its accumulators for two
+// would leave one wave per SIMD.
+#ifndef GRAV_M2L_NC32
+#define GRAV_M2L_NC32 2
+#endif
+#ifndef GRAV_M2L_NC64
+#define GRAV_M2L_NC64 1
+#endif
 constexpr int kNumOffsets = 316;   // M2L offsets d with 2 <= |d|_inf <= 3
 constexpr int kClassOffsets = 189; // offsets valid for one child-parity class
 constexpr int kTileCols = 64;      // columns (box, model) per M2L tile
@@ -80,6 +91,9 @@ struct Plan {
     // split[k] times); slot l >= 2 = level l's tiles in the unrepeated numbering
     TileRange tiles[TK_COUNT][kMaxLevels + 1];
     int split[TK_COUNT] = {1, 1};
+    // the forward M2L's (tile, split) units again, longest first (the launch
+    // order of its workgroups; offset into d_tiles)
+    TileRange m2l_order;
     // near field of voxel-centre targets by lattice matrices (b <= 4)
     bool lat_near = false;
     int lat_RB = 0, lat_Q = 0;                     // row blocks (4 b^3 / 16); chunks of four k steps

@@ -7,16 +7,7 @@
 #ifndef GRAV_M2L_DB_BYTES
 #define GRAV_M2L_DB_BYTES 128
 #endif
-// 16-column blocks per wave (1, 2 or 4) for the FP32 and FP64 kernels: each
-// A fragment feeds this many instructions; a workgroup holds 4 / NC waves
-// (64 columns).  FP64 keeps one block: its accumulators for two would leave
-// one wave per SIMD.
-#ifndef GRAV_M2L_NC32
-#define GRAV_M2L_NC32 2
-#endif
-#ifndef GRAV_M2L_NC64
-#define GRAV_M2L_NC64 1
-#endif
+
 
 namespace grav {
 
@@ -198,7 +189,7 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
 template <typename T>
 grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
 {
-    const TileRange &r = p->tiles[TK_M2L][0];
+    const TileRange &r = p->m2l_order;  // the units, longest first
     if (r.n == 0)
         return GRAV_OK;
     constexpr int NC = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;  // column blocks per wave

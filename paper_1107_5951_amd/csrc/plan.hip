@@ -590,6 +590,79 @@ grav_status build_tiles(Plan *p)
         r.off = off;
         r.n *= S;
     }
+    // Launch order of the forward M2L: its (tile, split) units sorted by
+    // their cost, longest first, so that the last workgroups to start are
+    // short ones (the device dispatches in index order, so this is a
+    // longest-processing-time schedule).  Cost of a unit = the largest number
+    // of offsets of its split that one of its waves computes (an offset is
+    // skipped only when no column of the wave has a source box there).
+    p->m2l_order = TileRange{};
+    {
+        const TileRange &r = p->tiles[TK_M2L][0];
+        if (r.n > 0) {
+            const int ncw = 16 * (p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32);
+            const int S = p->split[TK_M2L];
+            std::vector<int> alloffs;
+            std::vector<int32_t> fwd, rev;
+            offsets_tables(alloffs, fwd, rev);
+            std::vector<std::vector<uint32_t>> key(L + 1);
+            std::vector<std::vector<int32_t>> ord(L + 1);
+            for (int l = 2; l <= L; ++l) {
+                const int64_t n = p->lev[l].n_tgt;
+                key[l].resize(n);
+                ord[l].resize(n);
+                if (n > 0) {
+                    GRAV_HIP(hipMemcpyAsync(key[l].data(), p->d_tkey + p->tbox_off[l], 4 * n, hipMemcpyDeviceToHost,
+                                            p->bs));
+                    GRAV_HIP(hipMemcpyAsync(ord[l].data(), p->d_torder + p->tbox_off[l], 4 * n,
+                                            hipMemcpyDeviceToHost, p->bs));
+                }
+            }
+            GRAV_HIP(hipStreamSynchronize(p->bs));
+            std::vector<int> cost(r.n);
+            std::vector<char> hit;
+            for (int64_t u = 0; u < r.n; ++u) {
+                const GemmTile &t = split[r.off + u];
+                const LevelInfo &lv = p->lev[t.level];
+                const int o0 = t.pad * kClassOffsets / S, o1 = (t.pad + 1) * kClassOffsets / S;
+                int worst = 0;
+                for (int w0 = 0; w0 < t.ncol; w0 += ncw) {
+                    hit.assign(o1 - o0, 0);
+                    for (int cl = w0; cl < std::min(t.ncol, w0 + ncw); ++cl) {
+                        const int64_t col = t.col0 + cl;
+                        const int32_t box = ord[t.level][lv.class_start[t.cls] + col / B];
+                        const uint32_t k = key[t.level][box];
+                        const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+                        for (int o = o0; o < o1; ++o) {
+                            const int32_t *e = &fwd[((size_t)t.cls * kClassOffsets + o) * 4];
+                            bool in = true;
+                            for (int a = 0; a < 3; ++a) {
+                                const int s = c[a] + e[a] - lv.s0[a];
+                                in = in && s >= 0 && s < lv.ns[a];
+                            }
+                            hit[o - o0] |= in;
+                        }
+                    }
+                    int nh = 0;
+                    for (char h : hit)
+                        nh += h;
+                    worst = std::max(worst, nh);
+                }
+                cost[u] = worst;
+            }
+            std::vector<int64_t> perm(r.n);
+            for (int64_t u = 0; u < r.n; ++u)
+                perm[u] = u;
+            std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+            p->m2l_order.off = (int64_t)split.size();
+            p->m2l_order.n = r.n;
+            split.reserve(split.size() + r.n);
+            for (int64_t u = 0; u < r.n; ++u) {
+                const GemmTile t = split[r.off + perm[u]];
+                split.push_back(t);
+            }
+        }
+    }
     if (!split.empty())
         GRAV_CHECK(upload(p, &p->d_tiles, split));
     return GRAV_OK;
