@@ -181,8 +181,9 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
 
 // The multipole expansions regathered for the M2L's B operand, in the
 // M2L's element type.  Per level, boxes are ordered by parity class (x
-// fastest within a class, see class_split) and the coefficients chunk-major:
-//   out[level][q][kr][pos * B + model][u],  coefficient kr * PS/4 + 4 q + u.
+// fastest within a class, see class_split) and the coefficients chunk-major
+// in the M2L's interleaved contraction order:
+//   out[level][q][kr][pos * B + model][u],  coefficient 4 (4 q + u) + kr.
 // The source boxes that one wave's 16 columns read at one interaction offset
 // are boxes of a single class with consecutive x, so each B fragment load
 // of the M2L covers a few contiguous runs instead of 64 scattered lines.
@@ -211,11 +212,11 @@ __global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, 
                         ((ax - first[0]) >> 1);
     const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
     const int q = plane / 4, kr = plane % 4;
-    const double *src = me + col * g.PS + kr * NP + 4 * q;
+    const double *src = me + col * g.PS + 16 * q + kr;
     T *dst = out + lv.me_off * g.B * g.PS + ((int64_t)plane * nB + pos * g.B + bm) * 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-        dst[u] = (T)src[u];
+        dst[u] = (T)src[4 * u];
 }
 template __global__ void k_me_gather<double>(DevGeom, const double *, int64_t, double *);
 template __global__ void k_me_gather<float>(DevGeom, const double *, int64_t, float *);
@@ -393,6 +394,21 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
     blk[((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm) * 4 + u] = (T)r;
 }
 
+// Lattice near-field tile per workgroup: GRAV_NEAR_RW row blocks x
+// GRAV_NEAR_CW column blocks of 16; chunks per software-pipeline step.
+#ifndef GRAV_NEAR_RW
+#define GRAV_NEAR_RW 2
+#endif
+#ifndef GRAV_NEAR_CW
+#define GRAV_NEAR_CW 2
+#endif
+#ifndef GRAV_NEAR_DEPTH32
+#define GRAV_NEAR_DEPTH32 3
+#endif
+#ifndef GRAV_NEAR_DEPTH64
+#define GRAV_NEAR_DEPTH64 1
+#endif
+
 // --------------------------------------------------------------------------
 // The voxel-centre targets, fused: near field + far field + combine.
 // Targets and Gauss points both sit on the lattice, so the near field of a
@@ -475,13 +491,13 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
         for (int r = 0; r < RW; ++r)
             load_frags<T, 4>(ap + (int64_t)min(rb0 + r, RBn - 1) * 256, lane, aa[r]);
     };
-    auto compute = [&](const T (&bb)[CW][4], const T (&aa)[RW][4]) {
+    auto compute = [&](const T (&bb)[CW][4], const T (&aa)[RW][4], bool live) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             T bv[CW];
 #pragma unroll
             for (int c = 0; c < CW; ++c)
-                bv[c] = cvalid[c] ? bb[c][u] : (T)0;
+                bv[c] = (cvalid[c] && live) ? bb[c][u] : (T)0;
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 const T av = rvalid[r] ? aa[r][u] : (T)0;
@@ -495,23 +511,37 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
             }
         }
     };
-    // each step issues the next chunk's loads between this chunk's matrix
-    // instructions (the index is clamped, so the last step reloads the last
-    // chunk instead of branching)
-    constexpr int NLD = CW + RW * 4 * (int)sizeof(T) / 16, NMF = 4 * RW * CW;
-    if (i0 < i1) {
-        T bA[CW][4], bB[CW][4];
-        T aA[RW][4], aB[RW][4];
-        loadc(i0, bA, aA);
+    // Software pipeline over steps of D chunks: each step issues the loads of
+    // the next step one by one between its own matrix instructions, so a
+    // load has D chunks of instructions (and the other waves' work) to
+    // arrive.  Chunk indices past the wave's range are clamped (in bounds)
+    // and their products zeroed: the load sequence has no branch.
+    constexpr int D = sizeof(T) == 8 ? GRAV_NEAR_DEPTH64 : GRAV_NEAR_DEPTH32;
+    constexpr int NLD = D * (CW + RW * 4 * (int)sizeof(T) / 16), NMF = D * 4 * RW * CW;
+    auto load_step = [&](int st, T (&bb)[D][CW][4], T (&aa)[D][RW][4]) {
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            loadc(min(i0 + st * D + j, i1 - 1), bb[j], aa[j]);
+    };
+    auto compute_step = [&](int st, const T (&bb)[D][CW][4], const T (&aa)[D][RW][4]) {
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            compute(bb[j], aa[j], i0 + st * D + j < i1);
+    };
+    const int nst = (i1 - i0 + D - 1) / D;
+    if (nst > 0) {
+        T bA[D][CW][4], bB[D][CW][4];
+        T aA[D][RW][4], aB[D][RW][4];
+        load_step(0, bA, aA);
         __builtin_amdgcn_sched_barrier(0);
-        for (int i = i0; i < i1; i += 2) {
-            loadc(min(i + 1, i1 - 1), bB, aB);
-            compute(bA, aA);
+        for (int st = 0; st < nst; st += 2) {
+            load_step(min(st + 1, nst - 1), bB, aB);
+            compute_step(st, bA, aA);
             interleave_loads<NLD, NMF>();
             __builtin_amdgcn_sched_barrier(0);
-            if (i + 1 < i1) {
-                loadc(min(i + 2, i1 - 1), bA, aA);
-                compute(bB, aB);
+            if (st + 1 < nst) {
+                load_step(min(st + 2, nst - 1), bA, aA);
+                compute_step(st + 1, bB, aB);
                 interleave_loads<NLD, NMF>();
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -794,15 +824,6 @@ static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }
-
-// Lattice near-field tile per workgroup: GRAV_NEAR_RW row blocks x
-// GRAV_NEAR_CW column blocks of 16.
-#ifndef GRAV_NEAR_RW
-#define GRAV_NEAR_RW 2
-#endif
-#ifndef GRAV_NEAR_CW
-#define GRAV_NEAR_CW 2
-#endif
 
 static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho, double *out, hipStream_t s)
 {

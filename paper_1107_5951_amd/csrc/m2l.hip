@@ -21,18 +21,18 @@ namespace grav {
 // A fragment loaded feeds NC instructions.
 //
 // Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
-// instruction take coefficient c = kr * PS/4 + ks (ks = 0 .. PS/4 - 1), so
-// a lane's B values for four consecutive k steps are four consecutive
-// coefficients of one expansion (one aligned vector load from the
-// regathered, class-split expansions: the 16 source boxes of a wave at one
-// offset are one class, consecutive in x, so the load covers a few
-// contiguous runs), and the A
+// instruction take coefficient c = 4 ks + kr, so the coefficients c >= p^2
+// of the padding fill whole trailing k steps, which are skipped (KSV = the
+// k steps that hold coefficients).  A lane's B values for four consecutive
+// k steps are one aligned vector load from the regathered, class-split
+// expansions (the 16 source boxes of a wave at one offset are one class,
+// consecutive in x, so the load covers a few contiguous runs), and the A
 // fragments of four k steps and all row blocks form one group-major set
 // per (d, q) (value u * RB + rb, ks = 4q + u), read with 4 RB / G 16-byte
 // loads that each cover a contiguous kilobyte.  Padding coefficients
 // (c >= p^2) are zero in the expansions.
 // --------------------------------------------------------------------------
-template <int RB, int NC, typename T>
+template <int RB, int KSV, int NC, typename T>
 __global__ void __launch_bounds__(256 / NC)
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
       const int32_t *class_off, const T *K, const T *me, double *le, T *part, int S, int64_t part_stride)
@@ -70,6 +70,7 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
     const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
     const int kr = lane >> 4;
     constexpr int PS = 16 * RB;
+    constexpr int QC = (KSV + 3) / 4;  // chunks of four k steps holding coefficients
     // regathered expansions of this level: plane (q, kr) holds four
     // coefficients of every (class-split box, model), plane stride pstr
     const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
@@ -113,9 +114,11 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
                 load4(mp[c] + (int64_t)q * 4 * pstr, bb[set][c]);
             load_frags<T, 4 * RB>(kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
         };
-        auto compute = [&](int set) {
+        auto compute = [&](int q, int set) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
+                if (4 * q + u >= KSV)
+                    break;  // k steps past the last coefficient are all zero
                 T bv[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
@@ -137,24 +140,25 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
             load(0, 0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                if (q + 1 < RB) {
+            for (int q = 0; q < QC; ++q) {
+                if (q + 1 < QC) {
                     // the loads of chunk q + 1 issue one by one between this
                     // chunk's instructions, so the matrix pipe keeps running
                     // while the wave feeds the memory pipeline
                     load(q + 1, (q + 1) & 1);
-                    compute(q & 1);
+                    compute(q, q & 1);
                     interleave_loads<NC + 4 * RB * (int)sizeof(T) / 16, 4 * RB * NC>();
                 } else {
-                    compute(q & 1);
+                    compute(q, q & 1);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
-            for (int q = 0; q < RB; ++q) {
+#pragma unroll
+            for (int q = 0; q < QC; ++q) {
                 load(q, 0);
                 __builtin_amdgcn_sched_barrier(0);
-                compute(0);
+                compute(q, 0);
             }
         }
     }
@@ -198,23 +202,28 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
     T *part = reinterpret_cast<T *>(p->d_part);  // sized for FP64 partials
     const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see k_me_gather)
-#define M2L_CASE(R)                                                                             \
-    case R:                                                                                     \
-        hipLaunchKernelGGL((k_m2l<R, NC, T>), grid, blk, 0, s, g, (const GemmTile *)(p->d_tiles + r.off), \
-                           (const uint32_t *)p->d_tkey, (const int32_t *)p->d_torder,           \
-                           (const int32_t *)p->d_class_off, K, me_in, p->d_le, part, S, pstride); \
+#define M2L_CASE(P)                                                                             \
+    case P:                                                                                     \
+        hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T>), grid, blk, 0, s, g,  \
+                           (const GemmTile *)(p->d_tiles + r.off), (const uint32_t *)p->d_tkey, \
+                           (const int32_t *)p->d_torder, (const int32_t *)p->d_class_off, K, me_in, \
+                           p->d_le, part, S, pstride);                                          \
         break;
-    switch (p->PS / 16) {
+    switch (p->P) {
         M2L_CASE(1)
         M2L_CASE(2)
         M2L_CASE(3)
         M2L_CASE(4)
+        M2L_CASE(5)
         M2L_CASE(6)
         M2L_CASE(7)
         M2L_CASE(8)
         M2L_CASE(9)
+        M2L_CASE(10)
         M2L_CASE(11)
+        M2L_CASE(12)
         M2L_CASE(13)
+        M2L_CASE(14)
         M2L_CASE(15)
         M2L_CASE(16)
     default:
