@@ -439,7 +439,9 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
     using dvec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     __shared__ double red[4][CW * RW * 4][64];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave-uniform (scalar registers): everything that depends only on the
+    // chunk index below is scalar arithmetic
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t cg = blockIdx.x / nrg;
     const int rb0 = (int)(blockIdx.x % nrg) * RW;
     const DevLev &lv = g.lev[g.L];
@@ -477,13 +479,19 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
     // in flight while this chunk's instructions run
     const int NI = 27 * Qn;
     const int i0 = wave * NI / 4, i1 = (wave + 1) * NI / 4;
-    auto loadc = [&](int i, T (&bb)[CW][4], T (&aa)[RW][4]) {
-        const int nb = i / Qn, q = i % Qn;
+    // per lane: its column's density block at neighbour offset (0, 0, 0)
+    // (padded coordinates) and sub-row kr; a chunk adds a uniform offset
+    const T *bbase[CW];
 #pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            const int64_t pl = ((int64_t)(lz[c] + nb / 9) * py + (ly[c] + (nb / 3) % 3)) * px + (lx[c] + nb % 3);
-            load4(blk + ((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm[c]) * 4, bb[c]);
-        }
+    for (int c = 0; c < CW; ++c)
+        bbase[c] = blk + ((int64_t)kr * nplB + (((int64_t)lz[c] * py + ly[c]) * px + lx[c]) * g.B + bm[c]) * 4;
+    auto loadc = [&](int i, T (&bb)[CW][4], T (&aa)[RW][4]) {
+        const int nb = i / Qn, q = i - nb * Qn;
+        const int64_t nboff = ((int64_t)(nb / 9) * py + (nb / 3) % 3) * px + nb % 3;
+        const int64_t boff = ((int64_t)q * 4 * nplB + nboff * g.B) * 4;
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+            load4(bbase[c] + boff, bb[c]);
         // rows past the last row block read the last one (in bounds) and
         // are zeroed in compute: the load sequence has no branch
         const T *ap = A + ((int64_t)nb * Qn + q) * RBn * 256;
