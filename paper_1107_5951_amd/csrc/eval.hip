@@ -432,8 +432,8 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
 // --------------------------------------------------------------------------
 template <int RW, int CW, typename T>
 __global__ void __launch_bounds__(256)
-k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, const double *Lm,
-           const int32_t *tmap, const double *le, int64_t npts, int nrg, double *out)
+k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *ctab, int RBn, int Qn,
+           const double *Lm, const int32_t *tmap, const double *le, int64_t npts, int nrg, double *out)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     using dvec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
@@ -485,58 +485,51 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
 #pragma unroll
     for (int c = 0; c < CW; ++c)
         bbase[c] = blk + ((int64_t)kr * nplB + (((int64_t)lz[c] * py + ly[c]) * px + lx[c]) * g.B + bm[c]) * 4;
+    // Chunk i's offsets come from the plan's table (scalar loads).  Rows past
+    // the last row block read the last one and columns past the last column
+    // read leaf 0 (both in bounds): an output element depends only on its
+    // own row and column, and those are never written, so nothing needs
+    // zeroing.
     auto loadc = [&](int i, T (&bb)[CW][4], T (&aa)[RW][4]) {
-        const int nb = i / Qn, q = i - nb * Qn;
-        const int64_t nboff = ((int64_t)(nb / 9) * py + (nb / 3) % 3) * px + nb % 3;
-        const int64_t boff = ((int64_t)q * 4 * nplB + nboff * g.B) * 4;
+        const int64_t boff = ctab[2 * i], aoff = ctab[2 * i + 1];
 #pragma unroll
         for (int c = 0; c < CW; ++c)
             load4(bbase[c] + boff, bb[c]);
-        // rows past the last row block read the last one (in bounds) and
-        // are zeroed in compute: the load sequence has no branch
-        const T *ap = A + ((int64_t)nb * Qn + q) * RBn * 256;
+        const T *ap = A + aoff;
 #pragma unroll
         for (int r = 0; r < RW; ++r)
             load_frags<T, 4>(ap + (int64_t)min(rb0 + r, RBn - 1) * 256, lane, aa[r]);
     };
-    auto compute = [&](const T (&bb)[CW][4], const T (&aa)[RW][4], bool live) {
+    auto compute = [&](const T (&bb)[CW][4], const T (&aa)[RW][4]) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            T bv[CW];
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int c = 0; c < CW; ++c)
-                bv[c] = (cvalid[c] && live) ? bb[c][u] : (T)0;
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const T av = rvalid[r] ? aa[r][u] : (T)0;
+            for (int r = 0; r < RW; ++r)
 #pragma unroll
                 for (int c = 0; c < CW; ++c) {
                     if constexpr (sizeof(T) == 8)
-                        acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c][r], 0, 0, 0);
+                        acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[r][u], bb[c][u], acc[c][r], 0, 0, 0);
                     else
-                        acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c], acc[c][r], 0, 0, 0);
+                        acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[r][u], bb[c][u], acc[c][r], 0, 0, 0);
                 }
-            }
-        }
     };
     // Software pipeline over steps of D chunks: each step issues the loads of
     // the next step one by one between its own matrix instructions, so a
     // load has D chunks of instructions (and the other waves' work) to
-    // arrive.  Chunk indices past the wave's range are clamped (in bounds)
-    // and their products zeroed: the load sequence has no branch.
+    // arrive.  The chunks past the last whole step run unpipelined.
     constexpr int D = sizeof(T) == 8 ? GRAV_NEAR_DEPTH64 : GRAV_NEAR_DEPTH32;
     constexpr int NLD = D * (CW + RW * 4 * (int)sizeof(T) / 16), NMF = D * 4 * RW * CW;
     auto load_step = [&](int st, T (&bb)[D][CW][4], T (&aa)[D][RW][4]) {
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            loadc(min(i0 + st * D + j, i1 - 1), bb[j], aa[j]);
+            loadc(i0 + st * D + j, bb[j], aa[j]);
     };
-    auto compute_step = [&](int st, const T (&bb)[D][CW][4], const T (&aa)[D][RW][4]) {
+    auto compute_step = [&](const T (&bb)[D][CW][4], const T (&aa)[D][RW][4]) {
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            compute(bb[j], aa[j], i0 + st * D + j < i1);
+            compute(bb[j], aa[j]);
     };
-    const int nst = (i1 - i0 + D - 1) / D;
+    const int nst = (i1 - i0) / D;
     if (nst > 0) {
         T bA[D][CW][4], bB[D][CW][4];
         T aA[D][RW][4], aB[D][RW][4];
@@ -544,16 +537,21 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBn, int Qn, c
         __builtin_amdgcn_sched_barrier(0);
         for (int st = 0; st < nst; st += 2) {
             load_step(min(st + 1, nst - 1), bB, aB);
-            compute_step(st, bA, aA);
+            compute_step(bA, aA);
             interleave_loads<NLD, NMF>();
             __builtin_amdgcn_sched_barrier(0);
             if (st + 1 < nst) {
                 load_step(min(st + 2, nst - 1), bA, aA);
-                compute_step(st + 1, bB, aB);
+                compute_step(bB, aB);
                 interleave_loads<NLD, NMF>();
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+    }
+    for (int i = i0 + nst * D; i < i1; ++i) {
+        T bb[CW][4], aa[RW][4];
+        loadc(i, bb, aa);
+        compute(bb, aa);
     }
     // far field from the leaf's local expansion (FP64 in both precisions):
     // chunks q = wave, wave + 4, ...
@@ -859,11 +857,11 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
     const int64_t npts = p->d.n_points;
     if (f64)
         hipLaunchKernelGGL((k_near_lat<RW, CW, double>), grid, blk, 0, s, g, (const double *)p->d_rho_blk, nplB,
-                           (const double *)p->d_tn64, RBn, Qn, (const double *)p->d_tl2p,
+                           (const double *)p->d_tn64, (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,
                            (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
     else
         hipLaunchKernelGGL((k_near_lat<RW, CW, float>), grid, blk, 0, s, g, (const float *)p->d_rho_blk, nplB,
-                           (const float *)p->d_tn32, RBn, Qn, (const double *)p->d_tl2p,
+                           (const float *)p->d_tn32, (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,
                            (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;

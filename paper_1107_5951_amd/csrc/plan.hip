@@ -285,7 +285,7 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg,
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg, p->d_lat_tab,
                     p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
@@ -807,6 +807,19 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
         GRAV_CHECK(dalloc(p, &p->d_rho_blk, n, false));
         GRAV_HIP(hipMemsetAsync(p->d_rho_blk, 0, sizeof(double) * n, p->bs));
         GRAV_HIP(hipStreamSynchronize(p->bs));
+        // per near chunk i = (neighbour nb, four k steps q): element offsets
+        // of its density fragment (from a column's block at nb = (0, 0, 0))
+        // and of its operator fragments; the kernel reads them with scalar
+        // loads instead of recomputing them
+        const int64_t px = lv.ns[0] + 2, py = lv.ns[1] + 2, nplB = px * py * (lv.ns[2] + 2) * p->B;
+        std::vector<int64_t> tab((size_t)27 * Qn * 2);
+        for (int nb = 0; nb < 27; ++nb)
+            for (int q = 0; q < Qn; ++q) {
+                const int64_t nboff = ((int64_t)(nb / 9) * py + (nb / 3) % 3) * px + nb % 3;
+                tab[((size_t)nb * Qn + q) * 2 + 0] = ((int64_t)q * 4 * nplB + nboff * p->B) * 4;
+                tab[((size_t)nb * Qn + q) * 2 + 1] = ((int64_t)nb * Qn + q) * RBn * 256;
+            }
+        GRAV_CHECK(upload(p, &p->d_lat_tab, tab));
     }
     if (f64) {
         GRAV_CHECK(upload(p, &p->d_tn64, sw));
