@@ -593,12 +593,12 @@ grav_status build_tiles(Plan *p)
         r.off = off;
         r.n *= S;
     }
-    // Launch order of the forward M2L: its (tile, split) units sorted by
-    // their cost, longest first, so that the last workgroups to start are
-    // short ones (the device dispatches in index order, so this is a
-    // longest-processing-time schedule).  Cost of a unit = the largest number
-    // of offsets of its split that one of its waves computes (an offset is
-    // skipped only when no column of the wave has a source box there).
+    // Launch order of the forward M2L's (tile, split) units.  Cost of a unit
+    // = the largest number of offsets of its split that one of its waves
+    // computes (an offset is skipped only when no column of the wave has a
+    // source box there).  Long units start first, so that the last
+    // workgroups to start are short ones (the device dispatches in index
+    // order: a longest-processing-time schedule).
     p->m2l_order = TileRange{};
     {
         const TileRange &r = p->tiles[TK_M2L][0];
@@ -653,17 +653,52 @@ grav_status build_tiles(Plan *p)
                 }
                 cost[u] = worst;
             }
-            std::vector<int64_t> perm(r.n);
-            for (int64_t u = 0; u < r.n; ++u)
-                perm[u] = u;
-            std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-            p->m2l_order.off = (int64_t)split.size();
-            p->m2l_order.n = r.n;
-            split.reserve(split.size() + r.n);
+            // The device hands workgroup i to XCD i mod 8, and each XCD has
+            // its own L2.  Units of one (class, split) combination read the
+            // same operator matrices (they do not depend on the level), so
+            // whole combinations go to one XCD: its concurrent workgroups
+            // then share a few matrices instead of all 316.  Combinations
+            // are dealt to the XCDs longest first onto the least loaded one;
+            // each XCD runs its combinations longest first, units within a
+            // combination longest first.  Shorter XCD lists are padded with
+            // empty units (no columns: they compute and write nothing).
+            constexpr int kXcd = 8;
+            const int ncombo = 8 * S;
+            std::vector<std::vector<int64_t>> units(ncombo);
+            std::vector<int64_t> ccost(ncombo, 0);
             for (int64_t u = 0; u < r.n; ++u) {
-                const GemmTile t = split[r.off + perm[u]];
-                split.push_back(t);
+                const GemmTile &t = split[r.off + u];
+                const int cb = t.cls * S + t.pad;
+                units[cb].push_back(u);
+                ccost[cb] += cost[u];
             }
+            std::vector<int> corder(ncombo);
+            for (int c = 0; c < ncombo; ++c)
+                corder[c] = c;
+            std::stable_sort(corder.begin(), corder.end(), [&](int a, int b) { return ccost[a] > ccost[b]; });
+            std::vector<std::vector<int64_t>> xl(kXcd);
+            std::vector<int64_t> xload(kXcd, 0);
+            for (int c : corder) {
+                if (units[c].empty())
+                    continue;
+                const int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
+                std::stable_sort(units[c].begin(), units[c].end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+                xl[x].insert(xl[x].end(), units[c].begin(), units[c].end());
+                xload[x] += ccost[c];
+            }
+            size_t len = 0;
+            for (const auto &v : xl)
+                len = std::max(len, v.size());
+            p->m2l_order.off = (int64_t)split.size();
+            p->m2l_order.n = (int64_t)len * kXcd;
+            split.reserve(split.size() + len * kXcd);
+            GemmTile empty = split[r.off];
+            empty.ncol = 0;
+            for (size_t k = 0; k < len; ++k)
+                for (int x = 0; x < kXcd; ++x) {
+                    const GemmTile t = k < xl[x].size() ? split[r.off + xl[x][k]] : empty;
+                    split.push_back(t);
+                }
         }
     }
     if (!split.empty())
