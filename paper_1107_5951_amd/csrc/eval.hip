@@ -12,40 +12,55 @@ namespace grav {
 // --------------------------------------------------------------------------
 // P2M on the lattice: the scaled ME of a leaf is a fixed linear map of its
 // b^3 cell densities (all leaves share the point layout), ME = Pm * rho_leaf.
-// One workgroup per source leaf; thread t produces coefficient t.
+// A workgroup takes LB consecutive columns (leaf, model): their densities
+// are staged in LDS, and thread t produces coefficient t of all LB columns,
+// so each operator entry it loads feeds LB multiply-adds.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const double *pm,
-                                             double *me)
+template <int LB>
+__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const double *pm, double *me)
 {
-    extern __shared__ double sh[];
+    extern __shared__ double sh[];  // [LB][b^3]
     const DevLev &lv = g.lev[g.L];
-    const int64_t leaf = blockIdx.x;
-    const int lx = (int)(leaf % lv.ns[0]);
-    const int ly = (int)((leaf / lv.ns[0]) % lv.ns[1]);
-    const int lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
-    // first cell of the leaf (cell coordinates)
-    const int vx0 = (lv.s0[0] + lx - g.shift[0]) * g.b;
-    const int vy0 = (lv.s0[1] + ly - g.shift[1]) * g.b;
-    const int vz0 = (lv.s0[2] + lz - g.shift[2]) * g.b;
-    const int b3 = g.b * g.b * g.b;
+    const int b = g.b, b3 = b * b * b;
+    const int64_t ncol = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
+    const int64_t col0 = (int64_t)blockIdx.x * LB;
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    for (int bm = 0; bm < g.B; ++bm) {
-        for (int v = threadIdx.x; v < b3; v += blockDim.x) {
-            const int ix = vx0 + v % g.b, iy = vy0 + (v / g.b) % g.b, iz = vz0 + v / (g.b * g.b);
-            double r = 0.0;
+    for (int e = threadIdx.x; e < LB * b3; e += blockDim.x) {
+        const int l = e / b3, v = e - l * b3;
+        const int64_t col = col0 + l;
+        double r = 0.0;
+        if (col < ncol) {
+            const int64_t leaf = col / g.B;
+            const int bm = (int)(col - leaf * g.B);
+            const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
+                      lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+            const int ix = (lv.s0[0] + lx - g.shift[0]) * b + v % b;
+            const int iy = (lv.s0[1] + ly - g.shift[1]) * b + (v / b) % b;
+            const int iz = (lv.s0[2] + lz - g.shift[2]) * b + v / (b * b);
             if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
                 r = rho[bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
-            sh[v] = r;
         }
-        __syncthreads();
-        for (int t = threadIdx.x; t < g.PS; t += blockDim.x) {
-            double acc = 0.0;
-            for (int v = 0; v < b3; ++v)
-                acc += pm[(int64_t)v * g.PS + t] * sh[v];
-            me[((lv.me_off + leaf) * g.B + bm) * g.PS + t] = acc;
-        }
-        __syncthreads();
+        sh[e] = r;
     }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= g.PS)
+        return;
+    double acc[LB];
+#pragma unroll
+    for (int l = 0; l < LB; ++l)
+        acc[l] = 0.0;
+#pragma unroll 4
+    for (int v = 0; v < b3; ++v) {
+        const double w = pm[(int64_t)v * g.PS + t];
+#pragma unroll
+        for (int l = 0; l < LB; ++l)
+            acc[l] += w * sh[l * b3 + v];
+    }
+#pragma unroll
+    for (int l = 0; l < LB; ++l)
+        if (col0 + l < ncol)
+            me[(lv.me_off * g.B + col0 + l) * g.PS + t] = acc[l];
 }
 
 // --------------------------------------------------------------------------
@@ -128,6 +143,12 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
 // level l, grouped by child octant c (the M2L tiles of the level: same
 // columns, one matrix per tile).  Four waves of 16 columns per workgroup.
 // --------------------------------------------------------------------------
+// L2L on MFMA (FP64): LE[child] += T_c LE[parent] for the target boxes of
+// level l, grouped by child octant c (the M2L tiles of the level: same
+// columns, one matrix per tile).  A workgroup takes one tile (four waves of
+// 16 columns) and one 16-row block (blockIdx.y), so a level has RB times
+// as many workgroups as tiles.
+// --------------------------------------------------------------------------
 template <int RB>
 __global__ void __launch_bounds__(256)
 k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, const int32_t *torder,
@@ -136,6 +157,7 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     constexpr int PS = 16 * RB;
     const GemmTile tile = tiles[(int64_t)blockIdx.x * stride];
+    const int rb = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const DevLev &lv = g.lev[tile.level];
@@ -149,34 +171,39 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
         box = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
         par = tparent[lv.tbox_off + box];
     }
-    vec4 acc[RB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-        acc[rb] = vec4{0, 0, 0, 0};
+    vec4 acc = vec4{0, 0, 0, 0};
     const int kr = lane >> 4;
+    // B: column (lane % 16) of the parent LE, contraction order kr * PS/4 + ks
     const double2 *bp = (const double2 *)(le + (cvalid ? ((lp.tgt_off + par) * g.B + bm) * PS : 0) + kr * (PS / 4));
-    const double *ap = A + (int64_t)tile.cls * PS * PS;  // [c][q] sets of 4 RB values per lane
-    for (int q = 0; q < RB; ++q) {
-        const double2 b01 = bp[2 * q], b23 = bp[2 * q + 1];
-        double av[4 * RB];
-        load_frags<double, 4 * RB>(ap + (int64_t)q * 64 * 4 * RB, lane, av);
+    const double *ap = A + ((int64_t)tile.cls * RB * RB + rb) * 256;  // [c][q][rb] sets of 4 per lane
+    constexpr int U = RB < 8 ? RB : 8;  // chunks of four k steps loaded together
+    for (int q0 = 0; q0 < RB; q0 += U) {
+        double av[U][4];
+        double2 bb[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = min(q0 + u, RB - 1);
+            load_frags<double, 4>(ap + (int64_t)q * RB * 256, lane, av[u]);
+            bb[u][0] = bp[2 * q];
+            bb[u][1] = bp[2 * q + 1];
+        }
         __builtin_amdgcn_sched_barrier(0);
-        const double bv[4] = {cvalid ? b01.x : 0.0, cvalid ? b01.y : 0.0, cvalid ? b23.x : 0.0,
-                              cvalid ? b23.y : 0.0};
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < U; ++u) {
+            const bool in = cvalid && q0 + u < RB;
+            const double bv[4] = {in ? bb[u][0].x : 0.0, in ? bb[u][0].y : 0.0, in ? bb[u][1].x : 0.0,
+                                  in ? bb[u][1].y : 0.0};
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u * RB + rb], bv[u], acc[rb], 0, 0, 0);
+            for (int k = 0; k < 4; ++k)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][k], bv[k], acc, 0, 0, 0);
+        }
     }
     if (!cvalid)
         return;
     double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            dst[16 * rb + kr + 4 * r] += acc[rb][r];
+    for (int r = 0; r < 4; ++r)
+        dst[16 * rb + kr + 4 * r] += acc[r];
 }
 
 // The multipole expansions regathered for the M2L's B operand, in the
@@ -803,7 +830,7 @@ static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
         return GRAV_OK;
     const int S = p->split[TK_M2L];
     const GemmTile *t0 = (const GemmTile *)(p->d_tiles + all.off) + r.off * S;
-    dim3 grid((unsigned)r.n), blk(256);
+    dim3 grid((unsigned)r.n, (unsigned)(p->PS / 16)), blk(256);
 #define L2L_CASE(R)                                                                             \
     case R:                                                                                     \
         hipLaunchKernelGGL((k_l2l_mfma<R>), grid, blk, 0, s, g, t0, S, (const uint32_t *)p->d_tkey, \
@@ -876,8 +903,10 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
     if (L >= 2) {
         stage_begin(p, "p2m", s);
         const int b3 = p->b * p->b * p->b;
-        hipLaunchKernelGGL(k_p2m, dim3((unsigned)p->lev[L].n_src), dim3(256),
-                           sizeof(double) * b3, s, g, rho, (const double *)p->d_pm, p->d_me);
+        constexpr int LB = 8;  // columns per workgroup
+        const int64_t ncol = p->lev[L].n_src * p->B;
+        hipLaunchKernelGGL((k_p2m<LB>), dim3((unsigned)((ncol + LB - 1) / LB)), dim3((p->PS + 63) / 64 * 64),
+                           sizeof(double) * LB * b3, s, g, rho, (const double *)p->d_pm, p->d_me);
         GRAV_HIP(hipGetLastError());
         stage_end(p, s);
         stage_begin(p, "m2m", s);

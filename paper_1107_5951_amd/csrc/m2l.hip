@@ -32,8 +32,14 @@ namespace grav {
 // loads that each cover a contiguous kilobyte.  Padding coefficients
 // (c >= p^2) are zero in the expansions.
 // --------------------------------------------------------------------------
+#ifdef GRAV_M2L_WAVES_PER_EU
+#define GRAV_M2L_OCC __attribute__((amdgpu_waves_per_eu(GRAV_M2L_WAVES_PER_EU, 8)))
+#else
+#define GRAV_M2L_OCC
+#endif
+
 template <int RB, int KSV, int NC, typename T>
-__global__ void __launch_bounds__(256 / NC)
+__global__ void __launch_bounds__(256 / NC) GRAV_M2L_OCC
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
       const int32_t *class_off, const T *K, const T *me, double *le, T *part, int S, int64_t part_stride)
 {

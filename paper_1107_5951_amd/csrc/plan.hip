@@ -404,28 +404,29 @@ static inline size_t frag_pos(int lane, int e, int G)
     return ((size_t)(e / G) * 64 + lane) * G + e % G;
 }
 
-// Panel operand layout (all row blocks per lane): k step ks (0 .. PS/4 - 1)
-// and instruction sub-row kr = lane / 16 contract coefficient
-// kr * PS/4 + ks (L2L, which reads its B operand straight from the local
-// expansions), or 4 ks + kr with interleaved = true (the M2L, whose B operand
-// is regathered; this puts the padding coefficients in whole trailing k
-// steps).  The fragments of four consecutive k steps (ks = 4 q + u) and all
-// row blocks form one set of E = 4 RB values per lane, value e = u * RB + rb:
-// set q, value (lane, e)  =  m[16 rb + lane % 16][coefficient(lane / 16, 4 q + u)].
-void swizzle_panel(const double *m, int PS, int G, bool interleaved, double *dst)
+// M2L operand layout (all row blocks per lane): k step ks (0 .. PS/4 - 1)
+// and instruction sub-row kr = lane / 16 contract coefficient 4 ks + kr (the
+// M2L's B operand is regathered in the same order; this puts the padding
+// coefficients in whole trailing k steps).  The fragments of four
+// consecutive k steps (ks = 4 q + u) and all row blocks form one set of
+// E = 4 RB values per lane, value e = u * RB + rb:
+// set q, value (lane, e)  =  m[16 rb + lane % 16][4 (4 q + u) + lane / 16].
+void swizzle_panel(const double *m, int PS, int G, double *dst)
 {
-    const int RB = PS / 16, KP = PS / 4;
+    const int RB = PS / 16;
     for (int q = 0; q < RB; ++q)
         for (int lane = 0; lane < 64; ++lane)
             for (int u = 0; u < 4; ++u)
                 for (int rb = 0; rb < RB; ++rb) {
                     const int row = 16 * rb + (lane & 15);
-                    const int col = interleaved ? 4 * (4 * q + u) + (lane >> 4) : (lane >> 4) * KP + 4 * q + u;
+                    const int col = 4 * (4 * q + u) + (lane >> 4);
                     dst[(size_t)q * 64 * 4 * RB + frag_pos(lane, u * RB + rb, G)] = m[(size_t)row * PS + col];
                 }
 }
 
-// Row-blocked variant, one set of four values per (q, rb):
+// Row-blocked layout (M2M, L2L), contraction order kr * PS/4 + ks (their B
+// operand is read straight from the expansions), one set of four values per
+// (q, rb):
 // set (q, rb), value (lane, u)  =  m[16 rb + lane % 16][(lane / 16) * PS/4 + 4 q + u].
 void swizzle_rows(const double *m, int PS, int G, double *dst)
 {
@@ -479,9 +480,8 @@ grav_status build_operators(Plan *p)
     GRAV_CHECK(upload(p, &p->d_l2l, l2l));
     {
         // the same matrices as MFMA A operands (rows = output coefficient),
-        // contraction order kr * PS/4 + ks as in the M2L: M2M with row blocks
-        // outermost per four k steps (a workgroup takes one row block), L2L
-        // with all row blocks contiguous per lane (a wave takes all rows)
+        // contraction order kr * PS/4 + ks, one set of four k steps per
+        // (q, row block): both kernels give a workgroup one row block
         const size_t per8 = (size_t)PS * PS;
         std::vector<double> msw(8 * per8), lsw(8 * per8);
         for (int c = 0; c < 8; ++c) {
@@ -490,7 +490,7 @@ grav_status build_operators(Plan *p)
             m2m_matrix(P, delta, PS, m.data());
             swizzle_rows(m.data(), PS, 2, msw.data() + per8 * c);
             l2l_matrix(P, delta, PS, m.data());
-            swizzle_panel(m.data(), PS, 2, false, lsw.data() + per8 * c);
+            swizzle_rows(m.data(), PS, 2, lsw.data() + per8 * c);
         }
         GRAV_CHECK(upload(p, &p->d_m2m_sw, msw));
         GRAV_CHECK(upload(p, &p->d_l2l_sw, lsw));
@@ -507,7 +507,7 @@ grav_status build_operators(Plan *p)
         // source = target + d  =>  target centre - source centre = -d
         const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
         m2l_matrix(P, dd, PS, m.data());
-        swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, true, k.data() + perp * id);
+        swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, k.data() + perp * id);
         swizzle(m.data(), PS, KS, true, kT.data() + per * id);
     }
     if (p->d.precision == GRAV_FP64) {
