@@ -5,7 +5,7 @@
 // Largest per-lane A chunk (bytes) for which the M2L keeps two register
 // sets (loads of the next chunk in flight during this chunk's MFMAs).
 #ifndef GRAV_M2L_DB_BYTES
-#define GRAV_M2L_DB_BYTES 128
+#define GRAV_M2L_DB_BYTES 512
 #endif
 
 
