@@ -14,6 +14,9 @@ TEST INFRASTRUCTURE (part of the oracle; see ``oracle/__init__.py``).
   between the lower and upper corners (sign (-1)^(i+j+k), index 1 = lower).
   Plain ``arctan`` is used, not a two-argument arctangent: the branch must
   follow the sign of ``w``.
+* :func:`sum_an` -- the closed-form summation method SUM-AN of Sec. 2.1: gz
+  at each point as the sum over all cells of a cell-wise constant density of
+  :func:`prism_gz` of the cell, written out cell by cell.
 * :func:`field_norms` -- Appendix A: integrals of |gz| and gz^2 over the model
   domain with a 4-point Gauss-Legendre rule per axis on an m x m x m
   subdivision of each of the Mbar^3 cells (Table A1), plus max |gz| over the
@@ -51,6 +54,26 @@ def prism_gz(points, box, rho=1.0, G=1.0) -> np.ndarray:
                 sign = -1.0 if (i + j + k) % 2 else 1.0
                 acc += sign * _F(xa - px, yb - py, zc - pz)
     return G * rho * acc
+
+
+def sum_an(rho, origin, h, points, G=1.0) -> np.ndarray:
+    """SUM-AN (Sec. 2.1): gz at ``points [M, 3]`` of the density ``rho
+    [nz, ny, nx]`` (constant per cell, cell (i, j, k) = the box from
+    origin + (i, j, k) h to origin + (i + 1, j + 1, k + 1) h), as the sum over
+    cells of the closed-form prism attraction."""
+    r = np.asarray(rho, dtype=np.float64)
+    nz, ny, nx = r.shape
+    o = np.asarray(origin, dtype=np.float64)
+    out = np.zeros(np.asarray(points).shape[0], dtype=np.float64)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                if r[k, j, i] == 0.0:
+                    continue
+                box = ((o[0] + i * h, o[0] + (i + 1) * h), (o[1] + j * h, o[1] + (j + 1) * h),
+                       (o[2] + k * h, o[2] + (k + 1) * h))
+                out += prism_gz(points, box, r[k, j, i], G)
+    return out
 
 
 def gauss_legendre(n: int):

@@ -238,3 +238,55 @@ def test_adjoint_dot_product(q, comps):
     lhs = (Ax * r).sum()
     rhs = (rho * ATr).sum()
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Ax) * np.linalg.norm(r)
+
+
+# ---------------------------------------------------------------- SUM-AN
+def _st(n=5, z=1.1):
+    return W.stations(n, z)
+
+
+def test_sum_an_of_uniform_block_is_the_block_closed_form():
+    """Summing the closed form over the cells of a uniform, non-cubic block
+    gives the closed form of the whole block (interior faces cancel): pins
+    the cell indexing, its axis order and the corner signs of sum_an."""
+    h = 0.125
+    rho = np.zeros((4, 5, 6))
+    rho[1:3, 1:5, 2:5] = 2.5  # z in [1, 3), y in [1, 5), x in [2, 5) (cells)
+    origin = np.array([0.1, -0.2, 0.3])
+    pts = np.concatenate([_st(4, 1.1), [[0.4, 0.3, 0.45], [0.9, -0.5, 0.0]]])
+    got = prism.sum_an(rho, origin, h, pts)
+    box = ((origin[0] + 2 * h, origin[0] + 5 * h), (origin[1] + 1 * h, origin[1] + 5 * h),
+           (origin[2] + 1 * h, origin[2] + 3 * h))
+    ref = prism.prism_gz(pts, box, 2.5)
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-14)
+
+
+def test_sum_an_single_cell_matches_brute_force_quadrature():
+    """One off-centre cell against a 24-point-per-axis Gauss-Legendre
+    integral of (P_z - z') / |P - x'|^3 (Eq. (1)) far enough away that the
+    quadrature converges to rounding."""
+    h = 0.2
+    rho = np.zeros((2, 2, 3))
+    rho[1, 0, 2] = 1.7
+    origin = np.array([0.0, 0.0, 0.0])
+    pts = np.array([[0.1, 0.9, 1.5], [1.3, -0.4, -0.8], [0.5, 0.1, 0.7]])
+    got = prism.sum_an(rho, origin, h, pts)
+    xi, wi = prism.gauss_legendre(24)
+    lo = origin + np.array([2, 0, 1]) * h
+    q = lo[None, :] + 0.5 * h * (xi[:, None] + 1.0)
+    X, Y, Z = np.meshgrid(q[:, 0], q[:, 1], q[:, 2], indexing="ij")
+    Wt = np.einsum("i,j,k->ijk", wi, wi, wi) * (0.5 * h) ** 3
+    ref = []
+    for p in pts:
+        d = np.sqrt((p[0] - X) ** 2 + (p[1] - Y) ** 2 + (p[2] - Z) ** 2)
+        ref.append(1.7 * np.sum(Wt * (p[2] - Z) / d ** 3))
+    np.testing.assert_allclose(got, ref, rtol=1e-9)
+
+
+def test_sum_an_is_linear_in_rho():
+    rng = np.random.default_rng(3)
+    a, b = rng.normal(size=(3, 3, 3)), rng.normal(size=(3, 3, 3))
+    pts = _st(3, 0.9)
+    lhs = prism.sum_an(2.0 * a - b, (0, 0, 0), 0.3, pts)
+    rhs = 2.0 * prism.sum_an(a, (0, 0, 0), 0.3, pts) - prism.sum_an(b, (0, 0, 0), 0.3, pts)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12, atol=1e-14)
