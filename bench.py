@@ -184,7 +184,9 @@ def serving(args):
 def crossover(args):
     """Summation vs FMM as the number of stations grows (cf. the paper's
     crossover discussion, Sec. 4): a fixed 64^3 mesh, 1-point rule, gz at
-    ns x ns stations at z = 1.1, mixed precision p = 8."""
+    ns x ns stations at z = 1.1, mixed precision p = 8; the summation by the
+    1-point rule (SUM-G1, grav_direct) and in closed form (SUM-AN,
+    grav_analytic, FP64)."""
     import torch
 
     import paper_1107_5951_amd as G
@@ -198,7 +200,7 @@ def crossover(args):
                                  leaf_size=64, precision=G.GRAV_MIXED))
         out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
         t = {}
-        for name, fn in (("fmm", plan.eval), ("direct", plan.direct)):
+        for name, fn in (("fmm", plan.eval), ("direct", plan.direct), ("analytic", plan.analytic)):
             fn(rho, out)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -209,11 +211,14 @@ def crossover(args):
             e1.record()
             torch.cuda.synchronize()
             t[name] = e0.elapsed_time(e1) / reps
-        rows.append({"stations": ns * ns, "fmm_ms": t["fmm"], "direct_ms": t["direct"]})
+        rows.append({"stations": ns * ns, "fmm_ms": t["fmm"], "direct_ms": t["direct"],
+                     "analytic_ms": t["analytic"]})
         print(json.dumps(rows[-1]), flush=True)
     faster = [r["stations"] for r in rows if r["fmm_ms"] < r["direct_ms"]]
-    print(json.dumps({"crossover_stations": min(faster) if faster else None, "mesh": "64^3, q=1",
-                      "rows": rows}), flush=True)
+    faster_an = [r["stations"] for r in rows if r["fmm_ms"] < r["analytic_ms"]]
+    print(json.dumps({"crossover_stations": min(faster) if faster else None,
+                      "crossover_stations_analytic": min(faster_an) if faster_an else None,
+                      "mesh": "64^3, q=1", "rows": rows}), flush=True)
 
 
 def main():

@@ -143,6 +143,21 @@ grav_status grav_adjoint(grav_plan_t plan, const double *resid, double *drho_out
  * formed in FP64).  Shares the plan's workspace lock (GRAV_EBUSY). */
 grav_status grav_direct(grav_plan_t plan, const double *rho, double *g_out, void *stream);
 
+/* Closed-form summation (the analytic summation method SUM-AN of Sec. 2.1):
+ * gz at the plan's evaluation points as the sum over all cells of the exact
+ * attraction of a uniform rectangular prism (the closed form the paper cites
+ * for its analytic method and for the exact solution of Sec. 3), so no
+ * quadrature rule is involved: exact for a cell-wise constant density, up to
+ * rounding.  The plan's quadrature order and p are ignored.
+ * rho:    device pointer, double [batch][nz][ny][nx] (as grav_eval);
+ * gz_out: device pointer, double [batch][n_targets][1], descriptor order,
+ *         gz with the sign of Eq. (1) (positive above a positive anomaly),
+ *         G applied.
+ * FP64 arithmetic in both precisions, O(M (nx+1)(ny+1)(nz+1)) work.  Plans
+ * with components != 1 return GRAV_EUNSUPPORTED (the method gives gz only).
+ * Asynchrony, workspace lock and other errors as grav_direct. */
+grav_status grav_analytic(grav_plan_t plan, const double *rho, double *gz_out, void *stream);
+
 /* Stage timings of the last evaluation or adjoint enqueued with
  * grav_set_profiling(plan, 1), in milliseconds from HIP events on the
  * evaluation stream: up to n entries of (name, ms).  Synchronizes with the

@@ -160,6 +160,20 @@ class Plan:
         grav_direct(self, r, out, stream)
         return out[0] if squeeze else out
 
+    def analytic(self, rho, out=None, stream=None):
+        """gz by the closed-form summation method (grav_analytic): exact for a
+        cell-wise constant density; plans with components=1 only.  Output
+        [B, M, 1] (or [M, 1]), like eval."""
+        import torch
+        squeeze = rho.dim() == 3
+        r = rho.reshape(self.rho_shape)
+        if r.dtype != torch.float64 or not r.is_cuda or not r.is_contiguous():
+            raise ValueError("rho must be a contiguous float64 HIP tensor of shape %s" % (self.rho_shape,))
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=torch.float64, device=r.device)
+        grav_analytic(self, r, out, stream)
+        return out[0] if squeeze else out
+
     def adjoint(self, resid, out=None, stream=None):
         """drho = A^T resid for a float64 device tensor resid [B, M, C] (or [M, C])."""
         import torch
@@ -204,6 +218,11 @@ def grav_eval(plan: Plan, rho, g_out, stream=None) -> None:
 def grav_direct(plan: Plan, rho, g_out, stream=None) -> None:
     check(load().grav_direct(plan.handle, ctypes.c_void_p(rho.data_ptr()),
                              ctypes.c_void_p(g_out.data_ptr()), _stream_ptr(stream)), "grav_direct")
+
+
+def grav_analytic(plan: Plan, rho, gz_out, stream=None) -> None:
+    check(load().grav_analytic(plan.handle, ctypes.c_void_p(rho.data_ptr()),
+                               ctypes.c_void_p(gz_out.data_ptr()), _stream_ptr(stream)), "grav_analytic")
 
 
 def grav_adjoint(plan: Plan, resid, drho_out, stream=None) -> None:

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgrav.so")
-SOURCES = ["operators.cpp", "sort.hip", "plan.hip", "eval.hip", "adjoint.hip", "check.hip", "direct.hip", "m2l.hip"]
+SOURCES = ["operators.cpp", "sort.hip", "plan.hip", "eval.hip", "adjoint.hip", "check.hip", "direct.hip", "m2l.hip",
+           "analytic.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

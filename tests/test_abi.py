@@ -59,5 +59,6 @@ def test_null_pointers_are_rejected():
     assert lib.grav_eval(None, None, None, None) == _lib.GRAV_EINVAL
     assert lib.grav_adjoint(None, None, None, None) == _lib.GRAV_EINVAL
     assert lib.grav_direct(None, None, None, None) == _lib.GRAV_EINVAL
+    assert lib.grav_analytic(None, None, None, None) == _lib.GRAV_EINVAL
     assert lib.grav_plan(None, None) == _lib.GRAV_EINVAL
     assert lib.grav_status_string(_lib.GRAV_EBUSY).decode() != ""
