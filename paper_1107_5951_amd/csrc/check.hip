@@ -116,7 +116,6 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
     for (int k = 0; k < TK_COUNT; ++k)
         for (int l = 0; l <= kMaxLevels; ++l)
             ntile = std::max<int64_t>(ntile, p->tiles[k][l].off + p->tiles[k][l].n);
-    ntile = std::max<int64_t>(ntile, p->m2l_order.off + p->m2l_order.n);
     int64_t ntb = 0;
     const int lo = L >= 2 ? 2 : L;
     for (int l = lo; l <= L; ++l)
@@ -224,20 +223,44 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
     }
 
     if (L >= 2 && ck.ok) {
-        // the M2L launch order: its (tile, split) units, each once, plus
-        // empty units (no columns) as padding
-        const TileRange &r = p->tiles[TK_M2L][0], &o = p->m2l_order;
-        auto key = [](const GemmTile &t) { return std::make_tuple(t.level, t.cls, t.col0, t.ncol, t.pad); };
-        std::vector<std::tuple<int, int, int64_t, int, int>> a, b;
-        for (int64_t i = 0; i < r.n; ++i)
-            a.push_back(key(tiles[r.off + i]));
-        for (int64_t i = 0; i < o.n; ++i)
-            if (tiles[o.off + i].ncol > 0)
-                b.push_back(key(tiles[o.off + i]));
-        std::sort(a.begin(), a.end());
-        std::sort(b.begin(), b.end());
-        if (a != b)
-            ck.fail("m2l", "launch order is not the units, each once", (int64_t)b.size(), r.n);
+        // the forward M2L's stream-K schedule: segments cover every work item
+        // once, in order, one tile per segment; each tile lists its segments
+        // in order; every LE column maps to one valid (tile, column)
+        const TileRange &r = p->tiles[TK_M2L][0];
+        if (p->m2l_wgs > 0) {
+            const auto items = fetch(p->d_m2l_items, (size_t)p->m2l_items);
+            const auto segs = fetch(p->d_m2l_segs, (size_t)p->m2l_nseg * 4);
+            const auto wgseg = fetch(p->d_m2l_wgseg, (size_t)p->m2l_wgs + 1);
+            const auto tstart = fetch(p->d_m2l_tseg_start, (size_t)r.n + 1);
+            const auto tsegs = fetch(p->d_m2l_tsegs, (size_t)std::max<int64_t>(1, p->m2l_nseg));
+            const auto colmap = fetch(p->d_m2l_colmap, (size_t)(p->n_tbox * p->B));
+            if (wgseg[0] != 0 || wgseg[p->m2l_wgs] != p->m2l_nseg)
+                ck.fail("m2l", "segment ranges do not cover the segments", wgseg[0], p->m2l_nseg);
+            int64_t next = 0;
+            for (int64_t sg = 0; sg < p->m2l_nseg && ck.ok; ++sg) {
+                const int32_t t = segs[4 * sg], ib = segs[4 * sg + 1], ie = segs[4 * sg + 2];
+                if (t < 0 || t >= r.n || ib != next || ie <= ib || ie > p->m2l_items)
+                    ck.fail("m2l", "segment out of order or range", sg, t);
+                for (int32_t it = ib; it < ie && ck.ok; ++it)
+                    if (items[it] < 0 || items[it] >= kClassOffsets)
+                        ck.fail("m2l", "work item offset out of range", it, items[it]);
+                next = ie;
+            }
+            if (ck.ok && next != p->m2l_items)
+                ck.fail("m2l", "segments do not cover the work items", next, p->m2l_items);
+            if (ck.ok && (tstart[0] != 0 || tstart[r.n] != p->m2l_nseg))
+                ck.fail("m2l", "tile segment lists do not cover the segments", tstart[r.n], p->m2l_nseg);
+            for (int64_t t = 0; t < r.n && ck.ok; ++t)
+                for (int32_t j = tstart[t]; j < tstart[t + 1] && ck.ok; ++j)
+                    if (tsegs[j] < 0 || tsegs[j] >= p->m2l_nseg || segs[4 * tsegs[j]] != t ||
+                        (j > tstart[t] && tsegs[j] <= tsegs[j - 1]))
+                        ck.fail("m2l", "tile segment list inconsistent", t, j);
+            for (int64_t c = 0; c < p->n_tbox * p->B && ck.ok; ++c) {
+                const int32_t m = colmap[c];
+                if (m < 0 || (m >> 6) >= r.n || (m & 63) >= tiles[r.off + (m >> 6)].ncol)
+                    ck.fail("m2l", "LE column without a tile column", c, m);
+            }
+        }
     }
     if (L >= 2 && ck.ok) {
         const int64_t xme = p->n_me * p->B, xle = p->n_tbox * p->B;

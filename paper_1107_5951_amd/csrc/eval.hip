@@ -263,6 +263,32 @@ __global__ void __launch_bounds__(256) k_sum_parts(const T *part, int S, int64_t
 template __global__ void k_sum_parts<double>(const double *, int, int64_t, double *);
 template __global__ void k_sum_parts<float>(const float *, int, int64_t, double *);
 
+// LE from the forward M2L's segment slots: element (column, k) of the LE is
+// the sum, over the segments of the column's tile in their order, of the
+// slot entry (column in tile, k), in FP64.  A tile without segments (no
+// source box at any offset) gives zero.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_m2l_sum(const T *part, const int32_t *colmap, const int32_t *tseg_start, const int32_t *tsegs, int64_t n, int PS,
+          double *le)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int64_t col = i / PS;
+    const int k = (int)(i - col * PS);
+    const int32_t m = colmap[col];
+    const int t = m >> 6, cl = m & 63;
+    double acc = 0.0;
+    for (int j = tseg_start[t]; j < tseg_start[t + 1]; ++j)
+        acc += (double)part[((int64_t)tsegs[j] * 64 + cl) * PS + k];
+    le[i] = acc;
+}
+template __global__ void k_m2l_sum<double>(const double *, const int32_t *, const int32_t *, const int32_t *,
+                                           int64_t, int, double *);
+template __global__ void k_m2l_sum<float>(const float *, const int32_t *, const int32_t *, const int32_t *,
+                                          int64_t, int, double *);
+
 // --------------------------------------------------------------------------
 // Near field (P2P): direct sum over the quadrature points of the cells of the
 // 27 leaves around a target leaf (the near term of Eq. (13)); coincident
@@ -932,15 +958,18 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         else
             GRAV_CHECK(launch_m2l<float>(p, g, s, p->d_k32));
         stage_end(p, s);
-        if (p->split[TK_M2L] > 1) {
+        {
             stage_begin(p, "m2l_sum", s);
             const int64_t n = p->n_tbox * p->B * p->PS;
+            const dim3 gs((unsigned)((n + 255) / 256));
             if (p->d.precision == GRAV_FP64)
-                hipLaunchKernelGGL(k_sum_parts<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                                   (const double *)p->d_part, p->split[TK_M2L], n, p->d_le);
+                hipLaunchKernelGGL(k_m2l_sum<double>, gs, dim3(256), 0, s, (const double *)p->d_part,
+                                   (const int32_t *)p->d_m2l_colmap, (const int32_t *)p->d_m2l_tseg_start,
+                                   (const int32_t *)p->d_m2l_tsegs, n, p->PS, p->d_le);
             else
-                hipLaunchKernelGGL(k_sum_parts<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                                   (const float *)p->d_part, p->split[TK_M2L], n, p->d_le);
+                hipLaunchKernelGGL(k_m2l_sum<float>, gs, dim3(256), 0, s, (const float *)p->d_part,
+                                   (const int32_t *)p->d_m2l_colmap, (const int32_t *)p->d_m2l_tseg_start,
+                                   (const int32_t *)p->d_m2l_tsegs, n, p->PS, p->d_le);
             GRAV_HIP(hipGetLastError());
             stage_end(p, s);
         }

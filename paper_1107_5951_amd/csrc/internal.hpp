@@ -91,9 +91,14 @@ struct Plan {
     // split[k] times); slot l >= 2 = level l's tiles in the unrepeated numbering
     TileRange tiles[TK_COUNT][kMaxLevels + 1];
     int split[TK_COUNT] = {1, 1};
-    // the forward M2L's (tile, split) units again, longest first (the launch
-    // order of its workgroups; offset into d_tiles)
-    TileRange m2l_order;
+    // stream-K schedule of the forward M2L (see build_tiles): work items
+    // (offset index per item, tile by tile), segments {tile, first item,
+    // end item, 0} per workgroup (wgseg: CSR over workgroups), per tile its
+    // segment slots (CSR), and LE column -> 64 * tile + column in tile
+    int32_t m2l_wgs = 0;
+    int64_t m2l_nseg = 0, m2l_items = 0;
+    int32_t *d_m2l_items = nullptr, *d_m2l_segs = nullptr, *d_m2l_wgseg = nullptr;
+    int32_t *d_m2l_tseg_start = nullptr, *d_m2l_tsegs = nullptr, *d_m2l_colmap = nullptr;
     // near field of voxel-centre targets by lattice matrices (b <= 4)
     bool lat_near = false;
     int lat_RB = 0, lat_Q = 0;                     // row blocks (4 b^3 / 16); chunks of four k steps

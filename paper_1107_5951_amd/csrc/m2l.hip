@@ -13,12 +13,15 @@ namespace grav {
 
 // --------------------------------------------------------------------------
 // M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
-// child-parity class, model) of one split of the class's 189 interaction-
-// list offsets d.  A workgroup has 4 / NC waves; wave w owns the NC blocks
-// of 16 columns 16 (NC w + c), c < NC, and all row blocks.  For each d the
-// wave accumulates LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA
-// tiles, accumulating in registers across the offsets (no atomics); every
-// A fragment loaded feeds NC instructions.
+// child-parity class, model); its work items are the class's interaction-
+// list offsets d at which some column has a source box.  A workgroup runs
+// its segments (a tile and a contiguous run of its items, see the stream-K
+// schedule in build_tiles) one after the other; it has 4 / NC waves, wave w
+// owning the NC blocks of 16 columns 16 (NC w + c), c < NC, and all row
+// blocks.  For each d the wave accumulates LE[:, col] += K_d * ME[box(col) + d]
+// with 16x16x4 MFMA tiles in registers across the segment's offsets (no
+// atomics), then writes the segment's partial to its slot; every A fragment
+// loaded feeds NC instructions.
 //
 // Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
 // instruction take coefficient c = 4 ks + kr, so the coefficients c >= p^2
@@ -41,157 +44,150 @@ namespace grav {
 template <int RB, int KSV, int NC, typename T>
 __global__ void __launch_bounds__(256 / NC) GRAV_M2L_OCC
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
-      const int32_t *class_off, const T *K, const T *me, double *le, T *part, int S, int64_t part_stride)
+      const int32_t *class_off, const T *K, const T *me, const int32_t *segs, const int32_t *wgseg,
+      const int32_t *items, T *part)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
-    const GemmTile tile = tiles[blockIdx.x];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const DevLev &lv = g.lev[tile.level];
-    bool cvalid[NC];
-    int bm[NC], bx[NC], by[NC], bz[NC];
-    int64_t box[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const int cl = (wave * NC + c) * 16 + (lane & 15);
-        cvalid[c] = cl < tile.ncol;
-        const int64_t col = tile.col0 + cl;
-        bm[c] = (int)(col % g.B);
-        box[c] = 0;
-        bx[c] = by[c] = bz[c] = 0;
-        if (cvalid[c]) {
-            box[c] = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
-            const uint32_t key = tkey[lv.tbox_off + box[c]];
-            bx[c] = (int)compact3(key);
-            by[c] = (int)compact3(key >> 1);
-            bz[c] = (int)compact3(key >> 2);
-        }
-    }
-    vec4 acc[NC][RB];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-            acc[c][rb] = vec4{0, 0, 0, 0};
-    const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
-    const int kr = lane >> 4;
-    constexpr int PS = 16 * RB;
-    constexpr int QC = (KSV + 3) / 4;  // chunks of four k steps holding coefficients
-    // regathered expansions of this level: plane (q, kr) holds four
-    // coefficients of every (class-split box, model), plane stride pstr
-    const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
-    const int64_t pstr = nB * 4;
-    const T *mlev = me + lv.me_off * g.B * PS + kr * pstr;
-    constexpr int64_t kstride = (int64_t)RB * 64 * 4 * RB;  // elements per offset matrix
-    // offsets [o0, o1) of this split (tile.pad of S)
-    const int o0 = tile.pad * kClassOffsets / S, o1 = (tile.pad + 1) * kClassOffsets / S;
-    for (int o = o0; o < o1; ++o) {
-        const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
-        const int id = offs[4 * o + 3];
-        // the source boxes at this offset all belong to one parity class
-        int first[3], cnt[3];
-        const int64_t cstart =
-            class_split(lv, tile.cls ^ ((dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2)), first, cnt);
-        bool have[NC];
-        const T *mp[NC];
-        bool any = false;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int sg = wgseg[blockIdx.x]; sg < wgseg[blockIdx.x + 1]; ++sg) {
+        const int32_t *sd = segs + 4 * sg;  // tile, first item, end item
+        const GemmTile tile = tiles[sd[0]];
+        const DevLev &lv = g.lev[tile.level];
+        bool cvalid[NC];
+        int bm[NC], bx[NC], by[NC], bz[NC];
+        int64_t box[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const int ax = bx[c] + dx, ay = by[c] + dy, az = bz[c] + dz;
-            const int sx = ax - lv.s0[0], sy = ay - lv.s0[1], sz = az - lv.s0[2];
-            have[c] = cvalid[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
-                      sz < lv.ns[2];
-            const int64_t pos = cstart + ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
-                                ((ax - first[0]) >> 1);
-            mp[c] = mlev + (have[c] ? (pos * g.B + bm[c]) * 4 : 0);
-            any = any || have[c];
+            const int cl = (wave * NC + c) * 16 + (lane & 15);
+            cvalid[c] = cl < tile.ncol;
+            const int64_t col = tile.col0 + cl;
+            bm[c] = (int)(col % g.B);
+            box[c] = 0;
+            bx[c] = by[c] = bz[c] = 0;
+            if (cvalid[c]) {
+                box[c] = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
+                const uint32_t key = tkey[lv.tbox_off + box[c]];
+                bx[c] = (int)compact3(key);
+                by[c] = (int)compact3(key >> 1);
+                bz[c] = (int)compact3(key >> 2);
+            }
         }
-        if (__ballot(any) == 0ull)
-            continue;  // no column of this wave sees a source box at this offset
-        const T *kp = K + (int64_t)id * kstride;
-        // two register sets (when they fit): the loads of chunk q + 1 are in
-        // flight while the instructions of chunk q run
-        constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
-        T av[NSET][4 * RB];
-        T bb[NSET][NC][4];
-        auto load = [&](int q, int set) {
+        vec4 acc[NC][RB];
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                load4(mp[c] + (int64_t)q * 4 * pstr, bb[set][c]);
-            load_frags<T, 4 * RB>(kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
-        };
-        auto compute = [&](int q, int set) {
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (4 * q + u >= KSV)
-                    break;  // k steps past the last coefficient are all zero
-                T bv[NC];
+            for (int rb = 0; rb < RB; ++rb)
+                acc[c][rb] = vec4{0, 0, 0, 0};
+        const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
+        const int kr = lane >> 4;
+        constexpr int PS = 16 * RB;
+        constexpr int QC = (KSV + 3) / 4;  // chunks of four k steps holding coefficients
+        // regathered expansions of this level: plane (q, kr) holds four
+        // coefficients of every (class-split box, model), plane stride pstr
+        const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
+        const int64_t pstr = nB * 4;
+        const T *mlev = me + lv.me_off * g.B * PS + kr * pstr;
+        constexpr int64_t kstride = (int64_t)RB * 64 * 4 * RB;  // elements per offset matrix
+        for (int it = sd[1]; it < sd[2]; ++it) {
+            const int o = items[it];
+            const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
+            const int id = offs[4 * o + 3];
+            // the source boxes at this offset all belong to one parity class
+            int first[3], cnt[3];
+            const int64_t cstart =
+                class_split(lv, tile.cls ^ ((dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2)), first, cnt);
+            bool have[NC];
+            const T *mp[NC];
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int ax = bx[c] + dx, ay = by[c] + dy, az = bz[c] + dz;
+                const int sx = ax - lv.s0[0], sy = ay - lv.s0[1], sz = az - lv.s0[2];
+                have[c] = cvalid[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
+                          sz < lv.ns[2];
+                const int64_t pos = cstart + ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
+                                    ((ax - first[0]) >> 1);
+                mp[c] = mlev + (have[c] ? (pos * g.B + bm[c]) * 4 : 0);
+                any = any || have[c];
+            }
+            if (__ballot(any) == 0ull)
+                continue;  // no column of this wave sees a source box at this offset
+            const T *kp = K + (int64_t)id * kstride;
+            // two register sets (when they fit): the loads of chunk q + 1 are in
+            // flight while the instructions of chunk q run
+            constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
+            T av[NSET][4 * RB];
+            T bb[NSET][NC][4];
+            auto load = [&](int q, int set) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
-                    bv[c] = have[c] ? bb[set][c][u] : (T)0;
+                    load4(mp[c] + (int64_t)q * 4 * pstr, bb[set][c]);
+                load_frags<T, 4 * RB>(kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
+            };
+            auto compute = [&](int q, int set) {
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
+                for (int u = 0; u < 4; ++u) {
+                    if (4 * q + u >= KSV)
+                        break;  // k steps past the last coefficient are all zero
+                    T bv[NC];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        if constexpr (sizeof(T) == 8)
-                            acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[c],
-                                                                              acc[c][rb], 0, 0, 0);
-                        else
-                            acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[c],
-                                                                              acc[c][rb], 0, 0, 0);
-                    }
-            }
-        };
-        if constexpr (NSET == 2) {
-            load(0, 0);
-            __builtin_amdgcn_sched_barrier(0);
+                    for (int c = 0; c < NC; ++c)
+                        bv[c] = have[c] ? bb[set][c][u] : (T)0;
 #pragma unroll
-            for (int q = 0; q < QC; ++q) {
-                if (q + 1 < QC) {
-                    // the loads of chunk q + 1 issue one by one between this
-                    // chunk's instructions, so the matrix pipe keeps running
-                    // while the wave feeds the memory pipeline
-                    load(q + 1, (q + 1) & 1);
-                    compute(q, q & 1);
-                    interleave_loads<NC + 4 * RB * (int)sizeof(T) / 16, 4 * RB * NC>();
-                } else {
-                    compute(q, q & 1);
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            if constexpr (sizeof(T) == 8)
+                                acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[c],
+                                                                                  acc[c][rb], 0, 0, 0);
+                            else
+                                acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[c],
+                                                                                  acc[c][rb], 0, 0, 0);
+                        }
                 }
+            };
+            if constexpr (NSET == 2) {
+                load(0, 0);
                 __builtin_amdgcn_sched_barrier(0);
-            }
-        } else {
 #pragma unroll
-            for (int q = 0; q < QC; ++q) {
-                load(q, 0);
-                __builtin_amdgcn_sched_barrier(0);
-                compute(q, 0);
+                for (int q = 0; q < QC; ++q) {
+                    if (q + 1 < QC) {
+                        // the loads of chunk q + 1 issue one by one between this
+                        // chunk's instructions, so the matrix pipe keeps running
+                        // while the wave feeds the memory pipeline
+                        load(q + 1, (q + 1) & 1);
+                        compute(q, q & 1);
+                        interleave_loads<NC + 4 * RB * (int)sizeof(T) / 16, 4 * RB * NC>();
+                    } else {
+                        compute(q, q & 1);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    load(q, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    compute(q, 0);
+                }
             }
         }
-    }
-    // Output fragment: lane holds column lane % 16 and four rows; the FP32
-    // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
-    // Split partials go to their own slab of the workspace.
-    constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
-    const int rbase = sizeof(T) == 8 ? kr : 4 * kr;
+        // Output fragment: lane holds column lane % 16 and four rows; the FP32
+        // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
+        // The segment's partial LE goes to its own slot [64 columns][PS].
+        constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
+        const int rbase = sizeof(T) == 8 ? kr : 4 * kr;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (!cvalid[c])
-            continue;
-        if (S > 1) {
-            // partial sums in the accumulation type, one slab per split
-            T *dst = part + (tile.pad * part_stride + (lv.tgt_off + box[c]) * g.B + bm[c]) * PS;
+        for (int c = 0; c < NC; ++c) {
+            if (!cvalid[c])
+                continue;
+            T *dst = part + ((int64_t)sg * 64 + (wave * NC + c) * 16 + (lane & 15)) * PS;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     dst[16 * rb + rbase + rstride * r] = acc[c][rb][r];
-        } else {
-            double *dst = le + ((lv.tgt_off + box[c]) * g.B + bm[c]) * PS;
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    dst[16 * rb + rbase + rstride * r] = (double)acc[c][rb][r];
         }
     }
 }
@@ -199,21 +195,20 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
 template <typename T>
 grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
 {
-    const TileRange &r = p->m2l_order;  // the units, longest first
-    if (r.n == 0)
+    const TileRange &r = p->tiles[TK_M2L][0];
+    if (r.n == 0 || p->m2l_wgs == 0)
         return GRAV_OK;
     constexpr int NC = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;  // column blocks per wave
-    dim3 grid(r.n), blk(256 / NC);
-    const int S = p->split[TK_M2L];
-    const int64_t pstride = p->n_tbox * p->B;  // expansions per partial slab
-    T *part = reinterpret_cast<T *>(p->d_part);  // sized for FP64 partials
+    dim3 grid(p->m2l_wgs), blk(256 / NC);
+    T *part = reinterpret_cast<T *>(p->d_part);  // segment slots (sized for FP64)
     const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see k_me_gather)
 #define M2L_CASE(P)                                                                             \
     case P:                                                                                     \
         hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T>), grid, blk, 0, s, g,  \
                            (const GemmTile *)(p->d_tiles + r.off), (const uint32_t *)p->d_tkey, \
                            (const int32_t *)p->d_torder, (const int32_t *)p->d_class_off, K, me_in, \
-                           p->d_le, part, S, pstride);                                          \
+                           (const int32_t *)p->d_m2l_segs, (const int32_t *)p->d_m2l_wgseg,     \
+                           (const int32_t *)p->d_m2l_items, part);                              \
         break;
     switch (p->P) {
         M2L_CASE(1)

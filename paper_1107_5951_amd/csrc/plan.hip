@@ -22,6 +22,11 @@
 #ifndef GRAV_M2L_TARGET_WG
 #define GRAV_M2L_TARGET_WG 8192
 #endif
+// Waves of the forward M2L's stream-K schedule: all resident at once
+// (256 CUs x 4 SIMDs x 2 waves; both M2L kernels fit two waves per SIMD).
+#ifndef GRAV_M2L_WAVES
+#define GRAV_M2L_WAVES 2048
+#endif
 
 namespace grav {
 
@@ -285,7 +290,8 @@ void free_plan(Plan *p)
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
-                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg, p->d_lat_tab,
+                    p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg, p->d_lat_tab, p->d_m2l_items, p->d_m2l_segs,
+                    p->d_m2l_wgseg, p->d_m2l_tseg_start, p->d_m2l_tsegs, p->d_m2l_colmap,
                     p->d_cell_slot, p->d_leaf_pend};
     for (void *b : bufs)
         if (b)
@@ -572,16 +578,17 @@ grav_status build_tiles(Plan *p)
             for (int c = 0; c < 8; ++c)
                 add(TK_M2LT, l, c, class_count(p->lev[l], c) * B);
     }
-    // Split the 189 offsets of each tile over S <= 16 workgroups when there
-    // are too few tiles to fill the device (about 4096 workgroups wanted, so
-    // that work also balances over the 1024 SIMDs); the S partial expansions
-    // are summed in a fixed order afterwards.
+    // Transposed M2L: split the 189 offsets of each tile over S workgroups
+    // when there are too few tiles to fill the device; the S partial
+    // expansions are summed in a fixed order afterwards.  The forward M2L is
+    // not split this way (S = 1): it runs on the stream-K schedule below.
     std::vector<GemmTile> split;
     for (int k = 0; k < TK_COUNT; ++k) {
         TileRange &r = p->tiles[k][0];
-        const int S = r.n == 0 ? 1
-                              : (int)std::min<int64_t>(GRAV_M2L_SPLIT_MAX,
-                                                       std::max<int64_t>(1, ceil_div(GRAV_M2L_TARGET_WG, r.n)));
+        const int S = (r.n == 0 || k == TK_M2L)
+                          ? 1
+                          : (int)std::min<int64_t>(GRAV_M2L_SPLIT_MAX,
+                                                   std::max<int64_t>(1, ceil_div(GRAV_M2L_TARGET_WG, r.n)));
         p->split[k] = S;
         const int64_t off = (int64_t)split.size();
         for (int64_t i = 0; i < r.n; ++i)
@@ -593,18 +600,20 @@ grav_status build_tiles(Plan *p)
         r.off = off;
         r.n *= S;
     }
-    // Launch order of the forward M2L's (tile, split) units.  Cost of a unit
-    // = the largest number of offsets of its split that one of its waves
-    // computes (an offset is skipped only when no column of the wave has a
-    // source box there).  Long units start first, so that the last
-    // workgroups to start are short ones (the device dispatches in index
-    // order: a longest-processing-time schedule).
-    p->m2l_order = TileRange{};
+    // Stream-K schedule of the forward M2L.  Work items are the (tile,
+    // offset) pairs in which some column of the tile has a source box (the
+    // others cost nothing), listed tile by tile.  A fixed number of
+    // workgroups, all resident at once, take equal contiguous shares of the
+    // list; a workgroup's share is cut into segments at tile boundaries, and
+    // each segment writes the partial LE of its tile's columns to a slot of
+    // its own.  k_m2l_sum then adds, per tile, its segments' slots in order
+    // (deterministic).  The work is balanced to one item per workgroup and
+    // there are at most (tiles + workgroups) partial slots.
+    p->m2l_wgs = 0;
+    p->m2l_nseg = 0;
     {
-        const TileRange &r = p->tiles[TK_M2L][0];
+        const TileRange &r = p->tiles[TK_M2L][0];  // S = 1: one entry per tile
         if (r.n > 0) {
-            const int ncw = 16 * (p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32);
-            const int S = p->split[TK_M2L];
             std::vector<int> alloffs;
             std::vector<int32_t> fwd, rev;
             offsets_tables(alloffs, fwd, rev);
@@ -622,83 +631,72 @@ grav_status build_tiles(Plan *p)
                 }
             }
             GRAV_HIP(hipStreamSynchronize(p->bs));
-            std::vector<int> cost(r.n);
-            std::vector<char> hit;
+            std::vector<int32_t> item_tile, item_off;
+            std::vector<int32_t> colmap((size_t)p->n_tbox * B, -1);
+            std::vector<char> hit(kClassOffsets);
             for (int64_t u = 0; u < r.n; ++u) {
                 const GemmTile &t = split[r.off + u];
                 const LevelInfo &lv = p->lev[t.level];
-                const int o0 = t.pad * kClassOffsets / S, o1 = (t.pad + 1) * kClassOffsets / S;
-                int worst = 0;
-                for (int w0 = 0; w0 < t.ncol; w0 += ncw) {
-                    hit.assign(o1 - o0, 0);
-                    for (int cl = w0; cl < std::min(t.ncol, w0 + ncw); ++cl) {
-                        const int64_t col = t.col0 + cl;
-                        const int32_t box = ord[t.level][lv.class_start[t.cls] + col / B];
-                        const uint32_t k = key[t.level][box];
-                        const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
-                        for (int o = o0; o < o1; ++o) {
-                            const int32_t *e = &fwd[((size_t)t.cls * kClassOffsets + o) * 4];
-                            bool in = true;
-                            for (int a = 0; a < 3; ++a) {
-                                const int s = c[a] + e[a] - lv.s0[a];
-                                in = in && s >= 0 && s < lv.ns[a];
-                            }
-                            hit[o - o0] |= in;
+                std::fill(hit.begin(), hit.end(), 0);
+                for (int cl = 0; cl < t.ncol; ++cl) {
+                    const int64_t col = t.col0 + cl;
+                    const int32_t box = ord[t.level][lv.class_start[t.cls] + col / B];
+                    colmap[(size_t)((lv.tgt_off + box) * B + col % B)] = (int32_t)(u * 64 + cl);
+                    const uint32_t k = key[t.level][box];
+                    const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+                    for (int o = 0; o < kClassOffsets; ++o) {
+                        const int32_t *e = &fwd[((size_t)t.cls * kClassOffsets + o) * 4];
+                        bool in = true;
+                        for (int a = 0; a < 3; ++a) {
+                            const int s = c[a] + e[a] - lv.s0[a];
+                            in = in && s >= 0 && s < lv.ns[a];
                         }
+                        hit[o] |= in;
                     }
-                    int nh = 0;
-                    for (char h : hit)
-                        nh += h;
-                    worst = std::max(worst, nh);
                 }
-                cost[u] = worst;
+                for (int o = 0; o < kClassOffsets; ++o)
+                    if (hit[o]) {
+                        item_tile.push_back((int32_t)u);
+                        item_off.push_back(o);
+                    }
             }
-            // The device hands workgroup i to XCD i mod 8, and each XCD has
-            // its own L2.  Units of one (class, split) combination read the
-            // same operator matrices (they do not depend on the level), so
-            // whole combinations go to one XCD: its concurrent workgroups
-            // then share a few matrices instead of all 316.  Combinations
-            // are dealt to the XCDs longest first onto the least loaded one;
-            // each XCD runs its combinations longest first, units within a
-            // combination longest first.  Shorter XCD lists are padded with
-            // empty units (no columns: they compute and write nothing).
-            constexpr int kXcd = 8;
-            const int ncombo = 8 * S;
-            std::vector<std::vector<int64_t>> units(ncombo);
-            std::vector<int64_t> ccost(ncombo, 0);
-            for (int64_t u = 0; u < r.n; ++u) {
-                const GemmTile &t = split[r.off + u];
-                const int cb = t.cls * S + t.pad;
-                units[cb].push_back(u);
-                ccost[cb] += cost[u];
-            }
-            std::vector<int> corder(ncombo);
-            for (int c = 0; c < ncombo; ++c)
-                corder[c] = c;
-            std::stable_sort(corder.begin(), corder.end(), [&](int a, int b) { return ccost[a] > ccost[b]; });
-            std::vector<std::vector<int64_t>> xl(kXcd);
-            std::vector<int64_t> xload(kXcd, 0);
-            for (int c : corder) {
-                if (units[c].empty())
-                    continue;
-                const int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
-                std::stable_sort(units[c].begin(), units[c].end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-                xl[x].insert(xl[x].end(), units[c].begin(), units[c].end());
-                xload[x] += ccost[c];
-            }
-            size_t len = 0;
-            for (const auto &v : xl)
-                len = std::max(len, v.size());
-            p->m2l_order.off = (int64_t)split.size();
-            p->m2l_order.n = (int64_t)len * kXcd;
-            split.reserve(split.size() + len * kXcd);
-            GemmTile empty = split[r.off];
-            empty.ncol = 0;
-            for (size_t k = 0; k < len; ++k)
-                for (int x = 0; x < kXcd; ++x) {
-                    const GemmTile t = k < xl[x].size() ? split[r.off + xl[x][k]] : empty;
-                    split.push_back(t);
+            const int64_t T = (int64_t)item_tile.size();
+            const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
+            const int64_t P = std::max<int64_t>(1, std::min<int64_t>(GRAV_M2L_WAVES / (4 / nc), T));
+            std::vector<int32_t> seg, wgseg(P + 1, 0), tseg_n(r.n + 1, 0);
+            for (int64_t w = 0; w < P; ++w) {
+                wgseg[w] = (int32_t)(seg.size() / 4);
+                const int64_t ie = (w + 1) * T / P;
+                for (int64_t i = w * T / P; i < ie;) {
+                    int64_t j = i;
+                    while (j < ie && item_tile[j] == item_tile[i])
+                        ++j;
+                    seg.insert(seg.end(), {item_tile[i], (int32_t)i, (int32_t)j, 0});
+                    ++tseg_n[item_tile[i] + 1];
+                    i = j;
                 }
+            }
+            const int64_t nseg = (int64_t)seg.size() / 4;
+            wgseg[P] = (int32_t)nseg;
+            // per tile, its segments in workgroup order
+            std::vector<int32_t> tseg_start(r.n + 1, 0), tsegs(nseg), fill(r.n, 0);
+            for (int64_t u = 0; u < r.n; ++u)
+                tseg_start[u + 1] = tseg_start[u] + tseg_n[u + 1];
+            for (int64_t sgi = 0; sgi < nseg; ++sgi) {
+                const int32_t u = seg[4 * sgi];
+                tsegs[tseg_start[u] + fill[u]++] = (int32_t)sgi;
+            }
+            if (item_off.empty())
+                item_off.push_back(0);
+            GRAV_CHECK(upload(p, &p->d_m2l_items, item_off));
+            GRAV_CHECK(upload(p, &p->d_m2l_segs, seg.empty() ? std::vector<int32_t>(4, 0) : seg));
+            GRAV_CHECK(upload(p, &p->d_m2l_wgseg, wgseg));
+            GRAV_CHECK(upload(p, &p->d_m2l_tseg_start, tseg_start));
+            GRAV_CHECK(upload(p, &p->d_m2l_tsegs, tsegs.empty() ? std::vector<int32_t>(1, 0) : tsegs));
+            GRAV_CHECK(upload(p, &p->d_m2l_colmap, colmap));
+            p->m2l_wgs = T > 0 ? (int32_t)P : 0;
+            p->m2l_nseg = nseg;
+            p->m2l_items = T;
         }
     }
     if (!split.empty())
@@ -1365,9 +1363,7 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
         }
         {
             // partial expansions of split M2L stages
-            size_t part = 0;
-            if (p->split[TK_M2L] > 1)
-                part = std::max(part, (size_t)p->split[TK_M2L] * p->n_tbox * p->B * p->PS);
+            size_t part = (size_t)p->m2l_nseg * 64 * p->PS;  // forward M2L segment slots
             if (p->split[TK_M2LT] > 1)
                 part = std::max(part, (size_t)p->split[TK_M2LT] * p->n_me * p->B * p->PS);
             if ((st = dalloc(p, &p->d_part, part, false)) != GRAV_OK)
