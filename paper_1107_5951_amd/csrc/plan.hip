@@ -662,7 +662,10 @@ grav_status build_tiles(Plan *p)
             }
             const int64_t T = (int64_t)item_tile.size();
             const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
-            const int64_t P = std::max<int64_t>(1, std::min<int64_t>(GRAV_M2L_WAVES / (4 / nc), T));
+            // at least kMinItems items per workgroup: small plans get fewer
+            // workgroups rather than one partial slot per item
+            constexpr int64_t kMinItems = 8;
+            const int64_t P = std::max<int64_t>(1, std::min<int64_t>(GRAV_M2L_WAVES / (4 / nc), T / kMinItems));
             std::vector<int32_t> seg, wgseg(P + 1, 0), tseg_n(r.n + 1, 0);
             for (int64_t w = 0; w < P; ++w) {
                 wgseg[w] = (int32_t)(seg.size() / 4);
