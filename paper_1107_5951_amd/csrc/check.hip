@@ -224,14 +224,15 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
 
     if (L >= 2 && ck.ok) {
         // the forward M2L's stream-K schedule: segments cover every work item
-        // once, in order, one tile per segment; each tile lists its segments
-        // in order; every LE column maps to one valid (tile, column)
+        // once, in order, one unit per segment; each unit lists its segments
+        // in order; every LE column maps to one valid (unit, column)
         const TileRange &r = p->tiles[TK_M2L][0];
         if (p->m2l_wgs > 0) {
             const auto items = fetch(p->d_m2l_items, (size_t)p->m2l_items);
             const auto segs = fetch(p->d_m2l_segs, (size_t)p->m2l_nseg * 4);
             const auto wgseg = fetch(p->d_m2l_wgseg, (size_t)p->m2l_wgs + 1);
-            const auto tstart = fetch(p->d_m2l_tseg_start, (size_t)r.n + 1);
+            const int64_t nunit = p->m2l_nunit, upt = 64 / p->m2l_ncw;
+            const auto tstart = fetch(p->d_m2l_tseg_start, (size_t)nunit + 1);
             const auto tsegs = fetch(p->d_m2l_tsegs, (size_t)std::max<int64_t>(1, p->m2l_nseg));
             const auto colmap = fetch(p->d_m2l_colmap, (size_t)(p->n_tbox * p->B));
             if (wgseg[0] != 0 || wgseg[p->m2l_wgs] != p->m2l_nseg)
@@ -239,7 +240,7 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
             int64_t next = 0;
             for (int64_t sg = 0; sg < p->m2l_nseg && ck.ok; ++sg) {
                 const int32_t t = segs[4 * sg], ib = segs[4 * sg + 1], ie = segs[4 * sg + 2];
-                if (t < 0 || t >= r.n || ib != next || ie <= ib || ie > p->m2l_items)
+                if (t < 0 || t >= nunit || ib != next || ie <= ib || ie > p->m2l_items)
                     ck.fail("m2l", "segment out of order or range", sg, t);
                 for (int32_t it = ib; it < ie && ck.ok; ++it)
                     if (items[it] < 0 || items[it] >= kClassOffsets)
@@ -248,17 +249,19 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
             }
             if (ck.ok && next != p->m2l_items)
                 ck.fail("m2l", "segments do not cover the work items", next, p->m2l_items);
-            if (ck.ok && (tstart[0] != 0 || tstart[r.n] != p->m2l_nseg))
-                ck.fail("m2l", "tile segment lists do not cover the segments", tstart[r.n], p->m2l_nseg);
-            for (int64_t t = 0; t < r.n && ck.ok; ++t)
+            if (ck.ok && (tstart[0] != 0 || tstart[nunit] != p->m2l_nseg))
+                ck.fail("m2l", "unit segment lists do not cover the segments", tstart[nunit], p->m2l_nseg);
+            for (int64_t t = 0; t < nunit && ck.ok; ++t)
                 for (int32_t j = tstart[t]; j < tstart[t + 1] && ck.ok; ++j)
                     if (tsegs[j] < 0 || tsegs[j] >= p->m2l_nseg || segs[4 * tsegs[j]] != t ||
                         (j > tstart[t] && tsegs[j] <= tsegs[j - 1]))
-                        ck.fail("m2l", "tile segment list inconsistent", t, j);
+                        ck.fail("m2l", "unit segment list inconsistent", t, j);
             for (int64_t c = 0; c < p->n_tbox * p->B && ck.ok; ++c) {
                 const int32_t m = colmap[c];
-                if (m < 0 || (m >> 6) >= r.n || (m & 63) >= tiles[r.off + (m >> 6)].ncol)
-                    ck.fail("m2l", "LE column without a tile column", c, m);
+                const int64_t u = m >> 6;
+                if (m < 0 || u >= nunit || (m & 63) >= p->m2l_ncw ||
+                    (u % upt) * p->m2l_ncw + (m & 63) >= tiles[r.off + u / upt].ncol)
+                    ck.fail("m2l", "LE column without a unit column", c, m);
             }
         }
     }

@@ -264,13 +264,13 @@ template __global__ void k_sum_parts<double>(const double *, int, int64_t, doubl
 template __global__ void k_sum_parts<float>(const float *, int, int64_t, double *);
 
 // LE from the forward M2L's segment slots: element (column, k) of the LE is
-// the sum, over the segments of the column's tile in their order, of the
-// slot entry (column in tile, k), in FP64.  A tile without segments (no
+// the sum, over the segments of the column's unit in their order, of the
+// slot entry (column in unit, k), in FP64.  A unit without segments (no
 // source box at any offset) gives zero.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_m2l_sum(const T *part, const int32_t *colmap, const int32_t *tseg_start, const int32_t *tsegs, int64_t n, int PS,
-          double *le)
+          int ncw, double *le)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
@@ -281,13 +281,13 @@ k_m2l_sum(const T *part, const int32_t *colmap, const int32_t *tseg_start, const
     const int t = m >> 6, cl = m & 63;
     double acc = 0.0;
     for (int j = tseg_start[t]; j < tseg_start[t + 1]; ++j)
-        acc += (double)part[((int64_t)tsegs[j] * 64 + cl) * PS + k];
+        acc += (double)part[((int64_t)tsegs[j] * ncw + cl) * PS + k];
     le[i] = acc;
 }
 template __global__ void k_m2l_sum<double>(const double *, const int32_t *, const int32_t *, const int32_t *,
-                                           int64_t, int, double *);
+                                           int64_t, int, int, double *);
 template __global__ void k_m2l_sum<float>(const float *, const int32_t *, const int32_t *, const int32_t *,
-                                          int64_t, int, double *);
+                                          int64_t, int, int, double *);
 
 // --------------------------------------------------------------------------
 // Near field (P2P): direct sum over the quadrature points of the cells of the
@@ -965,11 +965,11 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
             if (p->d.precision == GRAV_FP64)
                 hipLaunchKernelGGL(k_m2l_sum<double>, gs, dim3(256), 0, s, (const double *)p->d_part,
                                    (const int32_t *)p->d_m2l_colmap, (const int32_t *)p->d_m2l_tseg_start,
-                                   (const int32_t *)p->d_m2l_tsegs, n, p->PS, p->d_le);
+                                   (const int32_t *)p->d_m2l_tsegs, n, p->PS, p->m2l_ncw, p->d_le);
             else
                 hipLaunchKernelGGL(k_m2l_sum<float>, gs, dim3(256), 0, s, (const float *)p->d_part,
                                    (const int32_t *)p->d_m2l_colmap, (const int32_t *)p->d_m2l_tseg_start,
-                                   (const int32_t *)p->d_m2l_tsegs, n, p->PS, p->d_le);
+                                   (const int32_t *)p->d_m2l_tsegs, n, p->PS, p->m2l_ncw, p->d_le);
             GRAV_HIP(hipGetLastError());
             stage_end(p, s);
         }

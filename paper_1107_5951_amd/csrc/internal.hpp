@@ -92,11 +92,11 @@ struct Plan {
     TileRange tiles[TK_COUNT][kMaxLevels + 1];
     int split[TK_COUNT] = {1, 1};
     // stream-K schedule of the forward M2L (see build_tiles): work items
-    // (offset index per item, tile by tile), segments {tile, first item,
-    // end item, 0} per workgroup (wgseg: CSR over workgroups), per tile its
-    // segment slots (CSR), and LE column -> 64 * tile + column in tile
-    int32_t m2l_wgs = 0;
-    int64_t m2l_nseg = 0, m2l_items = 0;
+    // (offset index per item, unit by unit), segments {unit, first item,
+    // end item, 0} per workgroup (wgseg: CSR over workgroups), per unit its
+    // segment slots (CSR), and LE column -> 64 * unit + column in unit
+    int32_t m2l_wgs = 0, m2l_ncw = 64;  // workgroups (one wave each); columns per unit
+    int64_t m2l_nseg = 0, m2l_items = 0, m2l_nunit = 0;
     int32_t *d_m2l_items = nullptr, *d_m2l_segs = nullptr, *d_m2l_wgseg = nullptr;
     int32_t *d_m2l_tseg_start = nullptr, *d_m2l_tsegs = nullptr, *d_m2l_colmap = nullptr;
     // near field of voxel-centre targets by lattice matrices (b <= 4)

@@ -13,15 +13,15 @@ namespace grav {
 
 // --------------------------------------------------------------------------
 // M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
-// child-parity class, model); its work items are the class's interaction-
-// list offsets d at which some column has a source box.  A workgroup runs
-// its segments (a tile and a contiguous run of its items, see the stream-K
-// schedule in build_tiles) one after the other; it has 4 / NC waves, wave w
-// owning the NC blocks of 16 columns 16 (NC w + c), c < NC, and all row
-// blocks.  For each d the wave accumulates LE[:, col] += K_d * ME[box(col) + d]
-// with 16x16x4 MFMA tiles in registers across the segment's offsets (no
-// atomics), then writes the segment's partial to its slot; every A fragment
-// loaded feeds NC instructions.
+// child-parity class, model), split into 4 / NC units of 16 NC columns; a
+// unit's work items are the class's interaction-list offsets d at which some
+// of its columns has a source box.  A workgroup is one wave; it runs its
+// segments (a unit and a contiguous run of its items, see the stream-K
+// schedule in build_tiles) one after the other, holding the unit's NC blocks
+// of 16 columns and all row blocks.  For each d it accumulates
+// LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA tiles in registers
+// across the segment's offsets (no atomics), then writes the segment's
+// partial to its slot; every A fragment loaded feeds NC instructions.
 //
 // Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
 // instruction take coefficient c = 4 ks + kr, so the coefficients c >= p^2
@@ -42,24 +42,25 @@ namespace grav {
 #endif
 
 template <int RB, int KSV, int NC, typename T>
-__global__ void __launch_bounds__(256 / NC) GRAV_M2L_OCC
+__global__ void __launch_bounds__(64) GRAV_M2L_OCC
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
       const int32_t *class_off, const T *K, const T *me, const int32_t *segs, const int32_t *wgseg,
       const int32_t *items, T *part)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x;  // one wave per workgroup
+    constexpr int UPT = 4 / NC;      // units (waves' column blocks) per tile
     for (int sg = wgseg[blockIdx.x]; sg < wgseg[blockIdx.x + 1]; ++sg) {
-        const int32_t *sd = segs + 4 * sg;  // tile, first item, end item
-        const GemmTile tile = tiles[sd[0]];
+        const int32_t *sd = segs + 4 * sg;  // unit, first item, end item
+        const GemmTile tile = tiles[sd[0] / UPT];
+        const int hq = sd[0] % UPT;       // the unit's column block in the tile
         const DevLev &lv = g.lev[tile.level];
         bool cvalid[NC];
         int bm[NC], bx[NC], by[NC], bz[NC];
         int64_t box[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const int cl = (wave * NC + c) * 16 + (lane & 15);
+            const int cl = (hq * NC + c) * 16 + (lane & 15);
             cvalid[c] = cl < tile.ncol;
             const int64_t col = tile.col0 + cl;
             bm[c] = (int)(col % g.B);
@@ -175,14 +176,14 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         }
         // Output fragment: lane holds column lane % 16 and four rows; the FP32
         // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.
-        // The segment's partial LE goes to its own slot [64 columns][PS].
+        // The segment's partial LE goes to its own slot [16 NC columns][PS].
         constexpr int rstride = sizeof(T) == 8 ? 4 : 1;
         const int rbase = sizeof(T) == 8 ? kr : 4 * kr;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (!cvalid[c])
                 continue;
-            T *dst = part + ((int64_t)sg * 64 + (wave * NC + c) * 16 + (lane & 15)) * PS;
+            T *dst = part + ((int64_t)sg * (16 * NC) + c * 16 + (lane & 15)) * PS;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -199,7 +200,7 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     if (r.n == 0 || p->m2l_wgs == 0)
         return GRAV_OK;
     constexpr int NC = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;  // column blocks per wave
-    dim3 grid(p->m2l_wgs), blk(256 / NC);
+    dim3 grid(p->m2l_wgs), blk(64);
     T *part = reinterpret_cast<T *>(p->d_part);  // segment slots (sized for FP64)
     const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see k_me_gather)
 #define M2L_CASE(P)                                                                             \

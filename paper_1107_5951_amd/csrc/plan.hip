@@ -22,8 +22,9 @@
 #ifndef GRAV_M2L_TARGET_WG
 #define GRAV_M2L_TARGET_WG 8192
 #endif
-// Waves of the forward M2L's stream-K schedule: all resident at once
-// (256 CUs x 4 SIMDs x 2 waves; both M2L kernels fit two waves per SIMD).
+// One-wave workgroups of the forward M2L's stream-K schedule: all resident
+// at once (256 CUs x 4 SIMDs x 2 waves; both M2L kernels fit two waves per
+// SIMD).
 #ifndef GRAV_M2L_WAVES
 #define GRAV_M2L_WAVES 2048
 #endif
@@ -600,15 +601,16 @@ grav_status build_tiles(Plan *p)
         r.off = off;
         r.n *= S;
     }
-    // Stream-K schedule of the forward M2L.  Work items are the (tile,
-    // offset) pairs in which some column of the tile has a source box (the
-    // others cost nothing), listed tile by tile.  A fixed number of
-    // workgroups, all resident at once, take equal contiguous shares of the
-    // list; a workgroup's share is cut into segments at tile boundaries, and
-    // each segment writes the partial LE of its tile's columns to a slot of
-    // its own.  k_m2l_sum then adds, per tile, its segments' slots in order
-    // (deterministic).  The work is balanced to one item per workgroup and
-    // there are at most (tiles + workgroups) partial slots.
+    // Stream-K schedule of the forward M2L.  A unit is the 16 NC columns of
+    // one wave of a tile; work items are the (unit, offset) pairs in which
+    // some column of the unit has a source box (the others cost nothing), so
+    // every item costs the same.  A fixed number of one-wave workgroups, all
+    // resident at once, take equal contiguous shares of the item list; a
+    // share is cut into segments at unit boundaries, and each segment writes
+    // the partial LE of its unit's columns to a slot of its own.  k_m2l_sum
+    // then adds, per unit, its segments' slots in order (deterministic).  The
+    // work is balanced to one item per wave and there are at most
+    // (units + workgroups) partial slots.
     p->m2l_wgs = 0;
     p->m2l_nseg = 0;
     {
@@ -631,42 +633,48 @@ grav_status build_tiles(Plan *p)
                 }
             }
             GRAV_HIP(hipStreamSynchronize(p->bs));
-            std::vector<int32_t> item_tile, item_off;
+            // a unit is the columns of one wave: 16 NC columns of a tile
+            const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
+            const int ncw = 16 * nc, upt = 4 / nc;
+            const int64_t nunit = r.n * upt;
+            std::vector<int32_t> item_tile, item_off;  // item_tile holds the unit
             std::vector<int32_t> colmap((size_t)p->n_tbox * B, -1);
             std::vector<char> hit(kClassOffsets);
             for (int64_t u = 0; u < r.n; ++u) {
                 const GemmTile &t = split[r.off + u];
                 const LevelInfo &lv = p->lev[t.level];
-                std::fill(hit.begin(), hit.end(), 0);
-                for (int cl = 0; cl < t.ncol; ++cl) {
-                    const int64_t col = t.col0 + cl;
-                    const int32_t box = ord[t.level][lv.class_start[t.cls] + col / B];
-                    colmap[(size_t)((lv.tgt_off + box) * B + col % B)] = (int32_t)(u * 64 + cl);
-                    const uint32_t k = key[t.level][box];
-                    const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
-                    for (int o = 0; o < kClassOffsets; ++o) {
-                        const int32_t *e = &fwd[((size_t)t.cls * kClassOffsets + o) * 4];
-                        bool in = true;
-                        for (int a = 0; a < 3; ++a) {
-                            const int s = c[a] + e[a] - lv.s0[a];
-                            in = in && s >= 0 && s < lv.ns[a];
+                for (int hq = 0; hq < upt; ++hq) {
+                    std::fill(hit.begin(), hit.end(), 0);
+                    for (int cl = hq * ncw; cl < std::min(t.ncol, (hq + 1) * ncw); ++cl) {
+                        const int64_t col = t.col0 + cl;
+                        const int32_t box = ord[t.level][lv.class_start[t.cls] + col / B];
+                        colmap[(size_t)((lv.tgt_off + box) * B + col % B)] =
+                            (int32_t)((u * upt + hq) * 64 + cl - hq * ncw);
+                        const uint32_t k = key[t.level][box];
+                        const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+                        for (int o = 0; o < kClassOffsets; ++o) {
+                            const int32_t *e = &fwd[((size_t)t.cls * kClassOffsets + o) * 4];
+                            bool in = true;
+                            for (int a = 0; a < 3; ++a) {
+                                const int s = c[a] + e[a] - lv.s0[a];
+                                in = in && s >= 0 && s < lv.ns[a];
+                            }
+                            hit[o] |= in;
                         }
-                        hit[o] |= in;
                     }
+                    for (int o = 0; o < kClassOffsets; ++o)
+                        if (hit[o]) {
+                            item_tile.push_back((int32_t)(u * upt + hq));
+                            item_off.push_back(o);
+                        }
                 }
-                for (int o = 0; o < kClassOffsets; ++o)
-                    if (hit[o]) {
-                        item_tile.push_back((int32_t)u);
-                        item_off.push_back(o);
-                    }
             }
             const int64_t T = (int64_t)item_tile.size();
-            const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
             // at least kMinItems items per workgroup: small plans get fewer
             // workgroups rather than one partial slot per item
             constexpr int64_t kMinItems = 8;
-            const int64_t P = std::max<int64_t>(1, std::min<int64_t>(GRAV_M2L_WAVES / (4 / nc), T / kMinItems));
-            std::vector<int32_t> seg, wgseg(P + 1, 0), tseg_n(r.n + 1, 0);
+            const int64_t P = std::max<int64_t>(1, std::min<int64_t>(GRAV_M2L_WAVES, T / kMinItems));
+            std::vector<int32_t> seg, wgseg(P + 1, 0), tseg_n(nunit + 1, 0);
             for (int64_t w = 0; w < P; ++w) {
                 wgseg[w] = (int32_t)(seg.size() / 4);
                 const int64_t ie = (w + 1) * T / P;
@@ -681,9 +689,9 @@ grav_status build_tiles(Plan *p)
             }
             const int64_t nseg = (int64_t)seg.size() / 4;
             wgseg[P] = (int32_t)nseg;
-            // per tile, its segments in workgroup order
-            std::vector<int32_t> tseg_start(r.n + 1, 0), tsegs(nseg), fill(r.n, 0);
-            for (int64_t u = 0; u < r.n; ++u)
+            // per unit, its segments in workgroup order
+            std::vector<int32_t> tseg_start(nunit + 1, 0), tsegs(nseg), fill(nunit, 0);
+            for (int64_t u = 0; u < nunit; ++u)
                 tseg_start[u + 1] = tseg_start[u] + tseg_n[u + 1];
             for (int64_t sgi = 0; sgi < nseg; ++sgi) {
                 const int32_t u = seg[4 * sgi];
@@ -700,6 +708,8 @@ grav_status build_tiles(Plan *p)
             p->m2l_wgs = T > 0 ? (int32_t)P : 0;
             p->m2l_nseg = nseg;
             p->m2l_items = T;
+            p->m2l_ncw = ncw;
+            p->m2l_nunit = nunit;
         }
     }
     if (!split.empty())
@@ -1366,7 +1376,7 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
         }
         {
             // partial expansions of split M2L stages
-            size_t part = (size_t)p->m2l_nseg * 64 * p->PS;  // forward M2L segment slots
+            size_t part = (size_t)p->m2l_nseg * p->m2l_ncw * p->PS;  // forward M2L segment slots
             if (p->split[TK_M2LT] > 1)
                 part = std::max(part, (size_t)p->split[TK_M2LT] * p->n_me * p->B * p->PS);
             if ((st = dalloc(p, &p->d_part, part, false)) != GRAV_OK)
