@@ -1,5 +1,7 @@
 // M2L on MFMA for the forward pass (kept in its own file: its measured HBM
 // traffic is tied to this source).
+#include <type_traits>
+
 #include "resolve.hpp"
 
 // Largest per-lane A chunk (bytes) for which the M2L keeps two register
@@ -90,7 +92,15 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         const int64_t pstr = nB * 4;
         const T *mlev = me + lv.me_off * g.B * PS + kr * pstr;
         constexpr int64_t kstride = (int64_t)RB * 64 * 4 * RB;  // elements per offset matrix
-        for (int it = sd[1]; it < sd[2]; ++it) {
+        // One work item = one offset d of the unit (every item has a source
+        // box for some column of the unit).  Its B pointers, operator and
+        // column mask:
+        struct Item {
+            const T *mp[NC];
+            const T *kp;
+            bool have[NC];
+        };
+        auto setup = [&](int it, Item &st) {
             const int o = items[it];
             const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
             const int id = offs[4 * o + 3];
@@ -98,79 +108,120 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
             int first[3], cnt[3];
             const int64_t cstart =
                 class_split(lv, tile.cls ^ ((dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2)), first, cnt);
-            bool have[NC];
-            const T *mp[NC];
-            bool any = false;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int ax = bx[c] + dx, ay = by[c] + dy, az = bz[c] + dz;
                 const int sx = ax - lv.s0[0], sy = ay - lv.s0[1], sz = az - lv.s0[2];
-                have[c] = cvalid[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
-                          sz < lv.ns[2];
+                st.have[c] = cvalid[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] && sy < lv.ns[1] &&
+                             sz < lv.ns[2];
                 const int64_t pos = cstart + ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
                                     ((ax - first[0]) >> 1);
-                mp[c] = mlev + (have[c] ? (pos * g.B + bm[c]) * 4 : 0);
-                any = any || have[c];
+                st.mp[c] = mlev + (st.have[c] ? (pos * g.B + bm[c]) * 4 : 0);
             }
-            if (__ballot(any) == 0ull)
-                continue;  // no column of this wave sees a source box at this offset
-            const T *kp = K + (int64_t)id * kstride;
-            // two register sets (when they fit): the loads of chunk q + 1 are in
-            // flight while the instructions of chunk q run
-            constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
-            T av[NSET][4 * RB];
-            T bb[NSET][NC][4];
-            auto load = [&](int q, int set) {
+            st.kp = K + (int64_t)id * kstride;
+        };
+        // two register sets (when they fit): the loads of chunk q + 1 (or of
+        // the next item's first chunk) are in flight while the instructions
+        // of chunk q run
+        constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
+        T av[NSET][4 * RB];
+        T bb[NSET][NC][4];
+        auto load = [&](const Item &st, int q, int set) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                load4(st.mp[c] + (int64_t)q * 4 * pstr, bb[set][c]);
+            load_frags<T, 4 * RB>(st.kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
+        };
+        auto compute = [&](const Item &st, int q, int set) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (4 * q + u >= KSV)
+                    break;  // k steps past the last coefficient are all zero
+                T bv[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
-                    load4(mp[c] + (int64_t)q * 4 * pstr, bb[set][c]);
-                load_frags<T, 4 * RB>(kp + (int64_t)q * 64 * 4 * RB, lane, av[set]);
-            };
-            auto compute = [&](int q, int set) {
+                    bv[c] = st.have[c] ? bb[set][c][u] : (T)0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (4 * q + u >= KSV)
-                        break;  // k steps past the last coefficient are all zero
-                    T bv[NC];
+                for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                    for (int c = 0; c < NC; ++c)
-                        bv[c] = have[c] ? bb[set][c][u] : (T)0;
+                    for (int c = 0; c < NC; ++c) {
+                        if constexpr (sizeof(T) == 8)
+                            acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[c],
+                                                                              acc[c][rb], 0, 0, 0);
+                        else
+                            acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[c],
+                                                                              acc[c][rb], 0, 0, 0);
+                    }
+            }
+        };
+        constexpr int NLD = NC + 4 * RB * (int)sizeof(T) / 16, NMF = 4 * RB * NC;
+        const int ib = sd[1], ie = sd[2];
+        if constexpr (NSET == 2 && sizeof(T) == 4) {
+            // item k's chunk q uses register set (P0 + q) & 1, P0 = parity of
+            // the chunks before it; items are handled in pairs so that P0 is
+            // a compile-time constant
+            auto item = [&](auto p0, int it, const Item &cur, Item &nxt) {
+                constexpr int P0 = decltype(p0)::value;
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) {
-                            if constexpr (sizeof(T) == 8)
-                                acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[c],
-                                                                                  acc[c][rb], 0, 0, 0);
-                            else
-                                acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[c],
-                                                                                  acc[c][rb], 0, 0, 0);
-                        }
+                for (int q = 0; q < QC; ++q) {
+                    if (q + 1 < QC) {
+                        // the loads of chunk q + 1 issue one by one between
+                        // this chunk's instructions
+                        load(cur, q + 1, (P0 + q + 1) & 1);
+                        compute(cur, q, (P0 + q) & 1);
+                        interleave_loads<NLD, NMF>();
+                    } else if (it + 1 < ie) {
+                        // last chunk: the next item's first loads instead
+                        setup(it + 1, nxt);
+                        load(nxt, 0, (P0 + QC) & 1);
+                        compute(cur, q, (P0 + q) & 1);
+                        interleave_loads<NLD, NMF>();
+                    } else {
+                        compute(cur, q, (P0 + q) & 1);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             };
-            if constexpr (NSET == 2) {
-                load(0, 0);
+            Item A, Bn;
+            if (ib < ie) {
+                setup(ib, A);
+                load(A, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            for (int it = ib; it < ie; it += 2) {
+                item(std::integral_constant<int, 0>{}, it, A, Bn);
+                if (it + 1 < ie)
+                    item(std::integral_constant<int, QC & 1>{}, it + 1, Bn, A);
+            }
+        } else if constexpr (NSET == 2) {
+            // FP64: the cross-item prefetch would need the registers of a
+            // second wave per SIMD; pipeline within each item only
+            for (int it = ib; it < ie; ++it) {
+                Item A;
+                setup(it, A);
+                load(A, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int q = 0; q < QC; ++q) {
                     if (q + 1 < QC) {
-                        // the loads of chunk q + 1 issue one by one between this
-                        // chunk's instructions, so the matrix pipe keeps running
-                        // while the wave feeds the memory pipeline
-                        load(q + 1, (q + 1) & 1);
-                        compute(q, q & 1);
-                        interleave_loads<NC + 4 * RB * (int)sizeof(T) / 16, 4 * RB * NC>();
+                        load(A, q + 1, (q + 1) & 1);
+                        compute(A, q, q & 1);
+                        interleave_loads<NLD, NMF>();
                     } else {
-                        compute(q, q & 1);
+                        compute(A, q, q & 1);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
-            } else {
+            }
+        } else {
+            for (int it = ib; it < ie; ++it) {
+                Item A;
+                setup(it, A);
 #pragma unroll
                 for (int q = 0; q < QC; ++q) {
-                    load(q, 0);
+                    load(A, q, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    compute(q, 0);
+                    compute(A, q, 0);
                 }
             }
         }
