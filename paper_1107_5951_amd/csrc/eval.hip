@@ -279,9 +279,24 @@ k_m2l_sum(const T *part, const int32_t *colmap, const int32_t *tseg_start, const
     const int k = (int)(i - col * PS);
     const int32_t m = colmap[col];
     const int t = m >> 6, cl = m & 63;
+    const int j0 = tseg_start[t], j1 = tseg_start[t + 1];
     double acc = 0.0;
-    for (int j = tseg_start[t]; j < tseg_start[t + 1]; ++j)
-        acc += (double)part[((int64_t)tsegs[j] * ncw + cl) * PS + k];
+    // eight slots at a time: their indices, then their values, are loaded
+    // together (no chain of dependent loads); the sum stays in slot order
+    for (int jb = j0; jb < j1; jb += 8) {
+        int32_t sl[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            sl[u] = jb + u < j1 ? tsegs[jb + u] : -1;
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = sl[u] >= 0 ? part[((int64_t)sl[u] * ncw + cl) * PS + k] : (T)0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (jb + u < j1)
+                acc += (double)v[u];
+    }
     le[i] = acc;
 }
 template __global__ void k_m2l_sum<double>(const double *, const int32_t *, const int32_t *, const int32_t *,
@@ -459,7 +474,7 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
 #define GRAV_NEAR_DEPTH32 3
 #endif
 #ifndef GRAV_NEAR_DEPTH64
-#define GRAV_NEAR_DEPTH64 1
+#define GRAV_NEAR_DEPTH64 2
 #endif
 
 // --------------------------------------------------------------------------
