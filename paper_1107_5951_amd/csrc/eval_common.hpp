@@ -50,6 +50,35 @@ __host__ __device__ inline int64_t class_split(const DevLev &lv, int cls, int fi
     return start;
 }
 
+// The multipole expansions regathered for the M2L's B operand, in the
+// M2L's element type (float or double), written by P2M and M2M beside the
+// FP64 expansions.  Per level, boxes are ordered by parity class (x fastest
+// within a class, see class_split) and the coefficients chunk-major in the
+// M2L's interleaved contraction order:
+//   meg[level][q][kr][pos * B + model][u],  coefficient 4 (4 q + u) + kr.
+// The source boxes that one wave's 16 columns read at one interaction
+// offset are boxes of a single class with consecutive x, so each B fragment
+// load of the M2L covers a few contiguous runs instead of 64 scattered
+// lines.  meg_store puts coefficient t of box j (dense index in level lv's
+// source block), model bm, in place.
+__device__ inline void meg_store(const DevGeom &g, const DevLev &lv, int64_t j, int bm, int t, double v, void *meg,
+                                 bool f32)
+{
+    const int ax = lv.s0[0] + (int)(j % lv.ns[0]), ay = lv.s0[1] + (int)((j / lv.ns[0]) % lv.ns[1]),
+              az = lv.s0[2] + (int)(j / ((int64_t)lv.ns[0] * lv.ns[1]));
+    int first[3], cnt[3];
+    const int64_t pos = class_split(lv, (ax & 1) | ((ay & 1) << 1) | ((az & 1) << 2), first, cnt) +
+                        ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
+                        ((ax - first[0]) >> 1);
+    const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
+    const int q = t >> 4, u = (t >> 2) & 3, kr = t & 3;
+    const int64_t e = lv.me_off * g.B * g.PS + ((int64_t)(q * 4 + kr) * nB + pos * g.B + bm) * 4 + u;
+    if (f32)
+        static_cast<float *>(meg)[e] = (float)v;
+    else
+        static_cast<double *>(meg)[e] = v;
+}
+
 DevGeom make_geom(const Plan *p);
 template <typename T>
 __global__ void k_sum_parts(const T *part, int S, int64_t n, double *out);
