@@ -17,8 +17,7 @@ namespace grav {
 // so each operator entry it loads feeds LB multiply-adds.
 // --------------------------------------------------------------------------
 template <int LB>
-__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const double *pm, double *me, void *meg,
-                                             bool meg_f32)
+__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const double *pm, double *me)
 {
     extern __shared__ double sh[];  // [LB][b^3]
     const DevLev &lv = g.lev[g.L];
@@ -60,10 +59,8 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const
     }
 #pragma unroll
     for (int l = 0; l < LB; ++l)
-        if (col0 + l < ncol) {
+        if (col0 + l < ncol)
             me[(lv.me_off * g.B + col0 + l) * g.PS + t] = acc[l];
-            meg_store(g, lv, (col0 + l) / g.B, (int)((col0 + l) % g.B), t, acc[l], meg, meg_f32);
-        }
 }
 
 // --------------------------------------------------------------------------
@@ -75,7 +72,7 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const
 // --------------------------------------------------------------------------
 template <int RB>
 __global__ void __launch_bounds__(256)
-k_m2m_mfma(DevGeom g, int l, const double *A, double *me, void *meg, bool meg_f32)
+k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     __shared__ double red[4][256];
@@ -135,12 +132,9 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me, void *meg, bool meg_f3
     if (wave == 0 && cvalid) {
         double *dst = me + ((lp.me_off + box) * g.B + bm) * PS;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double v =
+        for (int r = 0; r < 4; ++r)
+            dst[16 * rb + kr + 4 * r] =
                 ((red[0][lane * 4 + r] + red[1][lane * 4 + r]) + red[2][lane * 4 + r]) + red[3][lane * 4 + r];
-            dst[16 * rb + kr + 4 * r] = v;
-            meg_store(g, lp, box, bm, 16 * rb + kr + 4 * r, v, meg, meg_f32);
-        }
     }
 }
 
@@ -211,6 +205,48 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
     for (int r = 0; r < 4; ++r)
         dst[16 * rb + kr + 4 * r] += acc[r];
 }
+
+// The multipole expansions regathered for the M2L's B operand, in the
+// M2L's element type.  Per level, boxes are ordered by parity class (x
+// fastest within a class, see class_split) and the coefficients chunk-major
+// in the M2L's interleaved contraction order:
+//   out[level][q][kr][pos * B + model][u],  coefficient 4 (4 q + u) + kr.
+// The source boxes that one wave's 16 columns read at one interaction offset
+// are boxes of a single class with consecutive x, so each B fragment load
+// of the M2L covers a few contiguous runs instead of 64 scattered lines.
+// One thread per (box, model, chunk q, sub-row kr).
+template <typename T>
+__global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, int64_t n_me, T *out)
+{
+    const int NP = g.PS / 4;  // (q, kr) planes
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_me * g.B * NP)
+        return;
+    const int plane = (int)(i % NP);
+    const int64_t col = i / NP;  // box * B + model
+    const int bm = (int)(col % g.B);
+    const int64_t box = col / g.B;
+    int l = 2;
+    while (l < g.L && box >= g.lev[l + 1].me_off)
+        ++l;
+    const DevLev &lv = g.lev[l];
+    const int64_t j = box - lv.me_off;
+    const int ax = lv.s0[0] + (int)(j % lv.ns[0]), ay = lv.s0[1] + (int)((j / lv.ns[0]) % lv.ns[1]),
+              az = lv.s0[2] + (int)(j / ((int64_t)lv.ns[0] * lv.ns[1]));
+    int first[3], cnt[3];
+    const int64_t pos = class_split(lv, (ax & 1) | ((ay & 1) << 1) | ((az & 1) << 2), first, cnt) +
+                        ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
+                        ((ax - first[0]) >> 1);
+    const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
+    const int q = plane / 4, kr = plane % 4;
+    const double *src = me + col * g.PS + 16 * q + kr;
+    T *dst = out + lv.me_off * g.B * g.PS + ((int64_t)plane * nB + pos * g.B + bm) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        dst[u] = (T)src[4 * u];
+}
+template __global__ void k_me_gather<double>(DevGeom, const double *, int64_t, double *);
+template __global__ void k_me_gather<float>(DevGeom, const double *, int64_t, float *);
 
 // out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ..., in FP64
 template <typename T>
@@ -804,8 +840,7 @@ static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
     const dim3 grid((unsigned)((p->lev[l].n_src * p->B + 15) / 16 * RB)), blk(256);
 #define M2M_CASE(R)                                                                             \
     case R:                                                                                     \
-        hipLaunchKernelGGL((k_m2m_mfma<R>), grid, blk, 0, s, g, l, (const double *)p->d_m2m_sw, p->d_me, \
-                           (void *)p->d_meg, p->d.precision != GRAV_FP64);                       \
+        hipLaunchKernelGGL((k_m2m_mfma<R>), grid, blk, 0, s, g, l, (const double *)p->d_m2m_sw, p->d_me); \
         break;
     switch (RB) {
         M2M_CASE(1)
@@ -912,13 +947,25 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         constexpr int LB = 8;  // columns per workgroup
         const int64_t ncol = p->lev[L].n_src * p->B;
         hipLaunchKernelGGL((k_p2m<LB>), dim3((unsigned)((ncol + LB - 1) / LB)), dim3((p->PS + 63) / 64 * 64),
-                           sizeof(double) * LB * b3, s, g, rho, (const double *)p->d_pm, p->d_me,
-                           (void *)p->d_meg, p->d.precision != GRAV_FP64);
+                           sizeof(double) * LB * b3, s, g, rho, (const double *)p->d_pm, p->d_me);
         GRAV_HIP(hipGetLastError());
         stage_end(p, s);
         stage_begin(p, "m2m", s);
         for (int l = L - 1; l >= 2; --l)
             GRAV_CHECK(launch_m2m(p, g, l, s));
+        stage_end(p, s);
+        stage_begin(p, "me_gather", s);
+        {
+            const int64_t n = p->n_me * p->B * (p->PS / 4);
+            const dim3 gg((unsigned)((n + 255) / 256));
+            if (p->d.precision == GRAV_FP64)
+                hipLaunchKernelGGL((k_me_gather<double>), gg, dim3(256), 0, s, g, (const double *)p->d_me, p->n_me,
+                                   p->d_meg);
+            else
+                hipLaunchKernelGGL((k_me_gather<float>), gg, dim3(256), 0, s, g, (const double *)p->d_me, p->n_me,
+                                   reinterpret_cast<float *>(p->d_meg));
+            GRAV_HIP(hipGetLastError());
+        }
         stage_end(p, s);
         stage_begin(p, "m2l", s);
         if (p->d.precision == GRAV_FP64)

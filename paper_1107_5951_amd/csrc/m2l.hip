@@ -253,7 +253,7 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     constexpr int NC = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;  // column blocks per wave
     dim3 grid(p->m2l_wgs), blk(64);
     T *part = reinterpret_cast<T *>(p->d_part);  // segment slots (sized for FP64)
-    const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see meg_store)
+    const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see k_me_gather)
 #define M2L_CASE(P)                                                                             \
     case P:                                                                                     \
         hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T>), grid, blk, 0, s, g,  \
