@@ -462,16 +462,20 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
     blk[((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm) * 4 + u] = (T)r;
 }
 
-// Lattice near-field tile per workgroup: GRAV_NEAR_RW row blocks x
-// GRAV_NEAR_CW column blocks of 16; chunks per software-pipeline step.
-#ifndef GRAV_NEAR_RW
-#define GRAV_NEAR_RW 2
+// Lattice near-field tile per workgroup: GRAV_NEAR_RW32 (FP32) or
+// GRAV_NEAR_RW64 (FP64) row blocks x GRAV_NEAR_CW column blocks of 16;
+// chunks per software-pipeline step.
+#ifndef GRAV_NEAR_RW32
+#define GRAV_NEAR_RW32 4
+#endif
+#ifndef GRAV_NEAR_RW64
+#define GRAV_NEAR_RW64 2
 #endif
 #ifndef GRAV_NEAR_CW
 #define GRAV_NEAR_CW 2
 #endif
 #ifndef GRAV_NEAR_DEPTH32
-#define GRAV_NEAR_DEPTH32 3
+#define GRAV_NEAR_DEPTH32 2
 #endif
 #ifndef GRAV_NEAR_DEPTH64
 #define GRAV_NEAR_DEPTH64 2
@@ -916,7 +920,8 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
     GRAV_HIP(hipGetLastError());
     const int64_t ncol = lv.n_src * p->B;
     const int RBn = p->lat_RB, Qn = p->lat_Q;
-    constexpr int RW = GRAV_NEAR_RW, CW = GRAV_NEAR_CW;
+    constexpr int CW = GRAV_NEAR_CW;
+    const int RW = f64 ? GRAV_NEAR_RW64 : GRAV_NEAR_RW32;
     const int nrg = (RBn + RW - 1) / RW;
     const int64_t ncg = (ncol + 16 * CW - 1) / (16 * CW);
     if (ncg * nrg > 0x7fffffffll)
@@ -924,11 +929,11 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
     dim3 grid((unsigned)(ncg * nrg)), blk(256);
     const int64_t npts = p->d.n_points;
     if (f64)
-        hipLaunchKernelGGL((k_near_lat<RW, CW, double>), grid, blk, 0, s, g, (const double *)p->d_rho_blk, nplB,
+        hipLaunchKernelGGL((k_near_lat<GRAV_NEAR_RW64, CW, double>), grid, blk, 0, s, g, (const double *)p->d_rho_blk, nplB,
                            (const double *)p->d_tn64, (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,
                            (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
     else
-        hipLaunchKernelGGL((k_near_lat<RW, CW, float>), grid, blk, 0, s, g, (const float *)p->d_rho_blk, nplB,
+        hipLaunchKernelGGL((k_near_lat<GRAV_NEAR_RW32, CW, float>), grid, blk, 0, s, g, (const float *)p->d_rho_blk, nplB,
                            (const float *)p->d_tn32, (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,
                            (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
     GRAV_HIP(hipGetLastError());
