@@ -284,7 +284,7 @@ def main():
     cand = {
         "m2l": (flops_m2l, "k_m2l<%d,%d,2,float> (M2L, FP32 MFMA 16x16x4)" % (-(-P2 // 16), -(-P2 // 4)), "mfma",
                 "fp32_mfma"),
-        "near_lat": (flops_near, "k_near_lat<2,2,float> (lattice near field, FP32 MFMA 16x16x4)", "mfma",
+        "near_lat": (flops_near, "k_near_lat<4,2,float> (lattice near field, FP32 MFMA 16x16x4)", "mfma",
                      "fp32_mfma"),
         "p2p": (flops_p2p, "k_p2p<float> (direct near field, FP32 VALU)", "alu", "fp32_vector"),
     }
