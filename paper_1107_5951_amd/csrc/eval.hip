@@ -66,16 +66,17 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const
 // --------------------------------------------------------------------------
 // M2M on MFMA (FP64): ME[parent] = sum over the 8 children c of T_c ME[child],
 // a GEMM with columns = (parent box, model) and K = 8 x p^2.  A workgroup
-// owns 16 columns and one 16-row block; its four waves take two children
-// each and their partial fragments are added through LDS.  Children outside
-// the source block contribute nothing.
+// owns 16 columns and one 16-row block; its eight waves take one child each
+// (so each wave waits on a single round of loads) and their partial
+// fragments are added through LDS in wave order.  Children outside the
+// source block contribute nothing.
 // --------------------------------------------------------------------------
 template <int RB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
-    __shared__ double red[4][256];
+    __shared__ double red[8][256];
     constexpr int PS = 16 * RB;
     constexpr int U = RB < 8 ? RB : 8;  // chunks of four k steps loaded together
     const int lane = threadIdx.x & 63;
@@ -94,8 +95,9 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
     const int kr = lane >> 4;
     vec4 acc = vec4{0, 0, 0, 0};
-    // wave w takes children 2w and 2w + 1
-    for (int c = 2 * wave; c < 2 * wave + 2; ++c) {
+    // wave w takes child w
+    {
+        const int c = wave;
         const int64_t ci = cvalid ? dense_index(lc, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1),
                                                 2 * pz + ((c >> 2) & 1))
                                   : -1;
@@ -124,7 +126,7 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
             }
         }
     }
-    // the four waves' fragments share one lane layout: add them in wave order
+    // the eight waves' fragments share one lane layout: add them in wave order
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         red[wave][lane * 4 + r] = acc[r];
@@ -132,9 +134,13 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     if (wave == 0 && cvalid) {
         double *dst = me + ((lp.me_off + box) * g.B + bm) * PS;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            dst[16 * rb + kr + 4 * r] =
-                ((red[0][lane * 4 + r] + red[1][lane * 4 + r]) + red[2][lane * 4 + r]) + red[3][lane * 4 + r];
+        for (int r = 0; r < 4; ++r) {
+            double v = red[0][lane * 4 + r];
+#pragma unroll
+            for (int w = 1; w < 8; ++w)
+                v += red[w][lane * 4 + r];
+            dst[16 * rb + kr + 4 * r] = v;
+        }
     }
 }
 
@@ -176,6 +182,15 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
     // B: column (lane % 16) of the parent LE, contraction order kr * PS/4 + ks
     const double2 *bp = (const double2 *)(le + (cvalid ? ((lp.tgt_off + par) * g.B + bm) * PS : 0) + kr * (PS / 4));
     const double *ap = A + ((int64_t)tile.cls * RB * RB + rb) * 256;  // [c][q][rb] sets of 4 per lane
+    // the child's LE (from the M2L) is read with the operands, not after the
+    // products: no other workgroup writes these entries during the launch
+    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
+    double old[4] = {0.0, 0.0, 0.0, 0.0};
+    if (cvalid) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            old[r] = dst[16 * rb + kr + 4 * r];
+    }
     constexpr int U = RB < 8 ? RB : 8;  // chunks of four k steps loaded together
     for (int q0 = 0; q0 < RB; q0 += U) {
         double av[U][4];
@@ -200,10 +215,9 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
     }
     if (!cvalid)
         return;
-    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        dst[16 * rb + kr + 4 * r] += acc[r];
+        dst[16 * rb + kr + 4 * r] = old[r] + acc[r];
 }
 
 // The multipole expansions regathered for the M2L's B operand, in the
@@ -281,19 +295,21 @@ k_m2l_sum(const T *part, const int32_t *colmap, const int32_t *tseg_start, const
     const int t = m >> 6, cl = m & 63;
     const int j0 = tseg_start[t], j1 = tseg_start[t + 1];
     double acc = 0.0;
-    // eight slots at a time: their indices, then their values, are loaded
-    // together (no chain of dependent loads); the sum stays in slot order
-    for (int jb = j0; jb < j1; jb += 8) {
-        int32_t sl[8];
+    // SB slots at a time: their indices, then their values, are loaded
+    // together (no chain of dependent loads); the sum stays in slot order.
+    // A unit typically spans fewer than SB shares, so one round usually does.
+    constexpr int SB = 16;
+    for (int jb = j0; jb < j1; jb += SB) {
+        int32_t sl[SB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < SB; ++u)
             sl[u] = jb + u < j1 ? tsegs[jb + u] : -1;
-        T v[8];
+        T v[SB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < SB; ++u)
             v[u] = sl[u] >= 0 ? part[((int64_t)sl[u] * ncw + cl) * PS + k] : (T)0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < SB; ++u)
             if (jb + u < j1)
                 acc += (double)v[u];
     }
@@ -841,7 +857,7 @@ void stage_end(Plan *p, hipStream_t s)
 static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
 {
     const int RB = p->PS / 16;
-    const dim3 grid((unsigned)((p->lev[l].n_src * p->B + 15) / 16 * RB)), blk(256);
+    const dim3 grid((unsigned)((p->lev[l].n_src * p->B + 15) / 16 * RB)), blk(512);
 #define M2M_CASE(R)                                                                             \
     case R:                                                                                     \
         hipLaunchKernelGGL((k_m2m_mfma<R>), grid, blk, 0, s, g, l, (const double *)p->d_m2m_sw, p->d_me); \
