@@ -125,6 +125,35 @@ def test_m2l_converges_in_p(d):
     assert errs[0] > errs[1] > errs[2] > errs[3]
 
 
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_translation_operators_couple_degrees_one_way(kind):
+    """Shifting a solid-harmonic expansion by delta multiplies degree-j terms
+    by regular harmonics R_{n-j}(delta): an M2M (kind 0) forms a parent's
+    degree n from child degrees j <= n, an L2L (kind 1) a child's degree j
+    from parent degrees n >= j, and the equal-degree term is R_0^0 = 1, so
+    the diagonal blocks are multiples of the identity that change by the
+    box-width ratio 1/2 from one degree to the next (2^-n for the M2M, whose
+    parent is twice the child's width)."""
+    p = 9
+    deg = np.array([int(np.sqrt(i)) for i in range(p * p)])
+    for which in range(8):
+        T = G.grav_operator(p, kind, which)
+        wrong = deg[:, None] < deg[None, :] if kind == 0 else deg[:, None] > deg[None, :]
+        assert np.all(T[wrong] == 0.0)
+        assert np.abs(T[~wrong & (deg[:, None] != deg[None, :])]).max() > 0.0
+        scale = []
+        for n in range(p):
+            blk = T[np.ix_(deg == n, deg == n)]
+            c = blk[0, 0]
+            np.testing.assert_allclose(blk, c * np.eye(2 * n + 1), rtol=0, atol=1e-15)
+            scale.append(c)
+        scale = np.array(scale)
+        np.testing.assert_allclose(scale[1:] / scale[:-1], 0.5, rtol=1e-14)
+        if kind == 0:
+            np.testing.assert_allclose(scale, 0.5 ** np.arange(p), rtol=1e-14)
+
+
 def test_operator_rejects_bad_arguments():
     with pytest.raises(G.GravError):
         G.grav_operator(8, 2, 0, (1, 0, 0))  # a neighbour, not in any interaction list
