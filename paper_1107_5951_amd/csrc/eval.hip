@@ -25,23 +25,32 @@ __global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const
     const int64_t ncol = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
     const int64_t col0 = (int64_t)blockIdx.x * LB;
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    for (int e = threadIdx.x; e < LB * b3; e += blockDim.x) {
-        const int l = e / b3, v = e - l * b3;
-        const int64_t col = col0 + l;
-        double r = 0.0;
-        if (col < ncol) {
-            const int64_t leaf = col / g.B;
-            const int bm = (int)(col - leaf * g.B);
-            const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
-                      lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
-            const int ix = (lv.s0[0] + lx - g.shift[0]) * b + v % b;
-            const int iy = (lv.s0[1] + ly - g.shift[1]) * b + (v / b) % b;
-            const int iz = (lv.s0[2] + lz - g.shift[2]) * b + v / (b * b);
-            if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
-                r = rho[bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+    // the leaf decomposition in the index type I: 32-bit whenever the column
+    // count allows (64-bit integer division is a long instruction sequence)
+    auto stage = [&](auto zero) {
+        using I = decltype(zero);
+        for (int e = threadIdx.x; e < LB * b3; e += blockDim.x) {
+            const int l = e / b3, v = e - l * b3;
+            const I col = (I)(col0 + l);
+            double r = 0.0;
+            if (col < (I)ncol) {
+                const I leaf = col / (I)g.B;
+                const int bm = (int)(col - leaf * (I)g.B);
+                const I ns0 = (I)lv.ns[0], ns1 = (I)lv.ns[1];
+                const int lx = (int)(leaf % ns0), ly = (int)((leaf / ns0) % ns1), lz = (int)(leaf / (ns0 * ns1));
+                const int ix = (lv.s0[0] + lx - g.shift[0]) * b + v % b;
+                const int iy = (lv.s0[1] + ly - g.shift[1]) * b + (v / b) % b;
+                const int iz = (lv.s0[2] + lz - g.shift[2]) * b + v / (b * b);
+                if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
+                    r = rho[bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+            }
+            sh[e] = r;
         }
-        sh[e] = r;
-    }
+    };
+    if (ncol + LB <= (int64_t)0x7fffffff)
+        stage(int32_t(0));
+    else
+        stage(int64_t(0));
     __syncthreads();
     const int t = threadIdx.x;
     if (t >= g.PS)
