@@ -224,8 +224,8 @@ def crossover(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solve would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
