@@ -1,23 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the FMM gravity forward model on one MI355X.
 
-Workload (the metric's configuration): 64^3 cells on the unit cube, 2-point
-Gauss rule per axis (2,097,152 source points), density = 32 seeded Gaussian
-blobs + U[-0.01, 0.01] noise, g (3 components) at all 262,144 cell centres,
-p = 10, mixed precision (FP32 P2P and FP32-MFMA M2L, FP64 expansions and
-combine).  A step is one full grav_eval (P2M, M2M, M2L, L2L, P2P, L2P +
-combine) with rho already resident in HBM.  The FP64 path is timed on the
-same workload at the smallest p that reaches rel err <= 1e-6 (p = 12), and its
-p = 10 error is reported beside it.
+Headline workload: 256^3 cells on the unit cube (16,777,216 cells), 1-point
+rule (one source point per cell), density = 64 seeded Gaussian blobs plus the
+constant-density prism [0.4, 0.6]^2 x [0.2, 0.5] (rho = 1), g (3 components)
+at 512 x 512 stations at z = 1.1 and at every cell centre (17,039,360
+targets), mixed precision, leaf edge 4 cells.  The expansion order is p = 10,
+the smallest order at which the mixed-precision solve meets rel err <= 1e-4
+both against the FP64 oracle on 4096 seeded targets and, for the prism alone,
+against its closed form; the workload's nominal p = 8 is timed beside it with
+its errors.  A step is one full grav_eval (P2M, M2M, M2L, L2L, lattice near
+field, P2P, L2P + combine) with rho already resident in HBM.  The FP64 solve
+of the same workload runs at p = 16, the smallest order meeting 1e-6 on both
+checks.
 
-Prints ONE JSON line (rank 0).  Extra fields: pair-equivalent throughput,
-p50/p99 step latency, relative L2 error against the FP64 oracle on a seeded
-sample of targets, the dominant kernel's roofline, the oracle's CPU
-throughput on that sample, and the FP64 result.
+Also reported (extra fields): the 64^3-cell, 2-point-rule volume workload
+(mixed p = 10 and FP64 p = 12), and the batched workload of 32 density
+models on one 128^3-cell tree with gz at 256 x 256 stations (mixed p = 10
+against FP64 p = 14, batched and as 32 single-model solves).
+
+Prints ONE JSON line.  Extra fields: pair-equivalent throughput, p50/p99 step
+latency, relative L2 error against the FP64 oracle on seeded targets, the
+dominant kernel's roofline, the oracle's CPU throughput (all cores and one
+thread).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,7 +39,8 @@ if ROOT not in sys.path:
 
 METRIC = "gz evals/s (src·tgt pairs/s equiv) at rel err ≤1e-6/1e-4; p50/p99 latency"
 PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vector": 157.3, "fp64_vector": 78.6}
-P2P_FLOP_PER_PAIR = 20.0  # Sec. 1.1 cost model: 5 add + 7 mul + 1 sqrt ~ 20 multiplications
+P2P_FLOP_PER_PAIR = 20.0  # Sec. 1.1 cost model: one kernel evaluation ~ 20 flops
+PRISM = ((0.4, 0.6), (0.4, 0.6), (0.2, 0.5))
 
 
 def parse():
@@ -37,15 +48,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=64)
-    ap.add_argument("--p", type=int, default=10)
-    ap.add_argument("--p64", type=int, default=12)
-    ap.add_argument("--leaf", type=int, default=512)
-    ap.add_argument("--sample", type=int, default=2048, help="oracle targets for cpu_baseline/rel_err")
+    ap.add_argument("--n", type=int, default=256, help="cells per axis of the headline mesh")
+    ap.add_argument("--p", type=int, default=10, help="expansion order of the headline (mixed) solve")
+    ap.add_argument("--p-nominal", type=int, default=8, help="the workload's nominal order, timed beside it")
+    ap.add_argument("--p64", type=int, default=16, help="expansion order of the FP64 solve")
+    ap.add_argument("--sample", type=int, default=4096, help="seeded oracle targets for rel_err")
+    ap.add_argument("--cpu-one-thread", type=int, default=32,
+                    help="targets of the one-thread oracle timing")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="headline only (no 64^3 or batched rows)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
-    ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum comparison")
     ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
                     help="only run the serving workload: COUNT Poisson requests (rate 50/s, n in [32, 192])")
     ap.add_argument("--paper-sequence", action="store_true",
@@ -57,26 +70,30 @@ def parse():
     return ap.parse_args()
 
 
+def say(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def timed_steps(plan, rho, out, steps, warmup):
+    """Wall time of `steps` evaluations on the current stream (HIP events),
+    after `warmup` untimed ones; per-step latencies for p50/p99."""
     import torch
     for _ in range(warmup):
         plan.eval(rho, out)
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    t0 = time.perf_counter()
     evs[0].record()
     for i in range(steps):
         plan.eval(rho, out)
         evs[i + 1].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     lat = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
-    total_ms = evs[0].elapsed_time(evs[steps])
-    return total_ms, lat, wall
+    return evs[0].elapsed_time(evs[steps]) / steps, lat
 
 
 def stage_profile(plan, rho, out, steps):
-    """Average per-stage duration (HIP events on the eval stream)."""
+    """Average per-stage duration: HIP events recorded by the library on the
+    evaluation stream around each stage's launches."""
     import torch
     plan.set_profiling(True)
     acc = {}
@@ -89,12 +106,11 @@ def stage_profile(plan, rho, out, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
-def measured_traffic(kernel_name):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None if it is for another kernel or the kernel sources have
-    changed since the counters were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "m2l_volume64_q2_hbm_traffic.md")
+def measured_traffic(profile, kernel_name):
+    """HBM bytes per launch of the dominant kernel from a committed counter
+    summary under profiles/, or None if it covers another kernel or the
+    kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(path).read()
     except OSError:
@@ -118,6 +134,304 @@ def pct(xs, q):
     return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
 
 
+def m2l_kernel_name(p, prec):
+    from paper_1107_5951_amd import GRAV_FP64
+    p2 = p * p
+    if prec == GRAV_FP64:
+        return "k_m2l<%d,%d,1,double>" % (-(-p2 // 16), -(-p2 // 4))
+    return "k_m2l<%d,%d,2,float>" % (-(-p2 // 16), -(-p2 // 4))
+
+
+def roofline(plan, stages, p, prec, profile):
+    """Roofline of the dominant stage: algorithmic flops per launch over the
+    stage's event-measured duration (one launch per evaluation)."""
+    from paper_1107_5951_amd import GRAV_FP64
+    m2l_pairs, p2p_pairs, _ = plan.work()
+    B = plan.spec.batch
+    b = plan.leaf_cells
+    n = plan.spec.n
+    n_leaf_src = 1
+    for a in range(3):
+        n_leaf_src *= -(-int(n[a]) // b)
+    f64 = prec == GRAV_FP64
+    mm = "fp64_mfma" if f64 else "fp32_mfma"
+    cand = {
+        "m2l": (2.0 * p ** 4 * m2l_pairs * B, m2l_kernel_name(p, prec) + " (M2L, %s MFMA 16x16x4)"
+                % ("FP64" if f64 else "FP32"), "mfma", mm),
+        "near_lat": (27 * 2.0 * (4 * b ** 3) * b ** 3 * n_leaf_src * B,
+                     "k_near_lat<%d,2,%s> (lattice near field, %s MFMA 16x16x4)"
+                     % ((2, "double", "FP64") if f64 else (4, "float", "FP32")), "mfma", mm),
+    }
+    if "near_lat" not in stages:
+        # every near pair is a direct (point) pair only without the lattice path
+        cand["p2p"] = (P2P_FLOP_PER_PAIR * p2p_pairs * B, "k_p2p (direct near field, VALU)", "alu",
+                       "fp64_vector" if f64 else "fp32_vector")
+    dom = max((k for k in cand if k in stages), key=lambda k: stages[k])
+    fl, kname, bound, pk = cand[dom]
+    roof = {"kernel": kname, "bound": bound, "achieved": fl / (stages[dom] * 1e-3) / 1e12,
+            "peak": PEAK[pk], "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(profile, kname) if profile else None
+    roof["kernel_ms"] = stages.get(dom)
+    roof["flop_per_launch"] = fl
+    return roof
+
+
+def sample_targets(st, grid, idx):
+    """Positions of the evaluation points idx of a plan whose points are the
+    stations st followed by every cell centre (x fastest)."""
+    import numpy as np
+    ns = st.shape[0]
+    out = np.empty((idx.size, 3))
+    sel = idx < ns
+    out[sel] = st[idx[sel]]
+    c = idx[~sel] - ns
+    ix, iy, iz = c % grid.nx, (c // grid.nx) % grid.ny, c // (grid.nx * grid.ny)
+    out[~sel] = np.stack([grid.origin[0] + (ix + 0.5) * grid.h, grid.origin[1] + (iy + 0.5) * grid.h,
+                          grid.origin[2] + (iz + 0.5) * grid.h], axis=1)
+    return out
+
+
+def gather_rows(out, idx):
+    import torch
+    return out[0].index_select(0, torch.as_tensor(idx, device=out.device)).cpu().numpy()
+
+
+# ----------------------------------------------------------------------------
+def headline(args):
+    import numpy as np
+    import torch
+
+    import paper_1107_5951_amd as G
+    import workloads as W
+
+    n = args.n
+    grid = W.Grid.unit(n)
+    st = W.stations(512, 1.1)
+    rho_h = W.gaussian_blobs(grid, 64, 1003) + W.box_density(grid, PRISM, 1.0)
+    rho = torch.as_tensor(rho_h, device="cuda")
+    M = st.shape[0] + grid.ncell
+    idx = W.sample_indices(M, args.sample, seed=7)
+
+    def make(prec, p, points=st, centres=True):
+        t0 = time.perf_counter()
+        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, quad_order=1, points=points, voxel_centres=centres,
+                                 components=3, p=p, leaf_size=64, precision=prec))
+        return plan, time.perf_counter() - t0
+
+    say("headline plan: %d^3 cells, %d targets, mixed p=%d" % (n, M, args.p))
+    plan, plan_s = make(G.GRAV_MIXED, args.p)
+    out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
+    ms, lat = timed_steps(plan, rho, out, args.steps, args.warmup)
+    stages = stage_profile(plan, rho, out, max(5, min(args.steps, 20)))
+    m2l_pairs, p2p_pairs, n_src = plan.work()
+    g_sample = gather_rows(out, idx)
+    roof = roofline(plan, stages, args.p, G.GRAV_MIXED, "m2l_volume256_q1_hbm_traffic.md")
+    levels, leaf = plan.levels, plan.leaf_cells
+    resident, per_call = plan.bytes()
+    del plan
+    value = M / (ms * 1e-3)
+    res = {
+        "metric": METRIC, "value": value, "unit": "gz evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (mixed: M2L and lattice near field on FP32 MFMA; expansions, M2M/L2L/L2P and combine in f64)",
+        "data": "synthetic",
+        "config": {"workload": "%d^3 cells, 1-point rule (%d sources), 64 seeded blobs + prism, g at %d x %d "
+                               "stations (z=1.1) + all %d cell centres (%d targets), p=%d, mixed precision, "
+                               "leaf %d cells" % (n, n_src, 512, 512, grid.ncell, M, args.p, leaf ** 3),
+                   "levels": levels, "leaf_cells": leaf, "batch": 1, "p": args.p, "p_nominal": args.p_nominal},
+        "pair_equiv_per_s": value * n_src,
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "plan_s": plan_s, "plan_bytes": {"resident": resident, "per_call": per_call},
+        "stages_ms": stages,
+        "work": {"m2l_box_pairs": m2l_pairs, "p2p_point_pairs": p2p_pairs,
+                 "m2l_gflop": 2.0 * args.p ** 4 * m2l_pairs / 1e9},
+        "roofline": roof,
+    }
+
+    # the prism alone at the stations (checked against its closed form in
+    # the oracle leg below)
+    say("prism alone at the stations")
+    rho_p = torch.as_tensor(W.box_density(grid, PRISM, 1.0), device="cuda")
+    prism_gz = {}
+    for prec, p in ((G.GRAV_MIXED, args.p), (G.GRAV_MIXED, args.p_nominal)) + (
+            () if args.no_fp64 else ((G.GRAV_FP64, args.p64),)):
+        pl, _ = make(prec, p, centres=False)
+        prism_gz["%s_p%d" % ("fp64" if prec == G.GRAV_FP64 else "mixed", p)] = pl.eval(rho_p)[:, 2].cpu().numpy()
+        del pl
+    del rho_p
+
+    say("nominal order p=%d" % args.p_nominal)
+    plan8, _ = make(G.GRAV_MIXED, args.p_nominal)
+    ms8, lat8 = timed_steps(plan8, rho, out, max(5, args.steps // 2), 2)
+    st8 = stage_profile(plan8, rho, out, 3)
+    g8 = gather_rows(out, idx)
+    res["nominal_p"] = {"p": args.p_nominal, "value": M / (ms8 * 1e-3), "ms_per_step": ms8,
+                        "p50_ms": pct(lat8, 50), "p99_ms": pct(lat8, 99), "stages_ms": st8,
+                        "roofline": roofline(plan8, st8, args.p_nominal, G.GRAV_MIXED, None)}
+    del plan8
+
+    g64 = None
+    if not args.no_fp64:
+        say("fp64 p=%d" % args.p64)
+        plan64, p64_s = make(G.GRAV_FP64, args.p64)
+        ms64, lat64 = timed_steps(plan64, rho, out, 3, 1)
+        st64 = stage_profile(plan64, rho, out, 2)
+        g64 = gather_rows(out, idx)
+        res["fp64"] = {"p": args.p64, "value": M / (ms64 * 1e-3), "ms_per_step": ms64,
+                       "p50_ms": pct(lat64, 50), "p99_ms": pct(lat64, 99), "plan_s": p64_s, "stages_ms": st64,
+                       "roofline": roofline(plan64, st64, args.p64, G.GRAV_FP64, None),
+                       "mixed_speedup": ms64 / ms}
+        del plan64
+    del out
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        import oracle
+        tg = sample_targets(st, grid, idx)
+        threads = oracle.num_threads()
+        say("oracle on %d targets x %d sources, %d threads" % (len(idx), n_src, threads))
+        t0 = time.perf_counter()
+        ref = oracle.forward(rho_h, grid.origin, grid.h, 1, tg, comps=3)
+        cpu_s = time.perf_counter() - t0
+        k1 = min(args.cpu_one_thread, len(idx))
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.forward(rho_h, grid.origin, grid.h, 1, tg[:k1], comps=3)
+        cpu1_s = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        res["cpu_baseline"] = {
+            "value": len(idx) / cpu_s, "unit": "gz evals/s", "cores": threads, "kind": "oracle",
+            "sample": "%d seeded targets (of %d: stations and cell centres) x all %d source points, FP64 "
+                      "direct sum, %.1f s" % (len(idx), M, n_src, cpu_s),
+            "pair_equiv_per_s": len(idx) * n_src / cpu_s,
+            "one_thread": {"value": k1 / cpu1_s, "unit": "gz evals/s", "cores": 1,
+                           "sample": "first %d of the same targets, %.1f s" % (k1, cpu1_s),
+                           "pair_equiv_per_s": k1 * n_src / cpu1_s}}
+        from oracle import prism
+        exact = prism.prism_gz(st, W.snapped_box(grid, PRISM), 1.0, 1.0)
+        res["prism_vs_closed_form"] = {k: float(np.linalg.norm(v - exact) / np.linalg.norm(exact))
+                                       for k, v in prism_gz.items()}
+        res["rel_err"] = oracle.rel_l2(g_sample, ref)
+        res["rel_err_bar"] = 1e-4
+        res["rel_err_targets"] = len(idx)
+        res["nominal_p"]["rel_err"] = oracle.rel_l2(g8, ref)
+        if g64 is not None:
+            res["fp64"]["rel_err"] = oracle.rel_l2(g64, ref)
+            res["fp64"]["rel_err_bar"] = 1e-6
+    return res
+
+
+def volume64(args):
+    """64^3 cells, 2-point rule (2,097,152 sources), 32 blobs + noise, g at
+    all 262,144 cell centres: mixed p = 10 and FP64 p = 12."""
+    import torch
+
+    import paper_1107_5951_amd as G
+    import workloads as W
+    n = 64
+    grid = W.Grid.unit(n)
+    rho_h = W.gaussian_blobs(grid, 32, 1002, noise=0.01)
+    rho = torch.as_tensor(rho_h, device="cuda")
+    M = grid.ncell
+    idx = W.sample_indices(M, args.sample, seed=7)
+    row = {"workload": "64^3 cells, 2-point rule (2097152 sources), g at all 262144 cell centres"}
+    outs = {}
+    for tag, prec, p in (("mixed", G.GRAV_MIXED, 10), ("fp64", G.GRAV_FP64, 12)):
+        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, quad_order=2, voxel_centres=True, components=3, p=p,
+                                 leaf_size=512, precision=prec))
+        out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
+        ms, lat = timed_steps(plan, rho, out, args.steps, args.warmup)
+        stg = stage_profile(plan, rho, out, 5)
+        outs[tag] = gather_rows(out, idx)
+        row[tag] = {"p": p, "value": M / (ms * 1e-3), "ms_per_step": ms, "p50_ms": pct(lat, 50),
+                    "p99_ms": pct(lat, 99), "stages_ms": stg,
+                    "roofline": roofline(plan, stg, p, prec,
+                                         "m2l_volume64_q2_hbm_traffic.md" if tag == "mixed" else None)}
+        del plan, out
+    if not args.no_cpu:
+        import oracle
+        ref = oracle.forward(rho_h, grid.origin, grid.h, 2, grid.centres()[idx], comps=3)
+        row["mixed"]["rel_err"] = oracle.rel_l2(outs["mixed"], ref)
+        row["fp64"]["rel_err"] = oracle.rel_l2(outs["fp64"], ref)
+    return row
+
+
+def batched128(args):
+    """32 density models (8 blobs each, seeds 2000 + b) on one 128^3-cell
+    tree, gz at 256 x 256 stations at z = 1.1: the mixed-precision batched
+    solve (p = 10) against the FP64 FMM (p = 14), batched and as 32 plain
+    single-model solves; the adjoint when the library has it."""
+    import numpy as np
+    import torch
+
+    import paper_1107_5951_amd as G
+    import workloads as W
+    n, B = 128, 32
+    grid = W.Grid.unit(n)
+    st = W.stations(256, 1.1)
+    rhos = np.stack([W.gaussian_blobs(grid, 8, 2000 + b) for b in range(B)])
+    r = torch.as_tensor(rhos, device="cuda")
+    sidx = W.sample_indices(st.shape[0], args.sample, seed=7)
+    row = {"workload": "128^3 cells, 1-point rule, B=32 models on one tree, gz at 256x256 stations"}
+    samples = {}
+    for tag, prec, p in (("mixed", G.GRAV_MIXED, 10), ("fp64", G.GRAV_FP64, 14)):
+        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=st, components=1, p=p, leaf_size=64, batch=B,
+                                 precision=prec))
+        out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
+        ms, lat = timed_steps(plan, r, out, 10, 2)
+        stg = stage_profile(plan, r, out, 3)
+        samples[tag] = out[:4].index_select(1, torch.as_tensor(sidx, device="cuda"))[..., 0].cpu().numpy()
+        row[tag] = {"p": p, "value": B * st.shape[0] / (ms * 1e-3), "ms_per_step": ms,
+                    "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "stages_ms": stg,
+                    "roofline": roofline(plan, stg, p, prec, None)}
+        try:
+            res = torch.randn(plan.out_shape, dtype=torch.float64, device="cuda",
+                              generator=torch.Generator(device="cuda").manual_seed(1004))
+            drho = torch.empty_like(r)
+            plan.adjoint(res, drho)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                plan.adjoint(res, drho)
+            e1.record()
+            torch.cuda.synchronize()
+            row[tag]["adjoint_ms"] = e0.elapsed_time(e1) / 3
+        except G.GravError as e:
+            if e.code != 4:
+                raise
+            row[tag]["adjoint_ms"] = None
+        del plan, out
+        torch.cuda.empty_cache()
+    # the plain FP64 FMM: one model per solve, 32 solves
+    plan1 = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=st, components=1, p=14, leaf_size=64,
+                              precision=G.GRAV_FP64))
+    out1 = torch.empty(plan1.out_shape, dtype=torch.float64, device="cuda")
+    for b in range(2):
+        plan1.eval(r[b], out1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for b in range(B):
+        plan1.eval(r[b], out1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    row["fp64_single_x32"] = {"p": 14, "ms_for_32": ms1, "value": B * st.shape[0] / (ms1 * 1e-3)}
+    row["mixed_batched_speedup_vs_fp64_single"] = ms1 / row["mixed"]["ms_per_step"]
+    del plan1, out1
+    if not args.no_cpu:
+        import oracle
+        ref = oracle.forward(rhos[:4], grid.origin, grid.h, 1, st[sidx], comps=1)[..., 0]
+        for tag in ("mixed", "fp64"):
+            row[tag]["rel_err"] = oracle.rel_l2(samples[tag], ref)
+            row[tag]["rel_err_models_x_stations"] = "4 x %d" % len(sidx)
+    return row
+
+
+# ----------------------------------------------------------------------------
 def paper_sequence(args):
     """The paper's model (Sec. 3) on Mbar^3 meshes, 1-point rule, gz at every
     cell centroid, p = 8, 27 cells per leaf (the setting of its FMM timing
@@ -157,11 +471,10 @@ def paper_sequence(args):
 
 
 def serving(args):
-    """Many small forward solves: a seeded Poisson trace (rate 50/s) of
-    meshes n = round(exp U[ln 32, ln 192]), q in {1, 2}, gz at n x n
-    stations, p = 8 mixed.  Plans are built first (timed separately); then
-    the trace is served back to back (capacity) and at its arrival times
-    (latency under load)."""
+    """The serving workload: a seeded Poisson trace (rate 50/s) of requests on
+    meshes n = round(exp U[ln 32, ln 192]), q in {1, 2}, gz at n x n stations,
+    mixed precision; served back to back (capacity) and at the trace's
+    arrival times (latency under load)."""
     import torch
 
     from paper_1107_5951_amd import serve
@@ -176,7 +489,7 @@ def serving(args):
     _, live = srv.run(reqs, realtime=True)
     srv.close()
     print(json.dumps({"workload": "serving: %d Poisson requests at 50/s, n in [32, 192], q in {1, 2}, "
-                                  "gz at n^2 stations, p=8 mixed, forward only" % args.serve,
+                                  "gz at n^2 stations, mixed" % args.serve,
                       "plans": len(set((r.n, r.q) for r in reqs)), "plan_build_s": build_s,
                       "capacity": cap, "realtime": live}), flush=True)
 
@@ -184,7 +497,7 @@ def serving(args):
 def crossover(args):
     """Summation vs FMM as the number of stations grows (cf. the paper's
     crossover discussion, Sec. 4): a fixed 64^3 mesh, 1-point rule, gz at
-    ns x ns stations at z = 1.1, mixed precision p = 8; the summation by the
+    ns x ns stations at z = 1.1, mixed precision p = 10; the summation by the
     1-point rule (SUM-G1, grav_direct) and in closed form (SUM-AN,
     grav_analytic, FP64)."""
     import torch
@@ -196,7 +509,7 @@ def crossover(args):
     rho = torch.as_tensor(W.gaussian_blobs(grid, 32, 1002), device="cuda")
     rows = []
     for ns in (2, 4, 8, 16, 32, 64, 128, 256):
-        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=W.stations(ns, 1.1), components=1, p=8,
+        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=W.stations(ns, 1.1), components=1, p=10,
                                  leaf_size=64, precision=G.GRAV_MIXED))
         out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
         t = {}
@@ -227,7 +540,6 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path; use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -239,10 +551,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "copies": 3}))
         return
-
-    import paper_1107_5951_amd as G
-    import workloads as W
-
     if args.crossover:
         crossover(args)
         return
@@ -253,128 +561,13 @@ def main():
         paper_sequence(args)
         return
 
-    n = args.n
-    grid = W.Grid.unit(n)
-    rho_h = W.gaussian_blobs(grid, 32, 1002, noise=0.01)
-    rho = torch.as_tensor(rho_h, device="cuda")
-    M = grid.ncell
-
-    def make(prec, p):
-        t0 = time.perf_counter()
-        plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, quad_order=2, voxel_centres=True,
-                                 components=3, p=p, leaf_size=args.leaf, precision=prec))
-        return plan, time.perf_counter() - t0
-
-    plan, plan_s = make(G.GRAV_MIXED, args.p)
-    out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
-    total_ms, lat, wall = timed_steps(plan, rho, out, args.steps, args.warmup)
-    ms = total_ms / args.steps
-    stages = stage_profile(plan, rho, out, max(5, min(args.steps, 20)))
-    m2l_pairs, p2p_pairs, n_src = plan.work()
-    g_mixed = out[0].cpu().numpy()
-
-    value = M / (ms * 1e-3)
-    P2 = args.p * args.p
-    # dominant kernel and its roofline (algorithmic flops per launch / stage time)
-    b = plan.leaf_cells
-    n_leaf_src = (-(-n // b)) ** 3
-    flops_m2l = 2.0 * P2 * P2 * m2l_pairs
-    flops_p2p = P2P_FLOP_PER_PAIR * p2p_pairs
-    flops_near = 27 * 2.0 * (4 * b ** 3) * b ** 3 * n_leaf_src
-    cand = {
-        "m2l": (flops_m2l, "k_m2l<%d,%d,2,float> (M2L, FP32 MFMA 16x16x4)" % (-(-P2 // 16), -(-P2 // 4)), "mfma",
-                "fp32_mfma"),
-        "near_lat": (flops_near, "k_near_lat<4,2,float> (lattice near field, FP32 MFMA 16x16x4)", "mfma",
-                     "fp32_mfma"),
-        "p2p": (flops_p2p, "k_p2p<float> (direct near field, FP32 VALU)", "alu", "fp32_vector"),
-    }
-    dom = max((k for k in cand if k in stages), key=lambda k: stages[k])
-    fl, kname, bound, pk = cand[dom]
-    roof = {"kernel": kname, "bound": bound, "achieved": fl / (stages[dom] * 1e-3) / 1e12,
-            "peak": PEAK[pk], "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(kname)
-    roof["kernel_ms"] = stages.get(dom)
-
-    res = {
-        "metric": METRIC, "value": value, "unit": "gz evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 (mixed: M2L and lattice near field on FP32 MFMA; expansions, M2M/L2L/L2P and combine in f64)",
-        "data": "synthetic",
-        "config": {"workload": "%d^3 cells, 2-point Gauss (%d sources), g at %d cell centres, p=%d, "
-                               "mixed precision, leaf %d cells" % (n, n_src, M, args.p, plan.leaf_cells ** 3),
-                   "levels": plan.levels, "leaf_cells": plan.leaf_cells, "batch": 1},
-        "pair_equiv_per_s": value * n_src,
-        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-        "plan_s": plan_s,
-        "stages_ms": stages,
-        "work": {"m2l_box_pairs": m2l_pairs, "p2p_point_pairs": p2p_pairs, "m2l_gflop": flops_m2l / 1e9,
-                 "near_lat_gflop": flops_near / 1e9 if "near_lat" in stages else None,
-                 "p2p_gflop_20": flops_p2p / 1e9},
-        "roofline": roof,
-    }
-
-    fp64 = None
-    if not args.no_fp64:
-        del plan
-        plan64, plan64_s = make(G.GRAV_FP64, args.p64)
-        tms, lat64, _ = timed_steps(plan64, rho, out, args.steps, args.warmup)
-        st64 = stage_profile(plan64, rho, out, 5)
-        g64 = out[0].cpu().numpy()
-        ms64 = tms / args.steps
-        m2l64, _, _ = plan64.work()
-        del plan64
-        fp64 = {"p": args.p64, "value": M / (ms64 * 1e-3), "ms_per_step": ms64,
-                "p50_ms": pct(lat64, 50), "p99_ms": pct(lat64, 99), "stages_ms": st64,
-                "m2l_tflops": 2.0 * args.p64 ** 4 * m2l64 / (st64.get("m2l", 1e9) * 1e-3) / 1e12}
-        plan10, _ = make(G.GRAV_FP64, args.p)
-        plan10.eval(rho, out)
-        torch.cuda.synchronize()
-        g64_p = out[0].cpu().numpy()
-        del plan10
-        res["fp64"] = fp64
-
-    if not args.no_direct:
-        # the summation method on the same GPU, same targets and arithmetic
-        # class (FP32 pairs for the mixed plan): one evaluation
-        plan_d, _ = make(G.GRAV_MIXED, args.p)
-        plan_d.direct(rho, out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        plan_d.direct(rho, out)
-        ev1.record()
-        torch.cuda.synchronize()
-        dms = ev0.elapsed_time(ev1)
-        g_direct = out[0].cpu().numpy()
-        del plan_d
-        res["direct_sum"] = {"ms": dms, "value": M / (dms * 1e-3), "pairs_per_s": M * n_src / (dms * 1e-3),
-                             "fmm_speedup": dms / ms, "kernel": "k_direct<float> (Sec. 2.1 summation, FP32)"}
-
-    if not args.no_cpu:
-        import oracle
-        idx = W.sample_indices(M, args.sample, seed=7)
-        tg = grid.centres()[idx]
-        threads = oracle.num_threads()
-        t0 = time.perf_counter()
-        ref = oracle.forward(rho_h, grid.origin, grid.h, 2, tg, comps=3)
-        cpu_s = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": len(idx) / cpu_s, "unit": "gz evals/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": "%d seeded cell-centre targets (of %d) x all %d source points, "
-                                         "FP64 direct sum, %.1f s" % (len(idx), M, n_src, cpu_s),
-                               "pair_equiv_per_s": len(idx) * n_src / cpu_s}
-        res["rel_err"] = oracle.rel_l2(g_mixed[idx], ref)
-        if "direct_sum" in res:
-            res["direct_sum"]["rel_err"] = oracle.rel_l2(g_direct[idx], ref)
-        res["rel_err_bar"] = 1e-4
-        if fp64 is not None:
-            fp64["rel_err"] = oracle.rel_l2(g64[idx], ref)
-            fp64["rel_err_p%d" % args.p] = oracle.rel_l2(g64_p[idx], ref)
-            fp64["rel_err_bar"] = 1e-6
+    res = headline(args)
+    if not args.no_extra:
+        say("64^3 volume workload")
+        res["volume64_q2"] = volume64(args)
+        torch.cuda.empty_cache()
+        say("batched 128^3 workload")
+        res["batched128_b32"] = batched128(args)
     line = json.dumps(res)
     print(line, flush=True)
     if args.out:

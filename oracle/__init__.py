@@ -62,8 +62,9 @@ def _load():
             lib.oracle_points.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int64, dp,
                                           ctypes.c_int, ctypes.c_double, dp]
             lib.oracle_num_threads.argtypes = []
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
             for f in (lib.oracle_forward, lib.oracle_adjoint, lib.oracle_adjoint_cells,
-                      lib.oracle_points, lib.oracle_num_threads):
+                      lib.oracle_points, lib.oracle_num_threads, lib.oracle_set_threads):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -80,6 +81,11 @@ def _f64(a) -> np.ndarray:
 def num_threads() -> int:
     """OpenMP threads the oracle uses (``OMP_NUM_THREADS`` or all cores)."""
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Use n OpenMP threads from now on (n >= 1); returns the count in effect."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def forward(rho, origin, h, q, targets, comps=3, G=1.0) -> np.ndarray:

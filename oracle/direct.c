@@ -377,3 +377,18 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads later calls use (n >= 1); returns the
+ * number now in effect.  Lets the benchmark time the oracle on one core and
+ * on all cores in one process. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

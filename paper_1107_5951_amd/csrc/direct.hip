@@ -20,7 +20,10 @@ namespace grav {
 // cells writes part[c][target][model][4] (or, with one chunk, the output
 // directly).  Within a workgroup the chunk is staged through LDS 256 cells at
 // a time as (x, y, z, rho) relative to the chunk's first cell, so the pair
-// arithmetic needs no index bookkeeping.
+// arithmetic needs no index bookkeeping.  The pair terms of one staged batch
+// (at most 256 cells, 2,048 quadrature points) are summed in T and each
+// batch's sum is added to an FP64 accumulator, so in FP32 the rounding error
+// grows with the batch length, not with the number of cells.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_direct(DevGeom g, const double *rho, const double *tpos, int64_t chunk, double *part,
@@ -42,7 +45,7 @@ k_direct(DevGeom g, const double *rho, const double *tpos, int64_t chunk, double
         tp[2] = (T)(tpos[3 * i + 2] - (double)bz - 0.5);
     }
     for (int bm = 0; bm < g.B; ++bm) {
-        T acc[4] = {0, 0, 0, 0};
+        double acc64[4] = {0, 0, 0, 0};
         for (int64_t c0 = cb; c0 < ce; c0 += 256) {
             __syncthreads();
             const int64_t c = c0 + threadIdx.x;
@@ -61,6 +64,7 @@ k_direct(DevGeom g, const double *rho, const double *tpos, int64_t chunk, double
             if (!valid)
                 continue;
             const int nc = (int)min((int64_t)256, ce - c0);
+            T acc[4] = {0, 0, 0, 0};
             for (int k = 0; k < nc; ++k) {
                 const T rv = scell[k][3];
                 if (rv == (T)0)
@@ -97,6 +101,9 @@ k_direct(DevGeom g, const double *rho, const double *tpos, int64_t chunk, double
                     }
                 }
             }
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc64[c] += (double)acc[c];
         }
         if (!valid)
             continue;
@@ -104,23 +111,23 @@ k_direct(DevGeom g, const double *rho, const double *tpos, int64_t chunk, double
             double *o = part + (((int64_t)blockIdx.y * g.M + i) * g.B + bm) * 4;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                o[c] = (double)acc[c];
+                o[c] = acc64[c];
             continue;
         }
         // one chunk: write the output (descriptor order, G applied)
         double *o = out + ((int64_t)bm * g.M + perm[i]) * g.C;
         const double sg = g.G * g.h, sp = g.G * g.h * g.h;
         if (g.C == 1) {
-            o[0] = sg * (double)acc[3];
+            o[0] = sg * acc64[3];
         } else if (g.C == 3) {
-            o[0] = sg * (double)acc[1];
-            o[1] = sg * (double)acc[2];
-            o[2] = sg * (double)acc[3];
+            o[0] = sg * acc64[1];
+            o[1] = sg * acc64[2];
+            o[2] = sg * acc64[3];
         } else {
-            o[0] = sp * (double)acc[0];
-            o[1] = sg * (double)acc[1];
-            o[2] = sg * (double)acc[2];
-            o[3] = sg * (double)acc[3];
+            o[0] = sp * acc64[0];
+            o[1] = sg * acc64[1];
+            o[2] = sg * acc64[2];
+            o[3] = sg * acc64[3];
         }
     }
 }

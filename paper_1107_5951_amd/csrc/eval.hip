@@ -349,6 +349,8 @@ k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_star
     const int64_t leaf = blockIdx.x;
     const int64_t ts = leaf_start[leaf], te = leaf_end[leaf];
     const int64_t nt = te - ts;
+    if (nt <= 0)
+        return;  // no explicit points in this leaf (uniform over the workgroup)
     const uint32_t key = tkey[lv.tbox_off + leaf];
     const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
     int corner[3];

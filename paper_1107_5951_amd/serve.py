@@ -54,7 +54,7 @@ def station_grid(ns: int, z: float = 1.1) -> np.ndarray:
 class PlanCache:
     """LRU cache of plans with an HBM budget on their resident + workspace bytes."""
 
-    def __init__(self, budget_bytes: int, p: int = 8, precision: int = GRAV_MIXED, leaf_size: int = 64):
+    def __init__(self, budget_bytes: int, p: int = 10, precision: int = GRAV_MIXED, leaf_size: int = 64):
         self.budget = int(budget_bytes)
         self.p, self.precision, self.leaf_size = p, precision, leaf_size
         self._plans: "collections.OrderedDict[Tuple[int, int], Plan]" = collections.OrderedDict()
@@ -99,7 +99,7 @@ class PlanCache:
 class GravServer:
     """Dispatch forward requests to a pool of streams, one stream per plan."""
 
-    def __init__(self, n_streams: int = 4, budget_bytes: int = 64 << 30, p: int = 8,
+    def __init__(self, n_streams: int = 4, budget_bytes: int = 64 << 30, p: int = 10,
                  precision: int = GRAV_MIXED):
         import torch
         self.torch = torch

@@ -1,10 +1,16 @@
 """The large volume workload: 256^3 cells, 1-point rule (16.8M sources),
 g at 512 x 512 stations (z = 1.1) plus every cell centre (17.0M targets),
-p = 8, mixed precision, one plan.
+mixed precision, one plan.
 
-* parity against the FP64 oracle on 4096 seeded targets (blobs + prism);
+* parity against the FP64 oracle on 4096 seeded targets (blobs + prism), bar
+  1e-4 for mixed precision, at p = 10 (the order the library runs this
+  workload at) and at the workload's nominal p = 8;
 * the prism alone against its closed form (the form Appendix A of the paper
-  uses for Table A1), at p = 12 in FP64, bar 1e-4.
+  uses for Table A1).  The 1-point rule itself is far inside the bars here
+  (its error is O((h/d)^4), about 2e-11 at h = 1/256, d = 0.6), so the check
+  measures the FMM: mixed precision meets 1e-4 from p = 10 on (p = 8 gives
+  4e-4, reported, not asserted) and FP64 meets 1e-6 at p = 16 (p = 14 gives
+  2e-6).
 """
 import sys
 
@@ -29,53 +35,57 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _plan(grid, st):
-    return G.Plan(G.PlanSpec(n=(N, N, N), h=grid.h, quad_order=1, points=st, voxel_centres=True,
-                             components=3, p=8, leaf_size=64, precision=G.GRAV_MIXED))
-
-
-def test_config3_blobs_and_prism_sampled_parity():
+@pytest.fixture(scope="module")
+def volume():
     grid = W.Grid.unit(N)
     st = W.stations(512, 1.1)
     rho = W.gaussian_blobs(grid, 64, 1003) + W.box_density(grid, PRISM, 1.0)
-    plan = _plan(grid, st)
-    _say("config3 plan: %d targets, levels %d, leaf %d" % (plan.n_targets, plan.levels, plan.leaf_cells))
+    idx = W.sample_indices(st.shape[0] + grid.ncell, 4096, seed=7)
+    tg = np.concatenate([st, grid.centres()])[idx]
+    _say("config3 oracle on %d targets" % idx.size)
+    ref = oracle.forward(rho, grid.origin, grid.h, 1, tg, comps=3)
+    return grid, st, rho, idx, ref
+
+
+@pytest.mark.parametrize("p", [10, 8])
+def test_config3_blobs_and_prism_sampled_parity(volume, p):
+    grid, st, rho, idx, ref = volume
+    plan = G.Plan(G.PlanSpec(n=(N, N, N), h=grid.h, quad_order=1, points=st, voxel_centres=True,
+                             components=3, p=p, leaf_size=64, precision=G.GRAV_MIXED))
+    _say("config3 plan p=%d: %d targets, levels %d, leaf %d" % (p, plan.n_targets, plan.levels,
+                                                               plan.leaf_cells))
     out = plan.eval(torch.as_tensor(rho, device="cuda"))
     torch.cuda.synchronize()
-    idx = W.sample_indices(plan.n_targets, 4096, seed=7)
     g = out.index_select(0, torch.as_tensor(idx, device="cuda")).cpu().numpy()
-    tg = np.concatenate([st, grid.centres()])[idx]
-    ref = oracle.forward(rho, grid.origin, grid.h, 1, tg, comps=3)
     e = oracle.rel_l2(g, ref)
-    _say("config3 mixed p=8, 4096 sampled targets: rel err %.3e" % e)
-    assert e < 1e-4
+    _say("config3 mixed p=%d, 4096 sampled targets: rel err %.3e" % (p, e))
+    assert e <= 1e-4
 
 
-def test_config3_prism_against_closed_form():
-    """gz of the prism alone at the stations.  The oracle (direct sum of the
-    1-point rule) against the closed form of the snapped box measures the
-    quadrature error, which is O((h/d)^4) here: the kernel is harmonic in the
-    source point away from the station, so the h^2 term of the midpoint rule
-    vanishes (about 2e-11 at h = 1/256, d = 0.6).  The FMM runs in FP64 at
-    p = 12; for this compact, sharp-edged source its error is about 1e-5
-    (p = 8 in mixed precision gives 4e-4), well inside the 1e-4 bar."""
+@pytest.fixture(scope="module")
+def prism_case():
     grid = W.Grid.unit(N)
     st = W.stations(512, 1.1)
     rho = W.box_density(grid, PRISM, 1.0)
     box = W.snapped_box(grid, PRISM)
-    plan = G.Plan(G.PlanSpec(n=(N, N, N), h=grid.h, quad_order=1, points=st, components=3, p=12,
-                             leaf_size=64))
-    out = plan.eval(torch.as_tensor(rho, device="cuda"))
-    torch.cuda.synchronize()
-    gz = out[:, 2].cpu().numpy()
     exact = prism.prism_gz(st, box, 1.0, 1.0)
-    idx = W.sample_indices(st.shape[0], 1024, seed=11)
-    ref = oracle.forward(rho, grid.origin, grid.h, 1, st[idx], comps=1)[:, 0]
-    quad = np.linalg.norm(ref - exact[idx]) / np.linalg.norm(exact[idx])
-    fmm = np.linalg.norm(gz[idx] - ref) / np.linalg.norm(ref)
-    e = np.linalg.norm(gz - exact) / np.linalg.norm(exact)
-    _say("config3 prism: 1-point rule vs closed form %.3e, FMM vs oracle %.3e, FMM vs closed form %.3e"
-         % (quad, fmm, e))
+    sidx = W.sample_indices(st.shape[0], 1024, seed=11)
+    ref = oracle.forward(rho, grid.origin, grid.h, 1, st[sidx], comps=1)[:, 0]
+    quad = np.linalg.norm(ref - exact[sidx]) / np.linalg.norm(exact[sidx])
+    _say("config3 prism: 1-point rule vs closed form %.3e" % quad)
     assert quad < 1e-8
-    assert fmm < 1e-4
-    assert e < 1e-4
+    return grid, st, rho, exact
+
+
+@pytest.mark.parametrize("prec,p,bar", [(1, 10, 1e-4), (0, 16, 1e-6), (1, 8, None)])
+def test_config3_prism_against_closed_form(prism_case, prec, p, bar):
+    """gz of the prism alone at all 262,144 stations against the closed form of
+    the snapped box; bar None = the nominal order, reported only."""
+    grid, st, rho, exact = prism_case
+    plan = G.Plan(G.PlanSpec(n=(N, N, N), h=grid.h, quad_order=1, points=st, components=1, p=p,
+                             leaf_size=64, precision=prec))
+    gz = plan.eval(torch.as_tensor(rho, device="cuda"))[:, 0].cpu().numpy()
+    e = np.linalg.norm(gz - exact) / np.linalg.norm(exact)
+    _say("config3 prism, prec=%d p=%d: FMM vs closed form %.3e (bar %s)" % (prec, p, e, bar))
+    if bar is not None:
+        assert e <= bar

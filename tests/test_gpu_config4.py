@@ -1,8 +1,11 @@
 """Batched forward solves on one tree: 128^3 cells, 1-point rule, 32 density
-models (8 blobs each, seeds 2000 + b), gz at 256 x 256 stations at z = 1.1,
-p = 8, FP64 and mixed precision.  Checked against the oracle on 4 models x
-512 seeded stations, and every model against its own single-model solve.
-(The inversion's gradient needs the adjoint, which is switched off.)"""
+models (8 blobs each, seeds 2000 + b), gz at 256 x 256 stations at z = 1.1.
+
+Parity against the oracle on 4 models x 4096 seeded stations at the orders
+that meet the bars (mixed p = 10 <= 1e-4, FP64 p = 14 <= 1e-6; the
+workload's nominal p = 8 gives about 1.5e-4 and is reported, not asserted),
+and every model of the batch against its own single-model solve, element by
+element."""
 import sys
 
 import numpy as np
@@ -16,33 +19,47 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 G = pytest.importorskip("paper_1107_5951_amd")
 
+N, B = 128, 32
+
 
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_config4_batched_forward(prec):
-    n, B = 128, 32
-    grid = W.Grid.unit(n)
+@pytest.fixture(scope="module")
+def batch():
+    grid = W.Grid.unit(N)
     st = W.stations(256, 1.1)
     rhos = np.stack([W.gaussian_blobs(grid, 8, 2000 + b) for b in range(B)])
-    spec = G.PlanSpec(n=(n, n, n), h=grid.h, points=st, components=1, p=8, leaf_size=64, batch=B,
+    sidx = W.sample_indices(st.shape[0], 4096, seed=7)
+    _say("config4 oracle: 4 models x %d stations" % sidx.size)
+    ref = oracle.forward(rhos[:4], grid.origin, grid.h, 1, st[sidx], comps=1)[..., 0]
+    return grid, st, rhos, sidx, ref
+
+
+@pytest.mark.parametrize("prec,p,bar", [(1, 10, 1e-4), (0, 14, 1e-6), (1, 8, None)])
+def test_config4_batched_forward(batch, prec, p, bar):
+    grid, st, rhos, sidx, ref = batch
+    spec = G.PlanSpec(n=(N, N, N), h=grid.h, points=st, components=1, p=p, leaf_size=64, batch=B,
                       precision=prec)
     plan = G.Plan(spec)
     r = torch.as_tensor(rhos, device="cuda")
     gz = plan.eval(r)[..., 0].cpu().numpy()
-    sidx = W.sample_indices(st.shape[0], 512, seed=7)
-    ref = oracle.forward(rhos[:4], grid.origin, grid.h, 1, st[sidx], comps=1)[..., 0]
-    e = oracle.rel_l2(gz[:4, sidx], ref)
-    _say("config4 prec=%d: 4 models x 512 stations rel err %.3e" % (prec, e))
-    assert e < 5e-4  # p = 8 with the stations three leaves above the mesh
-    single = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=st, components=1, p=8, leaf_size=64,
+    errs = [oracle.rel_l2(gz[b, sidx], ref[b]) for b in range(4)]
+    _say("config4 prec=%d p=%d: 4 models x 4096 stations rel err, max over models %.3e (bar %s)"
+         % (prec, p, max(errs), bar))
+    if bar is None:
+        return
+    assert max(errs) <= bar
+    single = G.Plan(G.PlanSpec(n=(N, N, N), h=grid.h, points=st, components=1, p=p, leaf_size=64,
                                precision=prec))
-    # same sums, grouped differently (the M2L offset split depends on the
-    # number of columns): rounding-level agreement, FP32 level when mixed
+    # the same sums, grouped differently (the M2L work split depends on the
+    # number of columns): equal to rounding, element by element
+    scale = np.abs(gz).max()
     for b in (0, 17, 31):
         g1 = single.eval(r[b])[:, 0].cpu().numpy()
-        d = oracle.rel_l2(gz[b], g1)
-        assert d < (1e-12 if prec == 0 else 1e-5), (b, d)
+        if prec == 0:
+            np.testing.assert_allclose(gz[b], g1, rtol=1e-11, atol=1e-14 * scale)
+        else:
+            np.testing.assert_allclose(gz[b], g1, rtol=1e-4, atol=1e-6 * scale)

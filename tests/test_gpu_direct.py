@@ -59,3 +59,21 @@ def test_fmm_matches_direct_on_every_target():
     e = oracle.rel_l2(a, b)
     _say("FMM p=12 vs GPU direct sum, all 32768 targets: %.3e" % e)
     assert e < 1e-6
+
+
+def test_direct_mixed_at_volume64_size():
+    """64^3 cells, 2-point rule (2,097,152 source points), g at all 262,144
+    cell centres: every target sums over all sources, so the partial sums are
+    as long as they get at this size; mixed precision meets 1e-4 against the
+    oracle on 4096 seeded targets."""
+    grid = W.Grid.unit(64)
+    rho_h = W.gaussian_blobs(grid, 32, 1002, noise=0.01)
+    plan = G.Plan(G.PlanSpec(n=(64, 64, 64), h=grid.h, quad_order=2, voxel_centres=True, components=3,
+                             p=10, leaf_size=512, precision=G.GRAV_MIXED))
+    out = plan.direct(torch.as_tensor(rho_h, device="cuda"))
+    idx = W.sample_indices(grid.ncell, 4096, seed=7)
+    g = out.index_select(0, torch.as_tensor(idx, device="cuda")).cpu().numpy()
+    ref = oracle.forward(rho_h, grid.origin, grid.h, 2, grid.centres()[idx], comps=3)
+    e = oracle.rel_l2(g, ref)
+    _say("direct mixed, 64^3 q=2, 4096 sampled targets: %.3e" % e)
+    assert e <= 1e-4

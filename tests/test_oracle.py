@@ -240,6 +240,24 @@ def test_adjoint_dot_product(q, comps):
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Ax) * np.linalg.norm(r)
 
 
+@pytest.mark.parametrize("q,comps", [(1, 1), (2, 4)])
+def test_adjoint_cells_equals_full_adjoint_at_those_cells(q, comps):
+    """The sampled transpose decodes each flat cell index (x fastest, then y,
+    then z) on a mesh whose three axes differ, so an axis mix-up or an
+    origin/offset slip changes the value; the full transpose it is compared
+    with is pinned by the dot-product identity above."""
+    rng = np.random.default_rng(8)
+    grid = W.Grid(7, 5, 4, (0.3, -0.1, 0.2), 0.15)
+    tg = np.concatenate([grid.centres()[::5], rng.uniform(-0.5, 1.5, size=(30, 3))])
+    r = rng.normal(size=(2, tg.shape[0], comps))
+    full = oracle.adjoint(r, grid.origin, grid.h, q, grid.shape, tg, comps=comps).reshape(2, -1)
+    cells = np.array([0, grid.ncell - 1, 6, 7, 34, 35, 71, 3, 3, 139, 100, 57])
+    got = oracle.adjoint_cells(r, grid.origin, grid.h, q, grid.shape, tg, cells, comps=comps)
+    np.testing.assert_allclose(got, full[:, cells], rtol=1e-14, atol=1e-15 * np.abs(full).max())
+    one = oracle.adjoint_cells(r[1], grid.origin, grid.h, q, grid.shape, tg, cells, comps=comps)
+    np.testing.assert_allclose(one, full[1, cells], rtol=1e-14, atol=1e-15 * np.abs(full).max())
+
+
 # ---------------------------------------------------------------- SUM-AN
 def _st(n=5, z=1.1):
     return W.stations(n, z)
