@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no 64^3 or batched rows)")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="only the headline's timed evaluations (one plan; for kernel profiles)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
                     help="only run the serving workload: COUNT Poisson requests (rate 50/s, n in [32, 192])")
@@ -250,6 +252,8 @@ def headline(args):
         "roofline": roof,
     }
 
+    if args.timed_only:
+        return res
     # the prism alone at the stations (checked against its closed form in
     # the oracle leg below)
     say("prism alone at the stations")
@@ -562,7 +566,7 @@ def main():
         return
 
     res = headline(args)
-    if not args.no_extra:
+    if not args.no_extra and not args.timed_only:
         say("64^3 volume workload")
         res["volume64_q2"] = volume64(args)
         torch.cuda.empty_cache()
