@@ -143,6 +143,22 @@ grav_status grav_adjoint(grav_plan_t plan, const double *resid, double *drho_out
  * formed in FP64).  Shares the plan's workspace lock (GRAV_EBUSY). */
 grav_status grav_direct(grav_plan_t plan, const double *rho, double *g_out, void *stream);
 
+/* grav_direct without any device allocation behind it, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels, launch
+ * shape and summation order as grav_direct, so the output is identical, but
+ * the per-chunk partial sums live in a fixed 8 MiB device array inside the
+ * library (one per GPU, held until the process ends; its address is looked
+ * up on the first call on each device) instead of the plan's buffer.
+ * Arguments, layouts and asynchrony as grav_direct.  Every call on one GPU
+ * shares that array: calls that overlap in time on one GPU (different
+ * streams, or different plans) race and must be serialised by the caller.
+ * The array needs no clearing: each call writes every partial it reads.
+ * Errors: EUNSUPPORTED if the plan's partials (chunks x targets x batch x 4
+ * doubles) exceed 8 MiB or its device ordinal is 64 or more; otherwise as
+ * grav_direct. */
+grav_status grav_direct_noalloc(grav_plan_t plan, const double *rho, double *g_out, void *stream);
+
 /* Closed-form summation (the analytic summation method SUM-AN of Sec. 2.1):
  * gz at the plan's evaluation points as the sum over all cells of the exact
  * attraction of a uniform rectangular prism (the closed form the paper cites

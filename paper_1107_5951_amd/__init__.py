@@ -220,6 +220,12 @@ def grav_direct(plan: Plan, rho, g_out, stream=None) -> None:
                              ctypes.c_void_p(g_out.data_ptr()), _stream_ptr(stream)), "grav_direct")
 
 
+def grav_direct_noalloc(plan: Plan, rho, g_out, stream=None) -> None:
+    check(load().grav_direct_noalloc(plan.handle, ctypes.c_void_p(rho.data_ptr()),
+                                     ctypes.c_void_p(g_out.data_ptr()), _stream_ptr(stream)),
+          "grav_direct_noalloc")
+
+
 def grav_analytic(plan: Plan, rho, gz_out, stream=None) -> None:
     check(load().grav_analytic(plan.handle, ctypes.c_void_p(rho.data_ptr()),
                                ctypes.c_void_p(gz_out.data_ptr()), _stream_ptr(stream)), "grav_analytic")

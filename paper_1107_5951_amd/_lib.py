@@ -19,7 +19,7 @@ GRAV_FP64, GRAV_MIXED = 0, 1
 EXPORTS = (
     "grav_desc_init", "grav_plan", "grav_plan_destroy", "grav_plan_bytes", "grav_plan_info",
     "grav_plan_work", "grav_plan_check",
-    "grav_eval", "grav_adjoint", "grav_direct", "grav_analytic", "grav_set_profiling", "grav_stage_times", "grav_operator",
+    "grav_eval", "grav_adjoint", "grav_direct", "grav_direct_noalloc", "grav_analytic", "grav_set_profiling", "grav_stage_times", "grav_operator",
     "grav_harmonics", "grav_status_string", "grav_version",
 )
 
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
             "grav_eval": ([vp, vp, vp, vp], ctypes.c_int),
             "grav_adjoint": ([vp, vp, vp, vp], ctypes.c_int),
             "grav_direct": ([vp, vp, vp, vp], ctypes.c_int),
+            "grav_direct_noalloc": ([vp, vp, vp, vp], ctypes.c_int),
             "grav_analytic": ([vp, vp, vp, vp], ctypes.c_int),
             "grav_set_profiling": ([vp, i32], ctypes.c_int),
             "grav_stage_times": ([vp, ctypes.POINTER(ctypes.c_char_p), dp, i32, ctypes.POINTER(i32)],

@@ -11,6 +11,7 @@
 // the lattice frame (cell units), so source coordinates are exact small
 // integers plus the Gauss offsets.
 #include <algorithm>
+#include <mutex>
 
 #include "resolve.hpp"
 
@@ -164,6 +165,63 @@ k_direct_finish(DevGeom g, const double *part, int nchunk, const uint32_t *perm,
 
 }  // namespace grav
 
+namespace grav {
+
+// Enqueue the direct sum with its chunk partials in `part` (device memory of
+// at least direct_chunks x M x B x 4 doubles when direct_chunks > 1).
+static grav_status enqueue_direct(Plan *p, const double *rho, double *g_out, double *part, hipStream_t s)
+{
+    const DevGeom g = make_geom(p);
+    const int64_t ncell = (int64_t)p->d.nx * p->d.ny * p->d.nz;
+    const int nchunk = p->direct_chunks;
+    const int64_t chunk = (ncell + nchunk - 1) / nchunk;
+    const dim3 grid((unsigned)((p->M + 255) / 256), (unsigned)nchunk), blk(256);
+    if (p->d.precision == GRAV_FP64)
+        hipLaunchKernelGGL(k_direct<double>, grid, blk, 0, s, g, rho, (const double *)p->d_tpos, chunk, part,
+                           (const uint32_t *)p->d_perm, g_out);
+    else
+        hipLaunchKernelGGL(k_direct<float>, grid, blk, 0, s, g, rho, (const double *)p->d_tpos, chunk, part,
+                           (const uint32_t *)p->d_perm, g_out);
+    GRAV_HIP(hipGetLastError());
+    if (nchunk > 1) {
+        hipLaunchKernelGGL(k_direct_finish, dim3((unsigned)((p->M * p->B + 255) / 256)), dim3(256), 0, s, g,
+                           (const double *)part, nchunk, (const uint32_t *)p->d_perm, g_out);
+        GRAV_HIP(hipGetLastError());
+    }
+    return GRAV_OK;
+}
+
+// Chunk partials of grav_direct_noalloc: a fixed device array (one copy per
+// GPU, alive until the process ends) in place of the plan's buffer.  Host
+// code must not use the name: it stands for a host-side shadow, so kernels
+// get the device address from hipGetSymbolAddress (scratch_ptr below).
+constexpr size_t kScratchDoubles = (size_t)1 << 20;  // 8 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kScratchDevices = 64;
+static std::once_flag g_scratch_once[kScratchDevices];
+static double *g_scratch_ptr[kScratchDevices];
+static hipError_t g_scratch_err[kScratchDevices];
+
+// Device address of `scratch` on device dev, which must be current: looked up
+// once per device, on that device's first call.
+static grav_status scratch_ptr(int dev, double **out)
+{
+    if (dev < 0 || dev >= kScratchDevices)
+        return GRAV_EUNSUPPORTED;
+    std::call_once(g_scratch_once[dev], [dev]() {
+        void *ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? (double *)ptr : nullptr;
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+        return GRAV_EDEVICE;
+    *out = g_scratch_ptr[dev];
+    return GRAV_OK;
+}
+
+}  // namespace grav
+
 using namespace grav;
 
 extern "C" grav_status grav_direct(grav_plan_t plan, const double *rho, double *g_out, void *stream)
@@ -181,25 +239,38 @@ extern "C" grav_status grav_direct(grav_plan_t plan, const double *rho, double *
     if (cur != p->device)
         GRAV_HIP(hipSetDevice(p->device));
     grav_status st = begin_call(p, s);
-    if (st == GRAV_OK) {
-        const DevGeom g = make_geom(p);
-        const int64_t ncell = (int64_t)p->d.nx * p->d.ny * p->d.nz;
-        const int nchunk = p->direct_chunks;
-        const int64_t chunk = (ncell + nchunk - 1) / nchunk;
-        const dim3 grid((unsigned)((p->M + 255) / 256), (unsigned)nchunk), blk(256);
-        if (p->d.precision == GRAV_FP64)
-            hipLaunchKernelGGL(k_direct<double>, grid, blk, 0, s, g, rho, (const double *)p->d_tpos, chunk,
-                               p->d_dpart, (const uint32_t *)p->d_perm, g_out);
-        else
-            hipLaunchKernelGGL(k_direct<float>, grid, blk, 0, s, g, rho, (const double *)p->d_tpos, chunk,
-                               p->d_dpart, (const uint32_t *)p->d_perm, g_out);
-        st = hipGetLastError() == hipSuccess ? GRAV_OK : GRAV_EDEVICE;
-        if (st == GRAV_OK && nchunk > 1) {
-            hipLaunchKernelGGL(k_direct_finish, dim3((unsigned)((p->M * p->B + 255) / 256)), dim3(256), 0, s, g,
-                               (const double *)p->d_dpart, nchunk, (const uint32_t *)p->d_perm, g_out);
-            st = hipGetLastError() == hipSuccess ? GRAV_OK : GRAV_EDEVICE;
-        }
-    }
+    if (st == GRAV_OK)
+        st = enqueue_direct(p, rho, g_out, p->d_dpart, s);
+    if (st == GRAV_OK)
+        st = end_call(p, s);
+    if (cur != p->device)
+        (void)hipSetDevice(cur);
+    return st;
+}
+
+extern "C" grav_status grav_direct_noalloc(grav_plan_t plan, const double *rho, double *g_out, void *stream)
+{
+    if (!plan)
+        return GRAV_EINVAL;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (p->M == 0)
+        return GRAV_OK;
+    if (!rho || !g_out)
+        return GRAV_EINVAL;
+    const size_t need = p->direct_chunks > 1 ? (size_t)p->direct_chunks * p->M * p->B * 4 : 0;
+    if (need > kScratchDoubles)
+        return GRAV_EUNSUPPORTED;  // partials larger than the 8 MiB device array
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    GRAV_HIP(hipGetDevice(&cur));
+    if (cur != p->device)
+        GRAV_HIP(hipSetDevice(p->device));
+    double *part = nullptr;
+    grav_status st = scratch_ptr(p->device, &part);
+    if (st == GRAV_OK)
+        st = begin_call(p, s);
+    if (st == GRAV_OK)
+        st = enqueue_direct(p, rho, g_out, part, s);
     if (st == GRAV_OK)
         st = end_call(p, s);
     if (cur != p->device)
