@@ -202,6 +202,13 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
                 ck.fail("tmap", "entry out of range", v, p->lev[l].n_tgt);
         }
     }
+    // reverse interaction lists of the adjoint's M2L: offsets of the list and
+    // operator ids inside the 316 stored transposes
+    for (size_t e = 0; e < roff.size() && ck.ok; e += 4) {
+        const int mx = std::max(std::abs(roff[e]), std::max(std::abs(roff[e + 1]), std::abs(roff[e + 2])));
+        if (mx < 2 || mx > 3 || roff[e + 3] < 0 || roff[e + 3] >= kNumOffsets)
+            ck.fail("m2lT", "reverse list entry out of range", (long long)e, roff[e + 3]);
+    }
     for (int l = 2; l < L && ck.ok; ++l) {
         const DevLev &lv = g.lev[l];
         for (int64_t i = 0; i < p->lev[l].n_tgt && ck.ok; ++i) {
@@ -271,12 +278,8 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
         {
             const TileRange &r = p->tiles[TK_M2L][0];
             ResM2L res{&g, tiles.data() + r.off, tkey.data(), torder.data(), coff.data()};
-            check_stage(ck, "m2l", res, r, p->split[TK_M2L], kNumOffsets, xme, xle, w);
-        }
-        {
-            const TileRange &r = p->tiles[TK_M2LT][0];
-            ResM2LT res{&g, tiles.data() + r.off, tmap.data(), roff.data()};
-            check_stage(ck, "m2lT", res, r, p->split[TK_M2LT], kNumOffsets, xle, xme, w);
+            check_stage(ck, "m2l", res, r, p->split[TK_M2L],
+                        p->d.precision == GRAV_FP64 ? kNumOffsets : kCanonOffsets, xme, xle, w);
         }
         // M2M / M2M^T: every parent of a level >= 3 box lies in the block above
         for (int l = 3; l <= L && ck.ok; ++l) {

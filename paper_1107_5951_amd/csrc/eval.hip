@@ -821,6 +821,7 @@ DevGeom make_geom(const Plan *p)
             d.class_start[c] = s.class_start[c];
         d.tmap_off = s.tmap_off;
         d.tchild_off = s.tchild_off;
+        d.n_tgt = s.n_tgt;
     }
     g.L = p->L;
     g.b = p->b;

@@ -14,6 +14,7 @@ struct DevLev {
     int64_t class_start[9];
     int64_t tmap_off;
     int64_t tchild_off;
+    int64_t n_tgt;       // target boxes of the level
 };
 
 struct DevGeom {
@@ -127,8 +128,22 @@ __device__ __forceinline__ void load_frags(const T *set, int lane, T (&v)[E])
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
 
-__host__ __device__ inline double lre(const double *L, int n, int m) { return m == 0 ? L[n * n] : L[n * n + 2 * m - 1]; }
-__host__ __device__ inline double lim(const double *L, int n, int m) { return m == 0 ? 0.0 : L[n * n + 2 * m]; }
+// Coefficient accessors of the local-expansion evaluation: the real and
+// imaginary parts of coefficient (n, m) in the library's real order (degree
+// n block of 2n+1 values: real part of order 0, then real and imaginary
+// parts of orders 1..n).
+struct CoefArray {
+    const double *L;
+    __host__ __device__ double re(int n, int m) const { return m == 0 ? L[n * n] : L[n * n + 2 * m - 1]; }
+    __host__ __device__ double im(int n, int m) const { return m == 0 ? 0.0 : L[n * n + 2 * m]; }
+};
+// The unit vector of coefficient k: evaluating with it gives the derivatives
+// of the evaluation with respect to coefficient k (the transposed L2P).
+struct CoefUnit {
+    int k;
+    __host__ __device__ double re(int n, int m) const { return (m == 0 ? n * n : n * n + 2 * m - 1) == k ? 1.0 : 0.0; }
+    __host__ __device__ double im(int n, int m) const { return (m != 0 && n * n + 2 * m == k) ? 1.0 : 0.0; }
+};
 
 // Local expansion evaluation at u (box-width units from the box centre):
 // out[0] = sum L_j^k R_j^k(u), out[1..3] = its gradient with respect to u.
@@ -137,7 +152,8 @@ __host__ __device__ inline double lim(const double *L, int n, int m) { return m 
 // d/dz R_n^m = R_{n-1}^m, d/dx R_n^m = (R_{n-1}^{m-1} - R_{n-1}^{m+1})/2 and
 // d/dy R_n^m = i (R_{n-1}^{m-1} + R_{n-1}^{m+1})/2, each R_n^m pairs with
 // degree-(n+1) coefficients for the gradient.
-__host__ __device__ inline void l2p_eval(int P, const double *L, double x, double y, double z, double out[4])
+template <class Coef>
+__host__ __device__ inline void l2p_eval_t(int P, const Coef &L, double x, double y, double z, double out[4])
 {
     double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
     const double r2 = x * x + y * y + z * z;
@@ -169,22 +185,22 @@ __host__ __device__ inline void l2p_eval(int P, const double *L, double x, doubl
             p1r = Rr;
             p1i = Ri;
             if (m == 0)
-                phi += lre(L, n, 0) * Rr;
+                phi += L.re(n, 0) * Rr;
             else
-                phi += 2.0 * (lre(L, n, m) * Rr - lim(L, n, m) * Ri);
+                phi += 2.0 * (L.re(n, m) * Rr - L.im(n, m) * Ri);
             if (n + 1 < P) {
                 const int n1 = n + 1;
                 if (m == 0) {
-                    gz += Rr * lre(L, n1, 0);
-                    gx += Rr * lre(L, n1, 1);
-                    gy -= Rr * lim(L, n1, 1);
+                    gz += Rr * L.re(n1, 0);
+                    gx += Rr * L.re(n1, 1);
+                    gy -= Rr * L.im(n1, 1);
                 } else {
-                    gz += 2.0 * (Rr * lre(L, n1, m) - Ri * lim(L, n1, m));
-                    const double ar = lre(L, n1, m + 1) - lre(L, n1, m - 1);
-                    const double ai = lim(L, n1, m + 1) - lim(L, n1, m - 1);
+                    gz += 2.0 * (Rr * L.re(n1, m) - Ri * L.im(n1, m));
+                    const double ar = L.re(n1, m + 1) - L.re(n1, m - 1);
+                    const double ai = L.im(n1, m + 1) - L.im(n1, m - 1);
                     gx += Rr * ar - Ri * ai;
-                    const double br = lre(L, n1, m + 1) + lre(L, n1, m - 1);
-                    const double bi = lim(L, n1, m + 1) + lim(L, n1, m - 1);
+                    const double br = L.re(n1, m + 1) + L.re(n1, m - 1);
+                    const double bi = L.im(n1, m + 1) + L.im(n1, m - 1);
                     gy -= Rr * bi + Ri * br;
                 }
             }
@@ -194,6 +210,17 @@ __host__ __device__ inline void l2p_eval(int P, const double *L, double x, doubl
     out[1] = gx;
     out[2] = gy;
     out[3] = gz;
+}
+
+__host__ __device__ inline void l2p_eval(int P, const double *L, double x, double y, double z, double out[4])
+{
+    l2p_eval_t(P, CoefArray{L}, x, y, z, out);
+}
+
+// Derivatives of l2p_eval's four outputs with respect to coefficient k.
+__host__ __device__ inline void l2p_coef(int P, int k, double x, double y, double z, double out[4])
+{
+    l2p_eval_t(P, CoefUnit{k}, x, y, z, out);
 }
 
 }  // namespace grav

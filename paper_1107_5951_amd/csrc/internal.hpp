@@ -25,6 +25,16 @@ constexpr int kMaxLevels = 10;
 #define GRAV_M2L_NC64 1
 #endif
 constexpr int kNumOffsets = 316;   // M2L offsets d with 2 <= |d|_inf <= 3
+// The mixed-precision (FP32) forward M2L stores one operator per offset with
+// non-negative components (56 of them): the operator of any other offset is
+// that of its component-wise absolute value with the signs of a reflection
+// applied to its rows and columns (see m2l.hip).  Its offset tables hold the
+// operator index plus kReflShift times the reflection bits (x, y, z = bits
+// 0, 1, 2).  The FP64 forward M2L stores all 316 operators (reflection bits
+// zero): sign flips on 64-bit operands would cost the registers of a second
+// wave per SIMD.
+constexpr int kCanonOffsets = 56;
+constexpr int kReflShift = 512;
 constexpr int kClassOffsets = 189; // offsets valid for one child-parity class
 constexpr int kTileCols = 64;      // columns (box, model) per M2L tile
 constexpr int kMaxLeafCells = 8;     // leaf edge cap: a leaf's densities fit one 512-entry LDS stage
@@ -45,8 +55,8 @@ struct LevelInfo {
     int64_t src_class[8] = {0};       // source boxes of each parity class
 };
 
-// Tiled stages: forward and transposed M2L.
-enum TileKind { TK_M2L = 0, TK_M2LT, TK_COUNT };
+// Tiled stages: the forward M2L (its tiles also give the L2L its columns).
+enum TileKind { TK_M2L = 0, TK_COUNT };
 
 struct TileRange {
     int64_t off = 0;
@@ -90,7 +100,7 @@ struct Plan {
     // per stage: slot 0 = all levels, in launch order (each tile repeated
     // split[k] times); slot l >= 2 = level l's tiles in the unrepeated numbering
     TileRange tiles[TK_COUNT][kMaxLevels + 1];
-    int split[TK_COUNT] = {1, 1};
+    int split[TK_COUNT] = {1};
     // stream-K schedule of the forward M2L (see build_tiles): work items
     // (offset index per item, unit by unit), segments {unit, first item,
     // end item, 0} per workgroup (wgseg: CSR over workgroups), per unit its
@@ -126,10 +136,10 @@ struct Plan {
     double *d_pm = nullptr;        // [b^3][PS] lattice P2M
     double *d_m2m = nullptr;       // [8][PS][PS] M2M, stored [child][in][out]
     double *d_l2l = nullptr;       // [8][PS][PS] L2L, stored [child][in][out]
-    double *d_k64 = nullptr;       // [316][KS][RB][64] swizzled M2L (FP64)
-    double *d_k64T = nullptr;      // transposes
-    float *d_k32 = nullptr;        // same, FP32 (mixed precision)
-    float *d_k32T = nullptr;
+    double *d_k64 = nullptr;       // forward M2L operators as MFMA A fragments (FP64 plans: all 316)
+    float *d_k32 = nullptr;        // same, FP32 (mixed plans: the 56 stored operators)
+    double *d_kplain = nullptr;    // [316][p^2][p^2] M2L operators row-major, in the forward's
+                                   // precision (FP32-rounded for mixed plans), for the adjoint
 
     double *d_me = nullptr;        // [n_me][B][PS]
     double *d_le = nullptr;        // [n_tbox][B][PS]

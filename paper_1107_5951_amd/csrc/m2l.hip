@@ -13,6 +13,31 @@
 
 namespace grav {
 
+// Sign bits of real coefficient c (degree n block of 2n+1 values: the real
+// part of order 0, then real and imaginary parts of orders 1..n) under the
+// reflections of the z, y and x axes.
+__device__ inline void coef_sign_bits(int c, uint32_t &bz, uint32_t &by, uint32_t &bx)
+{
+    int n = 0;
+    while ((n + 1) * (n + 1) <= c)
+        ++n;
+    const int i = c - n * n;
+    const int m = (i + 1) / 2;
+    const uint32_t im = (i > 0 && (i & 1) == 0) ? 1u : 0u;
+    bz = (uint32_t)((n + m) & 1);
+    by = im;
+    bx = (uint32_t)((m + (int)im) & 1);
+}
+
+__device__ __forceinline__ float flip_sign(float v, uint32_t s)
+{
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ (s << 31));
+}
+__device__ __forceinline__ double flip_sign(double v, uint32_t s)
+{
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)s << 63));
+}
+
 // --------------------------------------------------------------------------
 // M2L on MFMA.  A tile is up to 64 columns (target box of one level and one
 // child-parity class, model), split into 4 / NC units of 16 NC columns; a
@@ -24,6 +49,17 @@ namespace grav {
 // LE[:, col] += K_d * ME[box(col) + d] with 16x16x4 MFMA tiles in registers
 // across the segment's offsets (no atomics), then writes the segment's
 // partial to its slot; every A fragment loaded feeds NC instructions.
+//
+// Operators: only the 56 offsets with non-negative components have stored
+// matrices.  Reflecting an axis maps the real solid harmonics into
+// themselves up to a sign per coefficient (degree n, order m, real or
+// imaginary part): z -> -z multiplies by (-1)^(n+m), y -> -y by -1 on
+// imaginary parts, x -> -x by (-1)^m on real and -(-1)^m on imaginary
+// parts.  So with S the diagonal sign matrix of the reflection r that maps
+// |d| to d, K_d = S K_|d| S: the kernel negates the A rows and the B entries
+// whose sign bit is set, which reproduces K_d exactly (a sign flip is exact),
+// and the operator set read by a launch shrinks from 316 to 56 matrices.
+// The FP64 kernel reads all 316 operators (reflection bits zero).
 //
 // Contraction order: k step ks and sub-row kr = lane / 16 of the 16x16x4
 // instruction take coefficient c = 4 ks + kr, so the coefficients c >= p^2
@@ -50,8 +86,27 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
       const int32_t *items, T *part)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
+    using kmask_t = std::conditional_t<(KSV > 32), uint64_t, uint32_t>;
     const int lane = threadIdx.x;  // one wave per workgroup
     constexpr int UPT = 4 / NC;      // units (waves' column blocks) per tile
+    // reflection sign bits of this lane's A rows (bit rb: row 16 rb + lane %
+    // 16) and B contraction indices (bit ks: coefficient 4 ks + lane / 16)
+    uint32_t rsz = 0, rsy = 0, rsx = 0;
+    kmask_t ksz = 0, ksy = 0, ksx = 0;
+    for (int rb = 0; rb < RB; ++rb) {
+        uint32_t bz, by, bx;
+        coef_sign_bits(16 * rb + (lane & 15), bz, by, bx);
+        rsz |= bz << rb;
+        rsy |= by << rb;
+        rsx |= bx << rb;
+    }
+    for (int ks = 0; ks < KSV; ++ks) {
+        uint32_t bz, by, bx;
+        coef_sign_bits(4 * ks + (lane >> 4), bz, by, bx);
+        ksz |= (kmask_t)bz << ks;
+        ksy |= (kmask_t)by << ks;
+        ksx |= (kmask_t)bx << ks;
+    }
     for (int sg = wgseg[blockIdx.x]; sg < wgseg[blockIdx.x + 1]; ++sg) {
         const int32_t *sd = segs + 4 * sg;  // unit, first item, end item
         const GemmTile tile = tiles[sd[0] / UPT];
@@ -99,11 +154,17 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
             const T *mp[NC];
             const T *kp;
             bool have[NC];
+            uint32_t rflip;   // bit rb: negate the A rows of row block rb
+            kmask_t kflip;    // bit ks: negate the B entries of k step ks
         };
         auto setup = [&](int it, Item &st) {
             const int o = items[it];
             const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
-            const int id = offs[4 * o + 3];
+            const int id = offs[4 * o + 3] % kReflShift;  // stored operator of |d|
+            const int refl = offs[4 * o + 3] / kReflShift;
+            st.rflip = ((refl & 4) ? rsz : 0u) ^ ((refl & 2) ? rsy : 0u) ^ ((refl & 1) ? rsx : 0u);
+            st.kflip = ((refl & 4) ? ksz : (kmask_t)0) ^ ((refl & 2) ? ksy : (kmask_t)0) ^
+                       ((refl & 1) ? ksx : (kmask_t)0);
             // the source boxes at this offset all belong to one parity class
             int first[3], cnt[3];
             const int64_t cstart =
@@ -137,21 +198,23 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
             for (int u = 0; u < 4; ++u) {
                 if (4 * q + u >= KSV)
                     break;  // k steps past the last coefficient are all zero
+                constexpr bool kFlip = sizeof(T) == 4;  // FP64 plans store all 316 operators
+                const uint32_t ks_flip = kFlip ? (uint32_t)(st.kflip >> (4 * q + u)) & 1u : 0u;
                 T bv[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
-                    bv[c] = st.have[c] ? bb[set][c][u] : (T)0;
+                    bv[c] = st.have[c] ? (kFlip ? flip_sign(bb[set][c][u], ks_flip) : bb[set][c][u]) : (T)0;
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
+                for (int rb = 0; rb < RB; ++rb) {
+                    const T a = kFlip ? flip_sign(av[set][u * RB + rb], (st.rflip >> rb) & 1u) : av[set][u * RB + rb];
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         if constexpr (sizeof(T) == 8)
-                            acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][u * RB + rb], bv[c],
-                                                                              acc[c][rb], 0, 0, 0);
+                            acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[c], acc[c][rb], 0, 0, 0);
                         else
-                            acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][u * RB + rb], bv[c],
-                                                                              acc[c][rb], 0, 0, 0);
+                            acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[c], acc[c][rb], 0, 0, 0);
                     }
+                }
             }
         };
         constexpr int NLD = NC + 4 * RB * (int)sizeof(T) / 16, NMF = 4 * RB * NC;

@@ -15,13 +15,6 @@
 #include "internal.hpp"
 #include "operators.hpp"
 
-// Splitting of the M2L offsets over workgroups (see build_tiles).
-#ifndef GRAV_M2L_SPLIT_MAX
-#define GRAV_M2L_SPLIT_MAX 32
-#endif
-#ifndef GRAV_M2L_TARGET_WG
-#define GRAV_M2L_TARGET_WG 8192
-#endif
 // One-wave workgroups of the forward M2L's stream-K schedule: all resident
 // at once (256 CUs x 4 SIMDs x 2 waves; both M2L kernels fit two waves per
 // SIMD).
@@ -290,7 +283,7 @@ void free_plan(Plan *p)
     void *bufs[] = {p->d_points, p->d_perm, p->d_tpos, p->d_tleaf, p->d_leaf_start, p->d_tkey,
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
-                    p->d_l2l, p->d_k64, p->d_k64T, p->d_k32, p->d_k32T, p->d_me,
+                    p->d_l2l, p->d_k64, p->d_kplain, p->d_k32, p->d_me,
                     p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg, p->d_lat_tab, p->d_m2l_items, p->d_m2l_segs,
                     p->d_m2l_wgseg, p->d_m2l_tseg_start, p->d_m2l_tsegs, p->d_m2l_colmap,
                     p->d_cell_slot, p->d_leaf_pend};
@@ -345,11 +338,32 @@ grav_status validate(const grav_plan_desc *d)
     return GRAV_OK;
 }
 
+// Index of the operator of offset |d| (components 0..3, largest >= 2) among
+// the 56 stored for the mixed-precision forward M2L, z slowest, x fastest.
+int canon_index(int ax, int ay, int az)
+{
+    int k = 0;
+    for (int z = 0; z <= 3; ++z)
+        for (int y = 0; y <= 3; ++y)
+            for (int x = 0; x <= 3; ++x) {
+                if (std::max(x, std::max(y, z)) < 2)
+                    continue;
+                if (x == ax && y == ay && z == az)
+                    return k;
+                ++k;
+            }
+    return -1;
+}
+
 // The 316 M2L offsets (2 <= |d|_inf <= 3), and per child-parity class the
-// 189 valid ones, entries (dx, dy, dz, offset id).  Forward: a target box of
-// class c sees sources at T + d for d_a in [-2 - c_a, 3 - c_a].  Transposed:
-// a source box S of class c feeds targets T = S - d whose class admits d.
-void offsets_tables(std::vector<int> &all, std::vector<int32_t> &fwd, std::vector<int32_t> &rev)
+// 189 valid ones, entries (dx, dy, dz, operator).  Forward: a target box of
+// class c sees sources at T + d for d_a in [-2 - c_a, 3 - c_a]; the operator
+// field is, with `canonical`, the index of |d| among the 56 stored operators
+// plus kReflShift times the reflection bits (bit a set where d_a < 0), else
+// the offset id.  Transposed: a source box S of class c
+// feeds targets T = S - d whose class admits d; the operator field is the
+// offset id (0..315, the transposed operators are stored per offset).
+void offsets_tables(std::vector<int> &all, std::vector<int32_t> &fwd, std::vector<int32_t> &rev, bool canonical)
 {
     all.clear();
     for (int dz = -3; dz <= 3; ++dz)
@@ -377,7 +391,10 @@ void offsets_tables(std::vector<int> &all, std::vector<int32_t> &fwd, std::vecto
             }
             if (okf) {
                 int32_t *e = &fwd[(c * kClassOffsets + nf++) * 4];
-                e[0] = d[0], e[1] = d[1], e[2] = d[2], e[3] = id;
+                const int refl = (d[0] < 0 ? 1 : 0) | (d[1] < 0 ? 2 : 0) | (d[2] < 0 ? 4 : 0);
+                e[0] = d[0], e[1] = d[1], e[2] = d[2];
+                e[3] = canonical ? canon_index(std::abs(d[0]), std::abs(d[1]), std::abs(d[2])) + kReflShift * refl
+                                 : id;
             }
             if (okr) {
                 int32_t *e = &rev[(c * kClassOffsets + nr++) * 4];
@@ -385,21 +402,6 @@ void offsets_tables(std::vector<int> &all, std::vector<int32_t> &fwd, std::vecto
             }
         }
     }
-}
-
-// Swizzle a dense [PS][PS] matrix (or its transpose) into the MFMA A-operand
-// order [ks][rb][lane] = K[16 rb + lane % 16][4 ks + lane / 16].
-void swizzle(const double *m, int PS, int KS, bool transpose, double *dst)
-{
-    const int RB = PS / 16;
-    for (int ks = 0; ks < KS; ++ks)
-        for (int rb = 0; rb < RB; ++rb)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int row = 16 * rb + (lane & 15);
-                const int col = 4 * ks + (lane >> 4);
-                dst[((size_t)ks * RB + rb) * 64 + lane] =
-                    transpose ? m[(size_t)col * PS + row] : m[(size_t)row * PS + col];
-            }
 }
 
 // Position of value e (of E per lane) of a lane in a set of MFMA operand
@@ -460,7 +462,7 @@ grav_status upload(Plan *p, T **dst, const std::vector<T> &src)
 
 grav_status build_operators(Plan *p)
 {
-    const int P = p->P, PS = p->PS, KS = p->KS, RB = PS / 16;
+    const int P = p->P, PS = p->PS, RB = PS / 16;
     const int b3 = p->b * p->b * p->b;
     std::vector<double> pm((size_t)b3 * PS);
     p2m_lattice(P, p->b, p->q, 1.0, PS, pm.data());
@@ -504,47 +506,42 @@ grav_status build_operators(Plan *p)
     }
 
     // M2L for all 316 offsets, swizzled for the MFMA A operand, and transposes
+    const bool canonical = p->d.precision != GRAV_FP64;
     std::vector<int> all;
     std::vector<int32_t> fwd, rev;
-    offsets_tables(all, fwd, rev);
-    const size_t per = (size_t)KS * RB * 64;
+    offsets_tables(all, fwd, rev, canonical);
     const size_t perp = (size_t)RB * 64 * 4 * RB;  // forward M2L: PS/4 k steps, grouped by four
-    std::vector<double> k(perp * kNumOffsets), kT(per * kNumOffsets);
+    const size_t P2 = (size_t)P * P;
+    std::vector<double> k(perp * (canonical ? kCanonOffsets : kNumOffsets)), kp(P2 * P2 * kNumOffsets);
     for (int id = 0; id < kNumOffsets; ++id) {
         // source = target + d  =>  target centre - source centre = -d
         const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
         m2l_matrix(P, dd, PS, m.data());
-        swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, k.data() + perp * id);
-        swizzle(m.data(), PS, KS, true, kT.data() + per * id);
+        // the adjoint's copy holds exactly the values the forward multiplies by
+        for (size_t i = 0; i < P2; ++i)
+            for (size_t j = 0; j < P2; ++j) {
+                const double v = m[i * PS + j];
+                kp[((size_t)id * P2 + i) * P2 + j] = canonical ? (double)(float)v : v;
+            }
+        // the forward operators: all 316, or the 56 with non-negative components
+        const int ci = canonical ? canon_index(all[3 * id], all[3 * id + 1], all[3 * id + 2]) : id;
+        if (ci >= 0)
+            swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, k.data() + perp * ci);
     }
     if (p->d.precision == GRAV_FP64) {
         GRAV_CHECK(upload(p, &p->d_k64, k));
-        GRAV_CHECK(upload(p, &p->d_k64T, kT));
     } else {
-        std::vector<float> k32(k.begin(), k.end()), k32T(kT.begin(), kT.end());
+        std::vector<float> k32(k.begin(), k.end());
         GRAV_CHECK(upload(p, &p->d_k32, k32));
-        GRAV_CHECK(upload(p, &p->d_k32T, k32T));
     }
+    GRAV_CHECK(upload(p, &p->d_kplain, kp));
     GRAV_CHECK(upload(p, &p->d_class_off, fwd));
     GRAV_CHECK(upload(p, &p->d_rclass_off, rev));
     return GRAV_OK;
 }
 
-// Source boxes of parity class c in a dense block.
-int64_t class_count(const LevelInfo &lv, int c)
-{
-    int64_t n = 1;
-    for (int a = 0; a < 3; ++a) {
-        const int par = (c >> a) & 1;
-        const int first = lv.s0[a] + ((par - lv.s0[a]) & 1);
-        n *= std::max(0, (lv.ns[a] - (first - lv.s0[a]) + 1) / 2);
-    }
-    return n;
-}
-
-// Tile lists of the M2L stages: 64 columns (4 waves x 16) per tile, per
-// level and child-parity class; forward columns are target boxes, transposed
-// columns source boxes.
+// Tile lists of the M2L stage: 64 columns (4 waves x 16) per tile, per
+// level and child-parity class; the columns are target boxes (x models).
 grav_status build_tiles(Plan *p)
 {
     std::vector<GemmTile> all;
@@ -575,21 +572,13 @@ grav_status build_tiles(Plan *p)
         for (int l = 2; l <= L; ++l)
             for (int c = 0; c < 8; ++c)
                 add(TK_M2L, l, c, (p->lev[l].class_start[c + 1] - p->lev[l].class_start[c]) * B);
-        for (int l = 2; l <= L; ++l)
-            for (int c = 0; c < 8; ++c)
-                add(TK_M2LT, l, c, class_count(p->lev[l], c) * B);
     }
-    // Transposed M2L: split the 189 offsets of each tile over S workgroups
-    // when there are too few tiles to fill the device; the S partial
-    // expansions are summed in a fixed order afterwards.  The forward M2L is
-    // not split this way (S = 1): it runs on the stream-K schedule below.
+    // Tiles are not split over workgroups (S = 1): the forward M2L runs on
+    // the stream-K schedule below.
     std::vector<GemmTile> split;
     for (int k = 0; k < TK_COUNT; ++k) {
         TileRange &r = p->tiles[k][0];
-        const int S = (r.n == 0 || k == TK_M2L)
-                          ? 1
-                          : (int)std::min<int64_t>(GRAV_M2L_SPLIT_MAX,
-                                                   std::max<int64_t>(1, ceil_div(GRAV_M2L_TARGET_WG, r.n)));
+        const int S = 1;
         p->split[k] = S;
         const int64_t off = (int64_t)split.size();
         for (int64_t i = 0; i < r.n; ++i)
@@ -618,7 +607,7 @@ grav_status build_tiles(Plan *p)
         if (r.n > 0) {
             std::vector<int> alloffs;
             std::vector<int32_t> fwd, rev;
-            offsets_tables(alloffs, fwd, rev);
+            offsets_tables(alloffs, fwd, rev, false);  // only the offsets themselves are used here
             std::vector<std::vector<uint32_t>> key(L + 1);
             std::vector<std::vector<int32_t>> ord(L + 1);
             for (int l = 2; l <= L; ++l) {
@@ -1376,9 +1365,7 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
         }
         {
             // partial expansions of split M2L stages
-            size_t part = (size_t)p->m2l_nseg * p->m2l_ncw * p->PS;  // forward M2L segment slots
-            if (p->split[TK_M2LT] > 1)
-                part = std::max(part, (size_t)p->split[TK_M2LT] * p->n_me * p->B * p->PS);
+            const size_t part = (size_t)p->m2l_nseg * p->m2l_ncw * p->PS;  // forward M2L segment slots
             if ((st = dalloc(p, &p->d_part, part, false)) != GRAV_OK)
                 break;
         }

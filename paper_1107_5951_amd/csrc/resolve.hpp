@@ -1,10 +1,8 @@
-// Index helpers of the M2L stages: tile/column/term resolution for the
+// Index helpers of the M2L stage: tile/column/term resolution for the
 // forward M2L (columns are target boxes of one child-parity class, terms the
-// class's 189 interaction-list offsets) and the transposed M2L (columns are
-// source boxes of one class, terms the offsets d with S - d a target box whose
-// class admits d).  The functions compile for host and device: the M2L
-// kernels use them, and grav_plan_check runs them on the host to validate a
-// plan's tables.
+// class's 189 interaction-list offsets).  The functions compile for host and
+// device: the M2L kernels use them, and grav_plan_check runs them on the
+// host to validate a plan's tables.
 #pragma once
 
 #include "eval_common.hpp"
@@ -75,7 +73,7 @@ struct ResM2L {
     const GemmTile *tiles;
     const uint32_t *tkey;
     const int32_t *torder;
-    const int32_t *offs;  // [8][189][4]: dx, dy, dz, offset id (0..315)
+    const int32_t *offs;  // [8][189][4]: dx, dy, dz, operator index + kReflShift x reflection bits
     __host__ __device__ int nterms(const GemmTile &) const { return kClassOffsets; }
     __host__ __device__ GemmCol column(const GemmTile &t, int cl) const
     {
@@ -96,7 +94,7 @@ struct ResM2L {
     __host__ __device__ GemmTerm term(const GemmTile &t, int i) const
     {
         const int32_t *e = offs + (t.cls * kClassOffsets + i) * 4;
-        return GemmTerm{e[3], e[0], e[1], e[2]};
+        return GemmTerm{e[3] % kReflShift, e[0], e[1], e[2]};  // canonical operator index
     }
     // position of the source expansion in the regathered (class-split) array
     // the M2L reads, computed as the kernel does; a position that does not
@@ -121,49 +119,6 @@ struct ResM2L {
     __host__ __device__ int64_t out(const GemmTile &t, const GemmCol &c) const
     {
         return (g->lev[t.level].tgt_off + c.box) * g->B + c.bm;
-    }
-};
-
-// Transposed M2L: columns = source boxes of one class; terms = offsets d
-// with S - d a target box whose class admits d; X = LE adjoint, Y = ME
-// adjoint (store).
-struct ResM2LT {
-    const DevGeom *g;
-    const GemmTile *tiles;
-    const int32_t *tmap;
-    const int32_t *offs;  // reverse class tables, same layout as ResM2L's
-    __host__ __device__ int nterms(const GemmTile &) const { return kClassOffsets; }
-    __host__ __device__ GemmCol column(const GemmTile &t, int cl) const
-    {
-        GemmCol c{};
-        c.valid = cl < t.ncol;
-        if (!c.valid)
-            return c;
-        const DevLev &lv = g->lev[t.level];
-        const int64_t col = t.col0 + cl;
-        c.bm = (int)(col % g->B);
-        int xyz[3];
-        class_box((int)(col / g->B), t.cls, lv.s0, lv.ns, xyz);
-        c.x = xyz[0];
-        c.y = xyz[1];
-        c.z = xyz[2];
-        c.box = dense_index(lv, c.x, c.y, c.z);
-        return c;
-    }
-    __host__ __device__ GemmTerm term(const GemmTile &t, int i) const
-    {
-        const int32_t *e = offs + (t.cls * kClassOffsets + i) * 4;
-        return GemmTerm{e[3], e[0], e[1], e[2]};
-    }
-    __host__ __device__ int64_t src(const GemmTile &t, const GemmCol &c, const GemmTerm &m) const
-    {
-        const DevLev &lv = g->lev[t.level];
-        const int64_t ti = tmap_lookup(lv, tmap, 3, c.x - m.dx, c.y - m.dy, c.z - m.dz);
-        return ti < 0 ? -1 : (lv.tgt_off + ti) * g->B + c.bm;
-    }
-    __host__ __device__ int64_t out(const GemmTile &t, const GemmCol &c) const
-    {
-        return (g->lev[t.level].me_off + c.box) * g->B + c.bm;
     }
 };
 

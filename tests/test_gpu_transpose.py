@@ -1,0 +1,167 @@
+"""GPU adjoint (grav_adjoint, the per-element transposed kernels): exact
+transpose of the forward FMM, the autograd wrapper, and the batched inversion
+workload.  Eq. (1) of the paper (Sec. 1.1) is linear in rho, so the adjoint
+of the FMM is the FMM's own transpose:
+
+* dot-product identity <A rho, r> = <rho, A^T r> to rounding (1e-12 in FP64;
+  the mixed-precision forward rounds its M2L and near field to FP32, so 1e-5);
+* parity with the oracle's transpose (the exact sum's adjoint) within the
+  forward's accuracy bar;
+* the gradient of 0.5 ||gz - d||^2 through GravFMM against central
+  differences of the same FMM misfit (exact for a quadratic, up to rounding);
+* the batched inversion gradient (128^3 cells, 32 models, 256 x 256
+  stations) against the oracle's transpose at the FP64 and mixed bars.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+G = pytest.importorskip("paper_1107_5951_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dot_gap(spec, rho, seed=0):
+    plan = G.Plan(spec)
+    assert plan.check() == "ok"  # host-side validation of every index table the kernels read
+    r = torch.as_tensor(np.ascontiguousarray(rho), device="cuda").reshape(plan.rho_shape)
+    g = plan.eval(r)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    res = torch.randn(plan.out_shape, dtype=torch.float64, device="cuda", generator=gen)
+    d = plan.adjoint(res)
+    torch.cuda.synchronize()
+    lhs = float((g * res).sum())
+    rhs = float((r * d).sum())
+    return abs(lhs - rhs) / (float(g.norm()) * float(res.norm())), plan
+
+
+# smallest first: a tree with no far field, then deeper trees
+CASES = [
+    ("all-near q2", dict(n=(8, 8, 8), h=1 / 8, quad_order=2, points=W.stations(10, 1.1),
+                         voxel_centres=True, components=4, p=4, leaf_size=4096)),
+    ("stations p8", dict(n=(16, 16, 16), h=1 / 16, quad_order=1, points=W.stations(32, 1.1),
+                         components=1, p=8, leaf_size=32)),
+    ("volume q2 p10", dict(n=(32, 32, 32), h=1 / 32, quad_order=2, voxel_centres=True, components=3,
+                           p=10, leaf_size=512)),
+    ("ragged phi+g", dict(n=(13, 7, 9), h=0.1, origin=(-0.3, 0.2, -1.0), quad_order=1,
+                          points=np.random.default_rng(4).uniform(-1.5, 2.0, size=(300, 3)),
+                          components=4, p=12, leaf_size=8)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_transpose_dot_product_fp64(name, kw):
+    n = kw["n"]
+    rho = np.random.default_rng(1).normal(size=(n[2], n[1], n[0]))
+    _say("adjoint dot product, FP64:", name)
+    gap, plan = _dot_gap(G.PlanSpec(**kw), rho)
+    _say("  gap %.3e levels %d leaf %d" % (gap, plan.levels, plan.leaf_cells))
+    assert gap <= 1e-12
+
+
+def test_transpose_dot_product_batched_and_mixed():
+    grid = W.Grid.unit(16)
+    rho = np.stack([W.gaussian_blobs(grid, 8, 2000 + b) for b in range(3)])
+    spec = G.PlanSpec(n=(16, 16, 16), h=grid.h, points=W.stations(16, 1.1), voxel_centres=True,
+                      components=3, p=8, leaf_size=64, batch=3)
+    gap, _ = _dot_gap(spec, rho)
+    _say("adjoint dot product, FP64 batch 3: %.3e" % gap)
+    assert gap <= 1e-12
+    spec.precision = G.GRAV_MIXED
+    gap, _ = _dot_gap(spec, rho)
+    _say("adjoint dot product, mixed batch 3: %.3e" % gap)
+    assert gap <= 1e-5
+
+
+def test_transpose_matches_oracle_transpose():
+    rng = np.random.default_rng(2)
+    grid = W.Grid.unit(16)
+    st = np.concatenate([W.stations(16, 1.1), rng.uniform(-0.2, 1.2, size=(200, 3))])
+    spec = G.PlanSpec(n=(16, 16, 16), h=grid.h, quad_order=2, points=st, components=3, p=14,
+                      leaf_size=64)
+    plan = G.Plan(spec)
+    res = rng.normal(size=(st.shape[0], 3))
+    d = plan.adjoint(torch.as_tensor(res, device="cuda")).cpu().numpy()
+    ref = oracle.adjoint(res, grid.origin, grid.h, 2, grid.shape, st, comps=3)
+    e = oracle.rel_l2(d, ref)
+    _say("adjoint vs oracle transpose (FP64 p=14): %.3e" % e)
+    assert e <= 1e-6
+
+
+def test_autograd_gradient_matches_finite_differences():
+    grid = W.Grid.unit(16)
+    st = W.stations(24, 1.1)
+    spec = G.PlanSpec(n=(16, 16, 16), h=grid.h, points=st, components=1, p=10, leaf_size=64)
+    plan = G.Plan(spec)
+    rho0 = torch.as_tensor(W.gaussian_blobs(grid, 8, 1999), device="cuda")
+    d = plan.eval(rho0 * 0.9 + 0.01)[:, 0].detach()
+    rho = rho0.clone().requires_grad_(True)
+    gz = G.GravFMM.apply(rho, plan)[:, 0]
+    loss = 0.5 * ((gz - d) ** 2).sum()
+    loss.backward()
+    grad = rho.grad.detach().cpu().numpy().ravel()
+    cells = W.sample_indices(grid.ncell, 16, seed=5)
+    eps = 1e-3 * float(rho0.abs().max())
+
+    def f(x):
+        return 0.5 * float(((plan.eval(x)[:, 0] - d) ** 2).sum())
+
+    worst = 0.0
+    for c in cells:
+        e = torch.zeros(grid.ncell, dtype=torch.float64, device="cuda")
+        e[c] = eps
+        e = e.reshape(grid.shape)
+        fd = (f(rho0 + e) - f(rho0 - e)) / (2 * eps)
+        worst = max(worst, abs(fd - grad[c]) / np.abs(grad).max())
+        assert fd == pytest.approx(grad[c], rel=1e-6, abs=1e-9 * np.abs(grad).max())
+    _say("autograd gradient vs central differences, 16 cells: worst %.3e (of max |grad|)" % worst)
+
+
+@pytest.fixture(scope="module")
+def inversion():
+    """128^3 cells, 1-point rule, 32 density models (8 blobs each, seeds
+    2000 + b) on one tree, gz at 256 x 256 stations at z = 1.1; data
+    d = forward(true rho, seed 1999) + N(0, 1e-3) (seed 1004)."""
+    n, B = 128, 32
+    grid = W.Grid.unit(n)
+    st = W.stations(256, 1.1)
+    rhos = np.stack([W.gaussian_blobs(grid, 8, 2000 + b) for b in range(B)])
+    true = W.gaussian_blobs(grid, 8, 1999)
+    return grid, st, rhos, true
+
+
+@pytest.mark.parametrize("prec,p,bar", [(0, 14, 1e-6), (1, 10, 1e-4)])
+def test_config4_inversion_gradient(inversion, prec, p, bar):
+    grid, st, rhos, true = inversion
+    n, B = grid.nx, rhos.shape[0]
+    spec = G.PlanSpec(n=(n, n, n), h=grid.h, points=st, components=1, p=p, leaf_size=64, batch=B,
+                      precision=prec)
+    _say("config4 inversion plan prec=%d p=%d" % (prec, p))
+    plan = G.Plan(spec)
+    plan1 = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, points=st, components=1, p=p, leaf_size=64,
+                              precision=prec))
+    d = plan1.eval(torch.as_tensor(true, device="cuda"))[:, 0]
+    d = d + 1e-3 * torch.randn(d.shape, dtype=torch.float64, device="cuda",
+                               generator=torch.Generator(device="cuda").manual_seed(1004))
+    rho = torch.as_tensor(rhos, device="cuda").requires_grad_(True)
+    gz = G.GravFMM.apply(rho, plan)[..., 0]
+    loss = 0.5 * ((gz - d[None]) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    resid = (gz.detach() - d[None]).cpu().numpy()
+    grad = rho.grad.detach().cpu().numpy().reshape(B, -1)
+    cells = W.sample_indices(grid.ncell, 4096, seed=9)
+    refg = oracle.adjoint_cells(resid[:4, :, None], grid.origin, grid.h, 1, grid.shape, st, cells, comps=1)
+    errs = [oracle.rel_l2(grad[b, cells], refg[b]) for b in range(4)]
+    _say("  gradient vs oracle transpose (4 models x 4096 cells): max %.3e (bar %g)" % (max(errs), bar))
+    assert max(errs) <= bar
