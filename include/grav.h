@@ -125,13 +125,18 @@ grav_status grav_plan_work(grav_plan_t plan, int64_t *m2l_pairs, int64_t *p2p_pa
  * and accepts NULL buffers.  Errors: EINVAL (NULL pointer), EBUSY, EDEVICE. */
 grav_status grav_eval(grav_plan_t plan, const double *rho, double *g_out, void *stream);
 
-/* Adjoint (exact transpose of grav_eval's linear map rho -> g):
+/* Adjoint: the exact transpose of grav_eval's linear map rho -> g (Eq. (1)
+ * of Sec. 1.1 is linear in rho, and so is every FMM stage of Sec. 2.3), so
+ * that <grav_eval(rho), r> = <rho, grav_adjoint(r)> to rounding and the
+ * gradient of a misfit such as 0.5 ||gz - d||^2 is grav_adjoint(gz - d).
  * resid:    device pointer, double [batch][n_targets][components];
  * drho_out: device pointer, double [batch][nz][ny][nx]; overwritten with
  *           drho[b][cell] = sum_j,c resid[b][j][c] * d g[b][j][c] / d rho[b][cell].
- * Same asynchrony and errors as grav_eval.  Unless the library is compiled
- * with GRAV_ENABLE_ADJOINT defined, this path is switched off: the call
- * validates its arguments and returns GRAV_EUNSUPPORTED. */
+ * The transposed stages use the forward's operators (in mixed precision the
+ * FP32-rounded M2L matrices), interaction lists, point pairs and
+ * coincidence rule; the near field is transposed in the forward's arithmetic
+ * type.  Uses the plan's workspace (shared with grav_eval).  Same asynchrony
+ * and errors as grav_eval; a plan with no evaluation points writes zeros. */
 grav_status grav_adjoint(grav_plan_t plan, const double *resid, double *drho_out, void *stream);
 
 /* Direct summation (the summation method of Sec. 2.1, SUM-G1 / SUM-G2): the

@@ -22,6 +22,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+# extra hipcc flags for the HIP sources, e.g. -D overrides of the kernels'
+# tuning macros (GRAV_M2L_*, GRAV_NEAR_*)
+FLAGS += os.environ.get("GRAV_HIPFLAGS", "").split()
 
 
 def _compile(src: str) -> str:

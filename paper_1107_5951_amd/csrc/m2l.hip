@@ -1,13 +1,22 @@
 // M2L on MFMA for the forward pass (kept in its own file: its measured HBM
 // traffic is tied to this source).
+#include <algorithm>
 #include <type_traits>
 
 #include "resolve.hpp"
 
 // Largest per-lane A chunk (bytes) for which the M2L keeps two register
-// sets (loads of the next chunk in flight during this chunk's MFMAs).
-#ifndef GRAV_M2L_DB_BYTES
-#define GRAV_M2L_DB_BYTES 512
+// sets (loads of the next chunk in flight during this chunk's MFMAs), per
+// element type.  The FP32 kernel keeps one set: its registers then leave
+// room for three waves per SIMD at p = 10 (five at p = 8), which hide the
+// load latency better than a second set does (measured on the 256^3 volume
+// workload: M2L 10.5 against 10.9 ms at p = 10, 4.3 against 4.6 ms at p = 8).
+// The FP64 kernel keeps two sets up to p = 16.
+#ifndef GRAV_M2L_DB_BYTES32
+#define GRAV_M2L_DB_BYTES32 0
+#endif
+#ifndef GRAV_M2L_DB_BYTES64
+#define GRAV_M2L_DB_BYTES64 512
 #endif
 
 
@@ -184,7 +193,8 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         // two register sets (when they fit): the loads of chunk q + 1 (or of
         // the next item's first chunk) are in flight while the instructions
         // of chunk q run
-        constexpr int NSET = 4 * RB * (int)sizeof(T) <= GRAV_M2L_DB_BYTES ? 2 : 1;
+        constexpr int NSET =
+            4 * RB * (int)sizeof(T) <= (sizeof(T) == 4 ? GRAV_M2L_DB_BYTES32 : GRAV_M2L_DB_BYTES64) ? 2 : 1;
         T av[NSET][4 * RB];
         T bb[NSET][NC][4];
         auto load = [&](const Item &st, int q, int set) {
@@ -352,5 +362,45 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
 
 template grav_status launch_m2l<double>(Plan *, const DevGeom &, hipStream_t, const double *);
 template grav_status launch_m2l<float>(Plan *, const DevGeom &, hipStream_t, const float *);
+
+// One-wave workgroups of the plan's M2L kernel that the device holds at once
+// (blocks per CU from the occupancy calculator, times the CUs): the size of
+// the stream-K schedule, so that every worker is resident from the start.
+grav_status m2l_resident_workers(const Plan *p, int *workers)
+{
+    const bool f64 = p->d.precision == GRAV_FP64;
+    const void *fn = nullptr;
+#define M2L_FN(P)                                                                                          \
+    case P:                                                                                                \
+        fn = f64 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64, double>) \
+                 : reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32, float>);  \
+        break;
+    switch (p->P) {
+        M2L_FN(1)
+        M2L_FN(2)
+        M2L_FN(3)
+        M2L_FN(4)
+        M2L_FN(5)
+        M2L_FN(6)
+        M2L_FN(7)
+        M2L_FN(8)
+        M2L_FN(9)
+        M2L_FN(10)
+        M2L_FN(11)
+        M2L_FN(12)
+        M2L_FN(13)
+        M2L_FN(14)
+        M2L_FN(15)
+        M2L_FN(16)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef M2L_FN
+    int per_cu = 0, n_cu = 0;
+    GRAV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0));
+    GRAV_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+    *workers = std::max(1, per_cu) * std::max(1, n_cu);
+    return GRAV_OK;
+}
 
 }  // namespace grav

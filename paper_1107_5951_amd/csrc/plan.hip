@@ -15,11 +15,11 @@
 #include "internal.hpp"
 #include "operators.hpp"
 
-// One-wave workgroups of the forward M2L's stream-K schedule: all resident
-// at once (256 CUs x 4 SIMDs x 2 waves; both M2L kernels fit two waves per
-// SIMD).
+// Upper bound on the one-wave workgroups of the forward M2L's stream-K
+// schedule; the plan takes as many as the device holds at once
+// (m2l_resident_workers), up to this.
 #ifndef GRAV_M2L_WAVES
-#define GRAV_M2L_WAVES 2048
+#define GRAV_M2L_WAVES 8192
 #endif
 
 namespace grav {
@@ -662,7 +662,10 @@ grav_status build_tiles(Plan *p)
             // at least kMinItems items per workgroup: small plans get fewer
             // workgroups rather than one partial slot per item
             constexpr int64_t kMinItems = 8;
-            const int64_t P = std::max<int64_t>(1, std::min<int64_t>(GRAV_M2L_WAVES, T / kMinItems));
+            int resident = 0;
+            GRAV_CHECK(m2l_resident_workers(p, &resident));
+            const int64_t P = std::max<int64_t>(
+                1, std::min<int64_t>(std::min<int64_t>(GRAV_M2L_WAVES, resident), T / kMinItems));
             std::vector<int32_t> seg, wgseg(P + 1, 0), tseg_n(nunit + 1, 0);
             for (int64_t w = 0; w < P; ++w) {
                 wgseg[w] = (int32_t)(seg.size() / 4);
