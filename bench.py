@@ -475,27 +475,13 @@ def paper_sequence(args):
 
 
 def serving(args):
-    """The serving workload: a seeded Poisson trace (rate 50/s) of requests on
-    meshes n = round(exp U[ln 32, ln 192]), q in {1, 2}, gz at n x n stations,
-    mixed precision; served back to back (capacity) and at the trace's
-    arrival times (latency under load)."""
-    import torch
-
+    """The serving workload: a seeded Poisson trace (rate 50/s, seed 1005) of
+    forward and adjoint requests (50/50) on meshes n = round(exp U[ln 32,
+    ln 192]), q in {1, 2}, gz at n x n stations, mixed precision p = 10;
+    graph-captured solves with continuous batching, served back to back
+    (capacity) and at the trace's arrival times (latency under load)."""
     from paper_1107_5951_amd import serve
-    reqs = serve.poisson_trace(args.serve, rate=50.0, seed=1005, host_blobs=False)
-    srv = serve.GravServer(n_streams=4)
-    t0 = time.perf_counter()
-    for r in reqs:
-        srv.cache.get(r.n, r.q)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    _, cap = srv.run(reqs)
-    _, live = srv.run(reqs, realtime=True)
-    srv.close()
-    print(json.dumps({"workload": "serving: %d Poisson requests at 50/s, n in [32, 192], q in {1, 2}, "
-                                  "gz at n^2 stations, mixed" % args.serve,
-                      "plans": len(set((r.n, r.q) for r in reqs)), "plan_build_s": build_s,
-                      "capacity": cap, "realtime": live}), flush=True)
+    print(json.dumps(serve.benchmark(args.serve)), flush=True)
 
 
 def crossover(args):

@@ -121,8 +121,13 @@ grav_status grav_plan_work(grav_plan_t plan, int64_t *m2l_pairs, int64_t *p2p_pa
  * Asynchronous: enqueues kernels only (no allocation, no host sync); the
  * caller keeps rho and g_out alive until the stream reaches that point.
  * Calls on one plan from different streams while earlier work is still in
- * flight return GRAV_EBUSY.  A plan with no evaluation points does nothing
- * and accepts NULL buffers.  Errors: EINVAL (NULL pointer), EBUSY, EDEVICE. */
+ * flight return GRAV_EBUSY.  The call may be recorded into a HIP graph
+ * (stream capture): it enqueues kernels only (no memset, allocation or
+ * host synchronisation); during capture the workspace lock is neither
+ * checked nor updated, so the caller serialises the replays of graphs that
+ * share a plan (and profiling must be off: GRAV_EUNSUPPORTED otherwise).  A
+ * plan with no evaluation points does nothing and accepts NULL buffers.
+ * Errors: EINVAL (NULL pointer), EBUSY, EDEVICE. */
 grav_status grav_eval(grav_plan_t plan, const double *rho, double *g_out, void *stream);
 
 /* Adjoint: the exact transpose of grav_eval's linear map rho -> g (Eq. (1)

@@ -315,6 +315,13 @@ k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, int64_t n_le
     drho[t] = acc + near;
 }
 
+__global__ void __launch_bounds__(256) k_t_zero(double *x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        x[i] = 0.0;
+}
+
 }  // namespace
 
 grav_status enqueue_adjoint(Plan *p, const double *resid, double *drho, hipStream_t s)
@@ -395,9 +402,11 @@ extern "C" grav_status grav_adjoint(grav_plan_t plan, const double *resid, doubl
     grav_status st = begin_call(p, s);
     if (st == GRAV_OK) {
         if (p->M == 0) {
-            // no evaluation points: the transpose is zero
+            // no evaluation points: the transpose is zero (a fill kernel, not a
+            // memset, so that the call can be recorded in a graph)
             const int64_t n = (int64_t)p->d.nx * p->d.ny * p->d.nz * p->B;
-            st = hipMemsetAsync(drho_out, 0, sizeof(double) * n, s) == hipSuccess ? GRAV_OK : GRAV_EDEVICE;
+            hipLaunchKernelGGL(k_t_zero, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, drho_out, n);
+            st = hipGetLastError() == hipSuccess ? GRAV_OK : GRAV_EDEVICE;
         } else {
             st = enqueue_adjoint(p, resid, drho_out, s);
         }

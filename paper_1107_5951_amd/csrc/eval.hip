@@ -1055,8 +1055,22 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
     return GRAV_OK;
 }
 
+// Workspace lock of a plan: a call on another stream while the previous
+// call's work is still in flight returns GRAV_EBUSY.  Under stream capture
+// (a HIP graph being recorded) nothing is enqueued yet, so the lock is not
+// consulted or updated and no event is recorded; the replays of a captured
+// call are the caller's to serialise.
+static bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 grav_status begin_call(Plan *p, hipStream_t s)
 {
+    p->n_stage_used = 0;
+    if (capturing(s))
+        return p->profiling ? GRAV_EUNSUPPORTED : GRAV_OK;
     if (p->has_pending && p->last_stream != s) {
         const hipError_t q = hipEventQuery(p->done);
         if (q == hipErrorNotReady)
@@ -1064,12 +1078,13 @@ grav_status begin_call(Plan *p, hipStream_t s)
         if (q != hipSuccess)
             return GRAV_EDEVICE;
     }
-    p->n_stage_used = 0;
     return GRAV_OK;
 }
 
 grav_status end_call(Plan *p, hipStream_t s)
 {
+    if (capturing(s))
+        return GRAV_OK;
     GRAV_HIP(hipEventRecord(p->done, s));
     p->has_pending = true;
     p->last_stream = s;

@@ -1,18 +1,30 @@
-"""Serving loop for many small forward solves on one GPU.
+"""Serving loop for gravity inversion workloads on one GPU.
 
-Requests are independent gravity forward models: a density on an n x n x n
-unit-cube mesh (1- or 2-point rule) and gz at n x n stations at z = 1.1.
-The server keeps a cache of plans keyed by the request's geometry, admits
-plans against an HBM budget using their reported footprint
-(``grav_plan_bytes``), and keeps several requests in flight on a small pool
-of HIP streams.  A plan's workspace serves one call at a time, so every plan
-is bound to one stream and its requests run there in arrival order; requests
-of different plans overlap.  Results do not depend on what else is in
-flight: each evaluation uses only its own plan and buffers, and every kernel
-is deterministic.
+Requests are independent forward or adjoint solves: a density on an
+n x n x n unit-cube mesh (1- or 2-point rule) mapped to gz at n x n stations
+at z = 1.1 (forward), or gz residuals at those stations mapped back to a
+density gradient (adjoint, the transpose of the forward map).
 
-The transposed (adjoint) solve is not served: ``grav_adjoint`` is switched
-off in the library build.
+* Plans stay resident: a slot is one plan (mesh size, rule, batch size) with
+  its own HIP stream, static input and output buffers and, by default, one
+  captured HIP graph per direction, so serving a request is a device copy of
+  its input, a graph replay and a device copy of its output.
+* Admission by HBM footprint: a slot's bytes are the plan's reported
+  footprint (grav_plan_bytes) plus its static buffers.  A request whose slot
+  does not fit the budget waits until enough in-flight work finishes for
+  idle slots to be evicted (least recently used first); it is rejected only
+  when its slot alone exceeds the budget.
+* Continuous batching: whenever a stream slot frees up, the oldest waiting
+  request is started together with the other waiting requests of the same
+  mesh, rule and direction, as one batched solve (batch sizes 1, 2, 4, 8;
+  unused batch members are computed and ignored).  Requests that arrive
+  while others run are admitted as slots and memory free up, and their work
+  overlaps on the device with the work already in flight.
+
+Results do not depend on what else is in flight: each slot's work uses only
+its own plan and buffers, every kernel is deterministic, and a batched solve
+computes each model independently (its rounding can differ from a
+single-model solve only in the order of the M2L partial sums).
 """
 from __future__ import annotations
 
@@ -25,23 +37,29 @@ import numpy as np
 
 from . import GRAV_MIXED, Plan, PlanSpec
 
+BATCH_SIZES = (1, 2, 4, 8)
+
 
 @dataclasses.dataclass
 class Request:
     n: int                      # cells per axis of the unit-cube mesh
     q: int                      # 1- or 2-point rule per axis
-    rho: object                 # float64 HIP tensor [n, n, n]
-    kind: str = "forward"
+    data: object                # forward: float64 HIP tensor [n, n, n] (rho);
+                                # adjoint: float64 HIP tensor [n * n] (gz residuals)
+    kind: str = "forward"       # "forward" or "adjoint"
     arrival: float = 0.0        # seconds, trace time
 
 
 @dataclasses.dataclass
 class Result:
     index: int
-    out: object                 # float64 HIP tensor [n*n, 1] (gz at the stations)
-    t_submit: float
+    kind: str
+    out: object = None          # forward: [n * n] gz; adjoint: [n, n, n] drho
+    t_arrive: float = 0.0
+    t_start: float = 0.0
     t_done: float = 0.0
-    event: object = None
+    batch: int = 1
+    error: Optional[str] = None
 
 
 def station_grid(ns: int, z: float = 1.1) -> np.ndarray:
@@ -51,140 +69,262 @@ def station_grid(ns: int, z: float = 1.1) -> np.ndarray:
     return np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], axis=1)
 
 
-class PlanCache:
-    """LRU cache of plans with an HBM budget on their resident + workspace bytes."""
+def plan_spec(n: int, q: int, batch: int = 1, p: int = 10, precision: int = GRAV_MIXED,
+              leaf_size: int = 64) -> PlanSpec:
+    """The plan a request of mesh n and rule q is served with."""
+    return PlanSpec(n=(n, n, n), h=1.0 / n, quad_order=q, points=station_grid(n), components=1, p=p,
+                    leaf_size=leaf_size * q ** 3, precision=precision, batch=batch)
 
-    def __init__(self, budget_bytes: int, p: int = 10, precision: int = GRAV_MIXED, leaf_size: int = 64):
-        self.budget = int(budget_bytes)
-        self.p, self.precision, self.leaf_size = p, precision, leaf_size
-        self._plans: "collections.OrderedDict[Tuple[int, int], Plan]" = collections.OrderedDict()
-        self._bytes: Dict[Tuple[int, int], int] = {}
-        self.hits = self.misses = self.evictions = 0
+
+class Slot:
+    """A resident plan with its stream, static buffers and captured graphs."""
+
+    def __init__(self, n: int, q: int, batch: int, p: int, precision: int, graphs: bool):
+        import torch
+        self.torch = torch
+        self.key = (n, q, batch)
+        self.plan = Plan(plan_spec(n, q, batch, p, precision))
+        self.stream = torch.cuda.Stream()  # default priority
+        dev = torch.device("cuda")
+        self.rho = torch.zeros(self.plan.rho_shape, dtype=torch.float64, device=dev)
+        self.g = torch.zeros(self.plan.out_shape, dtype=torch.float64, device=dev)
+        self.resid = torch.zeros(self.plan.out_shape, dtype=torch.float64, device=dev)
+        self.drho = torch.zeros(self.plan.rho_shape, dtype=torch.float64, device=dev)
+        resident, per_call = self.plan.bytes()
+        self.nbytes = resident + per_call + 8 * (2 * self.rho.numel() + 2 * self.g.numel())
+        self.graphs: Dict[str, object] = {}
+        self.event = None           # completion of the last launch
+        self.last_used = 0.0
+        self._run("forward")        # eager warm-up on the slot's stream
+        self._run("adjoint")
+        if graphs:
+            self._capture()
+        torch.cuda.synchronize()
+
+    def _run(self, kind: str) -> None:
+        if kind == "forward":
+            self.plan.eval(self.rho, self.g, stream=self.stream)
+        else:
+            self.plan.adjoint(self.resid, self.drho, stream=self.stream)
+
+    def _capture(self) -> None:
+        torch = self.torch
+        torch.cuda.synchronize()
+        for kind in ("forward", "adjoint"):
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=self.stream):
+                self._run(kind)
+            self.graphs[kind] = graph
 
     @property
-    def used(self) -> int:
-        return sum(self._bytes.values())
+    def busy(self) -> bool:
+        return self.event is not None and not self.event.query()
 
-    def get(self, n: int, q: int) -> Plan:
-        key = (n, q)
-        if key in self._plans:
-            self._plans.move_to_end(key)
-            self.hits += 1
-            return self._plans[key]
-        self.misses += 1
-        spec = PlanSpec(n=(n, n, n), h=1.0 / n, quad_order=q, points=station_grid(n), components=1,
-                        p=self.p, leaf_size=self.leaf_size * q ** 3, precision=self.precision)
-        plan = Plan(spec)
-        resident, per_call = plan.bytes()
-        need = resident + per_call
-        if need > self.budget:
-            plan.close()
-            raise MemoryError("plan for n=%d q=%d needs %d bytes, budget %d" % (n, q, need, self.budget))
-        while self._plans and self.used + need > self.budget:
-            old, victim = self._plans.popitem(last=False)
-            del self._bytes[old]
-            victim.close()
-            self.evictions += 1
-        self._plans[key] = plan
-        self._bytes[key] = need
-        return plan
+    def launch(self, kind: str, reqs: List[Request], src_stream) -> List[object]:
+        """Copy the requests' inputs into the static buffers, run the solve
+        (graph replay or eager) and copy each request's output out, all on the
+        slot's stream; returns the output tensors."""
+        torch = self.torch
+        s = self.stream
+        s.wait_stream(src_stream)  # inputs were produced on the caller's stream
+        outs = []
+        with torch.cuda.stream(s):
+            for b, r in enumerate(reqs):
+                if kind == "forward":
+                    self.rho[b].copy_(r.data.reshape(self.rho.shape[1:]))
+                else:
+                    self.resid[b].copy_(r.data.reshape(self.resid.shape[1:]))
+                r.data.record_stream(s)
+            if kind in self.graphs:
+                self.graphs[kind].replay()
+            else:
+                self._run(kind)
+            for b in range(len(reqs)):
+                src = self.g[b, :, 0] if kind == "forward" else self.drho[b]
+                outs.append(src.clone())
+            self.event = torch.cuda.Event()
+            self.event.record(s)
+        return outs
 
     def close(self) -> None:
-        for plan in self._plans.values():
-            plan.close()
-        self._plans.clear()
-        self._bytes.clear()
+        if self.event is not None:
+            self.event.synchronize()
+        self.graphs.clear()
+        self.plan.close()
 
 
 class GravServer:
-    """Dispatch forward requests to a pool of streams, one stream per plan."""
+    """Continuous-batching server for forward and adjoint requests."""
 
-    def __init__(self, n_streams: int = 4, budget_bytes: int = 64 << 30, p: int = 10,
-                 precision: int = GRAV_MIXED):
+    def __init__(self, budget_bytes: int = 64 << 30, max_inflight: int = 4, p: int = 10,
+                 precision: int = GRAV_MIXED, batching: bool = True, graphs: bool = True):
         import torch
         self.torch = torch
-        self.cache = PlanCache(budget_bytes, p=p, precision=precision)
-        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]  # default priority
-        self._stream_of: Dict[Tuple[int, int], int] = {}
-        self._next = 0
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.p, self.precision = p, precision
+        self.batching, self.use_graphs = batching, graphs
+        self.slots: "collections.OrderedDict[Tuple[int, int, int], Slot]" = collections.OrderedDict()
+        self._footprint: Dict[Tuple[int, int, int], int] = {}
+        self.stats = collections.Counter()
 
-    def _stream_for(self, key: Tuple[int, int]):
-        if key not in self._stream_of:
-            self._stream_of[key] = self._next % len(self.streams)
-            self._next += 1
-        return self.streams[self._stream_of[key]]
+    # ------------------------------------------------------------ admission
+    @property
+    def used(self) -> int:
+        return sum(s.nbytes for s in self.slots.values())
 
-    def submit(self, index: int, req: Request) -> Result:
-        torch = self.torch
-        if req.kind != "forward":
-            raise NotImplementedError("only forward requests are served")
-        plan = self.cache.get(req.n, req.q)
-        s = self._stream_for((req.n, req.q))
-        t0 = time.perf_counter()
-        # the request's input was produced on the current stream
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
-            plan.eval(req.rho, out, stream=s)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        req.rho.record_stream(s)
-        return Result(index, out[0], t0, event=ev)
+    def _slot(self, n: int, q: int, batch: int) -> Optional[Slot]:
+        """The resident slot for (n, q, batch), built if the budget allows
+        (evicting idle slots, least recently used first); None if it has to
+        wait for in-flight work to finish; MemoryError if it can never fit."""
+        key = (n, q, batch)
+        if key in self.slots:
+            self.slots.move_to_end(key)
+            self.stats["slot_hits"] += 1
+            return self.slots[key]
+        need = self._footprint.get(key)
+        if need is not None:
+            if need > self.budget:
+                raise MemoryError("a plan for n=%d q=%d batch %d needs %d bytes, budget %d"
+                                  % (n, q, batch, need, self.budget))
+            if not self._make_room(need):
+                self.stats["admission_waits"] += 1
+                return None
+        slot = Slot(n, q, batch, self.p, self.precision, self.use_graphs)
+        self._footprint[key] = slot.nbytes
+        self.stats["slot_builds"] += 1
+        if slot.nbytes > self.budget:
+            slot.close()
+            raise MemoryError("a plan for n=%d q=%d batch %d needs %d bytes, budget %d"
+                              % (n, q, batch, slot.nbytes, self.budget))
+        if not self._make_room(slot.nbytes):
+            slot.close()
+            self.stats["admission_waits"] += 1
+            return None
+        self.slots[key] = slot
+        return slot
 
+    def _make_room(self, need: int) -> bool:
+        """Evict idle slots (least recently used first) until `need` more bytes
+        fit the budget; False if only in-flight slots are left to evict."""
+        while self.used + need > self.budget:
+            idle = [k for k, s in self.slots.items() if not s.busy]
+            if not idle:
+                return False
+            self.slots.pop(idle[0]).close()
+            self.stats["evictions"] += 1
+        return True
+
+    # ------------------------------------------------------------ serving
     def run(self, requests: List[Request], realtime: bool = False) -> Tuple[List[Result], dict]:
-        """Serve a trace.  realtime=True waits for each arrival time (latency
-        under load); otherwise requests are submitted back to back
-        (capacity).  Returns the results and summary statistics."""
-        results: List[Result] = []
-        pending: List[Result] = []
-        t_start = time.perf_counter()
+        """Serve a trace.  realtime=True admits each request at its arrival
+        time (latency under load); otherwise all requests are waiting from the
+        start (capacity).  Returns the results in request order and summary
+        statistics (latency from arrival to completion)."""
+        torch = self.torch
+        src = torch.cuda.current_stream()
+        results = [Result(i, r.kind) for i, r in enumerate(requests)]
+        waiting: "collections.deque[int]" = collections.deque()
+        inflight: List[Tuple[Slot, List[int]]] = []
+        nxt = 0
+        t0 = time.perf_counter()
+        self.stats.clear()
 
-        def reap(block: bool):
-            nonlocal pending
+        def now():
+            return time.perf_counter() - t0
+
+        def reap():
+            nonlocal inflight
             keep = []
-            for r in pending:
-                if block:
-                    r.event.synchronize()
-                if r.event.query():
-                    r.t_done = time.perf_counter()
+            for slot, idx in inflight:
+                if slot.event.query():
+                    t = now()
+                    for i in idx:
+                        results[i].t_done = t
                 else:
-                    keep.append(r)
-            pending = keep
+                    keep.append((slot, idx))
+            inflight = keep
 
-        for i, req in enumerate(requests):
-            if realtime:
-                while time.perf_counter() - t_start < req.arrival:
-                    reap(False)
-                    time.sleep(0.0002)
-            r = self.submit(i, req)
-            if realtime:
-                r.t_submit = t_start + req.arrival
-            results.append(r)
-            pending.append(r)
-            reap(False)
-        reap(True)
-        wall = time.perf_counter() - t_start
-        lat = sorted((r.t_done - r.t_submit) * 1e3 for r in results)
+        while nxt < len(requests) or waiting or inflight:
+            # admit arrivals
+            while nxt < len(requests) and (not realtime or requests[nxt].arrival <= now()):
+                results[nxt].t_arrive = requests[nxt].arrival if realtime else 0.0
+                waiting.append(nxt)
+                nxt += 1
+            reap()
+            started = False
+            tried = set()
+            # the oldest waiting request of each (mesh, rule, direction) in
+            # arrival order, with the waiting requests that share its plan
+            for i in list(waiting):
+                if len(inflight) >= self.max_inflight:
+                    break
+                head = requests[i]
+                kind, key = head.kind, (head.n, head.q)
+                if (kind, key) in tried or i not in waiting:
+                    continue
+                tried.add((kind, key))
+                group = [j for j in waiting if requests[j].kind == kind and
+                         (requests[j].n, requests[j].q) == key] if self.batching else [i]
+                group = group[:BATCH_SIZES[-1]]
+                batch = next(b for b in BATCH_SIZES if b >= len(group))
+                try:
+                    slot = self._slot(head.n, head.q, batch)
+                except MemoryError as e:
+                    for j in group:
+                        results[j].error = str(e)
+                        results[j].t_done = now()
+                        waiting.remove(j)
+                    continue
+                if slot is None or slot.busy:
+                    continue  # memory or this plan's stream frees up later
+                t = now()
+                outs = slot.launch(kind, [requests[j] for j in group], src)
+                for j, o in zip(group, outs):
+                    results[j].out = o
+                    results[j].t_start = t
+                    results[j].batch = batch
+                    waiting.remove(j)
+                inflight.append((slot, group))
+                slot.last_used = t
+                self.stats["batches"] += 1
+                self.stats["batched_requests"] += len(group)
+                started = True
+            if not started:
+                if inflight and (waiting or nxt >= len(requests)):
+                    inflight[0][0].event.synchronize()
+                elif realtime and nxt < len(requests):
+                    time.sleep(min(2e-4, max(0.0, requests[nxt].arrival - now())))
+        torch.cuda.synchronize()
+        wall = now()
+        ok = [r for r in results if r.error is None]
+        lat = sorted((r.t_done - r.t_arrive) * 1e3 for r in ok)
         pick = lambda q: lat[min(len(lat) - 1, int(round(q / 100.0 * (len(lat) - 1))))] if lat else 0.0
-        evals = sum(r.out.shape[0] for r in results)
-        stats = {"requests": len(results), "wall_s": wall, "requests_per_s": len(results) / wall,
-                 "gz_evals_per_s": evals / wall, "p50_ms": pick(50), "p99_ms": pick(99),
-                 "plan_hits": self.cache.hits, "plan_misses": self.cache.misses,
-                 "plan_evictions": self.cache.evictions, "plan_bytes": self.cache.used}
+        evals = sum(requests[r.index].n ** 2 for r in ok)
+        stats = {"requests": len(results), "served": len(ok), "rejected": len(results) - len(ok),
+                 "forward": sum(1 for r in ok if r.kind == "forward"),
+                 "adjoint": sum(1 for r in ok if r.kind == "adjoint"),
+                 "wall_s": wall, "requests_per_s": len(ok) / wall, "gz_evals_per_s": evals / wall,
+                 "p50_ms": pick(50), "p99_ms": pick(99), "resident_slots": len(self.slots),
+                 "resident_bytes": self.used, "graphs": self.use_graphs}
+        stats.update({k: int(v) for k, v in self.stats.items()})
         return results, stats
 
     def close(self) -> None:
         self.torch.cuda.synchronize()
-        self.cache.close()
+        for s in self.slots.values():
+            s.close()
+        self.slots.clear()
 
 
 def poisson_trace(count: int, rate: float, seed: int, n_min: int = 32, n_max: int = 192,
-                  device: str = "cuda", host_blobs: bool = True) -> List[Request]:
-    """Synthetic request trace: Poisson arrivals, n log-uniform on
-    [n_min, n_max], q uniform in {1, 2}.  Densities: 8 seeded Gaussian blobs
+                  adjoint_fraction: float = 0.5, device: str = "cuda", host_blobs: bool = True) -> List[Request]:
+    """Synthetic request trace: Poisson arrivals at `rate` per second, n
+    log-uniform on [n_min, n_max], q uniform in {1, 2}, adjoint with
+    probability `adjoint_fraction`.  Forward inputs: 8 seeded Gaussian blobs
     (seed + request index) built on the host, or, with host_blobs=False,
-    seeded uniform noise drawn on the device (for timing runs with large
-    meshes, where host generation would dominate)."""
+    seeded uniform noise drawn on the device (timing runs with large meshes);
+    adjoint inputs: seeded standard normal residuals at the n x n stations."""
     import torch
 
     from workloads import Grid, gaussian_blobs
@@ -193,13 +333,45 @@ def poisson_trace(count: int, rate: float, seed: int, n_min: int = 32, n_max: in
     t = np.cumsum(rng.exponential(1.0 / rate, size=count))
     ns = np.rint(np.exp(rng.uniform(np.log(n_min), np.log(n_max), size=count))).astype(int)
     qs = rng.integers(1, 3, size=count)
+    adj = rng.uniform(size=count) < adjoint_fraction
     reqs = []
     for i in range(count):
         n = int(ns[i])
-        if host_blobs:
-            rho = torch.as_tensor(gaussian_blobs(Grid.unit(n), 8, seed + 1 + i), device=device)
+        gen = torch.Generator(device=device).manual_seed(seed + 1 + i)
+        if adj[i]:
+            data = torch.randn((n * n,), dtype=torch.float64, device=device, generator=gen)
+        elif host_blobs:
+            data = torch.as_tensor(gaussian_blobs(Grid.unit(n), 8, seed + 1 + i), device=device)
         else:
-            gen = torch.Generator(device=device).manual_seed(seed + 1 + i)
-            rho = torch.rand((n, n, n), dtype=torch.float64, device=device, generator=gen)
-        reqs.append(Request(n=n, q=int(qs[i]), rho=rho, arrival=float(t[i])))
+            data = torch.rand((n, n, n), dtype=torch.float64, device=device, generator=gen)
+        reqs.append(Request(n=n, q=int(qs[i]), data=data, kind="adjoint" if adj[i] else "forward",
+                            arrival=float(t[i])))
     return reqs
+
+
+def benchmark(count: int = 3000, rate: float = 50.0, seed: int = 1005) -> dict:
+    """The serving workload: a Poisson trace of forward and adjoint requests
+    (50/50), meshes 32^3 .. 192^3, q in {1, 2}, mixed precision at p = 10;
+    plans and graphs are built first (timed separately), then the trace is
+    served back to back (capacity) and at its arrival times (latency under
+    load).  The back-to-back figure is the second pass over the trace, with
+    the batched slots its first pass built resident."""
+    import torch
+    reqs = poisson_trace(count, rate, seed, host_blobs=False)
+    srv = GravServer(budget_bytes=128 << 30)
+    t0 = time.perf_counter()
+    for key in sorted(set((r.n, r.q) for r in reqs)):
+        srv._slot(key[0], key[1], 1)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    _, cold = srv.run(reqs)             # builds the batched slots it needs
+    _, cap = srv.run(reqs)              # back to back, slots resident
+    _, live = srv.run(reqs, realtime=True)
+    srv.close()
+    cap["first_pass_wall_s"] = cold["wall_s"]
+    cap["first_pass_slot_builds"] = cold.get("slot_builds", 0)
+    return {"workload": "serving: %d Poisson requests at %g/s (seed %d), forward and adjoint 50/50, n in [32, 192], "
+                        "q in {1, 2}, gz at n^2 stations, mixed precision p=10, graph replays, continuous batching"
+                        % (count, rate, seed),
+            "plans": len(set((r.n, r.q) for r in reqs)), "plan_and_graph_build_s": build_s,
+            "capacity": cap, "realtime": live}
