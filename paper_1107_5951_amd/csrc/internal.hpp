@@ -134,8 +134,8 @@ struct Plan {
     struct DevGeom *d_geom = nullptr;
 
     double *d_pm = nullptr;        // [b^3][PS] lattice P2M
-    double *d_m2m = nullptr;       // [8][PS][PS] M2M, stored [child][in][out]
-    double *d_l2l = nullptr;       // [8][PS][PS] L2L, stored [child][in][out]
+    double *d_m2m = nullptr;       // [8][PS][PS] M2M per child octant, row-major [out][in] (adjoint)
+    double *d_l2l = nullptr;       // [8][PS][PS] L2L per child octant, row-major [out][in] (adjoint)
     double *d_k64 = nullptr;       // forward M2L operators as MFMA A fragments (FP64 plans: all 316)
     float *d_k32 = nullptr;        // same, FP32 (mixed plans: the 56 stored operators)
     double *d_kplain = nullptr;    // [316][p^2][p^2] M2L operators row-major, in the forward's

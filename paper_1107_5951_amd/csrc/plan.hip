@@ -470,20 +470,17 @@ grav_status build_operators(Plan *p)
     if (p->L < 2)
         return GRAV_OK;
 
-    // M2M / L2L: [child][in s][out t] (the transpose of the matrix), so that
-    // thread t of the forward kernels reads consecutive entries
+    // M2M / L2L row-major, [octant][out][in], for the adjoint: its thread
+    // for input coefficient j reads column j, so a wave's loads at one row
+    // are consecutive
     std::vector<double> m((size_t)PS * PS), m2m(8 * (size_t)PS * PS), l2l(8 * (size_t)PS * PS);
     for (int c = 0; c < 8; ++c) {
         const double delta[3] = {((c & 1) - 0.5) * 0.5, (((c >> 1) & 1) - 0.5) * 0.5,
                                  (((c >> 2) & 1) - 0.5) * 0.5};
         m2m_matrix(P, delta, PS, m.data());
-        for (int t = 0; t < PS; ++t)
-            for (int s2 = 0; s2 < PS; ++s2)
-                m2m[((size_t)c * PS + s2) * PS + t] = m[(size_t)t * PS + s2];
+        std::copy(m.begin(), m.end(), m2m.begin() + (size_t)c * PS * PS);
         l2l_matrix(P, delta, PS, m.data());
-        for (int t = 0; t < PS; ++t)
-            for (int s2 = 0; s2 < PS; ++s2)
-                l2l[((size_t)c * PS + s2) * PS + t] = m[(size_t)t * PS + s2];
+        std::copy(m.begin(), m.end(), l2l.begin() + (size_t)c * PS * PS);
     }
     GRAV_CHECK(upload(p, &p->d_m2m, m2m));
     GRAV_CHECK(upload(p, &p->d_l2l, l2l));
