@@ -38,7 +38,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "gz evals/s (src·tgt pairs/s equiv) at rel err ≤1e-6/1e-4; p50/p99 latency"
-PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vector": 157.3, "fp64_vector": 78.6}
+PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 P2P_FLOP_PER_PAIR = 20.0  # Sec. 1.1 cost model: one kernel evaluation ~ 20 flops
 PRISM = ((0.4, 0.6), (0.4, 0.6), (0.2, 0.5))
 
@@ -145,37 +145,55 @@ def m2l_kernel_name(p, prec):
 
 
 def roofline(plan, stages, p, prec, profile):
-    """Roofline of the dominant stage: algorithmic flops per launch over the
-    stage's event-measured duration (one launch per evaluation)."""
+    """Roofline of the dominant stage: its algorithmic work per launch over
+    the stage's event-measured duration.  Compute-bound stages count flops
+    (M2L: 2 p^4 per box pair and model; lattice near field: 27 x 2 x 4b^3 x
+    b^3 per leaf and model; M2M: 8 x 2 p^4 per parent box and model); the P2M
+    on a surface-target plan is bound by HBM and counts the bytes it must
+    move (the densities read and the leaf expansions written)."""
     from paper_1107_5951_amd import GRAV_FP64
     m2l_pairs, p2p_pairs, _ = plan.work()
     B = plan.spec.batch
     b = plan.leaf_cells
-    n = plan.spec.n
-    n_leaf_src = 1
-    for a in range(3):
-        n_leaf_src *= -(-int(n[a]) // b)
+    n = [int(v) for v in plan.spec.n]
+    L = plan.levels
+    leaves = [-(-v // b) for v in n]
+    n_leaf_src = leaves[0] * leaves[1] * leaves[2]
+    parents = 0
+    for lvl in range(2, L):
+        c = 1
+        for a in range(3):
+            c *= -(-leaves[a] // (1 << (L - lvl)))
+        parents += c
     f64 = prec == GRAV_FP64
     mm = "fp64_mfma" if f64 else "fp32_mfma"
+    ps = -(-p * p // 16) * 16
     cand = {
         "m2l": (2.0 * p ** 4 * m2l_pairs * B, m2l_kernel_name(p, prec) + " (M2L, %s MFMA 16x16x4)"
-                % ("FP64" if f64 else "FP32"), "mfma", mm),
+                % ("FP64" if f64 else "FP32"), "mfma", mm, "TFLOP/s"),
         "near_lat": (27 * 2.0 * (4 * b ** 3) * b ** 3 * n_leaf_src * B,
                      "k_near_lat<%d,2,%s> (lattice near field, %s MFMA 16x16x4)"
-                     % ((2, "double", "FP64") if f64 else (4, "float", "FP32")), "mfma", mm),
+                     % ((2, "double", "FP64") if f64 else (4, "float", "FP32")), "mfma", mm, "TFLOP/s"),
+        "m2m": (8 * 2.0 * p ** 4 * parents * B, "k_m2m_lds<%d> / k_m2m_split<%d> (M2M, FP64 MFMA 16x16x4)"
+                % (ps // 16, ps // 16), "mfma", "fp64_mfma", "TFLOP/s"),
+        # the leaf's cells times the lattice P2M matrix (p^2 x b^3, FP64)
+        "p2m": (2.0 * p * p * b ** 3 * n_leaf_src * B, "k_p2m_mfma<%d> (P2M, FP64 MFMA 16x16x4)" % (ps // 16),
+                "mfma", "fp64_mfma", "TFLOP/s"),
     }
     if "near_lat" not in stages:
         # every near pair is a direct (point) pair only without the lattice path
         cand["p2p"] = (P2P_FLOP_PER_PAIR * p2p_pairs * B, "k_p2p (direct near field, VALU)", "alu",
-                       "fp64_vector" if f64 else "fp32_vector")
-    dom = max((k for k in cand if k in stages), key=lambda k: stages[k])
-    fl, kname, bound, pk = cand[dom]
-    roof = {"kernel": kname, "bound": bound, "achieved": fl / (stages[dom] * 1e-3) / 1e12,
-            "peak": PEAK[pk], "unit": "TFLOP/s"}
+                       "fp64_vector" if f64 else "fp32_vector", "TFLOP/s")
+    live = [k for k in cand if k in stages and cand[k][0] > 0]
+    dom = max(live, key=lambda k: stages[k])
+    work, kname, bound, pk, unit = cand[dom]
+    scale = 1e9 if unit == "GB/s" else 1e12
+    roof = {"kernel": kname, "bound": bound, "achieved": work / (stages[dom] * 1e-3) / scale,
+            "peak": PEAK[pk], "unit": unit}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(profile, kname) if profile else None
     roof["kernel_ms"] = stages.get(dom)
-    roof["flop_per_launch"] = fl
+    roof["work_per_launch"] = work
     return roof
 
 

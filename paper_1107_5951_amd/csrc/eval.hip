@@ -7,89 +7,194 @@
 
 #include "resolve.hpp"
 
+#ifndef GRAV_M2M_LDS_MIN_WG
+#define GRAV_M2M_LDS_MIN_WG 256  // 64-column M2M tiles from this many workgroups on
+#endif
+
 namespace grav {
 
 // --------------------------------------------------------------------------
 // P2M on the lattice: the scaled ME of a leaf is a fixed linear map of its
-// b^3 cell densities (all leaves share the point layout), ME = Pm * rho_leaf.
-// A workgroup takes LB consecutive columns (leaf, model): their densities
-// are staged in LDS, and thread t produces coefficient t of all LB columns,
-// so each operator entry it loads feeds LB multiply-adds.
+// b^3 cell densities (all leaves share the point layout), ME = Pm^T rho_leaf,
+// a GEMM with rows = coefficients, contraction = the leaf's cells and
+// columns = (model, leaf), leaves fastest.  FP64 MFMA: a wave owns 16
+// columns and all row blocks; k step kv and sub-row kr take cell 4 kv + kr.
+// With b = 4 the 64 lanes of one k step read one contiguous run of 64 cell
+// densities (16 consecutive leaves along x, four cells each), and every
+// density is read once.
 // --------------------------------------------------------------------------
-template <int LB>
-__global__ void __launch_bounds__(256) k_p2m(DevGeom g, const double *rho, const double *pm, double *me)
+template <int RB>
+__global__ void __launch_bounds__(64) k_p2m_mfma(DevGeom g, const double *rho, const double *A, int KV, double *me)
 {
-    extern __shared__ double sh[];  // [LB][b^3]
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int KB = 8;  // density loads issued together
     const DevLev &lv = g.lev[g.L];
-    const int b = g.b, b3 = b * b * b;
-    const int64_t ncol = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
-    const int64_t col0 = (int64_t)blockIdx.x * LB;
+    const int lane = threadIdx.x;
+    const int b = g.b, b2 = b * b, b3 = b2 * b;
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    // the leaf decomposition in the index type I: 32-bit whenever the column
-    // count allows (64-bit integer division is a long instruction sequence)
-    auto stage = [&](auto zero) {
-        using I = decltype(zero);
-        for (int e = threadIdx.x; e < LB * b3; e += blockDim.x) {
-            const int l = e / b3, v = e - l * b3;
-            const I col = (I)(col0 + l);
-            double r = 0.0;
-            if (col < (I)ncol) {
-                const I leaf = col / (I)g.B;
-                const int bm = (int)(col - leaf * (I)g.B);
-                const I ns0 = (I)lv.ns[0], ns1 = (I)lv.ns[1];
-                const int lx = (int)(leaf % ns0), ly = (int)((leaf / ns0) % ns1), lz = (int)(leaf / (ns0 * ns1));
-                const int ix = (lv.s0[0] + lx - g.shift[0]) * b + v % b;
-                const int iy = (lv.s0[1] + ly - g.shift[1]) * b + (v / b) % b;
-                const int iz = (lv.s0[2] + lz - g.shift[2]) * b + v / (b * b);
+    const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const bool cvalid = col < nleaf * g.B;
+    const int bm = cvalid ? (int)(col / nleaf) : 0;
+    const int64_t leaf = cvalid ? col - (int64_t)bm * nleaf : 0;
+    const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    const int cx = (lv.s0[0] + lx - g.shift[0]) * b, cy = (lv.s0[1] + ly - g.shift[1]) * b,
+              cz = (lv.s0[2] + lz - g.shift[2]) * b;
+    const double *rb0 = rho + (int64_t)bm * ncell;
+    const int kr = lane >> 4;
+    vec4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < KV; k0 += KB) {
+        double rv[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int v = 4 * (k0 + u) + kr;
+            rv[u] = 0.0;
+            if (cvalid && k0 + u < KV && v < b3) {
+                const int ix = cx + v % b, iy = cy + (v / b) % b, iz = cz + v / b2;
                 if (ix >= 0 && iy >= 0 && iz >= 0 && ix < g.n[0] && iy < g.n[1] && iz < g.n[2])
-                    r = rho[bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+                    rv[u] = rb0[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
             }
-            sh[e] = r;
         }
-    };
-    if (ncol + LB <= (int64_t)0x7fffffff)
-        stage(int32_t(0));
-    else
-        stage(int64_t(0));
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t >= g.PS)
-        return;
-    double acc[LB];
 #pragma unroll
-    for (int l = 0; l < LB; ++l)
-        acc[l] = 0.0;
-#pragma unroll 4
-    for (int v = 0; v < b3; ++v) {
-        const double w = pm[(int64_t)v * g.PS + t];
+        for (int u = 0; u < KB; ++u) {
+            if (k0 + u >= KV)
+                break;
+            const double *ap = A + (int64_t)(k0 + u) * RB * 64 + lane;
 #pragma unroll
-        for (int l = 0; l < LB; ++l)
-            acc[l] += w * sh[l * b3 + v];
+            for (int r = 0; r < RB; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[r * 64], rv[u], acc[r], 0, 0, 0);
+        }
     }
+    if (!cvalid)
+        return;
+    // output fragment: column lane % 16, rows lane / 16 + 4 r of each block
+    double *dst = me + ((lv.me_off + leaf) * g.B + bm) * PS;
 #pragma unroll
-    for (int l = 0; l < LB; ++l)
-        if (col0 + l < ncol)
-            me[(lv.me_off * g.B + col0 + l) * g.PS + t] = acc[l];
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            dst[16 * r + kr + 4 * i] = acc[r][i];
 }
 
 // --------------------------------------------------------------------------
 // M2M on MFMA (FP64): ME[parent] = sum over the 8 children c of T_c ME[child],
-// a GEMM with columns = (parent box, model) and K = 8 x p^2.  A workgroup
-// owns 16 columns and one 16-row block; its eight waves take one child each
-// (so each wave waits on a single round of loads) and their partial
-// fragments are added through LDS in wave order.  Children outside the
-// source block contribute nothing.
+// a GEMM with M = p^2 rows, K = 8 p^2 and columns = (parent box, model).
+// The operator is stored as 8 RB chunks of four k steps each (all row
+// blocks of a k step together, 64 lanes per fragment); within a child the
+// contraction order is kr * PS/4 + ks, so a lane's four k steps of a chunk
+// are four consecutive coefficients of its child's expansion.  A child
+// outside the source block contributes zero.
+//
+// Large levels: k_m2m_lds.  A workgroup owns 64 columns (16 per wave) and
+// all row blocks; the chunks of the operator pass through LDS (double
+// buffered, one barrier per chunk), so each is read from L2 once per 64
+// columns instead of once per wave, and each wave streams its columns'
+// child expansions once.
 // --------------------------------------------------------------------------
 template <int RB>
-__global__ void __launch_bounds__(512)
-k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
+__global__ void __launch_bounds__(256) k_m2m_lds(DevGeom g, int l, const double *A, double *me)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int K4 = PS / 4;
+    constexpr int CH = 4 * RB * 64;  // doubles per chunk: 4 k steps x RB blocks x 64 lanes
+    constexpr int NCH = 8 * RB;      // chunks: 8 children x RB chunks of 4 k steps
+    __shared__ double sa[2][CH];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const DevLev &lp = g.lev[l];
+    const DevLev &lc = g.lev[l + 1];
+    const int64_t nbox = (int64_t)lp.ns[0] * lp.ns[1] * lp.ns[2];
+    const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
+    const bool cvalid = col < nbox * g.B;
+    const int64_t box = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
+    const int px = lp.s0[0] + (int)(box % lp.ns[0]);
+    const int py = lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1]);
+    const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
+    const int kr = lane >> 4;
+    // the column's expansion of child c (nullptr: no such child)
+    auto child = [&](int c) -> const double2 * {
+        const int64_t ci = cvalid ? dense_index(lc, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1),
+                                                2 * pz + ((c >> 2) & 1))
+                                  : -1;
+        return ci >= 0 ? (const double2 *)(me + ((lc.me_off + ci) * g.B + bm) * PS + kr * K4) : nullptr;
+    };
+    vec4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    double ra[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        ra[i] = A[i * 256 + tid];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        sa[0][i * 256 + tid] = ra[i];
+    const double2 *bp = child(0);
+    double2 b01 = bp ? bp[0] : double2{0.0, 0.0};
+    double2 b23 = bp ? bp[1] : double2{0.0, 0.0};
+    __syncthreads();
+    for (int j = 0; j < NCH; ++j) {
+        const int buf = j & 1;
+        const bool more = j + 1 < NCH;
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                ra[i] = A[(int64_t)(j + 1) * CH + i * 256 + tid];
+        }
+        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+        if (more) {
+            const int qn = (j + 1) % RB;
+            if (qn == 0)
+                bp = child((j + 1) / RB);
+            b01 = bp ? bp[2 * qn] : double2{0.0, 0.0};
+            b23 = bp ? bp[2 * qn + 1] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                                                             0);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                sa[buf ^ 1][i * 256 + tid] = ra[i];
+        }
+        __syncthreads();
+    }
+    if (!cvalid)
+        return;
+    // output fragment: column lane % 16, rows lane / 16 + 4 i of each block
+    double *dst = me + ((lp.me_off + box) * g.B + bm) * PS;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            dst[16 * r + kr + 4 * i] = acc[r][i];
+}
+
+// Small levels (too few columns to fill the chip with 64-column tiles):
+// k_m2m_split.  A workgroup owns 16 columns and one 16-row block; its eight
+// waves take one child each, so every wave runs PS/4 MFMAs behind a single
+// round of loads, and the eight partial fragments are added through LDS in
+// child order.
+template <int RB>
+__global__ void __launch_bounds__(512) k_m2m_split(DevGeom g, int l, const double *A, double *me)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     __shared__ double red[8][256];
     constexpr int PS = 16 * RB;
-    constexpr int U = RB < 8 ? RB : 8;  // chunks of four k steps loaded together
+    constexpr int K4 = PS / 4;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int c = threadIdx.x >> 6;  // the wave's child
     const DevLev &lp = g.lev[l];
     const DevLev &lc = g.lev[l + 1];
     const int64_t cg = blockIdx.x / RB;
@@ -103,30 +208,28 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
     const int py = lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1]);
     const int pz = lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]));
     const int kr = lane >> 4;
+    const int64_t ci =
+        cvalid ? dense_index(lc, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1), 2 * pz + ((c >> 2) & 1)) : -1;
     vec4 acc = vec4{0, 0, 0, 0};
-    // wave w takes child w
-    {
-        const int c = wave;
-        const int64_t ci = cvalid ? dense_index(lc, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1),
-                                                2 * pz + ((c >> 2) & 1))
-                                  : -1;
-        const bool have = ci >= 0;
-        const double2 *bp = (const double2 *)(me + (have ? ((lc.me_off + ci) * g.B + bm) * PS : 0) + kr * (PS / 4));
-        const double *ap = A + ((int64_t)c * RB * RB + rb) * 256;  // [c][q][rb] sets of 4 per lane
+    if (__ballot(ci >= 0) != 0ull) {
+        const double2 *bp = (const double2 *)(me + (ci >= 0 ? ((lc.me_off + ci) * g.B + bm) * PS : 0) + kr * K4);
+        const double *ap = A + (int64_t)c * PS * PS + rb * 64 + lane;  // k step ks at ap[ks * RB * 64]
+        constexpr int U = RB < 8 ? RB : 8;  // chunks of four k steps loaded together
         for (int q0 = 0; q0 < RB; q0 += U) {
             double av[U][4];
             double2 bb[U][2];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = min(q0 + u, RB - 1);
-                load_frags<double, 4>(ap + (int64_t)q * RB * 256, lane, av[u]);
-                bb[u][0] = bp[2 * q];
-                bb[u][1] = bp[2 * q + 1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    av[u][k] = ap[(int64_t)(4 * q + k) * RB * 64];
+                bb[u][0] = ci >= 0 ? bp[2 * q] : double2{0.0, 0.0};
+                bb[u][1] = ci >= 0 ? bp[2 * q + 1] : double2{0.0, 0.0};
             }
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const bool in = have && q0 + u < RB;
+                const bool in = q0 + u < RB;
                 const double bv[4] = {in ? bb[u][0].x : 0.0, in ? bb[u][0].y : 0.0, in ? bb[u][1].x : 0.0,
                                       in ? bb[u][1].y : 0.0};
 #pragma unroll
@@ -135,12 +238,12 @@ k_m2m_mfma(DevGeom g, int l, const double *A, double *me)
             }
         }
     }
-    // the eight waves' fragments share one lane layout: add them in wave order
+    // the eight waves' fragments share one lane layout: add them in child order
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        red[wave][lane * 4 + r] = acc[r];
+        red[c][lane * 4 + r] = acc[r];
     __syncthreads();
-    if (wave == 0 && cvalid) {
+    if (c == 0 && cvalid) {
         double *dst = me + ((lp.me_off + box) * g.B + bm) * PS;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -237,7 +340,10 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
 // The source boxes that one wave's 16 columns read at one interaction offset
 // are boxes of a single class with consecutive x, so each B fragment load
 // of the M2L covers a few contiguous runs instead of 64 scattered lines.
-// One thread per (box, model, chunk q, sub-row kr).
+// Boxes farther than 3 boxes from every target box of their level (for
+// surface stations, the deep part of the mesh) are skipped: the M2L reads
+// only sources within its interaction offsets.  One thread per (box, model,
+// chunk q, sub-row kr).
 template <typename T>
 __global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, int64_t n_me, T *out)
 {
@@ -256,6 +362,9 @@ __global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, 
     const int64_t j = box - lv.me_off;
     const int ax = lv.s0[0] + (int)(j % lv.ns[0]), ay = lv.s0[1] + (int)((j / lv.ns[0]) % lv.ns[1]),
               az = lv.s0[2] + (int)(j / ((int64_t)lv.ns[0] * lv.ns[1]));
+    if (ax < lv.need_lo[0] || ax > lv.need_hi[0] || ay < lv.need_lo[1] || ay > lv.need_hi[1] ||
+        az < lv.need_lo[2] || az > lv.need_hi[2])
+        return;  // no target box within reach: the M2L never reads this expansion
     int first[3], cnt[3];
     const int64_t pos = class_split(lv, (ax & 1) | ((ay & 1) << 1) | ((az & 1) << 2), first, cnt) +
                         ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
@@ -357,6 +466,22 @@ k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_star
     for (int a = 0; a < 3; ++a)
         corner[a] = (lc[a] - g.shift[a]) * g.b;  // cell coords of the leaf corner
     const int b = g.b, b3 = b * b * b;
+    // no neighbour leaf inside the source block (e.g. stations far above the
+    // mesh): the near field of these targets is zero
+    bool any_nb = false;
+    for (int nb = 0; nb < 27; ++nb) {
+        bool inb = true;
+        for (int a = 0; a < 3; ++a) {
+            const int sx = lc[a] + (nb / (a == 0 ? 1 : a == 1 ? 3 : 9)) % 3 - 1 - lv.s0[a];
+            inb = inb && sx >= 0 && sx < lv.ns[a];
+        }
+        any_nb = any_nb || inb;
+    }
+    if (!any_nb) {
+        for (int64_t e = threadIdx.x; e < nt * g.B * 4; e += blockDim.x)
+            near[ts * g.B * 4 + e] = 0.0;
+        return;
+    }
     int TC = 1;
     while (TC < nt && TC < 256)
         TC <<= 1;
@@ -743,61 +868,59 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *cta
 // --------------------------------------------------------------------------
 // L2P + combine: far field at each target from its leaf LE (phi and
 // g = -grad phi), plus the near field, times G and the lattice-to-physical
-// scale, scattered back to descriptor order.  One thread per target.
+// scale, scattered back to descriptor order.  One thread per (target, model),
+// targets fastest.
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_l2p_combine(DevGeom g, const double *tpos, const int32_t *tleaf, const uint32_t *tkey,
               const uint32_t *perm, const double *le, const double *near, int64_t first_lattice,
               double *out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.M)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.M * g.B)
         return;
-    if ((int64_t)perm[i] >= first_lattice)
+    const int bm = (int)(t / g.M);
+    const int64_t i = t - (int64_t)bm * g.M;
+    const int64_t dst_t = perm[i];
+    if (dst_t >= first_lattice)
         return;  // a voxel centre written by the fused lattice kernel
     const DevLev &lv = g.lev[g.L];
     const int64_t leaf = tleaf[i];
-    double u[3] = {0, 0, 0};
+    double far[4] = {0, 0, 0, 0};
     if (g.L >= 2) {
         const uint32_t key = tkey[lv.tbox_off + leaf];
         const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
         const double inv_w = 1.0 / (double)g.b;
+        double u[3];
         for (int a = 0; a < 3; ++a) {
             const double centre = ((double)(lc[a] - g.shift[a]) + 0.5) * g.b;
             u[a] = (tpos[3 * i + a] - centre) * inv_w;
         }
+        const double *L = le + ((lv.tgt_off + leaf) * g.B + bm) * g.PS;
+        l2p_eval(g.P, L, u[0], u[1], u[2], far);
+        far[0] *= inv_w;
+        const double s = inv_w * inv_w;
+        far[1] = -far[1] * s;  // g = -grad phi
+        far[2] = -far[2] * s;
+        far[3] = -far[3] * s;
     }
-    const int64_t dst_t = perm[i];
-    for (int bm = 0; bm < g.B; ++bm) {
-        double far[4] = {0, 0, 0, 0};
-        if (g.L >= 2) {
-            const double *L = le + ((lv.tgt_off + leaf) * g.B + bm) * g.PS;
-            l2p_eval(g.P, L, u[0], u[1], u[2], far);
-            const double inv_w = 1.0 / (double)g.b;
-            far[0] *= inv_w;
-            const double s = inv_w * inv_w;
-            far[1] = -far[1] * s;  // g = -grad phi
-            far[2] = -far[2] * s;
-            far[3] = -far[3] * s;
-        }
-        const double *nr = near + (i * g.B + bm) * 4;
-        double v[4];
-        for (int c = 0; c < 4; ++c)
-            v[c] = nr[c] + far[c];
-        double *o = out + ((int64_t)bm * g.M + dst_t) * g.C;
-        const double sg = g.G * g.h, sp = g.G * g.h * g.h;
-        if (g.C == 1) {
-            o[0] = sg * v[3];
-        } else if (g.C == 3) {
-            o[0] = sg * v[1];
-            o[1] = sg * v[2];
-            o[2] = sg * v[3];
-        } else {
-            o[0] = sp * v[0];
-            o[1] = sg * v[1];
-            o[2] = sg * v[2];
-            o[3] = sg * v[3];
-        }
+    const double *nr = near + (i * g.B + bm) * 4;
+    double v[4];
+    for (int c = 0; c < 4; ++c)
+        v[c] = nr[c] + far[c];
+    double *o = out + ((int64_t)bm * g.M + dst_t) * g.C;
+    const double sg = g.G * g.h, sp = g.G * g.h * g.h;
+    if (g.C == 1) {
+        o[0] = sg * v[3];
+    } else if (g.C == 3) {
+        o[0] = sg * v[1];
+        o[1] = sg * v[2];
+        o[2] = sg * v[3];
+    } else {
+        o[0] = sp * v[0];
+        o[1] = sg * v[1];
+        o[2] = sg * v[2];
+        o[3] = sg * v[3];
     }
 }
 
@@ -822,6 +945,10 @@ DevGeom make_geom(const Plan *p)
         d.tmap_off = s.tmap_off;
         d.tchild_off = s.tchild_off;
         d.n_tgt = s.n_tgt;
+        for (int a = 0; a < 3; ++a) {
+            d.need_lo[a] = s.need_lo[a];
+            d.need_hi[a] = s.need_hi[a];
+        }
     }
     g.L = p->L;
     g.b = p->b;
@@ -869,10 +996,18 @@ void stage_end(Plan *p, hipStream_t s)
 static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
 {
     const int RB = p->PS / 16;
-    const dim3 grid((unsigned)((p->lev[l].n_src * p->B + 15) / 16 * RB)), blk(512);
-#define M2M_CASE(R)                                                                             \
-    case R:                                                                                     \
-        hipLaunchKernelGGL((k_m2m_mfma<R>), grid, blk, 0, s, g, l, (const double *)p->d_m2m_sw, p->d_me); \
+    const int64_t ncol = p->lev[l].n_src * p->B;
+    // 64-column tiles once they give every CU a workgroup or more
+    const bool lds = (ncol + 63) / 64 >= GRAV_M2M_LDS_MIN_WG;
+    const dim3 grid_lds((unsigned)((ncol + 63) / 64)), grid_split((unsigned)((ncol + 15) / 16 * RB));
+#define M2M_CASE(R)                                                                                          \
+    case R:                                                                                                  \
+        if (lds)                                                                                             \
+            hipLaunchKernelGGL((k_m2m_lds<R>), grid_lds, dim3(256), 0, s, g, l, (const double *)p->d_m2m_sw, \
+                               p->d_me);                                                                     \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_m2m_split<R>), grid_split, dim3(512), 0, s, g, l,                          \
+                               (const double *)p->d_m2m_sw, p->d_me);                                        \
         break;
     switch (RB) {
         M2M_CASE(1)
@@ -891,6 +1026,37 @@ static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
         return GRAV_EUNSUPPORTED;
     }
 #undef M2M_CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+static grav_status launch_p2m(Plan *p, const DevGeom &g, const double *rho, hipStream_t s)
+{
+    const int RB = p->PS / 16;
+    const int b3 = p->b * p->b * p->b;
+    const int KV = (b3 + 3) / 4;
+    const dim3 grid((unsigned)((p->lev[p->L].n_src * p->B + 15) / 16)), blk(64);
+#define P2M_CASE(R)                                                                             \
+    case R:                                                                                     \
+        hipLaunchKernelGGL((k_p2m_mfma<R>), grid, blk, 0, s, g, rho, (const double *)p->d_pm_sw, KV, p->d_me); \
+        break;
+    switch (RB) {
+        P2M_CASE(1)
+        P2M_CASE(2)
+        P2M_CASE(3)
+        P2M_CASE(4)
+        P2M_CASE(6)
+        P2M_CASE(7)
+        P2M_CASE(8)
+        P2M_CASE(9)
+        P2M_CASE(11)
+        P2M_CASE(13)
+        P2M_CASE(15)
+        P2M_CASE(16)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef P2M_CASE
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }
@@ -976,12 +1142,7 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         return GRAV_OK;
     if (L >= 2) {
         stage_begin(p, "p2m", s);
-        const int b3 = p->b * p->b * p->b;
-        constexpr int LB = 8;  // columns per workgroup
-        const int64_t ncol = p->lev[L].n_src * p->B;
-        hipLaunchKernelGGL((k_p2m<LB>), dim3((unsigned)((ncol + LB - 1) / LB)), dim3((p->PS + 63) / 64 * 64),
-                           sizeof(double) * LB * b3, s, g, rho, (const double *)p->d_pm, p->d_me);
-        GRAV_HIP(hipGetLastError());
+        GRAV_CHECK(launch_p2m(p, g, rho, s));
         stage_end(p, s);
         stage_begin(p, "m2m", s);
         for (int l = L - 1; l >= 2; --l)
@@ -1044,7 +1205,7 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         GRAV_HIP(hipGetLastError());
         stage_end(p, s);
         stage_begin(p, "l2p", s);
-        hipLaunchKernelGGL(k_l2p_combine, dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s, g,
+        hipLaunchKernelGGL(k_l2p_combine, dim3((unsigned)((p->M * p->B + 255) / 256)), dim3(256), 0, s, g,
                            (const double *)p->d_tpos, (const int32_t *)p->d_tleaf,
                            (const uint32_t *)p->d_tkey, (const uint32_t *)p->d_perm,
                            (const double *)p->d_le, (const double *)p->d_near,

@@ -15,6 +15,8 @@ struct DevLev {
     int64_t tmap_off;
     int64_t tchild_off;
     int64_t n_tgt;       // target boxes of the level
+    int need_lo[3];      // box range (inclusive) whose expansions the M2L reads
+    int need_hi[3];
 };
 
 struct DevGeom {
@@ -56,7 +58,7 @@ template <typename T>
 __global__ void k_sum_parts(const T *part, int S, int64_t n, double *out);
 template <typename T>
 grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K);
-grav_status m2l_resident_workers(const Plan *p, int *workers);
+grav_status m2l_resident_workers(const Plan *p, int nset, int *workers);
 grav_status begin_call(Plan *p, hipStream_t s);
 grav_status end_call(Plan *p, hipStream_t s);
 

@@ -53,6 +53,8 @@ struct LevelInfo {
     int64_t tmap_off = 0;             // offset of this level's target map (source block + halo 3)
     int64_t tchild_off = 0;           // offset of this level's first-child table
     int64_t src_class[8] = {0};       // source boxes of each parity class
+    int need_lo[3] = {0, 0, 0};       // box range whose expansions the M2L reads (the
+    int need_hi[3] = {-1, -1, -1};    // target boxes' range widened by 3, inclusive)
 };
 
 // Tiled stages: the forward M2L (its tiles also give the L2L its columns).
@@ -106,6 +108,7 @@ struct Plan {
     // end item, 0} per workgroup (wgseg: CSR over workgroups), per unit its
     // segment slots (CSR), and LE column -> 64 * unit + column in unit
     int32_t m2l_wgs = 0, m2l_ncw = 64;  // workgroups (one wave each); columns per unit
+    int32_t m2l_nset = 2;               // operand register sets of the FP32 M2L kernel (1 or 2)
     int64_t m2l_nseg = 0, m2l_items = 0, m2l_nunit = 0;
     int32_t *d_m2l_items = nullptr, *d_m2l_segs = nullptr, *d_m2l_wgseg = nullptr;
     int32_t *d_m2l_tseg_start = nullptr, *d_m2l_tsegs = nullptr, *d_m2l_colmap = nullptr;
@@ -114,7 +117,7 @@ struct Plan {
     int lat_RB = 0, lat_Q = 0;                     // row blocks (4 b^3 / 16); chunks of four k steps
     double *d_tl2p = nullptr;                      // [PS/16][RB][64][4] far field (L2P) at the cell centres, FP64
     int64_t *d_lat_tab = nullptr;                  // [27 Q][2] per near chunk: density and operator offsets
-    double *d_m2m_sw = nullptr;                    // [8][KS][RB][64] M2M as MFMA A fragments (FP64)
+    double *d_m2m_sw = nullptr;                    // [8][PS/4][RB][64] M2M as MFMA A fragments (FP64)
     double *d_l2l_sw = nullptr;                    // [8][KS][RB][64] L2L likewise
     double *d_tn64 = nullptr;                      // [27][KS][RB][64] swizzled, FP64 plans
     float *d_tn32 = nullptr;                       // same, mixed plans
@@ -134,6 +137,7 @@ struct Plan {
     struct DevGeom *d_geom = nullptr;
 
     double *d_pm = nullptr;        // [b^3][PS] lattice P2M
+    double *d_pm_sw = nullptr;     // [b^3/4][RB][64] the same as MFMA A fragments (FP64)
     double *d_m2m = nullptr;       // [8][PS][PS] M2M per child octant, row-major [out][in] (adjoint)
     double *d_l2l = nullptr;       // [8][PS][PS] L2L per child octant, row-major [out][in] (adjoint)
     double *d_k64 = nullptr;       // forward M2L operators as MFMA A fragments (FP64 plans: all 316)

@@ -5,16 +5,15 @@
 
 #include "resolve.hpp"
 
-// Largest per-lane A chunk (bytes) for which the M2L keeps two register
-// sets (loads of the next chunk in flight during this chunk's MFMAs), per
-// element type.  The FP32 kernel keeps one set: its registers then leave
-// room for three waves per SIMD at p = 10 (five at p = 8), which hide the
-// load latency better than a second set does (measured on the 256^3 volume
-// workload: M2L 10.5 against 10.9 ms at p = 10, 4.3 against 4.6 ms at p = 8).
-// The FP64 kernel keeps two sets up to p = 16.
-#ifndef GRAV_M2L_DB_BYTES32
-#define GRAV_M2L_DB_BYTES32 0
-#endif
+// Operand register sets of the M2L (NS template parameter): with two sets
+// the loads of the next chunk are in flight during this chunk's MFMAs; with
+// one, the registers leave room for more waves per SIMD (three at p = 10 in
+// FP32, five at p = 8), which hide the load latency better on large plans
+// (256^3 volume workload: M2L 10.5 against 10.9 ms at p = 10, 4.3 against
+// 4.6 ms at p = 8) but not on small ones, where each wave has only a few
+// work items (64^3: 0.20 against 0.18 ms).  The plan picks the FP32 variant
+// by its work per resident wave (see build_tiles); the FP64 kernel keeps two
+// sets while a chunk's A values fit this many bytes per lane.
 #ifndef GRAV_M2L_DB_BYTES64
 #define GRAV_M2L_DB_BYTES64 512
 #endif
@@ -88,7 +87,7 @@ __device__ __forceinline__ double flip_sign(double v, uint32_t s)
 #define GRAV_M2L_OCC
 #endif
 
-template <int RB, int KSV, int NC, typename T>
+template <int RB, int KSV, int NC, typename T, int NS>
 __global__ void __launch_bounds__(64) GRAV_M2L_OCC
 k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
       const int32_t *class_off, const T *K, const T *me, const int32_t *segs, const int32_t *wgseg,
@@ -194,7 +193,7 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
         // the next item's first chunk) are in flight while the instructions
         // of chunk q run
         constexpr int NSET =
-            4 * RB * (int)sizeof(T) <= (sizeof(T) == 4 ? GRAV_M2L_DB_BYTES32 : GRAV_M2L_DB_BYTES64) ? 2 : 1;
+            NS == 2 && 4 * RB * (int)sizeof(T) <= (sizeof(T) == 4 ? 512 : GRAV_M2L_DB_BYTES64) ? 2 : 1;
         T av[NSET][4 * RB];
         T bb[NSET][NC][4];
         auto load = [&](const Item &st, int q, int set) {
@@ -327,13 +326,18 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     dim3 grid(p->m2l_wgs), blk(64);
     T *part = reinterpret_cast<T *>(p->d_part);  // segment slots (sized for FP64)
     const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see k_me_gather)
+#define M2L_LAUNCH(P, NS)                                                                       \
+    hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T, NS>), grid, blk, 0, s, g,  \
+                       (const GemmTile *)(p->d_tiles + r.off), (const uint32_t *)p->d_tkey,     \
+                       (const int32_t *)p->d_torder, (const int32_t *)p->d_class_off, K, me_in, \
+                       (const int32_t *)p->d_m2l_segs, (const int32_t *)p->d_m2l_wgseg,         \
+                       (const int32_t *)p->d_m2l_items, part)
 #define M2L_CASE(P)                                                                             \
     case P:                                                                                     \
-        hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T>), grid, blk, 0, s, g,  \
-                           (const GemmTile *)(p->d_tiles + r.off), (const uint32_t *)p->d_tkey, \
-                           (const int32_t *)p->d_torder, (const int32_t *)p->d_class_off, K, me_in, \
-                           (const int32_t *)p->d_m2l_segs, (const int32_t *)p->d_m2l_wgseg,     \
-                           (const int32_t *)p->d_m2l_items, part);                              \
+        if (sizeof(T) == 4 && p->m2l_nset == 1)                                                 \
+            M2L_LAUNCH(P, 1);                                                                   \
+        else                                                                                    \
+            M2L_LAUNCH(P, 2);                                                                   \
         break;
     switch (p->P) {
         M2L_CASE(1)
@@ -356,6 +360,7 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
         return GRAV_EUNSUPPORTED;
     }
 #undef M2L_CASE
+#undef M2L_LAUNCH
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }
@@ -363,17 +368,19 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
 template grav_status launch_m2l<double>(Plan *, const DevGeom &, hipStream_t, const double *);
 template grav_status launch_m2l<float>(Plan *, const DevGeom &, hipStream_t, const float *);
 
-// One-wave workgroups of the plan's M2L kernel that the device holds at once
-// (blocks per CU from the occupancy calculator, times the CUs): the size of
-// the stream-K schedule, so that every worker is resident from the start.
-grav_status m2l_resident_workers(const Plan *p, int *workers)
+// One-wave workgroups of the plan's M2L kernel (with nset operand register
+// sets in FP32) that the device holds at once (blocks per CU from the
+// occupancy calculator, times the CUs): the size of the stream-K schedule,
+// so that every worker is resident from the start.
+grav_status m2l_resident_workers(const Plan *p, int nset, int *workers)
 {
     const bool f64 = p->d.precision == GRAV_FP64;
     const void *fn = nullptr;
-#define M2L_FN(P)                                                                                          \
-    case P:                                                                                                \
-        fn = f64 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64, double>) \
-                 : reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32, float>);  \
+#define M2L_FN(P)                                                                                           \
+    case P:                                                                                                 \
+        fn = f64 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64, double, 2>) \
+             : nset == 1 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32, float, 1>) \
+                         : reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32, float, 2>); \
         break;
     switch (p->P) {
         M2L_FN(1)

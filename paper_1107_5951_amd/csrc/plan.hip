@@ -7,6 +7,7 @@
 // Cell-centre evaluation points are placed at exact half-integers, so a
 // point that coincides with a 1-point source has an exactly zero offset.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -282,7 +283,7 @@ void free_plan(Plan *p)
     (void)hipSetDevice(p->device);
     void *bufs[] = {p->d_points, p->d_perm, p->d_tpos, p->d_tleaf, p->d_leaf_start, p->d_tkey,
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
-                    p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_m2m,
+                    p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_pm_sw, p->d_m2m,
                     p->d_l2l, p->d_k64, p->d_kplain, p->d_k32, p->d_me,
                     p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg, p->d_lat_tab, p->d_m2l_items, p->d_m2l_segs,
                     p->d_m2l_wgseg, p->d_m2l_tseg_start, p->d_m2l_tsegs, p->d_m2l_colmap,
@@ -467,6 +468,21 @@ grav_status build_operators(Plan *p)
     std::vector<double> pm((size_t)b3 * PS);
     p2m_lattice(P, p->b, p->q, 1.0, PS, pm.data());
     GRAV_CHECK(upload(p, &p->d_pm, pm));
+    {
+        // the same map as FP64 MFMA A fragments: rows = coefficients, the
+        // contraction runs over the leaf's cells, k step kv and sub-row kr
+        // taking cell 4 kv + kr; [kv][rb][lane] = pm[4 kv + lane/16][16 rb + lane%16]
+        const int KV = (b3 + 3) / 4;
+        std::vector<double> psw((size_t)KV * RB * 64, 0.0);
+        for (int kv = 0; kv < KV; ++kv)
+            for (int rb = 0; rb < RB; ++rb)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int v = 4 * kv + lane / 16;
+                    if (v < b3)
+                        psw[((size_t)kv * RB + rb) * 64 + lane] = pm[(size_t)v * PS + 16 * rb + lane % 16];
+                }
+        GRAV_CHECK(upload(p, &p->d_pm_sw, psw));
+    }
     if (p->L < 2)
         return GRAV_OK;
 
@@ -486,15 +502,22 @@ grav_status build_operators(Plan *p)
     GRAV_CHECK(upload(p, &p->d_l2l, l2l));
     {
         // the same matrices as MFMA A operands (rows = output coefficient),
-        // contraction order kr * PS/4 + ks, one set of four k steps per
-        // (q, row block): both kernels give a workgroup one row block
+        // contraction order kr * PS/4 + ks.  L2L: one set of four k steps per
+        // (q, row block) (a workgroup takes one row block).  M2M: one fragment
+        // per (k step, row block), [octant][ks][rb][lane] = m[16 rb + lane%16][
+        // (lane/16) PS/4 + ks] (a wave takes all row blocks).
         const size_t per8 = (size_t)PS * PS;
+        const int K4 = PS / 4;
         std::vector<double> msw(8 * per8), lsw(8 * per8);
         for (int c = 0; c < 8; ++c) {
             const double delta[3] = {((c & 1) - 0.5) * 0.5, (((c >> 1) & 1) - 0.5) * 0.5,
                                      (((c >> 2) & 1) - 0.5) * 0.5};
             m2m_matrix(P, delta, PS, m.data());
-            swizzle_rows(m.data(), PS, 2, msw.data() + per8 * c);
+            for (int ks = 0; ks < K4; ++ks)
+                for (int rb = 0; rb < RB; ++rb)
+                    for (int lane = 0; lane < 64; ++lane)
+                        msw[per8 * c + ((size_t)ks * RB + rb) * 64 + lane] =
+                            m[(size_t)(16 * rb + lane % 16) * PS + (lane / 16) * K4 + ks];
             l2l_matrix(P, delta, PS, m.data());
             swizzle_rows(m.data(), PS, 2, lsw.data() + per8 * c);
         }
@@ -619,6 +642,23 @@ grav_status build_tiles(Plan *p)
                 }
             }
             GRAV_HIP(hipStreamSynchronize(p->bs));
+            // per level, the box range whose expansions the M2L can read: the
+            // target boxes' bounding box widened by the largest offset (3)
+            for (int l = 2; l <= L; ++l) {
+                LevelInfo &lv = p->lev[l];
+                int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+                for (const uint32_t k : key[l]) {
+                    const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = std::min(lo[a], c[a]);
+                        hi[a] = std::max(hi[a], c[a]);
+                    }
+                }
+                for (int a = 0; a < 3; ++a) {
+                    lv.need_lo[a] = key[l].empty() ? 0 : lo[a] - 3;
+                    lv.need_hi[a] = key[l].empty() ? -1 : hi[a] + 3;
+                }
+            }
             // a unit is the columns of one wave: 16 NC columns of a tile
             const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
             const int ncw = 16 * nc, upt = 4 / nc;
@@ -659,8 +699,17 @@ grav_status build_tiles(Plan *p)
             // at least kMinItems items per workgroup: small plans get fewer
             // workgroups rather than one partial slot per item
             constexpr int64_t kMinItems = 8;
+            constexpr int64_t kItemsOneSet = 32;  // items per resident wave above which one set pays
+            // FP32: one operand register set (more resident waves) when every
+            // wave gets a long run of items, two sets on small plans
             int resident = 0;
-            GRAV_CHECK(m2l_resident_workers(p, &resident));
+            p->m2l_nset = 2;
+            if (p->d.precision != GRAV_FP64) {
+                GRAV_CHECK(m2l_resident_workers(p, 1, &resident));
+                if (T >= (int64_t)kItemsOneSet * resident)
+                    p->m2l_nset = 1;
+            }
+            GRAV_CHECK(m2l_resident_workers(p, p->m2l_nset, &resident));
             const int64_t P = std::max<int64_t>(
                 1, std::min<int64_t>(std::min<int64_t>(GRAV_M2L_WAVES, resident), T / kMinItems));
             std::vector<int32_t> seg, wgseg(P + 1, 0), tseg_n(nunit + 1, 0);
