@@ -140,8 +140,8 @@ def m2l_kernel_name(p, prec):
     from paper_1107_5951_amd import GRAV_FP64
     p2 = p * p
     if prec == GRAV_FP64:
-        return "k_m2l<%d,%d,1,double>" % (-(-p2 // 16), -(-p2 // 4))
-    return "k_m2l<%d,%d,2,float>" % (-(-p2 // 16), -(-p2 // 4))
+        return "k_m2l<%d,%d,1,double,*>" % (-(-p2 // 16), -(-p2 // 4))
+    return "k_m2l<%d,%d,2,float,*>" % (-(-p2 // 16), -(-p2 // 4))
 
 
 def roofline(plan, stages, p, prec, profile):
