@@ -168,94 +168,95 @@ k_t_l2l(DevGeom g, int l, const uint32_t *tkey, const int32_t *tchild, const dou
     }
 }
 
-// M2L^T: ME_l[S] = sum over the offsets d of the reverse list of S's parity
-// class, for which T = S - d is a target box, of K_d^T LE_l[T] (the forward
-// M2L adds K_d ME[T + d] into LE[T] for exactly these pairs).  K is stored
-// plain, [offset][row i (LE)][column j (ME)], p^2 x p^2.  One workgroup per
-// source box of any level >= 2: its threads first look up the box's 189
-// reverse offsets in the level's target-box map (an LDS list, invalid
-// entries -1, kept in list order), then each thread accumulates
-// coefficients j of a model group over the valid entries.
-template <int MT>
+// M2L^T runs on the forward's stream-K M2L kernel (transposed operators,
+// columns = source boxes of each level's column block, see
+// build_m2l_transposed).  Its B operand: the adjoint LE of each level's
+// gather region regathered in the kernel's layout (class-split boxes,
+// chunk-major planes (q, kr) of four coefficients 16 q + kr + 4 u), zero
+// where the region has no target box and for the padding coefficients.
+// The target box at a position comes from the level's target map (source
+// block plus a halo of 3, which holds the region).  One thread per (region
+// box, model, plane).
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_t_m2l(DevGeom g, int64_t n_tbox, const int32_t *tmap, int64_t n_tmap, const int32_t *roffs, const double *K,
-        const double *le, double *me)
+k_le_gather(DevGeom gt, DevGeom g, const int32_t *tmap, int64_t n_tmap, int64_t n_tbox, const double *le,
+            int64_t n_leg, T *out)
 {
-    __shared__ int32_t pt[kClassOffsets], pid[kClassOffsets];
-    __shared__ int32_t nvalid;
-    const int NG = (g.B + MT - 1) / MT;
-    const int64_t sbox = blockIdx.x;  // over all levels' source blocks
+    const int NP = g.PS / 4;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_leg * g.B * NP)
+        return;
+    const int plane = (int)(i % NP);
+    const int64_t col = i / NP;  // region box * B + model
+    const int bm = (int)(col % g.B);
+    const int64_t box = col / g.B;
     int l = 2;
-    while (l < g.L && sbox >= g.lev[l + 1].me_off)
+    while (l < g.L && box >= gt.lev[l + 1].me_off)
         ++l;
+    const DevLev &lt = gt.lev[l];
     const DevLev &lv = g.lev[l];
-    const int64_t r = sbox - lv.me_off;
-    const int x = lv.s0[0] + (int)(r % lv.ns[0]);
-    const int y = lv.s0[1] + (int)((r / lv.ns[0]) % lv.ns[1]);
-    const int z = lv.s0[2] + (int)(r / ((int64_t)lv.ns[0] * lv.ns[1]));
-    const int cls = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-    if (threadIdx.x == 0)
-        nvalid = 0;
-    __syncthreads();
-    for (int o = threadIdx.x; o < kClassOffsets; o += blockDim.x) {
-        const int32_t *e = roffs + (cls * kClassOffsets + o) * 4;
-        int32_t tb = -1;
-        const int id = e[3];
-        const int mx = x - e[0] - lv.s0[0] + 3, my = y - e[1] - lv.s0[1] + 3, mz = z - e[2] - lv.s0[2] + 3;
-        if (id >= 0 && id < kNumOffsets && mx >= 0 && my >= 0 && mz >= 0 && mx < lv.ns[0] + 6 &&
-            my < lv.ns[1] + 6 && mz < lv.ns[2] + 6) {
-            const int64_t mi = lv.tmap_off + ((int64_t)mz * (lv.ns[1] + 6) + my) * (lv.ns[0] + 6) + mx;
-            if (mi < n_tmap) {
-                const int64_t v = tmap[mi];
-                if (v >= 0 && v < lv.n_tgt && lv.tgt_off + v < n_tbox)
-                    tb = (int32_t)v;
-            }
+    const int64_t r = box - lt.me_off;
+    const int x = lt.s0[0] + (int)(r % lt.ns[0]), y = lt.s0[1] + (int)((r / lt.ns[0]) % lt.ns[1]),
+              z = lt.s0[2] + (int)(r / ((int64_t)lt.ns[0] * lt.ns[1]));
+    int first[3], cnt[3];
+    const int64_t pos = class_split(lt, (x & 1) | ((y & 1) << 1) | ((z & 1) << 2), first, cnt) +
+                        ((int64_t)((z - first[2]) >> 1) * cnt[1] + ((y - first[1]) >> 1)) * cnt[0] +
+                        ((x - first[0]) >> 1);
+    int64_t tb = -1;
+    const int mx = x - lv.s0[0] + 3, my = y - lv.s0[1] + 3, mz = z - lv.s0[2] + 3;
+    if (mx >= 0 && my >= 0 && mz >= 0 && mx < lv.ns[0] + 6 && my < lv.ns[1] + 6 && mz < lv.ns[2] + 6) {
+        const int64_t mi = lv.tmap_off + ((int64_t)mz * (lv.ns[1] + 6) + my) * (lv.ns[0] + 6) + mx;
+        if (mi < n_tmap) {
+            const int64_t v = tmap[mi];
+            if (v >= 0 && v < lv.n_tgt && lv.tgt_off + v < n_tbox)
+                tb = v;
         }
-        pt[o] = tb;
-        pid[o] = id;
-        if (tb >= 0)
-            atomicAdd(&nvalid, 1);  // only the count: the entries keep list order
     }
-    __syncthreads();
-    const bool any = nvalid > 0;
-    for (int64_t oi = threadIdx.x; oi < (int64_t)NG * g.PS; oi += blockDim.x) {
-        const int j = (int)(oi % g.PS);
-        const int grp = (int)(oi / g.PS);
-        double acc[MT];
+    const int q = plane / 4, kr = plane % 4;
+    const int64_t nB = (int64_t)lt.ns[0] * lt.ns[1] * lt.ns[2] * g.B;
+    T *dst = out + lt.me_off * g.B * g.PS + ((int64_t)plane * nB + pos * g.B + bm) * 4;
+    const double *src = le + (tb >= 0 ? ((lv.tgt_off + tb) * g.B + bm) * g.PS : 0);
 #pragma unroll
-        for (int u = 0; u < MT; ++u)
-            acc[u] = 0.0;
-        if (any && j < g.P2) {
-            for (int o = 0; o < kClassOffsets; ++o) {
-                const int32_t tb = pt[o];
-                if (tb < 0)
-                    continue;
-                const double *kc = K + (int64_t)pid[o] * g.P2 * g.P2 + j;
-                const double *yv = le + ((lv.tgt_off + tb) * g.B + grp * MT) * g.PS;
-                for (int i = 0; i < g.P2; ++i) {
-                    const double kv = kc[(int64_t)i * g.P2];
-#pragma unroll
-                    for (int u = 0; u < MT; ++u)
-                        if (grp * MT + u < g.B)
-                            acc[u] += kv * yv[(int64_t)u * g.PS + i];
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < MT; ++u) {
-            const int bm = grp * MT + u;
-            if (bm < g.B)
-                me[(sbox * g.B + bm) * g.PS + j] = acc[u];
-        }
+    for (int u = 0; u < 4; ++u) {
+        const int c = 16 * q + kr + 4 * u;
+        dst[u] = (T)(tb >= 0 && c < g.P2 ? src[c] : 0.0);
     }
 }
+
+// ME of the transposed M2L's columns from its segment slots: the sum, over
+// the segments of the column's unit in their order, of the slot entry, in
+// FP64 (as the forward's k_m2l_sum); the column's ME is overwritten.  A
+// unit without segments (no target box at any offset) gives zero.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_m2lt_sum(const T *part, const int32_t *colmap, const int64_t *colbox, const int32_t *tseg_start,
+           const int32_t *tsegs, int64_t ncols, int PS, int ncw, double *me)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncols * PS)
+        return;
+    const int64_t c = i / PS;
+    const int k = (int)(i - c * PS);
+    const int32_t m = colmap[c];
+    const int t = m >> 6, cl = m & 63;
+    double acc = 0.0;
+    for (int j = tseg_start[t]; j < tseg_start[t + 1]; ++j)
+        acc += (double)part[((int64_t)tsegs[j] * ncw + cl) * PS + k];
+    me[colbox[c] * PS + k] = acc;
+}
+
+// The column blocks of the transposed M2L: the boxes of level l whose ME it
+// writes (inclusive range); M2M^T adds to these and sets the others.
+struct ColBlock {
+    int lo[3], hi[3];
+};
 
 // M2M^T (downward over the source blocks): ME_l[child] += M2M_c^T
 // ME_l-1[parent], M2M row-major [octant][out i][in j], so the thread of
 // coefficient j reads column j.  One thread per (source box of level l,
 // model group, coefficient j).
 template <int MT>
-__global__ void __launch_bounds__(256) k_t_m2m(DevGeom g, int l, const double *m2m, double *me)
+__global__ void __launch_bounds__(256) k_t_m2m(DevGeom g, int l, ColBlock cb, const double *m2m, double *me)
 {
     const int NG = (g.B + MT - 1) / MT;
     const DevLev &lv = g.lev[l];
@@ -274,27 +275,30 @@ __global__ void __launch_bounds__(256) k_t_m2m(DevGeom g, int l, const double *m
     const int y = lv.s0[1] + (int)((box / lv.ns[0]) % lv.ns[1]);
     const int z = lv.s0[2] + (int)(box / ((int64_t)lv.ns[0] * lv.ns[1]));
     const int64_t par = dense_index(lp, x >> 1, y >> 1, z >> 1);
-    if (par < 0)
-        return;
     const int oct = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
     const double *col = m2m + (int64_t)oct * g.PS * g.PS + j;
-    const double *mp = me + ((lp.me_off + par) * g.B + grp * MT) * g.PS;
+    const double *mp = me + ((lp.me_off + (par >= 0 ? par : 0)) * g.B + grp * MT) * g.PS;
     double acc[MT];
 #pragma unroll
     for (int u = 0; u < MT; ++u)
         acc[u] = 0.0;
-    for (int i = 0; i < g.P2; ++i) {
+    for (int i = 0; i < (par >= 0 ? g.P2 : 0); ++i) {
         const double m = col[(int64_t)i * g.PS];
 #pragma unroll
         for (int u = 0; u < MT; ++u)
             if (grp * MT + u < g.B)
                 acc[u] += m * mp[(int64_t)u * g.PS + i];
     }
+    // inside the column block the transposed M2L has written the ME
+    const bool add = x >= cb.lo[0] && x <= cb.hi[0] && y >= cb.lo[1] && y <= cb.hi[1] && z >= cb.lo[2] &&
+                     z <= cb.hi[2];
 #pragma unroll
     for (int u = 0; u < MT; ++u) {
         const int bm = grp * MT + u;
-        if (bm < g.B)
-            me[((lv.me_off + box) * g.B + bm) * g.PS + j] += acc[u];
+        if (bm < g.B) {
+            double *o = me + ((lv.me_off + box) * g.B + bm) * g.PS + j;
+            *o = add ? *o + acc[u] : acc[u];
+        }
     }
 }
 
@@ -431,6 +435,62 @@ __global__ void __launch_bounds__(256) k_t_zero(double *x, int64_t n)
 
 }  // namespace
 
+// M2L^T: regather the adjoint LE, run the forward kernel on the transposed
+// problem, add each column's segment slots into its ME.
+template <typename T>
+static grav_status m2l_transposed_t(Plan *p, const DevGeom &g, hipStream_t s, const T *Kt)
+{
+    DevGeom gt = g;  // the kernel's view: columns = source boxes, B = gathered adjoint LE
+    for (int l = 2; l <= p->L; ++l) {
+        const LevelInfo &lv = p->lev[l];
+        DevLev &d = gt.lev[l];
+        for (int a = 0; a < 3; ++a) {
+            d.s0[a] = lv.gs0[a];
+            d.ns[a] = lv.gns[a];
+        }
+        d.me_off = lv.g_off;
+        d.tbox_off = lv.me_off;
+        for (int c = 0; c < 9; ++c)
+            d.class_start[c] = lv.col_class_start[c];
+    }
+    T *leg = reinterpret_cast<T *>(p->d_leg);
+    const int64_t n = p->n_leg * p->B * (p->PS / 4);
+    if (n > 0) {
+        hipLaunchKernelGGL((k_le_gather<T>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, gt, g,
+                           (const int32_t *)p->d_tmap, p->n_tmap, p->n_tbox, (const double *)p->d_le, p->n_leg, leg);
+        GRAV_HIP(hipGetLastError());
+    }
+    M2LRun<T> r;
+    r.tiles = (const GemmTile *)p->d_m2lt_tiles;
+    r.keys = (const uint32_t *)p->d_skey;
+    r.order = (const int32_t *)p->d_sorder;
+    r.class_off = (const int32_t *)p->d_tclass_off;
+    r.K = Kt;
+    r.b_in = leg;
+    r.segs = (const int32_t *)p->d_m2lt_segs;
+    r.wgseg = (const int32_t *)p->d_m2lt_wgseg;
+    r.items = (const int32_t *)p->d_m2lt_items;
+    r.part = reinterpret_cast<T *>(p->d_partt);
+    r.wgs = p->m2lt_wgs;
+    r.nset = p->m2lt_nset;
+    GRAV_CHECK(launch_m2l<T>(p, gt, s, r));
+    const int64_t ns = p->m2lt_ncols * p->PS;
+    if (ns > 0) {
+        hipLaunchKernelGGL((k_m2lt_sum<T>), dim3((unsigned)ceil_div(ns, 256)), dim3(256), 0, s,
+                           (const T *)p->d_partt, (const int32_t *)p->d_m2lt_colmap, (const int64_t *)p->d_m2lt_colbox,
+                           (const int32_t *)p->d_m2lt_tseg_start, (const int32_t *)p->d_m2lt_tsegs, p->m2lt_ncols,
+                           p->PS, p->m2l_ncw, p->d_me);
+        GRAV_HIP(hipGetLastError());
+    }
+    return GRAV_OK;
+}
+
+static grav_status enqueue_m2l_transposed(Plan *p, const DevGeom &g, hipStream_t s)
+{
+    return p->d.precision == GRAV_FP64 ? m2l_transposed_t<double>(p, g, s, p->d_kt64)
+                                       : m2l_transposed_t<float>(p, g, s, p->d_kt32);
+}
+
 template <int MT>
 static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho, hipStream_t s)
 {
@@ -465,14 +525,17 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
         }
         stage_end(p, s);
         stage_begin(p, "m2lT", s);
-        hipLaunchKernelGGL(k_t_m2l<MT>, dim3((unsigned)p->n_me), blk, 0, s, g, p->n_tbox,
-                           (const int32_t *)p->d_tmap, p->n_tmap, (const int32_t *)p->d_rclass_off,
-                           (const double *)p->d_kplain, (const double *)p->d_le, p->d_me);
-        GRAV_HIP(hipGetLastError());
+        GRAV_CHECK(enqueue_m2l_transposed(p, g, s));
         stage_end(p, s);
         stage_begin(p, "m2mT", s);
         for (int l = 3; l <= L; ++l) {
-            hipLaunchKernelGGL(k_t_m2m<MT>, grid(p->lev[l].n_src * NG * p->PS), blk, 0, s, g, l,
+            const LevelInfo &lv = p->lev[l];
+            ColBlock cb;
+            for (int a = 0; a < 3; ++a) {
+                cb.lo[a] = lv.cs0[a];
+                cb.hi[a] = lv.cs0[a] + lv.cns[a] - 1;
+            }
+            hipLaunchKernelGGL(k_t_m2m<MT>, grid(p->lev[l].n_src * NG * p->PS), blk, 0, s, g, l, cb,
                                (const double *)p->d_m2m, p->d_me);
             GRAV_HIP(hipGetLastError());
         }

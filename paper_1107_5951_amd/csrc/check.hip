@@ -209,6 +209,19 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
         if (mx < 2 || mx > 3 || roff[e + 3] < 0 || roff[e + 3] >= kNumOffsets)
             ck.fail("m2lT", "reverse list entry out of range", (long long)e, roff[e + 3]);
     }
+    // the transposed M2L's offset table: (-d) of a reverse list entry, and
+    // an operator index inside the stored transposes (56 canonical ones
+    // with reflection bits in mixed plans, 316 in FP64)
+    if (p->d_tclass_off) {
+        const auto tco = fetch(p->d_tclass_off, (size_t)8 * kClassOffsets * 4);
+        const bool f64 = p->d.precision == GRAV_FP64;
+        for (size_t e = 0; e < tco.size() && ck.ok; e += 4) {
+            const int id = tco[e + 3] % kReflShift, refl = tco[e + 3] / kReflShift;
+            if (tco[e] != -roff[e] || tco[e + 1] != -roff[e + 1] || tco[e + 2] != -roff[e + 2] || tco[e + 3] < 0 ||
+                id >= (f64 ? kNumOffsets : kCanonOffsets) || refl > (f64 ? 0 : 7))
+                ck.fail("m2lT", "transposed offset entry out of range", (long long)e, tco[e + 3]);
+        }
+    }
     for (int l = 2; l < L && ck.ok; ++l) {
         const DevLev &lv = g.lev[l];
         for (int64_t i = 0; i < p->lev[l].n_tgt && ck.ok; ++i) {
@@ -233,42 +246,95 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
         // the forward M2L's stream-K schedule: segments cover every work item
         // once, in order, one unit per segment; each unit lists its segments
         // in order; every LE column maps to one valid (unit, column)
-        const TileRange &r = p->tiles[TK_M2L][0];
-        if (p->m2l_wgs > 0) {
-            const auto items = fetch(p->d_m2l_items, (size_t)p->m2l_items);
-            const auto segs = fetch(p->d_m2l_segs, (size_t)p->m2l_nseg * 4);
-            const auto wgseg = fetch(p->d_m2l_wgseg, (size_t)p->m2l_wgs + 1);
-            const int64_t nunit = p->m2l_nunit, upt = 64 / p->m2l_ncw;
-            const auto tstart = fetch(p->d_m2l_tseg_start, (size_t)nunit + 1);
-            const auto tsegs = fetch(p->d_m2l_tsegs, (size_t)std::max<int64_t>(1, p->m2l_nseg));
-            const auto colmap = fetch(p->d_m2l_colmap, (size_t)(p->n_tbox * p->B));
-            if (wgseg[0] != 0 || wgseg[p->m2l_wgs] != p->m2l_nseg)
-                ck.fail("m2l", "segment ranges do not cover the segments", wgseg[0], p->m2l_nseg);
+        auto schedule = [&](const char *name, const int32_t *d_items, int64_t n_items, const int32_t *d_segs,
+                            int64_t nseg, const int32_t *d_wgseg, int32_t wgs, const int32_t *d_tstart,
+                            const int32_t *d_tsegs, int64_t nunit) {
+            const auto items = fetch(d_items, (size_t)std::max<int64_t>(1, n_items));
+            const auto segs = fetch(d_segs, (size_t)std::max<int64_t>(1, nseg) * 4);
+            const auto wgseg = fetch(d_wgseg, (size_t)wgs + 1);
+            const auto tstart = fetch(d_tstart, (size_t)nunit + 1);
+            const auto tsegs = fetch(d_tsegs, (size_t)std::max<int64_t>(1, nseg));
+            if (wgseg[0] != 0 || wgseg[wgs] != nseg)
+                ck.fail(name, "segment ranges do not cover the segments", wgseg[0], nseg);
             int64_t next = 0;
-            for (int64_t sg = 0; sg < p->m2l_nseg && ck.ok; ++sg) {
+            for (int64_t sg = 0; sg < nseg && ck.ok; ++sg) {
                 const int32_t t = segs[4 * sg], ib = segs[4 * sg + 1], ie = segs[4 * sg + 2];
-                if (t < 0 || t >= nunit || ib != next || ie <= ib || ie > p->m2l_items)
-                    ck.fail("m2l", "segment out of order or range", sg, t);
+                if (t < 0 || t >= nunit || ib != next || ie <= ib || ie > n_items)
+                    ck.fail(name, "segment out of order or range", sg, t);
                 for (int32_t it = ib; it < ie && ck.ok; ++it)
                     if (items[it] < 0 || items[it] >= kClassOffsets)
-                        ck.fail("m2l", "work item offset out of range", it, items[it]);
+                        ck.fail(name, "work item offset out of range", it, items[it]);
                 next = ie;
             }
-            if (ck.ok && next != p->m2l_items)
-                ck.fail("m2l", "segments do not cover the work items", next, p->m2l_items);
-            if (ck.ok && (tstart[0] != 0 || tstart[nunit] != p->m2l_nseg))
-                ck.fail("m2l", "unit segment lists do not cover the segments", tstart[nunit], p->m2l_nseg);
+            if (ck.ok && next != n_items)
+                ck.fail(name, "segments do not cover the work items", next, n_items);
+            if (ck.ok && (tstart[0] != 0 || tstart[nunit] != nseg))
+                ck.fail(name, "unit segment lists do not cover the segments", tstart[nunit], nseg);
             for (int64_t t = 0; t < nunit && ck.ok; ++t)
                 for (int32_t j = tstart[t]; j < tstart[t + 1] && ck.ok; ++j)
-                    if (tsegs[j] < 0 || tsegs[j] >= p->m2l_nseg || segs[4 * tsegs[j]] != t ||
+                    if (tsegs[j] < 0 || tsegs[j] >= nseg || segs[4 * tsegs[j]] != t ||
                         (j > tstart[t] && tsegs[j] <= tsegs[j - 1]))
-                        ck.fail("m2l", "unit segment list inconsistent", t, j);
+                        ck.fail(name, "unit segment list inconsistent", t, j);
+        };
+        const TileRange &r = p->tiles[TK_M2L][0];
+        const int64_t upt = 64 / p->m2l_ncw;
+        if (p->m2l_wgs > 0) {
+            const int64_t nunit = p->m2l_nunit;
+            schedule("m2l", p->d_m2l_items, p->m2l_items, p->d_m2l_segs, p->m2l_nseg, p->d_m2l_wgseg, p->m2l_wgs,
+                     p->d_m2l_tseg_start, p->d_m2l_tsegs, nunit);
+            const auto colmap = fetch(p->d_m2l_colmap, (size_t)(p->n_tbox * p->B));
             for (int64_t c = 0; c < p->n_tbox * p->B && ck.ok; ++c) {
                 const int32_t m = colmap[c];
                 const int64_t u = m >> 6;
                 if (m < 0 || u >= nunit || (m & 63) >= p->m2l_ncw ||
                     (u % upt) * p->m2l_ncw + (m & 63) >= tiles[r.off + u / upt].ncol)
                     ck.fail("m2l", "LE column without a unit column", c, m);
+            }
+        }
+        // the transposed M2L (adjoint): the same schedule checks; its tiles
+        // address the column blocks, its columns map to units and to ME
+        // columns, each ME column at most once; the gather regions lie in
+        // the target maps (source block + halo 3)
+        if (ck.ok) {
+            const int64_t nunit = p->m2lt_nunit, ntile = nunit / upt;
+            if (p->m2lt_wgs > 0)
+                schedule("m2lT", p->d_m2lt_items, p->m2lt_items, p->d_m2lt_segs, p->m2lt_nseg, p->d_m2lt_wgseg,
+                         p->m2lt_wgs, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, nunit);
+            const auto ttiles = fetch(p->d_m2lt_tiles, (size_t)std::max<int64_t>(1, ntile));
+            const auto sorder = fetch(p->d_sorder, (size_t)std::max<int64_t>(1, p->n_me));
+            for (int64_t t = 0; t < ntile && ck.ok; ++t) {
+                const GemmTile &tl = ttiles[t];
+                if (tl.level < 2 || tl.level > L || tl.cls < 0 || tl.cls > 7 || tl.ncol < 1 || tl.ncol > kTileCols)
+                    ck.fail("m2lT", "tile out of range", t, tl.level);
+                else {
+                    const LevelInfo &lv = p->lev[tl.level];
+                    const int64_t nb = lv.col_class_start[tl.cls + 1] - lv.col_class_start[tl.cls];
+                    if (tl.col0 < 0 || tl.col0 + tl.ncol > nb * p->B)
+                        ck.fail("m2lT", "tile columns outside its class", t, tl.col0);
+                }
+            }
+            for (int l = 2; l <= L && ck.ok; ++l) {
+                const LevelInfo &lv = p->lev[l];
+                if (lv.col_class_start[8] > lv.n_src)
+                    ck.fail("m2lT", "column block larger than the source block", l, lv.col_class_start[8]);
+                for (int64_t i = 0; i < lv.col_class_start[8] && ck.ok; ++i)
+                    if (sorder[lv.me_off + i] < 0 || sorder[lv.me_off + i] >= lv.n_src)
+                        ck.fail("m2lT", "column box outside the source block", l, sorder[lv.me_off + i]);
+                for (int a = 0; a < 3 && ck.ok; ++a)
+                    if (lv.gns[a] > 0 && (lv.gs0[a] < lv.s0[a] - 3 || lv.gs0[a] + lv.gns[a] > lv.s0[a] + lv.ns[a] + 3))
+                        ck.fail("m2lT", "gather region outside the target map", l, a);
+            }
+            const auto colmap = fetch(p->d_m2lt_colmap, (size_t)std::max<int64_t>(1, p->m2lt_ncols));
+            const auto colbox = fetch(p->d_m2lt_colbox, (size_t)std::max<int64_t>(1, p->m2lt_ncols));
+            std::vector<char> seen((size_t)std::max<int64_t>(1, p->n_me * p->B), 0);
+            for (int64_t c = 0; c < p->m2lt_ncols && ck.ok; ++c) {
+                const int32_t m = colmap[c];
+                const int64_t u = m >> 6;
+                if (m < 0 || u >= nunit || (m & 63) >= p->m2l_ncw ||
+                    (u % upt) * p->m2l_ncw + (m & 63) >= ttiles[u / upt].ncol)
+                    ck.fail("m2lT", "column without a unit column", c, m);
+                else if (colbox[c] < 0 || colbox[c] >= p->n_me * p->B || seen[colbox[c]]++)
+                    ck.fail("m2lT", "ME column out of range or repeated", c, colbox[c]);
             }
         }
     }

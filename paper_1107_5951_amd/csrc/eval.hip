@@ -993,6 +993,25 @@ void stage_end(Plan *p, hipStream_t s)
     ++p->n_stage_used;
 }
 
+template <typename T>
+static M2LRun<T> forward_m2l(const Plan *p, const T *K)
+{
+    M2LRun<T> r;
+    r.tiles = (const GemmTile *)(p->d_tiles + p->tiles[TK_M2L][0].off);
+    r.keys = (const uint32_t *)p->d_tkey;
+    r.order = (const int32_t *)p->d_torder;
+    r.class_off = (const int32_t *)p->d_class_off;
+    r.K = K;
+    r.b_in = reinterpret_cast<const T *>(p->d_meg);
+    r.segs = (const int32_t *)p->d_m2l_segs;
+    r.wgseg = (const int32_t *)p->d_m2l_wgseg;
+    r.items = (const int32_t *)p->d_m2l_items;
+    r.part = reinterpret_cast<T *>(p->d_part);
+    r.wgs = p->m2l_wgs;
+    r.nset = p->m2l_nset;
+    return r;
+}
+
 static grav_status launch_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
 {
     const int RB = p->PS / 16;
@@ -1162,10 +1181,14 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         }
         stage_end(p, s);
         stage_begin(p, "m2l", s);
-        if (p->d.precision == GRAV_FP64)
-            GRAV_CHECK(launch_m2l<double>(p, g, s, p->d_k64));
-        else
-            GRAV_CHECK(launch_m2l<float>(p, g, s, p->d_k32));
+        if (p->tiles[TK_M2L][0].n > 0) {
+            // the segment slots are sized for FP64; the regathered expansions
+            // are FP32 in mixed plans (see k_me_gather)
+            if (p->d.precision == GRAV_FP64)
+                GRAV_CHECK(launch_m2l<double>(p, g, s, forward_m2l<double>(p, p->d_k64)));
+            else
+                GRAV_CHECK(launch_m2l<float>(p, g, s, forward_m2l<float>(p, p->d_k32)));
+        }
         stage_end(p, s);
         {
             stage_begin(p, "m2l_sum", s);

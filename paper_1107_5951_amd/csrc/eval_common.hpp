@@ -56,8 +56,25 @@ __host__ __device__ inline int64_t class_split(const DevLev &lv, int cls, int fi
 DevGeom make_geom(const Plan *p);
 template <typename T>
 __global__ void k_sum_parts(const T *part, int S, int64_t n, double *out);
+// One M2L problem on the stream-K kernel: the forward M2L (columns are
+// target boxes, B the regathered multipole expansions) or the adjoint's
+// transposed M2L (columns are source boxes, B the regathered adjoint local
+// expansions, operators K_d^T).
 template <typename T>
-grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K);
+struct M2LRun {
+    const GemmTile *tiles;
+    const uint32_t *keys;      // Morton key of each column box (per level, from lev.tbox_off)
+    const int32_t *order;      // class-grouped column order -> box (per level, from lev.tbox_off)
+    const int32_t *class_off;  // [8][189][4] (dx, dy, dz, operator) per column class
+    const T *K;                // operators in the panel layout
+    const T *b_in;             // regathered B operand
+    const int32_t *segs, *wgseg, *items;
+    T *part;                   // segment slots
+    int32_t wgs;               // workgroups (0: nothing to do)
+    int nset;                  // operand register sets of the FP32 kernel
+};
+template <typename T>
+grav_status launch_m2l(const Plan *p, const DevGeom &g, hipStream_t s, const M2LRun<T> &r);
 grav_status m2l_resident_workers(const Plan *p, int nset, int *workers);
 grav_status begin_call(Plan *p, hipStream_t s);
 grav_status end_call(Plan *p, hipStream_t s);

@@ -55,6 +55,16 @@ struct LevelInfo {
     int64_t src_class[8] = {0};       // source boxes of each parity class
     int need_lo[3] = {0, 0, 0};       // box range whose expansions the M2L reads (the
     int need_hi[3] = {-1, -1, -1};    // target boxes' range widened by 3, inclusive)
+    // transposed M2L (adjoint): its columns are the source boxes of the
+    // column block (the source block within reach of a target box; the
+    // whole block at level 2), class-grouped like the forward's target
+    // boxes; its B operand is the adjoint LE regathered over the gather
+    // region (the target boxes' bounding box within the source block
+    // widened by 3)
+    int cs0[3] = {0, 0, 0}, cns[3] = {0, 0, 0};
+    int64_t col_class_start[9] = {0};
+    int gs0[3] = {0, 0, 0}, gns[3] = {0, 0, 0};
+    int64_t g_off = 0;                // offset (in boxes) of the level in the gathered buffer
 };
 
 // Tiled stages: the forward M2L (its tiles also give the L2L its columns).
@@ -112,6 +122,25 @@ struct Plan {
     int64_t m2l_nseg = 0, m2l_items = 0, m2l_nunit = 0;
     int32_t *d_m2l_items = nullptr, *d_m2l_segs = nullptr, *d_m2l_wgseg = nullptr;
     int32_t *d_m2l_tseg_start = nullptr, *d_m2l_tsegs = nullptr, *d_m2l_colmap = nullptr;
+    // the transposed M2L's schedule, in the same form (columns: source boxes
+    // of the column blocks; colmap per column, colbox = its ME column
+    // (me box * B + model)); keys/order index the source boxes like
+    // d_tkey/d_torder the target boxes; class_off holds (-d, operator of
+    // K_d^T) per source class; the operators are K_d^T in the forward's
+    // panel layout (56 canonical ones in mixed plans, all 316 in FP64)
+    int32_t m2lt_wgs = 0, m2lt_nset = 2;
+    int64_t m2lt_nseg = 0, m2lt_ncols = 0, m2lt_nunit = 0, m2lt_items = 0, n_leg = 0;
+    struct GemmTile *d_m2lt_tiles = nullptr;
+    int32_t *d_m2lt_items = nullptr, *d_m2lt_segs = nullptr, *d_m2lt_wgseg = nullptr;
+    int32_t *d_m2lt_tseg_start = nullptr, *d_m2lt_tsegs = nullptr, *d_m2lt_colmap = nullptr;
+    int64_t *d_m2lt_colbox = nullptr;
+    uint32_t *d_skey = nullptr;       // [n_me] Morton key of every source box
+    int32_t *d_sorder = nullptr;      // [n_me] column-block class order -> dense index, per level
+    int32_t *d_tclass_off = nullptr;  // [8][189][4]
+    double *d_kt64 = nullptr;
+    float *d_kt32 = nullptr;
+    double *d_leg = nullptr;          // regathered adjoint LE (FP32 in mixed plans)
+    double *d_partt = nullptr;        // segment slots of the transposed M2L
     // near field of voxel-centre targets by lattice matrices (b <= 4)
     bool lat_near = false;
     int lat_RB = 0, lat_Q = 0;                     // row blocks (4 b^3 / 16); chunks of four k steps
@@ -142,8 +171,6 @@ struct Plan {
     double *d_l2l = nullptr;       // [8][PS][PS] L2L per child octant, row-major [out][in] (adjoint)
     double *d_k64 = nullptr;       // forward M2L operators as MFMA A fragments (FP64 plans: all 316)
     float *d_k32 = nullptr;        // same, FP32 (mixed plans: the 56 stored operators)
-    double *d_kplain = nullptr;    // [316][p^2][p^2] M2L operators row-major, in the forward's
-                                   // precision (FP32-rounded for mixed plans), for the adjoint
 
     double *d_me = nullptr;        // [n_me][B][PS]
     double *d_le = nullptr;        // [n_tbox][B][PS]

@@ -317,24 +317,18 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
 }
 
 template <typename T>
-grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
+grav_status launch_m2l(const Plan *p, const DevGeom &g, hipStream_t s, const M2LRun<T> &r)
 {
-    const TileRange &r = p->tiles[TK_M2L][0];
-    if (r.n == 0 || p->m2l_wgs == 0)
+    if (r.wgs == 0)
         return GRAV_OK;
     constexpr int NC = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;  // column blocks per wave
-    dim3 grid(p->m2l_wgs), blk(64);
-    T *part = reinterpret_cast<T *>(p->d_part);  // segment slots (sized for FP64)
-    const T *me_in = reinterpret_cast<const T *>(p->d_meg);  // regathered expansions (see k_me_gather)
-#define M2L_LAUNCH(P, NS)                                                                       \
-    hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T, NS>), grid, blk, 0, s, g,  \
-                       (const GemmTile *)(p->d_tiles + r.off), (const uint32_t *)p->d_tkey,     \
-                       (const int32_t *)p->d_torder, (const int32_t *)p->d_class_off, K, me_in, \
-                       (const int32_t *)p->d_m2l_segs, (const int32_t *)p->d_m2l_wgseg,         \
-                       (const int32_t *)p->d_m2l_items, part)
+    dim3 grid(r.wgs), blk(64);
+#define M2L_LAUNCH(P, NS)                                                                              \
+    hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T, NS>), grid, blk, 0, s, g, r.tiles, \
+                       r.keys, r.order, r.class_off, r.K, r.b_in, r.segs, r.wgseg, r.items, r.part)
 #define M2L_CASE(P)                                                                             \
     case P:                                                                                     \
-        if (sizeof(T) == 4 && p->m2l_nset == 1)                                                 \
+        if (sizeof(T) == 4 && r.nset == 1)                                                      \
             M2L_LAUNCH(P, 1);                                                                   \
         else                                                                                    \
             M2L_LAUNCH(P, 2);                                                                   \
@@ -365,8 +359,8 @@ grav_status launch_m2l(Plan *p, const DevGeom &g, hipStream_t s, const T *K)
     return GRAV_OK;
 }
 
-template grav_status launch_m2l<double>(Plan *, const DevGeom &, hipStream_t, const double *);
-template grav_status launch_m2l<float>(Plan *, const DevGeom &, hipStream_t, const float *);
+template grav_status launch_m2l<double>(const Plan *, const DevGeom &, hipStream_t, const M2LRun<double> &);
+template grav_status launch_m2l<float>(const Plan *, const DevGeom &, hipStream_t, const M2LRun<float> &);
 
 // One-wave workgroups of the plan's M2L kernel (with nset operand register
 // sets in FP32) that the device holds at once (blocks per CU from the

@@ -284,10 +284,12 @@ void free_plan(Plan *p)
     void *bufs[] = {p->d_points, p->d_perm, p->d_tpos, p->d_tleaf, p->d_leaf_start, p->d_tkey,
                     p->d_tparent, p->d_torder, p->d_tiles, p->d_class_off, p->d_rclass_off,
                     p->d_tmap, p->d_tchild, p->d_geom, p->d_pm, p->d_pm_sw, p->d_m2m,
-                    p->d_l2l, p->d_k64, p->d_kplain, p->d_k32, p->d_me,
+                    p->d_l2l, p->d_k64, p->d_k32, p->d_me,
                     p->d_le, p->d_near, p->d_part, p->d_tn64, p->d_tn32, p->d_m2m_sw, p->d_l2l_sw, p->d_rho_blk, p->d_tl2p, p->d_dpart, p->d_meg, p->d_lat_tab, p->d_m2l_items, p->d_m2l_segs,
                     p->d_m2l_wgseg, p->d_m2l_tseg_start, p->d_m2l_tsegs, p->d_m2l_colmap,
-                    p->d_cell_slot, p->d_leaf_pend};
+                    p->d_cell_slot, p->d_leaf_pend, p->d_m2lt_tiles, p->d_m2lt_items, p->d_m2lt_segs,
+                    p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
+                    p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -525,38 +527,277 @@ grav_status build_operators(Plan *p)
         GRAV_CHECK(upload(p, &p->d_l2l_sw, lsw));
     }
 
-    // M2L for all 316 offsets, swizzled for the MFMA A operand, and transposes
+    // M2L for all 316 offsets, swizzled for the MFMA A operand, and their transposes
     const bool canonical = p->d.precision != GRAV_FP64;
     std::vector<int> all;
     std::vector<int32_t> fwd, rev;
     offsets_tables(all, fwd, rev, canonical);
     const size_t perp = (size_t)RB * 64 * 4 * RB;  // forward M2L: PS/4 k steps, grouped by four
-    const size_t P2 = (size_t)P * P;
-    std::vector<double> k(perp * (canonical ? kCanonOffsets : kNumOffsets)), kp(P2 * P2 * kNumOffsets);
+    std::vector<double> k(perp * (canonical ? kCanonOffsets : kNumOffsets)), kt(k.size()), mt((size_t)PS * PS);
     for (int id = 0; id < kNumOffsets; ++id) {
         // source = target + d  =>  target centre - source centre = -d
         const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
         m2l_matrix(P, dd, PS, m.data());
-        // the adjoint's copy holds exactly the values the forward multiplies by
-        for (size_t i = 0; i < P2; ++i)
-            for (size_t j = 0; j < P2; ++j) {
-                const double v = m[i * PS + j];
-                kp[((size_t)id * P2 + i) * P2 + j] = canonical ? (double)(float)v : v;
-            }
-        // the forward operators: all 316, or the 56 with non-negative components
+        // the forward operators: all 316, or the 56 with non-negative
+        // components; the adjoint's transposes in the same layout (the
+        // reflections act on K_d^T as on K_d: K_d^T = S K_|d|^T S)
         const int ci = canonical ? canon_index(all[3 * id], all[3 * id + 1], all[3 * id + 2]) : id;
-        if (ci >= 0)
+        if (ci >= 0) {
             swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, k.data() + perp * ci);
+            for (int i = 0; i < PS; ++i)
+                for (int j = 0; j < PS; ++j)
+                    mt[(size_t)j * PS + i] = m[(size_t)i * PS + j];
+            swizzle_panel(mt.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, kt.data() + perp * ci);
+        }
     }
     if (p->d.precision == GRAV_FP64) {
         GRAV_CHECK(upload(p, &p->d_k64, k));
+        GRAV_CHECK(upload(p, &p->d_kt64, kt));
     } else {
+        // the FP32 copies are exactly what both directions multiply by
         std::vector<float> k32(k.begin(), k.end());
         GRAV_CHECK(upload(p, &p->d_k32, k32));
+        std::vector<float> kt32(kt.begin(), kt.end());
+        GRAV_CHECK(upload(p, &p->d_kt32, kt32));
     }
-    GRAV_CHECK(upload(p, &p->d_kplain, kp));
     GRAV_CHECK(upload(p, &p->d_class_off, fwd));
+    // the transposed M2L's offset table, keyed by the class of the source
+    // box S: entry (-d, operator of K_d^T) for each d of the reverse list
+    // (T = S - d), the operator field packed as in the forward table
+    std::vector<int32_t> tco(rev.size());
+    for (size_t e = 0; e < rev.size(); e += 4) {
+        const int d[3] = {rev[e], rev[e + 1], rev[e + 2]};
+        const int refl = (d[0] < 0 ? 1 : 0) | (d[1] < 0 ? 2 : 0) | (d[2] < 0 ? 4 : 0);
+        tco[e] = -d[0];
+        tco[e + 1] = -d[1];
+        tco[e + 2] = -d[2];
+        tco[e + 3] = canonical ? canon_index(std::abs(d[0]), std::abs(d[1]), std::abs(d[2])) + kReflShift * refl
+                               : rev[e + 3];
+    }
+    GRAV_CHECK(upload(p, &p->d_tclass_off, tco));
     GRAV_CHECK(upload(p, &p->d_rclass_off, rev));
+    return GRAV_OK;
+}
+
+// Stream-K partition of an M2L's work items (see build_tiles): item i
+// belongs to unit item_unit[i], units in order.  A fixed number of one-wave
+// workgroups, all resident at once, take equal contiguous shares of the
+// items; a share is cut into segments {unit, first item, end item, 0} at
+// unit boundaries (wgseg: CSR over workgroups), and per unit its segment
+// slots are listed in workgroup order (tseg_start/tsegs: CSR over units).
+struct StreamK {
+    std::vector<int32_t> seg, wgseg, tseg_start, tsegs;
+    int64_t P = 0, nseg = 0;
+    int nset = 2;
+};
+
+static grav_status stream_k(const Plan *p, const std::vector<int32_t> &item_unit, int64_t nunit, StreamK &o)
+{
+    const int64_t T = (int64_t)item_unit.size();
+    // at least kMinItems items per workgroup: small plans get fewer
+    // workgroups rather than one partial slot per item
+    constexpr int64_t kMinItems = 8;
+    constexpr int64_t kItemsOneSet = 32;  // items per resident wave above which one set pays
+    // FP32: one operand register set (more resident waves) when every wave
+    // gets a long run of items, two sets on small plans
+    int resident = 0;
+    o.nset = 2;
+    if (p->d.precision != GRAV_FP64) {
+        GRAV_CHECK(m2l_resident_workers(p, 1, &resident));
+        if (T >= kItemsOneSet * resident)
+            o.nset = 1;
+    }
+    GRAV_CHECK(m2l_resident_workers(p, o.nset, &resident));
+    const int64_t P = T == 0 ? 0
+                             : std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(GRAV_M2L_WAVES, resident),
+                                                                      T / kMinItems));
+    o.seg.clear();
+    o.wgseg.assign(P + 1, 0);
+    std::vector<int32_t> tseg_n(nunit + 1, 0);
+    for (int64_t w = 0; w < P; ++w) {
+        o.wgseg[w] = (int32_t)(o.seg.size() / 4);
+        const int64_t ie = (w + 1) * T / P;
+        for (int64_t i = w * T / P; i < ie;) {
+            int64_t j = i;
+            while (j < ie && item_unit[j] == item_unit[i])
+                ++j;
+            o.seg.insert(o.seg.end(), {item_unit[i], (int32_t)i, (int32_t)j, 0});
+            ++tseg_n[item_unit[i] + 1];
+            i = j;
+        }
+    }
+    o.nseg = (int64_t)o.seg.size() / 4;
+    o.wgseg[P] = (int32_t)o.nseg;
+    o.tseg_start.assign(nunit + 1, 0);
+    o.tsegs.assign(o.nseg, 0);
+    std::vector<int32_t> fill(nunit, 0);
+    for (int64_t u = 0; u < nunit; ++u)
+        o.tseg_start[u + 1] = o.tseg_start[u] + tseg_n[u + 1];
+    for (int64_t sgi = 0; sgi < o.nseg; ++sgi) {
+        const int32_t u = o.seg[4 * sgi];
+        o.tsegs[o.tseg_start[u] + fill[u]++] = (int32_t)sgi;
+    }
+    o.P = P;
+    return GRAV_OK;
+}
+
+// The adjoint's transposed M2L on the forward kernel: ME_l[S] = sum over the
+// reverse list of S's class of K_d^T LE_l[S - d] (the forward adds K_d
+// ME[T + d] into LE[T] for exactly these pairs).  Per level, the columns
+// are the source boxes of the column block, class-grouped as the forward
+// groups its target boxes, 64 (box, model) columns per tile, units of
+// 16 NC columns; the B operand is the adjoint LE regathered over the gather
+// region; a work item is a (unit, offset) pair at which some column meets
+// a target box.  Everything else (stream-K, slots, sums) is the forward's.
+static grav_status build_m2l_transposed(Plan *p, const std::vector<std::vector<uint32_t>> &key,
+                                        const std::vector<int32_t> &rev)
+{
+    const int L = p->L;
+    const int64_t B = p->B;
+    const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
+    const int ncw = 16 * nc, upt = 4 / nc;
+    std::vector<uint32_t> skey((size_t)std::max<int64_t>(p->n_me, 1), 0);
+    std::vector<int32_t> sorder((size_t)std::max<int64_t>(p->n_me, 1), 0);
+    std::vector<GemmTile> tiles;
+    std::vector<int32_t> item_unit, item_off, colmap;
+    std::vector<int64_t> colbox;
+    std::vector<char> hit(kClassOffsets);
+    int64_t goff = 0;
+    for (int l = 2; l <= L; ++l) {
+        LevelInfo &lv = p->lev[l];
+        // target boxes of the level within reach of the source block
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = lv.s0[a] - 3;
+            hi[a] = lv.s0[a] + lv.ns[a] + 2;
+        }
+        int blo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, bhi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+        for (const uint32_t k : key[l]) {
+            const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+            bool in = true;
+            for (int a = 0; a < 3; ++a)
+                in = in && c[a] >= lo[a] && c[a] <= hi[a];
+            if (!in)
+                continue;
+            for (int a = 0; a < 3; ++a) {
+                blo[a] = std::min(blo[a], c[a]);
+                bhi[a] = std::max(bhi[a], c[a]);
+            }
+        }
+        const bool any = blo[0] <= bhi[0];
+        int64_t gn = 1;
+        for (int a = 0; a < 3; ++a) {
+            lv.gs0[a] = any ? blo[a] : 0;
+            lv.gns[a] = any ? bhi[a] - blo[a] + 1 : 0;
+            gn *= lv.gns[a];
+        }
+        lv.g_off = goff;
+        goff += gn;
+        std::vector<char> tb((size_t)gn, 0);
+        for (const uint32_t k : key[l]) {
+            const int c[3] = {(int)compact3(k) - lv.gs0[0], (int)compact3(k >> 1) - lv.gs0[1],
+                              (int)compact3(k >> 2) - lv.gs0[2]};
+            if (c[0] >= 0 && c[1] >= 0 && c[2] >= 0 && c[0] < lv.gns[0] && c[1] < lv.gns[1] && c[2] < lv.gns[2])
+                tb[((size_t)c[2] * lv.gns[1] + c[1]) * lv.gns[0] + c[0]] = 1;
+        }
+        // column block: the source boxes within 3 of the gather region (the
+        // whole source block at level 2, so that every level-2 expansion is
+        // written; below, M2M^T sets the boxes outside the column block)
+        for (int a = 0; a < 3; ++a) {
+            int c0 = lv.s0[a], c1 = lv.s0[a] + lv.ns[a] - 1;
+            if (l > 2) {
+                c0 = std::max(c0, any ? lv.gs0[a] - 3 : c1 + 1);
+                c1 = std::min(c1, any ? lv.gs0[a] + lv.gns[a] + 2 : c0 - 1);
+            }
+            lv.cs0[a] = c0;
+            lv.cns[a] = std::max(0, c1 - c0 + 1);
+        }
+        for (int64_t j = 0; j < lv.n_src; ++j) {
+            const int x = lv.s0[0] + (int)(j % lv.ns[0]), y = lv.s0[1] + (int)((j / lv.ns[0]) % lv.ns[1]),
+                      z = lv.s0[2] + (int)(j / ((int64_t)lv.ns[0] * lv.ns[1]));
+            skey[(size_t)(lv.me_off + j)] = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+        }
+        DevLev cb{};
+        for (int a = 0; a < 3; ++a) {
+            cb.s0[a] = lv.cs0[a];
+            cb.ns[a] = lv.cns[a];
+        }
+        int64_t pos = 0;
+        for (int cls = 0; cls < 8; ++cls) {
+            int first[3], cnt[3];
+            lv.col_class_start[cls] = pos;
+            class_split(cb, cls, first, cnt);
+            for (int iz = 0; iz < cnt[2]; ++iz)
+                for (int iy = 0; iy < cnt[1]; ++iy)
+                    for (int ix = 0; ix < cnt[0]; ++ix) {
+                        const int x = first[0] + 2 * ix, y = first[1] + 2 * iy, z = first[2] + 2 * iz;
+                        sorder[(size_t)(lv.me_off + pos++)] =
+                            (int32_t)(((int64_t)(z - lv.s0[2]) * lv.ns[1] + (y - lv.s0[1])) * lv.ns[0] + (x - lv.s0[0]));
+                    }
+        }
+        lv.col_class_start[8] = pos;
+        for (int cls = 0; cls < 8; ++cls) {
+            const int64_t ncols = (lv.col_class_start[cls + 1] - lv.col_class_start[cls]) * B;
+            for (int64_t c0 = 0; c0 < ncols; c0 += kTileCols) {
+                GemmTile t{};
+                t.level = l;
+                t.cls = cls;
+                t.col0 = c0;
+                t.ncol = (int32_t)std::min<int64_t>(kTileCols, ncols - c0);
+                const int64_t u0 = (int64_t)tiles.size() * upt;
+                tiles.push_back(t);
+                for (int hq = 0; hq < upt; ++hq) {
+                    std::fill(hit.begin(), hit.end(), 0);
+                    for (int cl = hq * ncw; cl < std::min(t.ncol, (hq + 1) * ncw); ++cl) {
+                        const int64_t col = t.col0 + cl;
+                        const int32_t j = sorder[(size_t)(lv.me_off + lv.col_class_start[cls] + col / B)];
+                        colmap.push_back((int32_t)((u0 + hq) * 64 + cl - hq * ncw));
+                        colbox.push_back((lv.me_off + j) * B + col % B);
+                        const int c[3] = {lv.s0[0] + (int)(j % lv.ns[0]), lv.s0[1] + (int)((j / lv.ns[0]) % lv.ns[1]),
+                                          lv.s0[2] + (int)(j / ((int64_t)lv.ns[0] * lv.ns[1]))};
+                        for (int o = 0; o < kClassOffsets && any; ++o) {
+                            const int32_t *e = &rev[((size_t)cls * kClassOffsets + o) * 4];
+                            int g[3];
+                            bool in = true;
+                            for (int a = 0; a < 3; ++a) {
+                                g[a] = c[a] - e[a] - lv.gs0[a];  // T = S - d
+                                in = in && g[a] >= 0 && g[a] < lv.gns[a];
+                            }
+                            if (in && tb[((size_t)g[2] * lv.gns[1] + g[1]) * lv.gns[0] + g[0]])
+                                hit[o] = 1;
+                        }
+                    }
+                    for (int o = 0; o < kClassOffsets; ++o)
+                        if (hit[o]) {
+                            item_unit.push_back((int32_t)(u0 + hq));
+                            item_off.push_back(o);
+                        }
+                }
+            }
+        }
+    }
+    const int64_t nunit = (int64_t)tiles.size() * upt;
+    StreamK sk;
+    GRAV_CHECK(stream_k(p, item_unit, nunit, sk));
+    if (item_off.empty())
+        item_off.push_back(0);
+    GRAV_CHECK(upload(p, &p->d_m2lt_tiles, tiles.empty() ? std::vector<GemmTile>(1) : tiles));
+    GRAV_CHECK(upload(p, &p->d_m2lt_items, item_off));
+    GRAV_CHECK(upload(p, &p->d_m2lt_segs, sk.seg.empty() ? std::vector<int32_t>(4, 0) : sk.seg));
+    GRAV_CHECK(upload(p, &p->d_m2lt_wgseg, sk.wgseg));
+    GRAV_CHECK(upload(p, &p->d_m2lt_tseg_start, sk.tseg_start));
+    GRAV_CHECK(upload(p, &p->d_m2lt_tsegs, sk.tsegs.empty() ? std::vector<int32_t>(1, 0) : sk.tsegs));
+    GRAV_CHECK(upload(p, &p->d_m2lt_colmap, colmap.empty() ? std::vector<int32_t>(1, 0) : colmap));
+    GRAV_CHECK(upload(p, &p->d_m2lt_colbox, colbox.empty() ? std::vector<int64_t>(1, 0) : colbox));
+    GRAV_CHECK(upload(p, &p->d_skey, skey));
+    GRAV_CHECK(upload(p, &p->d_sorder, sorder));
+    p->m2lt_wgs = (int32_t)sk.P;
+    p->m2lt_nset = sk.nset;
+    p->m2lt_nseg = sk.nseg;
+    p->m2lt_ncols = (int64_t)colmap.size();
+    p->m2lt_nunit = nunit;
+    p->m2lt_items = (int64_t)item_unit.size();
+    p->n_leg = goff;
     return GRAV_OK;
 }
 
@@ -695,59 +936,23 @@ grav_status build_tiles(Plan *p)
                         }
                 }
             }
-            const int64_t T = (int64_t)item_tile.size();
-            // at least kMinItems items per workgroup: small plans get fewer
-            // workgroups rather than one partial slot per item
-            constexpr int64_t kMinItems = 8;
-            constexpr int64_t kItemsOneSet = 32;  // items per resident wave above which one set pays
-            // FP32: one operand register set (more resident waves) when every
-            // wave gets a long run of items, two sets on small plans
-            int resident = 0;
-            p->m2l_nset = 2;
-            if (p->d.precision != GRAV_FP64) {
-                GRAV_CHECK(m2l_resident_workers(p, 1, &resident));
-                if (T >= (int64_t)kItemsOneSet * resident)
-                    p->m2l_nset = 1;
-            }
-            GRAV_CHECK(m2l_resident_workers(p, p->m2l_nset, &resident));
-            const int64_t P = std::max<int64_t>(
-                1, std::min<int64_t>(std::min<int64_t>(GRAV_M2L_WAVES, resident), T / kMinItems));
-            std::vector<int32_t> seg, wgseg(P + 1, 0), tseg_n(nunit + 1, 0);
-            for (int64_t w = 0; w < P; ++w) {
-                wgseg[w] = (int32_t)(seg.size() / 4);
-                const int64_t ie = (w + 1) * T / P;
-                for (int64_t i = w * T / P; i < ie;) {
-                    int64_t j = i;
-                    while (j < ie && item_tile[j] == item_tile[i])
-                        ++j;
-                    seg.insert(seg.end(), {item_tile[i], (int32_t)i, (int32_t)j, 0});
-                    ++tseg_n[item_tile[i] + 1];
-                    i = j;
-                }
-            }
-            const int64_t nseg = (int64_t)seg.size() / 4;
-            wgseg[P] = (int32_t)nseg;
-            // per unit, its segments in workgroup order
-            std::vector<int32_t> tseg_start(nunit + 1, 0), tsegs(nseg), fill(nunit, 0);
-            for (int64_t u = 0; u < nunit; ++u)
-                tseg_start[u + 1] = tseg_start[u] + tseg_n[u + 1];
-            for (int64_t sgi = 0; sgi < nseg; ++sgi) {
-                const int32_t u = seg[4 * sgi];
-                tsegs[tseg_start[u] + fill[u]++] = (int32_t)sgi;
-            }
+            StreamK sk;
+            GRAV_CHECK(stream_k(p, item_tile, nunit, sk));
             if (item_off.empty())
                 item_off.push_back(0);
             GRAV_CHECK(upload(p, &p->d_m2l_items, item_off));
-            GRAV_CHECK(upload(p, &p->d_m2l_segs, seg.empty() ? std::vector<int32_t>(4, 0) : seg));
-            GRAV_CHECK(upload(p, &p->d_m2l_wgseg, wgseg));
-            GRAV_CHECK(upload(p, &p->d_m2l_tseg_start, tseg_start));
-            GRAV_CHECK(upload(p, &p->d_m2l_tsegs, tsegs.empty() ? std::vector<int32_t>(1, 0) : tsegs));
+            GRAV_CHECK(upload(p, &p->d_m2l_segs, sk.seg.empty() ? std::vector<int32_t>(4, 0) : sk.seg));
+            GRAV_CHECK(upload(p, &p->d_m2l_wgseg, sk.wgseg));
+            GRAV_CHECK(upload(p, &p->d_m2l_tseg_start, sk.tseg_start));
+            GRAV_CHECK(upload(p, &p->d_m2l_tsegs, sk.tsegs.empty() ? std::vector<int32_t>(1, 0) : sk.tsegs));
             GRAV_CHECK(upload(p, &p->d_m2l_colmap, colmap));
-            p->m2l_wgs = T > 0 ? (int32_t)P : 0;
-            p->m2l_nseg = nseg;
-            p->m2l_items = T;
+            p->m2l_nset = sk.nset;
+            p->m2l_wgs = (int32_t)sk.P;
+            p->m2l_nseg = sk.nseg;
+            p->m2l_items = (int64_t)item_tile.size();
             p->m2l_ncw = ncw;
             p->m2l_nunit = nunit;
+            GRAV_CHECK(build_m2l_transposed(p, key, rev));
         }
     }
     if (!split.empty())
@@ -1413,9 +1618,14 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
                 break;
         }
         {
-            // partial expansions of split M2L stages
-            const size_t part = (size_t)p->m2l_nseg * p->m2l_ncw * p->PS;  // forward M2L segment slots
+            // segment slots of the forward and the transposed M2L, and the
+            // adjoint LE regathered for the latter
+            const size_t part = (size_t)p->m2l_nseg * p->m2l_ncw * p->PS;
             if ((st = dalloc(p, &p->d_part, part, false)) != GRAV_OK)
+                break;
+            if ((st = dalloc(p, &p->d_partt, (size_t)p->m2lt_nseg * p->m2l_ncw * p->PS, false)) != GRAV_OK)
+                break;
+            if ((st = dalloc(p, &p->d_leg, (size_t)p->n_leg * p->B * p->PS, false)) != GRAV_OK)
                 break;
         }
         {
