@@ -69,103 +69,366 @@ k_t_weights(DevGeom g, const double *resid, const uint32_t *perm, double *w)
 // group), so that every operator entry or pair geometry it loads serves MT
 // models; groups are ceil(B / MT).
 
-// L2P^T: the adjoint of leaf expansion coefficient k is the sum over the
-// leaf's targets of the weights times the derivatives of (phi, grad phi) of
-// the local expansion with respect to that coefficient, scaled as the
-// combine scales the far field (phi / w, -grad phi / w^2).  One thread per
-// (target leaf, model group, coefficient).
-template <int MT>
-__global__ void __launch_bounds__(256)
-k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const uint32_t *tkey, int64_t n_leaf,
-        const double *w, double *le)
+// Transposed local-expansion evaluation: adds to col[k * CS] (k < p^2) the
+// derivative of a phi - (b1 gx + b2 gy + b3 gz) with respect to coefficient
+// k, where (phi, gx, gy, gz) is the local-expansion evaluation at u (box
+// widths from the box centre, see l2p_eval).  The same recurrences for the
+// regular harmonics R_n^m; each term c R of the evaluation adds its factor
+// R to the coefficient c it multiplies (the gradient pairs R_n^m with the
+// degree n+1 coefficients of orders m-1, m, m+1; order 0 has no imaginary
+// part).
+__device__ inline void l2p_transposed(int P, double x, double y, double z, double a, double b1, double b2, double b3,
+                                      double *col, int CS)
 {
-    const int NG = (g.B + MT - 1) / MT;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_leaf * NG * g.PS)
-        return;
-    const int k = (int)(t % g.PS);
-    const int64_t rest = t / g.PS;
-    const int grp = (int)(rest % NG);
-    const int64_t leaf = rest / NG;
-    const DevLev &lv = g.lev[g.L];
-    double acc[MT];
-#pragma unroll
-    for (int u = 0; u < MT; ++u)
-        acc[u] = 0.0;
-    if (k < g.P2) {
-        const uint32_t key = tkey[lv.tbox_off + leaf];
-        const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
-        double centre[3];
-        for (int a = 0; a < 3; ++a)
-            centre[a] = ((double)(lc[a] - g.shift[a]) + 0.5) * g.b;
-        const double inv_w = 1.0 / (double)g.b, inv_w2 = inv_w * inv_w;
-        const int64_t ts = max(leaf_start[leaf], (int64_t)0), te = min(leaf_start[leaf + 1], g.M);
-        for (int64_t j = ts; j < te; ++j) {
-            double d[4];
-            l2p_coef(g.P, k, (tpos[3 * j + 0] - centre[0]) * inv_w, (tpos[3 * j + 1] - centre[1]) * inv_w,
-                     (tpos[3 * j + 2] - centre[2]) * inv_w, d);
-            const double d0 = d[0] * inv_w, d1 = d[1] * inv_w2, d2 = d[2] * inv_w2, d3 = d[3] * inv_w2;
-#pragma unroll
-            for (int u = 0; u < MT; ++u) {
-                const int bm = grp * MT + u;
-                if (bm < g.B) {
-                    const double *wj = w + (j * g.B + bm) * 4;
-                    acc[u] += wj[0] * d0 - (wj[1] * d1 + wj[2] * d2 + wj[3] * d3);
+    auto RE = [&](int n, int m) -> double & { return col[(m == 0 ? n * n : n * n + 2 * m - 1) * CS]; };
+    auto IM = [&](int n, int m) -> double & { return col[(n * n + 2 * m) * CS]; };
+    const double r2 = x * x + y * y + z * z;
+    double mmr = 1.0, mmi = 0.0;
+    for (int m = 0; m < P; ++m) {
+        if (m > 0) {
+            const double s = 1.0 / (2.0 * m);
+            const double nr = (x * mmr - y * mmi) * s;
+            const double ni = (x * mmi + y * mmr) * s;
+            mmr = nr;
+            mmi = ni;
+        }
+        double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
+        for (int n = m; n < P; ++n) {
+            double Rr, Ri;
+            if (n == m) {
+                Rr = mmr;
+                Ri = mmi;
+            } else if (n == m + 1) {
+                Rr = z * p1r;
+                Ri = z * p1i;
+            } else {
+                const double f = 1.0 / (double)((n - m) * (n + m));
+                Rr = ((2.0 * n - 1.0) * z * p1r - r2 * p2r) * f;
+                Ri = ((2.0 * n - 1.0) * z * p1i - r2 * p2i) * f;
+            }
+            p2r = p1r;
+            p2i = p1i;
+            p1r = Rr;
+            p1i = Ri;
+            if (m == 0) {
+                RE(n, 0) += a * Rr;
+            } else {
+                RE(n, m) += 2.0 * a * Rr;
+                IM(n, m) -= 2.0 * a * Ri;
+            }
+            if (n + 1 < P) {
+                const int n1 = n + 1;
+                if (m == 0) {
+                    RE(n1, 0) -= b3 * Rr;
+                    RE(n1, 1) -= b1 * Rr;
+                    IM(n1, 1) += b2 * Rr;
+                } else {
+                    RE(n1, m) -= 2.0 * b3 * Rr;
+                    IM(n1, m) += 2.0 * b3 * Ri;
+                    RE(n1, m + 1) += b2 * Ri - b1 * Rr;
+                    RE(n1, m - 1) += b1 * Rr + b2 * Ri;
+                    IM(n1, m + 1) += b1 * Ri + b2 * Rr;
+                    if (m > 1)
+                        IM(n1, m - 1) += b2 * Rr - b1 * Ri;
                 }
             }
         }
     }
+}
+
+// L2P^T: the adjoint LE of a leaf is the sum over its targets of the
+// transposed evaluation with the target's weights, scaled as the combine
+// scales the far field (phi / w, -grad phi / w^2).  One wave per target
+// leaf; per model, the leaf's targets in chunks of 31: each of the first 31
+// lanes writes its target's p^2 terms into its own LDS column, then every
+// lane adds the columns of its coefficients (k = lane + 64 i) in target
+// order, so the sums are deterministic.  The odd row stride (31 doubles)
+// spreads the lanes of the second phase over the LDS banks.
+constexpr int kL2PTChunk = 31;
+__global__ void __launch_bounds__(64)
+k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const uint32_t *tkey, int64_t n_leaf,
+        const double *w, double *le)
+{
+    extern __shared__ double cols[];  // [p^2][kL2PTChunk]
+    const int64_t leaf = blockIdx.x;
+    const int lane = threadIdx.x;
+    const DevLev &lv = g.lev[g.L];
+    const uint32_t key = tkey[lv.tbox_off + leaf];
+    const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
+    double centre[3];
+    for (int a = 0; a < 3; ++a)
+        centre[a] = ((double)(lc[a] - g.shift[a]) + 0.5) * g.b;
+    const double inv_w = 1.0 / (double)g.b, inv_w2 = inv_w * inv_w;
+    const int64_t ts = max(leaf_start[leaf], (int64_t)0), te = min(leaf_start[leaf + 1], g.M);
+    for (int bm = 0; bm < g.B; ++bm) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};  // coefficients lane + 64 i (p^2 <= 256)
+        for (int64_t j0 = ts; j0 < te; j0 += kL2PTChunk) {
+            const int nt = (int)min((int64_t)kL2PTChunk, te - j0);
+            for (int i = lane; i < g.P2 * kL2PTChunk; i += 64)
+                cols[i] = 0.0;
+            __syncthreads();
+            if (lane < nt) {
+                const int64_t j = j0 + lane;
+                const double *wj = w + (j * g.B + bm) * 4;
+                l2p_transposed(g.P, (tpos[3 * j + 0] - centre[0]) * inv_w, (tpos[3 * j + 1] - centre[1]) * inv_w,
+                               (tpos[3 * j + 2] - centre[2]) * inv_w, wj[0] * inv_w, wj[1] * inv_w2, wj[2] * inv_w2,
+                               wj[3] * inv_w2, cols + lane, kL2PTChunk);
+            }
+            __syncthreads();
 #pragma unroll
-    for (int u = 0; u < MT; ++u) {
-        const int bm = grp * MT + u;
-        if (bm < g.B)
-            le[((lv.tgt_off + leaf) * g.B + bm) * g.PS + k] = acc[u];  // padding k >= p^2 gets 0
+            for (int i = 0; i < 4; ++i) {
+                const int k = lane + 64 * i;
+                if (k < g.P2)
+                    for (int t = 0; t < nt; ++t)
+                        acc[i] += cols[k * kL2PTChunk + t];
+            }
+            __syncthreads();
+        }
+        double *dst = le + ((lv.tgt_off + leaf) * g.B + bm) * g.PS;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = lane + 64 * i;
+            if (k < g.PS)
+                dst[k] = k < g.P2 ? acc[i] : 0.0;  // padding coefficients stay zero
+        }
     }
 }
 
-// L2L^T (upward over the target boxes): LE_l[box] = sum over the box's
-// children c of L2L_c^T LE_l+1[c], L2L row-major [octant][out t][in s], so
-// the thread of coefficient s reads column s.  One thread per (box of level
-// l, model group, coefficient s).
-template <int MT>
+// The column blocks of the transposed M2L: the boxes of level l whose ME it
+// writes (inclusive range); M2M^T adds to these and sets the others.
+struct ColBlock {
+    int lo[3], hi[3];
+};
+
+// The transposed translations M2M^T (downward over the source blocks) and
+// L2L^T (upward over the target boxes) as FP64 MFMA GEMMs in the layout of
+// the forward's k_m2m_lds: a workgroup owns 64 (box, model) columns, 16 per
+// wave, and all row blocks; the operator chunks (four k steps, all row
+// blocks) pass through LDS double-buffered, one barrier per chunk.
+//
+// L2L^T: LE_l[box] = sum over the box's children c of L2L_c^T LE_l+1[c];
+// the children of a target box are a contiguous range of level l+1 whose
+// keys give their octants.  K = 8 x p^2 (absent children read zero).
+template <int RB>
 __global__ void __launch_bounds__(256)
-k_t_l2l(DevGeom g, int l, const uint32_t *tkey, const int32_t *tchild, const double *l2l, double *le)
+k_t_l2l(DevGeom g, int l, const uint32_t *tkey, const int32_t *tchild, const double *A, double *le)
 {
-    const int NG = (g.B + MT - 1) / MT;
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int K4 = PS / 4;
+    constexpr int CH = 4 * RB * 64;
+    constexpr int NCH = 8 * RB;
+    __shared__ double sa[2][CH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kr = lane >> 4;
     const DevLev &lv = g.lev[l];
     const DevLev &lc = g.lev[l + 1];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= lv.n_tgt * NG * g.PS)
+    const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
+    const bool cvalid = col < lv.n_tgt * g.B;
+    const int64_t box = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
+    int32_t ca = 0, ce = 0;
+    if (cvalid) {
+        ca = max(tchild[lv.tchild_off + box], 0);
+        ce = min(tchild[lv.tchild_off + box + 1], (int32_t)lc.n_tgt);
+    }
+    auto child = [&](int c) -> const double2 * {
+        for (int32_t ch = ca; ch < ce; ++ch)
+            if ((int)(tkey[lc.tbox_off + ch] & 7u) == c)
+                return (const double2 *)(le + ((lc.tgt_off + ch) * g.B + bm) * PS + kr * K4);
+        return nullptr;
+    };
+    vec4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    double ra[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        ra[i] = A[i * 256 + tid];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        sa[0][i * 256 + tid] = ra[i];
+    const double2 *bp = child(0);
+    double2 b01 = bp ? bp[0] : double2{0.0, 0.0};
+    double2 b23 = bp ? bp[1] : double2{0.0, 0.0};
+    __syncthreads();
+    for (int j = 0; j < NCH; ++j) {
+        const int buf = j & 1;
+        const bool more = j + 1 < NCH;
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                ra[i] = A[(int64_t)(j + 1) * CH + i * 256 + tid];
+        }
+        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+        if (more) {
+            const int qn = (j + 1) % RB;
+            if (qn == 0)
+                bp = child((j + 1) / RB);
+            b01 = bp ? bp[2 * qn] : double2{0.0, 0.0};
+            b23 = bp ? bp[2 * qn + 1] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                                                             0);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                sa[buf ^ 1][i * 256 + tid] = ra[i];
+        }
+        __syncthreads();
+    }
+    if (!cvalid)
         return;
-    const int s = (int)(t % g.PS);
-    const int64_t rest = t / g.PS;
-    const int grp = (int)(rest % NG);
-    const int64_t box = rest / NG;
-    double acc[MT];
+    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
 #pragma unroll
-    for (int u = 0; u < MT; ++u)
-        acc[u] = 0.0;
-    if (s < g.P2) {
-        const int64_t a = tchild[lv.tchild_off + box], e = tchild[lv.tchild_off + box + 1];
-        for (int64_t ch = max(a, (int64_t)0); ch < min(e, lc.n_tgt); ++ch) {
-            const int oct = (int)(tkey[lc.tbox_off + ch] & 7u);
-            const double *col = l2l + (int64_t)oct * g.PS * g.PS + s;
-            const double *y = le + ((lc.tgt_off + ch) * g.B + grp * MT) * g.PS;
-            for (int q = 0; q < g.P2; ++q) {
-                const double m = col[(int64_t)q * g.PS];
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int u = 0; u < MT; ++u)
-                    if (grp * MT + u < g.B)
-                        acc[u] += m * y[(int64_t)u * g.PS + q];
-            }
+        for (int i = 0; i < 4; ++i)
+            dst[16 * r + kr + 4 * i] = acc[r][i];
+}
+
+// M2M^T: ME_l[child] (+)= M2M_c^T ME_l-1[parent] for the children of octant c
+// = blockIdx.y; the columns are the parent boxes of level l-1 (x models),
+// K = p^2.  Inside the transposed M2L's column block the child's ME already
+// holds the M2L^T terms and the product is added; elsewhere it is set.
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_t_m2m(DevGeom g, int l, ColBlock cb, const double *A, double *me)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int K4 = PS / 4;
+    constexpr int CH = 4 * RB * 64;
+    __shared__ double sa[2][CH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kr = lane >> 4;
+    const int oct = blockIdx.y;
+    const DevLev &lv = g.lev[l];
+    const DevLev &lp = g.lev[l - 1];
+    const int64_t nbox = (int64_t)lp.ns[0] * lp.ns[1] * lp.ns[2];
+    const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
+    const bool cvalid = col < nbox * g.B;
+    const int64_t box = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
+    const int x = 2 * (lp.s0[0] + (int)(box % lp.ns[0])) + (oct & 1);
+    const int y = 2 * (lp.s0[1] + (int)((box / lp.ns[0]) % lp.ns[1])) + ((oct >> 1) & 1);
+    const int z = 2 * (lp.s0[2] + (int)(box / ((int64_t)lp.ns[0] * lp.ns[1]))) + ((oct >> 2) & 1);
+    const int64_t ci = cvalid ? dense_index(lv, x, y, z) : -1;
+    const double2 *bp = (const double2 *)(me + ((lp.me_off + box) * g.B + bm) * PS + kr * K4);
+    const double *Ao = A + (int64_t)oct * PS * PS;
+    vec4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    double ra[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        ra[i] = Ao[i * 256 + tid];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        sa[0][i * 256 + tid] = ra[i];
+    double2 b01 = cvalid ? bp[0] : double2{0.0, 0.0};
+    double2 b23 = cvalid ? bp[1] : double2{0.0, 0.0};
+    __syncthreads();
+    for (int j = 0; j < RB; ++j) {
+        const int buf = j & 1;
+        const bool more = j + 1 < RB;
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                ra[i] = Ao[(int64_t)(j + 1) * CH + i * 256 + tid];
+        }
+        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+        if (more) {
+            b01 = cvalid ? bp[2 * (j + 1)] : double2{0.0, 0.0};
+            b23 = cvalid ? bp[2 * (j + 1) + 1] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                                                             0);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                sa[buf ^ 1][i * 256 + tid] = ra[i];
+        }
+        __syncthreads();
+    }
+    if (ci < 0)
+        return;
+    const bool add = x >= cb.lo[0] && x <= cb.hi[0] && y >= cb.lo[1] && y <= cb.hi[1] && z >= cb.lo[2] &&
+                     z <= cb.hi[2];
+    double *dst = me + ((lv.me_off + ci) * g.B + bm) * PS;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double *o = dst + 16 * r + kr + 4 * i;
+            *o = add ? *o + acc[r][i] : acc[r][i];
+        }
+}
+
+// P2M^T: drho[cell] = sum_k Pm[v][k] ME_L[leaf][k] for the cells v of every
+// leaf of the source block (each mesh cell once), as FP64 MFMA: one wave
+// owns 16 (leaf, model) columns and four 16-cell row blocks (blockIdx.y
+// selects the blocks), K = the coefficients in the order (lane/16) PS/4 + ks.
+template <int RB>
+__global__ void __launch_bounds__(64)
+k_t_p2m(DevGeom g, const double *A, int RBT, const double *me, double *drho)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int K4 = PS / 4;
+    const int lane = threadIdx.x, kr = lane >> 4;
+    const DevLev &lv = g.lev[g.L];
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const bool cvalid = col < nleaf * g.B;
+    const int64_t leaf = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
+    const int rb0 = 4 * blockIdx.y;
+    const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + kr * K4);
+    vec4 acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    for (int q = 0; q < RB; ++q) {
+        const double2 b01 = cvalid ? bp[2 * q] : double2{0.0, 0.0};
+        const double2 b23 = cvalid ? bp[2 * q + 1] : double2{0.0, 0.0};
+        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double *ap = A + ((int64_t)(4 * q + u) * RBT + rb0) * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (rb0 + r < RBT)
+                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[r * 64], bv[u], acc[r], 0, 0, 0);
         }
     }
+    if (!cvalid)
+        return;
+    const int b = g.b, b3 = b * b * b;
+    const int lx = lv.s0[0] + (int)(leaf % lv.ns[0]), ly = lv.s0[1] + (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              lz = lv.s0[2] + (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
 #pragma unroll
-    for (int u = 0; u < MT; ++u) {
-        const int bm = grp * MT + u;
-        if (bm < g.B)
-            le[((lv.tgt_off + box) * g.B + bm) * g.PS + s] = acc[u];
-    }
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = 16 * (rb0 + r) + kr + 4 * i;
+            if (rb0 + r >= RBT || v >= b3)
+                continue;
+            const int ix = (lx - g.shift[0]) * b + v % b, iy = (ly - g.shift[1]) * b + (v / b) % b,
+                      iz = (lz - g.shift[2]) * b + v / (b * b);
+            if (ix < 0 || iy < 0 || iz < 0 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+                continue;
+            drho[(int64_t)bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix] = acc[r][i];
+        }
 }
 
 // M2L^T runs on the forward's stream-K M2L kernel (transposed operators,
@@ -245,75 +508,18 @@ k_m2lt_sum(const T *part, const int32_t *colmap, const int64_t *colbox, const in
     me[colbox[c] * PS + k] = acc;
 }
 
-// The column blocks of the transposed M2L: the boxes of level l whose ME it
-// writes (inclusive range); M2M^T adds to these and sets the others.
-struct ColBlock {
-    int lo[3], hi[3];
-};
-
-// M2M^T (downward over the source blocks): ME_l[child] += M2M_c^T
-// ME_l-1[parent], M2M row-major [octant][out i][in j], so the thread of
-// coefficient j reads column j.  One thread per (source box of level l,
-// model group, coefficient j).
-template <int MT>
-__global__ void __launch_bounds__(256) k_t_m2m(DevGeom g, int l, ColBlock cb, const double *m2m, double *me)
-{
-    const int NG = (g.B + MT - 1) / MT;
-    const DevLev &lv = g.lev[l];
-    const DevLev &lp = g.lev[l - 1];
-    const int64_t n_box = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_box * NG * g.PS)
-        return;
-    const int j = (int)(t % g.PS);
-    if (j >= g.P2)
-        return;  // padding stays zero (written by M2L^T)
-    const int64_t rest = t / g.PS;
-    const int grp = (int)(rest % NG);
-    const int64_t box = rest / NG;
-    const int x = lv.s0[0] + (int)(box % lv.ns[0]);
-    const int y = lv.s0[1] + (int)((box / lv.ns[0]) % lv.ns[1]);
-    const int z = lv.s0[2] + (int)(box / ((int64_t)lv.ns[0] * lv.ns[1]));
-    const int64_t par = dense_index(lp, x >> 1, y >> 1, z >> 1);
-    const int oct = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-    const double *col = m2m + (int64_t)oct * g.PS * g.PS + j;
-    const double *mp = me + ((lp.me_off + (par >= 0 ? par : 0)) * g.B + grp * MT) * g.PS;
-    double acc[MT];
-#pragma unroll
-    for (int u = 0; u < MT; ++u)
-        acc[u] = 0.0;
-    for (int i = 0; i < (par >= 0 ? g.P2 : 0); ++i) {
-        const double m = col[(int64_t)i * g.PS];
-#pragma unroll
-        for (int u = 0; u < MT; ++u)
-            if (grp * MT + u < g.B)
-                acc[u] += m * mp[(int64_t)u * g.PS + i];
-    }
-    // inside the column block the transposed M2L has written the ME
-    const bool add = x >= cb.lo[0] && x <= cb.hi[0] && y >= cb.lo[1] && y <= cb.hi[1] && z >= cb.lo[2] &&
-                     z <= cb.hi[2];
-#pragma unroll
-    for (int u = 0; u < MT; ++u) {
-        const int bm = grp * MT + u;
-        if (bm < g.B) {
-            double *o = me + ((lv.me_off + box) * g.B + bm) * g.PS + j;
-            *o = add ? *o + acc[u] : acc[u];
-        }
-    }
-}
-
-// P2M^T and the near-field transpose, per cell: drho[cell] = sum_k Pm[v][k]
-// ME_L[leaf][k] (v = the cell's place in its leaf), plus, over the targets j
-// of the 27 leaves around the cell's leaf (the forward near field pairs every
-// target of a leaf with every quadrature point of its 27 neighbours), the
-// weights times the pair terms (1/r, (t - x)/r^3) of each of the cell's
-// quadrature points, with the forward's coincidence rule and arithmetic type
-// T.  One thread per (cell, model group): the pair geometry is computed once
-// for the group's models.
+// The near-field transpose, per cell: drho[cell] = (with `far`, the P2M^T
+// term already in drho, else 0) plus, over the targets j of the 27 leaves
+// around the cell's leaf (the forward near field pairs every target of a
+// leaf with every quadrature point of its 27 neighbours), the weights times
+// the pair terms (1/r, (t - x)/r^3) of each of the cell's quadrature
+// points, with the forward's coincidence rule and arithmetic type T.  One
+// thread per (cell, model group): the pair geometry is computed once for the
+// group's models.
 template <typename T, int MT>
 __global__ void __launch_bounds__(256)
 k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, int64_t n_leaf, const int32_t *tmap,
-          int64_t n_tmap, const double *w, const double *me, const double *pm, double *drho)
+          int64_t n_tmap, const double *w, int far, double *drho)
 {
     const int NG = (g.B + MT - 1) / MT;
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -333,19 +539,13 @@ k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, int64_t n_le
 #pragma unroll
     for (int u = 0; u < MT; ++u)
         acc[u] = 0.0;
-    if (g.L >= 2) {
-        const int64_t sl = dense_index(lv, lx, ly, lz);
-        if (sl >= 0) {
-            const double *mp = me + ((lv.me_off + sl) * g.B + grp * MT) * g.PS;
-            const double *pr = pm + (int64_t)v * g.PS;
-            for (int k = 0; k < g.P2; ++k) {
-                const double pv = pr[k];
+    (void)v;
+    if (far) {
+        // the P2M^T term, written by k_t_p2m
 #pragma unroll
-                for (int u = 0; u < MT; ++u)
-                    if (grp * MT + u < g.B)
-                        acc[u] += pv * mp[(int64_t)u * g.PS + k];
-            }
-        }
+        for (int u = 0; u < MT; ++u)
+            if (grp * MT + u < g.B)
+                acc[u] = drho[(int64_t)(grp * MT + u) * ncell + cell];
     }
     // near field: quadrature points of this cell relative to its centre
     const T go = (T)(0.5 / 1.7320508075688772);
@@ -491,6 +691,68 @@ static grav_status enqueue_m2l_transposed(Plan *p, const DevGeom &g, hipStream_t
                                        : m2l_transposed_t<float>(p, g, s, p->d_kt32);
 }
 
+#define GRAV_T_RB_CASES(X) X(1) X(2) X(3) X(4) X(6) X(7) X(8) X(9) X(11) X(13) X(15) X(16)
+
+static grav_status launch_t_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
+{
+    const dim3 grid((unsigned)ceil_div(p->lev[l].n_tgt * p->B, 64));
+#define CASE(R)                                                                                            \
+    case R:                                                                                                \
+        hipLaunchKernelGGL((k_t_l2l<R>), grid, dim3(256), 0, s, g, l, (const uint32_t *)p->d_tkey,         \
+                           (const int32_t *)p->d_tchild, (const double *)p->d_l2lt_sw, p->d_le);           \
+        break;
+    switch (p->PS / 16) {
+        GRAV_T_RB_CASES(CASE)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+static grav_status launch_t_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
+{
+    const LevelInfo &lv = p->lev[l];
+    ColBlock cb;
+    for (int a = 0; a < 3; ++a) {
+        cb.lo[a] = lv.cs0[a];
+        cb.hi[a] = lv.cs0[a] + lv.cns[a] - 1;
+    }
+    const dim3 grid((unsigned)ceil_div(p->lev[l - 1].n_src * p->B, 64), 8);
+#define CASE(R)                                                                                             \
+    case R:                                                                                                 \
+        hipLaunchKernelGGL((k_t_m2m<R>), grid, dim3(256), 0, s, g, l, cb, (const double *)p->d_m2mt_sw, p->d_me); \
+        break;
+    switch (p->PS / 16) {
+        GRAV_T_RB_CASES(CASE)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+static grav_status launch_t_p2m(Plan *p, const DevGeom &g, double *drho, hipStream_t s)
+{
+    const int b3 = p->b * p->b * p->b, RBT = (b3 + 15) / 16;
+    const dim3 grid((unsigned)ceil_div(p->lev[p->L].n_src * p->B, 16), (unsigned)ceil_div(RBT, 4));
+#define CASE(R)                                                                                             \
+    case R:                                                                                                 \
+        hipLaunchKernelGGL((k_t_p2m<R>), grid, dim3(64), 0, s, g, (const double *)p->d_pmt_sw, RBT,         \
+                           (const double *)p->d_me, drho);                                                  \
+        break;
+    switch (p->PS / 16) {
+        GRAV_T_RB_CASES(CASE)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
 template <int MT>
 static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho, hipStream_t s)
 {
@@ -500,7 +762,7 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
     const int64_t NG = (p->B + MT - 1) / MT;
     const dim3 blk(256);
     auto grid = [](int64_t n) { return dim3((unsigned)ceil_div(n, 256)); };
-    if (ncell * NG > 0x7fffffffll * 256 || p->n_me > 0x7fffffffll)
+    if (ncell * NG > 0x7fffffffll * 256 || p->n_me > 0x7fffffffll || p->P2 > 256)
         return GRAV_EUNSUPPORTED;
     stage_begin(p, "weights", s);
     hipLaunchKernelGGL(k_t_weights, grid(p->M * p->B), blk, 0, s, g, resid, (const uint32_t *)p->d_perm,
@@ -509,49 +771,43 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
     stage_end(p, s);
     if (L >= 2) {
         stage_begin(p, "l2pT", s);
-        hipLaunchKernelGGL(k_t_l2p<MT>, grid(p->n_leaf * NG * p->PS), blk, 0, s, g, (const double *)p->d_tpos,
-                           (const int64_t *)p->d_leaf_start, (const uint32_t *)p->d_tkey, p->n_leaf,
-                           (const double *)p->d_near, p->d_le);
-        GRAV_HIP(hipGetLastError());
-        stage_end(p, s);
-        stage_begin(p, "l2lT", s);
-        for (int l = L - 1; l >= 2; --l) {
-            if (p->lev[l].n_tgt == 0)
-                continue;
-            hipLaunchKernelGGL(k_t_l2l<MT>, grid(p->lev[l].n_tgt * NG * p->PS), blk, 0, s, g, l,
-                               (const uint32_t *)p->d_tkey, (const int32_t *)p->d_tchild, (const double *)p->d_l2l,
-                               p->d_le);
+        if (p->n_leaf > 0) {
+            hipLaunchKernelGGL(k_t_l2p, dim3((unsigned)p->n_leaf), dim3(64), sizeof(double) * p->P2 * kL2PTChunk, s,
+                               g, (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
+                               (const uint32_t *)p->d_tkey, p->n_leaf, (const double *)p->d_near, p->d_le);
             GRAV_HIP(hipGetLastError());
         }
+        stage_end(p, s);
+        stage_begin(p, "l2lT", s);
+        for (int l = L - 1; l >= 2; --l)
+            if (p->lev[l].n_tgt > 0)
+                GRAV_CHECK(launch_t_l2l(p, g, l, s));
         stage_end(p, s);
         stage_begin(p, "m2lT", s);
         GRAV_CHECK(enqueue_m2l_transposed(p, g, s));
         stage_end(p, s);
         stage_begin(p, "m2mT", s);
-        for (int l = 3; l <= L; ++l) {
-            const LevelInfo &lv = p->lev[l];
-            ColBlock cb;
-            for (int a = 0; a < 3; ++a) {
-                cb.lo[a] = lv.cs0[a];
-                cb.hi[a] = lv.cs0[a] + lv.cns[a] - 1;
-            }
-            hipLaunchKernelGGL(k_t_m2m<MT>, grid(p->lev[l].n_src * NG * p->PS), blk, 0, s, g, l, cb,
-                               (const double *)p->d_m2m, p->d_me);
-            GRAV_HIP(hipGetLastError());
-        }
+        for (int l = 3; l <= L; ++l)
+            GRAV_CHECK(launch_t_m2m(p, g, l, s));
+        stage_end(p, s);
+        stage_begin(p, "p2mT", s);
+        GRAV_CHECK(launch_t_p2m(p, g, drho, s));
         stage_end(p, s);
     }
-    stage_begin(p, "cellsT", s);
-    if (p->d.precision == GRAV_FP64)
-        hipLaunchKernelGGL((k_t_cells<double, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
-                           (const int64_t *)p->d_leaf_start, p->n_leaf, (const int32_t *)p->d_tmap, p->n_tmap,
-                           (const double *)p->d_near, (const double *)p->d_me, (const double *)p->d_pm, drho);
-    else
-        hipLaunchKernelGGL((k_t_cells<float, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
-                           (const int64_t *)p->d_leaf_start, p->n_leaf, (const int32_t *)p->d_tmap, p->n_tmap,
-                           (const double *)p->d_near, (const double *)p->d_me, (const double *)p->d_pm, drho);
-    GRAV_HIP(hipGetLastError());
-    stage_end(p, s);
+    // the near field's transpose (with no far field it also sets drho)
+    if (p->p2p_pairs > 0 || L < 2) {
+        stage_begin(p, "nearT", s);
+        if (p->d.precision == GRAV_FP64)
+            hipLaunchKernelGGL((k_t_cells<double, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
+                               (const int64_t *)p->d_leaf_start, p->n_leaf, (const int32_t *)p->d_tmap, p->n_tmap,
+                               (const double *)p->d_near, L >= 2 ? 1 : 0, drho);
+        else
+            hipLaunchKernelGGL((k_t_cells<float, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
+                               (const int64_t *)p->d_leaf_start, p->n_leaf, (const int32_t *)p->d_tmap, p->n_tmap,
+                               (const double *)p->d_near, L >= 2 ? 1 : 0, drho);
+        GRAV_HIP(hipGetLastError());
+        stage_end(p, s);
+    }
     return GRAV_OK;
 }
 

@@ -289,7 +289,8 @@ void free_plan(Plan *p)
                     p->d_m2l_wgseg, p->d_m2l_tseg_start, p->d_m2l_tsegs, p->d_m2l_colmap,
                     p->d_cell_slot, p->d_leaf_pend, p->d_m2lt_tiles, p->d_m2lt_items, p->d_m2lt_segs,
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
-                    p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt};
+                    p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
+                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -484,6 +485,19 @@ grav_status build_operators(Plan *p)
                         psw[((size_t)kv * RB + rb) * 64 + lane] = pm[(size_t)v * PS + 16 * rb + lane % 16];
                 }
         GRAV_CHECK(upload(p, &p->d_pm_sw, psw));
+        // the adjoint's P2M^T: rows = the leaf's cells (RBT blocks of 16),
+        // contraction over the coefficients in the order (lane/16) PS/4 + ks;
+        // [ks][rbt][lane] = pm[16 rbt + lane%16][(lane/16) PS/4 + ks]
+        const int RBT = (b3 + 15) / 16, K4 = PS / 4;
+        std::vector<double> pmt((size_t)K4 * RBT * 64, 0.0);
+        for (int ks = 0; ks < K4; ++ks)
+            for (int rb = 0; rb < RBT; ++rb)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int v = 16 * rb + lane % 16;
+                    if (v < b3)
+                        pmt[((size_t)ks * RBT + rb) * 64 + lane] = pm[(size_t)v * PS + (lane / 16) * K4 + ks];
+                }
+        GRAV_CHECK(upload(p, &p->d_pmt_sw, pmt));
     }
     if (p->L < 2)
         return GRAV_OK;
@@ -525,6 +539,20 @@ grav_status build_operators(Plan *p)
         }
         GRAV_CHECK(upload(p, &p->d_m2m_sw, msw));
         GRAV_CHECK(upload(p, &p->d_l2l_sw, lsw));
+        // the adjoint's M2M^T and L2L^T in the M2M fragment layout: row =
+        // output coefficient of the transpose (a column of the matrix),
+        // contraction index (lane/16) PS/4 + ks (a row of the matrix)
+        std::vector<double> mtsw(8 * per8), ltsw(8 * per8);
+        for (int c = 0; c < 8; ++c)
+            for (int ks = 0; ks < K4; ++ks)
+                for (int rb = 0; rb < RB; ++rb)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const size_t src = per8 * c + (size_t)((lane / 16) * K4 + ks) * PS + 16 * rb + lane % 16;
+                        mtsw[per8 * c + ((size_t)ks * RB + rb) * 64 + lane] = m2m[src];
+                        ltsw[per8 * c + ((size_t)ks * RB + rb) * 64 + lane] = l2l[src];
+                    }
+        GRAV_CHECK(upload(p, &p->d_m2mt_sw, mtsw));
+        GRAV_CHECK(upload(p, &p->d_l2lt_sw, ltsw));
     }
 
     // M2L for all 316 offsets, swizzled for the MFMA A operand, and their transposes
