@@ -136,8 +136,9 @@ __device__ inline void l2p_transposed(int P, double x, double y, double z, doubl
     }
 }
 
-// L2P^T: the adjoint LE of a leaf is the sum over its targets of the
-// transposed evaluation with the target's weights, scaled as the combine
+// L2P^T: the adjoint LE of a leaf is the sum over its targets (with `pend`,
+// its user points only) of the transposed evaluation with the target's
+// weights, scaled as the combine
 // scales the far field (phi / w, -grad phi / w^2).  One wave per target
 // leaf; per model, the leaf's targets in chunks of 31: each of the first 31
 // lanes writes its target's p^2 terms into its own LDS column, then every
@@ -146,8 +147,8 @@ __device__ inline void l2p_transposed(int P, double x, double y, double z, doubl
 // spreads the lanes of the second phase over the LDS banks.
 constexpr int kL2PTChunk = 31;
 __global__ void __launch_bounds__(64)
-k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const uint32_t *tkey, int64_t n_leaf,
-        const double *w, double *le)
+k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const int64_t *pend, const uint32_t *tkey,
+        int64_t n_leaf, const double *w, double *le)
 {
     extern __shared__ double cols[];  // [p^2][kL2PTChunk]
     const int64_t leaf = blockIdx.x;
@@ -159,7 +160,8 @@ k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const uint32_t
     for (int a = 0; a < 3; ++a)
         centre[a] = ((double)(lc[a] - g.shift[a]) + 0.5) * g.b;
     const double inv_w = 1.0 / (double)g.b, inv_w2 = inv_w * inv_w;
-    const int64_t ts = max(leaf_start[leaf], (int64_t)0), te = min(leaf_start[leaf + 1], g.M);
+    const int64_t ts = max(leaf_start[leaf], (int64_t)0);
+    const int64_t te = min(pend ? pend[leaf] : leaf_start[leaf + 1], g.M);  // pend: the user points only
     for (int bm = 0; bm < g.B; ++bm) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};  // coefficients lane + 64 i (p^2 <= 256)
         for (int64_t j0 = ts; j0 < te; j0 += kL2PTChunk) {
@@ -508,8 +510,9 @@ k_m2lt_sum(const T *part, const int32_t *colmap, const int64_t *colbox, const in
     me[colbox[c] * PS + k] = acc;
 }
 
-// The near-field transpose, per cell: drho[cell] = (with `far`, the P2M^T
-// term already in drho, else 0) plus, over the targets j of the 27 leaves
+// The near-field transpose, per cell: drho[cell] = (with `prior`, the terms
+// already in drho, else 0) plus, over the targets j (with `pend`, the user
+// points only: the lattice kernel takes the cell centres) of the 27 leaves
 // around the cell's leaf (the forward near field pairs every target of a
 // leaf with every quadrature point of its 27 neighbours), the weights times
 // the pair terms (1/r, (t - x)/r^3) of each of the cell's quadrature
@@ -518,8 +521,8 @@ k_m2lt_sum(const T *part, const int32_t *colmap, const int64_t *colbox, const in
 // group's models.
 template <typename T, int MT>
 __global__ void __launch_bounds__(256)
-k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, int64_t n_leaf, const int32_t *tmap,
-          int64_t n_tmap, const double *w, int far, double *drho)
+k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, const int64_t *pend, int64_t n_leaf,
+          const int32_t *tmap, int64_t n_tmap, const double *w, int prior, double *drho)
 {
     const int NG = (g.B + MT - 1) / MT;
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -540,8 +543,8 @@ k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, int64_t n_le
     for (int u = 0; u < MT; ++u)
         acc[u] = 0.0;
     (void)v;
-    if (far) {
-        // the P2M^T term, written by k_t_p2m
+    if (prior) {
+        // the terms already in drho (P2M^T, the lattice near field)
 #pragma unroll
         for (int u = 0; u < MT; ++u)
             if (grp * MT + u < g.B)
@@ -565,7 +568,8 @@ k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, int64_t n_le
         // forward near field forms them, and the cell centre in that frame
         const int cx = (tx - g.shift[0]) * b, cy = (ty - g.shift[1]) * b, cz = (tz - g.shift[2]) * b;
         const T sx = (T)(ix - cx) + (T)0.5, sy = (T)(iy - cy) + (T)0.5, sz = (T)(iz - cz) + (T)0.5;
-        const int64_t ts = max(leaf_start[tl], (int64_t)0), te = min(leaf_start[tl + 1], g.M);
+        const int64_t ts = max(leaf_start[tl], (int64_t)0);
+        const int64_t te = min(pend ? pend[tl] : leaf_start[tl + 1], g.M);
         T part[MT];
 #pragma unroll
         for (int u = 0; u < MT; ++u)
@@ -691,6 +695,176 @@ static grav_status enqueue_m2l_transposed(Plan *p, const DevGeom &g, hipStream_t
                                        : m2l_transposed_t<float>(p, g, s, p->d_kt32);
 }
 
+// The lattice transposes for voxel-centre targets (see k_near_lat): with w_T
+// the combine^T weights of target leaf T's b^3 cell centres (4 per centre),
+//   drho[S] (+)= sum over the 27 neighbours d of A_d^T w_{S - d}   (near^T)
+//   LE[T]   (+)= Lm^T w_T                                          (L2P^T)
+// GEMMs with columns = (leaf, model) and contraction over (centre t,
+// component) of the target leaf: chunk q and k step u take t = (lane/16) TQ
+// + q and component u, so a lane's four k steps are the four weights of one
+// centre (one 32-byte load from the weights, found through the centre's
+// sorted slot).  Centres outside the mesh or past b^3 read zero.
+__device__ __forceinline__ void lattice_weights(const DevGeom &g, const int32_t *cell_slot, const double *w, int tx,
+                                                int ty, int tz, int t, int bm, bool in, double (&v)[4])
+{
+    const int b = g.b;
+    v[0] = v[1] = v[2] = v[3] = 0.0;
+    if (!in || t >= b * b * b)
+        return;
+    const int ix = tx * b + t % b, iy = ty * b + (t / b) % b, iz = tz * b + t / (b * b);
+    if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+        return;
+    const int64_t slot = cell_slot[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+    if (slot < 0 || slot >= g.M)
+        return;
+    const double4 x = *(const double4 *)(w + (slot * g.B + bm) * 4);
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+}
+
+// near^T: one wave owns CW blocks of 16 (source leaf, model) columns and
+// four 16-cell row blocks (blockIdx.y), in the near field's element type.
+template <int CW, typename T>
+__global__ void __launch_bounds__(64)
+k_t_near_lat(DevGeom g, const T *A, int RBt, int TQ, const int32_t *cell_slot, const double *w, int add,
+             double *drho)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
+    const int lane = threadIdx.x, kr = lane >> 4;
+    const DevLev &lv = g.lev[g.L];
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int b = g.b, b3 = b * b * b;
+    const int rb0 = 4 * blockIdx.y;
+    bool cvalid[CW];
+    int bm[CW], sx[CW], sy[CW], sz[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+        const int64_t col = ((int64_t)blockIdx.x * CW + c) * 16 + (lane & 15);
+        cvalid[c] = col < nleaf * g.B;
+        const int64_t leaf = cvalid[c] ? col / g.B : 0;
+        bm[c] = cvalid[c] ? (int)(col % g.B) : 0;
+        sx[c] = (int)(leaf % lv.ns[0]);
+        sy[c] = (int)((leaf / lv.ns[0]) % lv.ns[1]);
+        sz[c] = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    }
+    vec4 acc[CW][4];
+#pragma unroll
+    for (int c = 0; c < CW; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[c][r] = vec4{0, 0, 0, 0};
+    for (int nb = 0; nb < 27; ++nb) {
+        // the forward pairs target leaf T with source leaf T + d: here T = S - d
+        const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
+        bool tin[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+            tin[c] = cvalid[c] && sx[c] - dx >= 0 && sy[c] - dy >= 0 && sz[c] - dz >= 0 && sx[c] - dx < lv.ns[0] &&
+                     sy[c] - dy < lv.ns[1] && sz[c] - dz < lv.ns[2];
+        for (int q = 0; q < TQ; ++q) {
+            T bv[CW][4];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                double v[4];
+                lattice_weights(g, cell_slot, w, sx[c] - dx, sy[c] - dy, sz[c] - dz, kr * TQ + q, bm[c], tin[c], v);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    bv[c][u] = (T)v[u];
+            }
+            T av[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                load_frags<T, 4>(A + (((int64_t)nb * TQ + q) * RBt + min(rb0 + r, RBt - 1)) * 256, lane, av[r]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) {
+                        if constexpr (sizeof(T) == 8)
+                            acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][u], bv[c][u], acc[c][r], 0, 0, 0);
+                        else
+                            acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][u], bv[c][u], acc[c][r], 0, 0, 0);
+                    }
+        }
+    }
+    // output rows: FP32 instruction rows 4 (lane/16) + i, FP64 rows lane/16 + 4 i
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+        if (!cvalid[c])
+            continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (rb0 + r >= RBt)
+                continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = 16 * (rb0 + r) + (sizeof(T) == 8 ? kr + 4 * i : 4 * kr + i);
+                if (v >= b3)
+                    continue;
+                const int ix = sx[c] * b + v % b, iy = sy[c] * b + (v / b) % b, iz = sz[c] * b + v / (b * b);
+                if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+                    continue;
+                double *o = drho + (int64_t)bm[c] * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
+                *o = add ? *o + (double)acc[c][r][i] : (double)acc[c][r][i];
+            }
+        }
+    }
+}
+
+// L2P^T at the cell centres (FP64): one wave owns 16 (leaf, model) columns
+// and all RB coefficient blocks; the column's target leaf is found in the
+// leaf level's target map.
+template <int RB>
+__global__ void __launch_bounds__(64)
+k_t_l2p_lat(DevGeom g, const double *A, int TQ, const int32_t *tmap, const int32_t *cell_slot, const double *w,
+            int add, double *le)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    const int lane = threadIdx.x, kr = lane >> 4;
+    const DevLev &lv = g.lev[g.L];
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
+    const bool cvalid = col < nleaf * g.B;
+    const int64_t leaf = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
+    const int sx = (int)(leaf % lv.ns[0]), sy = (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              sz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    const int64_t tl =
+        cvalid ? tmap_lookup(lv, tmap, 3, lv.s0[0] + sx, lv.s0[1] + sy, lv.s0[2] + sz) : -1;
+    vec4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    for (int q = 0; q < TQ; ++q) {
+        double bv[4];
+        lattice_weights(g, cell_slot, w, sx, sy, sz, kr * TQ + q, bm, tl >= 0, bv);
+        double av[RB][4];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            load_frags<double, 4>(A + ((int64_t)q * RB + r) * 256, lane, av[r]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][u], bv[u], acc[r], 0, 0, 0);
+    }
+    if (tl < 0 || tl >= lv.n_tgt)
+        return;
+    double *dst = le + ((lv.tgt_off + tl) * g.B + bm) * PS;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double *o = dst + 16 * r + kr + 4 * i;
+            *o = add ? *o + acc[r][i] : acc[r][i];
+        }
+}
+
 #define GRAV_T_RB_CASES(X) X(1) X(2) X(3) X(4) X(6) X(7) X(8) X(9) X(11) X(13) X(15) X(16)
 
 static grav_status launch_t_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
@@ -753,6 +927,40 @@ static grav_status launch_t_p2m(Plan *p, const DevGeom &g, double *drho, hipStre
     return GRAV_OK;
 }
 
+static grav_status launch_t_l2p_lat(Plan *p, const DevGeom &g, int add, hipStream_t s)
+{
+    const dim3 grid((unsigned)ceil_div(p->lev[p->L].n_src * p->B, 16));
+#define CASE(R)                                                                                             \
+    case R:                                                                                                 \
+        hipLaunchKernelGGL((k_t_l2p_lat<R>), grid, dim3(64), 0, s, g, (const double *)p->d_tl2pt, p->lat_TQ, \
+                           (const int32_t *)p->d_tmap, (const int32_t *)p->d_cell_slot, (const double *)p->d_near, \
+                           add, p->d_le);                                                                   \
+        break;
+    switch (p->PS / 16) {
+        GRAV_T_RB_CASES(CASE)
+    default:
+        return GRAV_EUNSUPPORTED;
+    }
+#undef CASE
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
+static grav_status launch_t_near_lat(Plan *p, const DevGeom &g, int add, double *drho, hipStream_t s)
+{
+    constexpr int CW = 2;
+    const int b3 = p->b * p->b * p->b, RBt = (int)ceil_div(b3, 16);
+    const dim3 grid((unsigned)ceil_div(p->lev[p->L].n_src * p->B, 16 * CW), (unsigned)ceil_div(RBt, 4));
+    if (p->d.precision == GRAV_FP64)
+        hipLaunchKernelGGL((k_t_near_lat<CW, double>), grid, dim3(64), 0, s, g, (const double *)p->d_tnt64, RBt,
+                           p->lat_TQ, (const int32_t *)p->d_cell_slot, (const double *)p->d_near, add, drho);
+    else
+        hipLaunchKernelGGL((k_t_near_lat<CW, float>), grid, dim3(64), 0, s, g, (const float *)p->d_tnt32, RBt,
+                           p->lat_TQ, (const int32_t *)p->d_cell_slot, (const double *)p->d_near, add, drho);
+    GRAV_HIP(hipGetLastError());
+    return GRAV_OK;
+}
+
 template <int MT>
 static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho, hipStream_t s)
 {
@@ -771,12 +979,18 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
     stage_end(p, s);
     if (L >= 2) {
         stage_begin(p, "l2pT", s);
-        if (p->n_leaf > 0) {
+        // user points by the transposed recurrence; cell centres of lattice
+        // plans by the transposed lattice L2P
+        const bool pts = !p->lat_near || p->d.n_points > 0;
+        if (p->n_leaf > 0 && pts) {
             hipLaunchKernelGGL(k_t_l2p, dim3((unsigned)p->n_leaf), dim3(64), sizeof(double) * p->P2 * kL2PTChunk, s,
                                g, (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
-                               (const uint32_t *)p->d_tkey, p->n_leaf, (const double *)p->d_near, p->d_le);
+                               p->lat_near ? (const int64_t *)p->d_leaf_pend : nullptr, (const uint32_t *)p->d_tkey,
+                               p->n_leaf, (const double *)p->d_near, p->d_le);
             GRAV_HIP(hipGetLastError());
         }
+        if (p->lat_near)
+            GRAV_CHECK(launch_t_l2p_lat(p, g, pts ? 1 : 0, s));
         stage_end(p, s);
         stage_begin(p, "l2lT", s);
         for (int l = L - 1; l >= 2; --l)
@@ -794,17 +1008,27 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
         GRAV_CHECK(launch_t_p2m(p, g, drho, s));
         stage_end(p, s);
     }
-    // the near field's transpose (with no far field it also sets drho)
-    if (p->p2p_pairs > 0 || L < 2) {
+    // the near field's transpose (with no far field it also sets drho):
+    // cell centres of lattice plans on MFMA, user points (or all targets of
+    // other plans) pair by pair
+    if (p->lat_near) {
         stage_begin(p, "nearT", s);
+        GRAV_CHECK(launch_t_near_lat(p, g, L >= 2 ? 1 : 0, drho, s));
+        stage_end(p, s);
+    }
+    const bool pts = p->lat_near ? p->d.n_points > 0 : (p->p2p_pairs > 0 || L < 2);
+    if (pts) {
+        const int prior = (L >= 2 || p->lat_near) ? 1 : 0;
+        const int64_t *pend = p->lat_near ? (const int64_t *)p->d_leaf_pend : nullptr;
+        stage_begin(p, "nearT_pts", s);
         if (p->d.precision == GRAV_FP64)
             hipLaunchKernelGGL((k_t_cells<double, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
-                               (const int64_t *)p->d_leaf_start, p->n_leaf, (const int32_t *)p->d_tmap, p->n_tmap,
-                               (const double *)p->d_near, L >= 2 ? 1 : 0, drho);
+                               (const int64_t *)p->d_leaf_start, pend, p->n_leaf, (const int32_t *)p->d_tmap,
+                               p->n_tmap, (const double *)p->d_near, prior, drho);
         else
             hipLaunchKernelGGL((k_t_cells<float, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
-                               (const int64_t *)p->d_leaf_start, p->n_leaf, (const int32_t *)p->d_tmap, p->n_tmap,
-                               (const double *)p->d_near, L >= 2 ? 1 : 0, drho);
+                               (const int64_t *)p->d_leaf_start, pend, p->n_leaf, (const int32_t *)p->d_tmap,
+                               p->n_tmap, (const double *)p->d_near, prior, drho);
         GRAV_HIP(hipGetLastError());
         stage_end(p, s);
     }

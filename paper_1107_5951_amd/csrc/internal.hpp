@@ -153,6 +153,10 @@ struct Plan {
     double *d_pmt_sw = nullptr;                    // [PS/4][ceil(b^3/16)][64] P2M^T fragments (adjoint)
     double *d_tn64 = nullptr;                      // [27][KS][RB][64] swizzled, FP64 plans
     float *d_tn32 = nullptr;                       // same, mixed plans
+    int lat_TQ = 0;                                // adjoint: chunks of the (target, component) contraction
+    double *d_tnt64 = nullptr;                     // [27][TQ][ceil(b^3/16)][64][4] transposed near field, FP64
+    float *d_tnt32 = nullptr;                      // same, mixed plans
+    double *d_tl2pt = nullptr;                     // [TQ][PS/16][64][4] transposed lattice L2P (FP64)
     int32_t *d_cell_slot = nullptr;                // [ncell] sorted slot of each voxel centre
     hipStream_t bs = nullptr;                      // plan-build stream (non-blocking), only inside grav_plan
     int direct_chunks = 1;                         // source chunks of grav_direct

@@ -290,7 +290,7 @@ void free_plan(Plan *p)
                     p->d_cell_slot, p->d_leaf_pend, p->d_m2lt_tiles, p->d_m2lt_items, p->d_m2lt_segs,
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
                     p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
-                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw};
+                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -1144,6 +1144,31 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
         std::vector<float> sw32(sw.begin(), sw.end());
         GRAV_CHECK(upload(p, &p->d_tn32, sw32));
     }
+    // the adjoint's transposes: rows = the cells of the source leaf (RBt
+    // blocks of 16), contraction over (target t, component) of the target
+    // leaf, chunk q and k step u taking t = (lane/16) TQ + q, component u;
+    // [nb][q][rb][lane][u] group-major sets
+    const int TQ = (int)ceil_div(b3, 4), RBt = (int)ceil_div(b3, 16);
+    p->lat_TQ = TQ;
+    {
+        std::vector<double> swt((size_t)27 * TQ * RBt * 256, 0.0);
+        for (int nb = 0; nb < 27; ++nb)
+            for (int q = 0; q < TQ; ++q)
+                for (int rb = 0; rb < RBt; ++rb)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int u = 0; u < 4; ++u) {
+                            const int t = (lane >> 4) * TQ + q, cell = 16 * rb + (lane & 15);
+                            const double v =
+                                t < b3 && cell < b3 ? dense[((size_t)nb * 4 * b3 + 4 * t + u) * b3 + cell] : 0.0;
+                            swt[(((size_t)nb * TQ + q) * RBt + rb) * 256 + frag_pos(lane, u, f64 ? 2 : 4)] = v;
+                        }
+        if (f64) {
+            GRAV_CHECK(upload(p, &p->d_tnt64, swt));
+        } else {
+            std::vector<float> swt32(swt.begin(), swt.end());
+            GRAV_CHECK(upload(p, &p->d_tnt32, swt32));
+        }
+    }
     if (p->L >= 2) {
         // Far field at the cell centres from the leaf's local expansion, with
         // the scaling of the combine folded in (phi / w, -grad phi / w^2), as
@@ -1177,6 +1202,18 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
                             t < b3 ? full[(size_t)(4 * t + comp) * PS + c] : 0.0;
                     }
         GRAV_CHECK(upload(p, &p->d_tl2p, lsw));
+        // its transpose for the adjoint: rows = coefficients (QL blocks),
+        // contraction over (t, component) as the transposed near field
+        std::vector<double> lst((size_t)TQ * QL * 256, 0.0);
+        for (int q = 0; q < TQ; ++q)
+            for (int rb = 0; rb < QL; ++rb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int u = 0; u < 4; ++u) {
+                        const int t = (lane >> 4) * TQ + q, c = 16 * rb + (lane & 15);
+                        lst[((size_t)q * QL + rb) * 256 + frag_pos(lane, u, 2)] =
+                            t < b3 ? full[(size_t)(4 * t + u) * PS + c] : 0.0;
+                    }
+        GRAV_CHECK(upload(p, &p->d_tl2pt, lst));
     }
     GRAV_HIP(hipStreamSynchronize(s));
     return GRAV_OK;
