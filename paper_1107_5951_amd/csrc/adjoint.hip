@@ -69,19 +69,17 @@ k_t_weights(DevGeom g, const double *resid, const uint32_t *perm, double *w)
 // group), so that every operator entry or pair geometry it loads serves MT
 // models; groups are ceil(B / MT).
 
-// Transposed local-expansion evaluation: adds to col[k * CS] (k < p^2) the
-// derivative of a phi - (b1 gx + b2 gy + b3 gz) with respect to coefficient
-// k, where (phi, gx, gy, gz) is the local-expansion evaluation at u (box
-// widths from the box centre, see l2p_eval).  The same recurrences for the
-// regular harmonics R_n^m; each term c R of the evaluation adds its factor
-// R to the coefficient c it multiplies (the gradient pairs R_n^m with the
-// degree n+1 coefficients of orders m-1, m, m+1; order 0 has no imaginary
-// part).
-__device__ inline void l2p_transposed(int P, double x, double y, double z, double a, double b1, double b2, double b3,
-                                      double *col, int CS)
+// Real index of the regular harmonic / coefficient (n, m): the real part
+// (order 0, or part 0 of order m > 0) or the imaginary part (part 1).
+__device__ __forceinline__ int harm_index(int n, int m, int part)
 {
-    auto RE = [&](int n, int m) -> double & { return col[(m == 0 ? n * n : n * n + 2 * m - 1) * CS]; };
-    auto IM = [&](int n, int m) -> double & { return col[(n * n + 2 * m) * CS]; };
+    return m == 0 ? n * n : n * n + 2 * m - 1 + part;
+}
+
+// The regular solid harmonics R_n^m(u), n < P, in the coefficients' real
+// order (the recurrences of l2p_eval), written to h[k * CS].
+__device__ inline void regular_harmonics(int P, double x, double y, double z, double *h, int CS)
+{
     const double r2 = x * x + y * y + z * z;
     double mmr = 1.0, mmi = 0.0;
     for (int m = 0; m < P; ++m) {
@@ -110,49 +108,80 @@ __device__ inline void l2p_transposed(int P, double x, double y, double z, doubl
             p2i = p1i;
             p1r = Rr;
             p1i = Ri;
-            if (m == 0) {
-                RE(n, 0) += a * Rr;
-            } else {
-                RE(n, m) += 2.0 * a * Rr;
-                IM(n, m) -= 2.0 * a * Ri;
-            }
-            if (n + 1 < P) {
-                const int n1 = n + 1;
-                if (m == 0) {
-                    RE(n1, 0) -= b3 * Rr;
-                    RE(n1, 1) -= b1 * Rr;
-                    IM(n1, 1) += b2 * Rr;
-                } else {
-                    RE(n1, m) -= 2.0 * b3 * Rr;
-                    IM(n1, m) += 2.0 * b3 * Ri;
-                    RE(n1, m + 1) += b2 * Ri - b1 * Rr;
-                    RE(n1, m - 1) += b1 * Rr + b2 * Ri;
-                    IM(n1, m + 1) += b1 * Ri + b2 * Rr;
-                    if (m > 1)
-                        IM(n1, m - 1) += b2 * Rr - b1 * Ri;
-                }
-            }
+            h[harm_index(n, m, 0) * CS] = Rr;
+            if (m > 0)
+                h[harm_index(n, m, 1) * CS] = Ri;
         }
     }
 }
 
-// L2P^T: the adjoint LE of a leaf is the sum over its targets (with `pend`,
-// its user points only) of the transposed evaluation with the target's
-// weights, scaled as the combine
-// scales the far field (phi / w, -grad phi / w^2).  One wave per target
-// leaf; per model, the leaf's targets in chunks of 31: each of the first 31
-// lanes writes its target's p^2 terms into its own LDS column, then every
-// lane adds the columns of its coefficients (k = lane + 64 i) in target
-// order, so the sums are deterministic.  The odd row stride (31 doubles)
-// spreads the lanes of the second phase over the LDS banks.
-constexpr int kL2PTChunk = 31;
-__global__ void __launch_bounds__(64)
+// L2P^T: the adjoint LE of a leaf is the derivative, with respect to its
+// coefficients, of the sum over the leaf's targets (with `pend`, its user
+// points only) of a phi - (b1 gx + b2 gy + b3 gz), with (a, b) the target's
+// weights scaled as the combine scales the far field (a = w0 / w, b = w_1..3
+// / w^2).  That derivative is linear in the weights: with the sums
+//   S_c[h] = sum over targets of (a, b1, b2, b3)_c R_h(target)
+// of the regular harmonics, coefficient (n, m) collects a R_n^m (x2 for
+// m > 0) and the gradient terms of degree n-1 and orders m-1, m, m+1, as
+// the evaluation pairs them (d/dz R_n^m = R_{n-1}^m, d/dx and d/dy from
+// R_{n-1}^{m-1} and R_{n-1}^{m+1}).  One workgroup per (target leaf, group
+// of MG models: 1 for single-model plans, else kL2PTModels); targets in
+// chunks of kL2PTChunk: their harmonics
+// and weights go to LDS, and every thread adds, in target order, the
+// products of the (c, model, h) sums it owns (deterministic).
+constexpr int kL2PTChunk = 24, kL2PTModels = 4;
+
+template <int MG>
+__device__ __forceinline__ double l2pt_gather(const double *S, int P2, int mg, int n, int m, int part)
+{
+    auto h = [&](int c, int nn, int mm, int pp) -> double {
+        if (nn < 0 || mm > nn || (mm == 0 && pp == 1))
+            return 0.0;
+        return S[(c * MG + mg) * P2 + harm_index(nn, mm, pp)];
+    };
+    const int q = n - 1;  // degree of the gradient terms
+    double v;
+    if (part == 0) {
+        v = (m == 0 ? 1.0 : 2.0) * h(0, n, m, 0);
+        if (q >= 0) {
+            if (m == 0) {
+                v += -h(3, q, 0, 0) + h(1, q, 1, 0) + h(2, q, 1, 1);
+            } else {
+                v += -2.0 * h(3, q, m, 0);
+                if (m == 1)
+                    v -= h(1, q, 0, 0);
+                else
+                    v += h(2, q, m - 1, 1) - h(1, q, m - 1, 0);
+                v += h(1, q, m + 1, 0) + h(2, q, m + 1, 1);
+            }
+        }
+    } else {
+        v = -2.0 * h(0, n, m, 1);
+        if (q >= 0) {
+            v += 2.0 * h(3, q, m, 1);
+            if (m == 1)
+                v += h(2, q, 0, 0);
+            else
+                v += h(1, q, m - 1, 1) + h(2, q, m - 1, 0);
+            v += h(2, q, m + 1, 0) - h(1, q, m + 1, 1);
+        }
+    }
+    return v;
+}
+
+template <int MG>
+__global__ void __launch_bounds__(256)
 k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const int64_t *pend, const uint32_t *tkey,
         int64_t n_leaf, const double *w, double *le)
 {
-    extern __shared__ double cols[];  // [p^2][kL2PTChunk]
+    extern __shared__ double sh[];
+    constexpr int TC = kL2PTChunk;
+    const int P2 = g.P2;
+    double *H = sh;             // [TC][P2] harmonics of the chunk's targets
+    double *W = sh + TC * P2;   // [TC][MG][4] their scaled weights
     const int64_t leaf = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int bm0 = blockIdx.y * MG;
+    const int tid = threadIdx.x;
     const DevLev &lv = g.lev[g.L];
     const uint32_t key = tkey[lv.tbox_off + leaf];
     const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
@@ -161,38 +190,62 @@ k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const int64_t 
         centre[a] = ((double)(lc[a] - g.shift[a]) + 0.5) * g.b;
     const double inv_w = 1.0 / (double)g.b, inv_w2 = inv_w * inv_w;
     const int64_t ts = max(leaf_start[leaf], (int64_t)0);
-    const int64_t te = min(pend ? pend[leaf] : leaf_start[leaf + 1], g.M);  // pend: the user points only
-    for (int bm = 0; bm < g.B; ++bm) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};  // coefficients lane + 64 i (p^2 <= 256)
-        for (int64_t j0 = ts; j0 < te; j0 += kL2PTChunk) {
-            const int nt = (int)min((int64_t)kL2PTChunk, te - j0);
-            for (int i = lane; i < g.P2 * kL2PTChunk; i += 64)
-                cols[i] = 0.0;
-            __syncthreads();
-            if (lane < nt) {
-                const int64_t j = j0 + lane;
-                const double *wj = w + (j * g.B + bm) * 4;
-                l2p_transposed(g.P, (tpos[3 * j + 0] - centre[0]) * inv_w, (tpos[3 * j + 1] - centre[1]) * inv_w,
-                               (tpos[3 * j + 2] - centre[2]) * inv_w, wj[0] * inv_w, wj[1] * inv_w2, wj[2] * inv_w2,
-                               wj[3] * inv_w2, cols + lane, kL2PTChunk);
-            }
-            __syncthreads();
+    const int64_t te = min(pend ? pend[leaf] : leaf_start[leaf + 1], g.M);
+    const int NO = 4 * MG * P2;  // sums (c, model, h), output o = (c MG + mg) P2 + h
+    constexpr int NJ = 4 * MG * 256 / 256;  // sums per thread (p^2 <= 256)
+    double acc[NJ];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = lane + 64 * i;
-                if (k < g.P2)
-                    for (int t = 0; t < nt; ++t)
-                        acc[i] += cols[k * kL2PTChunk + t];
-            }
-            __syncthreads();
+    for (int j = 0; j < NJ; ++j)
+        acc[j] = 0.0;
+    for (int64_t j0 = ts; j0 < te; j0 += TC) {
+        const int nt = (int)min((int64_t)TC, te - j0);
+        if (tid < nt) {
+            const int64_t j = j0 + tid;
+            regular_harmonics(g.P, (tpos[3 * j + 0] - centre[0]) * inv_w, (tpos[3 * j + 1] - centre[1]) * inv_w,
+                              (tpos[3 * j + 2] - centre[2]) * inv_w, H + tid * P2, 1);
         }
-        double *dst = le + ((lv.tgt_off + leaf) * g.B + bm) * g.PS;
+        for (int i = tid; i < nt * MG * 4; i += 256) {
+            const int t = i / (MG * 4), mg = (i / 4) % MG, c = i % 4;
+            const int bm = bm0 + mg;
+            W[i] = bm < g.B ? w[((j0 + t) * g.B + bm) * 4 + c] * (c == 0 ? inv_w : inv_w2) : 0.0;
+        }
+        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = lane + 64 * i;
-            if (k < g.PS)
-                dst[k] = k < g.P2 ? acc[i] : 0.0;  // padding coefficients stay zero
+        for (int j = 0; j < NJ; ++j) {
+            const int o = tid + 256 * j;
+            if (o < NO) {
+                const int h = o % P2, cm = o / P2;  // cm = c MG + mg
+                const int c = cm / MG, mg = cm % MG;
+                double v = acc[j];
+                for (int t = 0; t < nt; ++t)
+                    v += H[t * P2 + h] * W[(t * MG + mg) * 4 + c];
+                acc[j] = v;
+            }
         }
+        __syncthreads();
+    }
+    double *S = sh;  // [4][MG][P2]
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int o = tid + 256 * j;
+        if (o < NO)
+            S[o] = acc[j];
+    }
+    __syncthreads();
+    for (int i = tid; i < MG * g.PS; i += 256) {
+        const int mg = i / g.PS, k = i % g.PS;
+        const int bm = bm0 + mg;
+        if (bm >= g.B)
+            continue;
+        double v = 0.0;  // padding coefficients stay zero
+        if (k < P2) {
+            int n = 0;
+            while ((n + 1) * (n + 1) <= k)
+                ++n;
+            const int r = k - n * n;
+            v = l2pt_gather<MG>(S, P2, mg, n, (r + 1) / 2, (r > 0 && (r & 1) == 0) ? 1 : 0);
+        }
+        le[((lv.tgt_off + leaf) * g.B + bm) * g.PS + k] = v;
     }
 }
 
@@ -389,10 +442,12 @@ k_t_p2m(DevGeom g, const double *A, int RBT, const double *me, double *drho)
     const int lane = threadIdx.x, kr = lane >> 4;
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    // columns leaf-fastest: a row of the output fragment is 16 neighbouring
+    // leaves of one model, so the stores of x-runs of cells coalesce
     const int64_t col = (int64_t)blockIdx.x * 16 + (lane & 15);
     const bool cvalid = col < nleaf * g.B;
-    const int64_t leaf = cvalid ? col / g.B : 0;
-    const int bm = cvalid ? (int)(col % g.B) : 0;
+    const int64_t leaf = cvalid ? col % nleaf : 0;
+    const int bm = cvalid ? (int)(col / nleaf) : 0;
     const int rb0 = 4 * blockIdx.y;
     const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + kr * K4);
     vec4 acc[4];
@@ -695,6 +750,92 @@ static grav_status enqueue_m2l_transposed(Plan *p, const DevGeom &g, hipStream_t
                                        : m2l_transposed_t<float>(p, g, s, p->d_kt32);
 }
 
+// P2M^T for leaves of at most 64 cells (four row blocks): the layout of
+// k_m2m_lds, a workgroup owning 64 leaf-fastest columns with the chunks of
+// the operator (four k steps, all row blocks) double-buffered in LDS.
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int K4 = PS / 4;
+    __shared__ double sa[2][4 * 4 * 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kr = lane >> 4;
+    const int CH = 4 * RBT * 64;  // doubles per chunk
+    const DevLev &lv = g.lev[g.L];
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
+    const bool cvalid = col < nleaf * g.B;
+    const int64_t leaf = cvalid ? col % nleaf : 0;
+    const int bm = cvalid ? (int)(col / nleaf) : 0;
+    const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + kr * K4);
+    vec4 acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    double ra[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (i < RBT)
+            ra[i] = A[i * 256 + tid];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (i < RBT)
+            sa[0][i * 256 + tid] = ra[i];
+    double2 b01 = cvalid ? bp[0] : double2{0.0, 0.0};
+    double2 b23 = cvalid ? bp[1] : double2{0.0, 0.0};
+    __syncthreads();
+    for (int j = 0; j < RB; ++j) {
+        const int buf = j & 1;
+        const bool more = j + 1 < RB;
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < RBT)
+                    ra[i] = A[(int64_t)(j + 1) * CH + i * 256 + tid];
+        }
+        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+        if (more) {
+            b01 = cvalid ? bp[2 * (j + 1)] : double2{0.0, 0.0};
+            b23 = cvalid ? bp[2 * (j + 1) + 1] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < RBT)
+                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RBT + r) * 64 + lane], bv[u], acc[r], 0,
+                                                                 0, 0);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < RBT)
+                    sa[buf ^ 1][i * 256 + tid] = ra[i];
+        }
+        __syncthreads();
+    }
+    if (!cvalid)
+        return;
+    const int b = g.b, b3 = b * b * b;
+    const int lx = lv.s0[0] + (int)(leaf % lv.ns[0]), ly = lv.s0[1] + (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              lz = lv.s0[2] + (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = 16 * r + kr + 4 * i;
+            if (r >= RBT || v >= b3)
+                continue;
+            const int ix = (lx - g.shift[0]) * b + v % b, iy = (ly - g.shift[1]) * b + (v / b) % b,
+                      iz = (lz - g.shift[2]) * b + v / (b * b);
+            if (ix < 0 || iy < 0 || iz < 0 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+                continue;
+            drho[(int64_t)bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix] = acc[r][i];
+        }
+}
+
 // The lattice transposes for voxel-centre targets (see k_near_lat): with w_T
 // the combine^T weights of target leaf T's b^3 cell centres (4 per centre),
 //   drho[S] (+)= sum over the 27 neighbours d of A_d^T w_{S - d}   (near^T)
@@ -911,11 +1052,16 @@ static grav_status launch_t_m2m(Plan *p, const DevGeom &g, int l, hipStream_t s)
 static grav_status launch_t_p2m(Plan *p, const DevGeom &g, double *drho, hipStream_t s)
 {
     const int b3 = p->b * p->b * p->b, RBT = (b3 + 15) / 16;
-    const dim3 grid((unsigned)ceil_div(p->lev[p->L].n_src * p->B, 16), (unsigned)ceil_div(RBT, 4));
+    const int64_t ncol = p->lev[p->L].n_src * p->B;
+    const dim3 grid((unsigned)ceil_div(ncol, 16), (unsigned)ceil_div(RBT, 4)), grid_lds((unsigned)ceil_div(ncol, 64));
 #define CASE(R)                                                                                             \
     case R:                                                                                                 \
-        hipLaunchKernelGGL((k_t_p2m<R>), grid, dim3(64), 0, s, g, (const double *)p->d_pmt_sw, RBT,         \
-                           (const double *)p->d_me, drho);                                                  \
+        if (RBT <= 4)                                                                                       \
+            hipLaunchKernelGGL((k_t_p2m_lds<R>), grid_lds, dim3(256), 0, s, g, (const double *)p->d_pmt_sw, RBT, \
+                               (const double *)p->d_me, drho);                                              \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_t_p2m<R>), grid, dim3(64), 0, s, g, (const double *)p->d_pmt_sw, RBT,     \
+                               (const double *)p->d_me, drho);                                              \
         break;
     switch (p->PS / 16) {
         GRAV_T_RB_CASES(CASE)
@@ -983,10 +1129,18 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
         // plans by the transposed lattice L2P
         const bool pts = !p->lat_near || p->d.n_points > 0;
         if (p->n_leaf > 0 && pts) {
-            hipLaunchKernelGGL(k_t_l2p, dim3((unsigned)p->n_leaf), dim3(64), sizeof(double) * p->P2 * kL2PTChunk, s,
-                               g, (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
-                               p->lat_near ? (const int64_t *)p->d_leaf_pend : nullptr, (const uint32_t *)p->d_tkey,
-                               p->n_leaf, (const double *)p->d_near, p->d_le);
+            const int MG = p->B == 1 ? 1 : kL2PTModels;
+            const size_t lds = sizeof(double) * std::max(kL2PTChunk * (p->P2 + 4 * MG), 4 * MG * p->P2);
+            const dim3 lgrid((unsigned)p->n_leaf, (unsigned)ceil_div(p->B, MG));
+            const int64_t *pend = p->lat_near ? (const int64_t *)p->d_leaf_pend : nullptr;
+            if (MG == 1)
+                hipLaunchKernelGGL((k_t_l2p<1>), lgrid, dim3(256), lds, s, g, (const double *)p->d_tpos,
+                                   (const int64_t *)p->d_leaf_start, pend, (const uint32_t *)p->d_tkey, p->n_leaf,
+                                   (const double *)p->d_near, p->d_le);
+            else
+                hipLaunchKernelGGL((k_t_l2p<kL2PTModels>), lgrid, dim3(256), lds, s, g, (const double *)p->d_tpos,
+                                   (const int64_t *)p->d_leaf_start, pend, (const uint32_t *)p->d_tkey, p->n_leaf,
+                                   (const double *)p->d_near, p->d_le);
             GRAV_HIP(hipGetLastError());
         }
         if (p->lat_near)
