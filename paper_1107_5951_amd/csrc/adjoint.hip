@@ -346,6 +346,81 @@ k_t_l2l(DevGeom g, int l, const uint32_t *tkey, const int32_t *tchild, const dou
             dst[16 * r + kr + 4 * i] = acc[r][i];
 }
 
+// L2L^T on levels with few boxes: a workgroup owns 16 columns and one
+// 16-row block; its eight waves take one child octant each (a chain of PS/4
+// instructions instead of 8 PS/4) and add their fragments through LDS in
+// octant order.
+template <int RB>
+__global__ void __launch_bounds__(512)
+k_t_l2l_split(DevGeom g, int l, const uint32_t *tkey, const int32_t *tchild, const double *A, double *le)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    __shared__ double red[8][256];
+    constexpr int PS = 16 * RB;
+    constexpr int K4 = PS / 4;
+    const int lane = threadIdx.x & 63, kr = lane >> 4;
+    const int c = threadIdx.x >> 6;  // the wave's child octant
+    const DevLev &lv = g.lev[l];
+    const DevLev &lc = g.lev[l + 1];
+    const int64_t cg = blockIdx.x / RB;
+    const int rb = (int)(blockIdx.x % RB);
+    const int64_t col = cg * 16 + (lane & 15);
+    const bool cvalid = col < lv.n_tgt * g.B;
+    const int64_t box = cvalid ? col / g.B : 0;
+    const int bm = cvalid ? (int)(col % g.B) : 0;
+    int64_t ci = -1;
+    if (cvalid) {
+        const int32_t ca = max(tchild[lv.tchild_off + box], 0);
+        const int32_t ce = min(tchild[lv.tchild_off + box + 1], (int32_t)lc.n_tgt);
+        for (int32_t ch = ca; ch < ce; ++ch)
+            if ((int)(tkey[lc.tbox_off + ch] & 7u) == c)
+                ci = ch;
+    }
+    vec4 acc = vec4{0, 0, 0, 0};
+    if (__ballot(ci >= 0) != 0ull) {
+        const double2 *bp = (const double2 *)(le + (ci >= 0 ? ((lc.tgt_off + ci) * g.B + bm) * PS : 0) + kr * K4);
+        const double *ap = A + (int64_t)c * PS * PS + rb * 64 + lane;  // k step ks at ap[ks * RB * 64]
+        constexpr int U = RB < 8 ? RB : 8;
+        for (int q0 = 0; q0 < RB; q0 += U) {
+            double av[U][4];
+            double2 bb[U][2];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = min(q0 + u, RB - 1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    av[u][k] = ap[(int64_t)(4 * q + k) * RB * 64];
+                bb[u][0] = ci >= 0 ? bp[2 * q] : double2{0.0, 0.0};
+                bb[u][1] = ci >= 0 ? bp[2 * q + 1] : double2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = q0 + u < RB;
+                const double bv[4] = {in ? bb[u][0].x : 0.0, in ? bb[u][0].y : 0.0, in ? bb[u][1].x : 0.0,
+                                      in ? bb[u][1].y : 0.0};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][k], bv[k], acc, 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        red[c][lane * 4 + r] = acc[r];
+    __syncthreads();
+    if (c == 0 && cvalid) {
+        double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double v = red[0][lane * 4 + r];
+#pragma unroll
+            for (int w = 1; w < 8; ++w)
+                v += red[w][lane * 4 + r];
+            dst[16 * rb + kr + 4 * r] = v;
+        }
+    }
+}
+
 // M2M^T: ME_l[child] (+)= M2M_c^T ME_l-1[parent] for the children of octant c
 // = blockIdx.y; the columns are the parent boxes of level l-1 (x models),
 // K = p^2.  Inside the transposed M2L's column block the child's ME already
@@ -865,21 +940,56 @@ __device__ __forceinline__ void lattice_weights(const DevGeom &g, const int32_t 
     v[3] = x.w;
 }
 
-// near^T: one wave owns CW blocks of 16 (source leaf, model) columns and
-// four 16-cell row blocks (blockIdx.y), in the near field's element type.
+// The weights of the cell centres in leaf blocks for near^T, as k_rho_blocks
+// lays out the densities: centre t = kr TQ + q of a leaf, its four weights
+// at blk[q][kr][pl * B + model][0..3], pl = the leaf's index in the source
+// block padded by one leaf per side (padding zero).  One thread per
+// (leaf, model, centre).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_t_wblocks(DevGeom g, const int32_t *cell_slot, const double *w, int TQ, int64_t nplB, T *blk)
+{
+    const DevLev &lv = g.lev[g.L];
+    const int b = g.b, b3 = b * b * b;
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaf * g.B * b3)
+        return;
+    const int t = (int)(i % b3);
+    const int bm = (int)((i / b3) % g.B);
+    const int64_t leaf = i / ((int64_t)b3 * g.B);
+    const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    double v[4];
+    lattice_weights(g, cell_slot, w, lx, ly, lz, t, bm, true, v);
+    const int64_t pl = ((int64_t)(lz + 1) * (lv.ns[1] + 2) + (ly + 1)) * (lv.ns[0] + 2) + (lx + 1);
+    T *o = blk + ((int64_t)((t % TQ) * 4 + t / TQ) * nplB + pl * g.B + bm) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        o[u] = (T)v[u];
+}
+
+// near^T: a workgroup owns CW blocks of 16 (source leaf, model) columns and
+// four 16-cell row blocks (blockIdx.y); its four waves split the 27 TQ
+// chunks (neighbour d, centre chunk q) and add their partial tiles through
+// LDS in wave order (deterministic), as k_near_lat does.  Target leaf T =
+// S - d reads the padded weight blocks (no bounds test).
 template <int CW, typename T>
-__global__ void __launch_bounds__(64)
-k_t_near_lat(DevGeom g, const T *A, int RBt, int TQ, const int32_t *cell_slot, const double *w, int add,
-             double *drho)
+__global__ void __launch_bounds__(256)
+k_t_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBt, int TQ, int add, double *drho)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
-    const int lane = threadIdx.x, kr = lane >> 4;
+    __shared__ double red[4][CW * 4 * 4][64];
+    const int lane = threadIdx.x & 63, kr = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
     const int b = g.b, b3 = b * b * b;
+    const int px = lv.ns[0] + 2, py = lv.ns[1] + 2;
     const int rb0 = 4 * blockIdx.y;
     bool cvalid[CW];
     int bm[CW], sx[CW], sy[CW], sz[CW];
+    const T *bbase[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) {
         const int64_t col = ((int64_t)blockIdx.x * CW + c) * 16 + (lane & 15);
@@ -889,6 +999,8 @@ k_t_near_lat(DevGeom g, const T *A, int RBt, int TQ, const int32_t *cell_slot, c
         sx[c] = (int)(leaf % lv.ns[0]);
         sy[c] = (int)((leaf / lv.ns[0]) % lv.ns[1]);
         sz[c] = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+        bbase[c] = blk + ((int64_t)kr * nplB + (((int64_t)(sz[c] + 1) * py + (sy[c] + 1)) * px + (sx[c] + 1)) * g.B +
+                          bm[c]) * 4;
     }
     vec4 acc[CW][4];
 #pragma unroll
@@ -896,62 +1008,59 @@ k_t_near_lat(DevGeom g, const T *A, int RBt, int TQ, const int32_t *cell_slot, c
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             acc[c][r] = vec4{0, 0, 0, 0};
-    for (int nb = 0; nb < 27; ++nb) {
-        // the forward pairs target leaf T with source leaf T + d: here T = S - d
+    const int NI = 27 * TQ;
+    const int i0 = wave * NI / 4, i1 = (wave + 1) * NI / 4;
+    for (int i = i0; i < i1; ++i) {
+        const int nb = i / TQ, q = i - nb * TQ;
+        // the forward pairs target leaf T with source leaf T + d: T = S - d
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
-        bool tin[CW];
+        const int64_t boff = ((int64_t)q * 4 * nplB + (((int64_t)(-dz) * py - dy) * px - dx) * g.B) * 4;
+        T bb[CW][4];
 #pragma unroll
         for (int c = 0; c < CW; ++c)
-            tin[c] = cvalid[c] && sx[c] - dx >= 0 && sy[c] - dy >= 0 && sz[c] - dz >= 0 && sx[c] - dx < lv.ns[0] &&
-                     sy[c] - dy < lv.ns[1] && sz[c] - dz < lv.ns[2];
-        for (int q = 0; q < TQ; ++q) {
-            T bv[CW][4];
+            load4(bbase[c] + boff, bb[c]);
+        T av[4][4];
 #pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                double v[4];
-                lattice_weights(g, cell_slot, w, sx[c] - dx, sy[c] - dy, sz[c] - dz, kr * TQ + q, bm[c], tin[c], v);
+        for (int r = 0; r < 4; ++r)
+            load_frags<T, 4>(A + (((int64_t)nb * TQ + q) * RBt + min(rb0 + r, RBt - 1)) * 256, lane, av[r]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    bv[c][u] = (T)v[u];
-            }
-            T av[4][4];
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                load_frags<T, 4>(A + (((int64_t)nb * TQ + q) * RBt + min(rb0 + r, RBt - 1)) * 256, lane, av[r]);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int c = 0; c < CW; ++c) {
-                        if constexpr (sizeof(T) == 8)
-                            acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][u], bv[c][u], acc[c][r], 0, 0, 0);
-                        else
-                            acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][u], bv[c][u], acc[c][r], 0, 0, 0);
-                    }
-        }
+                for (int c = 0; c < CW; ++c) {
+                    if constexpr (sizeof(T) == 8)
+                        acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][u], bb[c][u], acc[c][r], 0, 0, 0);
+                    else
+                        acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][u], bb[c][u], acc[c][r], 0, 0, 0);
+                }
     }
+#pragma unroll
+    for (int c = 0; c < CW; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                red[wave][(c * 4 + r) * 4 + k][lane] = (double)acc[c][r][k];
+    __syncthreads();
     // output rows: FP32 instruction rows 4 (lane/16) + i, FP64 rows lane/16 + 4 i
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-#pragma unroll
-    for (int c = 0; c < CW; ++c) {
-        if (!cvalid[c])
+    for (int j = wave; j < CW * 4; j += 4) {
+        const int c = j / 4, r = j % 4;
+        if (!cvalid[c] || rb0 + r >= RBt)
             continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (rb0 + r >= RBt)
+        for (int i = 0; i < 4; ++i) {
+            const int v = 16 * (rb0 + r) + (sizeof(T) == 8 ? kr + 4 * i : 4 * kr + i);
+            if (v >= b3)
                 continue;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int v = 16 * (rb0 + r) + (sizeof(T) == 8 ? kr + 4 * i : 4 * kr + i);
-                if (v >= b3)
-                    continue;
-                const int ix = sx[c] * b + v % b, iy = sy[c] * b + (v / b) % b, iz = sz[c] * b + v / (b * b);
-                if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
-                    continue;
-                double *o = drho + (int64_t)bm[c] * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
-                *o = add ? *o + (double)acc[c][r][i] : (double)acc[c][r][i];
-            }
+            const int ix = sx[c] * b + v % b, iy = sy[c] * b + (v / b) % b, iz = sz[c] * b + v / (b * b);
+            if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+                continue;
+            const double sum = ((red[0][j * 4 + i][lane] + red[1][j * 4 + i][lane]) + red[2][j * 4 + i][lane]) +
+                               red[3][j * 4 + i][lane];
+            double *o = drho + (int64_t)bm[c] * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
+            *o = add ? *o + sum : sum;
         }
     }
 }
@@ -1008,15 +1117,26 @@ k_t_l2p_lat(DevGeom g, const double *A, int TQ, const int32_t *tmap, const int32
 
 #define GRAV_T_RB_CASES(X) X(1) X(2) X(3) X(4) X(6) X(7) X(8) X(9) X(11) X(13) X(15) X(16)
 
+// levels with fewer 64-column workgroups than this take the split kernel
+constexpr int64_t kTileWgsMin = 256;
+
 static grav_status launch_t_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
 {
-    const dim3 grid((unsigned)ceil_div(p->lev[l].n_tgt * p->B, 64));
+    const int64_t ncol = p->lev[l].n_tgt * p->B;
+    const int RB = p->PS / 16;
+    const bool tiled = ceil_div(ncol, 64) >= kTileWgsMin;
+    const dim3 grid((unsigned)ceil_div(ncol, 64)), grid_split((unsigned)(ceil_div(ncol, 16) * RB));
 #define CASE(R)                                                                                            \
     case R:                                                                                                \
-        hipLaunchKernelGGL((k_t_l2l<R>), grid, dim3(256), 0, s, g, l, (const uint32_t *)p->d_tkey,         \
-                           (const int32_t *)p->d_tchild, (const double *)p->d_l2lt_sw, p->d_le);           \
+        if (tiled)                                                                                         \
+            hipLaunchKernelGGL((k_t_l2l<R>), grid, dim3(256), 0, s, g, l, (const uint32_t *)p->d_tkey,     \
+                               (const int32_t *)p->d_tchild, (const double *)p->d_l2lt_sw, p->d_le);       \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_t_l2l_split<R>), grid_split, dim3(512), 0, s, g, l,                      \
+                               (const uint32_t *)p->d_tkey, (const int32_t *)p->d_tchild,                  \
+                               (const double *)p->d_l2lt_sw, p->d_le);                                     \
         break;
-    switch (p->PS / 16) {
+    switch (RB) {
         GRAV_T_RB_CASES(CASE)
     default:
         return GRAV_EUNSUPPORTED;
@@ -1095,14 +1215,24 @@ static grav_status launch_t_l2p_lat(Plan *p, const DevGeom &g, int add, hipStrea
 static grav_status launch_t_near_lat(Plan *p, const DevGeom &g, int add, double *drho, hipStream_t s)
 {
     constexpr int CW = 2;
+    const LevelInfo &lv = p->lev[p->L];
     const int b3 = p->b * p->b * p->b, RBt = (int)ceil_div(b3, 16);
-    const dim3 grid((unsigned)ceil_div(p->lev[p->L].n_src * p->B, 16 * CW), (unsigned)ceil_div(RBt, 4));
-    if (p->d.precision == GRAV_FP64)
-        hipLaunchKernelGGL((k_t_near_lat<CW, double>), grid, dim3(64), 0, s, g, (const double *)p->d_tnt64, RBt,
-                           p->lat_TQ, (const int32_t *)p->d_cell_slot, (const double *)p->d_near, add, drho);
-    else
-        hipLaunchKernelGGL((k_t_near_lat<CW, float>), grid, dim3(64), 0, s, g, (const float *)p->d_tnt32, RBt,
-                           p->lat_TQ, (const int32_t *)p->d_cell_slot, (const double *)p->d_near, add, drho);
+    const int64_t nplB = (int64_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B;
+    const bool f64 = p->d.precision == GRAV_FP64;
+    const dim3 fgrid((unsigned)ceil_div(lv.n_src * p->B * b3, 256));
+    const dim3 grid((unsigned)ceil_div(lv.n_src * p->B, 16 * CW), (unsigned)ceil_div(RBt, 4));
+    if (f64) {
+        hipLaunchKernelGGL((k_t_wblocks<double>), fgrid, dim3(256), 0, s, g, (const int32_t *)p->d_cell_slot,
+                           (const double *)p->d_near, p->lat_TQ, nplB, p->d_w_blk);
+        hipLaunchKernelGGL((k_t_near_lat<CW, double>), grid, dim3(256), 0, s, g, (const double *)p->d_w_blk, nplB,
+                           (const double *)p->d_tnt64, RBt, p->lat_TQ, add, drho);
+    } else {
+        float *wb = reinterpret_cast<float *>(p->d_w_blk);
+        hipLaunchKernelGGL((k_t_wblocks<float>), fgrid, dim3(256), 0, s, g, (const int32_t *)p->d_cell_slot,
+                           (const double *)p->d_near, p->lat_TQ, nplB, wb);
+        hipLaunchKernelGGL((k_t_near_lat<CW, float>), grid, dim3(256), 0, s, g, (const float *)wb, nplB,
+                           (const float *)p->d_tnt32, RBt, p->lat_TQ, add, drho);
+    }
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }

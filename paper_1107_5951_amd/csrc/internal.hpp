@@ -157,6 +157,7 @@ struct Plan {
     double *d_tnt64 = nullptr;                     // [27][TQ][ceil(b^3/16)][64][4] transposed near field, FP64
     float *d_tnt32 = nullptr;                      // same, mixed plans
     double *d_tl2pt = nullptr;                     // [TQ][PS/16][64][4] transposed lattice L2P (FP64)
+    double *d_w_blk = nullptr;                     // [TQ][4][padded leaves x B][4] adjoint weights per leaf (FP32 in mixed plans)
     int32_t *d_cell_slot = nullptr;                // [ncell] sorted slot of each voxel centre
     hipStream_t bs = nullptr;                      // plan-build stream (non-blocking), only inside grav_plan
     int direct_chunks = 1;                         // source chunks of grav_direct

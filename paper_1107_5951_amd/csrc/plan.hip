@@ -290,7 +290,7 @@ void free_plan(Plan *p)
                     p->d_cell_slot, p->d_leaf_pend, p->d_m2lt_tiles, p->d_m2lt_items, p->d_m2lt_segs,
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
                     p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
-                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt};
+                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -1150,6 +1150,17 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
     // [nb][q][rb][lane][u] group-major sets
     const int TQ = (int)ceil_div(b3, 4), RBt = (int)ceil_div(b3, 16);
     p->lat_TQ = TQ;
+    {
+        // the weights of the cell centres in leaf blocks (padded by one leaf
+        // per side, 4 TQ x 4 values per leaf and model, in the near field's
+        // element type); the padding and the slots past b^3 stay zero
+        const LevelInfo &lv = p->lev[p->L];
+        const size_t n = (size_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B * 16 * TQ;
+        const size_t nd = f64 ? n : (n + 1) / 2;  // in doubles
+        GRAV_CHECK(dalloc(p, &p->d_w_blk, nd, false));
+        GRAV_HIP(hipMemsetAsync(p->d_w_blk, 0, sizeof(double) * nd, p->bs));
+        GRAV_HIP(hipStreamSynchronize(p->bs));
+    }
     {
         std::vector<double> swt((size_t)27 * TQ * RBt * 256, 0.0);
         for (int nb = 0; nb < 27; ++nb)
