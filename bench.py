@@ -108,6 +108,33 @@ def stage_profile(plan, rho, out, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
+def adjoint_profile(plan, out_shape, reps):
+    """Time of the adjoint (grav_adjoint) on a seeded residual, HIP events
+    on the current stream, and its per-stage durations."""
+    import torch
+    res = torch.randn(out_shape, dtype=torch.float64, device="cuda",
+                      generator=torch.Generator(device="cuda").manual_seed(1004))
+    drho = torch.empty(plan.rho_shape, dtype=torch.float64, device="cuda")
+    plan.adjoint(res, drho)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.adjoint(res, drho)
+    e1.record()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    acc = {}
+    for _ in range(reps):
+        plan.adjoint(res, drho)
+        for name, ms in plan.stage_times():
+            acc[name] = acc.get(name, 0.0) + ms
+    plan.set_profiling(False)
+    torch.cuda.synchronize()
+    del res, drho
+    return e0.elapsed_time(e1) / reps, {k: v / reps for k, v in acc.items()}
+
+
 def measured_traffic(profile, kernel_name):
     """HBM bytes per launch of the dominant kernel from a committed counter
     summary under profiles/, or None if it covers another kernel or the
@@ -247,6 +274,7 @@ def headline(args):
     m2l_pairs, p2p_pairs, n_src = plan.work()
     g_sample = gather_rows(out, idx)
     roof = roofline(plan, stages, args.p, G.GRAV_MIXED, "m2l_volume256_q1_hbm_traffic.md")
+    adj_ms, adj_stages = (None, None) if args.timed_only else adjoint_profile(plan, plan.out_shape, 5)
     levels, leaf = plan.levels, plan.leaf_cells
     resident, per_call = plan.bytes()
     del plan
@@ -268,6 +296,8 @@ def headline(args):
         "work": {"m2l_box_pairs": m2l_pairs, "p2p_point_pairs": p2p_pairs,
                  "m2l_gflop": 2.0 * args.p ** 4 * m2l_pairs / 1e9},
         "roofline": roof,
+        "adjoint": {"ms": adj_ms, "stages_ms": adj_stages,
+                    "what": "grad of 0.5||g - d||^2 w.r.t. rho (grav_adjoint, exact transpose) at the same plan"},
     }
 
     if args.timed_only:
@@ -360,23 +390,25 @@ def volume64(args):
     idx = W.sample_indices(M, args.sample, seed=7)
     row = {"workload": "64^3 cells, 2-point rule (2097152 sources), g at all 262144 cell centres"}
     outs = {}
-    for tag, prec, p in (("mixed", G.GRAV_MIXED, 10), ("fp64", G.GRAV_FP64, 12)):
+    # leaf 512 points (4^3 cells) is the faster split; leaf 64 (2^3 cells)
+    # moves the work into the M2L (121 GFLOP at p = 10)
+    for tag, prec, p, leaf in (("mixed", G.GRAV_MIXED, 10, 512), ("fp64", G.GRAV_FP64, 12, 512),
+                               ("mixed_leaf64", G.GRAV_MIXED, 10, 64)):
         plan = G.Plan(G.PlanSpec(n=(n, n, n), h=grid.h, quad_order=2, voxel_centres=True, components=3, p=p,
-                                 leaf_size=512, precision=prec))
+                                 leaf_size=leaf, precision=prec))
         out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
         ms, lat = timed_steps(plan, rho, out, args.steps, args.warmup)
         stg = stage_profile(plan, rho, out, 5)
         outs[tag] = gather_rows(out, idx)
-        row[tag] = {"p": p, "value": M / (ms * 1e-3), "ms_per_step": ms, "p50_ms": pct(lat, 50),
-                    "p99_ms": pct(lat, 99), "stages_ms": stg,
-                    "roofline": roofline(plan, stg, p, prec,
-                                         "m2l_volume64_q2_hbm_traffic.md" if tag == "mixed" else None)}
+        row[tag] = {"p": p, "leaf_points": leaf, "value": M / (ms * 1e-3), "ms_per_step": ms,
+                    "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "stages_ms": stg,
+                    "roofline": roofline(plan, stg, p, prec, None)}
         del plan, out
     if not args.no_cpu:
         import oracle
         ref = oracle.forward(rho_h, grid.origin, grid.h, 2, grid.centres()[idx], comps=3)
-        row["mixed"]["rel_err"] = oracle.rel_l2(outs["mixed"], ref)
-        row["fp64"]["rel_err"] = oracle.rel_l2(outs["fp64"], ref)
+        for tag in outs:
+            row[tag]["rel_err"] = oracle.rel_l2(outs[tag], ref)
     return row
 
 
@@ -384,7 +416,7 @@ def batched128(args):
     """32 density models (8 blobs each, seeds 2000 + b) on one 128^3-cell
     tree, gz at 256 x 256 stations at z = 1.1: the mixed-precision batched
     solve (p = 10) against the FP64 FMM (p = 14), batched and as 32 plain
-    single-model solves; the adjoint when the library has it."""
+    single-model solves; the adjoint of each (the inversion gradient)."""
     import numpy as np
     import torch
 
@@ -408,23 +440,11 @@ def batched128(args):
         row[tag] = {"p": p, "value": B * st.shape[0] / (ms * 1e-3), "ms_per_step": ms,
                     "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "stages_ms": stg,
                     "roofline": roofline(plan, stg, p, prec, None)}
-        try:
-            res = torch.randn(plan.out_shape, dtype=torch.float64, device="cuda",
-                              generator=torch.Generator(device="cuda").manual_seed(1004))
-            drho = torch.empty_like(r)
-            plan.adjoint(res, drho)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(3):
-                plan.adjoint(res, drho)
-            e1.record()
-            torch.cuda.synchronize()
-            row[tag]["adjoint_ms"] = e0.elapsed_time(e1) / 3
-        except G.GravError as e:
-            if e.code != 4:
-                raise
-            row[tag]["adjoint_ms"] = None
+        adj_ms, adj_st = adjoint_profile(plan, plan.out_shape, 5)
+        row[tag]["adjoint_ms"] = adj_ms
+        row[tag]["adjoint_stages_ms"] = adj_st
+        # one inversion iteration: forward, misfit, adjoint (the gradient)
+        row[tag]["inversion_step_ms"] = ms + adj_ms
         del plan, out
         torch.cuda.empty_cache()
     # the plain FP64 FMM: one model per solve, 32 solves
