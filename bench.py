@@ -519,7 +519,7 @@ def serving(args):
     graph-captured solves with continuous batching, served back to back
     (capacity) and at the trace's arrival times (latency under load)."""
     from paper_1107_5951_amd import serve
-    print(json.dumps(serve.benchmark(args.serve)), flush=True)
+    print(json.dumps(serve.benchmark(args.serve, log=say)), flush=True)
 
 
 def crossover(args):

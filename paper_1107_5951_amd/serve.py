@@ -17,7 +17,8 @@ density gradient (adjoint, the transpose of the forward map).
 * Continuous batching: whenever a stream slot frees up, the oldest waiting
   request is started together with the other waiting requests of the same
   mesh, rule and direction, as one batched solve (batch sizes 1, 2, 4, 8;
-  unused batch members are computed and ignored).  Requests that arrive
+  unused batch members are computed and ignored; a resident slot is used
+  before a new batch size is built).  Requests that arrive
   while others run are admitted as slots and memory free up, and their work
   overlaps on the device with the work already in flight.
 
@@ -204,6 +205,21 @@ class GravServer:
         self.slots[key] = slot
         return slot
 
+    def _batch_size(self, n: int, q: int, waiting: int) -> int:
+        """Batch size for `waiting` same-plan requests: the smallest resident
+        slot that takes them all; else a resident slot that takes at least
+        half of them (the rest go in the next round); else the smallest batch
+        size that fits them all (a new slot: a plan and two graph captures,
+        worth it only when it replaces several launches)."""
+        k = min(waiting, BATCH_SIZES[-1])
+        have = [b for b in BATCH_SIZES if (n, q, b) in self.slots]
+        up = [b for b in have if b >= k]
+        if up:
+            return min(up)
+        if have and 2 * max(have) >= k:
+            return max(have)
+        return next(b for b in BATCH_SIZES if b >= k)
+
     def _make_room(self, need: int) -> bool:
         """Evict idle slots (least recently used first) until `need` more bytes
         fit the budget; False if only in-flight slots are left to evict."""
@@ -266,8 +282,8 @@ class GravServer:
                 tried.add((kind, key))
                 group = [j for j in waiting if requests[j].kind == kind and
                          (requests[j].n, requests[j].q) == key] if self.batching else [i]
-                group = group[:BATCH_SIZES[-1]]
-                batch = next(b for b in BATCH_SIZES if b >= len(group))
+                batch = self._batch_size(head.n, head.q, len(group))
+                group = group[:batch]
                 try:
                     slot = self._slot(head.n, head.q, batch)
                 except MemoryError as e:
@@ -349,7 +365,7 @@ def poisson_trace(count: int, rate: float, seed: int, n_min: int = 32, n_max: in
     return reqs
 
 
-def benchmark(count: int = 3000, rate: float = 50.0, seed: int = 1005) -> dict:
+def benchmark(count: int = 3000, rate: float = 50.0, seed: int = 1005, log=None) -> dict:
     """The serving workload: a Poisson trace of forward and adjoint requests
     (50/50), meshes 32^3 .. 192^3, q in {1, 2}, mixed precision at p = 10;
     plans and graphs are built first (timed separately), then the trace is
@@ -357,16 +373,23 @@ def benchmark(count: int = 3000, rate: float = 50.0, seed: int = 1005) -> dict:
     load).  The back-to-back figure is the second pass over the trace, with
     the batched slots its first pass built resident."""
     import torch
+    say = log or (lambda msg: None)
     reqs = poisson_trace(count, rate, seed, host_blobs=False)
     srv = GravServer(budget_bytes=128 << 30)
     t0 = time.perf_counter()
-    for key in sorted(set((r.n, r.q) for r in reqs)):
+    keys = sorted(set((r.n, r.q) for r in reqs))
+    for i, key in enumerate(keys):
         srv._slot(key[0], key[1], 1)
+        if (i + 1) % 25 == 0 or i + 1 == len(keys):
+            say("serving: %d of %d plans and graphs built" % (i + 1, len(keys)))
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     _, cold = srv.run(reqs)             # builds the batched slots it needs
+    say("serving: first pass done (%.1f s)" % cold["wall_s"])
     _, cap = srv.run(reqs)              # back to back, slots resident
+    say("serving: back-to-back pass done (%.1f s)" % cap["wall_s"])
     _, live = srv.run(reqs, realtime=True)
+    say("serving: pass at arrival times done")
     srv.close()
     cap["first_pass_wall_s"] = cold["wall_s"]
     cap["first_pass_slot_builds"] = cold.get("slot_builds", 0)
