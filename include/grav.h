@@ -78,10 +78,24 @@ typedef struct grav_plan_desc {
     int32_t batch;       /* B >= 1 density models sharing the tree */
     double G;            /* gravitational constant applied to every output */
     int32_t device;      /* HIP device ordinal the plan lives on */
+    /* Explicit sources in place of the cell quadrature (scattered points
+     * with volumes, the extension named in Sec. 4): n_sources > 0 points
+     * (host xyz[n][3], copied during grav_plan) inside the mesh box
+     * origin + [0, n) h, which then only frames the octree (leaves of b^3
+     * cells, b from leaf_size as above) and the voxel-centre targets.  The
+     * density arrays of grav_eval and grav_adjoint become [batch][n_sources]
+     * in source order: with source_volumes (host [n], each > 0, copied) a
+     * value is a density and the source's mass is value * volume; without,
+     * the value is the mass.  Requires quad_order 1.  grav_direct,
+     * grav_direct_noalloc and grav_analytic return GRAV_EUNSUPPORTED on such
+     * plans. */
+    int64_t n_sources;
+    const double *sources;
+    const double *source_volumes;
 } grav_plan_desc;
 
 /* Fill *d with defaults: 1-point rule, components 3, p = 8, leaf_size 64,
- * FP64, batch 1, G = 1, device 0, no points.  Always succeeds. */
+ * FP64, batch 1, G = 1, device 0, no points, cell sources.  Always succeeds. */
 void grav_desc_init(grav_plan_desc *d);
 
 /* Build a plan: validates the descriptor, sorts the evaluation points by

@@ -26,7 +26,11 @@ __all__ = [
 
 @dataclass
 class PlanSpec:
-    """Fields of ``grav_plan_desc``; points is an ``[n, 3]`` float64 array or None."""
+    """Fields of ``grav_plan_desc``; points is an ``[n, 3]`` float64 array or
+    None.  sources (``[n, 3]``) replaces the cells' quadrature points by
+    explicit point sources inside the mesh box; source_volumes (``[n]``)
+    makes the density values per-source densities (mass = value * volume),
+    without it they are masses."""
     n: Sequence[int]
     h: float
     origin: Sequence[float] = (0.0, 0.0, 0.0)
@@ -40,6 +44,8 @@ class PlanSpec:
     batch: int = 1
     G: float = 1.0
     device: int = 0
+    sources: Optional[np.ndarray] = None
+    source_volumes: Optional[np.ndarray] = None
 
     def to_desc(self):
         lib = load()
@@ -63,6 +69,18 @@ class PlanSpec:
         d.batch = int(self.batch)
         d.G = float(self.G)
         d.device = int(self.device)
+        keep = [keep]
+        if self.sources is not None and len(self.sources):
+            src = np.ascontiguousarray(self.sources, dtype=np.float64).reshape(-1, 3)
+            d.n_sources = src.shape[0]
+            d.sources = src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            keep.append(src)
+            if self.source_volumes is not None:
+                vol = np.ascontiguousarray(self.source_volumes, dtype=np.float64).reshape(-1)
+                if vol.shape[0] != src.shape[0]:
+                    raise ValueError("source_volumes must have one entry per source")
+                d.source_volumes = vol.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                keep.append(vol)
         return d, keep
 
 
@@ -115,6 +133,8 @@ class Plan:
 
     @property
     def rho_shape(self):
+        if self.spec.sources is not None and len(self.spec.sources):
+            return (self.spec.batch, int(np.asarray(self.spec.sources).reshape(-1, 3).shape[0]))
         n = self.spec.n
         return (self.spec.batch, int(n[2]), int(n[1]), int(n[0]))
 

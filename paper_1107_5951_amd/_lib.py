@@ -40,6 +40,9 @@ class GravDesc(ctypes.Structure):
         ("batch", ctypes.c_int32),
         ("G", ctypes.c_double),
         ("device", ctypes.c_int32),
+        ("n_sources", ctypes.c_int64),
+        ("sources", ctypes.POINTER(ctypes.c_double)),
+        ("source_volumes", ctypes.POINTER(ctypes.c_double)),
     ]
 
 

@@ -22,6 +22,7 @@
 // the size of the array it addresses before it is used.
 #include <algorithm>
 
+#include "harmonics.hpp"
 #include "resolve.hpp"
 
 namespace grav {
@@ -68,52 +69,6 @@ k_t_weights(DevGeom g, const double *resid, const uint32_t *perm, double *w)
 // The matrix stages below give each thread up to MT density models (a
 // group), so that every operator entry or pair geometry it loads serves MT
 // models; groups are ceil(B / MT).
-
-// Real index of the regular harmonic / coefficient (n, m): the real part
-// (order 0, or part 0 of order m > 0) or the imaginary part (part 1).
-__device__ __forceinline__ int harm_index(int n, int m, int part)
-{
-    return m == 0 ? n * n : n * n + 2 * m - 1 + part;
-}
-
-// The regular solid harmonics R_n^m(u), n < P, in the coefficients' real
-// order (the recurrences of l2p_eval), written to h[k * CS].
-__device__ inline void regular_harmonics(int P, double x, double y, double z, double *h, int CS)
-{
-    const double r2 = x * x + y * y + z * z;
-    double mmr = 1.0, mmi = 0.0;
-    for (int m = 0; m < P; ++m) {
-        if (m > 0) {
-            const double s = 1.0 / (2.0 * m);
-            const double nr = (x * mmr - y * mmi) * s;
-            const double ni = (x * mmi + y * mmr) * s;
-            mmr = nr;
-            mmi = ni;
-        }
-        double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
-        for (int n = m; n < P; ++n) {
-            double Rr, Ri;
-            if (n == m) {
-                Rr = mmr;
-                Ri = mmi;
-            } else if (n == m + 1) {
-                Rr = z * p1r;
-                Ri = z * p1i;
-            } else {
-                const double f = 1.0 / (double)((n - m) * (n + m));
-                Rr = ((2.0 * n - 1.0) * z * p1r - r2 * p2r) * f;
-                Ri = ((2.0 * n - 1.0) * z * p1i - r2 * p2i) * f;
-            }
-            p2r = p1r;
-            p2i = p1i;
-            p1r = Rr;
-            p1i = Ri;
-            h[harm_index(n, m, 0) * CS] = Rr;
-            if (m > 0)
-                h[harm_index(n, m, 1) * CS] = Ri;
-        }
-    }
-}
 
 // L2P^T: the adjoint LE of a leaf is the derivative, with respect to its
 // coefficients, of the sum over the leaf's targets (with `pend`, its user
@@ -760,6 +715,94 @@ k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, const int64_
     }
 }
 
+// Explicit sources, the transposes of P2M and of the near field per source:
+// drho[source] = mass per unit value x (the derivative of the leaf
+// expansion's contribution, multipole_basis_dot against ME_L^T, plus the
+// pair terms of the targets of the 27 leaves around the source's leaf with
+// their weights, formed as the forward near field forms them: relative to
+// the target leaf's corner, in type T, with its coincidence rule).  One
+// thread per (sorted source, model group).
+template <typename T, int MT>
+__global__ void __launch_bounds__(256)
+k_t_src(DevGeom g, const double *spos, const double *sw, const uint32_t *sperm, int64_t nsrc, const double *tpos,
+        const int64_t *leaf_start, int64_t n_leaf, const int32_t *tmap, int64_t n_tmap, const double *w,
+        const double *me, double *drho)
+{
+    const int NG = (g.B + MT - 1) / MT;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsrc * NG)
+        return;
+    const int grp = (int)(t / nsrc);
+    const int64_t i = t - (int64_t)grp * nsrc;
+    const int nm = min(MT, g.B - grp * MT);
+    const int b = g.b;
+    const DevLev &lv = g.lev[g.L];
+    const double x[3] = {spos[3 * i + 0], spos[3 * i + 1], spos[3 * i + 2]};
+    // the source's leaf (block-relative, as the sort key)
+    int lc[3];
+    for (int a = 0; a < 3; ++a)
+        lc[a] = min(max((int)floor(x[a] / b), 0), lv.ns[a] - 1);
+    double acc[MT];
+#pragma unroll
+    for (int u = 0; u < MT; ++u)
+        acc[u] = 0.0;
+    if (g.L >= 2) {
+        const int64_t leaf = ((int64_t)lc[2] * lv.ns[1] + lc[1]) * lv.ns[0] + lc[0];
+        const double inv_b = 1.0 / (double)b;
+        multipole_basis_dot<MT>(g.P, (x[0] - (lc[0] + 0.5) * b) * inv_b, (x[1] - (lc[1] + 0.5) * b) * inv_b,
+                                (x[2] - (lc[2] + 0.5) * b) * inv_b,
+                                me + ((lv.me_off + leaf) * g.B + grp * MT) * g.PS, g.PS, nm, acc);
+    }
+    const int mxl = lv.ns[0] + 6, myl = lv.ns[1] + 6, mzl = lv.ns[2] + 6;
+    for (int nb = 0; nb < 27; ++nb) {
+        // target leaf (root coordinates) and its place in the target map
+        const int tx = lc[0] + lv.s0[0] + nb % 3 - 1, ty = lc[1] + lv.s0[1] + (nb / 3) % 3 - 1,
+                  tz = lc[2] + lv.s0[2] + nb / 9 - 1;
+        const int mx = tx - lv.s0[0] + 3, my = ty - lv.s0[1] + 3, mz = tz - lv.s0[2] + 3;
+        if (mx < 0 || my < 0 || mz < 0 || mx >= mxl || my >= myl || mz >= mzl)
+            continue;
+        const int64_t mi = lv.tmap_off + ((int64_t)mz * myl + my) * mxl + mx;
+        if (mi >= n_tmap)
+            continue;
+        const int64_t tl = tmap[mi];
+        if (tl < 0 || tl >= n_leaf)
+            continue;
+        const double corner[3] = {(double)((tx - g.shift[0]) * b), (double)((ty - g.shift[1]) * b),
+                                  (double)((tz - g.shift[2]) * b)};
+        const T sx = (T)(x[0] - corner[0]), sy = (T)(x[1] - corner[1]), sz = (T)(x[2] - corner[2]);
+        const int64_t ts = max(leaf_start[tl], (int64_t)0), te = min(leaf_start[tl + 1], g.M);
+        T part[MT];
+#pragma unroll
+        for (int u = 0; u < MT; ++u)
+            part[u] = 0;
+        for (int64_t j = ts; j < te; ++j) {
+            const T cx = (T)(tpos[3 * j + 0] - corner[0]) - sx;
+            const T cy = (T)(tpos[3 * j + 1] - corner[1]) - sy;
+            const T cz = (T)(tpos[3 * j + 2] - corner[2]) - sz;
+            const T r2 = cx * cx + cy * cy + cz * cz;
+            if (!(r2 > coincident2<T>()))
+                continue;
+            const T ri = rsqrt_t(r2);
+            const T ri3 = ri * ri * ri;
+#pragma unroll
+            for (int u = 0; u < MT; ++u) {
+                if (u >= nm)
+                    break;
+                const double *wj = w + (j * g.B + grp * MT + u) * 4;
+                part[u] += (T)wj[0] * ri + ((T)wj[1] * (cx * ri3) + (T)wj[2] * (cy * ri3) + (T)wj[3] * (cz * ri3));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < MT; ++u)
+            acc[u] += (double)part[u];
+    }
+    const uint32_t user = sperm[i];
+#pragma unroll
+    for (int u = 0; u < MT; ++u)
+        if (u < nm)
+            drho[(int64_t)(grp * MT + u) * nsrc + user] = sw[i] * acc[u];
+}
+
 __global__ void __launch_bounds__(256) k_t_zero(double *x, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1288,9 +1331,31 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
         for (int l = 3; l <= L; ++l)
             GRAV_CHECK(launch_t_m2m(p, g, l, s));
         stage_end(p, s);
-        stage_begin(p, "p2mT", s);
-        GRAV_CHECK(launch_t_p2m(p, g, drho, s));
+        if (p->n_spts == 0) {
+            stage_begin(p, "p2mT", s);
+            GRAV_CHECK(launch_t_p2m(p, g, drho, s));
+            stage_end(p, s);
+        }
+    }
+    if (p->n_spts > 0) {
+        // explicit sources: P2M^T and near^T per source
+        stage_begin(p, "srcT", s);
+        const int64_t n = p->n_spts * NG;
+        if (p->d.precision == GRAV_FP64)
+            hipLaunchKernelGGL((k_t_src<double, MT>), grid(n), blk, 0, s, g, (const double *)p->d_spos,
+                               (const double *)p->d_sw, (const uint32_t *)p->d_sperm, p->n_spts,
+                               (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start, p->n_leaf,
+                               (const int32_t *)p->d_tmap, p->n_tmap, (const double *)p->d_near,
+                               (const double *)p->d_me, drho);
+        else
+            hipLaunchKernelGGL((k_t_src<float, MT>), grid(n), blk, 0, s, g, (const double *)p->d_spos,
+                               (const double *)p->d_sw, (const uint32_t *)p->d_sperm, p->n_spts,
+                               (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start, p->n_leaf,
+                               (const int32_t *)p->d_tmap, p->n_tmap, (const double *)p->d_near,
+                               (const double *)p->d_me, drho);
+        GRAV_HIP(hipGetLastError());
         stage_end(p, s);
+        return GRAV_OK;
     }
     // the near field's transpose (with no far field it also sets drho):
     // cell centres of lattice plans on MFMA, user points (or all targets of
@@ -1346,7 +1411,7 @@ extern "C" grav_status grav_adjoint(grav_plan_t plan, const double *resid, doubl
         if (p->M == 0) {
             // no evaluation points: the transpose is zero (a fill kernel, not a
             // memset, so that the call can be recorded in a graph)
-            const int64_t n = (int64_t)p->d.nx * p->d.ny * p->d.nz * p->B;
+            const int64_t n = (p->n_spts > 0 ? p->n_spts : (int64_t)p->d.nx * p->d.ny * p->d.nz) * p->B;
             hipLaunchKernelGGL(k_t_zero, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, drho_out, n);
             st = hipGetLastError() == hipSuccess ? GRAV_OK : GRAV_EDEVICE;
         } else {

@@ -126,7 +126,7 @@ extern "C" grav_status grav_analytic(grav_plan_t plan, const double *rho, double
     if (!plan)
         return GRAV_EINVAL;
     Plan *p = reinterpret_cast<Plan *>(plan);
-    if (p->d.components != 1)
+    if (p->d.components != 1 || p->n_spts > 0)
         return GRAV_EUNSUPPORTED;
     if (p->M == 0)
         return GRAV_OK;

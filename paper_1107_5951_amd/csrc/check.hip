@@ -358,5 +358,21 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
                             ck.fail("m2mT", "parent outside the source block", l, x);
         }
     }
+    // explicit sources: the per-leaf CSR is monotone and covers every
+    // source; the permutation is a permutation
+    if (ck.ok && p->n_spts > 0) {
+        const int64_t nleaf = p->lev[L].n_src;
+        const auto st = fetch(p->d_sstart, (size_t)nleaf + 1);
+        const auto pm = fetch(p->d_sperm, (size_t)p->n_spts);
+        if (st[0] != 0 || st[nleaf] != p->n_spts)
+            ck.fail("sources", "leaf ranges do not cover the sources", st[0], st[nleaf]);
+        for (int64_t j = 0; j < nleaf && ck.ok; ++j)
+            if (st[j + 1] < st[j])
+                ck.fail("sources", "leaf ranges out of order", j, st[j]);
+        std::vector<char> seen((size_t)p->n_spts, 0);
+        for (int64_t i = 0; i < p->n_spts && ck.ok; ++i)
+            if (pm[i] >= (uint32_t)p->n_spts || seen[pm[i]]++)
+                ck.fail("sources", "sorted order is not a permutation", i, pm[i]);
+    }
     return report();
 }

@@ -229,6 +229,8 @@ extern "C" grav_status grav_direct(grav_plan_t plan, const double *rho, double *
     if (!plan)
         return GRAV_EINVAL;
     Plan *p = reinterpret_cast<Plan *>(plan);
+    if (p->n_spts > 0)
+        return GRAV_EUNSUPPORTED;  // the summation sums over the cells' quadrature points
     if (p->M == 0)
         return GRAV_OK;
     if (!rho || !g_out)
@@ -253,6 +255,8 @@ extern "C" grav_status grav_direct_noalloc(grav_plan_t plan, const double *rho, 
     if (!plan)
         return GRAV_EINVAL;
     Plan *p = reinterpret_cast<Plan *>(plan);
+    if (p->n_spts > 0)
+        return GRAV_EUNSUPPORTED;
     if (p->M == 0)
         return GRAV_OK;
     if (!rho || !g_out)

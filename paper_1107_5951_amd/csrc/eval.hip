@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "harmonics.hpp"
 #include "resolve.hpp"
 
 #ifndef GRAV_M2M_LDS_MIN_WG
@@ -562,6 +563,188 @@ k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_star
                 }
             }
             // reduce the S source groups
+            __syncthreads();
+            for (int c = 0; c < 4; ++c)
+                red[t][c] = (double)acc[c];
+            __syncthreads();
+            if (si == 0 && valid) {
+                double s4[4] = {0, 0, 0, 0};
+                for (int k = 0; k < S; ++k)
+                    for (int c = 0; c < 4; ++c)
+                        s4[c] += red[k * TC + ti][c];
+                double *o = near + (j * g.B + bm) * 4;
+                for (int c = 0; c < 4; ++c)
+                    o[c] = s4[c];
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Explicit sources (scattered points with volumes).  P2M: the expansion of
+// a leaf is the sum over its sources of the mass times the multipole basis
+// at the source (the lattice P2M's basis: R_n^0, Re R_n^m, -Im R_n^m at
+// u = (x - centre) / b).  One workgroup per (leaf of the source block, MG
+// models): sources in chunks of kSrcChunk, their harmonics and masses in
+// LDS, every thread adding the products of the (model, coefficient) sums it
+// owns in source order (deterministic).
+// --------------------------------------------------------------------------
+constexpr int kSrcChunk = 24, kSrcModels = 4;
+
+template <int MG>
+__global__ void __launch_bounds__(256)
+k_p2m_src(DevGeom g, const double *spos, const double *sw, const uint32_t *sperm, const int64_t *sstart,
+          int64_t nsrc, const double *rho, double *me)
+{
+    extern __shared__ double sh[];
+    constexpr int TC = kSrcChunk;
+    const int P2 = g.P2;
+    double *H = sh;            // [TC][P2] harmonics of the chunk's sources
+    double *W = sh + TC * P2;  // [TC][MG] their masses
+    const int64_t leaf = blockIdx.x;
+    const int bm0 = blockIdx.y * MG;
+    const int tid = threadIdx.x;
+    const DevLev &lv = g.lev[g.L];
+    const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
+              lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+    const double inv_b = 1.0 / (double)g.b;
+    const double centre[3] = {(lx + 0.5) * g.b, (ly + 0.5) * g.b, (lz + 0.5) * g.b};
+    const int64_t ts = sstart[leaf], te = sstart[leaf + 1];
+    const int NO = MG * P2;  // sums (model, h), o = mg P2 + h
+    constexpr int NJ = MG;   // sums per thread (p^2 <= 256)
+    double acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        acc[j] = 0.0;
+    for (int64_t j0 = ts; j0 < te; j0 += TC) {
+        const int nt = (int)min((int64_t)TC, te - j0);
+        if (tid < nt) {
+            const int64_t i = j0 + tid;
+            regular_harmonics(g.P, (spos[3 * i + 0] - centre[0]) * inv_b, (spos[3 * i + 1] - centre[1]) * inv_b,
+                              (spos[3 * i + 2] - centre[2]) * inv_b, H + tid * P2, 1);
+        }
+        for (int i = tid; i < nt * MG; i += 256) {
+            const int t = i / MG, bm = bm0 + i % MG;
+            W[i] = bm < g.B ? rho[(int64_t)bm * nsrc + sperm[j0 + t]] * sw[j0 + t] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int o = tid + 256 * j;
+            if (o < NO) {
+                const int h = o % P2, mg = o / P2;
+                double v = acc[j];
+                for (int t = 0; t < nt; ++t)
+                    v += H[t * P2 + h] * W[t * MG + mg];
+                acc[j] = v;
+            }
+        }
+        __syncthreads();
+    }
+    // coefficient h: the real parts as summed, the imaginary parts negated
+    // (conjugate harmonic); padding coefficients zero
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int o = tid + 256 * j;
+        if (o < NO) {
+            const int h = o % P2, bm = bm0 + o / P2;
+            if (bm < g.B) {
+                int n = 0;
+                while ((n + 1) * (n + 1) <= h)
+                    ++n;
+                const int r = h - n * n;
+                const bool im = r > 0 && (r & 1) == 0;
+                me[((lv.me_off + leaf) * g.B + bm) * g.PS + h] = im ? -acc[j] : acc[j];
+            }
+        }
+    }
+    for (int i = tid; i < MG * (g.PS - P2); i += 256) {
+        const int bm = bm0 + i / (g.PS - P2), k = P2 + i % (g.PS - P2);
+        if (bm < g.B)
+            me[((lv.me_off + leaf) * g.B + bm) * g.PS + k] = 0.0;
+    }
+}
+
+// Near field with explicit sources: direct sum over the sources of the 27
+// leaves around a target leaf (the near term of Eq. (13)), coincident pairs
+// skipped.  One workgroup per target leaf; each neighbour leaf's sources are
+// staged in LDS in chunks of 256 (positions relative to the target leaf's
+// corner, and masses); targets over lanes, and when a leaf holds fewer than
+// 256 targets, sources over several lane groups reduced through LDS in a
+// fixed order.  Output as k_p2p: near = (sum m/r, sum m d/r^3), lattice frame.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_p2p_src(DevGeom g, const double *rho, const double *spos, const double *sw, const uint32_t *sperm,
+          const int64_t *sstart, int64_t nsrc, const double *tpos, const int64_t *leaf_start, const int64_t *leaf_end,
+          const uint32_t *tkey, double *near)
+{
+    __shared__ T sp[256][4];
+    __shared__ double red[256][4];
+    const DevLev &lv = g.lev[g.L];
+    const int64_t leaf = blockIdx.x;
+    const int64_t ts = leaf_start[leaf], te = leaf_end[leaf];
+    const int64_t nt = te - ts;
+    if (nt <= 0)
+        return;
+    const uint32_t key = tkey[lv.tbox_off + leaf];
+    const int lc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
+    double corner[3];
+    for (int a = 0; a < 3; ++a)
+        corner[a] = (double)((lc[a] - g.shift[a]) * g.b);
+    int TC = 1;
+    while (TC < nt && TC < 256)
+        TC <<= 1;
+    const int S = 256 / TC;
+    const int t = threadIdx.x;
+    const int ti = t % TC, si = t / TC;
+    for (int bm = 0; bm < g.B; ++bm) {
+        for (int64_t c0 = 0; c0 < nt; c0 += TC) {
+            const int64_t j = ts + c0 + ti;
+            const bool valid = (c0 + ti) < nt;
+            T tl[3] = {0, 0, 0};
+            if (valid)
+                for (int a = 0; a < 3; ++a)
+                    tl[a] = (T)(tpos[3 * j + a] - corner[a]);
+            T acc[4] = {0, 0, 0, 0};
+            for (int nb = 0; nb < 27; ++nb) {
+                const int d[3] = {nb % 3 - 1, (nb / 3) % 3 - 1, nb / 9 - 1};
+                int r[3];
+                bool inb = true;
+                for (int a = 0; a < 3; ++a) {
+                    r[a] = lc[a] + d[a] - lv.s0[a];
+                    inb = inb && r[a] >= 0 && r[a] < lv.ns[a];
+                }
+                if (!inb)
+                    continue;  // uniform over the workgroup
+                const int64_t jl = ((int64_t)r[2] * lv.ns[1] + r[1]) * lv.ns[0] + r[0];
+                const int64_t sa = sstart[jl], se = sstart[jl + 1];
+                for (int64_t s0 = sa; s0 < se; s0 += 256) {
+                    const int ns = (int)min((int64_t)256, se - s0);
+                    __syncthreads();
+                    if (t < ns) {
+                        const int64_t i = s0 + t;
+                        for (int a = 0; a < 3; ++a)
+                            sp[t][a] = (T)(spos[3 * i + a] - corner[a]);
+                        sp[t][3] = (T)(rho[(int64_t)bm * nsrc + sperm[i]] * sw[i]);
+                    }
+                    __syncthreads();
+                    if (!valid)
+                        continue;
+                    for (int v = si; v < ns; v += S) {
+                        const T cx = tl[0] - sp[v][0], cy = tl[1] - sp[v][1], cz = tl[2] - sp[v][2];
+                        const T r2 = cx * cx + cy * cy + cz * cz;
+                        if (r2 > coincident2<T>()) {
+                            const T ri = rsqrt_t(r2);
+                            const T m = sp[v][3] * ri;
+                            const T m3 = m * ri * ri;
+                            acc[0] += m;
+                            acc[1] += m3 * cx;
+                            acc[2] += m3 * cy;
+                            acc[3] += m3 * cz;
+                        }
+                    }
+                }
+            }
             __syncthreads();
             for (int c = 0; c < 4; ++c)
                 red[t][c] = (double)acc[c];
@@ -1161,7 +1344,22 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         return GRAV_OK;
     if (L >= 2) {
         stage_begin(p, "p2m", s);
-        GRAV_CHECK(launch_p2m(p, g, rho, s));
+        if (p->n_spts > 0) {
+            const int MG = p->B == 1 ? 1 : kSrcModels;
+            const size_t lds = sizeof(double) * (size_t)std::max(kSrcChunk * (p->P2 + MG), MG * p->P2);
+            const dim3 sg((unsigned)p->lev[L].n_src, (unsigned)((p->B + MG - 1) / MG));
+            if (MG == 1)
+                hipLaunchKernelGGL((k_p2m_src<1>), sg, dim3(256), lds, s, g, (const double *)p->d_spos,
+                                   (const double *)p->d_sw, (const uint32_t *)p->d_sperm,
+                                   (const int64_t *)p->d_sstart, p->n_spts, rho, p->d_me);
+            else
+                hipLaunchKernelGGL((k_p2m_src<kSrcModels>), sg, dim3(256), lds, s, g, (const double *)p->d_spos,
+                                   (const double *)p->d_sw, (const uint32_t *)p->d_sperm,
+                                   (const int64_t *)p->d_sstart, p->n_spts, rho, p->d_me);
+            GRAV_HIP(hipGetLastError());
+        } else {
+            GRAV_CHECK(launch_p2m(p, g, rho, s));
+        }
         stage_end(p, s);
         stage_begin(p, "m2m", s);
         for (int l = L - 1; l >= 2; --l)
@@ -1217,7 +1415,19 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
     }
     if (!p->lat_near || p->d.n_points > 0) {
         stage_begin(p, "p2p", s);
-        if (p->d.precision == GRAV_FP64)
+        if (p->n_spts > 0 && p->d.precision == GRAV_FP64)
+            hipLaunchKernelGGL(k_p2p_src<double>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+                               (const double *)p->d_spos, (const double *)p->d_sw, (const uint32_t *)p->d_sperm,
+                               (const int64_t *)p->d_sstart, p->n_spts, (const double *)p->d_tpos,
+                               (const int64_t *)p->d_leaf_start, (const int64_t *)p->d_leaf_pend,
+                               (const uint32_t *)p->d_tkey, p->d_near);
+        else if (p->n_spts > 0)
+            hipLaunchKernelGGL(k_p2p_src<float>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+                               (const double *)p->d_spos, (const double *)p->d_sw, (const uint32_t *)p->d_sperm,
+                               (const int64_t *)p->d_sstart, p->n_spts, (const double *)p->d_tpos,
+                               (const int64_t *)p->d_leaf_start, (const int64_t *)p->d_leaf_pend,
+                               (const uint32_t *)p->d_tkey, p->d_near);
+        else if (p->d.precision == GRAV_FP64)
             hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
                                (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
                                (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, p->d_near);

@@ -92,6 +92,7 @@ struct Plan {
     double root0[3] = {0, 0, 0};   // root lower corner
     int shift[3] = {0, 0, 0};      // leaves between root corner and the mesh origin
     int64_t M = 0;                 // evaluation points
+    int64_t n_spts = 0;            // explicit sources (0: the cells' quadrature points)
     int64_t n_leaf = 0;            // leaves holding evaluation points
     LevelInfo lev[kMaxLevels + 1];
     int64_t n_me = 0, n_le = 0;    // expansions (per model) in the ME / LE arrays
@@ -100,6 +101,14 @@ struct Plan {
 
     // device buffers
     double *d_points = nullptr;    // [n_points][3] user points (unsorted)
+    // explicit sources, sorted by their leaf (dense index in the leaf
+    // level's source block): lattice-frame positions, mass per unit input
+    // value (volume / h^3, or 1 / h^3), sorted -> user index, and the CSR
+    // of each leaf's sources
+    double *d_spos = nullptr;      // [n_spts][3]
+    double *d_sw = nullptr;        // [n_spts]
+    uint32_t *d_sperm = nullptr;   // [n_spts]
+    int64_t *d_sstart = nullptr;   // [leaves of the leaf-level source block + 1]
     uint32_t *d_perm = nullptr;    // [M] sorted position -> user index
     double *d_tpos = nullptr;      // [M][3] sorted target positions
     int32_t *d_tleaf = nullptr;    // [M] sorted target -> leaf (index in level-L list)

@@ -220,6 +220,33 @@ __global__ void k_count_p2p(const uint32_t *lkeys, const int64_t *leaf_start, in
     atomicAdd(acc, cells * (unsigned long long)a.nq3 * (unsigned long long)(leaf_start[i + 1] - leaf_start[i]));
 }
 
+// Point pairs of the near field with explicit sources: per target leaf, its
+// targets times the sources of its 27 neighbour leaves.
+__global__ void k_count_p2p_src(const uint32_t *lkeys, const int64_t *leaf_start, int64_t n, CountArgs a,
+                                const int64_t *sstart, unsigned long long *acc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t k = lkeys[i];
+    const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+    unsigned long long srcs = 0;
+    for (int nb = 0; nb < 27; ++nb) {
+        const int d[3] = {nb % 3 - 1, (nb / 3) % 3 - 1, nb / 9 - 1};
+        int r[3];
+        bool in = true;
+        for (int ax = 0; ax < 3; ++ax) {
+            r[ax] = c[ax] + d[ax] - a.s0[ax];
+            in = in && r[ax] >= 0 && r[ax] < a.ns[ax];
+        }
+        if (!in)
+            continue;
+        const int64_t j = ((int64_t)r[2] * a.ns[1] + r[1]) * a.ns[0] + r[0];
+        srcs += (unsigned long long)(sstart[j + 1] - sstart[j]);
+    }
+    atomicAdd(acc, srcs * (unsigned long long)(leaf_start[i + 1] - leaf_start[i]));
+}
+
 __global__ void k_fill_last(int64_t *leaf_start, int64_t n_leaf, int64_t M)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -290,7 +317,8 @@ void free_plan(Plan *p)
                     p->d_cell_slot, p->d_leaf_pend, p->d_m2lt_tiles, p->d_m2lt_items, p->d_m2lt_segs,
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
                     p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
-                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk};
+                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk,
+                    p->d_spos, p->d_sw, p->d_sperm, p->d_sstart};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -335,6 +363,20 @@ grav_status validate(const grav_plan_desc *d)
         return GRAV_EINVAL;
     if (!std::isfinite(d->G))
         return GRAV_EINVAL;
+    if (d->n_sources < 0 || (d->n_sources > 0 && (!d->sources || d->quad_order != 1)))
+        return GRAV_EINVAL;
+    if (d->n_sources > 0xffffffffll)
+        return GRAV_EUNSUPPORTED;
+    for (int64_t i = 0; i < d->n_sources; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            const int n = a == 0 ? d->nx : a == 1 ? d->ny : d->nz;
+            const double u = (d->sources[3 * i + a] - d->origin[a]) / d->h;
+            if (!(u >= 0.0 && u < (double)n))
+                return GRAV_EINVAL;  // outside the mesh box (or not finite)
+        }
+        if (d->source_volumes && !(d->source_volumes[i] > 0.0 && std::isfinite(d->source_volumes[i])))
+            return GRAV_EINVAL;
+    }
     const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
     const int64_t M = d->n_points + (d->voxel_centres ? ncell : 0);
     if (M > 0xffffffffll || (int64_t)d->nx > 0x3fffffff)
@@ -1066,7 +1108,8 @@ grav_status build_adjoint_maps(Plan *p)
 grav_status build_near_lattice(Plan *p, hipStream_t s)
 {
     const int64_t M = p->M, npts = p->d.n_points;
-    p->lat_near = p->d.voxel_centres && p->b <= kMaxLatticeLeaf;
+    // the lattice near field pairs lattice targets with lattice sources
+    p->lat_near = p->d.voxel_centres && p->b <= kMaxLatticeLeaf && p->n_spts == 0;
     GRAV_CHECK(dalloc(p, &p->d_leaf_pend, p->n_leaf, true));
     hipLaunchKernelGGL(k_leaf_point_end, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, s,
                        (const uint32_t *)p->d_perm, (const int64_t *)p->d_leaf_start, p->n_leaf,
@@ -1267,9 +1310,15 @@ grav_status count_work(Plan *p)
                 a.s0[ax] = p->lev[p->L].s0[ax];
                 a.ns[ax] = p->lev[p->L].ns[ax];
             }
-            hipLaunchKernelGGL(k_count_p2p, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, p->bs,
-                               (const uint32_t *)(p->d_tkey + p->tbox_off[p->L]),
-                               (const int64_t *)p->d_leaf_start, p->n_leaf, a, acc + 1);
+            if (p->n_spts > 0)
+                hipLaunchKernelGGL(k_count_p2p_src, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, p->bs,
+                                   (const uint32_t *)(p->d_tkey + p->tbox_off[p->L]),
+                                   (const int64_t *)p->d_leaf_start, p->n_leaf, a, (const int64_t *)p->d_sstart,
+                                   acc + 1);
+            else
+                hipLaunchKernelGGL(k_count_p2p, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, p->bs,
+                                   (const uint32_t *)(p->d_tkey + p->tbox_off[p->L]),
+                                   (const int64_t *)p->d_leaf_start, p->n_leaf, a, acc + 1);
         }
         unsigned long long h[2] = {0, 0};
         if (hipGetLastError() != hipSuccess ||
@@ -1282,6 +1331,116 @@ grav_status count_work(Plan *p)
         p->p2p_pairs = (int64_t)h[1];
     } while (0);
     (void)hipFree(acc);
+    return st;
+}
+
+// Explicit sources: the dense index of each source's leaf in the leaf
+// level's source block (the block starts at the mesh origin, so a source at
+// lattice position u lies in leaf floor(u / b)), the sort key.
+__global__ void k_source_keys(const double *src, int64_t n, double ox, double oy, double oz, double inv_h, int b,
+                              int nsx, int nsy, int nsz, uint32_t *keys, uint32_t *vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const double o[3] = {ox, oy, oz};
+    const int ns[3] = {nsx, nsy, nsz};
+    int c[3];
+    for (int a = 0; a < 3; ++a) {
+        const double u = (src[3 * i + a] - o[a]) * inv_h;
+        c[a] = min(max((int)floor(u / b), 0), ns[a] - 1);
+    }
+    keys[i] = (uint32_t)(((int64_t)c[2] * nsy + c[1]) * nsx + c[0]);
+    vals[i] = (uint32_t)i;
+}
+
+// Sorted sources: lattice-frame positions and the mass per unit input value.
+__global__ void k_gather_sources(const double *src, const double *vol, int64_t n, double ox, double oy, double oz,
+                                 double inv_h, const uint32_t *perm, double *pos, double *w)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int64_t u = perm[i];
+    const double o[3] = {ox, oy, oz};
+    for (int a = 0; a < 3; ++a)
+        pos[3 * i + a] = (src[3 * u + a] - o[a]) * inv_h;
+    const double ih3 = inv_h * inv_h * inv_h;
+    w[i] = (vol ? vol[u] : 1.0) * ih3;
+}
+
+// CSR of the sorted sources over the leaves: sorted source i starts every
+// leaf in (key[i-1], key[i]]; the last one also ends the leaves after it.
+__global__ void k_source_leaf_start(const uint32_t *keys, int64_t n, int64_t nleaf, int64_t *start)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n)
+        return;
+    const int64_t lo = i == 0 ? 0 : (int64_t)keys[i - 1] + 1;
+    const int64_t hi = i == n ? nleaf : (int64_t)keys[i];
+    for (int64_t l = lo; l <= hi && l <= nleaf; ++l)
+        start[l] = i;
+}
+
+// Explicit sources: sorted by leaf with the device radix sort, positions and
+// masses gathered, the per-leaf CSR built.
+grav_status build_sources(Plan *p, const grav_plan_desc *desc, hipStream_t s)
+{
+    const int64_t n = p->n_spts;
+    const LevelInfo &lv = p->lev[p->L];
+    const int64_t nleaf = lv.n_src;
+    int bits = 1;
+    while ((int64_t(1) << bits) < nleaf)
+        ++bits;
+    double *src = nullptr, *vol = nullptr;
+    uint32_t *keys = nullptr, *vals = nullptr, *ktmp = nullptr, *vtmp = nullptr, *scr = nullptr;
+    const size_t scr_words = radix_scratch_words(n);
+    grav_status st = GRAV_OK;
+    auto cleanup = [&]() {
+        void *bufs[] = {src, vol, keys, vals, ktmp, vtmp, scr};
+        for (void *b : bufs)
+            if (b)
+                (void)hipFree(b);
+    };
+    if (hipMalloc(&src, sizeof(double) * 3 * n) != hipSuccess ||
+        (desc->source_volumes && hipMalloc(&vol, sizeof(double) * n) != hipSuccess) ||
+        hipMalloc(&keys, 4 * n) != hipSuccess || hipMalloc(&vals, 4 * n) != hipSuccess ||
+        hipMalloc(&ktmp, 4 * n) != hipSuccess || hipMalloc(&vtmp, 4 * n) != hipSuccess ||
+        hipMalloc(&scr, 4 * std::max<size_t>(scr_words, 1)) != hipSuccess) {
+        cleanup();
+        return GRAV_ENOMEM;
+    }
+    do {
+        if ((st = dalloc(p, &p->d_spos, 3 * n, true)) != GRAV_OK || (st = dalloc(p, &p->d_sw, n, true)) != GRAV_OK ||
+            (st = dalloc(p, &p->d_sperm, n, true)) != GRAV_OK ||
+            (st = dalloc(p, &p->d_sstart, nleaf + 1, true)) != GRAV_OK)
+            break;
+        if (hipMemcpyAsync(src, desc->sources, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            (vol && hipMemcpyAsync(vol, desc->source_volumes, sizeof(double) * n, hipMemcpyHostToDevice, s) !=
+                        hipSuccess)) {
+            st = GRAV_EDEVICE;
+            break;
+        }
+        const dim3 g((unsigned)ceil_div(n, 256)), g1((unsigned)ceil_div(n + 1, 256));
+        const double inv_h = 1.0 / desc->h;
+        hipLaunchKernelGGL(k_source_keys, g, dim3(256), 0, s, (const double *)src, n, desc->origin[0],
+                           desc->origin[1], desc->origin[2], inv_h, p->b, lv.ns[0], lv.ns[1], lv.ns[2], keys, vals);
+        if (hipGetLastError() != hipSuccess || radix_sort_pairs(keys, vals, ktmp, vtmp, n, bits, scr, s) != GRAV_OK) {
+            st = GRAV_EDEVICE;
+            break;
+        }
+        hipLaunchKernelGGL(k_gather_sources, g, dim3(256), 0, s, (const double *)src, (const double *)vol, n,
+                           desc->origin[0], desc->origin[1], desc->origin[2], inv_h, (const uint32_t *)vals,
+                           p->d_spos, p->d_sw);
+        hipLaunchKernelGGL(k_source_leaf_start, g1, dim3(256), 0, s, (const uint32_t *)keys, n, nleaf, p->d_sstart);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(p->d_sperm, vals, 4 * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = GRAV_EDEVICE;
+            break;
+        }
+    } while (0);
+    cleanup();
     return st;
 }
 
@@ -1562,6 +1721,9 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
         return GRAV_ENOMEM;
     p->d = *desc;
     p->d.points = nullptr;
+    p->d.sources = nullptr;
+    p->d.source_volumes = nullptr;
+    p->n_spts = desc->n_sources;
     p->device = desc->device;
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(desc->device) != hipSuccess) {
@@ -1660,6 +1822,8 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             }
         }
         if (p->M > 0 && (st = build_tree(p, s)) != GRAV_OK)
+            break;
+        if (p->M > 0 && p->n_spts > 0 && (st = build_sources(p, desc, s)) != GRAV_OK)
             break;
         if (p->M > 0 && (st = build_near_lattice(p, s)) != GRAV_OK)
             break;
@@ -1781,7 +1945,7 @@ extern "C" grav_status grav_plan_work(grav_plan_t plan, int64_t *m2l_pairs, int6
     if (p2p_pairs)
         *p2p_pairs = p->p2p_pairs;
     if (n_sources)
-        *n_sources = (int64_t)p->d.nx * p->d.ny * p->d.nz * p->nq3;
+        *n_sources = p->n_spts > 0 ? p->n_spts : (int64_t)p->d.nx * p->d.ny * p->d.nz * p->nq3;
     return GRAV_OK;
 }
 

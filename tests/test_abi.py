@@ -62,3 +62,20 @@ def test_null_pointers_are_rejected():
     assert lib.grav_analytic(None, None, None, None) == _lib.GRAV_EINVAL
     assert lib.grav_plan(None, None) == _lib.GRAV_EINVAL
     assert lib.grav_status_string(_lib.GRAV_EBUSY).decode() != ""
+
+
+def test_explicit_source_descriptor_is_validated():
+    """Explicit sources must lie inside the mesh box, need the 1-point rule
+    and positive volumes (checked before any device work)."""
+    inside = np.array([[0.1, 0.2, 0.3], [0.9, 0.5, 0.5]])
+    for kw in (dict(sources=np.array([[1.2, 0.5, 0.5]])),                  # outside the box
+               dict(sources=np.array([[0.5, 0.5, float("nan")]])),         # not finite
+               dict(sources=inside, quad_order=2),                          # needs q = 1
+               dict(sources=inside, source_volumes=np.array([1e-3, 0.0]))):  # volume <= 0
+        spec = G.PlanSpec(n=(4, 4, 4), h=0.25, points=np.array([[0.5, 0.5, 1.5]]), **kw)
+        with pytest.raises(G.GravError) as e:
+            G.Plan(spec)
+        assert e.value.code == _lib.GRAV_EINVAL, kw
+    d = _lib.GravDesc()
+    G.load().grav_desc_init(ctypes.byref(d))
+    assert d.n_sources == 0 and not d.sources and not d.source_volumes
