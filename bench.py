@@ -512,6 +512,53 @@ def paper_sequence(args):
     print(json.dumps({"paper_sequence": rows}), flush=True)
 
 
+def scattered(args):
+    """Explicit sources: 2,097,152 scattered points (seed 1006, denser towards
+    z = 0) with volumes of a rough partition of the unit cube, a density per
+    point, gz at 256 x 256 stations at z = 1.1 and at 65,536 scattered points
+    inside; the octree framed by a 128^3 mesh (leaves of 4^3 cells, about 64
+    sources).  Mixed p = 10 and FP64 p = 14, forward and adjoint."""
+    import numpy as np
+    import torch
+
+    import paper_1107_5951_amd as G
+    import workloads as W
+    rng = np.random.default_rng(1006)
+    N = 1 << 21
+    src = rng.uniform(0.0, 1.0, size=(N, 3)) ** np.array([1.0, 1.0, 1.5])
+    vol = rng.uniform(0.5, 1.5, size=N) / N
+    dens = np.sin(3 * src[:, 0]) + np.cos(2 * src[:, 1]) * src[:, 2]
+    tg = np.concatenate([W.stations(256, 1.1), rng.uniform(0.0, 1.0, size=(65536, 3))])
+    sidx = W.sample_indices(tg.shape[0], 1024, seed=7)
+    row = {"workload": "2097152 scattered sources with volumes (128^3 frame, leaf 4^3 cells), gz at 256^2 "
+                       "stations + 65536 interior points"}
+    r = torch.as_tensor(dens[None], device="cuda")
+    samples = {}
+    for tag, prec, p in (("mixed", G.GRAV_MIXED, 10), ("fp64", G.GRAV_FP64, 14)):
+        t0 = time.perf_counter()
+        plan = G.Plan(G.PlanSpec(n=(128, 128, 128), h=1 / 128, points=tg, components=1, p=p, leaf_size=64,
+                                 precision=prec, sources=src, source_volumes=vol))
+        plan_s = time.perf_counter() - t0
+        out = torch.empty(plan.out_shape, dtype=torch.float64, device="cuda")
+        ms, lat = timed_steps(plan, r, out, 10, 2)
+        stg = stage_profile(plan, r, out, 3)
+        samples[tag] = out[0, torch.as_tensor(sidx, device="cuda"), 0].cpu().numpy()
+        adj_ms, adj_st = adjoint_profile(plan, plan.out_shape, 3)
+        m2l_pairs, p2p_pairs, _ = plan.work()
+        row[tag] = {"p": p, "value": tg.shape[0] / (ms * 1e-3), "ms_per_step": ms, "p50_ms": pct(lat, 50),
+                    "p99_ms": pct(lat, 99), "plan_s": plan_s, "stages_ms": stg, "adjoint_ms": adj_ms,
+                    "adjoint_stages_ms": adj_st, "p2p_point_pairs": p2p_pairs, "m2l_box_pairs": m2l_pairs}
+        del plan, out
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        import oracle
+        ref = oracle.points(src, dens * vol, tg[sidx], comps=4)[:, 3]
+        for tag in samples:
+            row[tag]["rel_err"] = oracle.rel_l2(samples[tag], ref)
+        row["rel_err_targets"] = len(sidx)
+    return row
+
+
 def serving(args):
     """The serving workload: a seeded Poisson trace (rate 50/s, seed 1005) of
     forward and adjoint requests (50/50) on meshes n = round(exp U[ln 32,
@@ -596,6 +643,9 @@ def main():
         torch.cuda.empty_cache()
         say("batched 128^3 workload")
         res["batched128_b32"] = batched128(args)
+        torch.cuda.empty_cache()
+        say("scattered sources")
+        res["scattered_sources"] = scattered(args)
     line = json.dumps(res)
     print(line, flush=True)
     if args.out:

@@ -82,6 +82,118 @@ __global__ void __launch_bounds__(64) k_p2m_mfma(DevGeom g, const double *rho, c
             dst[16 * r + kr + 4 * i] = acc[r][i];
 }
 
+// The same GEMM with the operator staged through LDS: a workgroup of four
+// waves owns 64 NCG columns (each wave NCG blocks of 16) and all row
+// blocks; the operator passes through LDS in double-buffered chunks of four
+// k steps (one barrier per chunk), so each chunk is read from L2 once per
+// 64 NCG columns instead of once per 16.
+template <int RB, int NCG>
+__global__ void __launch_bounds__(256) k_p2m_lds(DevGeom g, const double *rho, const double *A, int KV, double *me)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int CH = 4 * RB * 64;  // doubles per chunk
+    __shared__ double sa[2][CH];
+    const DevLev &lv = g.lev[g.L];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kr = lane >> 4;
+    const int b = g.b, b2 = b * b, b3 = b2 * b;
+    const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    bool cvalid[NCG];
+    int bm[NCG], cx[NCG], cy[NCG], cz[NCG];
+    int64_t leaf[NCG];
+#pragma unroll
+    for (int c = 0; c < NCG; ++c) {
+        const int64_t col = ((int64_t)blockIdx.x * 4 + wave) * 16 * NCG + c * 16 + (lane & 15);
+        cvalid[c] = col < nleaf * g.B;
+        bm[c] = cvalid[c] ? (int)(col / nleaf) : 0;
+        leaf[c] = cvalid[c] ? col - (int64_t)bm[c] * nleaf : 0;
+        const int lx = (int)(leaf[c] % lv.ns[0]), ly = (int)((leaf[c] / lv.ns[0]) % lv.ns[1]),
+                  lz = (int)(leaf[c] / ((int64_t)lv.ns[0] * lv.ns[1]));
+        cx[c] = (lv.s0[0] + lx - g.shift[0]) * b;
+        cy[c] = (lv.s0[1] + ly - g.shift[1]) * b;
+        cz[c] = (lv.s0[2] + lz - g.shift[2]) * b;
+    }
+    auto density = [&](int c, int ks) -> double {
+        const int v = 4 * ks + kr;
+        if (!cvalid[c] || ks >= KV || v >= b3)
+            return 0.0;
+        const int ix = cx[c] + v % b, iy = cy[c] + (v / b) % b, iz = cz[c] + v / b2;
+        if (ix < 0 || iy < 0 || iz < 0 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+            return 0.0;
+        return rho[(int64_t)bm[c] * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
+    };
+    // chunk j holds k steps 4 j .. 4 j + 3 (those past KV read zero)
+    auto load_chunk = [&](int j, double (&ra)[RB]) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int e = i * 256 + tid;
+            const int ks = 4 * j + e / (RB * 64);
+            ra[i] = ks < KV ? A[(int64_t)4 * j * RB * 64 + e] : 0.0;
+        }
+    };
+    const int NCH = (KV + 3) / 4;
+    vec4 acc[NCG][RB];
+#pragma unroll
+    for (int c = 0; c < NCG; ++c)
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            acc[c][r] = vec4{0, 0, 0, 0};
+    double ra[RB];
+    load_chunk(0, ra);
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        sa[0][i * 256 + tid] = ra[i];
+    double bv[NCG][4];
+#pragma unroll
+    for (int c = 0; c < NCG; ++c)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            bv[c][u] = density(c, u);
+    __syncthreads();
+    for (int j = 0; j < NCH; ++j) {
+        const int buf = j & 1;
+        const bool more = j + 1 < NCH;
+        if (more)
+            load_chunk(j + 1, ra);
+        double cur[NCG][4];
+#pragma unroll
+        for (int c = 0; c < NCG; ++c)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cur[c][u] = bv[c][u];
+                if (more)
+                    bv[c][u] = density(c, 4 * (j + 1) + u);
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const double a = sa[buf][(u * RB + r) * 64 + lane];
+#pragma unroll
+                for (int c = 0; c < NCG; ++c)
+                    acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cur[c][u], acc[c][r], 0, 0, 0);
+            }
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                sa[buf ^ 1][i * 256 + tid] = ra[i];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < NCG; ++c) {
+        if (!cvalid[c])
+            continue;
+        double *dst = me + ((lv.me_off + leaf[c]) * g.B + bm[c]) * PS;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                dst[16 * r + kr + 4 * i] = acc[c][r][i];
+    }
+}
+
 // --------------------------------------------------------------------------
 // M2M on MFMA (FP64): ME[parent] = sum over the 8 children c of T_c ME[child],
 // a GEMM with M = p^2 rows, K = 8 p^2 and columns = (parent box, model).
@@ -1238,9 +1350,20 @@ static grav_status launch_p2m(Plan *p, const DevGeom &g, const double *rho, hipS
     const int b3 = p->b * p->b * p->b;
     const int KV = (b3 + 3) / 4;
     const dim3 grid((unsigned)((p->lev[p->L].n_src * p->B + 15) / 16)), blk(64);
+    // the LDS-staged GEMM once it gives every CU a few workgroups
+    const int64_t ncol = p->lev[p->L].n_src * p->B;
+    const bool lds = (ncol + 127) / 128 >= 1024;
+    const dim3 grid2((unsigned)((ncol + 127) / 128)), grid1((unsigned)((ncol + 63) / 64));
 #define P2M_CASE(R)                                                                             \
     case R:                                                                                     \
-        hipLaunchKernelGGL((k_p2m_mfma<R>), grid, blk, 0, s, g, rho, (const double *)p->d_pm_sw, KV, p->d_me); \
+        if (lds && R <= 8)                                                                      \
+            hipLaunchKernelGGL((k_p2m_lds<R, 2>), grid2, dim3(256), 0, s, g, rho, (const double *)p->d_pm_sw, KV, \
+                               p->d_me);                                                        \
+        else if (lds)                                                                           \
+            hipLaunchKernelGGL((k_p2m_lds<R, 1>), grid1, dim3(256), 0, s, g, rho, (const double *)p->d_pm_sw, KV, \
+                               p->d_me);                                                        \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_p2m_mfma<R>), grid, blk, 0, s, g, rho, (const double *)p->d_pm_sw, KV, p->d_me); \
         break;
     switch (RB) {
         P2M_CASE(1)
