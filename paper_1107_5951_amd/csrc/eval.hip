@@ -374,6 +374,88 @@ __global__ void __launch_bounds__(512) k_m2m_split(DevGeom g, int l, const doubl
 // level l, grouped by child octant c (the M2L tiles of the level: same
 // columns, one matrix per tile).  Four waves of 16 columns per workgroup.
 // --------------------------------------------------------------------------
+// L2L, LDS-tiled (FP64 MFMA): a workgroup takes one M2L tile of a level (64
+// target-box columns of one child octant, so one matrix) with all row
+// blocks; the matrix passes through LDS in double-buffered chunks of four k
+// steps, each wave streams its 16 columns' parent expansions once and adds
+// the products into the children's LE.
+// --------------------------------------------------------------------------
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_l2l_lds(DevGeom g, const GemmTile *tiles, int stride, const int32_t *torder, const int32_t *tparent, const double *A,
+          double *le)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    constexpr int PS = 16 * RB;
+    constexpr int K4 = PS / 4;
+    constexpr int CH = 4 * RB * 64;
+    __shared__ double sa[2][CH];
+    const GemmTile tile = tiles[(int64_t)blockIdx.x * stride];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kr = lane >> 4;
+    const DevLev &lv = g.lev[tile.level];
+    const DevLev &lp = g.lev[tile.level - 1];
+    const int cl = wave * 16 + (lane & 15);
+    const bool cvalid = cl < tile.ncol;
+    const int64_t col = tile.col0 + cl;
+    const int bm = (int)(col % g.B);
+    int64_t box = 0, par = 0;
+    if (cvalid) {
+        box = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
+        par = tparent[lv.tbox_off + box];
+    }
+    const double2 *bp = (const double2 *)(le + ((lp.tgt_off + par) * g.B + bm) * PS + kr * K4);
+    const double *Ao = A + (int64_t)tile.cls * PS * PS;
+    vec4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        acc[r] = vec4{0, 0, 0, 0};
+    double ra[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        ra[i] = Ao[i * 256 + tid];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        sa[0][i * 256 + tid] = ra[i];
+    double2 b01 = cvalid ? bp[0] : double2{0.0, 0.0};
+    double2 b23 = cvalid ? bp[1] : double2{0.0, 0.0};
+    __syncthreads();
+    for (int j = 0; j < RB; ++j) {
+        const int buf = j & 1;
+        const bool more = j + 1 < RB;
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                ra[i] = Ao[(int64_t)(j + 1) * CH + i * 256 + tid];
+        }
+        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+        if (more) {
+            b01 = cvalid ? bp[2 * (j + 1)] : double2{0.0, 0.0};
+            b23 = cvalid ? bp[2 * (j + 1) + 1] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                                                             0);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                sa[buf ^ 1][i * 256 + tid] = ra[i];
+        }
+        __syncthreads();
+    }
+    if (!cvalid)
+        return;
+    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            dst[16 * r + kr + 4 * i] += acc[r][i];
+}
+
+// --------------------------------------------------------------------------
 // L2L on MFMA (FP64): LE[child] += T_c LE[parent] for the target boxes of
 // level l, grouped by child octant c (the M2L tiles of the level: same
 // columns, one matrix per tile).  A workgroup takes one tile (four waves of
@@ -1395,11 +1477,19 @@ static grav_status launch_l2l(Plan *p, const DevGeom &g, int l, hipStream_t s)
     const int S = p->split[TK_M2L];
     const GemmTile *t0 = (const GemmTile *)(p->d_tiles + all.off) + r.off * S;
     dim3 grid((unsigned)r.n, (unsigned)(p->PS / 16)), blk(256);
+    // one workgroup per tile with all row blocks once the level has enough
+    // tiles to fill the chip; otherwise one workgroup per (tile, row block)
+    const bool tiled = r.n >= GRAV_M2M_LDS_MIN_WG;
 #define L2L_CASE(R)                                                                             \
     case R:                                                                                     \
-        hipLaunchKernelGGL((k_l2l_mfma<R>), grid, blk, 0, s, g, t0, S, (const uint32_t *)p->d_tkey, \
-                           (const int32_t *)p->d_torder, (const int32_t *)p->d_tparent,         \
-                           (const double *)p->d_l2l_sw, p->d_le);                               \
+        if (tiled)                                                                              \
+            hipLaunchKernelGGL((k_l2l_lds<R>), dim3((unsigned)r.n), blk, 0, s, g, t0, S,        \
+                               (const int32_t *)p->d_torder, (const int32_t *)p->d_tparent,     \
+                               (const double *)p->d_l2l_msw, p->d_le);                          \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_l2l_mfma<R>), grid, blk, 0, s, g, t0, S, (const uint32_t *)p->d_tkey, \
+                               (const int32_t *)p->d_torder, (const int32_t *)p->d_tparent,     \
+                               (const double *)p->d_l2l_sw, p->d_le);                           \
         break;
     switch (p->PS / 16) {
         L2L_CASE(1)

@@ -157,6 +157,7 @@ struct Plan {
     int64_t *d_lat_tab = nullptr;                  // [27 Q][2] per near chunk: density and operator offsets
     double *d_m2m_sw = nullptr;                    // [8][PS/4][RB][64] M2M as MFMA A fragments (FP64)
     double *d_l2l_sw = nullptr;                    // [8][KS][RB][64] L2L likewise
+    double *d_l2l_msw = nullptr;                   // [8][PS/4][RB][64] L2L, as d_m2m_sw (forward, LDS-tiled)
     double *d_m2mt_sw = nullptr;                   // [8][PS/4][RB][64] M2M^T, as d_m2m_sw (adjoint)
     double *d_l2lt_sw = nullptr;                   // [8][PS/4][RB][64] L2L^T, as d_m2m_sw (adjoint)
     double *d_pmt_sw = nullptr;                    // [PS/4][ceil(b^3/16)][64] P2M^T fragments (adjoint)

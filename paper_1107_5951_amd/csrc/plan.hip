@@ -317,7 +317,7 @@ void free_plan(Plan *p)
                     p->d_cell_slot, p->d_leaf_pend, p->d_m2lt_tiles, p->d_m2lt_items, p->d_m2lt_segs,
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
                     p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
-                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk,
+                    p->d_m2mt_sw, p->d_l2lt_sw, p->d_l2l_msw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk,
                     p->d_spos, p->d_sw, p->d_sperm, p->d_sstart};
     for (void *b : bufs)
         if (b)
@@ -595,6 +595,15 @@ grav_status build_operators(Plan *p)
                     }
         GRAV_CHECK(upload(p, &p->d_m2mt_sw, mtsw));
         GRAV_CHECK(upload(p, &p->d_l2lt_sw, ltsw));
+        // L2L in the same layout for the forward's LDS-tiled kernel
+        std::vector<double> lmsw(8 * per8);
+        for (int c = 0; c < 8; ++c)
+            for (int ks = 0; ks < K4; ++ks)
+                for (int rb = 0; rb < RB; ++rb)
+                    for (int lane = 0; lane < 64; ++lane)
+                        lmsw[per8 * c + ((size_t)ks * RB + rb) * 64 + lane] =
+                            l2l[per8 * c + (size_t)(16 * rb + lane % 16) * PS + (lane / 16) * K4 + ks];
+        GRAV_CHECK(upload(p, &p->d_l2l_msw, lmsw));
     }
 
     // M2L for all 316 offsets, swizzled for the MFMA A operand, and their transposes
