@@ -150,7 +150,7 @@ def measured_traffic(profile, kernel_name):
             k, v = line.strip().split(":", 1)
             fields[k.strip()] = v.strip()
     src = b"".join(open(os.path.join(ROOT, "paper_1107_5951_amd", "csrc", f), "rb").read()
-                   for f in ("m2l.hip", "eval_common.hpp"))
+                   for f in ("m2l.hip", "eval_common.hpp", "internal.hpp", "resolve.hpp"))
     if fields.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
         return None
     if not kernel_name.startswith(fields.get("kernel", "?")):
@@ -168,7 +168,7 @@ def m2l_kernel_name(p, prec):
     p2 = p * p
     if prec == GRAV_FP64:
         return "k_m2l<%d,%d,1,double,*>" % (-(-p2 // 16), -(-p2 // 4))
-    return "k_m2l<%d,%d,2,float,*>" % (-(-p2 // 16), -(-p2 // 4))
+    return "k_m2l<%d,%d,*,float,*>" % (-(-p2 // 16), -(-p2 // 4))
 
 
 def roofline(plan, stages, p, prec, profile):

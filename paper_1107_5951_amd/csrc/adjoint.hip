@@ -850,13 +850,14 @@ static grav_status m2l_transposed_t(Plan *p, const DevGeom &g, hipStream_t s, co
     r.part = reinterpret_cast<T *>(p->d_partt);
     r.wgs = p->m2lt_wgs;
     r.nset = p->m2lt_nset;
+    r.nc = p->m2lt_nc;
     GRAV_CHECK(launch_m2l<T>(p, gt, s, r));
     const int64_t ns = p->m2lt_ncols * p->PS;
     if (ns > 0) {
         hipLaunchKernelGGL((k_m2lt_sum<T>), dim3((unsigned)ceil_div(ns, 256)), dim3(256), 0, s,
                            (const T *)p->d_partt, (const int32_t *)p->d_m2lt_colmap, (const int64_t *)p->d_m2lt_colbox,
                            (const int32_t *)p->d_m2lt_tseg_start, (const int32_t *)p->d_m2lt_tsegs, p->m2lt_ncols,
-                           p->PS, p->m2l_ncw, p->d_me);
+                           p->PS, p->m2lt_ncw, p->d_me);
         GRAV_HIP(hipGetLastError());
     }
     return GRAV_OK;

@@ -296,7 +296,7 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
         // columns, each ME column at most once; the gather regions lie in
         // the target maps (source block + halo 3)
         if (ck.ok) {
-            const int64_t nunit = p->m2lt_nunit, ntile = nunit / upt;
+            const int64_t uptt = 64 / p->m2lt_ncw, nunit = p->m2lt_nunit, ntile = nunit / uptt;
             if (p->m2lt_wgs > 0)
                 schedule("m2lT", p->d_m2lt_items, p->m2lt_items, p->d_m2lt_segs, p->m2lt_nseg, p->d_m2lt_wgseg,
                          p->m2lt_wgs, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, nunit);
@@ -330,8 +330,8 @@ extern "C" grav_status grav_plan_check(grav_plan_t plan, char *msg, int32_t msgl
             for (int64_t c = 0; c < p->m2lt_ncols && ck.ok; ++c) {
                 const int32_t m = colmap[c];
                 const int64_t u = m >> 6;
-                if (m < 0 || u >= nunit || (m & 63) >= p->m2l_ncw ||
-                    (u % upt) * p->m2l_ncw + (m & 63) >= ttiles[u / upt].ncol)
+                if (m < 0 || u >= nunit || (m & 63) >= p->m2lt_ncw ||
+                    (u % uptt) * p->m2lt_ncw + (m & 63) >= ttiles[u / uptt].ncol)
                     ck.fail("m2lT", "column without a unit column", c, m);
                 else if (colbox[c] < 0 || colbox[c] >= p->n_me * p->B || seen[colbox[c]]++)
                     ck.fail("m2lT", "ME column out of range or repeated", c, colbox[c]);

@@ -1386,6 +1386,7 @@ static M2LRun<T> forward_m2l(const Plan *p, const T *K)
     r.part = reinterpret_cast<T *>(p->d_part);
     r.wgs = p->m2l_wgs;
     r.nset = p->m2l_nset;
+    r.nc = p->m2l_nc;
     return r;
 }
 

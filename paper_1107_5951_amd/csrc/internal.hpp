@@ -14,12 +14,21 @@ namespace grav {
 constexpr int kMaxP = 16;
 constexpr int kMaxLevels = 10;
 
-// Forward M2L: 16-column blocks per wave (1, 2 or 4) for the FP32 and FP64
-// kernels: each A fragment feeds this many instructions; a workgroup holds
-// 4 / NC waves (64 columns).  FP64 keeps one block: its accumulators for two
-// would leave one wave per SIMD.
+// M2L: 16-column blocks per wave (1, 2 or 4) for the FP32 and FP64
+// kernels: each A fragment feeds this many instructions; a tile of 64
+// columns holds 4 / NC units.  FP64 keeps one block: its accumulators for
+// two would leave one wave per SIMD.
 #ifndef GRAV_M2L_NC32
 #define GRAV_M2L_NC32 2
+#endif
+// FP32 plans with at least this many (box, model) columns take four blocks
+// per wave (twice the operator reuse, two waves per SIMD instead of three):
+// large plans gain, small ones lose their few work items per wave
+#ifndef GRAV_M2L_NC32_WIDE
+#define GRAV_M2L_NC32_WIDE 4
+#endif
+#ifndef GRAV_M2L_WIDE_COLUMNS
+#define GRAV_M2L_WIDE_COLUMNS 131072
 #endif
 #ifndef GRAV_M2L_NC64
 #define GRAV_M2L_NC64 1
@@ -128,6 +137,7 @@ struct Plan {
     // segment slots (CSR), and LE column -> 64 * unit + column in unit
     int32_t m2l_wgs = 0, m2l_ncw = 64;  // workgroups (one wave each); columns per unit
     int32_t m2l_nset = 2;               // operand register sets of the FP32 M2L kernel (1 or 2)
+    int32_t m2l_nc = 1;                 // 16-column blocks per wave of the M2L kernel
     int64_t m2l_nseg = 0, m2l_items = 0, m2l_nunit = 0;
     int32_t *d_m2l_items = nullptr, *d_m2l_segs = nullptr, *d_m2l_wgseg = nullptr;
     int32_t *d_m2l_tseg_start = nullptr, *d_m2l_tsegs = nullptr, *d_m2l_colmap = nullptr;
@@ -137,7 +147,7 @@ struct Plan {
     // d_tkey/d_torder the target boxes; class_off holds (-d, operator of
     // K_d^T) per source class; the operators are K_d^T in the forward's
     // panel layout (56 canonical ones in mixed plans, all 316 in FP64)
-    int32_t m2lt_wgs = 0, m2lt_nset = 2;
+    int32_t m2lt_wgs = 0, m2lt_nset = 2, m2lt_nc = 1, m2lt_ncw = 64;
     int64_t m2lt_nseg = 0, m2lt_ncols = 0, m2lt_nunit = 0, m2lt_items = 0, n_leg = 0;
     struct GemmTile *d_m2lt_tiles = nullptr;
     int32_t *d_m2lt_items = nullptr, *d_m2lt_segs = nullptr, *d_m2lt_wgseg = nullptr;

@@ -7,13 +7,18 @@
 
 // Operand register sets of the M2L (NS template parameter): with two sets
 // the loads of the next chunk are in flight during this chunk's MFMAs; with
-// one, the registers leave room for more waves per SIMD (three at p = 10 in
-// FP32, five at p = 8), which hide the load latency better on large plans
-// (256^3 volume workload: M2L 10.5 against 10.9 ms at p = 10, 4.3 against
-// 4.6 ms at p = 8) but not on small ones, where each wave has only a few
-// work items (64^3: 0.20 against 0.18 ms).  The plan picks the FP32 variant
-// by its work per resident wave (see build_tiles); the FP64 kernel keeps two
-// sets while a chunk's A values fit this many bytes per lane.
+// one, the registers leave room for more waves per SIMD (with two column
+// blocks: three at p = 10 in FP32, five at p = 8), which hide the load
+// latency better on large plans (256^3 volume workload: M2L 10.5 against
+// 10.9 ms at p = 10, 4.3 against 4.6 ms at p = 8) but not on small ones,
+// where each wave has only a few work items (64^3: 0.20 against 0.18 ms).
+// The plan picks the FP32 variant by its work per resident wave (see
+// build_tiles), and the number of 16-column blocks per wave by its column
+// count: four blocks (each operator fragment feeds four instructions, two
+// waves per SIMD) took the 256^3 M2L from 10.5 to 10.2 ms at p = 10 and from
+// 4.3 to 4.05 ms at p = 8, but slowed the 64^3 one (0.20 to 0.22 ms).  The
+// FP64 kernel keeps two sets while a chunk's A values fit this many bytes
+// per lane.
 #ifndef GRAV_M2L_DB_BYTES64
 #define GRAV_M2L_DB_BYTES64 512
 #endif
@@ -321,17 +326,25 @@ grav_status launch_m2l(const Plan *p, const DevGeom &g, hipStream_t s, const M2L
 {
     if (r.wgs == 0)
         return GRAV_OK;
-    constexpr int NC = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;  // column blocks per wave
+    // column blocks per wave: FP64 one; FP32 the plan's (narrow or wide)
+    constexpr int NCN = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
+    constexpr int NCW = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32_WIDE;
+    if (r.nc != NCN && r.nc != NCW)
+        return GRAV_EUNSUPPORTED;
     dim3 grid(r.wgs), blk(64);
-#define M2L_LAUNCH(P, NS)                                                                              \
+#define M2L_LAUNCH(P, NC, NS)                                                                          \
     hipLaunchKernelGGL((k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, NC, T, NS>), grid, blk, 0, s, g, r.tiles, \
                        r.keys, r.order, r.class_off, r.K, r.b_in, r.segs, r.wgseg, r.items, r.part)
 #define M2L_CASE(P)                                                                             \
     case P:                                                                                     \
-        if (sizeof(T) == 4 && r.nset == 1)                                                      \
-            M2L_LAUNCH(P, 1);                                                                   \
+        if (sizeof(T) == 4 && r.nset == 1 && r.nc == NCW)                                       \
+            M2L_LAUNCH(P, NCW, 1);                                                              \
+        else if (sizeof(T) == 4 && r.nset == 1)                                                 \
+            M2L_LAUNCH(P, NCN, 1);                                                              \
+        else if (r.nc == NCW)                                                                   \
+            M2L_LAUNCH(P, NCW, 2);                                                              \
         else                                                                                    \
-            M2L_LAUNCH(P, 2);                                                                   \
+            M2L_LAUNCH(P, NCN, 2);                                                              \
         break;
     switch (p->P) {
         M2L_CASE(1)
@@ -366,13 +379,16 @@ template grav_status launch_m2l<float>(const Plan *, const DevGeom &, hipStream_
 // sets in FP32) that the device holds at once (blocks per CU from the
 // occupancy calculator, times the CUs): the size of the stream-K schedule,
 // so that every worker is resident from the start.
-grav_status m2l_resident_workers(const Plan *p, int nset, int *workers)
+grav_status m2l_resident_workers(const Plan *p, int nset, int nc, int *workers)
 {
     const bool f64 = p->d.precision == GRAV_FP64;
+    const bool wide = nc == GRAV_M2L_NC32_WIDE;
     const void *fn = nullptr;
 #define M2L_FN(P)                                                                                           \
     case P:                                                                                                 \
         fn = f64 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64, double, 2>) \
+             : wide ? (nset == 1 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32_WIDE, float, 1>) \
+                                 : reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32_WIDE, float, 2>)) \
              : nset == 1 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32, float, 1>) \
                          : reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32, float, 2>); \
         break;

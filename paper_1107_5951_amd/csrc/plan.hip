@@ -670,7 +670,7 @@ struct StreamK {
     int nset = 2;
 };
 
-static grav_status stream_k(const Plan *p, const std::vector<int32_t> &item_unit, int64_t nunit, StreamK &o)
+static grav_status stream_k(const Plan *p, const std::vector<int32_t> &item_unit, int64_t nunit, int nc, StreamK &o)
 {
     const int64_t T = (int64_t)item_unit.size();
     // at least kMinItems items per workgroup: small plans get fewer
@@ -682,11 +682,11 @@ static grav_status stream_k(const Plan *p, const std::vector<int32_t> &item_unit
     int resident = 0;
     o.nset = 2;
     if (p->d.precision != GRAV_FP64) {
-        GRAV_CHECK(m2l_resident_workers(p, 1, &resident));
+        GRAV_CHECK(m2l_resident_workers(p, 1, nc, &resident));
         if (T >= kItemsOneSet * resident)
             o.nset = 1;
     }
-    GRAV_CHECK(m2l_resident_workers(p, o.nset, &resident));
+    GRAV_CHECK(m2l_resident_workers(p, o.nset, nc, &resident));
     const int64_t P = T == 0 ? 0
                              : std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(GRAV_M2L_WAVES, resident),
                                                                       T / kMinItems));
@@ -733,7 +733,9 @@ static grav_status build_m2l_transposed(Plan *p, const std::vector<std::vector<u
 {
     const int L = p->L;
     const int64_t B = p->B;
-    const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
+    // the forward's column blocks per wave: the transposed M2L has the same
+    // box pairs
+    const int nc = p->m2l_nc;
     const int ncw = 16 * nc, upt = 4 / nc;
     std::vector<uint32_t> skey((size_t)std::max<int64_t>(p->n_me, 1), 0);
     std::vector<int32_t> sorder((size_t)std::max<int64_t>(p->n_me, 1), 0);
@@ -857,7 +859,7 @@ static grav_status build_m2l_transposed(Plan *p, const std::vector<std::vector<u
     }
     const int64_t nunit = (int64_t)tiles.size() * upt;
     StreamK sk;
-    GRAV_CHECK(stream_k(p, item_unit, nunit, sk));
+    GRAV_CHECK(stream_k(p, item_unit, nunit, nc, sk));
     if (item_off.empty())
         item_off.push_back(0);
     GRAV_CHECK(upload(p, &p->d_m2lt_tiles, tiles.empty() ? std::vector<GemmTile>(1) : tiles));
@@ -872,6 +874,8 @@ static grav_status build_m2l_transposed(Plan *p, const std::vector<std::vector<u
     GRAV_CHECK(upload(p, &p->d_sorder, sorder));
     p->m2lt_wgs = (int32_t)sk.P;
     p->m2lt_nset = sk.nset;
+    p->m2lt_nc = nc;
+    p->m2lt_ncw = ncw;
     p->m2lt_nseg = sk.nseg;
     p->m2lt_ncols = (int64_t)colmap.size();
     p->m2lt_nunit = nunit;
@@ -980,7 +984,10 @@ grav_status build_tiles(Plan *p)
                 }
             }
             // a unit is the columns of one wave: 16 NC columns of a tile
-            const int nc = p->d.precision == GRAV_FP64 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
+            // (FP32: four blocks on plans with many columns)
+            const int nc = p->d.precision == GRAV_FP64
+                               ? GRAV_M2L_NC64
+                               : (p->n_tbox * B >= GRAV_M2L_WIDE_COLUMNS ? GRAV_M2L_NC32_WIDE : GRAV_M2L_NC32);
             const int ncw = 16 * nc, upt = 4 / nc;
             const int64_t nunit = r.n * upt;
             std::vector<int32_t> item_tile, item_off;  // item_tile holds the unit
@@ -1016,7 +1023,7 @@ grav_status build_tiles(Plan *p)
                 }
             }
             StreamK sk;
-            GRAV_CHECK(stream_k(p, item_tile, nunit, sk));
+            GRAV_CHECK(stream_k(p, item_tile, nunit, nc, sk));
             if (item_off.empty())
                 item_off.push_back(0);
             GRAV_CHECK(upload(p, &p->d_m2l_items, item_off));
@@ -1030,6 +1037,7 @@ grav_status build_tiles(Plan *p)
             p->m2l_nseg = sk.nseg;
             p->m2l_items = (int64_t)item_tile.size();
             p->m2l_ncw = ncw;
+            p->m2l_nc = nc;
             p->m2l_nunit = nunit;
             GRAV_CHECK(build_m2l_transposed(p, key, rev));
         }
@@ -1872,7 +1880,7 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             const size_t part = (size_t)p->m2l_nseg * p->m2l_ncw * p->PS;
             if ((st = dalloc(p, &p->d_part, part, false)) != GRAV_OK)
                 break;
-            if ((st = dalloc(p, &p->d_partt, (size_t)p->m2lt_nseg * p->m2l_ncw * p->PS, false)) != GRAV_OK)
+            if ((st = dalloc(p, &p->d_partt, (size_t)p->m2lt_nseg * p->m2lt_ncw * p->PS, false)) != GRAV_OK)
                 break;
             if ((st = dalloc(p, &p->d_leg, (size_t)p->n_leg * p->B * p->PS, false)) != GRAV_OK)
                 break;
