@@ -16,8 +16,8 @@ constexpr int kMaxLevels = 10;
 
 // M2L: 16-column blocks per wave (1, 2 or 4) for the FP32 and FP64
 // kernels: each A fragment feeds this many instructions; a tile of 64
-// columns holds 4 / NC units.  FP64 keeps one block: its accumulators for
-// two would leave one wave per SIMD.
+// columns holds 4 / NC units.  Small FP64 plans keep one block (two would
+// leave one wave per SIMD).
 #ifndef GRAV_M2L_NC32
 #define GRAV_M2L_NC32 2
 #endif
@@ -29,6 +29,16 @@ constexpr int kMaxLevels = 10;
 #endif
 #ifndef GRAV_M2L_WIDE_COLUMNS
 #define GRAV_M2L_WIDE_COLUMNS 131072
+#endif
+// FP64 plans with at least this many columns take two blocks per wave: the
+// FP64 operators (up to 512 KB each at p = 16) are re-read half as often
+// (128^3 x 32 models at p = 14: 1.46 -> 0.79 ms; 256^3 at p = 16: 267 ->
+// 131 ms; the 64^3 plan at p = 12, 4,681 columns, is slower with two)
+#ifndef GRAV_M2L_NC64_WIDE
+#define GRAV_M2L_NC64_WIDE 2
+#endif
+#ifndef GRAV_M2L_WIDE_COLUMNS64
+#define GRAV_M2L_WIDE_COLUMNS64 16384
 #endif
 #ifndef GRAV_M2L_NC64
 #define GRAV_M2L_NC64 1

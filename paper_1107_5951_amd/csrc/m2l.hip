@@ -328,7 +328,7 @@ grav_status launch_m2l(const Plan *p, const DevGeom &g, hipStream_t s, const M2L
         return GRAV_OK;
     // column blocks per wave: FP64 one; FP32 the plan's (narrow or wide)
     constexpr int NCN = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
-    constexpr int NCW = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32_WIDE;
+    constexpr int NCW = sizeof(T) == 8 ? GRAV_M2L_NC64_WIDE : GRAV_M2L_NC32_WIDE;
     if (r.nc != NCN && r.nc != NCW)
         return GRAV_EUNSUPPORTED;
     dim3 grid(r.wgs), blk(64);
@@ -382,11 +382,12 @@ template grav_status launch_m2l<float>(const Plan *, const DevGeom &, hipStream_
 grav_status m2l_resident_workers(const Plan *p, int nset, int nc, int *workers)
 {
     const bool f64 = p->d.precision == GRAV_FP64;
-    const bool wide = nc == GRAV_M2L_NC32_WIDE;
+    const bool wide = nc == (f64 ? GRAV_M2L_NC64_WIDE : GRAV_M2L_NC32_WIDE);
     const void *fn = nullptr;
 #define M2L_FN(P)                                                                                           \
     case P:                                                                                                 \
-        fn = f64 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64, double, 2>) \
+        fn = f64 ? (wide ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64_WIDE, double, 2>) \
+                         : reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64, double, 2>)) \
              : wide ? (nset == 1 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32_WIDE, float, 1>) \
                                  : reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32_WIDE, float, 2>)) \
              : nset == 1 ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC32, float, 1>) \

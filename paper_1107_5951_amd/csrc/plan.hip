@@ -986,7 +986,7 @@ grav_status build_tiles(Plan *p)
             // a unit is the columns of one wave: 16 NC columns of a tile
             // (FP32: four blocks on plans with many columns)
             const int nc = p->d.precision == GRAV_FP64
-                               ? GRAV_M2L_NC64
+                               ? (p->n_tbox * B >= GRAV_M2L_WIDE_COLUMNS64 ? GRAV_M2L_NC64_WIDE : GRAV_M2L_NC64)
                                : (p->n_tbox * B >= GRAV_M2L_WIDE_COLUMNS ? GRAV_M2L_NC32_WIDE : GRAV_M2L_NC32);
             const int ncw = 16 * nc, upt = 4 / nc;
             const int64_t nunit = r.n * upt;
