@@ -167,7 +167,7 @@ def m2l_kernel_name(p, prec):
     from paper_1107_5951_amd import GRAV_FP64
     p2 = p * p
     if prec == GRAV_FP64:
-        return "k_m2l<%d,%d,1,double,*>" % (-(-p2 // 16), -(-p2 // 4))
+        return "k_m2l<%d,%d,*,double,*>" % (-(-p2 // 16), -(-p2 // 4))
     return "k_m2l<%d,%d,*,float,*>" % (-(-p2 // 16), -(-p2 // 4))
 
 
