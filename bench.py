@@ -174,8 +174,8 @@ def m2l_kernel_name(p, prec):
 def roofline(plan, stages, p, prec, profile):
     """Roofline of the dominant stage: its algorithmic work per launch over
     the stage's event-measured duration.  Compute-bound stages count flops
-    (M2L: 2 p^4 per box pair and model; lattice near field: 27 x 2 x 4b^3 x
-    b^3 per leaf and model; M2M: 8 x 2 p^4 per parent box and model); the P2M
+    (M2L: 2 p^4 per box pair and model; lattice near field: 27 x 2 x C b^3 x
+    b^3 per leaf and model for C output components; M2M: 8 x 2 p^4 per parent box and model); the P2M
     on a surface-target plan is bound by HBM and counts the bytes it must
     move (the densities read and the leaf expansions written)."""
     from paper_1107_5951_amd import GRAV_FP64
@@ -196,9 +196,10 @@ def roofline(plan, stages, p, prec, profile):
     mm = "fp64_mfma" if f64 else "fp32_mfma"
     ps = -(-p * p // 16) * 16
     cand = {
-        "m2l": (2.0 * p ** 4 * m2l_pairs * B, m2l_kernel_name(p, prec) + " (M2L, %s MFMA 16x16x4)"
-                % ("FP64" if f64 else "FP32"), "mfma", mm, "TFLOP/s"),
-        "near_lat": (27 * 2.0 * (4 * b ** 3) * b ** 3 * n_leaf_src * B,
+        "m2l": (2.0 * p ** 4 * m2l_pairs * B, m2l_kernel_name(p, prec) + " (M2L, %s MFMA 16x16x4%s)"
+                % ("FP64" if f64 else "FP32", "" if f64 or not 0 < p * p % 16 <= 4 else
+                   ", the last row block 4x4x1"), "mfma", mm, "TFLOP/s"),
+        "near_lat": (27 * 2.0 * (plan.spec.components * b ** 3) * b ** 3 * n_leaf_src * B,
                      "k_near_lat<%d,2,%s> (lattice near field, %s MFMA 16x16x4)"
                      % ((2, "double", "FP64") if f64 else (4, "float", "FP32")), "mfma", mm, "TFLOP/s"),
         "m2m": (8 * 2.0 * p ** 4 * parents * B, "k_m2m_lds<%d> / k_m2m_split<%d> (M2M, FP64 MFMA 16x16x4)"

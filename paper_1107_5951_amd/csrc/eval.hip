@@ -1015,9 +1015,10 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
 // Targets and Gauss points both sit on the lattice, so the near field of a
 // leaf's b^3 cell centres is
 //   near[leaf] = sum over the 27 neighbour offsets d of  A_d rho[leaf + d],
-// with A_d a fixed (4 b^3) x b^3 matrix (the direct sum over the same point
-// pairs, precomputed in FP64), and the far field is a fixed (4 b^3) x PS
-// matrix applied to the leaf's local expansion (L2P at fixed points, FP64).
+// with A_d a fixed (C b^3) x b^3 matrix (the direct sum over the same point
+// pairs, precomputed in FP64, rows for the C requested output components
+// only), and the far field is a fixed (C b^3) x PS matrix applied to the
+// leaf's local expansion (L2P at fixed points, FP64).
 // Over all leaves these are GEMMs with columns = (leaf, model).
 //
 // A workgroup owns a tile of 16 CW columns x 16 RW rows.  Its four waves
@@ -1209,35 +1210,27 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *cta
             for (int k = 0; k < 4; ++k)
                 red[wave][(c * RW + r) * 4 + k][lane] = (double)acc[c][r][k] + far[c][r][k];
     __syncthreads();
-    // lane holds target t = 4 rb + lane / 16 (the row order of both
-    // operators), components k = 0..3 = (phi, gx, gy, gz) in lattice units
+    // row block R holds targets 16 (R % RBc) + row of output component
+    // R / RBc (the row order of both operators, in lattice units); the
+    // lane's element k is row 4 kr + k (FP32) or kr + 4 k (FP64)
     const double sg = g.G * g.h, sp = g.G * g.h * g.h;
+    const int RBc = (b3 + 15) / 16;
     for (int j = wave; j < CW * RW; j += 4) {
         const int c = j / RW, r = j % RW;
-        const int t = 4 * (rb0 + r) + kr;
-        if (!cvalid[c] || !rvalid[r] || t >= b3)
+        if (!cvalid[c] || !rvalid[r])
             continue;
-        const int ix = lx[c] * b + t % b, iy = ly[c] * b + (t / b) % b, iz = lz[c] * b + t / b2;
-        if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
-            continue;
-        double v[4];
+        const int comp = (rb0 + r) / RBc, tb = 16 * ((rb0 + r) % RBc);
+        const double sc = g.C == 4 && comp == 0 ? sp : sg;
+        double *o = out + ((int64_t)bm[c] * g.M + npts) * g.C + comp;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            v[k] = ((red[0][j * 4 + k][lane] + red[1][j * 4 + k][lane]) + red[2][j * 4 + k][lane]) +
-                   red[3][j * 4 + k][lane];
-        const int64_t cell = ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
-        double *o = out + ((int64_t)bm[c] * g.M + npts + cell) * g.C;
-        if (g.C == 1) {
-            o[0] = sg * v[3];
-        } else if (g.C == 3) {
-            o[0] = sg * v[1];
-            o[1] = sg * v[2];
-            o[2] = sg * v[3];
-        } else {
-            o[0] = sp * v[0];
-            o[1] = sg * v[1];
-            o[2] = sg * v[2];
-            o[3] = sg * v[3];
+        for (int k = 0; k < 4; ++k) {
+            const int t = tb + (sizeof(T) == 8 ? kr + 4 * k : 4 * kr + k);
+            const int ix = lx[c] * b + t % b, iy = ly[c] * b + (t / b) % b, iz = lz[c] * b + t / b2;
+            if (t >= b3 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+                continue;
+            const double v = ((red[0][j * 4 + k][lane] + red[1][j * 4 + k][lane]) + red[2][j * 4 + k][lane]) +
+                             red[3][j * 4 + k][lane];
+            o[(((int64_t)iz * g.n[1] + iy) * g.n[0] + ix) * g.C] = sc * v;
         }
     }
 }

@@ -172,7 +172,7 @@ struct Plan {
     double *d_partt = nullptr;        // segment slots of the transposed M2L
     // near field of voxel-centre targets by lattice matrices (b <= 4)
     bool lat_near = false;
-    int lat_RB = 0, lat_Q = 0;                     // row blocks (4 b^3 / 16); chunks of four k steps
+    int lat_RB = 0, lat_Q = 0;                     // row blocks (C b^3 / 16); chunks of four k steps
     double *d_tl2p = nullptr;                      // [PS/16][RB][64][4] far field (L2P) at the cell centres, FP64
     int64_t *d_lat_tab = nullptr;                  // [27 Q][2] per near chunk: density and operator offsets
     double *d_m2m_sw = nullptr;                    // [8][PS/4][RB][64] M2M as MFMA A fragments (FP64)

@@ -102,13 +102,24 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
     using kmask_t = std::conditional_t<(KSV > 32), uint64_t, uint32_t>;
     const int lane = threadIdx.x;  // one wave per workgroup
     constexpr int UPT = 4 / NC;      // units (waves' column blocks) per tile
+    // FP32 with at most four coefficient rows in the last row block (p^2 mod
+    // 16 in 1..4, so that the coefficients end in k step 4 (RB - 1)): that
+    // block runs as 4x4x1 instructions (16 blocks, a quarter of the cycles
+    // of a 16x16x4 one).  Block 4 (lane / 16) + (lane % 16) / 4 takes the
+    // lane's own B value (coefficient 4 ks + lane / 16 of column lane % 16)
+    // and the A value of row lane % 4 at the same coefficient, so lane l
+    // accumulates the rows at column l % 16 over the coefficients of its
+    // residue l / 16 mod 4; the four residues are added across lanes at the
+    // end.
+    constexpr bool TAIL = sizeof(T) == 4 && KSV == 4 * (RB - 1) + 1;
     // reflection sign bits of this lane's A rows (bit rb: row 16 rb + lane %
-    // 16) and B contraction indices (bit ks: coefficient 4 ks + lane / 16)
+    // 16, or lane % 4 in a 4x4 tail) and B contraction indices (bit ks:
+    // coefficient 4 ks + lane / 16)
     uint32_t rsz = 0, rsy = 0, rsx = 0;
     kmask_t ksz = 0, ksy = 0, ksx = 0;
     for (int rb = 0; rb < RB; ++rb) {
         uint32_t bz, by, bx;
-        coef_sign_bits(16 * rb + (lane & 15), bz, by, bx);
+        coef_sign_bits(16 * rb + (TAIL && rb == RB - 1 ? (lane & 3) : (lane & 15)), bz, by, bx);
         rsz |= bz << rb;
         rsy |= by << rb;
         rsx |= bx << rb;
@@ -225,6 +236,8 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
                     for (int c = 0; c < NC; ++c) {
                         if constexpr (sizeof(T) == 8)
                             acc[c][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[c], acc[c][rb], 0, 0, 0);
+                        else if (TAIL && rb == RB - 1)
+                            acc[c][rb] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bv[c], acc[c][rb], 0, 0, 0);
                         else
                             acc[c][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[c], acc[c][rb], 0, 0, 0);
                     }
@@ -301,6 +314,22 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
                     compute(A, q, 0);
                 }
             }
+        }
+        if constexpr (TAIL) {
+            // the 4x4 tail: lane l holds rows 16 (RB - 1) + r of column l % 16
+            // summed over its coefficient residue; add the four residues in a
+            // fixed order and leave the sums in lanes 0..15, which is where
+            // the 16x16x4 layout below puts those rows (the other lanes'
+            // rows are padding: zero)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    T v = acc[c][RB - 1][r];
+                    v += __shfl_xor(v, 16);
+                    v += __shfl_xor(v, 32);
+                    acc[c][RB - 1][r] = lane < 16 ? v : (T)0;
+                }
         }
         // Output fragment: lane holds column lane % 16 and four rows; the FP32
         // instruction gives rows 4*(lane/16) + r, the FP64 one rows lane/16 + 4r.

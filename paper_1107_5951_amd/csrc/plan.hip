@@ -465,15 +465,18 @@ static inline size_t frag_pos(int lane, int e, int G)
 // coefficients in whole trailing k steps).  The fragments of four
 // consecutive k steps (ks = 4 q + u) and all row blocks form one set of
 // E = 4 RB values per lane, value e = u * RB + rb:
-// set q, value (lane, e)  =  m[16 rb + lane % 16][4 (4 q + u) + lane / 16].
-void swizzle_panel(const double *m, int PS, int G, double *dst)
+// set q, value (lane, e)  =  m[16 rb + lane % 16][4 (4 q + u) + lane / 16],
+// except that with tail4 the last row block (at most four rows of
+// coefficients) takes row 16 rb + lane % 4, the A operand of the 4x4x1
+// instructions that replace its 16x16x4 ones.
+void swizzle_panel(const double *m, int PS, int G, double *dst, bool tail4)
 {
     const int RB = PS / 16;
     for (int q = 0; q < RB; ++q)
         for (int lane = 0; lane < 64; ++lane)
             for (int u = 0; u < 4; ++u)
                 for (int rb = 0; rb < RB; ++rb) {
-                    const int row = 16 * rb + (lane & 15);
+                    const int row = 16 * rb + (tail4 && rb == RB - 1 ? (lane & 3) : (lane & 15));
                     const int col = 4 * (4 * q + u) + (lane >> 4);
                     dst[(size_t)q * 64 * 4 * RB + frag_pos(lane, u * RB + rb, G)] = m[(size_t)row * PS + col];
                 }
@@ -612,6 +615,9 @@ grav_status build_operators(Plan *p)
     std::vector<int32_t> fwd, rev;
     offsets_tables(all, fwd, rev, canonical);
     const size_t perp = (size_t)RB * 64 * 4 * RB;  // forward M2L: PS/4 k steps, grouped by four
+    // FP32 plans whose last row block holds at most four coefficient rows
+    // run it as 4x4 instructions: its A fragment repeats those rows
+    const bool tail4 = p->d.precision != GRAV_FP64 && p->P2 % 16 != 0 && p->P2 % 16 <= 4;
     std::vector<double> k(perp * (canonical ? kCanonOffsets : kNumOffsets)), kt(k.size()), mt((size_t)PS * PS);
     for (int id = 0; id < kNumOffsets; ++id) {
         // source = target + d  =>  target centre - source centre = -d
@@ -622,11 +628,11 @@ grav_status build_operators(Plan *p)
         // reflections act on K_d^T as on K_d: K_d^T = S K_|d|^T S)
         const int ci = canonical ? canon_index(all[3 * id], all[3 * id + 1], all[3 * id + 2]) : id;
         if (ci >= 0) {
-            swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, k.data() + perp * ci);
+            swizzle_panel(m.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, k.data() + perp * ci, tail4);
             for (int i = 0; i < PS; ++i)
                 for (int j = 0; j < PS; ++j)
                     mt[(size_t)j * PS + i] = m[(size_t)i * PS + j];
-            swizzle_panel(mt.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, kt.data() + perp * ci);
+            swizzle_panel(mt.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, kt.data() + perp * ci, tail4);
         }
     }
     if (p->d.precision == GRAV_FP64) {
@@ -1143,24 +1149,31 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
     GRAV_HIP(hipGetLastError());
 
     const int b = p->b, b3 = b * b * b;
-    // rows: (target, component) pairs, 4 b^3, in RBn blocks of 16; the
-    // contraction runs over Qn chunks of four k steps, k step ks and
-    // instruction sub-row kr taking cell kr * 4 Qn + ks (cells past b^3 are
-    // zero in both operands)
-    const int RBn = (int)ceil_div(4 * b3, 16), Qn = (int)ceil_div(ceil_div(b3, 4), 4);
+    // rows: (output component, target) pairs for the requested components
+    // only, component-major: each component owns RBc = b^3/16 (rounded up)
+    // blocks of 16 targets, RBn = C RBc blocks in all; the contraction runs
+    // over Qn chunks of four k steps, k step ks and instruction sub-row kr
+    // taking cell kr * 4 Qn + ks (cells past b^3 are zero in both operands)
+    const int C = p->d.components, RBc = (int)ceil_div(b3, 16);
+    const int RBn = C * RBc, Qn = (int)ceil_div(ceil_div(b3, 4), 4);
     const int KP = 16 * Qn;
     p->lat_RB = RBn;
     p->lat_Q = Qn;
     const bool f64 = p->d.precision == GRAV_FP64;
     std::vector<double> dense((size_t)27 * 4 * b3 * b3);
     near_lattice(b, p->q, f64 ? 1e-20 : 1e-10, dense.data());
-    // Row order: the accumulator of a lane holds the four components of one
-    // target: the FP32 instruction returns rows 4 (lane / 16) + r of each
-    // 16-row block, the FP64 one rows lane / 16 + 4 r; target t = 4 rb +
-    // lane / 16, component r.  Layout [nb][q][rb][lane][u], ks = 4 q + u.
-    auto row_target = [](int row, bool dbl, int rb, int &t, int &comp) {
-        t = 4 * rb + (dbl ? row % 4 : row / 4);
-        comp = dbl ? row / 4 : row % 4;
+    // Row r of block rb is target 16 (rb % RBc) + r of output component
+    // rb / RBc; the lattice matrices hold (phi, gx, gy, gz), of which
+    // components 1 and 3 take the trailing one or three.  The FP32
+    // instruction returns rows 4 (lane / 16) + k of a block and the FP64 one
+    // rows lane / 16 + 4 k, so a lane's accumulator holds four targets of one
+    // component.  The far field (FP64) is added element by element to the
+    // near field's accumulator, so next to an FP32 near field its rows take
+    // the FP32 order (swap: row 4 i + j holds target 4 j + i).  Layout
+    // [nb][q][rb][lane][u], ks = 4 q + u.
+    auto row_target = [C, RBc](int row, int rb, bool swap, int &t, int &comp) {
+        t = 16 * (rb % RBc) + (swap ? 4 * (row % 4) + row / 4 : row);
+        comp = rb / RBc + 4 - C;
     };
     std::vector<double> sw((size_t)27 * Qn * RBn * 64 * 4, 0.0);
     for (int nb = 0; nb < 27; ++nb)
@@ -1169,7 +1182,7 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int u = 0; u < 4; ++u) {
                         int t, comp;
-                        row_target(lane & 15, f64, rb, t, comp);
+                        row_target(lane & 15, rb, false, t, comp);
                         const int cell = (lane >> 4) * 4 * Qn + 4 * q + u;
                         double v = 0.0;
                         if (t < b3 && cell < b3)
@@ -1267,7 +1280,7 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int u = 0; u < 4; ++u) {
                         int t, comp;
-                        row_target(lane & 15, true, rb, t, comp);
+                        row_target(lane & 15, rb, !f64, t, comp);
                         const int c = (lane >> 4) * (PS / 4) + 4 * q + u;
                         lsw[((size_t)q * RBn + rb) * 256 + frag_pos(lane, u, 2)] =
                             t < b3 ? full[(size_t)(4 * t + comp) * PS + c] : 0.0;

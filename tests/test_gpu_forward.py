@@ -89,6 +89,25 @@ def test_config1_mixed_within_1e4():
     assert e <= 1e-4
 
 
+@pytest.mark.parametrize("p", [2, 6, 7, 8, 9, 10, 14, 15])
+def test_mixed_matches_fp64_at_the_same_order(p):
+    """Mixed precision against the FP64 FMM at the same order: the two differ
+    by FP32 rounding only.  The orders cover every FP32 M2L shape: p^2 mod 16
+    = 4 or 1 (the last row block run as 4x4 instructions, at p = 2 the whole
+    operator), 0 (whole 16-row blocks) and 9."""
+    grid = W.Grid.unit(32)
+    rho = W.gaussian_blobs(grid, 16, 1007)
+    pts = np.concatenate([W.stations(24, 1.1), np.random.default_rng(2).uniform(0.0, 1.0, size=(2000, 3))])
+    outs = []
+    for prec in (G.GRAV_FP64, G.GRAV_MIXED):
+        spec = G.PlanSpec(n=(32, 32, 32), h=grid.h, points=pts, components=4, p=p, leaf_size=32, precision=prec)
+        _, out = _run(spec, rho)
+        outs.append(out[0])
+    e = _rel(outs[1], outs[0])
+    _say("mixed vs FP64 at p=%d: %.3e" % (p, e))
+    assert e <= 5e-6
+
+
 @pytest.fixture(scope="module")
 def config2():
     """64^3 cells, 2-point rule (2.1M sources), 32 blobs + U[-0.01, 0.01]
@@ -196,26 +215,48 @@ def test_tree_leaf_count_matches_host_count():
     assert plan.n_target_leaves == len({tuple(r) for r in lc})
 
 
-@pytest.mark.parametrize("n,q,leaf,prec,B", [
-    ((32, 32, 32), 2, 64, 0, 1),    # b = 2, FP64
-    ((36, 33, 28), 1, 64, 0, 2),    # b = 4, ragged mesh, two models
-    ((27, 21, 24), 1, 27, 1, 1),    # b = 3, mixed precision
-    ((12, 12, 12), 1, 1, 0, 1),     # b = 1
+@pytest.mark.parametrize("n,q,leaf,prec,B,comps", [
+    ((32, 32, 32), 2, 64, 0, 1, 4),    # b = 2, FP64
+    ((36, 33, 28), 1, 64, 0, 2, 3),    # b = 4, ragged mesh, two models
+    ((36, 33, 28), 1, 64, 1, 2, 4),    # the same, mixed precision, all four components
+    ((27, 21, 24), 1, 27, 1, 1, 1),    # b = 3, mixed precision, gz only
+    ((40, 32, 24), 2, 64, 1, 1, 3),    # b = 2, two-point rule, mixed precision
+    ((12, 12, 12), 1, 1, 0, 1, 4),     # b = 1
 ])
-def test_lattice_near_field_matches_direct_sum(n, q, leaf, prec, B):
-    """Voxel-centre targets take the near field from the lattice matrices;
-    the same positions passed as explicit points take the direct sum over
-    the same pairs (same tree), so the two evaluations agree to rounding."""
+def test_lattice_near_field_matches_direct_sum(n, q, leaf, prec, B, comps):
+    """Voxel-centre targets take the near field from the lattice matrices
+    (rows for the requested components only); the same positions passed as
+    explicit points take the direct sum over the same pairs (same tree), so
+    the two evaluations agree to rounding."""
     h = 1.0 / 32  # a power of two: explicit centres land exactly on the lattice
     grid = W.Grid(n[0], n[1], n[2], (0.0, 0.0, 0.0), h)
     rho = np.random.default_rng(7).normal(size=(B, n[2], n[1], n[0]))
     r = torch.as_tensor(rho, device="cuda")
-    common = dict(n=n, h=h, quad_order=q, components=4, p=6, leaf_size=leaf, precision=prec, batch=B)
+    common = dict(n=n, h=h, quad_order=q, components=comps, p=6, leaf_size=leaf, precision=prec, batch=B)
     lat = G.Plan(G.PlanSpec(voxel_centres=True, **common))
     pts = G.Plan(G.PlanSpec(points=grid.centres(), **common))
     assert lat.levels == pts.levels and lat.leaf_cells == pts.leaf_cells
     a = lat.eval(r).cpu().numpy()
     b = pts.eval(r).cpu().numpy()
     e = np.linalg.norm(a - b) / np.linalg.norm(b)
-    _say("lattice vs direct near field, n=%s q=%d b=%d prec=%d B=%d: %.3e" % (n, q, lat.leaf_cells, prec, B, e))
+    _say("lattice vs direct near field, n=%s q=%d b=%d prec=%d B=%d C=%d: %.3e"
+         % (n, q, lat.leaf_cells, prec, B, comps, e))
     assert e < (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lattice_components_agree(prec):
+    """The lattice path computes only the requested components; gz alone,
+    g and (phi, g) give the same gz, and the same g, to rounding."""
+    n = (20, 24, 28)
+    rho = np.random.default_rng(9).normal(size=(n[2], n[1], n[0]))
+    r = torch.as_tensor(rho[None], device="cuda")
+    outs = {}
+    for comps in (1, 3, 4):
+        plan = G.Plan(G.PlanSpec(n=n, h=1 / 32, voxel_centres=True, components=comps, p=8, leaf_size=64,
+                                 precision=prec))
+        outs[comps] = plan.eval(r).cpu().numpy()[0]
+    for x, y in ((outs[1][:, 0], outs[3][:, 2]), (outs[3], outs[4][:, 1:])):
+        e = np.linalg.norm(x - y) / np.linalg.norm(y)
+        _say("lattice components, prec=%d: %.3e" % (prec, e))
+        assert e < (1e-14 if prec == 0 else 1e-6)
