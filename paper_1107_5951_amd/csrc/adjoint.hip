@@ -461,14 +461,16 @@ k_t_m2m(DevGeom g, int l, ColBlock cb, const double *A, double *me)
 // P2M^T: drho[cell] = sum_k Pm[v][k] ME_L[leaf][k] for the cells v of every
 // leaf of the source block (each mesh cell once), as FP64 MFMA: one wave
 // owns 16 (leaf, model) columns and four 16-cell row blocks (blockIdx.y
-// selects the blocks), K = the coefficients in the order (lane/16) PS/4 + ks.
+// selects the blocks), K = the coefficients in the order 16 (ks/4) +
+// 4 (lane/16) + ks%4: a lane's four k steps of chunk q are the coefficients
+// 16 q + 4 (lane/16) + 0..3, one 32-byte read, and the four sub-rows of a
+// column read one contiguous 128 bytes.
 template <int RB>
 __global__ void __launch_bounds__(64)
 k_t_p2m(DevGeom g, const double *A, int RBT, const double *me, double *drho)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     constexpr int PS = 16 * RB;
-    constexpr int K4 = PS / 4;
     const int lane = threadIdx.x, kr = lane >> 4;
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
@@ -479,14 +481,14 @@ k_t_p2m(DevGeom g, const double *A, int RBT, const double *me, double *drho)
     const int64_t leaf = cvalid ? col % nleaf : 0;
     const int bm = cvalid ? (int)(col / nleaf) : 0;
     const int rb0 = 4 * blockIdx.y;
-    const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + kr * K4);
+    const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + 4 * kr);
     vec4 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         acc[r] = vec4{0, 0, 0, 0};
     for (int q = 0; q < RB; ++q) {
-        const double2 b01 = cvalid ? bp[2 * q] : double2{0.0, 0.0};
-        const double2 b23 = cvalid ? bp[2 * q + 1] : double2{0.0, 0.0};
+        const double2 b01 = cvalid ? bp[8 * q] : double2{0.0, 0.0};
+        const double2 b23 = cvalid ? bp[8 * q + 1] : double2{0.0, 0.0};
         const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -878,7 +880,6 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     constexpr int PS = 16 * RB;
-    constexpr int K4 = PS / 4;
     __shared__ double sa[2][4 * 4 * 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kr = lane >> 4;
     const int CH = 4 * RBT * 64;  // doubles per chunk
@@ -888,7 +889,8 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
     const bool cvalid = col < nleaf * g.B;
     const int64_t leaf = cvalid ? col % nleaf : 0;
     const int bm = cvalid ? (int)(col / nleaf) : 0;
-    const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + kr * K4);
+    // chunk j: coefficients 16 j + 4 kr + 0..3 (the order of the fragments)
+    const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + 4 * kr);
     vec4 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -916,8 +918,8 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
         }
         const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
         if (more) {
-            b01 = cvalid ? bp[2 * (j + 1)] : double2{0.0, 0.0};
-            b23 = cvalid ? bp[2 * (j + 1) + 1] : double2{0.0, 0.0};
+            b01 = cvalid ? bp[8 * (j + 1)] : double2{0.0, 0.0};
+            b23 = cvalid ? bp[8 * (j + 1) + 1] : double2{0.0, 0.0};
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)

@@ -531,8 +531,11 @@ grav_status build_operators(Plan *p)
                 }
         GRAV_CHECK(upload(p, &p->d_pm_sw, psw));
         // the adjoint's P2M^T: rows = the leaf's cells (RBT blocks of 16),
-        // contraction over the coefficients in the order (lane/16) PS/4 + ks;
-        // [ks][rbt][lane] = pm[16 rbt + lane%16][(lane/16) PS/4 + ks]
+        // contraction over the coefficients in the order 16 (ks/4) +
+        // 4 (lane/16) + ks%4, so that a chunk of four k steps takes 16
+        // consecutive coefficients of a column, four per sub-row (one
+        // 128-byte line per column and chunk in FP64);
+        // [ks][rbt][lane] = pm[16 rbt + lane%16][16 (ks/4) + 4 (lane/16) + ks%4]
         const int RBT = (b3 + 15) / 16, K4 = PS / 4;
         std::vector<double> pmt((size_t)K4 * RBT * 64, 0.0);
         for (int ks = 0; ks < K4; ++ks)
@@ -540,7 +543,8 @@ grav_status build_operators(Plan *p)
                 for (int lane = 0; lane < 64; ++lane) {
                     const int v = 16 * rb + lane % 16;
                     if (v < b3)
-                        pmt[((size_t)ks * RBT + rb) * 64 + lane] = pm[(size_t)v * PS + (lane / 16) * K4 + ks];
+                        pmt[((size_t)ks * RBT + rb) * 64 + lane] =
+                            pm[(size_t)v * PS + 16 * (ks / 4) + 4 * (lane / 16) + ks % 4];
                 }
         GRAV_CHECK(upload(p, &p->d_pmt_sw, pmt));
     }
