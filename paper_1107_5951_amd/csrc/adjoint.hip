@@ -871,12 +871,20 @@ static grav_status enqueue_m2l_transposed(Plan *p, const DevGeom &g, hipStream_t
                                        : m2l_transposed_t<float>(p, g, s, p->d_kt32);
 }
 
+// Workgroups of the grouped P2M^T (each takes G groups of 64 columns so that
+// about this many cover the plan: eight per CU).
+constexpr int64_t kGroupedWorkgroups = 2048;
+
 // P2M^T for leaves of at most 64 cells (four row blocks): the layout of
-// k_m2m_lds, a workgroup owning 64 leaf-fastest columns with the chunks of
-// the operator (four k steps, all row blocks) double-buffered in LDS.
+// k_m2m_lds, a workgroup owning groups of 64 leaf-fastest columns, G groups
+// one after the other, with the chunks of the operator (four k steps, all
+// row blocks) double-buffered in LDS.  The chunk sequence runs on across
+// its groups (step s = chunk s % RB of group s / RB), so the loads of a
+// group's first chunk are in flight during the previous group's last one:
+// a short workgroup per group left the matrix units idle most of the time.
 template <int RB>
 __global__ void __launch_bounds__(256)
-k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
+k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho, int G)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     constexpr int PS = 16 * RB;
@@ -885,12 +893,30 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
     const int CH = 4 * RBT * 64;  // doubles per chunk
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
-    const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
-    const bool cvalid = col < nleaf * g.B;
-    const int64_t leaf = cvalid ? col % nleaf : 0;
-    const int bm = cvalid ? (int)(col / nleaf) : 0;
-    // chunk j: coefficients 16 j + 4 kr + 0..3 (the order of the fragments)
-    const double2 *bp = (const double2 *)(me + ((lv.me_off + leaf) * g.B + bm) * PS + 4 * kr);
+    const int64_t ncol = nleaf * g.B;
+    const int64_t ngrp = (ncol + 63) / 64;
+    const int64_t g0 = (int64_t)blockIdx.x * G;
+    const int ng = (int)min((int64_t)G, ngrp - g0);  // >= 1: the grid covers ngrp
+    const int b = g.b, b3 = b * b * b;
+    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    // this lane's column in group gi; chunk j reads coefficients 16 j +
+    // 4 kr + 0..3 (the order of the fragments)
+    struct Col {
+        bool valid;
+        int64_t leaf;
+        int bm;
+        const double2 *bp;
+    };
+    auto column = [&](int gi) {
+        Col c;
+        const int64_t col = (g0 + gi) * 64 + wave * 16 + (lane & 15);
+        c.valid = col < ncol;
+        c.leaf = c.valid ? col % nleaf : 0;
+        c.bm = c.valid ? (int)(col / nleaf) : 0;
+        c.bp = (const double2 *)(me + ((lv.me_off + c.leaf) * g.B + c.bm) * PS + 4 * kr);
+        return c;
+    };
+    Col cur = column(0), nxt = cur;
     vec4 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -904,22 +930,26 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
     for (int i = 0; i < 4; ++i)
         if (i < RBT)
             sa[0][i * 256 + tid] = ra[i];
-    double2 b01 = cvalid ? bp[0] : double2{0.0, 0.0};
-    double2 b23 = cvalid ? bp[1] : double2{0.0, 0.0};
+    double2 b01 = cur.valid ? cur.bp[0] : double2{0.0, 0.0};
+    double2 b23 = cur.valid ? cur.bp[1] : double2{0.0, 0.0};
     __syncthreads();
-    for (int j = 0; j < RB; ++j) {
-        const int buf = j & 1;
-        const bool more = j + 1 < RB;
+    const int S = ng * RB;
+    for (int s = 0; s < S; ++s) {
+        const int buf = s & 1, j = s % RB;
+        const bool more = s + 1 < S;
+        const int jn = j + 1 < RB ? j + 1 : 0;  // chunk of step s + 1
         if (more) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 if (i < RBT)
-                    ra[i] = A[(int64_t)(j + 1) * CH + i * 256 + tid];
+                    ra[i] = A[(int64_t)jn * CH + i * 256 + tid];
         }
         const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
         if (more) {
-            b01 = cvalid ? bp[8 * (j + 1)] : double2{0.0, 0.0};
-            b23 = cvalid ? bp[8 * (j + 1) + 1] : double2{0.0, 0.0};
+            if (jn == 0)
+                nxt = column(s / RB + 1);
+            b01 = nxt.valid ? nxt.bp[8 * jn] : double2{0.0, 0.0};
+            b23 = nxt.valid ? nxt.bp[8 * jn + 1] : double2{0.0, 0.0};
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -934,27 +964,33 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho)
                 if (i < RBT)
                     sa[buf ^ 1][i * 256 + tid] = ra[i];
         }
+        if (j == RB - 1) {
+            // the group is done: its cells, then the next group's sums
+            if (cur.valid) {
+                const int lx = lv.s0[0] + (int)(cur.leaf % lv.ns[0]),
+                          ly = lv.s0[1] + (int)((cur.leaf / lv.ns[0]) % lv.ns[1]),
+                          lz = lv.s0[2] + (int)(cur.leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int v = 16 * r + kr + 4 * i;
+                        if (r >= RBT || v >= b3)
+                            continue;
+                        const int ix = (lx - g.shift[0]) * b + v % b, iy = (ly - g.shift[1]) * b + (v / b) % b,
+                                  iz = (lz - g.shift[2]) * b + v / (b * b);
+                        if (ix < 0 || iy < 0 || iz < 0 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+                            continue;
+                        drho[(int64_t)cur.bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix] = acc[r][i];
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[r] = vec4{0, 0, 0, 0};
+            cur = nxt;
+        }
         __syncthreads();
     }
-    if (!cvalid)
-        return;
-    const int b = g.b, b3 = b * b * b;
-    const int lx = lv.s0[0] + (int)(leaf % lv.ns[0]), ly = lv.s0[1] + (int)((leaf / lv.ns[0]) % lv.ns[1]),
-              lz = lv.s0[2] + (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
-    const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int v = 16 * r + kr + 4 * i;
-            if (r >= RBT || v >= b3)
-                continue;
-            const int ix = (lx - g.shift[0]) * b + v % b, iy = (ly - g.shift[1]) * b + (v / b) % b,
-                      iz = (lz - g.shift[2]) * b + v / (b * b);
-            if (ix < 0 || iy < 0 || iz < 0 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
-                continue;
-            drho[(int64_t)bm * ncell + ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix] = acc[r][i];
-        }
 }
 
 // The lattice transposes for voxel-centre targets (see k_near_lat): with w_T
@@ -1219,12 +1255,15 @@ static grav_status launch_t_p2m(Plan *p, const DevGeom &g, double *drho, hipStre
 {
     const int b3 = p->b * p->b * p->b, RBT = (b3 + 15) / 16;
     const int64_t ncol = p->lev[p->L].n_src * p->B;
-    const dim3 grid((unsigned)ceil_div(ncol, 16), (unsigned)ceil_div(RBT, 4)), grid_lds((unsigned)ceil_div(ncol, 64));
+    // LDS kernel: groups of 64 columns, about kGroupedWorkgroups workgroups
+    const int64_t ngrp = ceil_div(ncol, 64);
+    const int G = (int)std::max<int64_t>(1, ceil_div(ngrp, kGroupedWorkgroups));
+    const dim3 grid((unsigned)ceil_div(ncol, 16), (unsigned)ceil_div(RBT, 4)), grid_lds((unsigned)ceil_div(ngrp, G));
 #define CASE(R)                                                                                             \
     case R:                                                                                                 \
         if (RBT <= 4)                                                                                       \
             hipLaunchKernelGGL((k_t_p2m_lds<R>), grid_lds, dim3(256), 0, s, g, (const double *)p->d_pmt_sw, RBT, \
-                               (const double *)p->d_me, drho);                                              \
+                               (const double *)p->d_me, drho, G);                                           \
         else                                                                                                \
             hipLaunchKernelGGL((k_t_p2m<R>), grid, dim3(64), 0, s, g, (const double *)p->d_pmt_sw, RBT,     \
                                (const double *)p->d_me, drho);                                              \
