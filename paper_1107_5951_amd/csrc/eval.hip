@@ -165,6 +165,9 @@ __global__ void __launch_bounds__(256) k_p2m_lds(DevGeom g, const double *rho, c
                 if (more)
                     bv[c][u] = density(c, 4 * (j + 1) + u);
             }
+        // the densities as the A operand and the operator as B: the product
+        // is the transposed tile (rows = columns, columns = coefficients),
+        // so that the stores below write whole rows of 16 coefficients
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -172,7 +175,7 @@ __global__ void __launch_bounds__(256) k_p2m_lds(DevGeom g, const double *rho, c
                 const double a = sa[buf][(u * RB + r) * 64 + lane];
 #pragma unroll
                 for (int c = 0; c < NCG; ++c)
-                    acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cur[c][u], acc[c][r], 0, 0, 0);
+                    acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[c][u], a, acc[c][r], 0, 0, 0);
             }
         if (more) {
 #pragma unroll
@@ -181,17 +184,21 @@ __global__ void __launch_bounds__(256) k_p2m_lds(DevGeom g, const double *rho, c
         }
         __syncthreads();
     }
+    // output fragment: rows kr + 4 i = columns of the block, column lane % 16
+    // = coefficient 16 r + lane % 16: 16 lanes write 128 contiguous bytes
 #pragma unroll
-    for (int c = 0; c < NCG; ++c) {
-        if (!cvalid[c])
-            continue;
-        double *dst = me + ((lv.me_off + leaf[c]) * g.B + bm[c]) * PS;
+    for (int c = 0; c < NCG; ++c)
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int i = 0; i < 4; ++i) {
+            const int64_t col = ((int64_t)blockIdx.x * 4 + wave) * 16 * NCG + c * 16 + kr + 4 * i;
+            if (col >= nleaf * g.B)
+                continue;
+            const int cbm = (int)(col / nleaf);
+            double *dst = me + ((lv.me_off + col - (int64_t)cbm * nleaf) * g.B + cbm) * PS + (lane & 15);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                dst[16 * r + kr + 4 * i] = acc[c][r][i];
-    }
+            for (int r = 0; r < RB; ++r)
+                dst[16 * r] = acc[c][r][i];
+        }
 }
 
 // --------------------------------------------------------------------------
