@@ -278,11 +278,14 @@ k_t_l2l(DevGeom g, int l, const uint32_t *tkey, const int32_t *tchild, const dou
             b01 = bp ? bp[2 * qn] : double2{0.0, 0.0};
             b23 = bp ? bp[2 * qn + 1] : double2{0.0, 0.0};
         }
+        // the children's expansions as the A operand and the matrix as B:
+        // the product is the transposed tile (rows = columns, columns =
+        // coefficients)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < RB; ++r)
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[u], sa[buf][(u * RB + r) * 64 + lane], acc[r], 0, 0,
                                                              0);
         if (more) {
 #pragma unroll
@@ -291,14 +294,18 @@ k_t_l2l(DevGeom g, int l, const uint32_t *tkey, const int32_t *tchild, const dou
         }
         __syncthreads();
     }
-    if (!cvalid)
-        return;
-    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
+    // output fragment: rows kr + 4 i = columns of the wave, column lane % 16
+    // = coefficient 16 r + lane % 16: 16 lanes write 128 contiguous bytes
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int i = 0; i < 4; ++i) {
+        const int64_t oc = (int64_t)blockIdx.x * 64 + wave * 16 + kr + 4 * i;
+        if (oc >= lv.n_tgt * g.B)
+            continue;
+        double *dst = le + (lv.tgt_off * g.B + oc) * PS + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            dst[16 * r + kr + 4 * i] = acc[r][i];
+        for (int r = 0; r < RB; ++r)
+            dst[16 * r] = acc[r][i];
+    }
 }
 
 // L2L^T on levels with few boxes: a workgroup owns 16 columns and one
@@ -431,11 +438,14 @@ k_t_m2m(DevGeom g, int l, ColBlock cb, const double *A, double *me)
             b01 = cvalid ? bp[2 * (j + 1)] : double2{0.0, 0.0};
             b23 = cvalid ? bp[2 * (j + 1) + 1] : double2{0.0, 0.0};
         }
+        // the parents' expansions as the A operand and the matrix as B: the
+        // product is the transposed tile (rows = columns, columns =
+        // coefficients)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < RB; ++r)
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[u], sa[buf][(u * RB + r) * 64 + lane], acc[r], 0, 0,
                                                              0);
         if (more) {
 #pragma unroll
@@ -444,18 +454,27 @@ k_t_m2m(DevGeom g, int l, ColBlock cb, const double *A, double *me)
         }
         __syncthreads();
     }
-    if (ci < 0)
-        return;
+    // output fragment: rows kr + 4 i = columns of the wave (child and add
+    // flag from the lanes that own them), column lane % 16 = coefficient
+    // 16 r + lane % 16: 16 lanes write 128 contiguous bytes
     const bool add = x >= cb.lo[0] && x <= cb.hi[0] && y >= cb.lo[1] && y <= cb.hi[1] && z >= cb.lo[2] &&
                      z <= cb.hi[2];
-    double *dst = me + ((lv.me_off + ci) * g.B + bm) * PS;
+    const int ci32 = (int)ci, add32 = add ? 1 : 0;
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int i = 0; i < 4; ++i) {
+        const int oc = kr + 4 * i;
+        const int oci = __shfl(ci32, oc);
+        const int oadd = __shfl(add32, oc);
+        if (oci < 0)
+            continue;
+        const int obm = (int)(((int64_t)blockIdx.x * 64 + wave * 16 + oc) % g.B);
+        double *dst = me + ((lv.me_off + oci) * g.B + obm) * PS + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            double *o = dst + 16 * r + kr + 4 * i;
-            *o = add ? *o + acc[r][i] : acc[r][i];
+        for (int r = 0; r < RB; ++r) {
+            double *o = dst + 16 * r;
+            *o = oadd ? *o + acc[r][i] : acc[r][i];
         }
+    }
 }
 
 // P2M^T: drho[cell] = sum_k Pm[v][k] ME_L[leaf][k] for the cells v of every

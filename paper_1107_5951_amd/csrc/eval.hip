@@ -277,11 +277,13 @@ __global__ void __launch_bounds__(256) k_m2m_lds(DevGeom g, int l, const double 
             b01 = bp ? bp[2 * qn] : double2{0.0, 0.0};
             b23 = bp ? bp[2 * qn + 1] : double2{0.0, 0.0};
         }
+        // the expansions as the A operand and the operator as B: the product
+        // is the transposed tile (rows = columns, columns = coefficients)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < RB; ++r)
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[u], sa[buf][(u * RB + r) * 64 + lane], acc[r], 0, 0,
                                                              0);
         if (more) {
 #pragma unroll
@@ -290,15 +292,18 @@ __global__ void __launch_bounds__(256) k_m2m_lds(DevGeom g, int l, const double 
         }
         __syncthreads();
     }
-    if (!cvalid)
-        return;
-    // output fragment: column lane % 16, rows lane / 16 + 4 i of each block
-    double *dst = me + ((lp.me_off + box) * g.B + bm) * PS;
+    // output fragment: rows kr + 4 i = columns of the wave, column lane % 16
+    // = coefficient 16 r + lane % 16: 16 lanes write 128 contiguous bytes
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int i = 0; i < 4; ++i) {
+        const int64_t oc = (int64_t)blockIdx.x * 64 + wave * 16 + kr + 4 * i;
+        if (oc >= nbox * g.B)
+            continue;
+        double *dst = me + (lp.me_off * g.B + oc) * PS + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            dst[16 * r + kr + 4 * i] = acc[r][i];
+        for (int r = 0; r < RB; ++r)
+            dst[16 * r] = acc[r][i];
+    }
 }
 
 // Small levels (too few columns to fill the chip with 64-column tiles):
@@ -439,11 +444,14 @@ k_l2l_lds(DevGeom g, const GemmTile *tiles, int stride, const int32_t *torder, c
             b01 = cvalid ? bp[2 * (j + 1)] : double2{0.0, 0.0};
             b23 = cvalid ? bp[2 * (j + 1) + 1] : double2{0.0, 0.0};
         }
+        // the parents' expansions as the A operand and the matrix as B: the
+        // product is the transposed tile (rows = columns, columns =
+        // coefficients)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < RB; ++r)
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[buf][(u * RB + r) * 64 + lane], bv[u], acc[r], 0, 0,
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[u], sa[buf][(u * RB + r) * 64 + lane], acc[r], 0, 0,
                                                              0);
         if (more) {
 #pragma unroll
@@ -452,14 +460,22 @@ k_l2l_lds(DevGeom g, const GemmTile *tiles, int stride, const int32_t *torder, c
         }
         __syncthreads();
     }
-    if (!cvalid)
-        return;
-    double *dst = le + ((lv.tgt_off + box) * g.B + bm) * PS;
+    // output fragment: rows kr + 4 i = columns of the wave (their boxes from
+    // the lanes that own them), column lane % 16 = coefficient 16 r +
+    // lane % 16: 16 lanes add into 128 contiguous bytes
+    const int box32 = (int)box;
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int i = 0; i < 4; ++i) {
+        const int oc = kr + 4 * i;
+        const int obox = __shfl(box32, oc);
+        if (wave * 16 + oc >= tile.ncol)
+            continue;
+        const int obm = (int)((tile.col0 + wave * 16 + oc) % g.B);
+        double *dst = le + ((lv.tgt_off + obox) * g.B + obm) * PS + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            dst[16 * r + kr + 4 * i] += acc[r][i];
+        for (int r = 0; r < RB; ++r)
+            dst[16 * r] += acc[r][i];
+    }
 }
 
 // --------------------------------------------------------------------------
