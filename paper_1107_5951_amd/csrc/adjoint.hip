@@ -1017,10 +1017,13 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho,
 //   drho[S] (+)= sum over the 27 neighbours d of A_d^T w_{S - d}   (near^T)
 //   LE[T]   (+)= Lm^T w_T                                          (L2P^T)
 // GEMMs with columns = (leaf, model) and contraction over (centre t,
-// component) of the target leaf: chunk q and k step u take t = (lane/16) TQ
-// + q and component u, so a lane's four k steps are the four weights of one
-// centre (one 32-byte load from the weights, found through the centre's
-// sorted slot).  Centres outside the mesh or past b^3 read zero.
+// component) of the target leaf.  L2P^T: chunk q and k step u take t =
+// (lane/16) TQ + q and component u, so a lane's four k steps are the four
+// weights of one centre (one 32-byte load from the weights, found through
+// the centre's sorted slot).  near^T: only the C output components, value
+// e = C t + c in chunk q, sub-row kr and k step u with e = 4 KQ kr + 4 q +
+// u, read from the weight blocks.  Centres outside the mesh or past b^3 read
+// zero.
 __device__ __forceinline__ void lattice_weights(const DevGeom &g, const int32_t *cell_slot, const double *w, int tx,
                                                 int ty, int tz, int t, int bm, bool in, double (&v)[4])
 {
@@ -1042,13 +1045,14 @@ __device__ __forceinline__ void lattice_weights(const DevGeom &g, const int32_t 
 }
 
 // The weights of the cell centres in leaf blocks for near^T, as k_rho_blocks
-// lays out the densities: centre t = kr TQ + q of a leaf, its four weights
-// at blk[q][kr][pl * B + model][0..3], pl = the leaf's index in the source
-// block padded by one leaf per side (padding zero).  One thread per
-// (leaf, model, centre).
+// lays out the densities, for the C output components only: value e =
+// C t + c (centre t, component c of the C) of a leaf sits at
+// blk[q][kr][pl * B + model][u] with e = 4 KQ kr + 4 q + u, pl = the leaf's
+// index in the source block padded by one leaf per side (padding and
+// e >= C b^3 zero).  One thread per (leaf, model, centre).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_t_wblocks(DevGeom g, const int32_t *cell_slot, const double *w, int TQ, int64_t nplB, T *blk)
+k_t_wblocks(DevGeom g, const int32_t *cell_slot, const double *w, int KQ, int64_t nplB, T *blk)
 {
     const DevLev &lv = g.lev[g.L];
     const int b = g.b, b3 = b * b * b;
@@ -1064,20 +1068,21 @@ k_t_wblocks(DevGeom g, const int32_t *cell_slot, const double *w, int TQ, int64_
     double v[4];
     lattice_weights(g, cell_slot, w, lx, ly, lz, t, bm, true, v);
     const int64_t pl = ((int64_t)(lz + 1) * (lv.ns[1] + 2) + (ly + 1)) * (lv.ns[0] + 2) + (lx + 1);
-    T *o = blk + ((int64_t)((t % TQ) * 4 + t / TQ) * nplB + pl * g.B + bm) * 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-        o[u] = (T)v[u];
+    for (int c = 0; c < g.C; ++c) {
+        const int e = g.C * t + c, kr = e / (4 * KQ), q = (e / 4) % KQ;
+        blk[((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm) * 4 + e % 4] = (T)v[c + 4 - g.C];
+    }
 }
 
 // near^T: a workgroup owns CW blocks of 16 (source leaf, model) columns and
-// four 16-cell row blocks (blockIdx.y); its four waves split the 27 TQ
-// chunks (neighbour d, centre chunk q) and add their partial tiles through
-// LDS in wave order (deterministic), as k_near_lat does.  Target leaf T =
-// S - d reads the padded weight blocks (no bounds test).
+// four 16-cell row blocks (blockIdx.y); its four waves split the 27 KQ
+// chunks (neighbour d, chunk q of the target leaf's C b^3 weights) and add
+// their partial tiles through LDS in wave order (deterministic), as
+// k_near_lat does.  Target leaf T = S - d reads the padded weight blocks (no
+// bounds test).
 template <int CW, typename T>
 __global__ void __launch_bounds__(256)
-k_t_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBt, int TQ, int add, double *drho)
+k_t_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBt, int KQ, int add, double *drho)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     __shared__ double red[4][CW * 4 * 4][64];
@@ -1109,10 +1114,10 @@ k_t_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBt, int TQ,
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             acc[c][r] = vec4{0, 0, 0, 0};
-    const int NI = 27 * TQ;
+    const int NI = 27 * KQ;
     const int i0 = wave * NI / 4, i1 = (wave + 1) * NI / 4;
     for (int i = i0; i < i1; ++i) {
-        const int nb = i / TQ, q = i - nb * TQ;
+        const int nb = i / KQ, q = i - nb * KQ;
         // the forward pairs target leaf T with source leaf T + d: T = S - d
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
         const int64_t boff = ((int64_t)q * 4 * nplB + (((int64_t)(-dz) * py - dy) * px - dx) * g.B) * 4;
@@ -1123,7 +1128,7 @@ k_t_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBt, int TQ,
         T av[4][4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            load_frags<T, 4>(A + (((int64_t)nb * TQ + q) * RBt + min(rb0 + r, RBt - 1)) * 256, lane, av[r]);
+            load_frags<T, 4>(A + (((int64_t)nb * KQ + q) * RBt + min(rb0 + r, RBt - 1)) * 256, lane, av[r]);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -1321,21 +1326,23 @@ static grav_status launch_t_near_lat(Plan *p, const DevGeom &g, int add, double 
     constexpr int CW = 2;
     const LevelInfo &lv = p->lev[p->L];
     const int b3 = p->b * p->b * p->b, RBt = (int)ceil_div(b3, 16);
+    // chunks of 16 weights over the C b^3 (centre, component) pairs of a leaf
+    const int KQ = (int)ceil_div((int64_t)p->d.components * b3, 16);
     const int64_t nplB = (int64_t)(lv.ns[0] + 2) * (lv.ns[1] + 2) * (lv.ns[2] + 2) * p->B;
     const bool f64 = p->d.precision == GRAV_FP64;
     const dim3 fgrid((unsigned)ceil_div(lv.n_src * p->B * b3, 256));
     const dim3 grid((unsigned)ceil_div(lv.n_src * p->B, 16 * CW), (unsigned)ceil_div(RBt, 4));
     if (f64) {
         hipLaunchKernelGGL((k_t_wblocks<double>), fgrid, dim3(256), 0, s, g, (const int32_t *)p->d_cell_slot,
-                           (const double *)p->d_near, p->lat_TQ, nplB, p->d_w_blk);
+                           (const double *)p->d_near, KQ, nplB, p->d_w_blk);
         hipLaunchKernelGGL((k_t_near_lat<CW, double>), grid, dim3(256), 0, s, g, (const double *)p->d_w_blk, nplB,
-                           (const double *)p->d_tnt64, RBt, p->lat_TQ, add, drho);
+                           (const double *)p->d_tnt64, RBt, KQ, add, drho);
     } else {
         float *wb = reinterpret_cast<float *>(p->d_w_blk);
         hipLaunchKernelGGL((k_t_wblocks<float>), fgrid, dim3(256), 0, s, g, (const int32_t *)p->d_cell_slot,
-                           (const double *)p->d_near, p->lat_TQ, nplB, wb);
+                           (const double *)p->d_near, KQ, nplB, wb);
         hipLaunchKernelGGL((k_t_near_lat<CW, float>), grid, dim3(256), 0, s, g, (const float *)wb, nplB,
-                           (const float *)p->d_tnt32, RBt, p->lat_TQ, add, drho);
+                           (const float *)p->d_tnt32, RBt, KQ, add, drho);
     }
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;

@@ -1223,8 +1223,9 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
     }
     // the adjoint's transposes: rows = the cells of the source leaf (RBt
     // blocks of 16), contraction over (target t, component) of the target
-    // leaf, chunk q and k step u taking t = (lane/16) TQ + q, component u;
-    // [nb][q][rb][lane][u] group-major sets
+    // leaf (near^T: the C output components; L2P^T: chunk q and k step u
+    // taking t = (lane/16) TQ + q, component u); [nb][q][rb][lane][u]
+    // group-major sets
     const int TQ = (int)ceil_div(b3, 4), RBt = (int)ceil_div(b3, 16);
     p->lat_TQ = TQ;
     {
@@ -1239,16 +1240,21 @@ grav_status build_near_lattice(Plan *p, hipStream_t s)
         GRAV_HIP(hipStreamSynchronize(p->bs));
     }
     {
-        std::vector<double> swt((size_t)27 * TQ * RBt * 256, 0.0);
+        // contraction over the C b^3 (centre, output component) pairs of the
+        // target leaf: value e = C t + c in chunk q, sub-row kr, k step u
+        // with e = 4 KQ kr + 4 q + u (the weight blocks' order)
+        const int KQ = (int)ceil_div((int64_t)C * b3, 16);
+        std::vector<double> swt((size_t)27 * KQ * RBt * 256, 0.0);
         for (int nb = 0; nb < 27; ++nb)
-            for (int q = 0; q < TQ; ++q)
+            for (int q = 0; q < KQ; ++q)
                 for (int rb = 0; rb < RBt; ++rb)
                     for (int lane = 0; lane < 64; ++lane)
                         for (int u = 0; u < 4; ++u) {
-                            const int t = (lane >> 4) * TQ + q, cell = 16 * rb + (lane & 15);
+                            const int e = 4 * KQ * (lane >> 4) + 4 * q + u, cell = 16 * rb + (lane & 15);
+                            const int t = e / C, comp = e % C + 4 - C;
                             const double v =
-                                t < b3 && cell < b3 ? dense[((size_t)nb * 4 * b3 + 4 * t + u) * b3 + cell] : 0.0;
-                            swt[(((size_t)nb * TQ + q) * RBt + rb) * 256 + frag_pos(lane, u, f64 ? 2 : 4)] = v;
+                                t < b3 && cell < b3 ? dense[((size_t)nb * 4 * b3 + 4 * t + comp) * b3 + cell] : 0.0;
+                            swt[(((size_t)nb * KQ + q) * RBt + rb) * 256 + frag_pos(lane, u, f64 ? 2 : 4)] = v;
                         }
         if (f64) {
             GRAV_CHECK(upload(p, &p->d_tnt64, swt));

@@ -56,6 +56,12 @@ CASES = [
     ("ragged phi+g", dict(n=(13, 7, 9), h=0.1, origin=(-0.3, 0.2, -1.0), quad_order=1,
                           points=np.random.default_rng(4).uniform(-1.5, 2.0, size=(300, 3)),
                           components=4, p=12, leaf_size=8)),
+    # lattice leaves of 27 cells: the transposed near field contracts over
+    # C b^3 = 27 and 81 (centre, component) pairs, chunks not filled
+    ("volume gz b3", dict(n=(27, 21, 24), h=1 / 32, quad_order=1, voxel_centres=True, components=1, p=8,
+                          leaf_size=27)),
+    ("volume g b3", dict(n=(27, 21, 24), h=1 / 32, quad_order=1, voxel_centres=True, components=3, p=8,
+                         leaf_size=27)),
 ]
 
 
