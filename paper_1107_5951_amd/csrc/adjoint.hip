@@ -624,23 +624,45 @@ k_m2lt_sum(const T *part, const int32_t *colmap, const int64_t *colbox, const in
 // the pair terms (1/r, (t - x)/r^3) of each of the cell's quadrature
 // points, with the forward's coincidence rule and arithmetic type T.  One
 // thread per (cell, model group): the pair geometry is computed once for the
-// group's models.
+// group's models.  With `leaves` (and `prior`), only the cells of those
+// source leaves (the leaves with user points around them; the other cells
+// keep their prior terms), else every cell.
 template <typename T, int MT>
 __global__ void __launch_bounds__(256)
 k_t_cells(DevGeom g, const double *tpos, const int64_t *leaf_start, const int64_t *pend, int64_t n_leaf,
-          const int32_t *tmap, int64_t n_tmap, const double *w, int prior, double *drho)
+          const int32_t *tmap, int64_t n_tmap, const double *w, int prior, const int32_t *leaves, int64_t n_leaves,
+          double *drho)
 {
     const int NG = (g.B + MT - 1) / MT;
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncell * NG)
-        return;
-    const int grp = (int)(t / ncell);
-    const int64_t cell = t - (int64_t)grp * ncell;
-    const int ix = (int)(cell % g.n[0]), iy = (int)((cell / g.n[0]) % g.n[1]),
-              iz = (int)(cell / ((int64_t)g.n[0] * g.n[1]));
     const int b = g.b;
     const DevLev &lv = g.lev[g.L];
+    int grp, ix, iy, iz;
+    if (leaves) {
+        const int b3 = b * b * b;
+        const int64_t per = n_leaves * b3;
+        if (t >= per * NG)
+            return;
+        grp = (int)(t / per);
+        const int64_t r = t - (int64_t)grp * per;
+        const int64_t sl = leaves[r / b3];
+        const int v = (int)(r % b3);
+        ix = (lv.s0[0] + (int)(sl % lv.ns[0]) - g.shift[0]) * b + v % b;
+        iy = (lv.s0[1] + (int)((sl / lv.ns[0]) % lv.ns[1]) - g.shift[1]) * b + (v / b) % b;
+        iz = (lv.s0[2] + (int)(sl / ((int64_t)lv.ns[0] * lv.ns[1])) - g.shift[2]) * b + v / (b * b);
+        if (ix < 0 || iy < 0 || iz < 0 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
+            return;
+    } else {
+        if (t >= ncell * NG)
+            return;
+        grp = (int)(t / ncell);
+        const int64_t c = t - (int64_t)grp * ncell;
+        ix = (int)(c % g.n[0]);
+        iy = (int)((c / g.n[0]) % g.n[1]);
+        iz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    }
+    const int64_t cell = ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
     // the cell's leaf (root-relative) and place in it
     const int lx = ix / b + g.shift[0], ly = iy / b + g.shift[1], lz = iz / b + g.shift[2];
     const int v = (ix % b) + b * ((iy % b) + b * (iz % b));
@@ -1438,15 +1460,21 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
         const int prior = (L >= 2 || p->lat_near) ? 1 : 0;
         const int64_t *pend = p->lat_near ? (const int64_t *)p->d_leaf_pend : nullptr;
         stage_begin(p, "nearT_pts", s);
-        if (p->d.precision == GRAV_FP64)
-            hipLaunchKernelGGL((k_t_cells<double, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
-                               (const int64_t *)p->d_leaf_start, pend, p->n_leaf, (const int32_t *)p->d_tmap,
-                               p->n_tmap, (const double *)p->d_near, prior, drho);
-        else
-            hipLaunchKernelGGL((k_t_cells<float, MT>), grid(ncell * NG), blk, 0, s, g, (const double *)p->d_tpos,
-                               (const int64_t *)p->d_leaf_start, pend, p->n_leaf, (const int32_t *)p->d_tmap,
-                               p->n_tmap, (const double *)p->d_near, prior, drho);
-        GRAV_HIP(hipGetLastError());
+        // with prior terms only the cells of the leaves near user points
+        // change (none when the points lie away from the mesh)
+        const int32_t *leaves = prior ? p->d_pt_leaves : nullptr;
+        const int64_t nthr = leaves ? p->n_pt_leaves * p->b * p->b * p->b * NG : ncell * NG;
+        if (nthr > 0) {
+            if (p->d.precision == GRAV_FP64)
+                hipLaunchKernelGGL((k_t_cells<double, MT>), grid(nthr), blk, 0, s, g, (const double *)p->d_tpos,
+                                   (const int64_t *)p->d_leaf_start, pend, p->n_leaf, (const int32_t *)p->d_tmap,
+                                   p->n_tmap, (const double *)p->d_near, prior, leaves, p->n_pt_leaves, drho);
+            else
+                hipLaunchKernelGGL((k_t_cells<float, MT>), grid(nthr), blk, 0, s, g, (const double *)p->d_tpos,
+                                   (const int64_t *)p->d_leaf_start, pend, p->n_leaf, (const int32_t *)p->d_tmap,
+                                   p->n_tmap, (const double *)p->d_near, prior, leaves, p->n_pt_leaves, drho);
+            GRAV_HIP(hipGetLastError());
+        }
         stage_end(p, s);
     }
     return GRAV_OK;

@@ -318,7 +318,7 @@ void free_plan(Plan *p)
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
                     p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
                     p->d_m2mt_sw, p->d_l2lt_sw, p->d_l2l_msw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk,
-                    p->d_spos, p->d_sw, p->d_sperm, p->d_sstart};
+                    p->d_spos, p->d_sw, p->d_sperm, p->d_sstart, p->d_pt_leaves};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -1086,6 +1086,36 @@ __global__ void k_fill_tchild(const int32_t *cparent, int64_t nc, int64_t np, in
 // Lookup tables of the adjoint: target-box maps over each level's source
 // block plus a halo of 3 boxes (M2L transpose, near field transpose) and the
 // first-child table of each level (L2L transpose).
+// Source leaves of the leaf level with some user point in their 27
+// neighbour leaves (target map entry with pend > start), appended in any
+// order: the cells of the other leaves get no term from the transposed
+// point near field.
+__global__ void k_point_leaves(const int32_t *tmap, int64_t n_tmap, int64_t tmap_off, int nsx, int nsy, int nsz,
+                               const int64_t *leaf_start, const int64_t *pend,
+                               int64_t n_leaf, int32_t *list, unsigned long long *count)
+{
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= (int64_t)nsx * nsy * nsz)
+        return;
+    const int lx = (int)(sl % nsx), ly = (int)((sl / nsx) % nsy), lz = (int)(sl / ((int64_t)nsx * nsy));
+    const int mxl = nsx + 6, myl = nsy + 6, mzl = nsz + 6;
+    bool active = false;
+    for (int nb = 0; nb < 27 && !active; ++nb) {
+        // neighbour position in the target map (source block + halo 3)
+        const int mx = lx + nb % 3 - 1 + 3, my = ly + (nb / 3) % 3 - 1 + 3, mz = lz + nb / 9 - 1 + 3;
+        if (mx < 0 || my < 0 || mz < 0 || mx >= mxl || my >= myl || mz >= mzl)
+            continue;
+        const int64_t mi = tmap_off + ((int64_t)mz * myl + my) * mxl + mx;
+        if (mi >= n_tmap)
+            continue;
+        const int64_t tl = tmap[mi];
+        if (tl >= 0 && tl < n_leaf && pend[tl] > max(leaf_start[tl], (int64_t)0))
+            active = true;
+    }
+    if (active)
+        list[atomicAdd(count, 1ull)] = (int32_t)sl;
+}
+
 grav_status build_adjoint_maps(Plan *p)
 {
     const int L = p->L;
@@ -1123,6 +1153,31 @@ grav_status build_adjoint_maps(Plan *p)
                                p->lev[l].n_tgt, p->d_tchild + p->lev[l].tchild_off);
             GRAV_HIP(hipGetLastError());
         }
+    }
+    {
+        // the leaf level's source leaves near user points
+        const LevelInfo &lv = p->lev[L];
+        GRAV_CHECK(dalloc(p, &p->d_pt_leaves, (size_t)std::max<int64_t>(lv.n_src, 1), true));
+        unsigned long long *cnt = nullptr;
+        GRAV_HIP(hipMalloc(&cnt, sizeof(unsigned long long)));
+        grav_status st = GRAV_OK;
+        unsigned long long n = 0;
+        if (hipMemsetAsync(cnt, 0, sizeof(unsigned long long), p->bs) != hipSuccess)
+            st = GRAV_EDEVICE;
+        if (st == GRAV_OK && lv.n_src > 0) {
+            hipLaunchKernelGGL(k_point_leaves, dim3((unsigned)ceil_div(lv.n_src, 256)), dim3(256), 0, p->bs,
+                               (const int32_t *)p->d_tmap, p->n_tmap, lv.tmap_off, lv.ns[0], lv.ns[1], lv.ns[2],
+                               (const int64_t *)p->d_leaf_start,
+                               (const int64_t *)p->d_leaf_pend, p->n_leaf, p->d_pt_leaves, cnt);
+            if (hipGetLastError() != hipSuccess)
+                st = GRAV_EDEVICE;
+        }
+        if (st == GRAV_OK && (hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, p->bs) != hipSuccess ||
+                              hipStreamSynchronize(p->bs) != hipSuccess))
+            st = GRAV_EDEVICE;
+        (void)hipFree(cnt);
+        GRAV_CHECK(st);
+        p->n_pt_leaves = (int64_t)n;
     }
     GRAV_HIP(hipStreamSynchronize(p->bs));
     return GRAV_OK;
