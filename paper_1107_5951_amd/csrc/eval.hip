@@ -668,12 +668,12 @@ template __global__ void k_m2l_sum<float>(const float *, const int32_t *, const 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_p2p(DevGeom g, const double *rho, const double *tpos, const int64_t *leaf_start,
-      const int64_t *leaf_end, const uint32_t *tkey, double *near)
+      const int64_t *leaf_end, const uint32_t *tkey, const int32_t *leaves, double *near)
 {
     __shared__ double srho[512];
     __shared__ double red[256][4];
     const DevLev &lv = g.lev[g.L];
-    const int64_t leaf = blockIdx.x;
+    const int64_t leaf = leaves[blockIdx.x];  // the target leaves holding user points
     const int64_t ts = leaf_start[leaf], te = leaf_end[leaf];
     const int64_t nt = te - ts;
     if (nt <= 0)
@@ -893,12 +893,12 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_p2p_src(DevGeom g, const double *rho, const double *spos, const double *sw, const uint32_t *sperm,
           const int64_t *sstart, int64_t nsrc, const double *tpos, const int64_t *leaf_start, const int64_t *leaf_end,
-          const uint32_t *tkey, double *near)
+          const uint32_t *tkey, const int32_t *leaves, double *near)
 {
     __shared__ T sp[256][4];
     __shared__ double red[256][4];
     const DevLev &lv = g.lev[g.L];
-    const int64_t leaf = blockIdx.x;
+    const int64_t leaf = leaves[blockIdx.x];  // the target leaves holding user points
     const int64_t ts = leaf_start[leaf], te = leaf_end[leaf];
     const int64_t nt = te - ts;
     if (nt <= 0)
@@ -1645,26 +1645,30 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
     }
     if (!p->lat_near || p->d.n_points > 0) {
         stage_begin(p, "p2p", s);
-        if (p->n_spts > 0 && p->d.precision == GRAV_FP64)
-            hipLaunchKernelGGL(k_p2p_src<double>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+        // one workgroup per target leaf holding user points
+        const dim3 pgrid((unsigned)p->n_user_leaves);
+        const int32_t *ul = (const int32_t *)p->d_user_leaves;
+        if (p->n_user_leaves == 0) {
+        } else if (p->n_spts > 0 && p->d.precision == GRAV_FP64)
+            hipLaunchKernelGGL(k_p2p_src<double>, pgrid, dim3(256), 0, s, g, rho,
                                (const double *)p->d_spos, (const double *)p->d_sw, (const uint32_t *)p->d_sperm,
                                (const int64_t *)p->d_sstart, p->n_spts, (const double *)p->d_tpos,
                                (const int64_t *)p->d_leaf_start, (const int64_t *)p->d_leaf_pend,
-                               (const uint32_t *)p->d_tkey, p->d_near);
+                               (const uint32_t *)p->d_tkey, ul, p->d_near);
         else if (p->n_spts > 0)
-            hipLaunchKernelGGL(k_p2p_src<float>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+            hipLaunchKernelGGL(k_p2p_src<float>, pgrid, dim3(256), 0, s, g, rho,
                                (const double *)p->d_spos, (const double *)p->d_sw, (const uint32_t *)p->d_sperm,
                                (const int64_t *)p->d_sstart, p->n_spts, (const double *)p->d_tpos,
                                (const int64_t *)p->d_leaf_start, (const int64_t *)p->d_leaf_pend,
-                               (const uint32_t *)p->d_tkey, p->d_near);
+                               (const uint32_t *)p->d_tkey, ul, p->d_near);
         else if (p->d.precision == GRAV_FP64)
-            hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+            hipLaunchKernelGGL(k_p2p<double>, pgrid, dim3(256), 0, s, g, rho,
                                (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
-                               (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, p->d_near);
+                               (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, ul, p->d_near);
         else
-            hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)p->n_leaf), dim3(256), 0, s, g, rho,
+            hipLaunchKernelGGL(k_p2p<float>, pgrid, dim3(256), 0, s, g, rho,
                                (const double *)p->d_tpos, (const int64_t *)p->d_leaf_start,
-                               (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, p->d_near);
+                               (const int64_t *)p->d_leaf_pend, (const uint32_t *)p->d_tkey, ul, p->d_near);
         GRAV_HIP(hipGetLastError());
         stage_end(p, s);
         stage_begin(p, "l2p", s);

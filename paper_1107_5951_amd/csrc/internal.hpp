@@ -197,7 +197,9 @@ struct Plan {
     double *d_rho_blk = nullptr;                   // [Q][4][padded leaves x B][4] densities per leaf (FP32 in mixed plans)
     int64_t *d_leaf_pend = nullptr;                // [n_leaf] end of the user points of a leaf
     int32_t *d_pt_leaves = nullptr;                // source leaves with user points in their 27 neighbours
-    int64_t n_pt_leaves = 0;                       // (any order), for the adjoint's point near field                  // workgroups sharing the offsets of one tile
+    int64_t n_pt_leaves = 0;                       // (any order), for the adjoint's point near field
+    int32_t *d_user_leaves = nullptr;              // target leaves holding user points (any order), for
+    int64_t n_user_leaves = 0;                     // the point near field                  // workgroups sharing the offsets of one tile
     double *d_part = nullptr;                      // [split][expansions][PS] partial sums
     int32_t *d_class_off = nullptr;  // [8][189][4] (dx, dy, dz, offset id)
     int32_t *d_rclass_off = nullptr; // same for the transposed M2L, keyed by source class

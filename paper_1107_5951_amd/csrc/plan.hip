@@ -318,7 +318,7 @@ void free_plan(Plan *p)
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
                     p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
                     p->d_m2mt_sw, p->d_l2lt_sw, p->d_l2l_msw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk,
-                    p->d_spos, p->d_sw, p->d_sperm, p->d_sstart, p->d_pt_leaves};
+                    p->d_spos, p->d_sw, p->d_sperm, p->d_sstart, p->d_pt_leaves, p->d_user_leaves};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -1116,6 +1116,15 @@ __global__ void k_point_leaves(const int32_t *tmap, int64_t n_tmap, int64_t tmap
         list[atomicAdd(count, 1ull)] = (int32_t)sl;
 }
 
+// Target leaves holding user points (pend > start), appended in any order.
+__global__ void k_user_leaves(const int64_t *leaf_start, const int64_t *pend, int64_t n_leaf, int32_t *list,
+                              unsigned long long *count)
+{
+    const int64_t tl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tl < n_leaf && pend[tl] > max(leaf_start[tl], (int64_t)0))
+        list[atomicAdd(count, 1ull)] = (int32_t)tl;
+}
+
 grav_status build_adjoint_maps(Plan *p)
 {
     const int L = p->L;
@@ -1155,14 +1164,16 @@ grav_status build_adjoint_maps(Plan *p)
         }
     }
     {
-        // the leaf level's source leaves near user points
+        // the leaf level's source leaves near user points, and the target
+        // leaves holding user points
         const LevelInfo &lv = p->lev[L];
         GRAV_CHECK(dalloc(p, &p->d_pt_leaves, (size_t)std::max<int64_t>(lv.n_src, 1), true));
+        GRAV_CHECK(dalloc(p, &p->d_user_leaves, (size_t)std::max<int64_t>(p->n_leaf, 1), true));
         unsigned long long *cnt = nullptr;
-        GRAV_HIP(hipMalloc(&cnt, sizeof(unsigned long long)));
+        GRAV_HIP(hipMalloc(&cnt, 2 * sizeof(unsigned long long)));
         grav_status st = GRAV_OK;
-        unsigned long long n = 0;
-        if (hipMemsetAsync(cnt, 0, sizeof(unsigned long long), p->bs) != hipSuccess)
+        unsigned long long n[2] = {0, 0};
+        if (hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), p->bs) != hipSuccess)
             st = GRAV_EDEVICE;
         if (st == GRAV_OK && lv.n_src > 0) {
             hipLaunchKernelGGL(k_point_leaves, dim3((unsigned)ceil_div(lv.n_src, 256)), dim3(256), 0, p->bs,
@@ -1172,12 +1183,20 @@ grav_status build_adjoint_maps(Plan *p)
             if (hipGetLastError() != hipSuccess)
                 st = GRAV_EDEVICE;
         }
-        if (st == GRAV_OK && (hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, p->bs) != hipSuccess ||
+        if (st == GRAV_OK && p->n_leaf > 0) {
+            hipLaunchKernelGGL(k_user_leaves, dim3((unsigned)ceil_div(p->n_leaf, 256)), dim3(256), 0, p->bs,
+                               (const int64_t *)p->d_leaf_start, (const int64_t *)p->d_leaf_pend, p->n_leaf,
+                               p->d_user_leaves, cnt + 1);
+            if (hipGetLastError() != hipSuccess)
+                st = GRAV_EDEVICE;
+        }
+        if (st == GRAV_OK && (hipMemcpyAsync(n, cnt, sizeof(n), hipMemcpyDeviceToHost, p->bs) != hipSuccess ||
                               hipStreamSynchronize(p->bs) != hipSuccess))
             st = GRAV_EDEVICE;
         (void)hipFree(cnt);
         GRAV_CHECK(st);
-        p->n_pt_leaves = (int64_t)n;
+        p->n_pt_leaves = (int64_t)n[0];
+        p->n_user_leaves = (int64_t)n[1];
     }
     GRAV_HIP(hipStreamSynchronize(p->bs));
     return GRAV_OK;
