@@ -127,14 +127,14 @@ __device__ __forceinline__ double l2pt_gather(const double *S, int P2, int mg, i
 template <int MG>
 __global__ void __launch_bounds__(256)
 k_t_l2p(DevGeom g, const double *tpos, const int64_t *leaf_start, const int64_t *pend, const uint32_t *tkey,
-        int64_t n_leaf, const double *w, double *le)
+        int64_t n_leaf, const int32_t *leaves, const double *w, double *le)
 {
     extern __shared__ double sh[];
     constexpr int TC = kL2PTChunk;
     const int P2 = g.P2;
     double *H = sh;             // [TC][P2] harmonics of the chunk's targets
     double *W = sh + TC * P2;   // [TC][MG][4] their scaled weights
-    const int64_t leaf = blockIdx.x;
+    const int64_t leaf = leaves[blockIdx.x];  // the target leaves holding user points
     const int bm0 = blockIdx.y * MG;
     const int tid = threadIdx.x;
     const DevLev &lv = g.lev[g.L];
@@ -1195,11 +1195,12 @@ k_t_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBt, int KQ,
 
 // L2P^T at the cell centres (FP64): one wave owns 16 (leaf, model) columns
 // and all RB coefficient blocks; the column's target leaf is found in the
-// leaf level's target map.
+// leaf level's target map.  With `add`, the LE of a leaf that also holds
+// user points (written by k_t_l2p) is added to, every other one set.
 template <int RB>
 __global__ void __launch_bounds__(64)
 k_t_l2p_lat(DevGeom g, const double *A, int TQ, const int32_t *tmap, const int32_t *cell_slot, const double *w,
-            int add, double *le)
+            int add, const int64_t *leaf_start, const int64_t *pend, double *le)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
     constexpr int PS = 16 * RB;
@@ -1233,13 +1234,14 @@ k_t_l2p_lat(DevGeom g, const double *A, int TQ, const int32_t *tmap, const int32
     }
     if (tl < 0 || tl >= lv.n_tgt)
         return;
+    const bool addc = add && pend[tl] > max(leaf_start[tl], (int64_t)0);
     double *dst = le + ((lv.tgt_off + tl) * g.B + bm) * PS;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             double *o = dst + 16 * r + kr + 4 * i;
-            *o = add ? *o + acc[r][i] : acc[r][i];
+            *o = addc ? *o + acc[r][i] : acc[r][i];
         }
 }
 
@@ -1331,7 +1333,7 @@ static grav_status launch_t_l2p_lat(Plan *p, const DevGeom &g, int add, hipStrea
     case R:                                                                                                 \
         hipLaunchKernelGGL((k_t_l2p_lat<R>), grid, dim3(64), 0, s, g, (const double *)p->d_tl2pt, p->lat_TQ, \
                            (const int32_t *)p->d_tmap, (const int32_t *)p->d_cell_slot, (const double *)p->d_near, \
-                           add, p->d_le);                                                                   \
+                           add, (const int64_t *)p->d_leaf_start, (const int64_t *)p->d_leaf_pend, p->d_le); \
         break;
     switch (p->PS / 16) {
         GRAV_T_RB_CASES(CASE)
@@ -1394,16 +1396,21 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
         if (p->n_leaf > 0 && pts) {
             const int MG = p->B == 1 ? 1 : kL2PTModels;
             const size_t lds = sizeof(double) * std::max(kL2PTChunk * (p->P2 + 4 * MG), 4 * MG * p->P2);
-            const dim3 lgrid((unsigned)p->n_leaf, (unsigned)ceil_div(p->B, MG));
+            // one workgroup per target leaf holding user points (the LE of
+            // the other leaves, cell centres only, is set by the lattice
+            // L2P^T below)
+            const dim3 lgrid((unsigned)p->n_user_leaves, (unsigned)ceil_div(p->B, MG));
             const int64_t *pend = p->lat_near ? (const int64_t *)p->d_leaf_pend : nullptr;
-            if (MG == 1)
+            const int32_t *ul = (const int32_t *)p->d_user_leaves;
+            if (p->n_user_leaves == 0) {
+            } else if (MG == 1)
                 hipLaunchKernelGGL((k_t_l2p<1>), lgrid, dim3(256), lds, s, g, (const double *)p->d_tpos,
                                    (const int64_t *)p->d_leaf_start, pend, (const uint32_t *)p->d_tkey, p->n_leaf,
-                                   (const double *)p->d_near, p->d_le);
+                                   ul, (const double *)p->d_near, p->d_le);
             else
                 hipLaunchKernelGGL((k_t_l2p<kL2PTModels>), lgrid, dim3(256), lds, s, g, (const double *)p->d_tpos,
                                    (const int64_t *)p->d_leaf_start, pend, (const uint32_t *)p->d_tkey, p->n_leaf,
-                                   (const double *)p->d_near, p->d_le);
+                                   ul, (const double *)p->d_near, p->d_le);
             GRAV_HIP(hipGetLastError());
         }
         if (p->lat_near)

@@ -62,6 +62,11 @@ CASES = [
                           leaf_size=27)),
     ("volume g b3", dict(n=(27, 21, 24), h=1 / 32, quad_order=1, voxel_centres=True, components=3, p=8,
                          leaf_size=27)),
+    # cell centres and user points in the same leaves (the transposed L2P
+    # adds the lattice part to the points' part there, sets it elsewhere)
+    ("centres + inner points", dict(n=(16, 16, 16), h=1 / 16, quad_order=1, voxel_centres=True, components=3,
+                                    points=np.random.default_rng(6).uniform(0.0, 1.0, size=(200, 3)), p=8,
+                                    leaf_size=64)),
 ]
 
 
