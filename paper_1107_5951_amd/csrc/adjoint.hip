@@ -31,24 +31,11 @@ namespace {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// combine^T: the weights that multiply (phi, gx, gy, gz) of each sorted
-// target in the lattice frame (G and the lattice-to-physical scale of the
-// combine folded in).  One thread per (sorted target, model).
-__global__ void __launch_bounds__(256)
-k_t_weights(DevGeom g, const double *resid, const uint32_t *perm, double *w)
+// combine^T: the weights that multiply (phi, gx, gy, gz) of a target in the
+// lattice frame (G and the lattice-to-physical scale of the combine folded
+// in), from its residual r (C values).
+__device__ __forceinline__ void combine_weights(const DevGeom &g, const double *r, double (&o)[4])
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= g.M * g.B)
-        return;
-    const int64_t i = t / g.B;
-    const int bm = (int)(t - i * g.B);
-    const int64_t u = perm[i];
-    double *o = w + t * 4;
-    if (u < 0 || u >= g.M) {
-        o[0] = o[1] = o[2] = o[3] = 0.0;
-        return;
-    }
-    const double *r = resid + ((int64_t)bm * g.M + u) * g.C;
     const double sg = g.G * g.h, sp = g.G * g.h * g.h;
     if (g.C == 1) {
         o[0] = o[1] = o[2] = 0.0;
@@ -64,6 +51,34 @@ k_t_weights(DevGeom g, const double *resid, const uint32_t *perm, double *w)
         o[2] = sg * r[2];
         o[3] = sg * r[3];
     }
+}
+
+// The weights of each sorted target (one thread per (sorted target,
+// model)), for the targets with descriptor index below `limit`: all of them,
+// or on lattice plans the user points only (the lattice kernels form the
+// cell centres' weights from the residuals themselves).
+__global__ void __launch_bounds__(256)
+k_t_weights(DevGeom g, const double *resid, const uint32_t *perm, int64_t limit, double *w)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.M * g.B)
+        return;
+    const int64_t i = t / g.B;
+    const int bm = (int)(t - i * g.B);
+    const int64_t u = perm[i];
+    if (u >= limit)
+        return;
+    double *o = w + t * 4;
+    if (u < 0 || u >= g.M) {
+        o[0] = o[1] = o[2] = o[3] = 0.0;
+        return;
+    }
+    double v[4];
+    combine_weights(g, resid + ((int64_t)bm * g.M + u) * g.C, v);
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = v[2];
+    o[3] = v[3];
 }
 
 // The matrix stages below give each thread up to MT density models (a
@@ -1041,13 +1056,13 @@ k_t_p2m_lds(DevGeom g, const double *A, int RBT, const double *me, double *drho,
 // GEMMs with columns = (leaf, model) and contraction over (centre t,
 // component) of the target leaf.  L2P^T: chunk q and k step u take t =
 // (lane/16) TQ + q and component u, so a lane's four k steps are the four
-// weights of one centre (one 32-byte load from the weights, found through
-// the centre's sorted slot).  near^T: only the C output components, value
-// e = C t + c in chunk q, sub-row kr and k step u with e = 4 KQ kr + 4 q +
-// u, read from the weight blocks.  Centres outside the mesh or past b^3 read
-// zero.
-__device__ __forceinline__ void lattice_weights(const DevGeom &g, const int32_t *cell_slot, const double *w, int tx,
-                                                int ty, int tz, int t, int bm, bool in, double (&v)[4])
+// weights of one centre.  near^T: only the C output components, value e =
+// C t + c in chunk q, sub-row kr and k step u with e = 4 KQ kr + 4 q + u,
+// read from the weight blocks.  A centre's weights come straight from its
+// residual (the centres follow the npts user points in descriptor order, x
+// fastest); centres outside the mesh or past b^3 read zero.
+__device__ __forceinline__ void lattice_weights(const DevGeom &g, const double *resid, int64_t npts, int tx, int ty,
+                                                int tz, int t, int bm, bool in, double (&v)[4])
 {
     const int b = g.b;
     v[0] = v[1] = v[2] = v[3] = 0.0;
@@ -1056,14 +1071,8 @@ __device__ __forceinline__ void lattice_weights(const DevGeom &g, const int32_t 
     const int ix = tx * b + t % b, iy = ty * b + (t / b) % b, iz = tz * b + t / (b * b);
     if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
         return;
-    const int64_t slot = cell_slot[((int64_t)iz * g.n[1] + iy) * g.n[0] + ix];
-    if (slot < 0 || slot >= g.M)
-        return;
-    const double4 x = *(const double4 *)(w + (slot * g.B + bm) * 4);
-    v[0] = x.x;
-    v[1] = x.y;
-    v[2] = x.z;
-    v[3] = x.w;
+    const int64_t cell = ((int64_t)iz * g.n[1] + iy) * g.n[0] + ix;
+    combine_weights(g, resid + ((int64_t)bm * g.M + npts + cell) * g.C, v);
 }
 
 // The weights of the cell centres in leaf blocks for near^T, as k_rho_blocks
@@ -1074,7 +1083,7 @@ __device__ __forceinline__ void lattice_weights(const DevGeom &g, const int32_t 
 // e >= C b^3 zero).  One thread per (leaf, model, centre).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_t_wblocks(DevGeom g, const int32_t *cell_slot, const double *w, int KQ, int64_t nplB, T *blk)
+k_t_wblocks(DevGeom g, const double *resid, int64_t npts, int KQ, int64_t nplB, T *blk)
 {
     const DevLev &lv = g.lev[g.L];
     const int b = g.b, b3 = b * b * b;
@@ -1088,7 +1097,7 @@ k_t_wblocks(DevGeom g, const int32_t *cell_slot, const double *w, int KQ, int64_
     const int lx = (int)(leaf % lv.ns[0]), ly = (int)((leaf / lv.ns[0]) % lv.ns[1]),
               lz = (int)(leaf / ((int64_t)lv.ns[0] * lv.ns[1]));
     double v[4];
-    lattice_weights(g, cell_slot, w, lx, ly, lz, t, bm, true, v);
+    lattice_weights(g, resid, npts, lx, ly, lz, t, bm, true, v);
     const int64_t pl = ((int64_t)(lz + 1) * (lv.ns[1] + 2) + (ly + 1)) * (lv.ns[0] + 2) + (lx + 1);
     for (int c = 0; c < g.C; ++c) {
         const int e = g.C * t + c, kr = e / (4 * KQ), q = (e / 4) % KQ;
@@ -1199,7 +1208,7 @@ k_t_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, int RBt, int KQ,
 // user points (written by k_t_l2p) is added to, every other one set.
 template <int RB>
 __global__ void __launch_bounds__(64)
-k_t_l2p_lat(DevGeom g, const double *A, int TQ, const int32_t *tmap, const int32_t *cell_slot, const double *w,
+k_t_l2p_lat(DevGeom g, const double *A, int TQ, const int32_t *tmap, const double *resid, int64_t npts,
             int add, const int64_t *leaf_start, const int64_t *pend, double *le)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
@@ -1221,7 +1230,7 @@ k_t_l2p_lat(DevGeom g, const double *A, int TQ, const int32_t *tmap, const int32
         acc[r] = vec4{0, 0, 0, 0};
     for (int q = 0; q < TQ; ++q) {
         double bv[4];
-        lattice_weights(g, cell_slot, w, sx, sy, sz, kr * TQ + q, bm, tl >= 0, bv);
+        lattice_weights(g, resid, npts, sx, sy, sz, kr * TQ + q, bm, tl >= 0, bv);
         double av[RB][4];
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -1326,13 +1335,13 @@ static grav_status launch_t_p2m(Plan *p, const DevGeom &g, double *drho, hipStre
     return GRAV_OK;
 }
 
-static grav_status launch_t_l2p_lat(Plan *p, const DevGeom &g, int add, hipStream_t s)
+static grav_status launch_t_l2p_lat(Plan *p, const DevGeom &g, const double *resid, int add, hipStream_t s)
 {
     const dim3 grid((unsigned)ceil_div(p->lev[p->L].n_src * p->B, 16));
 #define CASE(R)                                                                                             \
     case R:                                                                                                 \
         hipLaunchKernelGGL((k_t_l2p_lat<R>), grid, dim3(64), 0, s, g, (const double *)p->d_tl2pt, p->lat_TQ, \
-                           (const int32_t *)p->d_tmap, (const int32_t *)p->d_cell_slot, (const double *)p->d_near, \
+                           (const int32_t *)p->d_tmap, resid, p->d.n_points,                              \
                            add, (const int64_t *)p->d_leaf_start, (const int64_t *)p->d_leaf_pend, p->d_le); \
         break;
     switch (p->PS / 16) {
@@ -1345,7 +1354,8 @@ static grav_status launch_t_l2p_lat(Plan *p, const DevGeom &g, int add, hipStrea
     return GRAV_OK;
 }
 
-static grav_status launch_t_near_lat(Plan *p, const DevGeom &g, int add, double *drho, hipStream_t s)
+static grav_status launch_t_near_lat(Plan *p, const DevGeom &g, const double *resid, int add, double *drho,
+                                     hipStream_t s)
 {
     constexpr int CW = 2;
     const LevelInfo &lv = p->lev[p->L];
@@ -1357,14 +1367,14 @@ static grav_status launch_t_near_lat(Plan *p, const DevGeom &g, int add, double 
     const dim3 fgrid((unsigned)ceil_div(lv.n_src * p->B * b3, 256));
     const dim3 grid((unsigned)ceil_div(lv.n_src * p->B, 16 * CW), (unsigned)ceil_div(RBt, 4));
     if (f64) {
-        hipLaunchKernelGGL((k_t_wblocks<double>), fgrid, dim3(256), 0, s, g, (const int32_t *)p->d_cell_slot,
-                           (const double *)p->d_near, KQ, nplB, p->d_w_blk);
+        hipLaunchKernelGGL((k_t_wblocks<double>), fgrid, dim3(256), 0, s, g, resid, p->d.n_points, KQ, nplB,
+                           p->d_w_blk);
         hipLaunchKernelGGL((k_t_near_lat<CW, double>), grid, dim3(256), 0, s, g, (const double *)p->d_w_blk, nplB,
                            (const double *)p->d_tnt64, RBt, KQ, add, drho);
     } else {
         float *wb = reinterpret_cast<float *>(p->d_w_blk);
-        hipLaunchKernelGGL((k_t_wblocks<float>), fgrid, dim3(256), 0, s, g, (const int32_t *)p->d_cell_slot,
-                           (const double *)p->d_near, KQ, nplB, wb);
+        hipLaunchKernelGGL((k_t_wblocks<float>), fgrid, dim3(256), 0, s, g, resid, p->d.n_points, KQ, nplB,
+                           wb);
         hipLaunchKernelGGL((k_t_near_lat<CW, float>), grid, dim3(256), 0, s, g, (const float *)wb, nplB,
                            (const float *)p->d_tnt32, RBt, KQ, add, drho);
     }
@@ -1385,7 +1395,7 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
         return GRAV_EUNSUPPORTED;
     stage_begin(p, "weights", s);
     hipLaunchKernelGGL(k_t_weights, grid(p->M * p->B), blk, 0, s, g, resid, (const uint32_t *)p->d_perm,
-                       p->d_near);
+                       p->lat_near ? p->d.n_points : p->M, p->d_near);
     GRAV_HIP(hipGetLastError());
     stage_end(p, s);
     if (L >= 2) {
@@ -1414,7 +1424,7 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
             GRAV_HIP(hipGetLastError());
         }
         if (p->lat_near)
-            GRAV_CHECK(launch_t_l2p_lat(p, g, pts ? 1 : 0, s));
+            GRAV_CHECK(launch_t_l2p_lat(p, g, resid, pts ? 1 : 0, s));
         stage_end(p, s);
         stage_begin(p, "l2lT", s);
         for (int l = L - 1; l >= 2; --l)
@@ -1459,7 +1469,7 @@ static grav_status enqueue_adjoint_mt(Plan *p, const double *resid, double *drho
     // other plans) pair by pair
     if (p->lat_near) {
         stage_begin(p, "nearT", s);
-        GRAV_CHECK(launch_t_near_lat(p, g, L >= 2 ? 1 : 0, drho, s));
+        GRAV_CHECK(launch_t_near_lat(p, g, resid, L >= 2 ? 1 : 0, drho, s));
         stage_end(p, s);
     }
     const bool pts = p->lat_near ? p->d.n_points > 0 : (p->p2p_pairs > 0 || L < 2);
