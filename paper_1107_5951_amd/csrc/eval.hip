@@ -1014,9 +1014,13 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
     blk[((int64_t)(q * 4 + kr) * nplB + pl * g.B + bm) * 4 + u] = (T)r;
 }
 
-// Lattice near-field tile per workgroup: GRAV_NEAR_RW32 (FP32) or
-// GRAV_NEAR_RW64 (FP64) row blocks x GRAV_NEAR_CW column blocks of 16;
-// chunks per software-pipeline step.
+// Lattice near-field tile: GRAV_NEAR_RW32 (FP32) or GRAV_NEAR_RW64 (FP64)
+// row blocks x GRAV_NEAR_CW column blocks of 16, a tile per wave on plans
+// with at least GRAV_NEAR_WAVE_TILES tiles, else a tile per workgroup of
+// four waves; chunks per software-pipeline step.
+#ifndef GRAV_NEAR_WAVE_TILES
+#define GRAV_NEAR_WAVE_TILES 8192
+#endif
 #ifndef GRAV_NEAR_RW32
 #define GRAV_NEAR_RW32 4
 #endif
@@ -1044,31 +1048,39 @@ k_rho_blocks(DevGeom g, const double *rho, int Qn, int64_t nplB, T *blk)
 // leaf's local expansion (L2P at fixed points, FP64).
 // Over all leaves these are GEMMs with columns = (leaf, model).
 //
-// A workgroup owns a tile of 16 CW columns x 16 RW rows.  Its four waves
-// all hold the whole tile (CW x RW MFMA blocks, so every fragment loaded
-// feeds CW or RW instructions) and split the contraction: wave w takes a
-// quarter of the 27 Q near chunks (chunk = neighbour d, four k steps) and
-// every fourth chunk of the far field.  The four partial tiles meet in LDS
-// and are added in wave order (fixed, so the result is deterministic); wave
-// w then finishes blocks w, w + 4, ... of the tile and writes them straight
-// to the output in descriptor order, G applied.  Operand fragments are
-// group-major sets per (d, q, rb), the densities chunk-major (both read
-// with contiguous-kilobyte vector loads).
+// A tile is 16 CW columns x 16 RW rows (CW x RW MFMA blocks, so every
+// fragment loaded feeds CW or RW instructions).  NW = 1 (large plans): each
+// wave owns a tile, runs its 27 Q near chunks (chunk = neighbour d, four k
+// steps) and the far-field chunks, and writes the tile straight to the
+// output in descriptor order, G applied.  NW = 4: the four waves of a
+// workgroup share one tile and split the contraction (wave w a quarter of
+// the near chunks and every fourth far-field chunk); the four partial tiles
+// meet in LDS and are added in wave order (fixed, so the result is
+// deterministic).  Measured: 256^3 cells at leaf 4^3, 24,576 tiles: 1.82 ms
+// with NW = 1 against 1.96 with NW = 4 (the 64 KB reduction buffer held the
+// CU to two workgroups); 64^3 cells, 384 tiles: 0.094 ms against 0.053 (too
+// few waves to fill the chip).  Operand fragments are group-major sets per (d, q, rb), the
+// densities chunk-major (both read with contiguous-kilobyte vector loads).
 // --------------------------------------------------------------------------
-template <int RW, int CW, typename T>
+template <int RW, int CW, typename T, int NW>
 __global__ void __launch_bounds__(256)
 k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *ctab, int RBn, int Qn,
-           const double *Lm, const int32_t *tmap, const double *le, int64_t npts, int nrg, double *out)
+           const double *Lm, const int32_t *tmap, const double *le, int64_t npts, int nrg, int64_t ntile,
+           double *out)
 {
     using vec4 = __attribute__((__vector_size__(4 * sizeof(T)))) T;
     using dvec4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
-    __shared__ double red[4][CW * RW * 4][64];
     const int lane = threadIdx.x & 63;
     // wave-uniform (scalar registers): everything that depends only on the
     // chunk index below is scalar arithmetic
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t cg = blockIdx.x / nrg;
-    const int rb0 = (int)(blockIdx.x % nrg) * RW;
+    // NW = 4: the workgroup's four waves share one tile; NW = 1: each wave
+    // owns a tile of its own
+    const int64_t tile = NW == 4 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+    if (tile >= ntile)
+        return;  // NW = 1 only (no barrier there): the grid's last waves
+    const int64_t cg = tile / nrg;
+    const int rb0 = (int)(tile % nrg) * RW;
     const DevLev &lv = g.lev[g.L];
     const int64_t nleaf = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2];
     const int b = g.b, b2 = b * b, b3 = b2 * b;
@@ -1103,7 +1115,7 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *cta
     // near chunks [i0, i1) of this wave; the operands of the next chunk are
     // in flight while this chunk's instructions run
     const int NI = 27 * Qn;
-    const int i0 = wave * NI / 4, i1 = (wave + 1) * NI / 4;
+    const int i0 = NW == 4 ? wave * NI / 4 : 0, i1 = NW == 4 ? (wave + 1) * NI / 4 : NI;
     // per lane: its column's density block at neighbour offset (0, 0, 0)
     // (padded coordinates) and sub-row kr; a chunk adds a uniform offset
     const T *bbase[CW];
@@ -1192,7 +1204,7 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *cta
             bp[c] = (const double2 *)(le + (hl[c] ? ((lv.tgt_off + tl) * g.B + bm[c]) * g.PS : 0) + kr * (g.PS / 4));
         }
         const int QL = g.PS / 16;
-        for (int q = wave; q < QL; q += 4) {
+        for (int q = NW == 4 ? wave : 0; q < QL; q += NW) {
             double bv[CW][4];
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
@@ -1223,25 +1235,14 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *cta
                         far[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][u], bv[c][u], far[c][r], 0, 0, 0);
         }
     }
-    // partial tiles to LDS (FP64), then each wave adds the four partials of
-    // its blocks in wave order
-#pragma unroll
-    for (int c = 0; c < CW; ++c)
-#pragma unroll
-        for (int r = 0; r < RW; ++r)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                red[wave][(c * RW + r) * 4 + k][lane] = (double)acc[c][r][k] + far[c][r][k];
-    __syncthreads();
     // row block R holds targets 16 (R % RBc) + row of output component
     // R / RBc (the row order of both operators, in lattice units); the
     // lane's element k is row 4 kr + k (FP32) or kr + 4 k (FP64)
     const double sg = g.G * g.h, sp = g.G * g.h * g.h;
     const int RBc = (b3 + 15) / 16;
-    for (int j = wave; j < CW * RW; j += 4) {
-        const int c = j / RW, r = j % RW;
+    auto store = [&](int c, int r, auto &&value) {
         if (!cvalid[c] || !rvalid[r])
-            continue;
+            return;
         const int comp = (rb0 + r) / RBc, tb = 16 * ((rb0 + r) % RBc);
         const double sc = g.C == 4 && comp == 0 ? sp : sg;
         double *o = out + ((int64_t)bm[c] * g.M + npts) * g.C + comp;
@@ -1251,10 +1252,32 @@ k_near_lat(DevGeom g, const T *blk, int64_t nplB, const T *A, const int64_t *cta
             const int ix = lx[c] * b + t % b, iy = ly[c] * b + (t / b) % b, iz = lz[c] * b + t / b2;
             if (t >= b3 || ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2])
                 continue;
-            const double v = ((red[0][j * 4 + k][lane] + red[1][j * 4 + k][lane]) + red[2][j * 4 + k][lane]) +
-                             red[3][j * 4 + k][lane];
-            o[(((int64_t)iz * g.n[1] + iy) * g.n[0] + ix) * g.C] = sc * v;
+            o[(((int64_t)iz * g.n[1] + iy) * g.n[0] + ix) * g.C] = sc * value(k);
         }
+    };
+    if constexpr (NW == 4) {
+        // partial tiles to LDS (FP64), then each wave adds the four partials
+        // of its blocks in wave order (fixed, so the result is deterministic)
+        __shared__ double red[4][CW * RW * 4][64];
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    red[wave][(c * RW + r) * 4 + k][lane] = (double)acc[c][r][k] + far[c][r][k];
+        __syncthreads();
+        for (int j = wave; j < CW * RW; j += 4)
+            store(j / RW, j % RW, [&](int k) {
+                return ((red[0][j * 4 + k][lane] + red[1][j * 4 + k][lane]) + red[2][j * 4 + k][lane]) +
+                       red[3][j * 4 + k][lane];
+            });
+    } else {
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+                store(c, r, [&](int k) { return (double)acc[c][r][k] + far[c][r][k]; });
     }
 }
 
@@ -1552,16 +1575,30 @@ static grav_status launch_near_lat(Plan *p, const DevGeom &g, const double *rho,
     const int64_t ncg = (ncol + 16 * CW - 1) / (16 * CW);
     if (ncg * nrg > 0x7fffffffll)
         return GRAV_EUNSUPPORTED;
-    dim3 grid((unsigned)(ncg * nrg)), blk(256);
+    const int64_t ntile = ncg * nrg;
+    // a tile per wave once there are tiles for every wave slot of the chip,
+    // else four waves per tile (small plans: 64^3 cells at leaf 4^3 with two
+    // Gauss points have 384 tiles)
+    const bool per_wave = ntile >= GRAV_NEAR_WAVE_TILES;
+    dim3 grid((unsigned)(per_wave ? (ntile + 3) / 4 : ntile)), blk(256);
     const int64_t npts = p->d.n_points;
-    if (f64)
-        hipLaunchKernelGGL((k_near_lat<GRAV_NEAR_RW64, CW, double>), grid, blk, 0, s, g, (const double *)p->d_rho_blk, nplB,
-                           (const double *)p->d_tn64, (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,
-                           (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
-    else
-        hipLaunchKernelGGL((k_near_lat<GRAV_NEAR_RW32, CW, float>), grid, blk, 0, s, g, (const float *)p->d_rho_blk, nplB,
-                           (const float *)p->d_tn32, (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,
-                           (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, out);
+#define NEAR_LAUNCH(NW)                                                                                            \
+    if (f64)                                                                                                       \
+        hipLaunchKernelGGL((k_near_lat<GRAV_NEAR_RW64, CW, double, NW>), grid, blk, 0, s, g,                       \
+                           (const double *)p->d_rho_blk, nplB, (const double *)p->d_tn64,                          \
+                           (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,                      \
+                           (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, ntile, out);            \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_near_lat<GRAV_NEAR_RW32, CW, float, NW>), grid, blk, 0, s, g,                        \
+                           (const float *)p->d_rho_blk, nplB, (const float *)p->d_tn32,                            \
+                           (const int64_t *)p->d_lat_tab, RBn, Qn, (const double *)p->d_tl2p,                      \
+                           (const int32_t *)p->d_tmap, (const double *)p->d_le, npts, nrg, ntile, out);
+    if (per_wave) {
+        NEAR_LAUNCH(1)
+    } else {
+        NEAR_LAUNCH(4)
+    }
+#undef NEAR_LAUNCH
     GRAV_HIP(hipGetLastError());
     return GRAV_OK;
 }

@@ -222,6 +222,9 @@ def test_tree_leaf_count_matches_host_count():
     ((27, 21, 24), 1, 27, 1, 1, 1),    # b = 3, mixed precision, gz only
     ((40, 32, 24), 2, 64, 1, 1, 3),    # b = 2, two-point rule, mixed precision
     ((12, 12, 12), 1, 1, 0, 1, 4),     # b = 1
+    # at least 8192 tiles: a tile per wave instead of per workgroup
+    ((64, 64, 64), 1, 64, 1, 32, 3),   # 32 models, mixed: 12,288 tiles
+    ((64, 64, 64), 1, 64, 0, 32, 4),   # 32 models, FP64: 8192 tiles
 ])
 def test_lattice_near_field_matches_direct_sum(n, q, leaf, prec, B, comps):
     """Voxel-centre targets take the near field from the lattice matrices
