@@ -94,6 +94,20 @@ def test_transpose_dot_product_batched_and_mixed():
     assert gap <= 1e-5
 
 
+def test_transpose_dot_product_large_lattice():
+    """128^3 cells x 8 models with cell-centre targets: 8192 tiles of the
+    lattice near field, the size from which the forward gives each wave a
+    tile of its own."""
+    grid = W.Grid.unit(128)
+    rho = np.stack([W.gaussian_blobs(grid, 4, 2100 + b) for b in range(8)])
+    for prec, bar in ((G.GRAV_FP64, 1e-12), (G.GRAV_MIXED, 1e-5)):
+        spec = G.PlanSpec(n=(128, 128, 128), h=grid.h, voxel_centres=True, components=3, p=8, leaf_size=64,
+                          batch=8, precision=prec)
+        gap, _ = _dot_gap(spec, rho)
+        _say("adjoint dot product, 128^3 x 8 lattice, prec=%d: %.3e" % (prec, gap))
+        assert gap <= bar
+
+
 def test_transpose_matches_oracle_transpose():
     rng = np.random.default_rng(2)
     grid = W.Grid.unit(16)
