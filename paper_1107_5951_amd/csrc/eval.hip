@@ -633,8 +633,9 @@ k_m2l_sum(const T *part, const int32_t *colmap, const int32_t *tseg_start, const
     double acc = 0.0;
     // SB slots at a time: their indices, then their values, are loaded
     // together (no chain of dependent loads); the sum stays in slot order.
-    // A unit typically spans fewer than SB shares, so one round usually does.
-    constexpr int SB = 16;
+    // A unit typically spans one or two workers' shares (the 256^3 plan:
+    // about 400 items per worker, 189 per unit), so one round usually does.
+    constexpr int SB = 4;
     for (int jb = j0; jb < j1; jb += SB) {
         int32_t sl[SB];
 #pragma unroll
