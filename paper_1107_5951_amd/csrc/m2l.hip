@@ -22,6 +22,11 @@
 #ifndef GRAV_M2L_DB_BYTES64
 #define GRAV_M2L_DB_BYTES64 512
 #endif
+// One register set: raise the wave's priority while it runs a chunk's
+// matrix instructions (256^3 at p = 10: 9.45 -> 9.26 ms).
+#ifndef GRAV_M2L_PRIO
+#define GRAV_M2L_PRIO 1
+#endif
 
 
 namespace grav {
@@ -311,7 +316,17 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
                 for (int q = 0; q < QC; ++q) {
                     load(A, q, 0);
                     __builtin_amdgcn_sched_barrier(0);
+#if GRAV_M2L_PRIO
+                    // a wave that has its operands keeps the matrix unit for
+                    // its whole chunk (the waves of a SIMD alternate instead
+                    // of interleaving and then waiting for loads together)
+                    __builtin_amdgcn_s_setprio(1);
+#endif
                     compute(A, q, 0);
+#if GRAV_M2L_PRIO
+                    __builtin_amdgcn_sched_barrier(0);
+                    __builtin_amdgcn_s_setprio(0);
+#endif
                 }
             }
         }
