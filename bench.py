@@ -67,6 +67,8 @@ def parse():
                     help="only time the FMM on the paper's model over its mesh sequence (Mbar = 12 .. 384)")
     ap.add_argument("--crossover", action="store_true",
                     help="only time FMM vs GPU direct sum over station counts (summation/FMM crossover)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 128^3 x 32-model batched forward and adjoint rows (for kernel profiles)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -635,6 +637,10 @@ def main():
         return
     if args.paper_sequence:
         paper_sequence(args)
+        return
+    if args.batched_only:
+        say("batched 128^3 workload")
+        print(json.dumps({"batched128_b32": batched128(args)}), flush=True)
         return
 
     res = headline(args)
