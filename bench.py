@@ -165,12 +165,36 @@ def pct(xs, q):
     return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
 
 
+# mixed plans at these orders run the M2L once per reflection orbit of
+# offsets (k_m2l_orb): the eight sign classes of the coefficients hold at
+# most 16 each up to p = 10, and below p = 10 the per-offset kernel is as
+# fast or faster
+M2L_ORBIT_ORDERS = (10,)
+
+
+def m2l_orbit(p, prec):
+    from paper_1107_5951_amd import GRAV_FP64
+    return prec != GRAV_FP64 and p in M2L_ORBIT_ORDERS
+
+
 def m2l_kernel_name(p, prec):
     from paper_1107_5951_amd import GRAV_FP64
     p2 = p * p
     if prec == GRAV_FP64:
         return "k_m2l<%d,%d,*,double,*>" % (-(-p2 // 16), -(-p2 // 4))
+    if m2l_orbit(p, prec):
+        return "k_m2l_orb<*>"
     return "k_m2l<%d,%d,*,float,*>" % (-(-p2 // 16), -(-p2 // 4))
+
+
+def m2l_label(p, prec):
+    from paper_1107_5951_amd import GRAV_FP64
+    f64 = prec == GRAV_FP64
+    if m2l_orbit(p, prec):
+        return m2l_kernel_name(p, prec) + (" (M2L per reflection orbit of offsets, FP32 MFMA 16x16x4; work"
+                                           " counted as the per-offset product, 2 p^4 per box pair)")
+    return m2l_kernel_name(p, prec) + " (M2L, %s MFMA 16x16x4%s)" % (
+        "FP64" if f64 else "FP32", "" if f64 or not 0 < p * p % 16 <= 4 else ", the last row block 4x4x1")
 
 
 def roofline(plan, stages, p, prec, profile):
@@ -198,9 +222,7 @@ def roofline(plan, stages, p, prec, profile):
     mm = "fp64_mfma" if f64 else "fp32_mfma"
     ps = -(-p * p // 16) * 16
     cand = {
-        "m2l": (2.0 * p ** 4 * m2l_pairs * B, m2l_kernel_name(p, prec) + " (M2L, %s MFMA 16x16x4%s)"
-                % ("FP64" if f64 else "FP32", "" if f64 or not 0 < p * p % 16 <= 4 else
-                   ", the last row block 4x4x1"), "mfma", mm, "TFLOP/s"),
+        "m2l": (2.0 * p ** 4 * m2l_pairs * B, m2l_label(p, prec), "mfma", mm, "TFLOP/s"),
         "near_lat": (27 * 2.0 * (plan.spec.components * b ** 3) * b ** 3 * n_leaf_src * B,
                      "k_near_lat<%d,2,%s> (lattice near field, %s MFMA 16x16x4)"
                      % ((2, "double", "FP64") if f64 else (4, "float", "FP32")), "mfma", mm, "TFLOP/s"),

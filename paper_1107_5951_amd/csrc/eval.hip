@@ -554,7 +554,9 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
 // M2L's element type.  Per level, boxes are ordered by parity class (x
 // fastest within a class, see class_split) and the coefficients chunk-major
 // in the M2L's interleaved contraction order:
-//   out[level][q][kr][pos * B + model][u],  coefficient 4 (4 q + u) + kr.
+//   out[level][q][kr][pos * B + model][u],  coefficient kmap[4 (4 q + kr) + u]
+// (-1: zero), NP = 4 q + kr planes: in natural order coefficient 4 (4 q + u)
+// + kr; for the reflection-orbit M2L position 4 u + kr of sign class q.
 // The source boxes that one wave's 16 columns read at one interaction offset
 // are boxes of a single class with consecutive x, so each B fragment load
 // of the M2L covers a few contiguous runs instead of 64 scattered lines.
@@ -563,9 +565,15 @@ k_l2l_mfma(DevGeom g, const GemmTile *tiles, int stride, const uint32_t *tkey, c
 // only sources within its interaction offsets.  One thread per (box, model,
 // chunk q, sub-row kr).
 template <typename T>
-__global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, int64_t n_me, T *out)
+__global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, int64_t n_me, const int32_t *kmap,
+                                                   int NP, T *out)
 {
-    const int NP = g.PS / 4;  // (q, kr) planes
+    // the coefficient map (at most PS <= 256 entries) through LDS: its
+    // loads would otherwise sit in a dependent chain before the gathers
+    __shared__ int32_t km[256];
+    for (int e = threadIdx.x; e < 4 * NP; e += blockDim.x)
+        km[e] = kmap[e];
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_me * g.B * NP)
         return;
@@ -588,15 +596,24 @@ __global__ void __launch_bounds__(256) k_me_gather(DevGeom g, const double *me, 
                         ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
                         ((ax - first[0]) >> 1);
     const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
-    const int q = plane / 4, kr = plane % 4;
-    const double *src = me + col * g.PS + 16 * q + kr;
-    T *dst = out + lv.me_off * g.B * g.PS + ((int64_t)plane * nB + pos * g.B + bm) * 4;
+    const double *src = me + col * g.PS;
+    T *dst = out + lv.me_off * g.B * (4 * NP) + ((int64_t)plane * nB + pos * g.B + bm) * 4;
+    T v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        dst[u] = (T)src[4 * u];
+    for (int u = 0; u < 4; ++u) {
+        const int k = km[4 * plane + u];
+        v[u] = k >= 0 ? (T)src[k] : (T)0;
+    }
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            dst[u] = v[u];
+    }
 }
-template __global__ void k_me_gather<double>(DevGeom, const double *, int64_t, double *);
-template __global__ void k_me_gather<float>(DevGeom, const double *, int64_t, float *);
+template __global__ void k_me_gather<double>(DevGeom, const double *, int64_t, const int32_t *, int, double *);
+template __global__ void k_me_gather<float>(DevGeom, const double *, int64_t, const int32_t *, int, float *);
 
 // out[i] = sum over s < S of part[s * n + i], in order s = 0, 1, ..., in FP64
 template <typename T>
@@ -1427,6 +1444,11 @@ static M2LRun<T> forward_m2l(const Plan *p, const T *K)
     r.wgs = p->m2l_wgs;
     r.nset = p->m2l_nset;
     r.nc = p->m2l_nc;
+    if (sizeof(T) == 4 && p->m2l_orbit) {
+        r.K = reinterpret_cast<const T *>(p->d_k32o);
+        r.orbtab = (const int32_t *)p->d_orbtab;
+        r.ccoef = (const int32_t *)p->d_ccoef;
+    }
     return r;
 }
 
@@ -1635,14 +1657,15 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
         stage_end(p, s);
         stage_begin(p, "me_gather", s);
         {
-            const int64_t n = p->n_me * p->B * (p->PS / 4);
+            const int64_t n = p->n_me * p->B * p->m2l_npl;
             const dim3 gg((unsigned)((n + 255) / 256));
+            const int32_t *kmap = (const int32_t *)p->d_kmap;
             if (p->d.precision == GRAV_FP64)
                 hipLaunchKernelGGL((k_me_gather<double>), gg, dim3(256), 0, s, g, (const double *)p->d_me, p->n_me,
-                                   p->d_meg);
+                                   kmap, p->m2l_npl, p->d_meg);
             else
                 hipLaunchKernelGGL((k_me_gather<float>), gg, dim3(256), 0, s, g, (const double *)p->d_me, p->n_me,
-                                   reinterpret_cast<float *>(p->d_meg));
+                                   kmap, p->m2l_npl, reinterpret_cast<float *>(p->d_meg));
             GRAV_HIP(hipGetLastError());
         }
         stage_end(p, s);

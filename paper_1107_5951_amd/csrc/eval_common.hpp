@@ -73,10 +73,14 @@ struct M2LRun {
     int32_t wgs;               // workgroups (0: nothing to do)
     int nset;                  // operand register sets of the FP32 kernel
     int nc;                    // 16-column blocks per wave (FP32: 2 or 4; FP64: 1)
+    // the reflection-orbit M2L (forward, mixed plans): items are canonical
+    // offsets, K the class-blocked canonical operators, orbtab the class
+    // offset of each reflection, ccoef the coefficient of each class row
+    const int32_t *orbtab = nullptr, *ccoef = nullptr;
 };
 template <typename T>
 grav_status launch_m2l(const Plan *p, const DevGeom &g, hipStream_t s, const M2LRun<T> &r);
-grav_status m2l_resident_workers(const Plan *p, int nset, int nc, int *workers);
+grav_status m2l_resident_workers(const Plan *p, int nset, int nc, bool orbit, int *workers);
 grav_status begin_call(Plan *p, hipStream_t s);
 grav_status end_call(Plan *p, hipStream_t s);
 

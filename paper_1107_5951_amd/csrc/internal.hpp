@@ -43,6 +43,27 @@ constexpr int kMaxLevels = 10;
 #ifndef GRAV_M2L_NC64
 #define GRAV_M2L_NC64 1
 #endif
+// 16-column blocks per wave of the reflection-orbit M2L
+#ifndef GRAV_M2L_ORB_NC
+#define GRAV_M2L_ORB_NC 2
+#endif
+// Lowest expansion order that takes the reflection-orbit M2L: it runs 8 x 8
+// blocks of 16 x 16 per orbit whatever p is, so at lower orders much of each
+// block is padding (256^3 volume, M2L per offset and per orbit: p = 8 4.05
+// and 6.79 ms, p = 9 6.77 and 6.83 ms, p = 10 9.31 and 6.82 ms)
+#ifndef GRAV_M2L_ORB_MIN_P
+#define GRAV_M2L_ORB_MIN_P 10
+#endif
+// Forward M2L schedule locality: interleave the eight classes' tiles of a
+// level (they read the same source expansions), and give each XCD a
+// contiguous range of stream-K workers (workgroups go to the eight XCDs in
+// turn; each XCD has its own L2)
+#ifndef GRAV_M2L_INTERLEAVE
+#define GRAV_M2L_INTERLEAVE 0
+#endif
+#ifndef GRAV_M2L_XCD_REMAP
+#define GRAV_M2L_XCD_REMAP 0
+#endif
 constexpr int kNumOffsets = 316;   // M2L offsets d with 2 <= |d|_inf <= 3
 // The mixed-precision (FP32) forward M2L stores one operator per offset with
 // non-negative components (56 of them): the operator of any other offset is
@@ -149,6 +170,15 @@ struct Plan {
     int32_t m2l_nset = 2;               // operand register sets of the FP32 M2L kernel (1 or 2)
     int32_t m2l_nc = 1;                 // 16-column blocks per wave of the M2L kernel
     int64_t m2l_nseg = 0, m2l_items = 0, m2l_nunit = 0;
+    // reflection-orbit M2L (mixed plans with at most 16 coefficients per
+    // sign class, p <= 10): work items are (unit, canonical offset) pairs
+    bool m2l_orbit = false;
+    int32_t m2l_npl = 0;                // (chunk, sub-row) planes of the regathered ME
+    int64_t m2l_orb_pairs = 0;          // (target box, orbit with a source box) pairs x models
+    float *d_k32o = nullptr;            // [56][8 classes][8 classes][64][4] class-blocked canonical operators
+    int32_t *d_orbtab = nullptr;        // [8 classes][56][8 reflections] class offset index or -1
+    int32_t *d_ccoef = nullptr;         // [8][16] natural coefficient of (class, position) or -1
+    int32_t *d_kmap = nullptr;          // [planes][4] natural coefficient of a regathered value or -1
     int32_t *d_m2l_items = nullptr, *d_m2l_segs = nullptr, *d_m2l_wgseg = nullptr;
     int32_t *d_m2l_tseg_start = nullptr, *d_m2l_tsegs = nullptr, *d_m2l_colmap = nullptr;
     // the transposed M2L's schedule, in the same form (columns: source boxes

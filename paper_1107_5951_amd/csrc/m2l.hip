@@ -365,11 +365,216 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
     }
 }
 
+// --------------------------------------------------------------------------
+// Reflection-orbit M2L (mixed plans whose eight sign classes hold at most 16
+// coefficients each, p <= 10).  With S_r the diagonal sign matrix of
+// reflection r, the offsets r(|d|) of one orbit share the canonical operator
+// K = K_|d|: K_r(|d|) = S_r K S_r.  Entry (i, j) of S_r K S_r is K[i][j]
+// times chi_{a^b}(r) = (-1)^popcount(r & (a ^ b)), a and b the sign classes
+// of coefficients i and j.  Grouping rows and columns by class, the orbit's
+// contribution to the rows of class a is
+//   sum_b K[a, b] H_{a^b},   H_w = sum_r chi_w(r) ME_r[b],
+// ME_r the expansion of the source box at offset r(|d|) (zero where there
+// is none).  H is the Walsh-Hadamard transform of the eight ME_r (three
+// butterfly stages over the reflection bits), so an orbit costs one
+// operator's matrix instructions (8 x 8 blocks of 16 x 16, 256 16x16x4
+// instructions per column block) instead of one per offset (up to eight).
+// A work item is a (unit, canonical offset) pair; chunk q of an item is
+// column class q: its A fragments are the 8 row blocks of K[:, q] and its B
+// values the four k steps of class q from each of the eight source boxes.
+// The regathered expansions hold class q's coefficients in planes 4 q .. 4
+// q + 3 (value u of plane (q, kr): position 4 u + kr of the class).  Output
+// row 4 kr + r of row block a is coefficient ccoef[a][4 kr + r] (-1: none;
+// the slot's unused entries stay zero from the plan's clearing).
+// --------------------------------------------------------------------------
+// Stream-K worker of workgroup b out of P: with GRAV_M2L_XCD_REMAP the
+// workgroups that the hardware places on XCD x (b = x, x + 8, ...) take the
+// contiguous workers [x P / 8, (x + 1) P / 8) (a bijection for any P)
+__device__ __forceinline__ int m2l_worker(int b, int P)
+{
+#if GRAV_M2L_XCD_REMAP
+    const int q = P / 8, r = P % 8, x = b % 8, i = b / 8;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+#else
+    (void)P;
+    return b;
+#endif
+}
+
+#ifndef GRAV_M2L_ORB_WAVES
+#define GRAV_M2L_ORB_WAVES 2
+#endif
+template <int NC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GRAV_M2L_ORB_WAVES, 8)))
+k_m2l_orb(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *torder,
+          const int32_t *class_off, const int32_t *orbtab, const float *K, const float *me,
+          const int32_t *segs, const int32_t *wgseg, const int32_t *items, const int32_t *ccoef, float *part)
+{
+    using vec4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+    const int lane = threadIdx.x;  // one wave per workgroup
+    constexpr int UPT = 4 / NC;
+    const int kr = lane >> 4;
+    const int PS = g.PS;
+    const int w = m2l_worker(blockIdx.x, gridDim.x);
+    for (int sg = wgseg[w]; sg < wgseg[w + 1]; ++sg) {
+        const int32_t *sd = segs + 4 * sg;  // unit, first item, end item
+        const GemmTile tile = tiles[sd[0] / UPT];
+        const int hq = sd[0] % UPT;
+        const DevLev &lv = g.lev[tile.level];
+        bool cvalid[NC];
+        int bm[NC], bx[NC], by[NC], bz[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int cl = (hq * NC + c) * 16 + (lane & 15);
+            cvalid[c] = cl < tile.ncol;
+            const int64_t col = tile.col0 + cl;
+            bm[c] = (int)(col % g.B);
+            bx[c] = by[c] = bz[c] = 0;
+            if (cvalid[c]) {
+                const int32_t box = torder[lv.tbox_off + lv.class_start[tile.cls] + col / g.B];
+                const uint32_t key = tkey[lv.tbox_off + box];
+                bx[c] = (int)compact3(key);
+                by[c] = (int)compact3(key >> 1);
+                bz[c] = (int)compact3(key >> 2);
+            }
+        }
+        vec4 acc[NC][8];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                acc[c][a] = vec4{0, 0, 0, 0};
+        const int32_t *offs = class_off + tile.cls * kClassOffsets * 4;
+        const int32_t *otab = orbtab + tile.cls * kCanonOffsets * 8;
+        const int64_t nB = (int64_t)lv.ns[0] * lv.ns[1] * lv.ns[2] * g.B;
+        const int64_t pstr = nB * 4;
+        // chunk q's planes start at mlev + 4 q pstr (wave-uniform); a lane's
+        // byte offsets from there hold its sub-row kr (below 2^32: the plan
+        // takes this kernel only for smaller regathered buffers)
+        const char *mlev = reinterpret_cast<const char *>(me + lv.me_off * g.B * 128);
+        const uint32_t krb = (uint32_t)(kr * pstr * 4);
+        for (int it = sd[1]; it < sd[2]; ++it) {
+            const int ci = items[it];
+            // per reflection r: whether the class has that offset, and per
+            // column the byte offset of its source box's expansion and a
+            // have bit (the offsets of an orbit share their parity, hence the
+            // source class)
+            uint32_t present = 0, hm = 0;
+            uint32_t off[8][NC];
+            int first[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+            int64_t cstart = 0;
+            bool split = false;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int o = otab[ci * 8 + r];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    off[r][c] = krb;
+                if (o < 0)
+                    continue;
+                present |= 1u << r;
+                const int dx = offs[4 * o + 0], dy = offs[4 * o + 1], dz = offs[4 * o + 2];
+                if (!split) {
+                    cstart = class_split(lv, tile.cls ^ ((dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2)), first, cnt);
+                    split = true;
+                }
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const int ax = bx[c] + dx, ay = by[c] + dy, az = bz[c] + dz;
+                    const int sx = ax - lv.s0[0], sy = ay - lv.s0[1], sz = az - lv.s0[2];
+                    const bool have = cvalid[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < lv.ns[0] &&
+                                      sy < lv.ns[1] && sz < lv.ns[2];
+                    const int64_t pos = cstart +
+                                        ((int64_t)((az - first[2]) >> 1) * cnt[1] + ((ay - first[1]) >> 1)) * cnt[0] +
+                                        ((ax - first[0]) >> 1);
+                    if (have) {
+                        off[r][c] = krb + (uint32_t)((pos * g.B + bm[c]) * 16);
+                        hm |= 1u << (r * NC + c);
+                    }
+                }
+            }
+            const float *kp = K + (int64_t)ci * (8 * 8 * 256);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                float av[32];
+                vec4 h[NC][8];
+                load_frags<float, 32>(kp + q * (8 * 256), lane, av);
+                const char *mq = mlev + (int64_t)q * 16 * pstr;
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        h[c][r] = vec4{0, 0, 0, 0};
+                        if (present & (1u << r)) {
+                            const vec4 v = *(const vec4 *)(mq + off[r][c]);
+                            if ((hm >> (r * NC + c)) & 1u)
+                                h[c][r] = v;
+                        }
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#if GRAV_M2L_PRIO
+                __builtin_amdgcn_s_setprio(1);
+#endif
+                // Walsh-Hadamard transform over the reflection bits x, y, z
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+                        for (int r = 0; r < 8; ++r)
+                            if ((r & bit) == 0) {
+                                const vec4 x = h[c][r], y = h[c][r | bit];
+                                h[c][r] = x + y;
+                                h[c][r | bit] = x - y;
+                            }
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            acc[c][a] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[4 * a + u], h[c][a ^ q][u],
+                                                                             acc[c][a], 0, 0, 0);
+#if GRAV_M2L_PRIO
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(0);
+#endif
+            }
+        }
+        // lane: column lane % 16, rows 4 kr + r of each row block (class)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (!cvalid[c])
+                continue;
+            float *dst = part + ((int64_t)sg * (16 * NC) + c * 16 + (lane & 15)) * PS;
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = ccoef[16 * a + 4 * kr + r];
+                    if (k >= 0)
+                        dst[k] = acc[c][a][r];
+                }
+        }
+    }
+}
+
 template <typename T>
 grav_status launch_m2l(const Plan *p, const DevGeom &g, hipStream_t s, const M2LRun<T> &r)
 {
     if (r.wgs == 0)
         return GRAV_OK;
+    if constexpr (sizeof(T) == 4) {
+        if (r.orbtab != nullptr) {
+            if (r.nc != GRAV_M2L_ORB_NC)
+                return GRAV_EUNSUPPORTED;
+            hipLaunchKernelGGL((k_m2l_orb<GRAV_M2L_ORB_NC>), dim3(r.wgs), dim3(64), 0, s, g, r.tiles, r.keys,
+                               r.order, r.class_off, r.orbtab, r.K, r.b_in, r.segs, r.wgseg, r.items, r.ccoef,
+                               r.part);
+            GRAV_HIP(hipGetLastError());
+            return GRAV_OK;
+        }
+    }
     // column blocks per wave: FP64 one; FP32 the plan's (narrow or wide)
     constexpr int NCN = sizeof(T) == 8 ? GRAV_M2L_NC64 : GRAV_M2L_NC32;
     constexpr int NCW = sizeof(T) == 8 ? GRAV_M2L_NC64_WIDE : GRAV_M2L_NC32_WIDE;
@@ -423,11 +628,14 @@ template grav_status launch_m2l<float>(const Plan *, const DevGeom &, hipStream_
 // sets in FP32) that the device holds at once (blocks per CU from the
 // occupancy calculator, times the CUs): the size of the stream-K schedule,
 // so that every worker is resident from the start.
-grav_status m2l_resident_workers(const Plan *p, int nset, int nc, int *workers)
+grav_status m2l_resident_workers(const Plan *p, int nset, int nc, bool orbit, int *workers)
 {
     const bool f64 = p->d.precision == GRAV_FP64;
     const bool wide = nc == (f64 ? GRAV_M2L_NC64_WIDE : GRAV_M2L_NC32_WIDE);
     const void *fn = nullptr;
+    if (orbit)
+        fn = reinterpret_cast<const void *>(&k_m2l_orb<GRAV_M2L_ORB_NC>);
+    else
 #define M2L_FN(P)                                                                                           \
     case P:                                                                                                 \
         fn = f64 ? (wide ? reinterpret_cast<const void *>(&k_m2l<(P * P + 15) / 16, (P * P + 3) / 4, GRAV_M2L_NC64_WIDE, double, 2>) \

@@ -318,7 +318,8 @@ void free_plan(Plan *p)
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
                     p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
                     p->d_m2mt_sw, p->d_l2lt_sw, p->d_l2l_msw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk,
-                    p->d_spos, p->d_sw, p->d_sperm, p->d_sstart, p->d_pt_leaves, p->d_user_leaves};
+                    p->d_spos, p->d_sw, p->d_sperm, p->d_sstart, p->d_pt_leaves, p->d_user_leaves,
+                    p->d_k32o, p->d_orbtab, p->d_ccoef, p->d_kmap};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -386,6 +387,22 @@ grav_status validate(const grav_plan_desc *d)
 
 // Index of the operator of offset |d| (components 0..3, largest >= 2) among
 // the 56 stored for the mixed-precision forward M2L, z slowest, x fastest.
+// Sign class of real coefficient c under the z, y and x reflections (bits
+// 2, 1, 0; the bits of the reflection index of an offset): degree n block of
+// 2n+1 values, the real part of order 0, then real and imaginary parts of
+// orders 1..n; z -> -z gives (-1)^(n+m), y -> -y -1 on imaginary parts, x ->
+// -x (-1)^m on real and -(-1)^m on imaginary parts.
+static int sign_class(int c)
+{
+    int n = 0;
+    while ((n + 1) * (n + 1) <= c)
+        ++n;
+    const int i = c - n * n;
+    const int m = (i + 1) / 2;
+    const int im = (i > 0 && (i & 1) == 0) ? 1 : 0;
+    return (((n + m) & 1) << 2) | (im << 1) | ((m + im) & 1);
+}
+
 int canon_index(int ax, int ay, int az)
 {
     int k = 0;
@@ -623,6 +640,30 @@ grav_status build_operators(Plan *p)
     // run it as 4x4 instructions: its A fragment repeats those rows
     const bool tail4 = p->d.precision != GRAV_FP64 && p->P2 % 16 != 0 && p->P2 % 16 <= 4;
     std::vector<double> k(perp * (canonical ? kCanonOffsets : kNumOffsets)), kt(k.size()), mt((size_t)PS * PS);
+    // Reflection-orbit M2L (mixed plans whose sign classes hold at most 16
+    // coefficients each): the coefficients of each class in natural order,
+    // and the 56 canonical operators with rows and columns grouped by class
+    // (class rb's rows, class q's columns: 16 x 16 blocks, one per (q, rb)),
+    // as A fragments [ci][q][rb][lane][u] = K[row rb, lane%16][col q, 4 u +
+    // lane/16]
+    std::vector<int32_t> ccoef(8 * 16, -1);
+    {
+        int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        // (the kernel addresses a level's regathered expansions with 32-bit
+        // byte offsets)
+        bool fits = canonical && p->L >= 2 && p->P >= GRAV_M2L_ORB_MIN_P &&
+                    (int64_t)p->n_me * p->B * 128 * 4 < (int64_t(1) << 32);
+        for (int c = 0; c < p->P2; ++c) {
+            const int s = sign_class(c);
+            if (cnt[s] >= 16)
+                fits = false;
+            else
+                ccoef[s * 16 + cnt[s]] = c;
+            ++cnt[s];
+        }
+        p->m2l_orbit = fits;
+    }
+    std::vector<double> ko(p->m2l_orbit ? (size_t)kCanonOffsets * 8 * 8 * 256 : 0, 0.0);
     for (int id = 0; id < kNumOffsets; ++id) {
         // source = target + d  =>  target centre - source centre = -d
         const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
@@ -637,7 +678,40 @@ grav_status build_operators(Plan *p)
                 for (int j = 0; j < PS; ++j)
                     mt[(size_t)j * PS + i] = m[(size_t)i * PS + j];
             swizzle_panel(mt.data(), PS, p->d.precision == GRAV_FP64 ? 2 : 4, kt.data() + perp * ci, tail4);
+            if (p->m2l_orbit)
+                for (int q = 0; q < 8; ++q)
+                    for (int rb = 0; rb < 8; ++rb)
+                        for (int lane = 0; lane < 64; ++lane)
+                            for (int u = 0; u < 4; ++u) {
+                                const int row = ccoef[rb * 16 + (lane & 15)], col = ccoef[q * 16 + 4 * u + (lane >> 4)];
+                                ko[((((size_t)ci * 8 + q) * 8 + rb) * 64 + lane) * 4 + u] =
+                                    row >= 0 && col >= 0 ? m[(size_t)row * PS + col] : 0.0;
+                            }
         }
+    }
+    if (p->m2l_orbit) {
+        std::vector<float> ko32(ko.begin(), ko.end());
+        GRAV_CHECK(upload(p, &p->d_k32o, ko32));
+        GRAV_CHECK(upload(p, &p->d_ccoef, ccoef));
+        // the regathered expansions' planes (chunk q = class, sub-row kr):
+        // value u of plane (q, kr) is coefficient 4 u + kr of class q
+        p->m2l_npl = 32;
+        std::vector<int32_t> kmap(32 * 4);
+        for (int q = 0; q < 8; ++q)
+            for (int kr = 0; kr < 4; ++kr)
+                for (int u = 0; u < 4; ++u)
+                    kmap[(q * 4 + kr) * 4 + u] = ccoef[q * 16 + 4 * u + kr];
+        GRAV_CHECK(upload(p, &p->d_kmap, kmap));
+    } else {
+        // the natural order: value u of plane (q, kr) is coefficient 16 q + 4 u + kr
+        p->m2l_npl = PS / 4;
+        std::vector<int32_t> kmap((size_t)PS);
+        for (int pl = 0; pl < PS / 4; ++pl)
+            for (int u = 0; u < 4; ++u) {
+                const int c = 16 * (pl / 4) + 4 * u + pl % 4;
+                kmap[pl * 4 + u] = c < p->P2 ? c : -1;
+            }
+        GRAV_CHECK(upload(p, &p->d_kmap, kmap));
     }
     if (p->d.precision == GRAV_FP64) {
         GRAV_CHECK(upload(p, &p->d_k64, k));
@@ -680,7 +754,17 @@ struct StreamK {
     int nset = 2;
 };
 
-static grav_status stream_k(const Plan *p, const std::vector<int32_t> &item_unit, int64_t nunit, int nc, StreamK &o)
+// 16-column blocks per wave of the per-offset M2L kernel (FP32: four on
+// plans with many columns; FP64: two on plans with many columns)
+static int m2l_blocks_per_wave(const Plan *p)
+{
+    const int64_t ncol = p->n_tbox * p->B;
+    return p->d.precision == GRAV_FP64 ? (ncol >= GRAV_M2L_WIDE_COLUMNS64 ? GRAV_M2L_NC64_WIDE : GRAV_M2L_NC64)
+                                       : (ncol >= GRAV_M2L_WIDE_COLUMNS ? GRAV_M2L_NC32_WIDE : GRAV_M2L_NC32);
+}
+
+static grav_status stream_k(const Plan *p, const std::vector<int32_t> &item_unit, int64_t nunit, int nc, StreamK &o,
+                            bool orbit = false)
 {
     const int64_t T = (int64_t)item_unit.size();
     // at least kMinItems items per workgroup: small plans get fewer
@@ -692,11 +776,11 @@ static grav_status stream_k(const Plan *p, const std::vector<int32_t> &item_unit
     int resident = 0;
     o.nset = 2;
     if (p->d.precision != GRAV_FP64) {
-        GRAV_CHECK(m2l_resident_workers(p, 1, nc, &resident));
+        GRAV_CHECK(m2l_resident_workers(p, 1, nc, orbit, &resident));
         if (T >= kItemsOneSet * resident)
             o.nset = 1;
     }
-    GRAV_CHECK(m2l_resident_workers(p, o.nset, nc, &resident));
+    GRAV_CHECK(m2l_resident_workers(p, o.nset, nc, orbit, &resident));
     const int64_t P = T == 0 ? 0
                              : std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(GRAV_M2L_WAVES, resident),
                                                                       T / kMinItems));
@@ -743,9 +827,9 @@ static grav_status build_m2l_transposed(Plan *p, const std::vector<std::vector<u
 {
     const int L = p->L;
     const int64_t B = p->B;
-    // the forward's column blocks per wave: the transposed M2L has the same
-    // box pairs
-    const int nc = p->m2l_nc;
+    // the per-offset kernel's column blocks per wave (the transposed M2L has
+    // the forward's box pairs)
+    const int nc = m2l_blocks_per_wave(p);
     const int ncw = 16 * nc, upt = 4 / nc;
     std::vector<uint32_t> skey((size_t)std::max<int64_t>(p->n_me, 1), 0);
     std::vector<int32_t> sorder((size_t)std::max<int64_t>(p->n_me, 1), 0);
@@ -901,31 +985,48 @@ grav_status build_tiles(Plan *p)
     std::vector<GemmTile> all;
     const int L = p->L;
     const int64_t B = p->B;
-    auto add = [&](int kind, int level, int cls, int64_t ncols) {
+    auto add_tile = [&](int kind, int level, int cls, int64_t c0, int64_t ncol) {
         TileRange &r = p->tiles[kind][0];
         if (r.n == 0)
             r.off = (int64_t)all.size();
         TileRange &rl = p->tiles[kind][level];
         if (rl.n == 0)
             rl.off = r.n;  // level range, in this kind's own numbering
-        for (int64_t c0 = 0; c0 < ncols; c0 += kTileCols) {
-            GemmTile t{};
-            t.level = level;
-            t.cls = cls;
-            t.col0 = c0;
-            t.ncol = (int32_t)std::min<int64_t>(kTileCols, ncols - c0);
-            all.push_back(t);
-            ++r.n;
-            ++rl.n;
-        }
+        GemmTile t{};
+        t.level = level;
+        t.cls = cls;
+        t.col0 = c0;
+        t.ncol = (int32_t)ncol;
+        all.push_back(t);
+        ++r.n;
+        ++rl.n;
+    };
+    auto add = [&](int kind, int level, int cls, int64_t ncols) {
+        for (int64_t c0 = 0; c0 < ncols; c0 += kTileCols)
+            add_tile(kind, level, cls, c0, std::min<int64_t>(kTileCols, ncols - c0));
     };
     for (int k = 0; k < TK_COUNT; ++k)
         for (int l = 0; l <= kMaxLevels; ++l)
             p->tiles[k][l] = TileRange{};
     if (L >= 2) {
-        for (int l = 2; l <= L; ++l)
+        for (int l = 2; l <= L; ++l) {
+#if GRAV_M2L_INTERLEAVE
+            // the eight classes' tiles of the same rows next to each other:
+            // they read the same source expansions
+            int64_t nc[8], nt = 0;
+            for (int c = 0; c < 8; ++c) {
+                nc[c] = (p->lev[l].class_start[c + 1] - p->lev[l].class_start[c]) * B;
+                nt = std::max(nt, ceil_div(nc[c], kTileCols));
+            }
+            for (int64_t i = 0; i < nt; ++i)
+                for (int c = 0; c < 8; ++c)
+                    if (i * kTileCols < nc[c])
+                        add_tile(TK_M2L, l, c, i * kTileCols, std::min<int64_t>(kTileCols, nc[c] - i * kTileCols));
+#else
             for (int c = 0; c < 8; ++c)
                 add(TK_M2L, l, c, (p->lev[l].class_start[c + 1] - p->lev[l].class_start[c]) * B);
+#endif
+        }
     }
     // Tiles are not split over workgroups (S = 1): the forward M2L runs on
     // the stream-K schedule below.
@@ -995,14 +1096,27 @@ grav_status build_tiles(Plan *p)
             }
             // a unit is the columns of one wave: 16 NC columns of a tile
             // (FP32: four blocks on plans with many columns)
-            const int nc = p->d.precision == GRAV_FP64
-                               ? (p->n_tbox * B >= GRAV_M2L_WIDE_COLUMNS64 ? GRAV_M2L_NC64_WIDE : GRAV_M2L_NC64)
-                               : (p->n_tbox * B >= GRAV_M2L_WIDE_COLUMNS ? GRAV_M2L_NC32_WIDE : GRAV_M2L_NC32);
+            const int nc = p->m2l_orbit ? GRAV_M2L_ORB_NC : m2l_blocks_per_wave(p);
             const int ncw = 16 * nc, upt = 4 / nc;
             const int64_t nunit = r.n * upt;
             std::vector<int32_t> item_tile, item_off;  // item_tile holds the unit
             std::vector<int32_t> colmap((size_t)p->n_tbox * B, -1);
             std::vector<char> hit(kClassOffsets);
+            // reflection-orbit M2L: per class, the canonical offset of each
+            // of its offsets, and per (class, canonical offset, reflection)
+            // the class offset index or -1
+            std::vector<int> ocanon(8 * kClassOffsets);
+            std::vector<int32_t> orbtab(8 * kCanonOffsets * 8, -1);
+            for (int c = 0; c < 8; ++c)
+                for (int o = 0; o < kClassOffsets; ++o) {
+                    const int32_t *e = &fwd[((size_t)c * kClassOffsets + o) * 4];
+                    const int ci = canon_index(std::abs(e[0]), std::abs(e[1]), std::abs(e[2]));
+                    const int s = (e[0] < 0 ? 1 : 0) | (e[1] < 0 ? 2 : 0) | (e[2] < 0 ? 4 : 0);
+                    ocanon[c * kClassOffsets + o] = ci;
+                    orbtab[((size_t)c * kCanonOffsets + ci) * 8 + s] = o;
+                }
+            std::vector<char> ohit(kCanonOffsets);
+            p->m2l_orb_pairs = 0;
             for (int64_t u = 0; u < r.n; ++u) {
                 const GemmTile &t = split[r.off + u];
                 const LevelInfo &lv = p->lev[t.level];
@@ -1015,6 +1129,7 @@ grav_status build_tiles(Plan *p)
                             (int32_t)((u * upt + hq) * 64 + cl - hq * ncw);
                         const uint32_t k = key[t.level][box];
                         const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+                        uint64_t orbs = 0;
                         for (int o = 0; o < kClassOffsets; ++o) {
                             const int32_t *e = &fwd[((size_t)t.cls * kClassOffsets + o) * 4];
                             bool in = true;
@@ -1023,20 +1138,36 @@ grav_status build_tiles(Plan *p)
                                 in = in && s >= 0 && s < lv.ns[a];
                             }
                             hit[o] |= in;
+                            if (in)
+                                orbs |= 1ull << ocanon[t.cls * kClassOffsets + o];
                         }
+                        p->m2l_orb_pairs += __builtin_popcountll(orbs);
                     }
-                    for (int o = 0; o < kClassOffsets; ++o)
-                        if (hit[o]) {
-                            item_tile.push_back((int32_t)(u * upt + hq));
-                            item_off.push_back(o);
-                        }
+                    if (p->m2l_orbit) {
+                        std::fill(ohit.begin(), ohit.end(), 0);
+                        for (int o = 0; o < kClassOffsets; ++o)
+                            ohit[ocanon[t.cls * kClassOffsets + o]] |= hit[o];
+                        for (int ci = 0; ci < kCanonOffsets; ++ci)
+                            if (ohit[ci]) {
+                                item_tile.push_back((int32_t)(u * upt + hq));
+                                item_off.push_back(ci);
+                            }
+                    } else {
+                        for (int o = 0; o < kClassOffsets; ++o)
+                            if (hit[o]) {
+                                item_tile.push_back((int32_t)(u * upt + hq));
+                                item_off.push_back(o);
+                            }
+                    }
                 }
             }
             StreamK sk;
-            GRAV_CHECK(stream_k(p, item_tile, nunit, nc, sk));
+            GRAV_CHECK(stream_k(p, item_tile, nunit, nc, sk, p->m2l_orbit));
             if (item_off.empty())
                 item_off.push_back(0);
             GRAV_CHECK(upload(p, &p->d_m2l_items, item_off));
+            if (p->m2l_orbit)
+                GRAV_CHECK(upload(p, &p->d_orbtab, orbtab));
             GRAV_CHECK(upload(p, &p->d_m2l_segs, sk.seg.empty() ? std::vector<int32_t>(4, 0) : sk.seg));
             GRAV_CHECK(upload(p, &p->d_m2l_wgseg, sk.wgseg));
             GRAV_CHECK(upload(p, &p->d_m2l_tseg_start, sk.tseg_start));
@@ -1954,7 +2085,8 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             break;
         if ((st = dalloc(p, &p->d_le, (size_t)p->n_tbox * p->B * p->PS, false)) != GRAV_OK)
             break;
-        if (p->L >= 2 && (st = dalloc(p, &p->d_meg, (size_t)p->n_me * p->B * p->PS, false)) != GRAV_OK)
+        if (p->L >= 2 &&
+            (st = dalloc(p, &p->d_meg, (size_t)p->n_me * p->B * std::max(p->PS, 4 * p->m2l_npl), false)) != GRAV_OK)
             break;
         if ((st = dalloc(p, &p->d_near, (size_t)p->M * p->B * 4, false)) != GRAV_OK)
             break;
@@ -1977,6 +2109,14 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
             const size_t part = (size_t)p->m2l_nseg * p->m2l_ncw * p->PS;
             if ((st = dalloc(p, &p->d_part, part, false)) != GRAV_OK)
                 break;
+            // the orbit M2L writes the coefficients only: the padding of its
+            // slots stays zero from here on
+            if (p->m2l_orbit && part > 0 &&
+                (hipMemsetAsync(p->d_part, 0, part * sizeof(float), s) != hipSuccess ||
+                 hipStreamSynchronize(s) != hipSuccess)) {
+                st = GRAV_EDEVICE;
+                break;
+            }
             if ((st = dalloc(p, &p->d_partt, (size_t)p->m2lt_nseg * p->m2lt_ncw * p->PS, false)) != GRAV_OK)
                 break;
             if ((st = dalloc(p, &p->d_leg, (size_t)p->n_leg * p->B * p->PS, false)) != GRAV_OK)
