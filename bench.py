@@ -168,7 +168,9 @@ def pct(xs, q):
 # mixed plans at these orders run the M2L once per reflection orbit of
 # offsets (k_m2l_orb): the eight sign classes of the coefficients hold at
 # most 16 each up to p = 10, and below p = 10 the per-offset kernel is as
-# fast or faster
+# fast or faster.  (Plans whose orbits hold few offsets with a source, such
+# as stations above the source block, keep the per-offset kernel; in the
+# rows below their roofline stage is not the M2L.)
 M2L_ORBIT_ORDERS = (10,)
 
 

@@ -1660,7 +1660,8 @@ grav_status enqueue_forward(Plan *p, const double *rho, double *out, hipStream_t
             const int64_t n = p->n_me * p->B * p->m2l_npl;
             const dim3 gg((unsigned)((n + 255) / 256));
             const int32_t *kmap = (const int32_t *)p->d_kmap;
-            if (p->d.precision == GRAV_FP64)
+            if (n == 0 || kmap == nullptr) {
+            } else if (p->d.precision == GRAV_FP64)
                 hipLaunchKernelGGL((k_me_gather<double>), gg, dim3(256), 0, s, g, (const double *)p->d_me, p->n_me,
                                    kmap, p->m2l_npl, p->d_meg);
             else

@@ -54,15 +54,14 @@ constexpr int kMaxLevels = 10;
 #ifndef GRAV_M2L_ORB_MIN_P
 #define GRAV_M2L_ORB_MIN_P 10
 #endif
-// Forward M2L schedule locality: interleave the eight classes' tiles of a
-// level (they read the same source expansions), and give each XCD a
-// contiguous range of stream-K workers (workgroups go to the eight XCDs in
-// turn; each XCD has its own L2)
-#ifndef GRAV_M2L_INTERLEAVE
-#define GRAV_M2L_INTERLEAVE 0
-#endif
-#ifndef GRAV_M2L_XCD_REMAP
-#define GRAV_M2L_XCD_REMAP 0
+// ... and only for plans whose (column, offset) pairs with a source number at
+// least this many times their (column, orbit) pairs: an orbit item costs
+// 256 instructions per column block at about two thirds of the per-offset
+// kernel's MFMA occupancy, an offset item about 156 (break-even near 2.4);
+// 256^3 volume workload: M2L 9.31 ms per offset, 6.82 per orbit; 128^3 x 32
+// models, stations above the top face: 0.150 and 0.239 ms
+#ifndef GRAV_M2L_ORB_MIN_RATIO
+#define GRAV_M2L_ORB_MIN_RATIO 2.6
 #endif
 constexpr int kNumOffsets = 316;   // M2L offsets d with 2 <= |d|_inf <= 3
 // The mixed-precision (FP32) forward M2L stores one operator per offset with

@@ -387,20 +387,6 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
 // row 4 kr + r of row block a is coefficient ccoef[a][4 kr + r] (-1: none;
 // the slot's unused entries stay zero from the plan's clearing).
 // --------------------------------------------------------------------------
-// Stream-K worker of workgroup b out of P: with GRAV_M2L_XCD_REMAP the
-// workgroups that the hardware places on XCD x (b = x, x + 8, ...) take the
-// contiguous workers [x P / 8, (x + 1) P / 8) (a bijection for any P)
-__device__ __forceinline__ int m2l_worker(int b, int P)
-{
-#if GRAV_M2L_XCD_REMAP
-    const int q = P / 8, r = P % 8, x = b % 8, i = b / 8;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-#else
-    (void)P;
-    return b;
-#endif
-}
-
 #ifndef GRAV_M2L_ORB_WAVES
 #define GRAV_M2L_ORB_WAVES 2
 #endif
@@ -415,8 +401,7 @@ k_m2l_orb(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t 
     constexpr int UPT = 4 / NC;
     const int kr = lane >> 4;
     const int PS = g.PS;
-    const int w = m2l_worker(blockIdx.x, gridDim.x);
-    for (int sg = wgseg[w]; sg < wgseg[w + 1]; ++sg) {
+    for (int sg = wgseg[blockIdx.x]; sg < wgseg[blockIdx.x + 1]; ++sg) {
         const int32_t *sd = segs + 4 * sg;  // unit, first item, end item
         const GemmTile tile = tiles[sd[0] / UPT];
         const int hq = sd[0] % UPT;

@@ -661,7 +661,8 @@ grav_status build_operators(Plan *p)
                 ccoef[s * 16 + cnt[s]] = c;
             ++cnt[s];
         }
-        p->m2l_orbit = fits;
+        p->m2l_orbit = fits;  // tentative: build_tiles keeps it where it pays
+        p->m2l_npl = PS / 4;
     }
     std::vector<double> ko(p->m2l_orbit ? (size_t)kCanonOffsets * 8 * 8 * 256 : 0, 0.0);
     for (int id = 0; id < kNumOffsets; ++id) {
@@ -693,25 +694,6 @@ grav_status build_operators(Plan *p)
         std::vector<float> ko32(ko.begin(), ko.end());
         GRAV_CHECK(upload(p, &p->d_k32o, ko32));
         GRAV_CHECK(upload(p, &p->d_ccoef, ccoef));
-        // the regathered expansions' planes (chunk q = class, sub-row kr):
-        // value u of plane (q, kr) is coefficient 4 u + kr of class q
-        p->m2l_npl = 32;
-        std::vector<int32_t> kmap(32 * 4);
-        for (int q = 0; q < 8; ++q)
-            for (int kr = 0; kr < 4; ++kr)
-                for (int u = 0; u < 4; ++u)
-                    kmap[(q * 4 + kr) * 4 + u] = ccoef[q * 16 + 4 * u + kr];
-        GRAV_CHECK(upload(p, &p->d_kmap, kmap));
-    } else {
-        // the natural order: value u of plane (q, kr) is coefficient 16 q + 4 u + kr
-        p->m2l_npl = PS / 4;
-        std::vector<int32_t> kmap((size_t)PS);
-        for (int pl = 0; pl < PS / 4; ++pl)
-            for (int u = 0; u < 4; ++u) {
-                const int c = 16 * (pl / 4) + 4 * u + pl % 4;
-                kmap[pl * 4 + u] = c < p->P2 ? c : -1;
-            }
-        GRAV_CHECK(upload(p, &p->d_kmap, kmap));
     }
     if (p->d.precision == GRAV_FP64) {
         GRAV_CHECK(upload(p, &p->d_k64, k));
@@ -753,6 +735,40 @@ struct StreamK {
     int64_t P = 0, nseg = 0;
     int nset = 2;
 };
+
+// The regather's coefficient map (k_me_gather): value u of plane pl of a
+// box's regathered expansion is coefficient kmap[4 pl + u] (-1: zero).  The
+// orbit M2L reads chunk q = sign class q, sub-row kr, value u = position
+// 4 u + kr of the class; the per-offset M2L reads coefficient 16 q + 4 u + kr.
+static grav_status upload_gather_map(Plan *p)
+{
+    std::vector<int32_t> kmap;
+    if (p->m2l_orbit) {
+        p->m2l_npl = 32;
+        int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        std::vector<int32_t> ccoef(8 * 16, -1);
+        for (int c = 0; c < p->P2; ++c) {
+            const int s = sign_class(c);
+            if (cnt[s] < 16)
+                ccoef[s * 16 + cnt[s]] = c;
+            ++cnt[s];
+        }
+        kmap.resize(32 * 4);
+        for (int q = 0; q < 8; ++q)
+            for (int kr = 0; kr < 4; ++kr)
+                for (int u = 0; u < 4; ++u)
+                    kmap[(q * 4 + kr) * 4 + u] = ccoef[q * 16 + 4 * u + kr];
+    } else {
+        p->m2l_npl = p->PS / 4;
+        kmap.resize((size_t)p->PS);
+        for (int pl = 0; pl < p->PS / 4; ++pl)
+            for (int u = 0; u < 4; ++u) {
+                const int c = 16 * (pl / 4) + 4 * u + pl % 4;
+                kmap[pl * 4 + u] = c < p->P2 ? c : -1;
+            }
+    }
+    return upload(p, &p->d_kmap, kmap);
+}
 
 // 16-column blocks per wave of the per-offset M2L kernel (FP32: four on
 // plans with many columns; FP64: two on plans with many columns)
@@ -1010,22 +1026,8 @@ grav_status build_tiles(Plan *p)
             p->tiles[k][l] = TileRange{};
     if (L >= 2) {
         for (int l = 2; l <= L; ++l) {
-#if GRAV_M2L_INTERLEAVE
-            // the eight classes' tiles of the same rows next to each other:
-            // they read the same source expansions
-            int64_t nc[8], nt = 0;
-            for (int c = 0; c < 8; ++c) {
-                nc[c] = (p->lev[l].class_start[c + 1] - p->lev[l].class_start[c]) * B;
-                nt = std::max(nt, ceil_div(nc[c], kTileCols));
-            }
-            for (int64_t i = 0; i < nt; ++i)
-                for (int c = 0; c < 8; ++c)
-                    if (i * kTileCols < nc[c])
-                        add_tile(TK_M2L, l, c, i * kTileCols, std::min<int64_t>(kTileCols, nc[c] - i * kTileCols));
-#else
             for (int c = 0; c < 8; ++c)
                 add(TK_M2L, l, c, (p->lev[l].class_start[c + 1] - p->lev[l].class_start[c]) * B);
-#endif
         }
     }
     // Tiles are not split over workgroups (S = 1): the forward M2L runs on
@@ -1094,6 +1096,43 @@ grav_status build_tiles(Plan *p)
                     lv.need_hi[a] = key[l].empty() ? -1 : hi[a] + 3;
                 }
             }
+            // The orbit M2L costs one operator per (column, orbit with a
+            // source), the per-offset one an operator per (column, offset with
+            // a source): keep the orbit kernel only where orbits hold enough
+            // offsets with sources on average (target boxes near the edge of
+            // the source block, such as surface stations, see few).
+            if (p->m2l_orbit) {
+                int64_t n_off = 0, n_orb = 0;
+                for (int l = 2; l <= L; ++l) {
+                    const LevelInfo &lv = p->lev[l];
+                    for (int c = 0; c < 8; ++c)
+                        for (int64_t j = lv.class_start[c]; j < lv.class_start[c + 1]; ++j) {
+                            const uint32_t k = key[l][ord[l][j]];
+                            const int x[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
+                            uint64_t orbs = 0;
+                            for (int o = 0; o < kClassOffsets; ++o) {
+                                const int32_t *e = &fwd[((size_t)c * kClassOffsets + o) * 4];
+                                bool in = true;
+                                for (int a = 0; a < 3; ++a) {
+                                    const int s = x[a] + e[a] - lv.s0[a];
+                                    in = in && s >= 0 && s < lv.ns[a];
+                                }
+                                if (in) {
+                                    ++n_off;
+                                    orbs |= 1ull << canon_index(std::abs(e[0]), std::abs(e[1]), std::abs(e[2]));
+                                }
+                            }
+                            n_orb += __builtin_popcountll(orbs);
+                        }
+                }
+                if ((double)n_off < GRAV_M2L_ORB_MIN_RATIO * (double)n_orb) {
+                    p->m2l_orbit = false;
+                    (void)hipFree(p->d_k32o);
+                    p->d_k32o = nullptr;
+                    p->bytes_resident -= sizeof(float) * (size_t)kCanonOffsets * 8 * 8 * 256;
+                }
+            }
+            GRAV_CHECK(upload_gather_map(p));
             // a unit is the columns of one wave: 16 NC columns of a tile
             // (FP32: four blocks on plans with many columns)
             const int nc = p->m2l_orbit ? GRAV_M2L_ORB_NC : m2l_blocks_per_wave(p);
