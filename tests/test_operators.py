@@ -161,3 +161,85 @@ def test_operator_rejects_bad_arguments():
         G.grav_operator(17, 0, 0)
     with pytest.raises(G.GravError):
         G.grav_operator(8, 0, 9)
+
+
+def _reflection_signs(p):
+    """Sign of each real coefficient under the reflections of x, y and z
+    (bits 1, 2, 4 of r), read off the regular harmonics themselves:
+    R_k(r(v)) = s_r(k) R_k(v) at a generic point v."""
+    v = np.array([0.31, -0.47, 0.58])
+    R = G.grav_harmonics(p, 0, *v)
+    s = np.empty((8, p * p))
+    for r in range(8):
+        w = v * np.array([-1.0 if r & 1 else 1.0, -1.0 if r & 2 else 1.0, -1.0 if r & 4 else 1.0])
+        s[r] = G.grav_harmonics(p, 0, *w) / R
+    np.testing.assert_allclose(np.abs(s), 1.0, rtol=1e-12)
+    return np.sign(s)
+
+
+def _interaction_offsets():
+    """The 316 offsets with 2 <= |d|_inf <= 3 whose parents are neighbours
+    for some child parity (union of the eight class lists)."""
+    out = set()
+    for c in range(8):
+        par = [(c >> a) & 1 for a in range(3)]
+        for d in np.ndindex(7, 7, 7):
+            d = tuple(int(v) - 3 for v in d)
+            if max(abs(v) for v in d) < 2:
+                continue
+            if all(abs((par[a] + d[a]) // 2) <= 1 for a in range(3)):
+                out.add(d)
+    return sorted(out)
+
+
+def test_m2l_reflection_identity():
+    """K_{r(d)} = S_r K_d S_r: the M2L operator of a reflected offset is the
+    operator of the offset with the reflection's coefficient signs applied to
+    its rows and columns (what lets mixed plans store 56 operators)."""
+    p = 6
+    s = _reflection_signs(p)
+    offs = _interaction_offsets()
+    assert len(offs) == 316
+    for d in offs[::7]:
+        c = tuple(abs(v) for v in d)
+        r = (1 if d[0] < 0 else 0) | (2 if d[1] < 0 else 0) | (4 if d[2] < 0 else 0)
+        K = G.grav_operator(p, 2, 0, d)
+        Kc = G.grav_operator(p, 2, 0, c)
+        np.testing.assert_allclose(K, s[r][:, None] * Kc * s[r][None, :], rtol=1e-12, atol=1e-14 * np.abs(Kc).max())
+
+
+def test_m2l_orbit_walsh_hadamard_identity():
+    """Summing K_{r(c)} M_r over the reflections r of a canonical offset c
+    equals applying K_c once to the Walsh-Hadamard transform of the M_r,
+    blockwise by sign class: L[i] = sum_k K_c[i][k] H[cls(i) ^ cls(k)][k],
+    H[t] = sum_r (-1)^popcount(t & r) M_r (absent reflections contribute 0)."""
+    p = 10
+    s = _reflection_signs(p)
+    # sign class of a coefficient: the reflections that flip it
+    cls = np.array([sum(1 << b for b in range(3) if s[1 << b][k] < 0) for k in range(p * p)])
+    for r in range(1, 8):  # a product of reflections flips by the product of signs
+        np.testing.assert_array_equal(s[r], np.prod([s[1 << a] for a in range(3) if r >> a & 1], axis=0))
+    # the rule the kernels use: degree n, order m, imaginary part im flip
+    # under x by (m + im) mod 2, under y by im, under z by (n + m) mod 2
+    for k in range(p * p):
+        n = int(np.sqrt(k))
+        i = k - n * n
+        m, im = (i + 1) // 2, int(i > 0 and i % 2 == 0)
+        assert cls[k] == ((m + im) & 1) | (im << 1) | (((n + m) & 1) << 2)
+    assert np.bincount(cls, minlength=8).max() <= 16  # p = 10 fits 8 blocks of 16
+    rng = np.random.default_rng(11)
+    for c in [(3, 2, 1), (2, 0, 3), (0, 0, 2), (3, 3, 3)]:
+        Kc = G.grav_operator(p, 2, 0, c)
+        present = [r for r in range(8) if not any((r >> a & 1) and c[a] == 0 for a in range(3))]
+        present = [r for r in present if rng.random() < 0.8] or present[:1]
+        M = {r: rng.standard_normal(p * p) for r in present}
+        ref = np.zeros(p * p)
+        for r in present:
+            d = tuple(-v if r >> a & 1 else v for a, v in enumerate(c))
+            ref += G.grav_operator(p, 2, 0, d) @ M[r]
+        H = np.zeros((8, p * p))
+        for t in range(8):
+            for r in present:
+                H[t] += (-1) ** bin(t & r).count("1") * M[r]
+        got = np.array([sum(Kc[i, k] * H[cls[i] ^ cls[k], k] for k in range(p * p)) for i in range(p * p)])
+        np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
