@@ -173,7 +173,6 @@ struct Plan {
     // sign class, p <= 10): work items are (unit, canonical offset) pairs
     bool m2l_orbit = false;
     int32_t m2l_npl = 0;                // (chunk, sub-row) planes of the regathered ME
-    int64_t m2l_orb_pairs = 0;          // (target box, orbit with a source box) pairs x models
     float *d_k32o = nullptr;            // [56][8 classes][8 classes][64][4] class-blocked canonical operators
     int32_t *d_orbtab = nullptr;        // [8 classes][56][8 reflections] class offset index or -1
     int32_t *d_ccoef = nullptr;         // [8][16] natural coefficient of (class, position) or -1

@@ -1155,7 +1155,6 @@ grav_status build_tiles(Plan *p)
                     orbtab[((size_t)c * kCanonOffsets + ci) * 8 + s] = o;
                 }
             std::vector<char> ohit(kCanonOffsets);
-            p->m2l_orb_pairs = 0;
             for (int64_t u = 0; u < r.n; ++u) {
                 const GemmTile &t = split[r.off + u];
                 const LevelInfo &lv = p->lev[t.level];
@@ -1168,7 +1167,6 @@ grav_status build_tiles(Plan *p)
                             (int32_t)((u * upt + hq) * 64 + cl - hq * ncw);
                         const uint32_t k = key[t.level][box];
                         const int c[3] = {(int)compact3(k), (int)compact3(k >> 1), (int)compact3(k >> 2)};
-                        uint64_t orbs = 0;
                         for (int o = 0; o < kClassOffsets; ++o) {
                             const int32_t *e = &fwd[((size_t)t.cls * kClassOffsets + o) * 4];
                             bool in = true;
@@ -1177,10 +1175,7 @@ grav_status build_tiles(Plan *p)
                                 in = in && s >= 0 && s < lv.ns[a];
                             }
                             hit[o] |= in;
-                            if (in)
-                                orbs |= 1ull << ocanon[t.cls * kClassOffsets + o];
                         }
-                        p->m2l_orb_pairs += __builtin_popcountll(orbs);
                     }
                     if (p->m2l_orbit) {
                         std::fill(ohit.begin(), ohit.end(), 0);
