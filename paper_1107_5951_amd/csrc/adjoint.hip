@@ -566,9 +566,14 @@ k_t_p2m(DevGeom g, const double *A, int RBT, const double *me, double *drho)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_le_gather(DevGeom gt, DevGeom g, const int32_t *tmap, int64_t n_tmap, int64_t n_tbox, const double *le,
-            int64_t n_leg, T *out)
+            int64_t n_leg, const int32_t *kmap, int NP, T *out)
 {
-    const int NP = g.PS / 4;
+    // the forward regather's coefficient map (value u of plane pl is
+    // coefficient kmap[4 pl + u], -1: zero), through LDS
+    __shared__ int32_t km[256];
+    for (int e = threadIdx.x; e < 4 * NP; e += blockDim.x)
+        km[e] = kmap[e];
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_leg * g.B * NP)
         return;
@@ -598,14 +603,13 @@ k_le_gather(DevGeom gt, DevGeom g, const int32_t *tmap, int64_t n_tmap, int64_t 
                 tb = v;
         }
     }
-    const int q = plane / 4, kr = plane % 4;
     const int64_t nB = (int64_t)lt.ns[0] * lt.ns[1] * lt.ns[2] * g.B;
-    T *dst = out + lt.me_off * g.B * g.PS + ((int64_t)plane * nB + pos * g.B + bm) * 4;
+    T *dst = out + lt.me_off * g.B * (4 * NP) + ((int64_t)plane * nB + pos * g.B + bm) * 4;
     const double *src = le + (tb >= 0 ? ((lv.tgt_off + tb) * g.B + bm) * g.PS : 0);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int c = 16 * q + kr + 4 * u;
-        dst[u] = (T)(tb >= 0 && c < g.P2 ? src[c] : 0.0);
+        const int c = km[4 * plane + u];
+        dst[u] = (T)(tb >= 0 && c >= 0 ? src[c] : 0.0);
     }
 }
 
@@ -889,10 +893,11 @@ static grav_status m2l_transposed_t(Plan *p, const DevGeom &g, hipStream_t s, co
             d.class_start[c] = lv.col_class_start[c];
     }
     T *leg = reinterpret_cast<T *>(p->d_leg);
-    const int64_t n = p->n_leg * p->B * (p->PS / 4);
-    if (n > 0) {
+    const int64_t n = p->n_leg * p->B * p->m2l_npl;
+    if (n > 0 && p->d_kmap != nullptr) {
         hipLaunchKernelGGL((k_le_gather<T>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, gt, g,
-                           (const int32_t *)p->d_tmap, p->n_tmap, p->n_tbox, (const double *)p->d_le, p->n_leg, leg);
+                           (const int32_t *)p->d_tmap, p->n_tmap, p->n_tbox, (const double *)p->d_le, p->n_leg,
+                           (const int32_t *)p->d_kmap, p->m2l_npl, leg);
         GRAV_HIP(hipGetLastError());
     }
     M2LRun<T> r;
@@ -909,6 +914,11 @@ static grav_status m2l_transposed_t(Plan *p, const DevGeom &g, hipStream_t s, co
     r.wgs = p->m2lt_wgs;
     r.nset = p->m2lt_nset;
     r.nc = p->m2lt_nc;
+    if (sizeof(T) == 4 && p->m2l_orbit) {
+        r.K = reinterpret_cast<const T *>(p->d_kt32o);
+        r.orbtab = (const int32_t *)p->d_orbtab_t;
+        r.ccoef = (const int32_t *)p->d_ccoef;
+    }
     GRAV_CHECK(launch_m2l<T>(p, gt, s, r));
     const int64_t ns = p->m2lt_ncols * p->PS;
     if (ns > 0) {

@@ -177,6 +177,8 @@ struct Plan {
     int32_t *d_orbtab = nullptr;        // [8 classes][56][8 reflections] class offset index or -1
     int32_t *d_ccoef = nullptr;         // [8][16] natural coefficient of (class, position) or -1
     int32_t *d_kmap = nullptr;          // [planes][4] natural coefficient of a regathered value or -1
+    float *d_kt32o = nullptr;           // the transposed canonical operators, class-blocked like d_k32o
+    int32_t *d_orbtab_t = nullptr;      // transposed M2L: [8 source classes][56][8 reflections] entry or -1
     int32_t *d_m2l_items = nullptr, *d_m2l_segs = nullptr, *d_m2l_wgseg = nullptr;
     int32_t *d_m2l_tseg_start = nullptr, *d_m2l_tsegs = nullptr, *d_m2l_colmap = nullptr;
     // the transposed M2L's schedule, in the same form (columns: source boxes

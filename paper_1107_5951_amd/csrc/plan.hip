@@ -316,7 +316,7 @@ void free_plan(Plan *p)
                     p->d_m2l_wgseg, p->d_m2l_tseg_start, p->d_m2l_tsegs, p->d_m2l_colmap,
                     p->d_cell_slot, p->d_leaf_pend, p->d_m2lt_tiles, p->d_m2lt_items, p->d_m2lt_segs,
                     p->d_m2lt_wgseg, p->d_m2lt_tseg_start, p->d_m2lt_tsegs, p->d_m2lt_colmap, p->d_m2lt_colbox,
-                    p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt,
+                    p->d_skey, p->d_sorder, p->d_tclass_off, p->d_kt64, p->d_kt32, p->d_leg, p->d_partt, p->d_kt32o, p->d_orbtab_t,
                     p->d_m2mt_sw, p->d_l2lt_sw, p->d_l2l_msw, p->d_pmt_sw, p->d_tnt64, p->d_tnt32, p->d_tl2pt, p->d_w_blk,
                     p->d_spos, p->d_sw, p->d_sperm, p->d_sstart, p->d_pt_leaves, p->d_user_leaves,
                     p->d_k32o, p->d_orbtab, p->d_ccoef, p->d_kmap};
@@ -664,7 +664,7 @@ grav_status build_operators(Plan *p)
         p->m2l_orbit = fits;  // tentative: build_tiles keeps it where it pays
         p->m2l_npl = PS / 4;
     }
-    std::vector<double> ko(p->m2l_orbit ? (size_t)kCanonOffsets * 8 * 8 * 256 : 0, 0.0);
+    std::vector<double> ko(p->m2l_orbit ? (size_t)kCanonOffsets * 8 * 8 * 256 : 0, 0.0), kot(ko.size(), 0.0);
     for (int id = 0; id < kNumOffsets; ++id) {
         // source = target + d  =>  target centre - source centre = -d
         const double dd[3] = {-(double)all[3 * id], -(double)all[3 * id + 1], -(double)all[3 * id + 2]};
@@ -687,12 +687,16 @@ grav_status build_operators(Plan *p)
                                 const int row = ccoef[rb * 16 + (lane & 15)], col = ccoef[q * 16 + 4 * u + (lane >> 4)];
                                 ko[((((size_t)ci * 8 + q) * 8 + rb) * 64 + lane) * 4 + u] =
                                     row >= 0 && col >= 0 ? m[(size_t)row * PS + col] : 0.0;
+                                kot[((((size_t)ci * 8 + q) * 8 + rb) * 64 + lane) * 4 + u] =
+                                    row >= 0 && col >= 0 ? m[(size_t)col * PS + row] : 0.0;
                             }
         }
     }
     if (p->m2l_orbit) {
         std::vector<float> ko32(ko.begin(), ko.end());
         GRAV_CHECK(upload(p, &p->d_k32o, ko32));
+        std::vector<float> kot32(kot.begin(), kot.end());
+        GRAV_CHECK(upload(p, &p->d_kt32o, kot32));
         GRAV_CHECK(upload(p, &p->d_ccoef, ccoef));
     }
     if (p->d.precision == GRAV_FP64) {
@@ -843,9 +847,23 @@ static grav_status build_m2l_transposed(Plan *p, const std::vector<std::vector<u
 {
     const int L = p->L;
     const int64_t B = p->B;
-    // the per-offset kernel's column blocks per wave (the transposed M2L has
-    // the forward's box pairs)
-    const int nc = m2l_blocks_per_wave(p);
+    // the forward's kernel choice (the transposed M2L has the forward's box
+    // pairs): the orbit kernel's column blocks, or the per-offset one's
+    const int nc = p->m2l_orbit ? GRAV_M2L_ORB_NC : m2l_blocks_per_wave(p);
+    // orbit kernel: per source class, canonical offset |d| and reflection
+    // (sign bits of d, which give the operator S K_|d|^T S), the entry of the
+    // reverse list or -1
+    std::vector<int> rcanon(8 * kClassOffsets);
+    std::vector<int32_t> orbtab(8 * kCanonOffsets * 8, -1);
+    for (int c = 0; c < 8; ++c)
+        for (int o = 0; o < kClassOffsets; ++o) {
+            const int32_t *e = &rev[((size_t)c * kClassOffsets + o) * 4];
+            const int ci = canon_index(std::abs(e[0]), std::abs(e[1]), std::abs(e[2]));
+            const int r = (e[0] < 0 ? 1 : 0) | (e[1] < 0 ? 2 : 0) | (e[2] < 0 ? 4 : 0);
+            rcanon[c * kClassOffsets + o] = ci;
+            orbtab[((size_t)c * kCanonOffsets + ci) * 8 + r] = o;
+        }
+    std::vector<char> ohit(kCanonOffsets);
     const int ncw = 16 * nc, upt = 4 / nc;
     std::vector<uint32_t> skey((size_t)std::max<int64_t>(p->n_me, 1), 0);
     std::vector<int32_t> sorder((size_t)std::max<int64_t>(p->n_me, 1), 0);
@@ -958,18 +976,31 @@ static grav_status build_m2l_transposed(Plan *p, const std::vector<std::vector<u
                                 hit[o] = 1;
                         }
                     }
-                    for (int o = 0; o < kClassOffsets; ++o)
-                        if (hit[o]) {
-                            item_unit.push_back((int32_t)(u0 + hq));
-                            item_off.push_back(o);
-                        }
+                    if (p->m2l_orbit) {
+                        std::fill(ohit.begin(), ohit.end(), 0);
+                        for (int o = 0; o < kClassOffsets; ++o)
+                            ohit[rcanon[cls * kClassOffsets + o]] |= hit[o];
+                        for (int ci = 0; ci < kCanonOffsets; ++ci)
+                            if (ohit[ci]) {
+                                item_unit.push_back((int32_t)(u0 + hq));
+                                item_off.push_back(ci);
+                            }
+                    } else {
+                        for (int o = 0; o < kClassOffsets; ++o)
+                            if (hit[o]) {
+                                item_unit.push_back((int32_t)(u0 + hq));
+                                item_off.push_back(o);
+                            }
+                    }
                 }
             }
         }
     }
     const int64_t nunit = (int64_t)tiles.size() * upt;
     StreamK sk;
-    GRAV_CHECK(stream_k(p, item_unit, nunit, nc, sk));
+    GRAV_CHECK(stream_k(p, item_unit, nunit, nc, sk, p->m2l_orbit));
+    if (p->m2l_orbit)
+        GRAV_CHECK(upload(p, &p->d_orbtab_t, orbtab));
     if (item_off.empty())
         item_off.push_back(0);
     GRAV_CHECK(upload(p, &p->d_m2lt_tiles, tiles.empty() ? std::vector<GemmTile>(1) : tiles));
@@ -1125,11 +1156,19 @@ grav_status build_tiles(Plan *p)
                             n_orb += __builtin_popcountll(orbs);
                         }
                 }
-                if ((double)n_off < GRAV_M2L_ORB_MIN_RATIO * (double)n_orb) {
+                // the transposed M2L's gather regions (at most 3 boxes past the
+                // source block on each side) also take 32-bit byte offsets
+                double leg_bytes = 0.0;
+                for (int l = 2; l <= L; ++l)
+                    leg_bytes += 512.0 * (double)B * (p->lev[l].ns[0] + 6) * (p->lev[l].ns[1] + 6) *
+                                 (p->lev[l].ns[2] + 6);
+                if ((double)n_off < GRAV_M2L_ORB_MIN_RATIO * (double)n_orb || leg_bytes >= 4294967296.0) {
                     p->m2l_orbit = false;
                     (void)hipFree(p->d_k32o);
+                    (void)hipFree(p->d_kt32o);
                     p->d_k32o = nullptr;
-                    p->bytes_resident -= sizeof(float) * (size_t)kCanonOffsets * 8 * 8 * 256;
+                    p->d_kt32o = nullptr;
+                    p->bytes_resident -= 2 * sizeof(float) * (size_t)kCanonOffsets * 8 * 8 * 256;
                 }
             }
             GRAV_CHECK(upload_gather_map(p));
@@ -2151,9 +2190,19 @@ extern "C" grav_status grav_plan(const grav_plan_desc *desc, grav_plan_t *out)
                 st = GRAV_EDEVICE;
                 break;
             }
-            if ((st = dalloc(p, &p->d_partt, (size_t)p->m2lt_nseg * p->m2lt_ncw * p->PS, false)) != GRAV_OK)
+            const size_t partt = (size_t)p->m2lt_nseg * p->m2lt_ncw * p->PS;
+            if ((st = dalloc(p, &p->d_partt, partt, false)) != GRAV_OK)
                 break;
-            if ((st = dalloc(p, &p->d_leg, (size_t)p->n_leg * p->B * p->PS, false)) != GRAV_OK)
+            // as in the forward: the orbit kernel leaves the slots' padding
+            // entries alone, so they are cleared once here
+            if (p->m2l_orbit && partt > 0 &&
+                (hipMemsetAsync(p->d_partt, 0, partt * sizeof(float), s) != hipSuccess ||
+                 hipStreamSynchronize(s) != hipSuccess)) {
+                st = GRAV_EDEVICE;
+                break;
+            }
+            if ((st = dalloc(p, &p->d_leg, (size_t)p->n_leg * p->B * std::max(p->PS, 4 * p->m2l_npl), false)) !=
+                GRAV_OK)
                 break;
         }
         {

@@ -108,6 +108,19 @@ def test_transpose_dot_product_large_lattice():
         assert gap <= bar
 
 
+def test_transpose_dot_product_orbit_m2l():
+    """128^3 cells x 2 models, mixed at p = 10 with cell-centre targets: the
+    plan runs both M2L directions once per reflection orbit of offsets
+    (about three offsets with a source per orbit on a 32^3-leaf volume)."""
+    grid = W.Grid.unit(128)
+    rho = np.stack([W.gaussian_blobs(grid, 4, 2200 + b) for b in range(2)])
+    spec = G.PlanSpec(n=(128, 128, 128), h=grid.h, voxel_centres=True, components=3, p=10, leaf_size=64,
+                      batch=2, precision=G.GRAV_MIXED)
+    gap, _ = _dot_gap(spec, rho)
+    _say("adjoint dot product, 128^3 x 2 lattice, mixed p=10: %.3e" % gap)
+    assert gap <= 1e-5
+
+
 def test_transpose_matches_oracle_transpose():
     rng = np.random.default_rng(2)
     grid = W.Grid.unit(16)
