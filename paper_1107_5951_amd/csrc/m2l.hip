@@ -385,7 +385,10 @@ k_m2l(DevGeom g, const GemmTile *tiles, const uint32_t *tkey, const int32_t *tor
 // The regathered expansions hold class q's coefficients in planes 4 q .. 4
 // q + 3 (value u of plane (q, kr): position 4 u + kr of the class).  Output
 // row 4 kr + r of row block a is coefficient ccoef[a][4 kr + r] (-1: none;
-// the slot's unused entries stay zero from the plan's clearing).
+// the slot's unused entries stay zero from the plan's clearing).  The
+// adjoint's transposed M2L runs the same kernel on its own problem: columns
+// are source boxes, K the class-blocked K_c^T, and the orbit table groups
+// the reverse offset lists.
 // --------------------------------------------------------------------------
 #ifndef GRAV_M2L_ORB_WAVES
 #define GRAV_M2L_ORB_WAVES 2
